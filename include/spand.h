@@ -1,0 +1,146 @@
+/*
+ * spand.h - C ABI of an MI355X implementation of spaND with first-order and
+ * second-order sparsification (Klockiewicz, Cambier, Humble, Tchelepi, Darve,
+ * "Second order accurate hierarchical approximate factorization of sparse SPD
+ * matrices").
+ *
+ * Problem (Sec. 1): A x = b with A sparse symmetric positive definite (both
+ * triangles stored, CSR) and one coordinate vector per row.  The library
+ * computes the approximate factorization A ~ L L^T level by level (Alg. 2):
+ * interiors of a nested-dissection level are eliminated by block Cholesky,
+ * interfaces are scaled by the Cholesky factor of their diagonal block
+ * (eq. prescale) and sparsified by an early-stopping column-pivoted QR at
+ * tolerance eps (Alg. 1).  The preconditioner M = L^{-T} L^{-1} is applied in
+ * PCG with a zero initial guess and a relative residual stop (Sec. 4).
+ *
+ * Conventions
+ *  - Every call returns spand_status (0 = SPAND_OK, < 0 an error); no C++
+ *    exception crosses the boundary.  spand_last_error() describes the last
+ *    failure of a context, e.g. "interface block not SPD at step 7, cluster 12".
+ *  - Host pointers are read during the call only and copied; the caller keeps
+ *    ownership.  Device pointers (documented as such) must stay valid until the
+ *    call returns; results written to device memory are complete when the call
+ *    returns (the library synchronizes its stream before returning).
+ *  - Plans and factors belong to the library until the matching destroy call.
+ *  - One context per host thread.  The library allocates its device memory
+ *    with hipMalloc on the context's device.
+ */
+#ifndef SPAND_H
+#define SPAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spand_ctx_s*    spand_ctx_t;
+typedef struct spand_plan_s*   spand_plan_t;
+typedef struct spand_factor_s* spand_factor_t;
+
+typedef enum {
+  SPAND_OK = 0,
+  SPAND_E_INVALID = -1,        /* bad argument or option */
+  SPAND_E_NOT_SYMMETRIC = -2,  /* pattern or values not symmetric */
+  SPAND_E_NOT_SPD = -3,        /* a Cholesky factorization broke down */
+  SPAND_E_NO_CONVERGENCE = -4, /* PCG hit maxit */
+  SPAND_E_OOM = -5,            /* device allocation failed */
+  SPAND_E_HIP = -6,            /* HIP runtime error */
+  SPAND_E_STATE = -7,          /* call not valid in this state */
+  SPAND_E_LIMIT = -8           /* a size exceeds a kernel limit */
+} spand_status;
+
+/* Sparsification schemes (Sec. 2): first order drops E and E^T (eq.
+ * trailing-1); full second order keeps E in the outer factors and drops only
+ * -E^T E (eq. trailing-2); superfine keeps E_2 only (eq. trailing-3). */
+typedef enum { SPAND_FIRST_ORDER = 1, SPAND_SECOND_ORDER = 2, SPAND_SUPERFINE = 3 } spand_scheme;
+typedef enum { SPAND_FP64 = 0 } spand_precision;
+
+typedef struct {
+  int32_t depth;      /* nested-dissection depth D (levels D..0, Alg. 2); <= 0: round(log2(n/64)) */
+  int32_t skip;       /* levels D..D-skip+1 neither scale nor sparsify (Sec. 4 skips 4) */
+  double  eps;        /* 0 <= eps <= 1, RRQR tolerance (Alg. 1) */
+  int32_t scheme;     /* spand_scheme */
+  int32_t precision;  /* spand_precision */
+  int32_t debug_stop_step;  /* >= 0: stop after sparsifying this step (parity dumps); -1: off */
+} spand_opts;
+
+void spand_default_opts(spand_opts* opts);
+const char* spand_status_string(spand_status s);
+
+/* Context: device ordinal and a HIP stream (hipStream_t passed as void*; NULL
+ * = the library creates its own stream). */
+spand_status spand_create(spand_ctx_t* out, int device, void* stream);
+void spand_destroy(spand_ctx_t ctx);
+const char* spand_last_error(spand_ctx_t ctx);
+
+/* Symbolic analysis on the host: geometric nested dissection, clusters per
+ * level, block structure with symbolic fill, interface colouring (Sec. 3,
+ * Fig. 1; the coordinate-bisection partition replaces the algebraic spaND
+ * partition, whose definition the paper defers to the base spaND paper).
+ * rowptr[n+1], colind[nnz] (0-based, sorted or not), coords[n*dim] row-major:
+ * host pointers.  Checks pattern symmetry (SPAND_E_NOT_SYMMETRIC).  Pure host
+ * work: ctx may be NULL (errors are then only reported by the status); the
+ * plan is bound to a device by its first spand_factor. */
+spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                           const double* coords, int32_t dim, const spand_opts* opts,
+                           spand_plan_t* out);
+void spand_destroy_plan(spand_plan_t plan);
+
+/* Plan queries (host arrays supplied by the caller, sized from the counts). */
+spand_status spand_plan_sizes(spand_plan_t plan, int64_t* n, int64_t* nnz, int32_t* depth);
+/* lvl[n], path[n], perm[n] (elimination permutation sorted by (D-lvl, path, id)) */
+spand_status spand_plan_vertices(spand_plan_t plan, int32_t* lvl, int64_t* path, int64_t* perm);
+/* counts of step l: clusters, interiors, adjacency entries, children entries */
+spand_status spand_plan_step_counts(spand_plan_t plan, int32_t l, int32_t* n_clusters,
+                                    int32_t* n_interior, int64_t* n_adj, int64_t* n_child,
+                                    int32_t* sparsified);
+/* arrays of step l: key_lvl[nc], key_prefix[nc], adj_ptr[nc+1], adj[n_adj] (sorted,
+ * incl. self), colour[nc] (-1 interiors), child_ptr[nc+1], child[n_child]
+ * (children in step l+1; empty at l = depth).  Any pointer may be NULL. */
+spand_status spand_plan_step_arrays(spand_plan_t plan, int32_t l, int64_t* key_lvl,
+                                    int64_t* key_prefix, int64_t* adj_ptr, int32_t* adj,
+                                    int32_t* colour, int64_t* child_ptr, int32_t* child);
+
+/* Numeric factorization on the device.  vals[nnz]: device pointer, values in
+ * the CSR order given to spand_analyze.  SPAND_E_NOT_SPD names the step and
+ * cluster of the first Cholesky breakdown. */
+spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals, const spand_opts* opts,
+                          spand_factor_t* out);
+void spand_destroy_factor(spand_factor_t f);
+
+/* Per-cluster sparsification record of step l: a (size before), k (coupling
+ * width), r (eps rank), r2 (superfine rank, = r otherwise); -1 for interiors
+ * and for steps that are not sparsified.  Host arrays of n_clusters. */
+spand_status spand_factor_ranks(spand_factor_t f, int32_t l, int32_t* a, int32_t* k, int32_t* r,
+                                int32_t* r2);
+typedef struct {
+  int64_t nnz_L;          /* memory metric numerator (Sec. 4): see DESIGN counting rule */
+  double  flops;          /* algorithmic flops of the factorization */
+  double  factor_seconds; /* wall time of spand_factor */
+  int64_t factor_bytes;   /* device bytes held by the factor */
+  int32_t root_size;
+} spand_factor_stats;
+spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st);
+
+/* y = M x for nrhs columns; x, y: device pointers, n x nrhs column-major. */
+spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y);
+
+/* PCG (Sec. 4): x0 = 0, stop when ||r_k||_2 < tol ||b||_2 per column; b, x:
+ * device pointers (n x nrhs column-major); iters[nrhs], relres[nrhs] (true
+ * residual ||b - A x|| / ||b|| at exit): host pointers.  Returns
+ * SPAND_E_NO_CONVERGENCE if a column reaches maxit. */
+spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* b, double* x,
+                       double tol, int32_t maxit, int32_t* iters, double* relres);
+
+/* Debug dump for parity tests: with opts.debug_stop_step = l, after
+ * spand_factor returns, copies block (ci, cj) of step l (after its
+ * sparsification) to out (host, column-major, ld = *rows); rows/cols receive
+ * the current block size.  out may be NULL to query the size. */
+spand_status spand_debug_block(spand_factor_t f, int32_t ci, int32_t cj, double* out, int32_t* rows,
+                               int32_t* cols);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -110,8 +110,12 @@ def _assemble_leaf_blocks(A, st):
     return B
 
 
-def factor(A, plan, eps, scheme=SECOND_ORDER):
-    """Approximate factorization of the SPD matrix A (scipy sparse) on `plan`."""
+def factor(A, plan, eps, scheme=SECOND_ORDER, stop_after=None):
+    """Approximate factorization of the SPD matrix A (scipy sparse) on `plan`.
+
+    stop_after=l returns (F, B, sizes) right after step l's sparsification:
+    the block dict B[(i, j)] of step l's clusters and their current sizes
+    (used to compare intermediate blocks)."""
     if scheme not in (FIRST_ORDER, SECOND_ORDER, SUPERFINE):
         raise ValueError(scheme)
     A = sp.csr_matrix(A)
@@ -212,6 +216,8 @@ def factor(A, plan, eps, scheme=SECOND_ORDER):
                 pos[p] = pos[p][:r].copy()
         F.ranks[l] = ranks
         F.flops[l] = fl
+        if stop_after == l:
+            return F, B, [p_.size for p_ in pos]
         # (d) merge into the clusters of step l-1
         nxt = plan.steps[l - 1]
         new_pos = [np.concatenate([pos[ch] for ch in chs]) if chs else np.zeros(0, np.int64)

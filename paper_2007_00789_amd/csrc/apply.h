@@ -1,0 +1,90 @@
+// Descriptors of the preconditioner apply and the PCG building blocks.
+//
+// The vector z (n x nrhs, column-major, ld n) is indexed by original vertex
+// numbers; a cluster's current variables are a list of positions into it.
+// Forward (z <- L^{-1} z), per step l = depth ... 0:
+//   ApInt  (one workgroup per interior):  z_s <- L_s^{-1} z_s,
+//          t_s = G_s^T z_s written to a scratch buffer;
+//   ApGat  (one workgroup per interface): z_w -= sum_s t_s[w] (ascending s),
+//          then z_w <- Z_w^{-1} z_w on sparsified steps;
+//   per colour: ApSp  z_p <- Q_p^T z_p, t_p = E_p^T z_f (second order);
+//               ApGat z_w -= sum_p t_p[w] (ascending p).
+// Backward (y <- L^{-T} y) runs the transposes in reverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spand {
+
+struct ApInt {
+  const double* Linv;      // n x n
+  const double* G;         // n x k (G_s = L_s^{-1} B_sW)
+  const int32_t* pos;      // n
+  const int32_t* nbr_pos;  // k
+  int64_t toff;            // scratch offset (units of one right-hand side)
+  int32_t n, k;
+};
+
+struct ApSrc {             // one slice of a scratch vector subtracted from a target
+  int64_t toff;            // scratch offset of the producer (units of one rhs)
+  int32_t col, ld;         // slice start inside the producer's vector, producer length
+};
+
+struct ApGat {
+  const int32_t* pos;      // target positions (first n)
+  const double* Zinv;      // nullable: scale after the subtraction (forward only)
+  int64_t src0, src1;      // range in the ApSrc list
+  int32_t n, pad;
+};
+
+struct ApSp {
+  const double* V;         // a x nref reflectors (ld a)
+  const double* tau;       // nref
+  const double* E;         // rows f0..f1-1 of Q^T W (ld a), nullable
+  const int32_t* pos;      // a
+  const int32_t* nbr_pos;  // k
+  int64_t toff;
+  int32_t a, nref, f0, f1, k, pad;
+};
+
+struct ApScale {
+  const double* Zinv;
+  const int32_t* pos;
+  int32_t n, pad;
+};
+
+void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                       double* T, int32_t max_n, hipStream_t s);
+void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
+                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s);
+void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                      double* T, int32_t max_a, hipStream_t s);
+void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                      int32_t max_a, hipStream_t s);
+void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                         int32_t max_n, hipStream_t s);
+void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                       int32_t max_n, hipStream_t s);
+
+// PCG helpers (all per column j < nrhs; vectors n x nrhs, ld n)
+void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,
+                 int32_t nrhs, const double* x, double* y, hipStream_t s);
+// out[j] = sum_i x[i,j] * y[i,j] (deterministic two-stage reduction)
+void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, double* partial,
+                double* out, hipStream_t s);
+// alpha = rho/pq for active columns; x += alpha p; r -= alpha q
+void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
+                   const double* pq, const int32_t* active, int64_t n, int32_t nrhs,
+                   hipStream_t s);
+// p = z + (rho_new/rho) p for active columns (p = z when first != 0); rho <- rho_new
+void launch_pcg_p(double* p, const double* z, double* rho, const double* rho_new,
+                  const int32_t* active, int64_t n, int32_t nrhs, int32_t first, hipStream_t s);
+// y = b - y
+void launch_residual(const double* b, double* y, int64_t n, int32_t nrhs, hipStream_t s);
+void launch_copy_vec(const double* src, double* dst, int64_t count, hipStream_t s);
+
+constexpr int kDotBlocks = 256;
+
+}  // namespace spand

@@ -1,0 +1,339 @@
+// C ABI of libspand: argument checking, error translation and object lifetime.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "runtime.h"
+
+struct spand_ctx_s { spand::Ctx c; };
+struct spand_plan_s { spand::Plan p; };
+struct spand_factor_s {
+  spand::FactorObj f;
+  double* d_vals = nullptr;  // copy of A's values (SpMV inside PCG)
+  int device = 0;
+  ~spand_factor_s() { if (d_vals) (void)hipFree(d_vals); }
+};
+
+namespace spand {
+void build_apply(Ctx& C, FactorObj& F);
+void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y);
+void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const double* b, double* x,
+             double tol, int32_t maxit, int32_t* iters, double* relres, bool* converged);
+}  // namespace spand
+
+namespace {
+
+template <class F>
+spand_status guarded(spand_ctx_t ctx, F&& fn) {
+  try {
+    fn();
+    if (ctx) ctx->c.last_error.clear();
+    return SPAND_OK;
+  } catch (const spand::Error& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.last_error = "host allocation failed";
+    return SPAND_E_OOM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return SPAND_E_STATE;
+  }
+}
+
+void check_opts(const spand_opts* o) {
+  using spand::Error;
+  if (!o) throw Error(SPAND_E_INVALID, "opts is NULL");
+  if (!(o->eps >= 0.0 && o->eps <= 1.0)) throw Error(SPAND_E_INVALID, "eps must lie in [0, 1]");
+  if (o->scheme < SPAND_FIRST_ORDER || o->scheme > SPAND_SUPERFINE)
+    throw Error(SPAND_E_INVALID, "unknown scheme");
+  if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
+  if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
+}
+
+// device copies of the pattern and of the leaf assembly map, made on first use
+void upload_plan(spand::Plan& P, int device) {
+  if (P.d_rowptr) {
+    if (P.device != device) throw spand::Error(SPAND_E_STATE, "plan is bound to another device");
+    return;
+  }
+  P.device = device;
+  SPAND_HIP(hipMalloc(&P.d_rowptr, (P.n + 1) * sizeof(int64_t)));
+  SPAND_HIP(hipMalloc(&P.d_colind, std::max<int64_t>(P.nnz, 1) * sizeof(int32_t)));
+  SPAND_HIP(hipMalloc(&P.d_leaf_dest, std::max<int64_t>(P.nnz, 1) * sizeof(int64_t)));
+  SPAND_HIP(hipMemcpy(P.d_rowptr, P.rowptr.data(), (P.n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  SPAND_HIP(hipMemcpy(P.d_colind, P.colind.data(), P.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+  SPAND_HIP(hipMemcpy(P.d_leaf_dest, P.leaf_dest.data(), P.nnz * sizeof(int64_t),
+                      hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+extern "C" {
+
+void spand_default_opts(spand_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->depth = 0;
+  o->skip = 4;
+  o->eps = 1e-2;
+  o->scheme = SPAND_SECOND_ORDER;
+  o->precision = SPAND_FP64;
+  o->debug_stop_step = -1;
+}
+
+const char* spand_status_string(spand_status s) {
+  switch (s) {
+    case SPAND_OK: return "SPAND_OK";
+    case SPAND_E_INVALID: return "SPAND_E_INVALID";
+    case SPAND_E_NOT_SYMMETRIC: return "SPAND_E_NOT_SYMMETRIC";
+    case SPAND_E_NOT_SPD: return "SPAND_E_NOT_SPD";
+    case SPAND_E_NO_CONVERGENCE: return "SPAND_E_NO_CONVERGENCE";
+    case SPAND_E_OOM: return "SPAND_E_OOM";
+    case SPAND_E_HIP: return "SPAND_E_HIP";
+    case SPAND_E_STATE: return "SPAND_E_STATE";
+    case SPAND_E_LIMIT: return "SPAND_E_LIMIT";
+  }
+  return "unknown status";
+}
+
+spand_status spand_create(spand_ctx_t* out, int device, void* stream) {
+  if (!out) return SPAND_E_INVALID;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) spand_ctx_s();
+  if (!ctx) return SPAND_E_OOM;
+  spand_status st = guarded(ctx, [&] {
+    int ndev = 0;
+    SPAND_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw spand::Error(SPAND_E_INVALID, "bad device ordinal");
+    SPAND_HIP(hipSetDevice(device));
+    ctx->c.device = device;
+    if (stream) {
+      ctx->c.stream = static_cast<hipStream_t>(stream);
+    } else {
+      SPAND_HIP(hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking));
+      ctx->c.own_stream = true;
+    }
+  });
+  if (st != SPAND_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return SPAND_OK;
+}
+
+void spand_destroy(spand_ctx_t ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+  delete ctx;
+}
+
+const char* spand_last_error(spand_ctx_t ctx) { return ctx ? ctx->c.last_error.c_str() : ""; }
+
+spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                           const double* coords, int32_t dim, const spand_opts* opts,
+                           spand_plan_t* out) {
+  if (!out) return SPAND_E_INVALID;
+  *out = nullptr;
+  auto plan = std::make_unique<spand_plan_s>();
+  spand_status st = guarded(ctx, [&] {
+    using spand::Error;
+    check_opts(opts);
+    if (n <= 0 || !rowptr || !colind || !coords || dim < 1 || dim > 3)
+      throw Error(SPAND_E_INVALID, "bad matrix or coordinates");
+    if (rowptr[0] != 0 || rowptr[n] < 0) throw Error(SPAND_E_INVALID, "bad rowptr");
+    if (n >= (int64_t(1) << 31)) throw Error(SPAND_E_LIMIT, "n must be < 2^31");
+    int depth = opts->depth;
+    if (depth <= 0) depth = std::max(0, (int)std::lround(std::log2((double)n / 64.0)));
+    if (depth > 40) throw Error(SPAND_E_INVALID, "depth too large");
+    spand::Plan& P = plan->p;
+    P.n = n;
+    spand::analyze_plan(P, rowptr, colind, coords, dim, depth, opts->skip);
+    // leaf-step panel layout and the destination of every CSR value in it
+    const spand::StepPlan& st0 = P.steps[P.depth];
+    std::vector<int32_t> sizes(st0.nc), cid(n), loc(n);
+    for (int c = 0; c < st0.nc; ++c) {
+      sizes[c] = (int32_t)(st0.vert_ptr[c + 1] - st0.vert_ptr[c]);
+      for (int64_t e = st0.vert_ptr[c]; e < st0.vert_ptr[c + 1]; ++e) {
+        cid[st0.verts[e]] = c;
+        loc[st0.verts[e]] = (int32_t)(e - st0.vert_ptr[c]);
+      }
+    }
+    spand::PanelLayout lay = spand::make_layout(st0, sizes);
+    std::vector<int64_t> dest(P.nnz);
+    for (int64_t v = 0; v < n; ++v) {
+      const int c = cid[v];
+      for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1]; ++e) {
+        const int32_t u = P.colind[e];
+        const int c2 = cid[u];
+        const int32_t* b = st0.adj.data() + st0.adj_ptr[c];
+        const int32_t* en = st0.adj.data() + st0.adj_ptr[c + 1];
+        const int64_t ee = st0.adj_ptr[c] + (std::lower_bound(b, en, c2) - b);
+        dest[e] = lay.off[c] + (lay.coff[ee] + loc[u]) * sizes[c] + loc[v];
+      }
+    }
+    P.leaf_panel_elems = lay.total;
+    P.leaf_dest = std::move(dest);
+  });
+  if (st == SPAND_OK) *out = plan.release();
+  return st;
+}
+
+void spand_destroy_plan(spand_plan_t plan) { delete plan; }
+
+spand_status spand_plan_sizes(spand_plan_t plan, int64_t* n, int64_t* nnz, int32_t* depth) {
+  if (!plan) return SPAND_E_INVALID;
+  if (n) *n = plan->p.n;
+  if (nnz) *nnz = plan->p.nnz;
+  if (depth) *depth = plan->p.depth;
+  return SPAND_OK;
+}
+
+spand_status spand_plan_vertices(spand_plan_t plan, int32_t* lvl, int64_t* path, int64_t* perm) {
+  if (!plan) return SPAND_E_INVALID;
+  const spand::Plan& P = plan->p;
+  if (lvl) std::memcpy(lvl, P.lvl.data(), P.n * sizeof(int32_t));
+  if (path) std::memcpy(path, P.path.data(), P.n * sizeof(int64_t));
+  if (perm) std::memcpy(perm, P.perm.data(), P.n * sizeof(int64_t));
+  return SPAND_OK;
+}
+
+spand_status spand_plan_step_counts(spand_plan_t plan, int32_t l, int32_t* n_clusters,
+                                    int32_t* n_interior, int64_t* n_adj, int64_t* n_child,
+                                    int32_t* sparsified) {
+  if (!plan || l < 0 || l > plan->p.depth) return SPAND_E_INVALID;
+  const spand::StepPlan& st = plan->p.steps[l];
+  if (n_clusters) *n_clusters = st.nc;
+  if (n_interior) *n_interior = st.nI;
+  if (n_adj) *n_adj = (int64_t)st.adj.size();
+  if (n_child) *n_child = (int64_t)st.child.size();
+  if (sparsified) *sparsified = st.sparsified ? 1 : 0;
+  return SPAND_OK;
+}
+
+spand_status spand_plan_step_arrays(spand_plan_t plan, int32_t l, int64_t* key_lvl,
+                                    int64_t* key_prefix, int64_t* adj_ptr, int32_t* adj,
+                                    int32_t* colour, int64_t* child_ptr, int32_t* child) {
+  if (!plan || l < 0 || l > plan->p.depth) return SPAND_E_INVALID;
+  const spand::StepPlan& st = plan->p.steps[l];
+  auto cp = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  cp(key_lvl, st.key_lvl);
+  cp(key_prefix, st.key_prefix);
+  cp(adj_ptr, st.adj_ptr);
+  cp(adj, st.adj);
+  cp(colour, st.colour);
+  if (child_ptr) {
+    if (st.child_ptr.empty()) std::memset(child_ptr, 0, (st.nc + 1) * sizeof(int64_t));
+    else cp(child_ptr, st.child_ptr);
+  }
+  cp(child, st.child);
+  return SPAND_OK;
+}
+
+spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals, const spand_opts* opts,
+                          spand_factor_t* out) {
+  if (!ctx || !plan || !out) return SPAND_E_INVALID;
+  *out = nullptr;
+  auto f = std::make_unique<spand_factor_s>();
+  spand_status st = guarded(ctx, [&] {
+    check_opts(opts);
+    if (!vals) throw spand::Error(SPAND_E_INVALID, "vals is NULL");
+    if (opts->skip != plan->p.skip)
+      throw spand::Error(SPAND_E_INVALID, "skip differs from the one given to spand_analyze");
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    f->device = ctx->c.device;
+    upload_plan(plan->p, ctx->c.device);
+    const int64_t nnz = plan->p.nnz;
+    SPAND_HIP(hipMalloc(&f->d_vals, std::max<int64_t>(nnz, 1) * sizeof(double)));
+    SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->c.stream));
+    spand::run_factor(ctx->c, plan->p, f->d_vals, *opts, f->f);
+    if (f->f.stopped_at < 0) spand::build_apply(ctx->c, f->f);
+    f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();
+  });
+  if (st == SPAND_OK) *out = f.release();
+  return st;
+}
+
+void spand_destroy_factor(spand_factor_t f) {
+  if (!f) return;
+  (void)hipSetDevice(f->device);
+  delete f;
+}
+
+spand_status spand_factor_ranks(spand_factor_t f, int32_t l, int32_t* a, int32_t* k, int32_t* r,
+                                int32_t* r2) {
+  if (!f || l < 0 || l >= (int32_t)f->f.steps.size()) return SPAND_E_INVALID;
+  const spand::StepRec& R = f->f.steps[l];
+  const int nc = (int)R.r.size();
+  for (int c = 0; c < nc; ++c) {
+    const bool sp = R.r[c] >= 0;
+    if (a) a[c] = sp ? R.n0[c] : -1;
+    if (k) k[c] = R.k[c];
+    if (r) r[c] = R.r[c];
+    if (r2) r2[c] = R.r2[c];
+  }
+  return SPAND_OK;
+}
+
+spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st) {
+  if (!f || !st) return SPAND_E_INVALID;
+  *st = f->f.stats;
+  return SPAND_OK;
+}
+
+spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y) {
+  if (!ctx || !f || nrhs <= 0 || !x || !y) return SPAND_E_INVALID;
+  return guarded(ctx, [&] {
+    if (!f->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    spand::run_apply(ctx->c, f->f, nrhs, x, y);
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+  });
+}
+
+spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* b, double* x,
+                       double tol, int32_t maxit, int32_t* iters, double* relres) {
+  if (!ctx || !f || nrhs <= 0 || !b || !x || !iters || !relres || maxit < 0 || !(tol > 0))
+    return SPAND_E_INVALID;
+  bool conv = false;
+  spand_status st = guarded(ctx, [&] {
+    if (!f->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    spand::run_pcg(ctx->c, f->f, f->d_vals, nrhs, b, x, tol, maxit, iters, relres, &conv);
+  });
+  if (st == SPAND_OK && !conv) {
+    ctx->c.last_error = "PCG did not converge within maxit";
+    return SPAND_E_NO_CONVERGENCE;
+  }
+  return st;
+}
+
+spand_status spand_debug_block(spand_factor_t f, int32_t ci, int32_t cj, double* out, int32_t* rows,
+                               int32_t* cols) {
+  if (!f || f->f.stopped_at < 0 || !rows || !cols) return SPAND_E_STATE;
+  const spand::FactorObj& F = f->f;
+  const spand::StepPlan& st = F.plan->steps[F.stopped_at];
+  if (ci < 0 || cj < 0 || ci >= st.nc || cj >= st.nc) return SPAND_E_INVALID;
+  const int32_t* b = st.adj.data() + st.adj_ptr[ci];
+  const int32_t* e = st.adj.data() + st.adj_ptr[ci + 1];
+  const int32_t* it = std::lower_bound(b, e, cj);
+  if (it == e || *it != cj) return SPAND_E_INVALID;
+  const int64_t ee = st.adj_ptr[ci] + (it - b);
+  const spand::PanelLayout& L = F.dbg_layout;
+  *rows = F.dbg_ncur[ci];
+  *cols = F.dbg_ncur[cj];
+  if (out) {
+    const double* src = F.dbg_panels.data() + L.off[ci] + L.coff[ee] * L.n[ci];
+    for (int j = 0; j < *cols; ++j)
+      for (int i = 0; i < *rows; ++i) out[i + (int64_t)j * *rows] = src[i + (int64_t)j * L.n[ci]];
+  }
+  return SPAND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Work descriptors shared by the host drivers and the HIP kernels, plus the
+// kernel launchers.  Every launch works on a flat array of descriptors built
+// by the host planner for one step of the factorization (or one phase of the
+// apply), so uneven cluster sizes batch into a single launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spand {
+
+// Tie band of the pivot choice of the column-pivoted QR: columns whose
+// squared trailing norm is within this relative distance of the largest count
+// as tied, and the tie goes to the lowest column index.
+constexpr double kPivotTieRtol = 1e-8;
+
+// X = L^{-1} where A = L L^T (lower triangle of A read, ld lda; X: n x n, ld n).
+struct PotrfDesc {
+  const double* A;
+  double* X;
+  int32_t lda, n;
+  int32_t cluster;   // reported on breakdown
+  int32_t pad;
+};
+
+// One term of a multi-term GEMM: op(A) (m x k) times op(B) (k x n).
+struct GemmTerm {
+  const double* A;
+  const double* B;
+  int32_t lda, ldb, k, pad;
+};
+
+// C = beta C + alpha sum_terms op(A) op(B); when C2 != nullptr the result is
+// also stored transposed into C2 (ld ldc2).  lower_only: only tiles that touch
+// the lower triangle (square C) are computed.
+struct GemmDesc {
+  double* C;
+  double* C2;
+  int64_t term0, term1;
+  int32_t ldc, ldc2, m, n;
+  int32_t transA, transB, lower_only, pad;
+  double alpha, beta;
+};
+
+struct TileRef {
+  int32_t desc, ti, tj, pad;
+};
+
+// Early-stopping column-pivoted QR of one interface (Alg. 1).
+struct CpqrNbr {
+  double* blk_wp;    // block (w, p) in w's row panel (transposed write-back)
+  int64_t col;       // column offset of block (p, w) in p's row panel
+  int32_t w, ldw;
+};
+struct CpqrDesc {
+  double* panel;     // p's row panel, ld = a
+  double* Y;         // a x kmax workspace; holds Q^T W afterwards (E lives in rows r..)
+  double* V;         // a x min(a, kmax) Householder vectors (unit diagonal stored)
+  double* tau;       // min(a, kmax)
+  int64_t nb0, nb1;  // neighbour range
+  int64_t diag_col;  // column offset of the diagonal block (p, p)
+  int32_t a, kmax, p, pad;
+};
+
+// Dense block copy (merge of children's blocks into parent panels).
+struct CopyDesc {
+  const double* src;
+  double* dst;
+  int32_t lds, ldd, m, n;
+};
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double* panels,
+                    hipStream_t s);
+void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
+                      hipStream_t s);
+void launch_gemm(const GemmDesc* d, const GemmTerm* t, const TileRef* tiles, int64_t ntiles,
+                 hipStream_t s);
+void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n_cur,
+                 int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
+                 int32_t max_a, int32_t max_k, hipStream_t s);
+void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
+
+constexpr int kGemmTile = 64;
+constexpr int kPotrfLdsMax = 128;     // n <= this: factor and invert inside LDS
+constexpr int kCpqrMaxK = 12288;      // trailing norms of a CPQR live in LDS
+
+}  // namespace spand

@@ -1,0 +1,550 @@
+// Host driver of the level-by-level factorization (Alg. 2).
+//
+// For every step l = depth ... 0 the planner lays out the row panels of the
+// step's clusters (cluster c: n_c x sum_{j in adj(c)} n_j, column-major,
+// both orientations of every off-diagonal block), builds flat descriptor
+// lists and issues batched launches:
+//   interiors : L_s^{-1} (k_potrf_inv), G_s = L_s^{-1} B_sW (k_gemm),
+//               B_{w1 w2} -= G_{s,w1}^T G_{s,w2} summed over the interiors
+//               bordering both, in ascending interior order (k_gemm);
+//   scaling   : Z_p^{-1} (k_potrf_inv), B_pq <- Z_p^{-1} B_pq Z_q^{-T} (k_gemm x2);
+//   sparsify  : one k_cpqr launch per colour;
+//   merge     : parent panels assembled from the children's current blocks.
+// The ranks of a step decide the next step's sizes; they are read back once
+// per step (a few KB).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace spand {
+
+// ---------------------------------------------------------------------------
+// memory helpers
+// ---------------------------------------------------------------------------
+void* DevArena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    if (used_ + bytes <= chunks_[cur_].size) {
+      void* p = chunks_[cur_].p + used_;
+      used_ += bytes;
+      return p;
+    }
+    ++cur_;
+    used_ = 0;
+  }
+  size_t sz = std::max<size_t>(bytes, size_t(64) << 20);
+  char* p = nullptr;
+  SPAND_HIP(hipMalloc(&p, sz));
+  chunks_.push_back({p, sz});
+  reserved_ += sz;
+  cur_ = chunks_.size() - 1;
+  used_ = bytes;
+  return p;
+}
+
+void* PinnedArena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    if (used_ + bytes <= chunks_[cur_].size) {
+      void* p = chunks_[cur_].p + used_;
+      used_ += bytes;
+      return p;
+    }
+    ++cur_;
+    used_ = 0;
+  }
+  size_t sz = std::max<size_t>(bytes, size_t(16) << 20);
+  char* p = nullptr;
+  SPAND_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sz, hipHostMallocDefault));
+  chunks_.push_back({p, sz});
+  cur_ = chunks_.size() - 1;
+  used_ = bytes;
+  return p;
+}
+
+void PinnedArena::release() {
+  for (auto& c : chunks_) (void)hipHostFree(c.p);
+  chunks_.clear();
+  cur_ = used_ = 0;
+}
+
+void DevArena::release() {
+  for (auto& c : chunks_) (void)hipFree(c.p);
+  chunks_.clear();
+  cur_ = used_ = reserved_ = 0;
+}
+
+size_t DevArena::bytes_used() const {
+  size_t s = 0;
+  for (size_t i = 0; i < cur_ && i < chunks_.size(); ++i) s += chunks_[i].size;
+  return s + used_;
+}
+
+void* DevBuf::ensure(size_t need) {
+  if (need <= bytes && p) return p;
+  release();
+  size_t sz = std::max<size_t>(need, 1 << 20);
+  sz += sz / 4;
+  SPAND_HIP(hipMalloc(&p, sz));
+  bytes = sz;
+  return p;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+Plan::~Plan() {
+  if (d_rowptr) (void)hipFree(d_rowptr);
+  if (d_colind) (void)hipFree(d_colind);
+  if (d_leaf_dest) (void)hipFree(d_leaf_dest);
+}
+
+namespace {
+
+inline int64_t find_adj(const StepPlan& st, int c, int target) {
+  const int32_t* b = st.adj.data() + st.adj_ptr[c];
+  const int32_t* e = st.adj.data() + st.adj_ptr[c + 1];
+  const int32_t* it = std::lower_bound(b, e, target);
+  if (it == e || *it != target) return -1;
+  return st.adj_ptr[c] + (it - b);
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, bool lower_only) {
+  const int tm = (int)ceil_div(m, kGemmTile), tn = (int)ceil_div(n, kGemmTile);
+  for (int j = 0; j < tn; ++j)
+    for (int i = 0; i < tm; ++i)
+      if (!lower_only || i >= j) tiles.push_back({desc, i, j, 0});
+}
+
+void check_info(const std::vector<int32_t>& info, const std::vector<int32_t>& clusters, int l,
+                const char* what) {
+  for (size_t i = 0; i < info.size(); ++i)
+    if (info[i] != 0)
+      throw Error(SPAND_E_NOT_SPD, std::string(what) + " not SPD at step " + std::to_string(l) +
+                                       ", cluster " + std::to_string(clusters[i]) + " (column " +
+                                       std::to_string(info[i] - 1) + ")");
+}
+
+}  // namespace
+
+void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = C.stream;
+  const int D = P.depth;
+  F.plan = &P;
+  F.opts = o;
+  F.steps.assign(D + 1, StepRec());
+  const bool so = o.scheme == SPAND_SECOND_ORDER;
+  const bool sf = o.scheme == SPAND_SUPERFINE;
+  const double eps = o.eps;
+  const double eps_stop = sf ? eps * eps : eps;
+  double flops = 0.0;
+  int64_t nnzL = 0;
+
+  // leaf step: sizes are the vertex counts
+  std::vector<int32_t> sizes(P.steps[D].nc);
+  for (int c = 0; c < P.steps[D].nc; ++c)
+    sizes[c] = (int32_t)(P.steps[D].vert_ptr[c + 1] - P.steps[D].vert_ptr[c]);
+  std::vector<std::vector<int32_t>> pos(P.steps[D].nc);
+  for (int c = 0; c < P.steps[D].nc; ++c)
+    pos[c].assign(P.steps[D].verts.begin() + P.steps[D].vert_ptr[c],
+                  P.steps[D].verts.begin() + P.steps[D].vert_ptr[c + 1]);
+
+  int cur = 0;
+  PanelLayout lay = make_layout(P.steps[D], sizes);
+  double* panel = static_cast<double*>(C.panels[cur].ensure(lay.total * sizeof(double)));
+  launch_fill(panel, lay.total, 0.0, s);
+  launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s);
+
+  for (int l = D; l >= 0; --l) {
+    const StepPlan& st = P.steps[l];
+    StepRec& R = F.steps[l];
+    C.upload.reset();
+    C.stage.reset();
+    R.l = l;
+    R.sparsified = st.sparsified;
+    R.n0 = sizes;
+    R.pos = pos;
+    const int nI = st.nI, nc = st.nc;
+    R.r.assign(nc, -1);
+    R.r2.assign(nc, -1);
+    R.k.assign(nc, -1);
+    R.Linv.assign(nc, nullptr);
+    R.G.assign(nc, nullptr);
+    R.kint.assign(nc, 0);
+    R.Zinv.assign(nc, nullptr);
+    R.Y.assign(nc, nullptr);
+    R.V.assign(nc, nullptr);
+    R.tau.assign(nc, nullptr);
+    R.sp_nbr_pos.assign(nc, {});
+    auto blk = [&](int c, int64_t e) { return panel + lay.off[c] + lay.coff[e] * lay.n[c]; };
+
+    // per-step integer outputs: n_cur | r | r2 | k | info (interiors) | info (interfaces)
+    int32_t* dint = static_cast<int32_t*>(C.ints.ensure(sizeof(int32_t) * (6 * (size_t)nc + 64)));
+    int32_t* d_ncur = dint;
+    int32_t* d_r = dint + nc;
+    int32_t* d_r2 = dint + 2 * nc;
+    int32_t* d_k = dint + 3 * nc;
+    int32_t* d_info_i = dint + 4 * nc;
+    int32_t* d_info_f = dint + 5 * nc;
+    SPAND_HIP(hipMemsetAsync(dint, 0, sizeof(int32_t) * 6 * (size_t)nc, s));
+    {
+      void* h = C.stage.alloc(sizeof(int32_t) * nc);
+      std::memcpy(h, sizes.data(), sizeof(int32_t) * nc);
+      SPAND_HIP(hipMemcpyAsync(d_ncur, h, sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+    }
+
+    // ---------------- (a) interiors ----------------
+    std::vector<PotrfDesc> pd;
+    std::vector<int32_t> pd_cluster;
+    int max_n = 0;
+    for (int sI = 0; sI < nI; ++sI) {
+      const int ns = sizes[sI];
+      const int64_t ks = lay.width[sI] - ns;
+      R.kint[sI] = (int32_t)ks;
+      if (ns == 0) continue;
+      R.Linv[sI] = F.arena.alloc_n<double>((size_t)ns * ns);
+      if (ks > 0) R.G[sI] = F.arena.alloc_n<double>((size_t)ns * ks);
+      pd.push_back({panel + lay.off[sI], R.Linv[sI], ns, ns, sI, 0});
+      pd_cluster.push_back(sI);
+      max_n = std::max(max_n, ns);
+      flops += (double)ns * ns * ns / 3.0 + (double)ns * ns * ks + (double)ns * ks * ks;
+      nnzL += (int64_t)ns * (ns + 1) / 2 + (int64_t)ns * ks;
+    }
+    if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
+    if (!pd.empty()) {
+      launch_potrf_inv(C.upload.upload(pd, s, C.stage), (int32_t)pd.size(), max_n, d_info_i, s);
+      // G_s = L_s^{-1} B_{s,W}
+      std::vector<GemmDesc> gd;
+      std::vector<GemmTerm> gt;
+      std::vector<TileRef> tiles;
+      for (int sI = 0; sI < nI; ++sI) {
+        const int ns = sizes[sI];
+        const int ks = R.kint[sI];
+        if (ns == 0 || ks == 0) continue;
+        gt.push_back({R.Linv[sI], panel + lay.off[sI] + (int64_t)ns * ns, ns, ns, ns, 0});
+        GemmDesc g{};
+        g.C = R.G[sI];
+        g.C2 = nullptr;
+        g.term0 = (int64_t)gt.size() - 1;
+        g.term1 = (int64_t)gt.size();
+        g.ldc = ns;
+        g.m = ns;
+        g.n = ks;
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        gd.push_back(g);
+        add_gemm_tiles(tiles, (int32_t)gd.size() - 1, ns, ks, false);
+      }
+      if (!tiles.empty())
+        launch_gemm(C.upload.upload(gd, s, C.stage), C.upload.upload(gt, s, C.stage), C.upload.upload(tiles, s, C.stage),
+                    (int64_t)tiles.size(), s);
+      // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2}
+      gd.clear();
+      gt.clear();
+      tiles.clear();
+      for (int w1 = nI; w1 < nc; ++w1) {
+        if (sizes[w1] == 0) continue;
+        const int64_t b1 = st.adj_ptr[w1], e1 = st.adj_ptr[w1 + 1];
+        int64_t i1end = b1;
+        while (i1end < e1 && st.adj[i1end] < nI) ++i1end;
+        if (i1end == b1) continue;  // no interior neighbour
+        for (int64_t e = i1end; e < e1; ++e) {
+          const int w2 = st.adj[e];
+          if (w2 < w1 || sizes[w2] == 0) continue;
+          const int64_t b2 = st.adj_ptr[w2];
+          const int64_t t0 = (int64_t)gt.size();
+          int64_t x = b1, y = b2;
+          while (x < i1end && y < st.adj_ptr[w2 + 1] && st.adj[y] < nI) {
+            if (st.adj[x] < st.adj[y]) ++x;
+            else if (st.adj[y] < st.adj[x]) ++y;
+            else {
+              const int sI = st.adj[x];
+              const int ns = sizes[sI];
+              if (ns > 0) {
+                const int64_t c1 = lay.coff[find_adj(st, sI, w1)] - ns;
+                const int64_t c2 = lay.coff[find_adj(st, sI, w2)] - ns;
+                gt.push_back({R.G[sI] + c1 * ns, R.G[sI] + c2 * ns, ns, ns, ns, 0});
+              }
+              ++x;
+              ++y;
+            }
+          }
+          if ((int64_t)gt.size() == t0) continue;
+          GemmDesc g{};
+          g.C = blk(w1, e);
+          g.C2 = w1 == w2 ? nullptr : blk(w2, find_adj(st, w2, w1));
+          g.term0 = t0;
+          g.term1 = (int64_t)gt.size();
+          g.ldc = sizes[w1];
+          g.ldc2 = sizes[w2];
+          g.m = sizes[w1];
+          g.n = sizes[w2];
+          g.transA = 1;
+          g.transB = 0;
+          g.lower_only = w1 == w2;
+          g.alpha = -1.0;
+          g.beta = 1.0;
+          gd.push_back(g);
+          add_gemm_tiles(tiles, (int32_t)gd.size() - 1, g.m, g.n, w1 == w2);
+        }
+      }
+      if (!tiles.empty())
+        launch_gemm(C.upload.upload(gd, s, C.stage), C.upload.upload(gt, s, C.stage), C.upload.upload(tiles, s, C.stage),
+                    (int64_t)tiles.size(), s);
+    }
+
+    if (l == 0) {
+      std::vector<int32_t> info(pd.size());
+      if (!pd.empty())
+        SPAND_HIP(hipMemcpyAsync(info.data(), d_info_i, sizeof(int32_t) * pd.size(),
+                                 hipMemcpyDeviceToHost, s));
+      SPAND_HIP(hipStreamSynchronize(s));
+      check_info(info, pd_cluster, l, "interior block");
+      F.stats.root_size = nc > 0 ? sizes[0] : 0;
+      break;
+    }
+
+    // ---------------- (b) scaling and (c) sparsification ----------------
+    std::vector<PotrfDesc> zd;
+    std::vector<int32_t> zd_cluster;
+    if (st.sparsified) {
+      int max_a = 0;
+      for (int p = nI; p < nc; ++p) {
+        const int a = sizes[p];
+        if (a == 0) continue;
+        R.Zinv[p] = F.arena.alloc_n<double>((size_t)a * a);
+        zd.push_back({blk(p, find_adj(st, p, p)), R.Zinv[p], a, a, p, 0});
+        zd_cluster.push_back(p);
+        max_a = std::max(max_a, a);
+        flops += (double)a * a * a / 3.0;
+        nnzL += (int64_t)a * (a + 1) / 2;
+      }
+      if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
+      launch_potrf_inv(C.upload.upload(zd, s, C.stage), (int32_t)zd.size(), max_a, d_info_f, s);
+      // two-sided scaling of every interface pair p < q
+      std::vector<GemmDesc> g1, g2;
+      std::vector<GemmTerm> t1, t2;
+      std::vector<TileRef> tl1, tl2;
+      int64_t toff = 0;
+      std::vector<int64_t> tpos;
+      for (int p = nI; p < nc; ++p)
+        for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+          const int q = st.adj[e];
+          if (q <= p || sizes[p] == 0 || sizes[q] == 0) continue;
+          tpos.push_back(toff);
+          toff += (int64_t)sizes[p] * sizes[q];
+        }
+      double* T = static_cast<double*>(C.temp.ensure(std::max<int64_t>(toff, 1) * sizeof(double)));
+      size_t ti = 0;
+      for (int p = nI; p < nc; ++p)
+        for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+          const int q = st.adj[e];
+          if (q <= p || sizes[p] == 0 || sizes[q] == 0) continue;
+          const int ap = sizes[p], aq = sizes[q];
+          double* Tpq = T + tpos[ti++];
+          t1.push_back({R.Zinv[p], blk(p, e), ap, ap, ap, 0});
+          GemmDesc a{};
+          a.C = Tpq;
+          a.term0 = (int64_t)t1.size() - 1;
+          a.term1 = (int64_t)t1.size();
+          a.ldc = ap;
+          a.m = ap;
+          a.n = aq;
+          a.alpha = 1.0;
+          g1.push_back(a);
+          add_gemm_tiles(tl1, (int32_t)g1.size() - 1, ap, aq, false);
+          t2.push_back({Tpq, R.Zinv[q], ap, aq, aq, 0});
+          GemmDesc b{};
+          b.C = blk(p, e);
+          b.C2 = blk(q, find_adj(st, q, p));
+          b.term0 = (int64_t)t2.size() - 1;
+          b.term1 = (int64_t)t2.size();
+          b.ldc = ap;
+          b.ldc2 = aq;
+          b.m = ap;
+          b.n = aq;
+          b.transB = 1;
+          b.alpha = 1.0;
+          g2.push_back(b);
+          add_gemm_tiles(tl2, (int32_t)g2.size() - 1, ap, aq, false);
+        }
+      if (!tl1.empty()) {
+        launch_gemm(C.upload.upload(g1, s, C.stage), C.upload.upload(t1, s, C.stage), C.upload.upload(tl1, s, C.stage),
+                    (int64_t)tl1.size(), s);
+        launch_gemm(C.upload.upload(g2, s, C.stage), C.upload.upload(t2, s, C.stage), C.upload.upload(tl2, s, C.stage),
+                    (int64_t)tl2.size(), s);
+      }
+      // sparsification, one launch per colour
+      for (int colour = 0; colour < st.ncolours; ++colour) {
+        std::vector<CpqrDesc> cd;
+        std::vector<CpqrNbr> cn;
+        int ma = 1, mk = 1;
+        for (int p : st.order) {
+          if (st.colour[p] != colour) continue;
+          const int a = sizes[p];
+          CpqrDesc d{};
+          d.panel = panel + lay.off[p];
+          d.a = a;
+          d.p = p;
+          d.nb0 = (int64_t)cn.size();
+          int64_t kmax = 0;
+          for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+            const int w = st.adj[e];
+            if (w == p) { d.diag_col = lay.coff[e]; continue; }
+            if (w < nI) continue;
+            CpqrNbr nb{};
+            nb.blk_wp = blk(w, find_adj(st, w, p));
+            nb.col = lay.coff[e];
+            nb.w = w;
+            nb.ldw = sizes[w];
+            cn.push_back(nb);
+            kmax += sizes[w];
+          }
+          d.nb1 = (int64_t)cn.size();
+          d.kmax = (int32_t)kmax;
+          if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
+                                                               std::to_string(kCpqrMaxK));
+          const int64_t mn = std::min<int64_t>(a, kmax);
+          if (a > 0 && kmax > 0) {
+            R.Y[p] = F.arena.alloc_n<double>((size_t)a * kmax);
+            R.V[p] = F.arena.alloc_n<double>((size_t)a * mn);
+            R.tau[p] = F.arena.alloc_n<double>((size_t)mn);
+          }
+          d.Y = R.Y[p];
+          d.V = R.V[p];
+          d.tau = R.tau[p];
+          ma = std::max(ma, a);
+          mk = std::max<int>(mk, (int)kmax);
+          cd.push_back(d);
+        }
+        if (cd.empty()) continue;
+        launch_cpqr(C.upload.upload(cd, s, C.stage), C.upload.upload(cn, s, C.stage), (int32_t)cd.size(), d_ncur, d_r,
+                    d_r2, d_k, eps, eps_stop, ma, mk, s);
+      }
+    }
+    // read back breakdown flags and ranks
+    std::vector<int32_t> info_i(pd.size()), info_f(zd.size()), hr(nc), hr2(nc), hk(nc);
+    if (!pd.empty())
+      SPAND_HIP(hipMemcpyAsync(info_i.data(), d_info_i, sizeof(int32_t) * pd.size(),
+                               hipMemcpyDeviceToHost, s));
+    if (!zd.empty())
+      SPAND_HIP(hipMemcpyAsync(info_f.data(), d_info_f, sizeof(int32_t) * zd.size(),
+                               hipMemcpyDeviceToHost, s));
+    if (st.sparsified) {
+      SPAND_HIP(hipMemcpyAsync(hr.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+      SPAND_HIP(hipMemcpyAsync(hr2.data(), d_r2, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+      SPAND_HIP(hipMemcpyAsync(hk.data(), d_k, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+    }
+    SPAND_HIP(hipStreamSynchronize(s));
+    check_info(info_i, pd_cluster, l, "interior block");
+    check_info(info_f, zd_cluster, l, "interface block");
+
+    std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
+    if (st.sparsified) {
+      // sizes of the neighbours at the time each interface was sparsified
+      for (int p = nI; p < nc; ++p) {
+        R.r[p] = hr[p];
+        R.r2[p] = hr2[p];
+        R.k[p] = hk[p];
+        cur_sizes[p] = hr[p];
+      }
+      for (int p = nI; p < nc; ++p) {
+        auto& np = R.sp_nbr_pos[p];
+        for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+          const int w = st.adj[e];
+          if (w == p || w < nI) continue;
+          const int wc = st.colour[w] < st.colour[p] ? R.r[w] : sizes[w];
+          np.insert(np.end(), pos[w].begin(), pos[w].begin() + wc);
+        }
+        if ((int)np.size() != R.k[p])
+          throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " +
+                                         std::to_string(l));
+        const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
+        flops += (double)a * a * k;
+        for (int j = 0; j < r2; ++j) flops += 4.0 * (a - j) * (double)(k - j);
+        nnzL += (int64_t)a * r2 - (int64_t)r2 * (r2 - 1) / 2 + r2;
+        if (so) nnzL += (int64_t)(a - r) * (k - r);
+        if (sf) {
+          const int64_t m2 = r2 - r;
+          nnzL += m2 * (k - r) - m2 * (m2 - 1) / 2;
+        }
+      }
+    }
+
+    if (o.debug_stop_step == l) {
+      F.stopped_at = l;
+      F.dbg_layout = lay;
+      F.dbg_ncur = cur_sizes;
+      F.dbg_panels.resize(lay.total);
+      SPAND_HIP(hipMemcpy(F.dbg_panels.data(), panel, lay.total * sizeof(double),
+                          hipMemcpyDeviceToHost));
+      break;
+    }
+
+    // ---------------- (d) merge into step l-1 ----------------
+    const StepPlan& nx = P.steps[l - 1];
+    std::vector<int32_t> nsz(nx.nc, 0);
+    std::vector<std::vector<int32_t>> npos(nx.nc);
+    std::vector<int32_t> choff(st.nc, 0);  // row offset of a child inside its parent
+    for (int c = 0; c < nx.nc; ++c)
+      for (int64_t e = nx.child_ptr[c]; e < nx.child_ptr[c + 1]; ++e) {
+        const int ch = nx.child[e];
+        choff[ch] = nsz[c];
+        nsz[c] += cur_sizes[ch];
+        npos[c].insert(npos[c].end(), pos[ch].begin(), pos[ch].begin() + cur_sizes[ch]);
+      }
+    PanelLayout nlay = make_layout(nx, nsz);
+    double* npanel =
+        static_cast<double*>(C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
+    launch_fill(npanel, nlay.total, 0.0, s);
+    std::vector<CopyDesc> cp;
+    for (int P_ = 0; P_ < nx.nc; ++P_)
+      for (int64_t e = nx.adj_ptr[P_]; e < nx.adj_ptr[P_ + 1]; ++e) {
+        const int Q = nx.adj[e];
+        for (int64_t a = nx.child_ptr[P_]; a < nx.child_ptr[P_ + 1]; ++a) {
+          const int ci = nx.child[a];
+          if (cur_sizes[ci] == 0) continue;
+          for (int64_t b = nx.child_ptr[Q]; b < nx.child_ptr[Q + 1]; ++b) {
+            const int cj = nx.child[b];
+            if (cur_sizes[cj] == 0) continue;
+            const int64_t ee = find_adj(st, ci, cj);
+            if (ee < 0) continue;
+            CopyDesc d{};
+            d.src = blk(ci, ee);
+            d.lds = sizes[ci];
+            d.dst = npanel + nlay.off[P_] + (nlay.coff[e] + choff[cj]) * nsz[P_] + choff[ci];
+            d.ldd = nsz[P_];
+            d.m = cur_sizes[ci];
+            d.n = cur_sizes[cj];
+            cp.push_back(d);
+          }
+        }
+      }
+    launch_copy(C.upload.upload(cp, s, C.stage), (int64_t)cp.size(), s);
+    SPAND_HIP(hipStreamSynchronize(s));
+    cur = 1 - cur;
+    panel = npanel;
+    lay = std::move(nlay);
+    sizes = std::move(nsz);
+    pos = std::move(npos);
+  }
+  SPAND_HIP(hipStreamSynchronize(s));
+  F.stats.flops = flops;
+  F.stats.nnz_L = nnzL;
+  F.stats.factor_bytes = (int64_t)F.arena.bytes_used();
+  F.stats.factor_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace spand

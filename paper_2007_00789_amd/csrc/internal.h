@@ -1,0 +1,85 @@
+// Internal structures of libspand (host side).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/spand.h"
+
+namespace spand {
+
+// Error carried from deep inside the library to the C ABI boundary.
+struct Error : std::runtime_error {
+  spand_status code;
+  Error(spand_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPAND_HIP(call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::spand::Error(e_ == hipErrorOutOfMemory ? SPAND_E_OOM : SPAND_E_HIP,         \
+                           std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Symbolic plan (result of analyze)
+// ---------------------------------------------------------------------------
+struct StepPlan {
+  int l = 0;
+  int nI = 0;                          // interiors are clusters [0, nI)
+  int nc = 0;                          // clusters [nI, nc) are interfaces
+  bool sparsified = false;
+  std::vector<int64_t> key_lvl, key_prefix;
+  std::vector<int64_t> adj_ptr;        // CSR of the cluster adjacency (sorted, incl. self)
+  std::vector<int32_t> adj;
+  std::vector<int32_t> colour;         // -1 for interiors
+  int ncolours = 0;
+  std::vector<int32_t> order;          // interfaces in (colour, index) order
+  std::vector<int64_t> child_ptr;      // l < depth: children in step l+1
+  std::vector<int32_t> child;
+  std::vector<int32_t> parent;         // index in step l-1 (-1 for interiors / l == 0)
+  std::vector<int64_t> vert_ptr;       // l == depth: vertices of each cluster, ascending
+  std::vector<int32_t> verts;
+};
+
+struct Plan {
+  int64_t n = 0, nnz = 0;
+  int depth = 0, skip = 4, dim = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> colind;
+  std::vector<int32_t> lvl;
+  std::vector<int64_t> path;
+  std::vector<int64_t> perm;
+  std::vector<StepPlan> steps;         // indexed by l
+  // device copies of the pattern (SpMV) and of the leaf assembly map
+  int device = 0;
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_colind = nullptr;
+  int64_t* d_leaf_dest = nullptr;      // nnz: destination of each value in the leaf panels
+  std::vector<int64_t> leaf_dest;      // host copy of the same map
+  int64_t leaf_panel_elems = 0;
+  std::vector<int64_t> leaf_panel_off; // per leaf-step cluster
+  ~Plan();
+};
+
+void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const double* coords,
+                  int dim, int depth, int skip);
+
+// Layout of one step's row panels: cluster c holds rows n[c] x width[c] in
+// column-major order (ld = n[c]) at offset off[c]; the block (c, adj[e]) starts
+// at column coff[e].
+struct PanelLayout {
+  std::vector<int32_t> n;
+  std::vector<int64_t> off;
+  std::vector<int64_t> width;
+  std::vector<int64_t> coff;   // per adjacency entry
+  int64_t total = 0;
+};
+PanelLayout make_layout(const StepPlan& st, const std::vector<int32_t>& sizes);
+
+}  // namespace spand

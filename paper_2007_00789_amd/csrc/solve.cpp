@@ -1,0 +1,314 @@
+// Preconditioner apply y = M x, M = L^{-T} L^{-1} (Alg. 2 caption), and PCG
+// (Sec. 4: zero initial guess, stop when ||r_k|| < tol ||b|| per column).
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "apply.h"
+#include "runtime.h"
+
+namespace spand {
+
+struct ApplyColour {
+  ApSp* sp = nullptr;
+  int32_t n_sp = 0, max_a = 0;
+  ApGat* gat = nullptr;
+  ApSrc* src = nullptr;
+  int32_t n_gat = 0, max_n = 0;
+};
+
+struct ApplyStep {
+  int l = 0;
+  ApInt* in = nullptr;
+  int32_t n_in = 0, max_in = 0;
+  ApGat* gat = nullptr;
+  ApSrc* src = nullptr;
+  int32_t n_gat = 0, max_gat = 0;
+  std::vector<ApplyColour> colours;
+  ApScale* sc = nullptr;
+  int32_t n_sc = 0, max_sc = 0;
+};
+
+struct ApplyProg {
+  std::vector<ApplyStep> steps;  // in forward order (depth ... 0)
+  int64_t scratch = 0;           // doubles per right-hand side
+  DevBuf T;
+};
+
+FactorObj::~FactorObj() { delete prog; }
+
+namespace {
+
+int64_t find_adj(const StepPlan& st, int c, int target) {
+  const int32_t* b = st.adj.data() + st.adj_ptr[c];
+  const int32_t* e = st.adj.data() + st.adj_ptr[c + 1];
+  const int32_t* it = std::lower_bound(b, e, target);
+  if (it == e || *it != target) return -1;
+  return st.adj_ptr[c] + (it - b);
+}
+
+}  // namespace
+
+void build_apply(Ctx& C, FactorObj& F) {
+  hipStream_t s = C.stream;
+  const Plan& P = *F.plan;
+  SPAND_HIP(hipStreamSynchronize(s));
+  C.stage.reset();
+  auto* prog = new ApplyProg();
+  F.prog = prog;
+  const bool so = F.opts.scheme == SPAND_SECOND_ORDER;
+  const bool sf = F.opts.scheme == SPAND_SUPERFINE;
+  for (int l = P.depth; l >= 0; --l) {
+    const StepPlan& st = P.steps[l];
+    const StepRec& R = F.steps[l];
+    if (R.n0.empty()) break;  // stopped early
+    ApplyStep as;
+    as.l = l;
+    const int nI = st.nI, nc = st.nc;
+    std::vector<const int32_t*> dpos(nc, nullptr);
+    for (int c = 0; c < nc; ++c) dpos[c] = F.arena.upload(R.pos[c], s, C.stage);
+    // interiors
+    std::vector<ApInt> ins;
+    std::vector<int64_t> toff(nc, 0);
+    int64_t tsz = 0;
+    for (int sI = 0; sI < nI; ++sI) {
+      const int n = R.n0[sI];
+      if (n == 0) continue;
+      std::vector<int32_t> nbr;
+      for (int64_t e = st.adj_ptr[sI]; e < st.adj_ptr[sI + 1]; ++e) {
+        const int w = st.adj[e];
+        if (w == sI) continue;
+        nbr.insert(nbr.end(), R.pos[w].begin(), R.pos[w].end());
+      }
+      ApInt d{};
+      d.Linv = R.Linv[sI];
+      d.G = R.G[sI];
+      d.pos = dpos[sI];
+      d.nbr_pos = F.arena.upload(nbr, s, C.stage);
+      d.toff = tsz;
+      d.n = n;
+      d.k = (int32_t)nbr.size();
+      toff[sI] = tsz;
+      tsz += d.k;
+      ins.push_back(d);
+      as.max_in = std::max(as.max_in, n);
+    }
+    prog->scratch = std::max(prog->scratch, tsz);
+    as.in = F.arena.upload(ins, s, C.stage);
+    as.n_in = (int32_t)ins.size();
+    // interface gathers (+ scaling)
+    std::vector<ApGat> gs;
+    std::vector<ApSrc> srcs;
+    std::vector<ApScale> scs;
+    for (int w = nI; w < nc; ++w) {
+      const int n = R.n0[w];
+      if (n == 0) continue;
+      ApGat g{};
+      g.pos = dpos[w];
+      g.Zinv = st.sparsified ? R.Zinv[w] : nullptr;
+      g.src0 = (int64_t)srcs.size();
+      for (int64_t e = st.adj_ptr[w]; e < st.adj_ptr[w + 1]; ++e) {
+        const int sI = st.adj[e];
+        if (sI >= nI) break;
+        if (R.n0[sI] == 0) continue;
+        const int64_t ee = find_adj(st, sI, w);
+        // column of w inside G_s: sum of the sizes of s's earlier neighbours
+        int32_t col = 0;
+        for (int64_t q = st.adj_ptr[sI]; q < ee; ++q)
+          if (st.adj[q] != sI) col += R.n0[st.adj[q]];
+        srcs.push_back({toff[sI], col, R.kint[sI]});
+      }
+      g.src1 = (int64_t)srcs.size();
+      g.n = n;
+      if (g.src1 > g.src0 || g.Zinv) {
+        gs.push_back(g);
+        as.max_gat = std::max(as.max_gat, n);
+      }
+      if (st.sparsified) {
+        scs.push_back({R.Zinv[w], dpos[w], n, 0});
+        as.max_sc = std::max(as.max_sc, n);
+      }
+    }
+    as.gat = F.arena.upload(gs, s, C.stage);
+    as.src = F.arena.upload(srcs, s, C.stage);
+    as.n_gat = (int32_t)gs.size();
+    as.sc = F.arena.upload(scs, s, C.stage);
+    as.n_sc = (int32_t)scs.size();
+    // sparsification, per colour
+    if (st.sparsified) {
+      as.colours.resize(st.ncolours);
+      for (int colour = 0; colour < st.ncolours; ++colour) {
+        ApplyColour& ac = as.colours[colour];
+        std::vector<ApSp> sps;
+        int64_t csz = 0;
+        std::vector<int64_t> ptoff(nc, -1);
+        for (int p : st.order) {
+          if (st.colour[p] != colour || R.n0[p] == 0) continue;
+          ApSp d{};
+          d.V = R.V[p];
+          d.tau = R.tau[p];
+          d.pos = dpos[p];
+          d.nbr_pos = F.arena.upload(R.sp_nbr_pos[p], s, C.stage);
+          d.a = R.n0[p];
+          d.nref = R.r2[p];
+          d.f0 = R.r[p];
+          d.f1 = so ? R.n0[p] : (sf ? R.r2[p] : R.r[p]);
+          d.k = R.k[p];
+          d.E = (so || sf) && R.Y[p] ? R.Y[p] + d.f0 : nullptr;
+          d.toff = csz;
+          ptoff[p] = csz;
+          csz += d.k;
+          sps.push_back(d);
+          ac.max_a = std::max(ac.max_a, d.a);
+        }
+        prog->scratch = std::max(prog->scratch, csz);
+        ac.sp = F.arena.upload(sps, s, C.stage);
+        ac.n_sp = (int32_t)sps.size();
+        if (!(so || sf)) continue;
+        // targets: interfaces adjacent to an interface of this colour
+        std::vector<ApGat> eg;
+        std::vector<ApSrc> es;
+        for (int w = nI; w < nc; ++w) {
+          if (st.colour[w] == colour) continue;
+          const int wc = st.colour[w] < colour ? R.r[w] : R.n0[w];
+          if (wc == 0) continue;
+          ApGat g{};
+          g.pos = dpos[w];
+          g.src0 = (int64_t)es.size();
+          for (int64_t e = st.adj_ptr[w]; e < st.adj_ptr[w + 1]; ++e) {
+            const int p = st.adj[e];
+            if (p < nI || st.colour[p] != colour || ptoff[p] < 0) continue;
+            if (R.r[p] >= (so ? R.n0[p] : R.r2[p])) continue;  // no fine rows: E empty
+            // offset of w inside W_p
+            int32_t col = 0;
+            for (int64_t q = st.adj_ptr[p]; q < st.adj_ptr[p + 1]; ++q) {
+              const int x = st.adj[q];
+              if (x == p || x < nI) continue;
+              if (x == w) break;
+              col += st.colour[x] < colour ? R.r[x] : R.n0[x];
+            }
+            es.push_back({ptoff[p], col, R.k[p]});
+          }
+          g.src1 = (int64_t)es.size();
+          g.n = wc;
+          if (g.src1 > g.src0) {
+            eg.push_back(g);
+            ac.max_n = std::max(ac.max_n, wc);
+          }
+        }
+        ac.gat = F.arena.upload(eg, s, C.stage);
+        ac.src = F.arena.upload(es, s, C.stage);
+        ac.n_gat = (int32_t)eg.size();
+      }
+    }
+    prog->steps.push_back(std::move(as));
+  }
+  SPAND_HIP(hipStreamSynchronize(s));
+}
+
+// y = M x for nrhs columns (x and y may alias)
+void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
+  hipStream_t s = C.stream;
+  const int64_t n = F.plan->n;
+  ApplyProg& pg = *F.prog;
+  double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
+  // every apply kernel stages its cluster's slice of the vectors in LDS
+  constexpr int64_t kLds = 160 * 1024;
+  for (const ApplyStep& as : pg.steps) {
+    int64_t need = std::max<int64_t>(2 * as.max_in, std::max(as.max_gat, as.max_sc));
+    for (const ApplyColour& ac : as.colours) need = std::max<int64_t>(need, std::max(ac.max_a, ac.max_n));
+    if (need * nrhs * (int64_t)sizeof(double) > kLds)
+      throw Error(SPAND_E_LIMIT, "cluster too large for the apply with nrhs = " + std::to_string(nrhs));
+  }
+  if (x != y) launch_copy_vec(x, y, n * nrhs, s);
+  for (const ApplyStep& as : pg.steps) {
+    launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s);
+    launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s);
+    for (const ApplyColour& ac : as.colours) {
+      launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, T, ac.max_a, s);
+      launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s);
+    }
+  }
+  for (auto it = pg.steps.rbegin(); it != pg.steps.rend(); ++it) {
+    const ApplyStep& as = *it;
+    for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c)
+      launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, c->max_a, s);
+    launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s);
+    launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s);
+  }
+}
+
+void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const double* b, double* x,
+             double tol, int32_t maxit, int32_t* iters, double* relres, bool* converged) {
+  hipStream_t s = C.stream;
+  const Plan& P = *F.plan;
+  const int64_t n = P.n;
+  const int64_t nv = n * nrhs;
+  DevArena work;
+  double* r = work.alloc_n<double>(nv);
+  double* z = work.alloc_n<double>(nv);
+  double* p = work.alloc_n<double>(nv);
+  double* q = work.alloc_n<double>(nv);
+  double* partial = work.alloc_n<double>((size_t)kDotBlocks * nrhs);
+  double* sc = work.alloc_n<double>(4 * (size_t)nrhs);  // rho | rho_new | pq | rr
+  double* rho = sc;
+  double* rho_new = sc + nrhs;
+  double* pq = sc + 2 * nrhs;
+  double* rr = sc + 3 * nrhs;
+  int32_t* active = work.alloc_n<int32_t>(nrhs);
+  std::vector<int32_t> h_active(nrhs, 1);
+  std::vector<double> h_bn(nrhs), h_rr(nrhs);
+
+  launch_dot(b, b, n, nrhs, partial, rr, s);
+  SPAND_HIP(hipMemcpyAsync(h_bn.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPAND_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < nrhs; ++c) {
+    h_bn[c] = std::sqrt(h_bn[c]);
+    iters[c] = 0;
+    if (h_bn[c] == 0.0) h_active[c] = 0;
+  }
+  SPAND_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
+  SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  launch_copy_vec(b, r, nv, s);
+  run_apply(C, F, nrhs, r, z);
+  launch_dot(r, z, n, nrhs, partial, rho_new, s);
+  launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 1, s);
+  int nact = 0;
+  for (int c = 0; c < nrhs; ++c) nact += h_active[c];
+  for (int it = 1; it <= maxit && nact > 0; ++it) {
+    launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, p, q, s);
+    launch_dot(p, q, n, nrhs, partial, pq, s);
+    launch_pcg_xr(x, r, p, q, rho, pq, active, n, nrhs, s);
+    launch_dot(r, r, n, nrhs, partial, rr, s);
+    SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPAND_HIP(hipStreamSynchronize(s));
+    bool changed = false;
+    for (int c = 0; c < nrhs; ++c)
+      if (h_active[c] && std::sqrt(h_rr[c]) < tol * h_bn[c]) {
+        h_active[c] = 0;
+        iters[c] = it;
+        --nact;
+        changed = true;
+      } else if (h_active[c]) {
+        iters[c] = it;
+      }
+    if (nact == 0) break;
+    if (changed)
+      SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+    run_apply(C, F, nrhs, r, z);
+    launch_dot(r, z, n, nrhs, partial, rho_new, s);
+    launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 0, s);
+  }
+  // true residual
+  launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, x, q, s);
+  launch_residual(b, q, n, nrhs, s);
+  launch_dot(q, q, n, nrhs, partial, rr, s);
+  SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPAND_HIP(hipStreamSynchronize(s));
+  *converged = nact == 0;
+  for (int c = 0; c < nrhs; ++c)
+    relres[c] = h_bn[c] > 0 ? std::sqrt(h_rr[c]) / h_bn[c] : 0.0;
+}
+
+}  // namespace spand

@@ -1,0 +1,256 @@
+"""ctypes binding of libspand (the C ABI declared in include/spand.h).
+
+Argument marshalling only: every step of the factorization, apply and PCG
+runs inside the library.  Device buffers are passed as integer addresses
+(``tensor.data_ptr()`` of a torch tensor on the GPU works, as does any object
+with a ``data_ptr()`` method); host arrays are numpy arrays.
+
+The library must be built (``python -m paper_2007_00789_amd.build``); loading
+raises OSError when it is missing, so no caller can fall back silently.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspand.so")
+
+SPAND_OK = 0
+FIRST_ORDER, SECOND_ORDER, SUPERFINE = 1, 2, 3
+SCHEMES = {"FO": FIRST_ORDER, "SO": SECOND_ORDER, "SF": SUPERFINE}
+FP64 = 0
+
+STATUS = {
+    0: "SPAND_OK", -1: "SPAND_E_INVALID", -2: "SPAND_E_NOT_SYMMETRIC", -3: "SPAND_E_NOT_SPD",
+    -4: "SPAND_E_NO_CONVERGENCE", -5: "SPAND_E_OOM", -6: "SPAND_E_HIP", -7: "SPAND_E_STATE",
+    -8: "SPAND_E_LIMIT",
+}
+
+
+class Opts(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("skip", C.c_int32), ("eps", C.c_double),
+                ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32)]
+
+
+class FactorStats(C.Structure):
+    _fields_ = [("nnz_L", C.c_int64), ("flops", C.c_double), ("factor_seconds", C.c_double),
+                ("factor_bytes", C.c_int64), ("root_size", C.c_int32)]
+
+
+class SpandError(RuntimeError):
+    def __init__(self, status, message=""):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_P = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
+_I64P = C.POINTER(C.c_int64)
+_DP = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); mirrors include/spand.h
+SIGNATURES = {
+    "spand_default_opts": (None, [C.POINTER(Opts)]),
+    "spand_status_string": (C.c_char_p, [C.c_int]),
+    "spand_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "spand_destroy": (None, [_P]),
+    "spand_last_error": (C.c_char_p, [_P]),
+    "spand_analyze": (C.c_int, [_P, C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.POINTER(Opts),
+                                C.POINTER(_P)]),
+    "spand_destroy_plan": (None, [_P]),
+    "spand_plan_sizes": (C.c_int, [_P, _I64P, _I64P, _I32P]),
+    "spand_plan_vertices": (C.c_int, [_P, _I32P, _I64P, _I64P]),
+    "spand_plan_step_counts": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I64P, _I64P, _I32P]),
+    "spand_plan_step_arrays": (C.c_int, [_P, C.c_int32, _I64P, _I64P, _I64P, _I32P, _I32P,
+                                         _I64P, _I32P]),
+    "spand_factor": (C.c_int, [_P, _P, _P, C.POINTER(Opts), C.POINTER(_P)]),
+    "spand_destroy_factor": (None, [_P]),
+    "spand_factor_ranks": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I32P, _I32P]),
+    "spand_factor_info": (C.c_int, [_P, C.POINTER(FactorStats)]),
+    "spand_apply": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "spand_pcg": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_double, C.c_int32, _I32P, _DP]),
+    "spand_debug_block": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _I32P, _I32P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libspand.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with python -m paper_2007_00789_amd.build")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return C.c_void_p(x.data_ptr())
+    return C.c_void_p(int(x))
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1) -> Opts:
+    o = Opts()
+    load().spand_default_opts(C.byref(o))
+    o.depth = int(depth)
+    o.skip = int(skip)
+    o.eps = float(eps)
+    o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    o.precision = int(precision)
+    o.debug_stop_step = int(debug_stop_step)
+    return o
+
+
+class Context:
+    """spand_create / spand_destroy.  stream: a hipStream_t address or None."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.spand_create(C.byref(h), int(device), _ptr(stream))
+        if st != SPAND_OK:
+            raise SpandError(st, "spand_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spand_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, st):
+        if st != SPAND_OK:
+            raise SpandError(st, self.lib.spand_last_error(self.h).decode())
+
+    def factor(self, plan: "Plan", vals, opts: Opts) -> "Factor":
+        """spand_factor; vals: device buffer of nnz float64 values."""
+        h = C.c_void_p()
+        self._check(self.lib.spand_factor(self.h, plan.h, _ptr(vals), C.byref(opts), C.byref(h)))
+        return Factor(self.lib, h, plan)
+
+    def apply(self, fac: "Factor", nrhs: int, x, y):
+        """spand_apply: y = M x (device buffers, n x nrhs column-major)."""
+        self._check(self.lib.spand_apply(self.h, fac.h, int(nrhs), _ptr(x), _ptr(y)))
+
+    def pcg(self, fac: "Factor", nrhs: int, b, x, tol=1e-10, maxit=1000, check=True):
+        """spand_pcg; returns (iters, relres) numpy arrays."""
+        it = np.zeros(nrhs, dtype=np.int32)
+        rr = np.zeros(nrhs, dtype=np.float64)
+        st = self.lib.spand_pcg(self.h, fac.h, int(nrhs), _ptr(b), _ptr(x), float(tol), int(maxit),
+                                it.ctypes.data_as(_I32P), rr.ctypes.data_as(_DP))
+        if check or st not in (SPAND_OK, -4):
+            self._check(st)
+        return it, rr
+
+
+def analyze(n, rowptr, colind, coords, opts: Opts, ctx: Context | None = None) -> "Plan":
+    """spand_analyze (host work; ctx optional)."""
+    lib = load()
+    rp, rp_p = _np(rowptr, np.int64)
+    ci, ci_p = _np(colind, np.int32)
+    xy, xy_p = _np(coords, np.float64)
+    dim = 1 if xy.ndim == 1 else xy.shape[1]
+    h = C.c_void_p()
+    st = lib.spand_analyze(ctx.h if ctx else None, int(n), rp_p, ci_p, xy_p, dim, C.byref(opts),
+                           C.byref(h))
+    if st != SPAND_OK:
+        msg = lib.spand_last_error(ctx.h).decode() if ctx else ""
+        raise SpandError(st, msg or "spand_analyze failed")
+    return Plan(lib, h)
+
+
+class Plan:
+    def __init__(self, lib, h):
+        self.lib, self.h = lib, h
+        n, nnz, d = C.c_int64(), C.c_int64(), C.c_int32()
+        lib.spand_plan_sizes(h, C.byref(n), C.byref(nnz), C.byref(d))
+        self.n, self.nnz, self.depth = n.value, nnz.value, d.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spand_destroy_plan(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def vertices(self):
+        lvl = np.zeros(self.n, np.int32)
+        path = np.zeros(self.n, np.int64)
+        perm = np.zeros(self.n, np.int64)
+        self.lib.spand_plan_vertices(self.h, lvl.ctypes.data_as(_I32P), path.ctypes.data_as(_I64P),
+                                     perm.ctypes.data_as(_I64P))
+        return lvl, path, perm
+
+    def step(self, l: int) -> dict:
+        nc, ni, na, nch, sp = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
+        st = self.lib.spand_plan_step_counts(self.h, l, C.byref(nc), C.byref(ni), C.byref(na),
+                                             C.byref(nch), C.byref(sp))
+        if st != SPAND_OK:
+            raise SpandError(st, f"step {l}")
+        nc, na, nch = nc.value, na.value, nch.value
+        out = dict(n_clusters=nc, n_interior=ni.value, sparsified=bool(sp.value),
+                   key_lvl=np.zeros(nc, np.int64), key_prefix=np.zeros(nc, np.int64),
+                   adj_ptr=np.zeros(nc + 1, np.int64), adj=np.zeros(max(na, 1), np.int32),
+                   colour=np.zeros(nc, np.int32), child_ptr=np.zeros(nc + 1, np.int64),
+                   child=np.zeros(max(nch, 1), np.int32))
+        self.lib.spand_plan_step_arrays(
+            self.h, l, out["key_lvl"].ctypes.data_as(_I64P), out["key_prefix"].ctypes.data_as(_I64P),
+            out["adj_ptr"].ctypes.data_as(_I64P), out["adj"].ctypes.data_as(_I32P),
+            out["colour"].ctypes.data_as(_I32P), out["child_ptr"].ctypes.data_as(_I64P),
+            out["child"].ctypes.data_as(_I32P))
+        out["adj"] = out["adj"][:na]
+        out["child"] = out["child"][:nch]
+        return out
+
+
+class Factor:
+    def __init__(self, lib, h, plan):
+        self.lib, self.h, self.plan = lib, h, plan
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spand_destroy_factor(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def ranks(self, l: int, n_clusters: int):
+        arrs = [np.zeros(n_clusters, np.int32) for _ in range(4)]
+        st = self.lib.spand_factor_ranks(self.h, l, *[a.ctypes.data_as(_I32P) for a in arrs])
+        if st != SPAND_OK:
+            raise SpandError(st, f"ranks of step {l}")
+        return dict(zip(("a", "k", "r", "r2"), arrs))
+
+    def info(self) -> dict:
+        s = FactorStats()
+        self.lib.spand_factor_info(self.h, C.byref(s))
+        return {k: getattr(s, k) for k, _ in FactorStats._fields_}
+
+    def debug_block(self, ci: int, cj: int) -> np.ndarray:
+        r, c = C.c_int32(), C.c_int32()
+        st = self.lib.spand_debug_block(self.h, ci, cj, None, C.byref(r), C.byref(c))
+        if st != SPAND_OK:
+            raise SpandError(st, "debug block")
+        out = np.zeros((r.value, c.value), order="F")
+        self.lib.spand_debug_block(self.h, ci, cj, out.ctypes.data_as(_DP), C.byref(r), C.byref(c))
+        return out

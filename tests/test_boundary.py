@@ -1,0 +1,91 @@
+"""The C-ABI library on the host: it loads, exports every symbol of
+include/spand.h, and its symbolic analysis (host C++) equals the oracle's
+partition bit for bit: levels, paths, elimination permutation, the clusters of
+every step, their adjacency with symbolic fill, children and colours."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synthetic import laplacian_2d, laplacian_3d, fv_diffusion_3d
+from oracle import nd
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "spand.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spand_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "spand_analyze" in names and "spand_pcg" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2007_00789_amd import spand
+    assert set(names) == set(spand.SIGNATURES)
+
+
+CASES = [
+    ("lap2d_64", lambda: laplacian_2d(64), 6, 4),
+    ("lap2d_ragged", lambda: laplacian_2d(37, 23), 7, 2),
+    ("lap3d_16", lambda: laplacian_3d(16), 6, 4),
+    ("lap3d_box", lambda: laplacian_3d(5, shape=(11, 6, 9)), 7, 0),
+    ("fv3d_12", lambda: fv_diffusion_3d(12, 3.0, 1002), 5, 1),
+    ("lap3d_32", lambda: laplacian_3d(32), 9, 4),
+]
+
+
+@pytest.mark.parametrize("name,make,depth,skip", CASES, ids=[c[0] for c in CASES])
+def test_analyze_matches_oracle(lib, name, make, depth, skip):
+    from paper_2007_00789_amd import spand
+    p = make()
+    ref = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=depth, skip=skip))
+    assert plan.depth == depth and plan.n == p.n and plan.nnz == p.nnz
+    lvl, path, perm = plan.vertices()
+    assert np.array_equal(lvl, ref.lvl)
+    assert np.array_equal(path, ref.path)
+    assert np.array_equal(perm, ref.perm)
+    for l in range(depth, -1, -1):
+        st = ref.steps[l]
+        got = plan.step(l)
+        assert got["n_clusters"] == st.n_clusters and got["n_interior"] == st.n_interior
+        assert got["sparsified"] == st.sparsified
+        assert [(0 if i < st.n_interior else 1, int(a), int(b))
+                for i, (a, b) in enumerate(zip(got["key_lvl"], got["key_prefix"]))] == st.keys
+        adj = [got["adj"][got["adj_ptr"][c]:got["adj_ptr"][c + 1]] for c in range(st.n_clusters)]
+        for c in range(st.n_clusters):
+            assert np.array_equal(adj[c], st.adj[c]), (l, c)
+        assert np.array_equal(got["colour"], st.colour)
+        if st.children is not None:
+            ch = [list(got["child"][got["child_ptr"][c]:got["child_ptr"][c + 1]])
+                  for c in range(st.n_clusters)]
+            assert ch == st.children
+
+
+def test_default_depth_is_log2_n_over_64(lib):
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(64)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=0))
+    assert plan.depth == 6
+
+
+def test_error_paths(lib):
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(8)
+    ci = p.colind.copy()
+    ci[3] = (ci[3] + 5) % p.n          # breaks the symmetry of the pattern
+    with pytest.raises(spand.SpandError) as e:
+        spand.analyze(p.n, p.rowptr, ci, p.coords, spand.make_opts(depth=3))
+    assert e.value.status == -2
+    with pytest.raises(spand.SpandError) as e:
+        spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=3, eps=1.5))
+    assert e.value.status == -1
+    with pytest.raises(spand.SpandError) as e:
+        spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=3, scheme=7))
+    assert e.value.status == -1

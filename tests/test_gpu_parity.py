@@ -1,0 +1,213 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (FP64):
+* ordering, clusters and ranks: bit-exact (ranks of every sparsified step);
+* blocks after a step's sparsification: 1e-11 relative to the block norm;
+* y = M x: 1e-11 relative;
+* PCG: iteration count within +-1 (identical expected) and the solution within
+  1e-10 relative of the oracle's;
+* eps = 0 reproduces the exact nested-dissection Cholesky (one apply solves).
+"""
+import numpy as np
+import pytest
+
+from synthetic import laplacian_2d, laplacian_3d, fv_diffusion_3d, rhs
+from oracle import nd, spand as ospand, pcg as opcg
+
+gpu = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a).reshape(-1, order="F").copy()).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_00789_amd import spand
+    return spand.Context(0)
+
+
+def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1):
+    from paper_2007_00789_amd import spand
+    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    vals = _dev(p.vals)
+    fac = ctx.factor(plan, vals, opts)
+    return plan, fac
+
+
+def _oracle_ranks(F):
+    out = {}
+    for l, recs in F.ranks.items():
+        out[l] = {p: (a, k, r, r2) for (p, a, k, r, r2) in recs}
+    return out
+
+
+CASES = [
+    ("lap2d_64", lambda: laplacian_2d(64), 6, 4, 1e-2),
+    ("lap2d_64_skip0", lambda: laplacian_2d(64), 6, 0, 1e-2),
+    ("lap2d_ragged", lambda: laplacian_2d(45, 29), 6, 1, 3e-2),
+    ("lap3d_16", lambda: laplacian_3d(16), 6, 1, 1e-2),
+    ("fv3d_12", lambda: fv_diffusion_3d(12, 3.0, 1002), 5, 0, 1e-2),
+    ("lap3d_24_eps1e-3", lambda: laplacian_3d(24), 8, 2, 1e-3),
+]
+
+
+@gpu
+@pytest.mark.parametrize("scheme", ["FO", "SO", "SF"])
+@pytest.mark.parametrize("name,make,depth,skip,eps", CASES, ids=[c[0] for c in CASES])
+def test_ranks_and_memory_match_oracle(ctx, name, make, depth, skip, eps, scheme):
+    p = make()
+    print(f"case {name} {scheme}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, scheme)
+    plan, fac = _gpu_factor(ctx, p, depth, skip, eps, scheme)
+    ref = _oracle_ranks(F)
+    for l in range(depth, 0, -1):
+        st = plan_o.steps[l]
+        got = fac.ranks(l, st.n_clusters)
+        if not st.sparsified:
+            assert (got["r"] == -1).all()
+            continue
+        for p_, (a, k, r, r2) in ref[l].items():
+            assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), \
+                (l, p_)
+    info = fac.info()
+    assert info["nnz_L"] == F.nnz_L
+    assert info["flops"] == pytest.approx(sum(F.flops.values()), rel=1e-12)
+
+
+@gpu
+@pytest.mark.parametrize("stop", [6, 5, 3, 2])
+def test_blocks_after_a_step(ctx, stop):
+    p = laplacian_2d(64)
+    depth, skip, eps = 6, 0, 1e-2
+    print(f"blocks after step {stop}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    _, B, sizes = ospand.factor(p.scipy(), plan_o, eps, "SO", stop_after=stop)
+    _, fac = _gpu_factor(ctx, p, depth, skip, eps, "SO", stop=stop)
+    st = plan_o.steps[stop]
+    nmax = 0
+    for (i, j), blk in B.items():
+        got = fac.debug_block(i, j)
+        assert got.shape == blk.shape, (i, j)
+        if blk.size:
+            scale = max(np.abs(blk).max(), 1.0)
+            assert np.abs(got - blk).max() <= 1e-11 * scale, (i, j)
+            nmax += 1
+    assert nmax > 0
+    assert all(sizes[c] == fac.debug_block(c, c).shape[0] for c in range(st.n_interior, st.n_clusters))
+
+
+@gpu
+@pytest.mark.parametrize("scheme", ["FO", "SO", "SF"])
+@pytest.mark.parametrize("name,make,depth,skip,eps", CASES[:5], ids=[c[0] for c in CASES[:5]])
+def test_apply_matches_oracle(ctx, name, make, depth, skip, eps, scheme):
+    p = make()
+    print(f"apply {name} {scheme}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, scheme)
+    _, fac = _gpu_factor(ctx, p, depth, skip, eps, scheme)
+    x = rhs(p.n, 3, 11)
+    y_ref = ospand.apply(F, x)
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, 3, dx, dy)
+    y = dy.cpu().numpy().reshape(p.n, 3, order="F")
+    assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+
+
+@gpu
+@pytest.mark.parametrize("scheme", ["FO", "SO"])
+@pytest.mark.parametrize("name,make,depth,skip,eps,tol,nrhs", [
+    ("lap2d_64", lambda: laplacian_2d(64), 6, 4, 1e-2, 1e-12, 1),
+    ("lap3d_16", lambda: laplacian_3d(16), 6, 1, 1e-2, 1e-10, 4),
+    ("fv3d_12", lambda: fv_diffusion_3d(12, 3.0, 1002), 5, 0, 1e-2, 1e-10, 2),
+], ids=["lap2d_64", "lap3d_16", "fv3d_12"])
+def test_pcg_matches_oracle(ctx, name, make, depth, skip, eps, tol, nrhs, scheme):
+    p = make()
+    print(f"pcg {name} {scheme}", flush=True)
+    A = p.scipy()
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(A, plan_o, eps, scheme)
+    b = rhs(p.n, nrhs, 2000)
+    X, its, _ = opcg.pcg_multi(lambda v: A @ v, lambda v: ospand.apply(F, v), b, tol)
+    _, fac = _gpu_factor(ctx, p, depth, skip, eps, scheme)
+    db = _dev(b)
+    dx = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, nrhs, db, dx, tol, 1000)
+    x = dx.cpu().numpy().reshape(p.n, nrhs, order="F")
+    for j in range(nrhs):
+        assert abs(int(it[j]) - its[j]) <= 1
+        assert rr[j] < 10 * tol
+        assert np.linalg.norm(x[:, j] - X[:, j]) <= 1e-10 * np.linalg.norm(X[:, j])
+
+
+@gpu
+def test_eps_zero_is_exact_on_gpu(ctx):
+    p = laplacian_3d(12)
+    _, fac = _gpu_factor(ctx, p, 6, 0, 0.0, "SO")
+    b = rhs(p.n, 1, 5)
+    db = _dev(b)
+    dy = torch.zeros_like(db)
+    ctx.apply(fac, 1, db, dy)
+    y = dy.cpu().numpy()
+    res = np.linalg.norm(b[:, 0] - p.scipy() @ y) / np.linalg.norm(b)
+    assert res < 1e-13
+    dx = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, 1, db, dx, 1e-10, 100)
+    assert it[0] == 1
+
+
+@gpu
+def test_not_spd_reports_step_and_cluster(ctx):
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(16)
+    vals = p.vals.copy()
+    v = 77
+    diag = p.rowptr[v] + np.flatnonzero(p.colind[p.rowptr[v]:p.rowptr[v + 1]] == v)[0]
+    vals[diag] = -4.0
+    opts = spand.make_opts(depth=3, skip=0, eps=1e-2)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    with pytest.raises(spand.SpandError) as e:
+        ctx.factor(plan, _dev(vals), opts)
+    assert e.value.status == -3 and "step 3" in e.value.message
+
+
+@gpu
+def test_no_convergence_status(ctx):
+    p = laplacian_2d(32)
+    _, fac = _gpu_factor(ctx, p, 4, 0, 0.3, "FO")
+    db = _dev(rhs(p.n, 1, 1))
+    dx = torch.zeros_like(db)
+    from paper_2007_00789_amd import spand
+    with pytest.raises(spand.SpandError) as e:
+        ctx.pcg(fac, 1, db, dx, 1e-14, 1)
+    assert e.value.status == -4
+
+
+@gpu
+def test_factor_is_deterministic(ctx):
+    p = fv_diffusion_3d(12, 3.0, 7)
+    outs = []
+    for _ in range(2):
+        _, fac = _gpu_factor(ctx, p, 5, 0, 1e-2, "SO")
+        db = _dev(rhs(p.n, 2, 3))
+        dy = torch.zeros_like(db)
+        ctx.apply(fac, 2, db, dy)
+        outs.append(dy.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@gpu
+def test_tiny_and_degenerate_problems(ctx):
+    for p, depth in [(laplacian_2d(1), 2), (laplacian_2d(2), 3), (laplacian_2d(3, 1), 4)]:
+        _, fac = _gpu_factor(ctx, p, depth, 0, 1e-2, "SO")
+        b = rhs(p.n, 1, 2)
+        db = _dev(b)
+        dx = torch.zeros_like(db)
+        it, rr = ctx.pcg(fac, 1, db, dx, 1e-12, 50)
+        assert rr[0] < 1e-11
