@@ -133,6 +133,17 @@ spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const 
 spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* b, double* x,
                        double tol, int32_t maxit, int32_t* iters, double* relres);
 
+/* Per-kernel timing (for measurement).  spand_profile(ctx, 1) clears the
+ * counters and starts recording a HIP event pair on the context stream around
+ * every kernel launch of the library; spand_profile(ctx, 0) stops.  Entries
+ * accumulate, per kernel name, the summed event time in ms, the number of
+ * launches and (where the library knows it) the algorithmic work of those
+ * launches (k_cpqr: QR flops).  name receives at most name_len-1 characters. */
+spand_status spand_profile(spand_ctx_t ctx, int32_t enable);
+spand_status spand_profile_entries(spand_ctx_t ctx, int32_t* count);
+spand_status spand_profile_entry(spand_ctx_t ctx, int32_t i, char* name, int32_t name_len,
+                                 double* ms, int64_t* calls, double* work);
+
 /* Debug dump for parity tests: with opts.debug_stop_step = l, after
  * spand_factor returns, copies block (ci, cj) of step l (after its
  * sparsification) to out (host, column-major, ld = *rows); rows/cols receive

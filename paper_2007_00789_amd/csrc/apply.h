@@ -40,12 +40,14 @@ struct ApGat {
 };
 
 struct ApSp {
-  const double* V;         // a x nref reflectors (ld a)
+  const double* V;         // a x nref reflectors (ld a, zero above the unit diagonal)
   const double* tau;       // nref
-  const double* E;         // rows f0..f1-1 of Q^T W (ld a), nullable
+  const double* T;         // nref x nref: Q = I - V T V^T
+  const double* Et;        // E^T: k x (f1-f0), column i = row f0+i of Q^T W (ld lde); nullable
   const int32_t* pos;      // a
   const int32_t* nbr_pos;  // k
   int64_t toff;
+  int64_t lde;
   int32_t a, nref, f0, f1, k, pad;
 };
 

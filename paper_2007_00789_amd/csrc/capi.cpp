@@ -254,6 +254,8 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
                              ctx->c.stream));
     spand::run_factor(ctx->c, plan->p, f->d_vals, *opts, f->f);
     if (f->f.stopped_at < 0) spand::build_apply(ctx->c, f->f);
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
     f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();
   });
   if (st == SPAND_OK) *out = f.release();
@@ -294,6 +296,7 @@ spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const 
     SPAND_HIP(hipSetDevice(ctx->c.device));
     spand::run_apply(ctx->c, f->f, nrhs, x, y);
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
   });
 }
 
@@ -306,12 +309,44 @@ spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const do
     if (!f->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
     SPAND_HIP(hipSetDevice(ctx->c.device));
     spand::run_pcg(ctx->c, f->f, f->d_vals, nrhs, b, x, tol, maxit, iters, relres, &conv);
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
   });
   if (st == SPAND_OK && !conv) {
     ctx->c.last_error = "PCG did not converge within maxit";
     return SPAND_E_NO_CONVERGENCE;
   }
   return st;
+}
+
+spand_status spand_profile(spand_ctx_t ctx, int32_t enable) {
+  if (!ctx) return SPAND_E_INVALID;
+  return guarded(ctx, [&] {
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
+    ctx->c.prof.on = enable != 0;
+    ctx->c.prof.reset();
+  });
+}
+
+spand_status spand_profile_entries(spand_ctx_t ctx, int32_t* count) {
+  if (!ctx || !count) return SPAND_E_INVALID;
+  *count = (int32_t)ctx->c.prof.entries.size();
+  return SPAND_OK;
+}
+
+spand_status spand_profile_entry(spand_ctx_t ctx, int32_t i, char* name, int32_t name_len,
+                                 double* ms, int64_t* calls, double* work) {
+  if (!ctx || i < 0 || i >= (int32_t)ctx->c.prof.entries.size()) return SPAND_E_INVALID;
+  const auto& e = ctx->c.prof.entries[i];
+  if (name && name_len > 0) {
+    std::strncpy(name, e.name.c_str(), name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (ms) *ms = e.ms;
+  if (calls) *calls = e.calls;
+  if (work) *work = e.work;
+  return SPAND_OK;
 }
 
 spand_status spand_debug_block(spand_factor_t f, int32_t ci, int32_t cj, double* out, int32_t* rows,

@@ -15,7 +15,9 @@ namespace spand {
 // as tied, and the tie goes to the lowest column index.
 constexpr double kPivotTieRtol = 1e-8;
 
-// X = L^{-1} where A = L L^T (lower triangle of A read, ld lda; X: n x n, ld n).
+// X = L^{-1} where A = L L^T (lower triangle of A read, ld lda = n; X: n x n,
+// ld n).  Blocks larger than 64 are factored in place in A, which must be
+// dead after the call.
 struct PotrfDesc {
   const double* A;
   double* X;
@@ -58,6 +60,7 @@ struct CpqrDesc {
   double* Y;         // a x kmax workspace; holds Q^T W afterwards (E lives in rows r..)
   double* V;         // a x min(a, kmax) Householder vectors (unit diagonal stored)
   double* tau;       // min(a, kmax)
+  double* T;         // nref x nref (ld nref) triangular factor of the WY form
   int64_t nb0, nb1;  // neighbour range
   int64_t diag_col;  // column offset of the diagonal block (p, p)
   int32_t a, kmax, p, pad;
@@ -83,7 +86,6 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 
 constexpr int kGemmTile = 64;
-constexpr int kPotrfLdsMax = 128;     // n <= this: factor and invert inside LDS
 constexpr int kCpqrMaxK = 12288;      // trailing norms of a CPQR live in LDS
 
 }  // namespace spand

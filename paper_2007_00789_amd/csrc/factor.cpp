@@ -36,45 +36,37 @@ void* DevArena::alloc(size_t bytes) {
     ++cur_;
     used_ = 0;
   }
-  size_t sz = std::max<size_t>(bytes, size_t(64) << 20);
-  char* p = nullptr;
-  SPAND_HIP(hipMalloc(&p, sz));
-  chunks_.push_back({p, sz});
+  size_t sz = std::max<size_t>(bytes, size_t(mirrored_ ? 16 : 64) << 20);
+  Chunk c{nullptr, nullptr, sz, SIZE_MAX, 0};
+  SPAND_HIP(hipMalloc(&c.p, sz));
+  if (mirrored_) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c.h), sz, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipFree(c.p);
+      SPAND_HIP(e);
+    }
+  }
+  chunks_.push_back(c);
   reserved_ += sz;
   cur_ = chunks_.size() - 1;
   used_ = bytes;
-  return p;
+  return c.p;
 }
 
-void* PinnedArena::alloc(size_t bytes) {
-  bytes = (bytes + 255) & ~size_t(255);
-  if (bytes == 0) bytes = 256;
-  while (cur_ < chunks_.size()) {
-    if (used_ + bytes <= chunks_[cur_].size) {
-      void* p = chunks_[cur_].p + used_;
-      used_ += bytes;
-      return p;
+void DevArena::flush(hipStream_t s) {
+  for (auto& c : chunks_)
+    if (c.hi > c.lo) {
+      SPAND_HIP(hipMemcpyAsync(c.p + c.lo, c.h + c.lo, c.hi - c.lo, hipMemcpyHostToDevice, s));
+      c.lo = SIZE_MAX;
+      c.hi = 0;
     }
-    ++cur_;
-    used_ = 0;
-  }
-  size_t sz = std::max<size_t>(bytes, size_t(16) << 20);
-  char* p = nullptr;
-  SPAND_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sz, hipHostMallocDefault));
-  chunks_.push_back({p, sz});
-  cur_ = chunks_.size() - 1;
-  used_ = bytes;
-  return p;
-}
-
-void PinnedArena::release() {
-  for (auto& c : chunks_) (void)hipHostFree(c.p);
-  chunks_.clear();
-  cur_ = used_ = 0;
 }
 
 void DevArena::release() {
-  for (auto& c : chunks_) (void)hipFree(c.p);
+  for (auto& c : chunks_) {
+    (void)hipFree(c.p);
+    if (c.h) (void)hipHostFree(c.h);
+  }
   chunks_.clear();
   cur_ = used_ = reserved_ = 0;
 }
@@ -99,6 +91,55 @@ void DevBuf::release() {
   if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+}
+
+int Prof::find(const char* name) {
+  for (size_t i = 0; i < entries.size(); ++i)
+    if (entries[i].name == name) return (int)i;
+  entries.push_back(Entry{name});
+  return (int)entries.size() - 1;
+}
+
+int Prof::begin(const char* name, hipStream_t s) {
+  if (!on) return -1;
+  hipEvent_t ev[2];
+  for (auto& e : ev) {
+    if (!pool.empty()) { e = pool.back(); pool.pop_back(); }
+    else SPAND_HIP(hipEventCreate(&e));
+  }
+  SPAND_HIP(hipEventRecord(ev[0], s));
+  pending.push_back({find(name), ev[0], ev[1]});
+  return (int)pending.size() - 1;
+}
+
+void Prof::end(int id, hipStream_t s) {
+  if (id < 0) return;
+  SPAND_HIP(hipEventRecord(pending[id].b, s));
+}
+
+void Prof::add_work(const char* name, double w) {
+  if (on) entries[find(name)].work += w;
+}
+
+void Prof::resolve() {
+  for (auto& p : pending) {
+    float ms = 0.f;
+    SPAND_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    entries[p.entry].ms += ms;
+    entries[p.entry].calls += 1;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void Prof::reset() {
+  entries.clear();
+}
+
+Prof::~Prof() {
+  for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : pool) (void)hipEventDestroy(e);
 }
 
 Plan::~Plan() {
@@ -163,14 +204,13 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   int cur = 0;
   PanelLayout lay = make_layout(P.steps[D], sizes);
   double* panel = static_cast<double*>(C.panels[cur].ensure(lay.total * sizeof(double)));
-  launch_fill(panel, lay.total, 0.0, s);
-  launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s);
+  SPAND_PROF(C, "k_fill", launch_fill(panel, lay.total, 0.0, s));
+  SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
 
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
     StepRec& R = F.steps[l];
     C.upload.reset();
-    C.stage.reset();
     R.l = l;
     R.sparsified = st.sparsified;
     R.n0 = sizes;
@@ -186,6 +226,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.Y.assign(nc, nullptr);
     R.V.assign(nc, nullptr);
     R.tau.assign(nc, nullptr);
+    R.T.assign(nc, nullptr);
+    R.kmax.assign(nc, 0);
     R.sp_nbr_pos.assign(nc, {});
     auto blk = [&](int c, int64_t e) { return panel + lay.off[c] + lay.coff[e] * lay.n[c]; };
 
@@ -199,9 +241,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     int32_t* d_info_f = dint + 5 * nc;
     SPAND_HIP(hipMemsetAsync(dint, 0, sizeof(int32_t) * 6 * (size_t)nc, s));
     {
-      void* h = C.stage.alloc(sizeof(int32_t) * nc);
-      std::memcpy(h, sizes.data(), sizeof(int32_t) * nc);
-      SPAND_HIP(hipMemcpyAsync(d_ncur, h, sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+      const int32_t* h = C.upload.upload(sizes);
+      C.upload.flush(s);
+      SPAND_HIP(hipMemcpyAsync(d_ncur, h, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, s));
     }
 
     // ---------------- (a) interiors ----------------
@@ -223,7 +265,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
     if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
     if (!pd.empty()) {
-      launch_potrf_inv(C.upload.upload(pd, s, C.stage), (int32_t)pd.size(), max_n, d_info_i, s);
+      const auto* d_pd = C.upload.upload(pd);
+      SPAND_PROF(C, "k_potrf_inv", launch_potrf_inv(d_pd, (int32_t)pd.size(), max_n, d_info_i, s));
       // G_s = L_s^{-1} B_{s,W}
       std::vector<GemmDesc> gd;
       std::vector<GemmTerm> gt;
@@ -246,9 +289,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         gd.push_back(g);
         add_gemm_tiles(tiles, (int32_t)gd.size() - 1, ns, ks, false);
       }
-      if (!tiles.empty())
-        launch_gemm(C.upload.upload(gd, s, C.stage), C.upload.upload(gt, s, C.stage), C.upload.upload(tiles, s, C.stage),
-                    (int64_t)tiles.size(), s);
+      if (!tiles.empty()) {
+        const auto* d_gd = C.upload.upload(gd);
+        const auto* d_gt = C.upload.upload(gt);
+        const auto* d_tiles = C.upload.upload(tiles);
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
+      }
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2}
       gd.clear();
       gt.clear();
@@ -299,9 +345,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           add_gemm_tiles(tiles, (int32_t)gd.size() - 1, g.m, g.n, w1 == w2);
         }
       }
-      if (!tiles.empty())
-        launch_gemm(C.upload.upload(gd, s, C.stage), C.upload.upload(gt, s, C.stage), C.upload.upload(tiles, s, C.stage),
-                    (int64_t)tiles.size(), s);
+      if (!tiles.empty()) {
+        const auto* d_gd = C.upload.upload(gd);
+        const auto* d_gt = C.upload.upload(gt);
+        const auto* d_tiles = C.upload.upload(tiles);
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
+      }
     }
 
     if (l == 0) {
@@ -331,7 +380,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         nnzL += (int64_t)a * (a + 1) / 2;
       }
       if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
-      launch_potrf_inv(C.upload.upload(zd, s, C.stage), (int32_t)zd.size(), max_a, d_info_f, s);
+      const auto* d_zd = C.upload.upload(zd);
+      SPAND_PROF(C, "k_potrf_inv", launch_potrf_inv(d_zd, (int32_t)zd.size(), max_a, d_info_f, s));
       // two-sided scaling of every interface pair p < q
       std::vector<GemmDesc> g1, g2;
       std::vector<GemmTerm> t1, t2;
@@ -380,10 +430,16 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           add_gemm_tiles(tl2, (int32_t)g2.size() - 1, ap, aq, false);
         }
       if (!tl1.empty()) {
-        launch_gemm(C.upload.upload(g1, s, C.stage), C.upload.upload(t1, s, C.stage), C.upload.upload(tl1, s, C.stage),
-                    (int64_t)tl1.size(), s);
-        launch_gemm(C.upload.upload(g2, s, C.stage), C.upload.upload(t2, s, C.stage), C.upload.upload(tl2, s, C.stage),
-                    (int64_t)tl2.size(), s);
+        const auto* d_g1 = C.upload.upload(g1);
+        const auto* d_t1 = C.upload.upload(t1);
+        const auto* d_tl1 = C.upload.upload(tl1);
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1,
+                    (int64_t)tl1.size(), s));
+        const auto* d_g2 = C.upload.upload(g2);
+        const auto* d_t2 = C.upload.upload(t2);
+        const auto* d_tl2 = C.upload.upload(tl2);
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2,
+                    (int64_t)tl2.size(), s));
       }
       // sparsification, one launch per colour
       for (int colour = 0; colour < st.ncolours; ++colour) {
@@ -413,6 +469,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           }
           d.nb1 = (int64_t)cn.size();
           d.kmax = (int32_t)kmax;
+          R.kmax[p] = kmax;
           if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
                                                                std::to_string(kCpqrMaxK));
           const int64_t mn = std::min<int64_t>(a, kmax);
@@ -420,17 +477,21 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             R.Y[p] = F.arena.alloc_n<double>((size_t)a * kmax);
             R.V[p] = F.arena.alloc_n<double>((size_t)a * mn);
             R.tau[p] = F.arena.alloc_n<double>((size_t)mn);
+            R.T[p] = F.arena.alloc_n<double>((size_t)mn * mn);
           }
           d.Y = R.Y[p];
           d.V = R.V[p];
           d.tau = R.tau[p];
+          d.T = R.T[p];
           ma = std::max(ma, a);
           mk = std::max<int>(mk, (int)kmax);
           cd.push_back(d);
         }
         if (cd.empty()) continue;
-        launch_cpqr(C.upload.upload(cd, s, C.stage), C.upload.upload(cn, s, C.stage), (int32_t)cd.size(), d_ncur, d_r,
-                    d_r2, d_k, eps, eps_stop, ma, mk, s);
+        const auto* d_cd = C.upload.upload(cd);
+        const auto* d_cn = C.upload.upload(cn);
+        SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r,
+                    d_r2, d_k, eps, eps_stop, ma, mk, s));
       }
     }
     // read back breakdown flags and ranks
@@ -472,7 +533,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
                                          std::to_string(l));
         const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
         flops += (double)a * a * k;
-        for (int j = 0; j < r2; ++j) flops += 4.0 * (a - j) * (double)(k - j);
+        double qr = 0.0;
+        for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
+        flops += qr;
+        C.prof.add_work("k_cpqr", qr);
         nnzL += (int64_t)a * r2 - (int64_t)r2 * (r2 - 1) / 2 + r2;
         if (so) nnzL += (int64_t)(a - r) * (k - r);
         if (sf) {
@@ -507,7 +571,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     PanelLayout nlay = make_layout(nx, nsz);
     double* npanel =
         static_cast<double*>(C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
-    launch_fill(npanel, nlay.total, 0.0, s);
+    SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
     std::vector<CopyDesc> cp;
     for (int P_ = 0; P_ < nx.nc; ++P_)
       for (int64_t e = nx.adj_ptr[P_]; e < nx.adj_ptr[P_ + 1]; ++e) {
@@ -531,7 +595,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           }
         }
       }
-    launch_copy(C.upload.upload(cp, s, C.stage), (int64_t)cp.size(), s);
+    const auto* d_cp = C.upload.upload(cp);
+    SPAND_PROF(C, "k_copy", launch_copy(d_cp, (int64_t)cp.size(), s));
     SPAND_HIP(hipStreamSynchronize(s));
     cur = 1 - cur;
     panel = npanel;

@@ -23,10 +23,27 @@ namespace {
 
 constexpr int kWave = 64;
 
+// DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), kCtrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, returned to every lane.  Quad permutations and row
+// rotations reduce each row of 16 lanes; row broadcasts 15 and 31 then carry
+// the row sums upward so that lane 63 ends with the total.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  v += dpp_move<0x142>(v);  // row_bcast:15
+  v += dpp_move<0x143>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -90,7 +107,7 @@ __device__ int block_min_int(int v, int* red) {
 // Returns 0 or the 1-based column of the first non-positive pivot.
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ int chol_inv_inplace(double* S, int n, int ld, double* tmp, int* flag) {
+__device__ int chol_inplace(double* S, int n, int ld, int* flag) {
   const int tid = threadIdx.x;
   if (tid == 0) *flag = 0;
   __syncthreads();
@@ -115,6 +132,12 @@ __device__ int chol_inv_inplace(double* S, int n, int ld, double* tmp, int* flag
     }
     __syncthreads();
   }
+  return 0;
+}
+
+template <int NT>
+__device__ void trinv_inplace(double* S, int n, int ld, double* tmp) {
+  const int tid = threadIdx.x;
   for (int j = n - 1; j >= 0; --j) {
     for (int i = j + 1 + tid; i < n; i += NT) tmp[i] = S[i + (int64_t)j * ld];
     __syncthreads();
@@ -128,10 +151,162 @@ __device__ int chol_inv_inplace(double* S, int n, int ld, double* tmp, int* flag
     if (tid == 0) S[j + (int64_t)j * ld] = inv;
     __syncthreads();
   }
+}
+
+template <int NT>
+__device__ int chol_inv_inplace(double* S, int n, int ld, double* tmp, int* flag) {
+  const int f = chol_inplace<NT>(S, n, ld, flag);
+  if (f) return f;
+  trinv_inplace<NT>(S, n, ld, tmp);
   return 0;
 }
 
 constexpr int kPotrfThreads = 256;
+constexpr int kNb = 64;          // tile of the blocked Cholesky / inverse
+constexpr int kTl = kNb + 1;     // padded leading dimension of LDS tiles
+
+// LDS tile <- rows x cols block of a column-major global matrix (zero padded).
+__device__ __forceinline__ void tile_load(double* t, const double* g, int64_t ld, int rows,
+                                          int cols) {
+  for (int idx = threadIdx.x; idx < kNb * kNb; idx += kPotrfThreads) {
+    const int i = idx % kNb, j = idx / kNb;
+    t[i + j * kTl] = (i < rows && j < cols) ? g[i + j * ld] : 0.0;
+  }
+}
+
+// acc (4x4 per thread, rows tx+16r, cols ty+16c) += A * op(B) over kk < kdim,
+// A and B 64x64 LDS tiles; transB: B is used transposed.
+__device__ __forceinline__ void tile_mma(double (&acc)[4][4], const double* A, const double* B,
+                                         int kdim, bool transB) {
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  for (int kk = 0; kk < kdim; ++kk) {
+    double a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = A[tx + 16 * r + kk * kTl];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = transB ? B[ty + 16 * c + kk * kTl] : B[kk + (ty + 16 * c) * kTl];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+  }
+}
+
+__device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+}
+
+// Cholesky + inverse of a block larger than one tile: right-looking blocked
+// Cholesky in place in A (the dead diagonal block of the panel, ld n), the
+// inverses of the diagonal tiles into X's diagonal tiles, then the off-diagonal
+// tiles of X = L^{-1} by block forward substitution
+// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  LDS: four 64x65 tiles.
+__device__ int chol_inv_blocked(double* A, double* X, int n, double* lds, int* flag) {
+  double* T0 = lds;
+  double* T1 = lds + kNb * kTl;
+  double* T2 = lds + 2 * kNb * kTl;
+  double* tmp = lds + 3 * kNb * kTl;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int nb = (n + kNb - 1) / kNb;
+  double acc[4][4];
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * kNb, kw = min(kNb, n - k0);
+    // diagonal tile: factor (T1 = L_kk), invert a copy (T0 = L_kk^{-1})
+    tile_load(T1, A + k0 + (int64_t)k0 * n, n, kw, kw);
+    __syncthreads();
+    const int f = chol_inplace<kPotrfThreads>(T1, kw, kTl, flag);
+    if (f) return k0 + f;
+    for (int idx = threadIdx.x; idx < kNb * kNb; idx += kPotrfThreads) {
+      const int i = idx % kNb, j = idx / kNb;
+      T0[i + j * kTl] = (i >= j && i < kw) ? T1[i + j * kTl] : 0.0;
+    }
+    __syncthreads();
+    trinv_inplace<kPotrfThreads>(T0, kw, kTl, tmp);
+    for (int idx = threadIdx.x; idx < kw * kw; idx += kPotrfThreads) {
+      const int i = idx % kw, j = idx / kw;
+      A[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T1[i + j * kTl] : 0.0;
+      X[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T0[i + j * kTl] : 0.0;
+    }
+    __syncthreads();
+    // panel: A_Ik <- A_Ik L_kk^{-T}
+    for (int ib = kb + 1; ib < nb; ++ib) {
+      const int i0 = ib * kNb, iw = min(kNb, n - i0);
+      tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);
+      __syncthreads();
+      acc_zero(acc);
+      tile_mma(acc, T1, T0, kw, true);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = tx + 16 * r, j = ty + 16 * c;
+          if (i < iw && j < kw) A[i0 + i + (int64_t)(k0 + j) * n] = acc[r][c];
+        }
+      __syncthreads();
+    }
+    // trailing update of the lower triangle: A_IJ -= A_Ik A_Jk^T
+    for (int jb = kb + 1; jb < nb; ++jb) {
+      const int j0 = jb * kNb, jw = min(kNb, n - j0);
+      tile_load(T2, A + j0 + (int64_t)k0 * n, n, jw, kw);
+      for (int ib = jb; ib < nb; ++ib) {
+        const int i0 = ib * kNb, iw = min(kNb, n - i0);
+        tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);
+        __syncthreads();
+        acc_zero(acc);
+        tile_mma(acc, T1, T2, kw, true);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int i = tx + 16 * r, j = ty + 16 * c;
+            if (i < iw && j < jw) A[i0 + i + (int64_t)(j0 + j) * n] -= acc[r][c];
+          }
+        __syncthreads();
+      }
+    }
+  }
+  // off-diagonal tiles of X = L^{-1}, column block by column block
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * kNb, jw = min(kNb, n - j0);
+    for (int ib = jb + 1; ib < nb; ++ib) {
+      const int i0 = ib * kNb, iw = min(kNb, n - i0);
+      acc_zero(acc);
+      for (int kb = jb; kb < ib; ++kb) {
+        const int k0 = kb * kNb, kw = min(kNb, n - k0);
+        tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);   // L_IK
+        tile_load(T2, X + k0 + (int64_t)j0 * n, n, kw, jw);   // X_KJ
+        __syncthreads();
+        tile_mma(acc, T1, T2, kw, false);
+        __syncthreads();
+      }
+      // T1 <- S = sum, then X_IJ = -X_II S
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) T1[tx + 16 * r + (ty + 16 * c) * kTl] = acc[r][c];
+      tile_load(T2, X + i0 + (int64_t)i0 * n, n, iw, iw);
+      __syncthreads();
+      acc_zero(acc);
+      tile_mma(acc, T2, T1, iw, false);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = tx + 16 * r, j = ty + 16 * c;
+          if (i < iw && j < jw) {
+            X[i0 + i + (int64_t)(j0 + j) * n] = -acc[r][c];
+            X[j0 + j + (int64_t)(i0 + i) * n] = 0.0;   // strictly upper part
+          }
+        }
+      __syncthreads();
+    }
+  }
+  return 0;
+}
 
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* descs, int32_t* info) {
   extern __shared__ double sm[];
@@ -140,7 +315,7 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
   const int n = d.n;
   if (n == 0) return;
   const int tid = threadIdx.x;
-  if (n <= kPotrfLdsMax) {
+  if (n <= kNb) {
     double* S = sm;
     double* tmp = sm + n * n;
     for (int idx = tid; idx < n * n; idx += kPotrfThreads) {
@@ -155,12 +330,8 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
     }
     for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = S[idx];
   } else {
-    for (int64_t idx = tid; idx < (int64_t)n * n; idx += kPotrfThreads) {
-      const int i = (int)(idx % n), j = (int)(idx / n);
-      d.X[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : 0.0;
-    }
-    __syncthreads();
-    const int f = chol_inv_inplace<kPotrfThreads>(d.X, n, n, sm, &flag);
+    // the panel's diagonal block (ld n) is dead after this call: factor in place
+    const int f = chol_inv_blocked(const_cast<double*>(d.A), d.X, n, sm, &flag);
     if (f && tid == 0) info[blockIdx.x] = f;
   }
 }
@@ -239,43 +410,59 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmDesc* descs, co
 
 // ---------------------------------------------------------------------------
 // Early-stopping column-pivoted Householder QR, one interface per workgroup.
+// The coupling W (a x k) is copied transposed into the workspace Yt
+// (element (i, c) at Yt[c + i*kmax]), so one thread owns one column: the
+// reflector's dot product, the rank-1 update and the exact trailing norm of
+// the column need no cross-lane reduction, and the 64 lanes of a wave touch
+// 64 consecutive columns of a row (coalesced).  The first kQrCache rows of the
+// trailing column stay in registers between the dot and the update pass.
 // ---------------------------------------------------------------------------
-constexpr int kCpqrThreads = 256;
+constexpr int kQrThreads = 1024;
+constexpr int kQrWaves = kQrThreads / kWave;
+constexpr int kQrCache = 8;    // rows of a column kept in registers between passes
+constexpr int kQrUnroll = 8;   // independent loads in flight per thread
 
-__global__ __launch_bounds__(kCpqrThreads) void k_cpqr(const CpqrDesc* descs, const CpqrNbr* nbrs,
-                                                        int32_t* n_cur, int32_t* out_r,
-                                                        int32_t* out_r2, int32_t* out_k,
-                                                        double eps, double eps_stop, int32_t max_k) {
+__global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, const CpqrNbr* nbrs,
+                                                      int32_t* n_cur, int32_t* out_r,
+                                                      int32_t* out_r2, int32_t* out_k,
+                                                      double eps, double eps_stop, int32_t max_k) {
   extern __shared__ double sm[];
-  __shared__ double red[kCpqrThreads / kWave];
-  __shared__ int ired[kCpqrThreads / kWave];
+  __shared__ double redd[kQrWaves];
+  __shared__ int redi[kQrWaves];
   const CpqrDesc d = descs[blockIdx.x];
   const int a = d.a;
+  const int64_t K = d.kmax;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  constexpr int NW = kCpqrThreads / kWave;
   double* nrm2 = sm;
   double* v = sm + max_k;
-  double* Y = d.Y;
+  double* __restrict__ Yt = d.Y;
 
-  // gather W = [B_{p,w1} ... B_{p,wm}] with the neighbours' current widths
+  // gather W^T: the neighbours' blocks (p, w) with their current widths
   int k = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) {
     const CpqrNbr nb = nbrs[e];
     const int wc = n_cur[nb.w];
     const double* src = d.panel + nb.col * a;
-    double* dst = Y + (int64_t)k * a;
-    for (int64_t idx = tid; idx < (int64_t)a * wc; idx += kCpqrThreads) dst[idx] = src[idx];
+    for (int idx = tid; idx < a * wc; idx += kQrThreads) {
+      const int c = idx % wc, i = idx / wc;
+      Yt[(k + c) + i * K] = src[i + (int64_t)c * a];
+    }
     k += wc;
   }
   __syncthreads();
-  for (int c = wid; c < k; c += NW) {
+  for (int c = tid; c < k; c += kQrThreads) {
+    const double* col = Yt + c;
     double s = 0.0;
-    for (int i = lane; i < a; i += kWave) {
-      const double y = Y[i + (int64_t)c * a];
-      s = fma(y, y, s);
+    int i = 0;
+    for (; i + kQrUnroll <= a; i += kQrUnroll) {
+      double y[kQrUnroll];
+#pragma unroll
+      for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
+#pragma unroll
+      for (int u = 0; u < kQrUnroll; ++u) s = fma(y[u], y[u], s);
     }
-    s = wave_sum(s);
-    if (lane == 0) nrm2[c] = s;
+    for (; i < a; ++i) s = fma(col[i * K], col[i * K], s);
+    nrm2[c] = s;
   }
   __syncthreads();
 
@@ -285,72 +472,136 @@ __global__ __launch_bounds__(kCpqrThreads) void k_cpqr(const CpqrDesc* descs, co
   const int jmax = min(a, k);
   for (; j < jmax; ++j) {
     double m = -1.0;
-    for (int c = tid; c < k; c += kCpqrThreads) m = fmax(m, nrm2[c]);
-    m = block_max<kCpqrThreads>(m, red);
-    if (m < 0.0) break;
-    const double thr = m * (1.0 - kPivotTieRtol);
+    for (int c = tid; c < k; c += kQrThreads) m = fmax(m, nrm2[c]);
+    m = wave_max(m);
+    if (lane == 0) redd[wid] = m;
+    __syncthreads();
+    double M = redd[0];
+#pragma unroll
+    for (int w = 1; w < kQrWaves; ++w) M = fmax(M, redd[w]);
+    if (M < 0.0) break;
+    const double thr = M * (1.0 - kPivotTieRtol);
     int cand = INT_MAX;
-    for (int c = tid; c < k; c += kCpqrThreads)
+    for (int c = tid; c < k; c += kQrThreads)
       if (nrm2[c] >= 0.0 && nrm2[c] >= thr) { cand = c; break; }
-    cand = block_min_int<kCpqrThreads>(cand, ired);
-    double s = 0.0;
-    for (int i = j + tid; i < a; i += kCpqrThreads) {
-      const double y = Y[i + (int64_t)cand * a];
-      s = fma(y, y, s);
-    }
-    s = block_sum<kCpqrThreads>(s, red);
-    const double nrm = sqrt(s);
+    cand = wave_min_int(cand);
+    if (lane == 0) redi[wid] = cand;
+    __syncthreads();
+    int C = redi[0];
+#pragma unroll
+    for (int w = 1; w < kQrWaves; ++w) C = min(C, redi[w]);
+    const double nrm = sqrt(nrm2[C]);
     if (j == 0) R00 = nrm;
     if (nrm == 0.0 || nrm < eps_stop * R00) break;
     if (r < 0 && nrm < eps * R00) r = j;
-    const double alpha = Y[j + (int64_t)cand * a];
+    const double alpha = Yt[C + j * K];
     const double beta = alpha >= 0.0 ? -nrm : nrm;
     const double denom = alpha - beta;
     const double tau = (beta - alpha) / beta;
-    for (int i = j + tid; i < a; i += kCpqrThreads) {
-      const double vi = i == j ? 1.0 : Y[i + (int64_t)cand * a] / denom;
+    for (int i = tid; i < a; i += kQrThreads) {
+      const double vi = i < j ? 0.0 : (i == j ? 1.0 : Yt[C + i * K] / denom);
       v[i] = vi;
       d.V[i + (int64_t)j * a] = vi;
     }
     if (tid == 0) d.tau[j] = tau;
     __syncthreads();
-    for (int c = wid; c < k; c += NW) {
-      if (c == cand || nrm2[c] < 0.0) continue;
-      double* col = Y + (int64_t)c * a;
-      double w = 0.0;
-      for (int i = j + lane; i < a; i += kWave) w = fma(v[i], col[i], w);
-      w = wave_sum(w) * tau;
-      double s2 = 0.0;
-      for (int i = j + lane; i < a; i += kWave) {
-        const double y = fma(-w, v[i], col[i]);
-        col[i] = y;
-        if (i > j) s2 = fma(y, y, s2);
+    for (int c = tid; c < k; c += kQrThreads) {
+      if (c == C || nrm2[c] < 0.0) continue;
+      double* __restrict__ col = Yt + c;
+      double cache[kQrCache];
+      double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrCache; ++t) {
+        const int i = j + t;
+        cache[t] = i < a ? col[i * K] : 0.0;
       }
-      s2 = wave_sum(s2);
-      if (lane == 0) nrm2[c] = s2;
+#pragma unroll
+      for (int t = 0; t < kQrCache; ++t) w0 = fma(j + t < a ? v[j + t] : 0.0, cache[t], w0);
+      int i = j + kQrCache;
+      for (; i + kQrUnroll <= a; i += kQrUnroll) {
+        double y[kQrUnroll];
+#pragma unroll
+        for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
+#pragma unroll
+        for (int u = 0; u < kQrUnroll; ++u) w1 = fma(v[i + u], y[u], w1);
+      }
+      for (; i < a; ++i) w1 = fma(v[i], col[i * K], w1);
+      const double w = (w0 + w1) * tau;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrCache; ++t) {
+        const int ii = j + t;
+        if (ii < a) {
+          const double y = fma(-w, v[ii], cache[t]);
+          col[ii * K] = y;
+          if (t > 0) s0 = fma(y, y, s0);
+        }
+      }
+      i = j + kQrCache;
+      for (; i + kQrUnroll <= a; i += kQrUnroll) {
+        double y[kQrUnroll];
+#pragma unroll
+        for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
+#pragma unroll
+        for (int u = 0; u < kQrUnroll; ++u) {
+          y[u] = fma(-w, v[i + u], y[u]);
+          s1 = fma(y[u], y[u], s1);
+        }
+#pragma unroll
+        for (int u = 0; u < kQrUnroll; ++u) col[(i + u) * K] = y[u];
+      }
+      for (; i < a; ++i) {
+        const double y = fma(-w, v[i], col[i * K]);
+        col[i * K] = y;
+        s1 = fma(y, y, s1);
+      }
+      nrm2[c] = s0 + s1;
     }
-    for (int i = j + tid; i < a; i += kCpqrThreads) Y[i + (int64_t)cand * a] = i == j ? beta : 0.0;
-    __syncthreads();
-    if (tid == 0) nrm2[cand] = -1.0;
+    for (int i = j + tid; i < a; i += kQrThreads) Yt[C + i * K] = i == j ? beta : 0.0;
+    if (tid == 0) nrm2[C] = -1.0;
     __syncthreads();
   }
   const int nref = j;
   if (r < 0) r = nref;
+
+  // triangular factor of the compact WY form Q = H_0 ... H_{nref-1} = I - V T V^T
+  // (forward accumulation): T_jj = tau_j, T_{0:j,j} = -tau_j T_{0:j,0:j} V_{:,0:j}^T v_j.
+  // nrm2 (no longer needed) holds V_{:,0:j}^T v_j.
+  for (int jj = 0; jj < nref; ++jj) {
+    const double* vj = d.V + (int64_t)jj * a;
+    for (int i = wid; i < jj; i += kQrWaves) {
+      const double* vi = d.V + (int64_t)i * a;
+      double acc = 0.0;
+      for (int q = jj + lane; q < a; q += kWave) acc = fma(vi[q], vj[q], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) nrm2[i] = acc;
+    }
+    __syncthreads();
+    const double tj = d.tau[jj];
+    for (int i = tid; i < jj; i += kQrThreads) {
+      double acc = 0.0;
+      for (int m = i; m < jj; ++m) acc = fma(d.T[i + (int64_t)m * nref], nrm2[m], acc);
+      d.T[i + (int64_t)jj * nref] = -tj * acc;
+    }
+    for (int i = jj + 1 + tid; i < nref; i += kQrThreads) d.T[i + (int64_t)jj * nref] = 0.0;
+    if (tid == 0) d.T[jj + (int64_t)jj * nref] = tj;
+    __syncthreads();
+  }
 
   // coarse rows back into p's panel and, transposed, into the neighbours' panels
   int kk = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) {
     const CpqrNbr nb = nbrs[e];
     const int wc = n_cur[nb.w];
-    for (int idx = tid; idx < r * wc; idx += kCpqrThreads) {
-      const int i = idx % r, c = idx / r;
-      const double y = Y[i + (int64_t)(kk + c) * a];
+    for (int idx = tid; idx < r * wc; idx += kQrThreads) {
+      const int c = idx % wc, i = idx / wc;
+      const double y = Yt[(kk + c) + i * K];
       d.panel[i + (nb.col + c) * a] = y;
       nb.blk_wp[c + (int64_t)i * nb.ldw] = y;
     }
     kk += wc;
   }
-  for (int idx = tid; idx < r * r; idx += kCpqrThreads) {
+  for (int idx = tid; idx < r * r; idx += kQrThreads) {
     const int i = idx % r, c = idx / r;
     d.panel[i + (d.diag_col + c) * a] = i == c ? 1.0 : 0.0;
   }
@@ -405,8 +656,9 @@ void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double
 void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s) {
   if (count <= 0) return;
-  const int nl = max_n <= kPotrfLdsMax ? max_n : kPotrfLdsMax;
-  size_t lds = (size_t)nl * nl * sizeof(double) + (size_t)max_n * sizeof(double);
+  // n <= 64: the whole block and a column in LDS; larger: four 64x65 tiles
+  size_t lds = max_n <= kNb ? ((size_t)max_n * max_n + max_n) * sizeof(double)
+                            : (size_t)4 * kNb * kTl * sizeof(double);
   hipLaunchKernelGGL(k_potrf_inv, dim3(count), dim3(kPotrfThreads), lds, s, d, info);
 }
 
@@ -421,7 +673,7 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
                  int32_t max_a, int32_t max_k, hipStream_t s) {
   if (count <= 0) return;
   size_t lds = ((size_t)max_k + max_a) * sizeof(double);
-  hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kCpqrThreads), lds, s, d, nb, n_cur, out_r, out_r2,
+  hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kQrThreads), lds, s, d, nb, n_cur, out_r, out_r2,
                      out_k, eps, eps_stop, max_k);
 }
 

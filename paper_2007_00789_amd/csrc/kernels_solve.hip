@@ -10,10 +10,27 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kT = 256;
 
+// DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), kCtrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes (all active), returned to every lane: quad
+// permutations and row rotations reduce each row of 16 lanes, row broadcasts
+// 15 and 31 carry the row sums so that lane 63 holds the total.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  v += dpp_move<0x142>(v);  // row_bcast:15
+  v += dpp_move<0x143>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // all threads get the block sum; `red` holds kT/64 doubles
@@ -27,6 +44,127 @@ __device__ double block_sum(double v, double* red) {
   for (int w = 0; w < kT / kWave; ++w) s += red[w];
   __syncthreads();
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup building blocks.  Matrices are column-major in global memory;
+// vectors of the cluster being processed are staged in LDS (rows x nrhs).
+// ---------------------------------------------------------------------------
+constexpr int kNW = kT / kWave;
+constexpr int kBatch = 8;   // columns per wave iteration (independent loads in flight)
+constexpr int kChunk = 1024;  // staged neighbour values of the backward E product
+
+// out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx] for c < cols, r < nrhs.
+// One wave per batch of kBatch columns, lanes over rows; x lives in LDS, out
+// in LDS or global memory.
+__device__ void wg_coldots(const double* __restrict__ M, int64_t ld, int rows, int cols,
+                           const double* __restrict__ x, int ldx, int nrhs, double* __restrict__ out,
+                           int64_t ldo) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int c0 = wid * kBatch; c0 < cols; c0 += kNW * kBatch) {
+    double acc[kBatch][4];
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
+      for (int i = lane; i < rows; i += kWave) {
+        double m[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+          m[q] = c0 + q < cols ? M[i + (int64_t)(c0 + q) * ld] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double xv = x[i + (r0 + rr) * ldx];
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) acc[q][rr] = fma(m[q], xv, acc[q][rr]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double v = wave_sum(acc[q][rr]);
+          if (lane == 0 && c0 + q < cols) out[c0 + q + (int64_t)(r0 + rr) * ldo] = v;
+        }
+    }
+  }
+}
+
+// acc_out[i + r*rows] = sum_{c<cols} M[i + c*ld] z[pos[c] + r*ldz] for i < rows.
+// The gathered values are staged in LDS (chunks of kChunk columns, all
+// threads loading); then lanes hold rows and waves split the columns, and the
+// per-wave partial sums are reduced in a fixed order.
+// stage: LDS of kChunk * nrhs, part: LDS of kNW * rows * nrhs.  Ends with a barrier.
+__device__ void wg_rowsum_gather(const double* __restrict__ M, int64_t ld, int rows, int cols,
+                                 const int32_t* __restrict__ pos, const double* __restrict__ z,
+                                 int64_t ldz, int nrhs, double* __restrict__ stage,
+                                 double* __restrict__ part, double* __restrict__ acc_out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int idx = threadIdx.x; idx < kNW * rows * nrhs; idx += kT) part[idx] = 0.0;
+  for (int c0 = 0; c0 < cols; c0 += kChunk) {
+    const int cn = min(kChunk, cols - c0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cn * nrhs; idx += kT) {
+      const int c = idx % cn, r = idx / cn;
+      stage[idx] = z[pos[c0 + c] + r * ldz];
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < rows; i0 += kWave) {
+      const int i = i0 + lane;
+      if (i >= rows) continue;
+      for (int r = 0; r < nrhs; ++r) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int c = wid; c < cn; c += kNW) acc = fma(M[i + (int64_t)(c0 + c) * ld], stage[c + r * cn], acc);
+        part[(wid * nrhs + r) * rows + i] += acc;
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < rows * nrhs; idx += kT) {
+    const int i = idx % rows, r = idx / rows;
+    double sacc = 0.0;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) sacc += part[(w * nrhs + r) * rows + i];
+    acc_out[idx] = sacc;
+  }
+  __syncthreads();
+}
+
+// x <- Q^T x (trans = true) or Q x, Q = I - V T V^T with V (a x nref, ld a,
+// zero above the unit diagonal) and T (nref x nref upper triangular).
+// u, u2: LDS scratch of nref * nrhs.  x: LDS (a x nrhs).  Ends with a barrier.
+__device__ void wg_apply_wy(const double* __restrict__ V, const double* __restrict__ T, int a, int nref,
+                            double* __restrict__ x, int nrhs, double* __restrict__ u,
+                            double* __restrict__ u2, bool trans) {
+  if (nref == 0) return;
+  wg_coldots(V, a, a, nref, x, a, nrhs, u, nref);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nref * nrhs; idx += kT) {
+    const int j = idx % nref, r = idx / nref;
+    double acc = 0.0;
+    if (trans) {  // (T^T u)_j = sum_{i<=j} T_ij u_i
+#pragma unroll 8
+      for (int i = 0; i <= j; ++i) acc = fma(T[i + (int64_t)j * nref], u[i + r * nref], acc);
+    } else {      // (T u)_j = sum_{i>=j} T_ji u_i
+#pragma unroll 8
+      for (int i = j; i < nref; ++i) acc = fma(T[j + (int64_t)i * nref], u[i + r * nref], acc);
+    }
+    u2[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
+    const int i = idx % a, r = idx / a;
+    double acc = 0.0;
+    const int jm = min(i, nref - 1);
+#pragma unroll 8
+    for (int j = 0; j <= jm; ++j) acc = fma(V[i + (int64_t)j * a], u2[j + r * nref], acc);
+    x[idx] -= acc;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -47,23 +185,14 @@ __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     double acc = 0.0;
+#pragma unroll 8
     for (int m = 0; m <= i; ++m) acc = fma(d.Linv[i + (int64_t)m * n], xs[m + r * n], acc);
     ys[idx] = acc;
     z[d.pos[i] + r * ldz] = acc;
   }
   __syncthreads();
   if (k == 0) return;
-  double* t = T + d.toff * nrhs;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int j = wid; j < k; j += kT / kWave) {
-    const double* g = d.G + (int64_t)j * n;
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int i = lane; i < n; i += kWave) acc = fma(g[i], ys[i + r * n], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) t[j + (int64_t)r * k] = acc;
-    }
-  }
+  wg_coldots(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -90,6 +219,7 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     double acc = 0.0;
+#pragma unroll 8
     for (int m = 0; m <= i; ++m) acc = fma(d.Zinv[i + (int64_t)m * n], xs[m + r * n], acc);
     z[d.pos[i] + r * ldz] = acc;
   }
@@ -97,130 +227,142 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
 
 // ---------------------------------------------------------------------------
 // forward sparsification: z_p <- Q^T z_p ; t = E^T z_f
+// LDS: xs (a x nrhs) | u, u2 (nref x nrhs each)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_ap_sp_fwd(const ApSp* descs, double* z, int64_t ldz,
                                                   int nrhs, double* T) {
   extern __shared__ double sm[];
-  __shared__ double red[kT / kWave];
   const ApSp d = descs[blockIdx.x];
   const int a = d.a;
-  double* xs = sm;  // a x nrhs
+  double* xs = sm;
+  double* u = sm + a * nrhs;
+  double* u2 = u + d.nref * nrhs;
   for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
     const int i = idx % a, r = idx / a;
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  for (int j = 0; j < d.nref; ++j) {
-    const double* v = d.V + (int64_t)j * a;
-    const double tau = d.tau[j];
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int i = j + threadIdx.x; i < a; i += kT) acc = fma(v[i], xs[i + r * a], acc);
-      const double w = block_sum(acc, red) * tau;
-      for (int i = j + threadIdx.x; i < a; i += kT) xs[i + r * a] = fma(-w, v[i], xs[i + r * a]);
-      __syncthreads();
-    }
-  }
+  wg_apply_wy(d.V, d.T, a, d.nref, xs, nrhs, u, u2, true);
   for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
     const int i = idx % a, r = idx / a;
     z[d.pos[i] + r * ldz] = xs[idx];
   }
-  if (!d.E || d.f1 <= d.f0 || d.k == 0) return;
-  double* t = T + d.toff * nrhs;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (!d.Et || d.f1 <= d.f0 || d.k == 0) return;
+  // t_c = sum_i E[i, c] z_f[i]: one thread per column of E, rows of E^T are contiguous
   const int nf = d.f1 - d.f0;
-  for (int j = wid; j < d.k; j += kT / kWave) {
-    const double* e = d.E + (int64_t)j * a;  // rows f0.. of column j
+  double* t = T + d.toff * nrhs;
+  for (int c = threadIdx.x; c < d.k; c += kT) {
     for (int r = 0; r < nrhs; ++r) {
+      const double* xf = xs + d.f0 + r * a;
       double acc = 0.0;
-      for (int i = lane; i < nf; i += kWave) acc = fma(e[i], xs[d.f0 + i + r * a], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) t[j + (int64_t)r * d.k] = acc;
+#pragma unroll 8
+      for (int i = 0; i < nf; ++i) acc = fma(d.Et[c + i * d.lde], xf[i], acc);
+      t[c + (int64_t)r * d.k] = acc;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // backward sparsification: y_f -= E y_W ; y_p <- Q y_p
+// LDS: xs (a x nrhs) | u, u2 (nref x nrhs) | acc (nf x nrhs) | part (kChunk x nrhs)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_ap_sp_bwd(const ApSp* descs, double* z, int64_t ldz,
                                                   int nrhs) {
   extern __shared__ double sm[];
-  __shared__ double red[kT / kWave];
   const ApSp d = descs[blockIdx.x];
   const int a = d.a;
+  const int nf = d.f1 - d.f0;
   double* xs = sm;
+  double* u = sm + a * nrhs;
+  double* u2 = u + d.nref * nrhs;
+  double* acc = u2 + d.nref * nrhs;
+  double* part = acc + nf * nrhs;
   for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
     const int i = idx % a, r = idx / a;
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  if (d.E && d.f1 > d.f0 && d.k > 0) {
-    const int nf = d.f1 - d.f0;
+  if (d.Et && nf > 0 && d.k > 0) {
+    // y_f[i] -= sum_c E[i, c] y_W[c]: the neighbours' values are staged in LDS
+    // (chunks of kChunk columns); one wave per row of E, lanes over columns.
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) acc[idx] = 0.0;
+    for (int c0 = 0; c0 < d.k; c0 += kChunk) {
+      const int cn = min(kChunk, d.k - c0);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < cn * nrhs; idx += kT) {
+        const int c = idx % cn, r = idx / cn;
+        part[idx] = z[d.nbr_pos[c0 + c] + r * ldz];
+      }
+      __syncthreads();
+      for (int i = wid; i < nf; i += kNW) {
+        const double* er = d.Et + c0 + (int64_t)i * d.lde;
+        for (int r = 0; r < nrhs; ++r) {
+          double sacc = 0.0;
+#pragma unroll 8
+          for (int c = lane; c < cn; c += kWave) sacc = fma(er[c], part[c + r * cn], sacc);
+          sacc = wave_sum(sacc);
+          if (lane == 0) acc[i + r * nf] += sacc;
+        }
+      }
+    }
+    __syncthreads();
     for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) {
       const int i = idx % nf, r = idx / nf;
-      double acc = 0.0;
-      for (int j = 0; j < d.k; ++j)
-        acc = fma(d.E[i + (int64_t)j * a], z[d.nbr_pos[j] + r * ldz], acc);
-      xs[d.f0 + i + r * a] -= acc;
+      xs[d.f0 + i + r * a] -= acc[idx];
     }
     __syncthreads();
   }
-  for (int j = d.nref - 1; j >= 0; --j) {
-    const double* v = d.V + (int64_t)j * a;
-    const double tau = d.tau[j];
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int i = j + threadIdx.x; i < a; i += kT) acc = fma(v[i], xs[i + r * a], acc);
-      const double w = block_sum(acc, red) * tau;
-      for (int i = j + threadIdx.x; i < a; i += kT) xs[i + r * a] = fma(-w, v[i], xs[i + r * a]);
-      __syncthreads();
-    }
-  }
+  wg_apply_wy(d.V, d.T, a, d.nref, xs, nrhs, u, u2, false);
   for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
     const int i = idx % a, r = idx / a;
     z[d.pos[i] + r * ldz] = xs[idx];
   }
 }
 
+// backward scaling: y_w <- Zinv^T y_w (column dots of Zinv)
 __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, double* z, int64_t ldz,
                                                      int nrhs) {
   extern __shared__ double sm[];
   const ApScale d = descs[blockIdx.x];
   const int n = d.n;
   double* xs = sm;
+  double* ys = sm + n * nrhs;
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
+  wg_coldots(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
+  __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
-    double acc = 0.0;
-    for (int m = i; m < n; ++m) acc = fma(d.Zinv[m + (int64_t)i * n], xs[m + r * n], acc);
-    z[d.pos[i] + r * ldz] = acc;
+    z[d.pos[i] + r * ldz] = ys[idx];
   }
 }
 
 // backward interior: y_s <- L^{-T} (y_s - G y_W)
+// LDS: us (n x nrhs) | ys (n x nrhs) | part (kNW x n x nrhs) | stage (kChunk x nrhs)
 __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z, int64_t ldz,
                                                    int nrhs) {
   extern __shared__ double sm[];
   const ApInt d = descs[blockIdx.x];
   const int n = d.n, k = d.k;
   double* us = sm;
+  double* ys = sm + n * nrhs;
+  double* part = ys + n * nrhs;
+  double* stage = part + kNW * n * nrhs;
+  if (k > 0) wg_rowsum_gather(d.G, n, n, k, d.nbr_pos, z, ldz, nrhs, stage, part, ys);
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
-    double acc = z[d.pos[i] + r * ldz];
-    for (int j = 0; j < k; ++j) acc = fma(-d.G[i + (int64_t)j * n], z[d.nbr_pos[j] + r * ldz], acc);
-    us[idx] = acc;
+    us[idx] = z[d.pos[i] + r * ldz] - (k > 0 ? ys[idx] : 0.0);
   }
+  __syncthreads();
+  wg_coldots(d.Linv, n, n, n, us, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
-    double acc = 0.0;
-    for (int m = i; m < n; ++m) acc = fma(d.Linv[m + (int64_t)i * n], us[m + r * n], acc);
-    z[d.pos[i] + r * ldz] = acc;
+    z[d.pos[i] + r * ldz] = ys[idx];
   }
 }
 
@@ -321,28 +463,31 @@ void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z
   hipLaunchKernelGGL(k_ap_gather, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
                      d, src, z, ldz, nrhs, T);
 }
+size_t sp_lds(int32_t max_a, int32_t nrhs) {
+  // xs (a) + u, u2 (nref <= a) + acc (nf <= a) per rhs, + part (kChunk per rhs)
+  return ((size_t)max_a * nrhs * 4 + (size_t)kChunk * nrhs) * sizeof(double);
+}
 void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       double* T, int32_t max_a, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_fwd, dim3(count), dim3(kT), (size_t)max_a * nrhs * sizeof(double), s,
-                     d, z, ldz, nrhs, T);
+  hipLaunchKernelGGL(k_ap_sp_fwd, dim3(count), dim3(kT), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs, T);
 }
 void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       int32_t max_a, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kT), (size_t)max_a * nrhs * sizeof(double), s,
-                     d, z, ldz, nrhs);
+  hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kT), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs);
 }
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_scale_bwd, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double),
+  hipLaunchKernelGGL(k_ap_scale_bwd, dim3(count), dim3(kT), 2 * (size_t)max_n * nrhs * sizeof(double),
                      s, d, z, ldz, nrhs);
 }
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_int_bwd, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
+  hipLaunchKernelGGL(k_ap_int_bwd, dim3(count), dim3(kT),
+                     ((size_t)(2 + kNW) * max_n * nrhs + (size_t)kChunk * nrhs) * sizeof(double), s,
                      d, z, ldz, nrhs);
 }
 

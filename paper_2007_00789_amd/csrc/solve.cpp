@@ -52,8 +52,6 @@ int64_t find_adj(const StepPlan& st, int c, int target) {
 void build_apply(Ctx& C, FactorObj& F) {
   hipStream_t s = C.stream;
   const Plan& P = *F.plan;
-  SPAND_HIP(hipStreamSynchronize(s));
-  C.stage.reset();
   auto* prog = new ApplyProg();
   F.prog = prog;
   const bool so = F.opts.scheme == SPAND_SECOND_ORDER;
@@ -66,7 +64,7 @@ void build_apply(Ctx& C, FactorObj& F) {
     as.l = l;
     const int nI = st.nI, nc = st.nc;
     std::vector<const int32_t*> dpos(nc, nullptr);
-    for (int c = 0; c < nc; ++c) dpos[c] = F.arena.upload(R.pos[c], s, C.stage);
+    for (int c = 0; c < nc; ++c) dpos[c] = F.meta.upload(R.pos[c]);
     // interiors
     std::vector<ApInt> ins;
     std::vector<int64_t> toff(nc, 0);
@@ -84,7 +82,7 @@ void build_apply(Ctx& C, FactorObj& F) {
       d.Linv = R.Linv[sI];
       d.G = R.G[sI];
       d.pos = dpos[sI];
-      d.nbr_pos = F.arena.upload(nbr, s, C.stage);
+      d.nbr_pos = F.meta.upload(nbr);
       d.toff = tsz;
       d.n = n;
       d.k = (int32_t)nbr.size();
@@ -94,7 +92,7 @@ void build_apply(Ctx& C, FactorObj& F) {
       as.max_in = std::max(as.max_in, n);
     }
     prog->scratch = std::max(prog->scratch, tsz);
-    as.in = F.arena.upload(ins, s, C.stage);
+    as.in = F.meta.upload(ins);
     as.n_in = (int32_t)ins.size();
     // interface gathers (+ scaling)
     std::vector<ApGat> gs;
@@ -129,10 +127,10 @@ void build_apply(Ctx& C, FactorObj& F) {
         as.max_sc = std::max(as.max_sc, n);
       }
     }
-    as.gat = F.arena.upload(gs, s, C.stage);
-    as.src = F.arena.upload(srcs, s, C.stage);
+    as.gat = F.meta.upload(gs);
+    as.src = F.meta.upload(srcs);
     as.n_gat = (int32_t)gs.size();
-    as.sc = F.arena.upload(scs, s, C.stage);
+    as.sc = F.meta.upload(scs);
     as.n_sc = (int32_t)scs.size();
     // sparsification, per colour
     if (st.sparsified) {
@@ -147,14 +145,16 @@ void build_apply(Ctx& C, FactorObj& F) {
           ApSp d{};
           d.V = R.V[p];
           d.tau = R.tau[p];
+          d.T = R.T[p];
           d.pos = dpos[p];
-          d.nbr_pos = F.arena.upload(R.sp_nbr_pos[p], s, C.stage);
+          d.nbr_pos = F.meta.upload(R.sp_nbr_pos[p]);
           d.a = R.n0[p];
           d.nref = R.r2[p];
           d.f0 = R.r[p];
           d.f1 = so ? R.n0[p] : (sf ? R.r2[p] : R.r[p]);
           d.k = R.k[p];
-          d.E = (so || sf) && R.Y[p] ? R.Y[p] + d.f0 : nullptr;
+          d.lde = R.kmax[p];
+          d.Et = (so || sf) && R.Y[p] ? R.Y[p] + (int64_t)d.f0 * R.kmax[p] : nullptr;
           d.toff = csz;
           ptoff[p] = csz;
           csz += d.k;
@@ -162,7 +162,7 @@ void build_apply(Ctx& C, FactorObj& F) {
           ac.max_a = std::max(ac.max_a, d.a);
         }
         prog->scratch = std::max(prog->scratch, csz);
-        ac.sp = F.arena.upload(sps, s, C.stage);
+        ac.sp = F.meta.upload(sps);
         ac.n_sp = (int32_t)sps.size();
         if (!(so || sf)) continue;
         // targets: interfaces adjacent to an interface of this colour
@@ -196,13 +196,14 @@ void build_apply(Ctx& C, FactorObj& F) {
             ac.max_n = std::max(ac.max_n, wc);
           }
         }
-        ac.gat = F.arena.upload(eg, s, C.stage);
-        ac.src = F.arena.upload(es, s, C.stage);
+        ac.gat = F.meta.upload(eg);
+        ac.src = F.meta.upload(es);
         ac.n_gat = (int32_t)eg.size();
       }
     }
     prog->steps.push_back(std::move(as));
   }
+  F.meta.flush(s);
   SPAND_HIP(hipStreamSynchronize(s));
 }
 
@@ -215,26 +216,29 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   // every apply kernel stages its cluster's slice of the vectors in LDS
   constexpr int64_t kLds = 160 * 1024;
   for (const ApplyStep& as : pg.steps) {
-    int64_t need = std::max<int64_t>(2 * as.max_in, std::max(as.max_gat, as.max_sc));
-    for (const ApplyColour& ac : as.colours) need = std::max<int64_t>(need, std::max(ac.max_a, ac.max_n));
-    if (need * nrhs * (int64_t)sizeof(double) > kLds)
+    int64_t need = std::max<int64_t>((int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
+                                      (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
+    for (const ApplyColour& ac : as.colours)
+      need = std::max<int64_t>(need, std::max<int64_t>((int64_t)ac.max_a * 4 * nrhs + 1024 * nrhs,
+                                                       (int64_t)ac.max_n * nrhs));
+    if (need * (int64_t)sizeof(double) > kLds)
       throw Error(SPAND_E_LIMIT, "cluster too large for the apply with nrhs = " + std::to_string(nrhs));
   }
-  if (x != y) launch_copy_vec(x, y, n * nrhs, s);
+  if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
-    launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s);
-    launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s);
+    SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
+    SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
     for (const ApplyColour& ac : as.colours) {
-      launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, T, ac.max_a, s);
-      launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s);
+      SPAND_PROF(C, "k_ap_sp_fwd", launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, T, ac.max_a, s));
+      SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s));
     }
   }
   for (auto it = pg.steps.rbegin(); it != pg.steps.rend(); ++it) {
     const ApplyStep& as = *it;
     for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c)
-      launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, c->max_a, s);
-    launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s);
-    launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s);
+      SPAND_PROF(C, "k_ap_sp_bwd", launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, c->max_a, s));
+    SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
+    SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
   }
 }
 
@@ -259,7 +263,7 @@ void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const dou
   std::vector<int32_t> h_active(nrhs, 1);
   std::vector<double> h_bn(nrhs), h_rr(nrhs);
 
-  launch_dot(b, b, n, nrhs, partial, rr, s);
+  SPAND_PROF(C, "k_dot", launch_dot(b, b, n, nrhs, partial, rr, s));
   SPAND_HIP(hipMemcpyAsync(h_bn.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
   SPAND_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < nrhs; ++c) {
@@ -269,17 +273,17 @@ void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const dou
   }
   SPAND_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
   SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  launch_copy_vec(b, r, nv, s);
+  SPAND_PROF(C, "k_copy_vec", launch_copy_vec(b, r, nv, s));
   run_apply(C, F, nrhs, r, z);
-  launch_dot(r, z, n, nrhs, partial, rho_new, s);
-  launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 1, s);
+  SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, partial, rho_new, s));
+  SPAND_PROF(C, "k_pcg_p", launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 1, s));
   int nact = 0;
   for (int c = 0; c < nrhs; ++c) nact += h_active[c];
   for (int it = 1; it <= maxit && nact > 0; ++it) {
-    launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, p, q, s);
-    launch_dot(p, q, n, nrhs, partial, pq, s);
-    launch_pcg_xr(x, r, p, q, rho, pq, active, n, nrhs, s);
-    launch_dot(r, r, n, nrhs, partial, rr, s);
+    SPAND_PROF(C, "k_spmv", launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, p, q, s));
+    SPAND_PROF(C, "k_dot", launch_dot(p, q, n, nrhs, partial, pq, s));
+    SPAND_PROF(C, "k_pcg_xr", launch_pcg_xr(x, r, p, q, rho, pq, active, n, nrhs, s));
+    SPAND_PROF(C, "k_dot", launch_dot(r, r, n, nrhs, partial, rr, s));
     SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     SPAND_HIP(hipStreamSynchronize(s));
     bool changed = false;
@@ -297,13 +301,13 @@ void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const dou
       SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
     run_apply(C, F, nrhs, r, z);
-    launch_dot(r, z, n, nrhs, partial, rho_new, s);
-    launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 0, s);
+    SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, partial, rho_new, s));
+    SPAND_PROF(C, "k_pcg_p", launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 0, s));
   }
   // true residual
-  launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, x, q, s);
-  launch_residual(b, q, n, nrhs, s);
-  launch_dot(q, q, n, nrhs, partial, rr, s);
+  SPAND_PROF(C, "k_spmv", launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, x, q, s));
+  SPAND_PROF(C, "k_residual", launch_residual(b, q, n, nrhs, s));
+  SPAND_PROF(C, "k_dot", launch_dot(q, q, n, nrhs, partial, rr, s));
   SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
   SPAND_HIP(hipStreamSynchronize(s));
   *converged = nact == 0;

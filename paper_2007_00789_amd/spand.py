@@ -74,6 +74,9 @@ SIGNATURES = {
     "spand_apply": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "spand_pcg": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_double, C.c_int32, _I32P, _DP]),
     "spand_debug_block": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _I32P, _I32P]),
+    "spand_profile": (C.c_int, [_P, C.c_int32]),
+    "spand_profile_entries": (C.c_int, [_P, _I32P]),
+    "spand_profile_entry": (C.c_int, [_P, C.c_int32, C.c_char_p, C.c_int32, _DP, _I64P, _DP]),
 }
 
 _lib = None
@@ -141,6 +144,23 @@ class Context:
     def _check(self, st):
         if st != SPAND_OK:
             raise SpandError(st, self.lib.spand_last_error(self.h).decode())
+
+    def profile(self, enable: bool):
+        """spand_profile: clear and start (or stop) per-kernel event timing."""
+        self._check(self.lib.spand_profile(self.h, 1 if enable else 0))
+
+    def profile_entries(self) -> dict:
+        """{kernel: (total_ms, launches, work)} accumulated since profile(True)."""
+        n = C.c_int32()
+        self._check(self.lib.spand_profile_entries(self.h, C.byref(n)))
+        out = {}
+        buf = C.create_string_buffer(64)
+        for i in range(n.value):
+            ms, calls, work = C.c_double(), C.c_int64(), C.c_double()
+            self._check(self.lib.spand_profile_entry(self.h, i, buf, 64, C.byref(ms),
+                                                     C.byref(calls), C.byref(work)))
+            out[buf.value.decode()] = (ms.value, calls.value, work.value)
+        return out
 
     def factor(self, plan: "Plan", vals, opts: Opts) -> "Factor":
         """spand_factor; vals: device buffer of nnz float64 values."""
