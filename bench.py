@@ -73,6 +73,17 @@ def cpu_baseline(scheme: str, eps: float, gpu_ref: dict) -> dict:
     }
 
 
+def traffic_from_env(kernel):
+    """HBM traffic of the dominant kernel per launch, if a profiler summary
+    provided it (SPAND_TRAFFIC_JSON: {kernel: {"fetch_kib": F, "write_kib": W}},
+    already scaled by the copy-kernel calibration)."""
+    path = os.environ.get("SPAND_TRAFFIC_JSON")
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(kernel)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +93,19 @@ def main():
     ap.add_argument("--scheme", default="SO")
     ap.add_argument("--workload", default="lap3d_64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (calibrates the HBM "
+                         "byte counters of a profiler run) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
               "(see DESIGN.md for how it would shard); use --gpus 1.", file=sys.stderr)
@@ -141,10 +164,11 @@ def main():
     # dominant kernel by total event time inside the timed region
     dom, (dms, dcalls, dwork) = max(prof.items(), key=lambda kv: kv[1][0])
     kernel_ms = {k: round(v[0] / args.steps, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    if dom == "k_cpqr":
+    if dom in ("k_cpqr", "k_cpqr_coop"):
         # FP64 vector ALU work of the pivoted QR: sum over reflectors of 4(a-j)(k-j)
         ach = dwork / (dms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                "work": "FP64 flops of the pivoted QR, sum over reflectors j of 4(a-j)(k-j)",
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
                 "avg_launch_ms": dms / dcalls, "launches": dcalls}
     else:
@@ -178,6 +202,7 @@ def main():
         "mu": info["nnz_L"] / prob.nnz,
         "factor_gflop": flops / 1e9,
         "analyze_s": analyze_s,
+        "traffic_kib_per_launch": traffic_from_env(dom),
         "kernel_ms_per_step": kernel_ms,
         "roofline": roof,
     }

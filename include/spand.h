@@ -63,6 +63,9 @@ typedef struct {
   int32_t scheme;     /* spand_scheme */
   int32_t precision;  /* spand_precision */
   int32_t debug_stop_step;  /* >= 0: stop after sparsifying this step (parity dumps); -1: off */
+  int32_t qr_group;     /* QR workgroups per interface: 0 auto, -1 single-workgroup kernel only,
+                           g >= 1 force g (testing; capped by the coupling width and 32) */
+  int32_t qr_list_cap;  /* tie candidates exchanged per workgroup: -1 default (32), 0..32 (testing) */
 } spand_opts;
 
 void spand_default_opts(spand_opts* opts);

@@ -49,6 +49,8 @@ void check_opts(const spand_opts* o) {
     throw Error(SPAND_E_INVALID, "unknown scheme");
   if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
   if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
+  if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32)
+    throw Error(SPAND_E_INVALID, "bad QR testing options");
 }
 
 // device copies of the pattern and of the leaf assembly map, made on first use
@@ -80,6 +82,8 @@ void spand_default_opts(spand_opts* o) {
   o->scheme = SPAND_SECOND_ORDER;
   o->precision = SPAND_FP64;
   o->debug_stop_step = -1;
+  o->qr_group = 0;
+  o->qr_list_cap = -1;
 }
 
 const char* spand_status_string(spand_status s) {

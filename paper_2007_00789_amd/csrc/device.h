@@ -66,6 +66,21 @@ struct CpqrDesc {
   int32_t a, kmax, p, pad;
 };
 
+// One interface of a cooperative QR launch: G workgroups (blocks block0 ..
+// block0+G-1) share the columns of W, at most ncap each.
+struct CoopDesc {
+  CpqrDesc d;
+  int32_t* counter;  // group barrier counter (zeroed by the launcher)
+  double* xch;       // exchange buffer, coop_xch_doubles(G, a)
+  int32_t G, block0, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
+};
+constexpr int kCoopMaxGroup = 32;
+constexpr size_t kCoopLdsBytes = 140 * 1024;
+inline int64_t coop_xch_doubles(int G, int a) {
+  return 2 * (int64_t)G * (2 + 2 * 32) + (int64_t)(2 * G + 1) * (a + 1) + G;
+}
+constexpr int kCoopCounterStride = 32;   // one 128-byte line per group counter
+
 // Dense block copy (merge of children's blocks into parent panels).
 struct CopyDesc {
   const double* src;
@@ -84,6 +99,12 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
                  int32_t max_a, int32_t max_k, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
+// maximum co-resident workgroups of the cooperative QR for a given LDS size
+int coop_max_blocks(size_t lds_bytes);
+hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk2grp,
+                            int32_t nblocks, int32_t* counters, int32_t ncounters, int32_t* n_cur,
+                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
+                            double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s);
 
 constexpr int kGemmTile = 64;
 constexpr int kCpqrMaxK = 12288;      // trailing norms of a CPQR live in LDS

@@ -239,7 +239,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     int32_t* d_k = dint + 3 * nc;
     int32_t* d_info_i = dint + 4 * nc;
     int32_t* d_info_f = dint + 5 * nc;
-    SPAND_HIP(hipMemsetAsync(dint, 0, sizeof(int32_t) * 6 * (size_t)nc, s));
+    int32_t* d_err = dint + 6 * nc;
+    SPAND_HIP(hipMemsetAsync(dint, 0, sizeof(int32_t) * (6 * (size_t)nc + 1), s));
     {
       const int32_t* h = C.upload.upload(sizes);
       C.upload.flush(s);
@@ -365,6 +366,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
 
     // ---------------- (b) scaling and (c) sparsification ----------------
+    std::vector<char> coop_used;
     std::vector<PotrfDesc> zd;
     std::vector<int32_t> zd_cluster;
     if (st.sparsified) {
@@ -441,9 +443,13 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2,
                     (int64_t)tl2.size(), s));
       }
-      // sparsification, one launch per colour
+      // sparsification, one launch per colour: interfaces whose coupling fits
+      // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
+      // the others the single-workgroup QR on a global-memory workspace
+      coop_used.assign(nc, 0);
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrDesc> cd;
+        std::vector<CoopDesc> qd;
         std::vector<CpqrNbr> cn;
         int ma = 1, mk = 1;
         for (int p : st.order) {
@@ -470,8 +476,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           d.nb1 = (int64_t)cn.size();
           d.kmax = (int32_t)kmax;
           R.kmax[p] = kmax;
-          if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
-                                                               std::to_string(kCpqrMaxK));
           const int64_t mn = std::min<int64_t>(a, kmax);
           if (a > 0 && kmax > 0) {
             R.Y[p] = F.arena.alloc_n<double>((size_t)a * kmax);
@@ -483,15 +487,73 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           d.V = R.V[p];
           d.tau = R.tau[p];
           d.T = R.T[p];
+          const int64_t cap = a > 0 ? ((int64_t)(kCoopLdsBytes / 8) - a) / (a + 1) : 0;
+          int64_t G = cap > 0 ? (kmax + cap - 1) / cap : 0;
+          if (o.qr_group > 0) G = std::max(G, std::min<int64_t>(o.qr_group, kmax));
+          if (o.qr_group >= 0 && a > 0 && kmax > 0 && G >= 1 && G <= kCoopMaxGroup) {
+            CoopDesc q{};
+            q.d = d;
+            q.G = (int32_t)G;
+            q.ncap = (int32_t)((kmax + G - 1) / G);
+            q.list_cap = o.qr_list_cap < 0 ? 32 : o.qr_list_cap;
+            qd.push_back(q);
+            coop_used[p] = 1;
+            continue;
+          }
+          if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
+                                                               std::to_string(kCpqrMaxK));
           ma = std::max(ma, a);
           mk = std::max<int>(mk, (int)kmax);
           cd.push_back(d);
         }
-        if (cd.empty()) continue;
-        const auto* d_cd = C.upload.upload(cd);
-        const auto* d_cn = C.upload.upload(cn);
-        SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r,
-                    d_r2, d_k, eps, eps_stop, ma, mk, s));
+        const CpqrNbr* d_cn = C.upload.upload(cn);
+        if (!cd.empty()) {
+          const auto* d_cd = C.upload.upload(cd);
+          SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r, d_r2,
+                                              d_k, eps, eps_stop, ma, mk, s));
+        }
+        // cooperative batches bounded by co-residency
+        size_t i0 = 0;
+        while (i0 < qd.size()) {
+          size_t lds = 0;
+          int64_t blocks = 0, xdoubles = 0;
+          size_t i1 = i0;
+          for (; i1 < qd.size(); ++i1) {
+            const CoopDesc& q = qd[i1];
+            const size_t l = ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double);
+            const size_t lds2 = std::max(lds, l);
+            const int cap_blocks = coop_max_blocks(lds2);
+            if (cap_blocks <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
+            if (blocks + q.G > cap_blocks) break;
+            lds = lds2;
+            blocks += q.G;
+            xdoubles += coop_xch_doubles(q.G, q.d.a);
+          }
+          if (i1 == i0) throw Error(SPAND_E_LIMIT, "cooperative QR group larger than the device");
+          int32_t* counters = C.upload.alloc_n<int32_t>((i1 - i0) * kCoopCounterStride);
+          double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
+          std::vector<int32_t> blk2grp;
+          int64_t xo = 0;
+          for (size_t i = i0; i < i1; ++i) {
+            CoopDesc& q = qd[i];
+            q.block0 = (int32_t)blk2grp.size();
+            q.counter = counters + (i - i0) * kCoopCounterStride;
+            q.xch = xch + xo;
+            xo += coop_xch_doubles(q.G, q.d.a);
+            for (int g = 0; g < q.G; ++g) blk2grp.push_back((int32_t)(i - i0));
+          }
+          std::vector<CoopDesc> batch(qd.begin() + i0, qd.begin() + i1);
+          const auto* d_qd = C.upload.upload(batch);
+          const auto* d_b2g = C.upload.upload(blk2grp);
+          hipError_t he = hipSuccess;
+          SPAND_PROF(C, "k_cpqr_coop",
+                     he = launch_cpqr_coop(d_qd, d_cn, d_b2g, (int32_t)blk2grp.size(), counters,
+                                           (int32_t)((i1 - i0) * kCoopCounterStride), d_ncur, d_r,
+                                           d_r2, d_k, eps,
+                                           eps_stop, d_err, lds, s));
+          SPAND_HIP(he);
+          i0 = i1;
+        }
       }
     }
     // read back breakdown flags and ranks
@@ -502,7 +564,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     if (!zd.empty())
       SPAND_HIP(hipMemcpyAsync(info_f.data(), d_info_f, sizeof(int32_t) * zd.size(),
                                hipMemcpyDeviceToHost, s));
+    int32_t herr = 0;
     if (st.sparsified) {
+      SPAND_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       SPAND_HIP(hipMemcpyAsync(hr.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
       SPAND_HIP(hipMemcpyAsync(hr2.data(), d_r2, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
       SPAND_HIP(hipMemcpyAsync(hk.data(), d_k, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
@@ -510,6 +574,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     SPAND_HIP(hipStreamSynchronize(s));
     check_info(info_i, pd_cluster, l, "interior block");
     check_info(info_f, zd_cluster, l, "interface block");
+    if (herr) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
 
     std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
     if (st.sparsified) {
@@ -536,7 +601,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         double qr = 0.0;
         for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
         flops += qr;
-        C.prof.add_work("k_cpqr", qr);
+        C.prof.add_work(coop_used[p] ? "k_cpqr_coop" : "k_cpqr", qr);
         nnzL += (int64_t)a * r2 - (int64_t)r2 * (r2 - 1) / 2 + r2;
         if (so) nnzL += (int64_t)(a - r) * (k - r);
         if (sf) {

@@ -1,0 +1,488 @@
+// Cooperative early-stopping column-pivoted Householder QR (Alg. 1): the
+// coupling W (a x k) of one interface is split by columns over a group of G
+// workgroups, each holding its column slice in LDS for the whole
+// factorization, so every pivot step is on-chip work plus two group barriers:
+//
+//  A. every workgroup publishes its largest trailing norm and the complete
+//     list of its columns within the tie band of that maximum; since the
+//     global band lies inside every local band, the union of the lists holds
+//     every global candidate and each workgroup picks the same pivot (lowest
+//     index among columns within the band of the global maximum).  If a list
+//     overflows, an extra round exchanges exact local candidates.
+//  C. the owner of the pivot column publishes it; every workgroup builds the
+//     Householder vector and updates its columns, recomputing their trailing
+//     norms exactly (the same fused pass as the single-workgroup kernel).
+//
+// The launch is cooperative (all workgroups resident), group barriers are
+// agent-scope counters, and every spin is bounded: a timeout raises an error
+// flag and all workgroups leave, so a launch can never hang.
+#include <climits>
+
+#include "device.h"
+
+namespace spand {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kCT = 1024;               // threads per workgroup
+constexpr int kCW = kCT / kWave;        // waves per workgroup
+constexpr int kList = 32;               // tie candidates published per workgroup
+constexpr int kXs = 2 + 2 * kList;      // exchange stride: max, count, idx[], nrm2[]
+constexpr long kSpinLimit = 1L << 24;   // ~ seconds of s_sleep before giving up
+constexpr int kRpl = 16;                // rows per lane kept in registers by the update
+
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), kCtrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xb1>(v);
+  v += dpp_move<0x4e>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x128>(v);
+  v += dpp_move<0x142>(v);
+  v += dpp_move<0x143>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each group of 8 lanes, returned to all 8: two quad permutations and
+// a half-row mirror.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+// DPP move whose invalid source lanes read -inf (for maxima)
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move_ninf(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)0xfff00000, __double2hiint(x), kCtrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_move_ninf<0xb1>(v));
+  v = fmax(v, dpp_move_ninf<0x4e>(v));
+  v = fmax(v, dpp_move_ninf<0x124>(v));
+  v = fmax(v, dpp_move_ninf<0x128>(v));
+  v = fmax(v, dpp_move_ninf<0x142>(v));
+  v = fmax(v, dpp_move_ninf<0x143>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// exchange values go through agent-scope atomics (coherent across CUs/XCDs)
+__device__ __forceinline__ void xst(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xld(double* p) {
+  const unsigned long long u = __hip_atomic_load(reinterpret_cast<unsigned long long*>(p),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double(static_cast<long long>(u));
+}
+
+// Group barrier on a monotone counter: returns false after a timeout.  All
+// exchanged data travels through agent-scope atomics, which are performed at
+// the coherence point; the workgroup-scope release below only waits until the
+// workgroup's own stores have completed before thread 0 bumps the counter, and
+// readers fetch the data with agent-scope atomic loads after the barrier.
+__device__ bool group_barrier(int32_t* counter, int target, int G, int32_t* err, int* sok) {
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
+  __syncthreads();
+  if (G == 1) return true;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        ok = 0;
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    *sok = ok;
+  }
+  __syncthreads();
+  return *sok != 0;
+}
+
+__global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const CpqrNbr* nbrs,
+                                                  const int32_t* blk2grp, int32_t* n_cur,
+                                                  int32_t* out_r, int32_t* out_r2, int32_t* out_k,
+                                                  double eps, double eps_stop, int32_t* err) {
+  extern __shared__ double sm[];
+  __shared__ double redd[kCW];
+  __shared__ int redi[kCW];
+  __shared__ int sok;
+  __shared__ double sM;
+  __shared__ int sC, sover, sfirst, shead;
+  __shared__ int s_wcnt[kCW + 1];
+  const CoopDesc cd = descs[blk2grp[blockIdx.x]];
+  const CpqrDesc& d = cd.d;
+  const int G = cd.G, g = blockIdx.x - cd.block0;
+  const int a = d.a;
+  const int64_t K = d.kmax;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+
+  int k = 0;
+  for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
+  const int per = (k + G - 1) / G;
+  const int c0 = min(k, g * per), c1 = min(k, c0 + per), m = c1 - c0;
+  double* Ys = sm;                                  // a x ncap (ld a)
+  double* nrm2 = sm + (int64_t)a * cd.ncap;         // ncap
+  double* v = nrm2 + cd.ncap;                       // a
+  // exchange: lists and first-candidate columns are double buffered by step
+  // parity (a workgroup may publish step j+1 while others still read step j)
+  double* X2 = cd.xch;                              // 2 x G x kXs
+  double* PV2 = X2 + 2 * (int64_t)G * kXs;          // 2 x G x (a + 1)
+  double* PVx = PV2 + 2 * (int64_t)G * (a + 1);     // a + 1: pivot of the slow path
+  double* XB = PVx + a + 1;                         // G
+
+  // my columns [c0, c1) of W
+  {
+    int kk = 0;
+    for (int64_t e = d.nb0; e < d.nb1; ++e) {
+      const CpqrNbr nb = nbrs[e];
+      const int wc = n_cur[nb.w];
+      const int lo = max(kk, c0), hi = min(kk + wc, c1);
+      if (hi > lo) {
+        const double* src = d.panel + (nb.col + (lo - kk)) * a;
+        double* dst = Ys + (int64_t)(lo - c0) * a;
+        for (int idx = tid; idx < (hi - lo) * a; idx += kCT) dst[idx] = src[idx];
+      }
+      kk += wc;
+    }
+  }
+  __syncthreads();
+  for (int c = wid; c < m; c += kCW) {
+    const double* col = Ys + (int64_t)c * a;
+    double s = 0.0;
+    for (int i = lane; i < a; i += kWave) s = fma(col[i], col[i], s);
+    s = wave_sum(s);
+    if (lane == 0) nrm2[c] = s;
+  }
+  __syncthreads();
+
+  int phase = 0;
+  int r = -1, j = 0;
+  double R00 = 0.0;
+  const int jmax = min(a, k);
+  for (; j < jmax; ++j) {
+    // ---- A: local maximum, the ordered list of local tie candidates, and
+    //      the column of the first local candidate (speculative pivot) ----
+    double* X = X2 + (int64_t)(j & 1) * G * kXs;
+    double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
+    double ml = -1.0;
+    for (int c = tid; c < m; c += kCT) ml = fmax(ml, nrm2[c]);
+    ml = wave_max(ml);
+    if (lane == 0) redd[wid] = ml;
+    if (tid == 0) sfirst = -1;
+    __syncthreads();
+    double Mg = redd[0];
+#pragma unroll
+    for (int w = 1; w < kCW; ++w) Mg = fmax(Mg, redd[w]);
+    const double thl = Mg * (1.0 - kPivotTieRtol);
+    double* Xg = X + (int64_t)g * kXs;
+    int total = 0;
+    for (int cb = 0; cb < m; cb += kCT) {      // ordered compaction, kCT columns at a time
+      const int c = cb + tid;
+      const bool f = Mg >= 0.0 && c < m && nrm2[c] >= 0.0 && nrm2[c] >= thl;
+      const unsigned long long mask = __ballot(f);
+      if (lane == 0) s_wcnt[wid] = __popcll(mask);
+      __syncthreads();
+      int before = total;
+      for (int w = 0; w < wid; ++w) before += s_wcnt[w];
+      if (f) {
+        const int at = before + __popcll(mask & ((1ULL << lane) - 1ULL));
+        if (at == 0) sfirst = c;
+        if (at < cd.list_cap) {
+          xst(Xg + 2 + at, (double)(c0 + c));
+          xst(Xg + 2 + kList + at, nrm2[c]);
+        }
+      }
+      for (int w = 0; w < kCW; ++w) total += s_wcnt[w];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      xst(Xg, Mg);
+      xst(Xg + 1, (double)total);
+    }
+    const int first = sfirst;  // local index of my first candidate, or -1
+    if (first >= 0) {
+      double* Pg = PVs + (int64_t)g * (a + 1);
+      if (tid == 0) xst(Pg, nrm2[first]);
+      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
+    }
+    if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+    // global maximum and pivot (every workgroup computes the same).  One
+    // round of loads: thread (q, e) fetches group q's maximum, count and list
+    // entry e; the decision is made with workgroup reductions.
+    const int q = tid / kList, e = tid % kList;
+    double Mq = -2.0, nv = -1.0;
+    int cq = 0, ix = INT_MAX;
+    if (q < G) {
+      const double* Xq = X + (int64_t)q * kXs;
+      Mq = xld(const_cast<double*>(Xq));
+      cq = (int)xld(const_cast<double*>(Xq + 1));
+      if (e < cd.list_cap) {
+        ix = (int)xld(const_cast<double*>(Xq + 2 + e));
+        nv = xld(const_cast<double*>(Xq + 2 + kList + e));
+      }
+    }
+    {
+      double mm = wave_max(Mq);
+      const int ov = wave_max_int(q < G && e == 0 && cq > cd.list_cap ? 1 : 0);
+      if (lane == 0) { redd[wid] = mm; redi[wid] = ov; }
+      __syncthreads();
+      double M = redd[0];
+      int over = redi[0];
+      for (int w = 1; w < kCW; ++w) { M = fmax(M, redd[w]); over = max(over, redi[w]); }
+      if (tid == 0) { sM = M; sover = over; }
+      __syncthreads();
+    }
+    const double M = sM;
+    if (M < 0.0) break;
+    const double thr = M * (1.0 - kPivotTieRtol);
+    int C = INT_MAX;
+    if (!sover) {
+      if (q < G && e < cq && nv >= thr) C = ix;
+    } else {
+      // B: exact local candidates against the global threshold
+      int cl = INT_MAX;
+      for (int c = tid; c < m; c += kCT)
+        if (nrm2[c] >= 0.0 && nrm2[c] >= thr) { cl = c0 + c; break; }
+      cl = wave_min_int(cl);
+      if (lane == 0) redi[wid] = cl;
+      __syncthreads();
+      if (tid == 0) {
+        int mn = redi[0];
+        for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
+        xst(XB + g, (double)mn);
+      }
+      if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+      for (int qq = tid; qq < G; qq += kCT) C = min(C, (int)xld(XB + qq));
+    }
+    C = wave_min_int(C);
+    if (lane == 0) redi[wid] = C;
+    __syncthreads();
+    if (tid == 0) {
+      int mn = redi[0];
+      for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
+      sC = mn;
+    }
+    __syncthreads();
+    C = sC;
+    const bool owner = C >= c0 && C < c1;
+    const int Cl = C - c0;
+    const int og = min(C / max(per, 1), G - 1);   // owner workgroup
+    // the owner's published first candidate is the pivot unless the lists
+    // overflowed or its first candidate fell outside the global band
+    if (q == og && e == 0) shead = (cq > 0 && cd.list_cap > 0) ? ix : -1;
+    __syncthreads();
+    const bool spec = !sover && shead == C;
+    double* PV = PVs + (int64_t)og * (a + 1);
+    if (!spec) {
+      PV = PVx;
+      if (owner) {
+        if (tid == 0) xst(PV, nrm2[Cl]);
+        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
+      }
+      if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+    }
+    // one round of loads: the pivot's norm, its first entry and the rest of it
+    const double pn = xld(PV), alpha = xld(PV + 1);
+    double xi[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = j + 1 + tid + t * kCT;
+      xi[t] = i < a ? xld(PV + 1 + (i - j)) : 0.0;
+    }
+    const double nrm = sqrt(pn);
+    if (j == 0) R00 = nrm;
+    if (nrm == 0.0 || nrm < eps_stop * R00) break;
+    if (r < 0 && nrm < eps * R00) r = j;
+    const double beta = alpha >= 0.0 ? -nrm : nrm;
+    const double denom = alpha - beta;
+    const double tau = (beta - alpha) / beta;
+    for (int i = tid; i <= j; i += kCT) {
+      v[i] = i == j ? 1.0 : 0.0;
+      if (g == 0) d.V[i + (int64_t)j * a] = v[i];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = j + 1 + tid + t * kCT;
+      if (i < a) {
+        v[i] = xi[t] / denom;
+        if (g == 0) d.V[i + (int64_t)j * a] = v[i];
+      }
+    }
+    for (int i = j + 1 + tid + 4 * kCT; i < a; i += kCT) {
+      v[i] = xld(PV + 1 + (i - j)) / denom;
+      if (g == 0) d.V[i + (int64_t)j * a] = v[i];
+    }
+    if (g == 0 && tid == 0) d.tau[j] = tau;
+    __syncthreads();
+    // fused reflector update + exact trailing norms: 8 lanes per column,
+    // 8 columns per wave; one 3-step DPP reduction serves 8 columns at once
+    {
+      const int grp = lane >> 3, r8 = lane & 7;
+      for (int cb = wid * 8; cb < m; cb += kCW * 8) {
+        const int c = cb + grp;
+        const bool act = c < m && !(owner && c == Cl) && nrm2[c] >= 0.0;
+        double* col = Ys + (int64_t)(act ? c : 0) * a;
+        double yv[kRpl];
+        double dot = 0.0;
+#pragma unroll
+        for (int t = 0; t < kRpl; ++t) {
+          const int i = j + r8 + 8 * t;
+          const bool in = act && i < a;
+          yv[t] = in ? col[i] : 0.0;
+          dot = fma(in ? v[i] : 0.0, yv[t], dot);
+        }
+        for (int i = j + r8 + 8 * kRpl; i < a; i += 8)
+          if (act) dot = fma(v[i], col[i], dot);
+        dot = group8_sum(dot) * tau;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < kRpl; ++t) {
+          const int i = j + r8 + 8 * t;
+          if (act && i < a) {
+            const double y = fma(-dot, v[i], yv[t]);
+            col[i] = y;
+            if (i > j) s = fma(y, y, s);
+          }
+        }
+        for (int i = j + r8 + 8 * kRpl; i < a; i += 8)
+          if (act) {
+            const double y = fma(-dot, v[i], col[i]);
+            col[i] = y;
+            s = fma(y, y, s);
+          }
+        s = group8_sum(s);
+        if (act && r8 == 0) nrm2[c] = s;
+      }
+    }
+    if (owner) {
+      for (int i = j + tid; i < a; i += kCT) Ys[i + (int64_t)Cl * a] = i == j ? beta : 0.0;
+      if (tid == 0) nrm2[Cl] = -1.0;
+    }
+    __syncthreads();
+  }
+  const int nref = j;
+  if (r < 0) r = nref;
+
+  // Q^T W of my columns into the transposed workspace (E^T lives in rows r..)
+  for (int idx = tid; idx < m * a; idx += kCT) {
+    const int c = idx % m, i = idx / m;
+    d.Y[(c0 + c) + i * K] = Ys[i + (int64_t)c * a];
+  }
+  // coarse rows into p's panel and, transposed, into the neighbours' panels
+  {
+    int kk = 0;
+    for (int64_t e = d.nb0; e < d.nb1; ++e) {
+      const CpqrNbr nb = nbrs[e];
+      const int wc = n_cur[nb.w];
+      const int lo = max(kk, c0), hi = min(kk + wc, c1);
+      for (int idx = tid; idx < r * (hi - lo); idx += kCT) {
+        const int cc = idx % (hi - lo), i = idx / (hi - lo);
+        const int cw = lo - kk + cc;  // column inside block (p, w)
+        const double y = Ys[i + (int64_t)(lo - c0 + cc) * a];
+        d.panel[i + (nb.col + cw) * a] = y;
+        nb.blk_wp[cw + (int64_t)i * nb.ldw] = y;
+      }
+      kk += wc;
+    }
+  }
+  if (g != 0) return;
+  // triangular factor of the compact WY form (see k_cpqr); the dead slice
+  // (a * ncap >= nref doubles) holds V_{:,0:j}^T v_j
+  __syncthreads();
+  double* vtv = Ys;
+  for (int jj = 0; jj < nref; ++jj) {
+    const double* vj = d.V + (int64_t)jj * a;
+    for (int i = wid; i < jj; i += kCW) {
+      const double* vi = d.V + (int64_t)i * a;
+      double acc = 0.0;
+      for (int q = jj + lane; q < a; q += kWave) acc = fma(vi[q], vj[q], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) vtv[i] = acc;
+    }
+    __syncthreads();
+    const double tj = d.tau[jj];
+    for (int i = tid; i < jj; i += kCT) {
+      double acc = 0.0;
+      for (int q = i; q < jj; ++q) acc = fma(d.T[i + (int64_t)q * nref], vtv[q], acc);
+      d.T[i + (int64_t)jj * nref] = -tj * acc;
+    }
+    for (int i = jj + 1 + tid; i < nref; i += kCT) d.T[i + (int64_t)jj * nref] = 0.0;
+    if (tid == 0) d.T[jj + (int64_t)jj * nref] = tj;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < r * r; idx += kCT) {
+    const int i = idx % r, c = idx / r;
+    d.panel[i + (d.diag_col + c) * a] = i == c ? 1.0 : 0.0;
+  }
+  if (tid == 0) {
+    out_k[d.p] = k;
+    out_r[d.p] = r;
+    out_r2[d.p] = nref;
+    n_cur[d.p] = r;
+  }
+}
+
+__global__ void k_fill_int(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace
+
+int coop_max_blocks(size_t lds_bytes) {
+  int dev = 0, ncu = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_cpqr_coop),
+                                                   kCT, lds_bytes) != hipSuccess)
+    return 0;
+  return nb * ncu;
+}
+
+hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk2grp,
+                            int32_t nblocks, int32_t* counters, int32_t ncounters, int32_t* n_cur,
+                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
+                            double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3((ncounters + 255) / 256), dim3(256), 0, s, counters,
+                     (int64_t)ncounters);
+  void* args[] = {(void*)&d, (void*)&nb, (void*)&blk2grp, (void*)&n_cur, (void*)&out_r,
+                  (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cpqr_coop), dim3(nblocks),
+                                    dim3(kCT), args, lds_bytes, s);
+}
+
+}  // namespace spand

@@ -32,7 +32,8 @@ STATUS = {
 
 class Opts(C.Structure):
     _fields_ = [("depth", C.c_int32), ("skip", C.c_int32), ("eps", C.c_double),
-                ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32)]
+                ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32),
+                ("qr_group", C.c_int32), ("qr_list_cap", C.c_int32)]
 
 
 class FactorStats(C.Structure):
@@ -111,7 +112,8 @@ def _np(a, dtype):
     return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
 
 
-def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1) -> Opts:
+def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
+              qr_group=0, qr_list_cap=-1) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
     o.depth = int(depth)
@@ -120,6 +122,8 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = int(precision)
     o.debug_stop_step = int(debug_stop_step)
+    o.qr_group = int(qr_group)
+    o.qr_list_cap = int(qr_list_cap)
     return o
 
 

@@ -30,9 +30,10 @@ def ctx():
     return spand.Context(0)
 
 
-def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1):
+def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1, qr_group=0, qr_list_cap=-1):
     from paper_2007_00789_amd import spand
-    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop)
+    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop,
+                           qr_group=qr_group, qr_list_cap=qr_list_cap)
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
     vals = _dev(p.vals)
     fac = ctx.factor(plan, vals, opts)
@@ -211,3 +212,30 @@ def test_tiny_and_degenerate_problems(ctx):
         dx = torch.zeros_like(db)
         it, rr = ctx.pcg(fac, 1, db, dx, 1e-12, 50)
         assert rr[0] < 1e-11
+
+
+@gpu
+@pytest.mark.parametrize("qr_group,qr_list_cap", [(-1, -1), (1, -1), (3, -1), (5, 0), (8, 1)],
+                         ids=["single-wg", "coop-1", "coop-3", "coop-5-roundB", "coop-8-cap1"])
+@pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[4]],
+                         ids=[CASES[1][0], CASES[3][0], CASES[4][0]])
+def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group, qr_list_cap):
+    """Every QR path (single workgroup on a global workspace; cooperative groups
+    of several workgroups, with and without the overflow round) gives the
+    oracle's ranks and the same preconditioner."""
+    p = make()
+    print(f"qr paths {name} group={qr_group} cap={qr_list_cap}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, "SO")
+    _, fac = _gpu_factor(ctx, p, depth, skip, eps, "SO", qr_group=qr_group, qr_list_cap=qr_list_cap)
+    for l, recs in F.ranks.items():
+        got = fac.ranks(l, plan_o.steps[l].n_clusters)
+        for (p_, a, k, r, r2) in recs:
+            assert (got["k"][p_], got["r"][p_]) == (k, r), (l, p_)
+    x = rhs(p.n, 2, 13)
+    y_ref = ospand.apply(F, x)
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, 2, dx, dy)
+    y = dy.cpu().numpy().reshape(p.n, 2, order="F")
+    assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
