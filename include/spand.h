@@ -66,6 +66,8 @@ typedef struct {
   int32_t qr_group;     /* QR workgroups per interface: 0 auto, -1 single-workgroup kernel only,
                            g >= 1 force g (testing; capped by the coupling width and 32) */
   int32_t qr_list_cap;  /* tie candidates exchanged per workgroup: -1 default (32), 0..32 (testing) */
+  int32_t qr_xcd_local; /* cooperative QR groups synchronize inside one XCD's L2: 1 (default),
+                           0 device-wide exchanges only (testing) */
 } spand_opts;
 
 void spand_default_opts(spand_opts* opts);

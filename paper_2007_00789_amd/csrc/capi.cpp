@@ -49,7 +49,8 @@ void check_opts(const spand_opts* o) {
     throw Error(SPAND_E_INVALID, "unknown scheme");
   if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
   if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
-  if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32)
+  if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
+      o->qr_xcd_local > 1)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
 }
 
@@ -84,6 +85,7 @@ void spand_default_opts(spand_opts* o) {
   o->debug_stop_step = -1;
   o->qr_group = 0;
   o->qr_list_cap = -1;
+  o->qr_xcd_local = 1;
 }
 
 const char* spand_status_string(spand_status s) {

@@ -66,20 +66,37 @@ struct CpqrDesc {
   int32_t a, kmax, p, pad;
 };
 
-// One interface of a cooperative QR launch: G workgroups (blocks block0 ..
-// block0+G-1) share the columns of W, at most ncap each.
+// One interface of a cooperative QR launch: G workgroups share the columns of
+// W, at most ncap each.  The launcher places all G workgroups of a group on
+// one XCD (block index = xcd + 8 * slot) so that the group synchronizes through
+// that XCD's L2; the kernel verifies the placement and otherwise falls back to
+// device-coherent exchanges.
 struct CoopDesc {
   CpqrDesc d;
-  int32_t* counter;  // group barrier counter (zeroed by the launcher)
+  int32_t* sync;     // kCoopSyncInts ints, zeroed by the launcher: [0] placement
+                     // check counter, [kCoopFlag0 + g] barrier flag of member g
   double* xch;       // exchange buffer, coop_xch_doubles(G, a)
-  int32_t G, block0, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
+  int32_t G, xcd, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
 };
 constexpr int kCoopMaxGroup = 32;
+constexpr int kCoopXcds = 8;             // XCDs of an MI355X; block b runs on XCD b % 8
 constexpr size_t kCoopLdsBytes = 140 * 1024;
 inline int64_t coop_xch_doubles(int G, int a) {
   return 2 * (int64_t)G * (2 + 2 * 32) + (int64_t)(2 * G + 1) * (a + 1) + G;
 }
-constexpr int kCoopCounterStride = 32;   // one 128-byte line per group counter
+constexpr int kCoopSyncInts = 64;        // 256 bytes per group
+constexpr int kCoopFlag0 = 32;           // flags on their own 128-byte line
+
+// Triangular factor of the compact WY form of one interface's reflectors
+// (n = nref_of[p] reflectors, V a x n, T n x n, both column-major).
+struct WyDesc {
+  const double* V;
+  const double* tau;
+  double* T;
+  int32_t a, p;
+};
+constexpr int kWyThreads = 1024;
+constexpr int kWyLdsN = 143;   // 143^2 doubles fit in the 160 KiB of LDS
 
 // Dense block copy (merge of children's blocks into parent panels).
 struct CopyDesc {
@@ -99,10 +116,12 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
                  int32_t max_a, int32_t max_k, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
+void launch_wy_t(const WyDesc* d, int32_t count, const int32_t* nref_of, hipStream_t s);
 // maximum co-resident workgroups of the cooperative QR for a given LDS size
 int coop_max_blocks(size_t lds_bytes);
-hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk2grp,
-                            int32_t nblocks, int32_t* counters, int32_t ncounters, int32_t* n_cur,
+// blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block)
+hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
+                            int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
                             double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s);
 

@@ -512,48 +512,77 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r, d_r2,
                                               d_k, eps, eps_stop, ma, mk, s));
         }
-        // cooperative batches bounded by co-residency
-        size_t i0 = 0;
-        while (i0 < qd.size()) {
+        // cooperative groups, packed onto XCDs (all workgroups of a group on
+        // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
+        // groups per launch as can be co-resident
+        if (!qd.empty()) {
           size_t lds = 0;
-          int64_t blocks = 0, xdoubles = 0;
-          size_t i1 = i0;
-          for (; i1 < qd.size(); ++i1) {
-            const CoopDesc& q = qd[i1];
-            const size_t l = ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double);
-            const size_t lds2 = std::max(lds, l);
-            const int cap_blocks = coop_max_blocks(lds2);
-            if (cap_blocks <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
-            if (blocks + q.G > cap_blocks) break;
-            lds = lds2;
-            blocks += q.G;
-            xdoubles += coop_xch_doubles(q.G, q.d.a);
+          for (const CoopDesc& q : qd)
+            lds = std::max(lds, ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double));
+          const int cap_blocks = coop_max_blocks(lds);
+          const int slots = cap_blocks / kCoopXcds;
+          if (slots <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
+          std::vector<int> ord(qd.size());
+          for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+          std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return qd[x].G > qd[y].G; });
+          std::vector<char> done(qd.size(), 0);
+          size_t ndone = 0;
+          while (ndone < qd.size()) {
+            int fill[kCoopXcds] = {};
+            std::vector<int> members, at_xcd, at_slot;
+            for (int i : ord) {
+              if (done[i]) continue;
+              const int G = qd[i].G;
+              if (G > slots) throw Error(SPAND_E_LIMIT, "cooperative QR group larger than an XCD");
+              int best = -1;
+              for (int x = 0; x < kCoopXcds; ++x)
+                if (slots - fill[x] >= G && (best < 0 || fill[x] < fill[best])) best = x;
+              if (best < 0) continue;   // goes to the next launch
+              members.push_back(i);
+              at_xcd.push_back(best);
+              at_slot.push_back(fill[best]);
+              fill[best] += G;
+              done[i] = 1;
+              ++ndone;
+            }
+            const int maxfill = *std::max_element(fill, fill + kCoopXcds);
+            const int nblocks = maxfill * kCoopXcds;
+            std::vector<int32_t> blk_map((size_t)nblocks, -1);
+            int64_t xdoubles = 0;
+            for (int i : members) xdoubles += coop_xch_doubles(qd[i].G, qd[i].d.a);
+            const int nsync = (int)members.size() * kCoopSyncInts;
+            int32_t* sync = C.upload.alloc_n<int32_t>((size_t)nsync);
+            double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
+            std::vector<CoopDesc> batch;
+            int64_t xo = 0;
+            for (size_t bi = 0; bi < members.size(); ++bi) {
+              CoopDesc q = qd[members[bi]];
+              q.xcd = o.qr_xcd_local ? at_xcd[bi] : -1;
+              q.sync = sync + bi * kCoopSyncInts;
+              q.xch = xch + xo;
+              xo += coop_xch_doubles(q.G, q.d.a);
+              for (int g = 0; g < q.G; ++g)
+                blk_map[at_xcd[bi] + (size_t)kCoopXcds * (at_slot[bi] + g)] =
+                    (int32_t)(bi * kCoopMaxGroup + g);
+              batch.push_back(q);
+            }
+            const auto* d_qd = C.upload.upload(batch);
+            const auto* d_map = C.upload.upload(blk_map);
+            hipError_t he = hipSuccess;
+            SPAND_PROF(C, "k_cpqr_coop",
+                       he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur, d_r,
+                                             d_r2, d_k, eps, eps_stop, d_err, lds, s));
+            SPAND_HIP(he);
           }
-          if (i1 == i0) throw Error(SPAND_E_LIMIT, "cooperative QR group larger than the device");
-          int32_t* counters = C.upload.alloc_n<int32_t>((i1 - i0) * kCoopCounterStride);
-          double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
-          std::vector<int32_t> blk2grp;
-          int64_t xo = 0;
-          for (size_t i = i0; i < i1; ++i) {
-            CoopDesc& q = qd[i];
-            q.block0 = (int32_t)blk2grp.size();
-            q.counter = counters + (i - i0) * kCoopCounterStride;
-            q.xch = xch + xo;
-            xo += coop_xch_doubles(q.G, q.d.a);
-            for (int g = 0; g < q.G; ++g) blk2grp.push_back((int32_t)(i - i0));
-          }
-          std::vector<CoopDesc> batch(qd.begin() + i0, qd.begin() + i1);
-          const auto* d_qd = C.upload.upload(batch);
-          const auto* d_b2g = C.upload.upload(blk2grp);
-          hipError_t he = hipSuccess;
-          SPAND_PROF(C, "k_cpqr_coop",
-                     he = launch_cpqr_coop(d_qd, d_cn, d_b2g, (int32_t)blk2grp.size(), counters,
-                                           (int32_t)((i1 - i0) * kCoopCounterStride), d_ncur, d_r,
-                                           d_r2, d_k, eps,
-                                           eps_stop, d_err, lds, s));
-          SPAND_HIP(he);
-          i0 = i1;
         }
+      }
+      // triangular factors of the compact WY forms, all interfaces of the step
+      std::vector<WyDesc> wy;
+      for (int p = nI; p < nc; ++p)
+        if (R.V[p]) wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], sizes[p], p});
+      if (!wy.empty()) {
+        const auto* d_wy = C.upload.upload(wy);
+        SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), d_r2, s));
       }
     }
     // read back breakdown flags and ranks

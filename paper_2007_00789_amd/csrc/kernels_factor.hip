@@ -45,6 +45,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
 }
+// Sum over each group of 8 lanes, returned to all 8: two quad permutations and
+// a half-row mirror.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  return v;
+}
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
@@ -564,30 +572,6 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
   const int nref = j;
   if (r < 0) r = nref;
 
-  // triangular factor of the compact WY form Q = H_0 ... H_{nref-1} = I - V T V^T
-  // (forward accumulation): T_jj = tau_j, T_{0:j,j} = -tau_j T_{0:j,0:j} V_{:,0:j}^T v_j.
-  // nrm2 (no longer needed) holds V_{:,0:j}^T v_j.
-  for (int jj = 0; jj < nref; ++jj) {
-    const double* vj = d.V + (int64_t)jj * a;
-    for (int i = wid; i < jj; i += kQrWaves) {
-      const double* vi = d.V + (int64_t)i * a;
-      double acc = 0.0;
-      for (int q = jj + lane; q < a; q += kWave) acc = fma(vi[q], vj[q], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) nrm2[i] = acc;
-    }
-    __syncthreads();
-    const double tj = d.tau[jj];
-    for (int i = tid; i < jj; i += kQrThreads) {
-      double acc = 0.0;
-      for (int m = i; m < jj; ++m) acc = fma(d.T[i + (int64_t)m * nref], nrm2[m], acc);
-      d.T[i + (int64_t)jj * nref] = -tj * acc;
-    }
-    for (int i = jj + 1 + tid; i < nref; i += kQrThreads) d.T[i + (int64_t)jj * nref] = 0.0;
-    if (tid == 0) d.T[jj + (int64_t)jj * nref] = tj;
-    __syncthreads();
-  }
-
   // coarse rows back into p's panel and, transposed, into the neighbours' panels
   int kk = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) {
@@ -612,6 +596,63 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
   }
   __syncthreads();
   if (tid == 0) n_cur[d.p] = r;
+}
+
+// Triangular factor T of the compact WY form Q = H_0 H_1 ... H_{n-1} = I - V T V^T
+// of one interface's n reflectors.  T is upper triangular with
+// T^{-1} = diag(1/tau) + (strict upper part of V^T V), so column j follows from
+// the earlier ones: T_jj = tau_j, T_{0:j,j} = -tau_j T_{0:j,0:j} (V^T V)_{0:j,j}.
+// The work array A (n x n, column-major) holds T on and above the diagonal and
+// (V^T V)_{ij} at (j, i) below it; it lives in LDS when n <= kWyLdsN, else in
+// T itself.  All dot products and row sums use 8-lane groups.
+template <bool kInLds>
+__global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs, const int32_t* nref_of) {
+  extern __shared__ double lds[];
+  const WyDesc d = descs[blockIdx.x];
+  const int n = nref_of[d.p], a = d.a;
+  if (n <= 0 || (n <= kWyLdsN) != kInLds) return;
+  double* A = kInLds ? lds : d.T;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int grp = lane >> 3, r8 = lane & 7;
+  constexpr int kGroups = kWyThreads / 8;
+  // (V^T V)_{ij}, i < j: v_i and v_j are zero above their own row and v_j(j) = 1
+  const int64_t npairs = (int64_t)n * (n - 1) / 2;
+  for (int64_t base = (int64_t)wid * 8; base < npairs; base += kGroups) {
+    const int64_t pr = base + grp;
+    int i = 0, j = 1;
+    if (pr < npairs) {
+      j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5);
+      while ((int64_t)j * (j - 1) / 2 > pr) --j;
+      while ((int64_t)(j + 1) * j / 2 <= pr) ++j;
+      i = (int)(pr - (int64_t)j * (j - 1) / 2);
+    }
+    const double* vi = d.V + (int64_t)i * a;
+    const double* vj = d.V + (int64_t)j * a;
+    double acc = 0.0;
+    if (pr < npairs)
+      for (int q = j + r8; q < a; q += 8) acc = fma(vi[q], vj[q], acc);
+    acc = group8_sum(acc);
+    if (pr < npairs && r8 == 0) A[j + (int64_t)i * n] = acc;
+  }
+  for (int j = tid; j < n; j += kWyThreads) A[j + (int64_t)j * n] = d.tau[j];
+  __syncthreads();
+  for (int j = 1; j < n; ++j) {
+    const double tj = d.tau[j];
+    for (int ib = wid * 8; ib < j; ib += kGroups) {   // wave-uniform bound
+      const int i = ib + grp;
+      double acc = 0.0;
+      if (i < j)
+        for (int q = i + r8; q < j; q += 8)
+          acc = fma(A[i + (int64_t)q * n], A[j + (int64_t)q * n], acc);
+      acc = group8_sum(acc);
+      if (i < j && r8 == 0) A[i + (int64_t)j * n] = -tj * acc;
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < (int64_t)n * n; idx += kWyThreads) {
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    d.T[idx] = i <= c ? A[idx] : 0.0;
+  }
 }
 
 __global__ void k_fill(double* p, int64_t n, double v) {
@@ -675,6 +716,13 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
   size_t lds = ((size_t)max_k + max_a) * sizeof(double);
   hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kQrThreads), lds, s, d, nb, n_cur, out_r, out_r2,
                      out_k, eps, eps_stop, max_k);
+}
+
+void launch_wy_t(const WyDesc* d, int32_t count, const int32_t* nref_of, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_wy_t<true>, dim3(count), dim3(kWyThreads),
+                     (size_t)kWyLdsN * kWyLdsN * sizeof(double), s, d, nref_of);
+  hipLaunchKernelGGL(k_wy_t<false>, dim3(count), dim3(kWyThreads), 0, s, d, nref_of);
 }
 
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {

@@ -1,21 +1,29 @@
 // Cooperative early-stopping column-pivoted Householder QR (Alg. 1): the
 // coupling W (a x k) of one interface is split by columns over a group of G
 // workgroups, each holding its column slice in LDS for the whole
-// factorization, so every pivot step is on-chip work plus two group barriers:
+// factorization, so every pivot step is on-chip work plus one group barrier
+// (two on rare slow paths):
 //
-//  A. every workgroup publishes its largest trailing norm and the complete
-//     list of its columns within the tie band of that maximum; since the
-//     global band lies inside every local band, the union of the lists holds
-//     every global candidate and each workgroup picks the same pivot (lowest
-//     index among columns within the band of the global maximum).  If a list
-//     overflows, an extra round exchanges exact local candidates.
-//  C. the owner of the pivot column publishes it; every workgroup builds the
-//     Householder vector and updates its columns, recomputing their trailing
-//     norms exactly (the same fused pass as the single-workgroup kernel).
+//  A. every workgroup publishes its largest trailing norm, the complete list
+//     of its columns within the tie band of that maximum and the column of its
+//     first candidate; since the global band lies inside every local band, the
+//     union of the lists holds every global candidate and each workgroup picks
+//     the same pivot (lowest index among columns within the band of the global
+//     maximum).  If a list overflows, an extra round exchanges exact local
+//     candidates; if the pivot is not the owner's first candidate, the owner
+//     publishes it in an extra round.
+//  C. every workgroup builds the Householder vector and updates its columns,
+//     recomputing their trailing norms exactly.
 //
-// The launch is cooperative (all workgroups resident), group barriers are
-// agent-scope counters, and every spin is bounded: a timeout raises an error
-// flag and all workgroups leave, so a launch can never hang.
+// Synchronization.  The launcher puts all workgroups of a group on one XCD
+// (workgroup b of a launch runs on XCD b mod 8).  The group then exchanges
+// data through that XCD's L2: plain stores (the CU's L1 is write-through) and
+// agent-scope loads (which miss the L1), with barrier flags polled the same
+// way.  At entry every workgroup checks its XCD against the planned one with
+// one round of device-coherent atomics; a group that is not on one XCD uses
+// agent-scope stores, which reach the device coherence point, for everything.
+// The launch is cooperative (all workgroups resident) and every spin is
+// bounded: a timeout raises an error flag and all workgroups leave.
 #include <climits>
 
 #include "device.h"
@@ -92,47 +100,67 @@ __device__ __forceinline__ int wave_min_int(int v) {
   return v;
 }
 
-// exchange values go through agent-scope atomics (coherent across CUs/XCDs)
-__device__ __forceinline__ void xst(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+// XCD this wave runs on (hardware register XCC_ID, bits 3:0)
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
 }
+
+// exchange stores: into the XCD's L2 when the group is XCD-local, through to
+// the device coherence point otherwise
+__device__ __forceinline__ void xst(double* p, double v, bool local) {
+  auto* q = reinterpret_cast<unsigned long long*>(p);
+  const auto u = static_cast<unsigned long long>(__double_as_longlong(v));
+  if (local)
+    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// exchange loads bypass the CU's L1
 __device__ __forceinline__ double xld(double* p) {
   const unsigned long long u = __hip_atomic_load(reinterpret_cast<unsigned long long*>(p),
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return __longlong_as_double(static_cast<long long>(u));
 }
 
-// Group barrier on a monotone counter: returns false after a timeout.  All
-// exchanged data travels through agent-scope atomics, which are performed at
-// the coherence point; the workgroup-scope release below only waits until the
-// workgroup's own stores have completed before thread 0 bumps the counter, and
-// readers fetch the data with agent-scope atomic loads after the barrier.
-__device__ bool group_barrier(int32_t* counter, int target, int G, int32_t* err, int* sok) {
+// Group barrier on per-member flags holding the last phase each member
+// reached: the workgroup waits for its own exchange stores, member g raises
+// its flag to `phase`, and wave 0 polls the G flags (one load per lane) until
+// all have reached it.  Returns false after a timeout.
+__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, bool local, int32_t* err,
+                              int* sok) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
   __syncthreads();
   if (G == 1) return true;
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+      if (local)
+        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     long spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (true) {
+      const int f = lane < G
+                        ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : phase;
+      if (__all(f >= phase)) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         ok = 0;
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
-    *sok = ok;
+    if (lane == 0) *sok = ok;
   }
   __syncthreads();
   return *sok != 0;
 }
 
 __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const CpqrNbr* nbrs,
-                                                  const int32_t* blk2grp, int32_t* n_cur,
+                                                  const int32_t* blk_map, int32_t* n_cur,
                                                   int32_t* out_r, int32_t* out_r2, int32_t* out_k,
                                                   double eps, double eps_stop, int32_t* err) {
   extern __shared__ double sm[];
@@ -142,12 +170,43 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   __shared__ double sM;
   __shared__ int sC, sover, sfirst, shead;
   __shared__ int s_wcnt[kCW + 1];
-  const CoopDesc cd = descs[blk2grp[blockIdx.x]];
+  __shared__ int slocal;
+  const int code = blk_map[blockIdx.x];
+  if (code < 0) return;   // idle slot of the XCD packing
+  const CoopDesc cd = descs[code / kCoopMaxGroup];
   const CpqrDesc& d = cd.d;
-  const int G = cd.G, g = blockIdx.x - cd.block0;
+  const int G = cd.G, g = code % kCoopMaxGroup;
   const int a = d.a;
   const int64_t K = d.kmax;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  int32_t* flags = cd.sync + kCoopFlag0;
+
+  // placement check: one round of device-coherent atomics on sync[0] (low
+  // half counts arrivals, high half counts members off the planned XCD)
+  if (tid == 0) {
+    int ok = 1, loc = 0;
+    if (G > 1) {
+      const int mine = 1 + ((cd.xcd >= 0 && xcc_id() == cd.xcd) ? 0 : (1 << 16));
+      __hip_atomic_fetch_add(cd.sync, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      long spins = 0;
+      int cnt;
+      while (((cnt = __hip_atomic_load(cd.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+              0xffff) < G) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          ok = 0;
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      loc = ok && (cnt >> 16) == 0;
+    }
+    slocal = loc;
+    sok = ok;
+  }
+  __syncthreads();
+  if (!sok) return;
+  const bool local = slocal != 0;
 
   int k = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
@@ -221,24 +280,24 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         const int at = before + __popcll(mask & ((1ULL << lane) - 1ULL));
         if (at == 0) sfirst = c;
         if (at < cd.list_cap) {
-          xst(Xg + 2 + at, (double)(c0 + c));
-          xst(Xg + 2 + kList + at, nrm2[c]);
+          xst(Xg + 2 + at, (double)(c0 + c), local);
+          xst(Xg + 2 + kList + at, nrm2[c], local);
         }
       }
       for (int w = 0; w < kCW; ++w) total += s_wcnt[w];
       __syncthreads();
     }
     if (tid == 0) {
-      xst(Xg, Mg);
-      xst(Xg + 1, (double)total);
+      xst(Xg, Mg, local);
+      xst(Xg + 1, (double)total, local);
     }
     const int first = sfirst;  // local index of my first candidate, or -1
     if (first >= 0) {
       double* Pg = PVs + (int64_t)g * (a + 1);
-      if (tid == 0) xst(Pg, nrm2[first]);
-      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
+      if (tid == 0) xst(Pg, nrm2[first], local);
+      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a], local);
     }
-    if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+    if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
     // global maximum and pivot (every workgroup computes the same).  One
     // round of loads: thread (q, e) fetches group q's maximum, count and list
     // entry e; the decision is made with workgroup reductions.
@@ -282,9 +341,9 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
       if (tid == 0) {
         int mn = redi[0];
         for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
-        xst(XB + g, (double)mn);
+        xst(XB + g, (double)mn, local);
       }
-      if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
       for (int qq = tid; qq < G; qq += kCT) C = min(C, (int)xld(XB + qq));
     }
     C = wave_min_int(C);
@@ -309,10 +368,10 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     if (!spec) {
       PV = PVx;
       if (owner) {
-        if (tid == 0) xst(PV, nrm2[Cl]);
-        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
+        if (tid == 0) xst(PV, nrm2[Cl], local);
+        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a], local);
       }
-      if (!group_barrier(cd.counter, ++phase * G, G, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
     }
     // one round of loads: the pivot's norm, its first entry and the rest of it
     const double pn = xld(PV), alpha = xld(PV + 1);
@@ -419,30 +478,6 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     }
   }
   if (g != 0) return;
-  // triangular factor of the compact WY form (see k_cpqr); the dead slice
-  // (a * ncap >= nref doubles) holds V_{:,0:j}^T v_j
-  __syncthreads();
-  double* vtv = Ys;
-  for (int jj = 0; jj < nref; ++jj) {
-    const double* vj = d.V + (int64_t)jj * a;
-    for (int i = wid; i < jj; i += kCW) {
-      const double* vi = d.V + (int64_t)i * a;
-      double acc = 0.0;
-      for (int q = jj + lane; q < a; q += kWave) acc = fma(vi[q], vj[q], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) vtv[i] = acc;
-    }
-    __syncthreads();
-    const double tj = d.tau[jj];
-    for (int i = tid; i < jj; i += kCT) {
-      double acc = 0.0;
-      for (int q = i; q < jj; ++q) acc = fma(d.T[i + (int64_t)q * nref], vtv[q], acc);
-      d.T[i + (int64_t)jj * nref] = -tj * acc;
-    }
-    for (int i = jj + 1 + tid; i < nref; i += kCT) d.T[i + (int64_t)jj * nref] = 0.0;
-    if (tid == 0) d.T[jj + (int64_t)jj * nref] = tj;
-    __syncthreads();
-  }
   for (int idx = tid; idx < r * r; idx += kCT) {
     const int i = idx % r, c = idx / r;
     d.panel[i + (d.diag_col + c) * a] = i == c ? 1.0 : 0.0;
@@ -473,13 +508,12 @@ int coop_max_blocks(size_t lds_bytes) {
   return nb * ncu;
 }
 
-hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk2grp,
-                            int32_t nblocks, int32_t* counters, int32_t ncounters, int32_t* n_cur,
+hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
+                            int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
                             double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_int, dim3((ncounters + 255) / 256), dim3(256), 0, s, counters,
-                     (int64_t)ncounters);
-  void* args[] = {(void*)&d, (void*)&nb, (void*)&blk2grp, (void*)&n_cur, (void*)&out_r,
+  hipLaunchKernelGGL(k_fill_int, dim3((nsync + 255) / 256), dim3(256), 0, s, sync, (int64_t)nsync);
+  void* args[] = {(void*)&d, (void*)&nb, (void*)&blk_map, (void*)&n_cur, (void*)&out_r,
                   (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cpqr_coop), dim3(nblocks),
                                     dim3(kCT), args, lds_bytes, s);

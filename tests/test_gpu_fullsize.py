@@ -1,0 +1,83 @@
+"""Full-size parity on the benchmark workload (3D 7-point Laplacian 64^3,
+n = 262,144, depth 12, skip 4), in the launch configuration bench.py times.
+
+Expected values are the FP64 oracle's, stored in tests/golden/ by
+tests/golden/make_golden.py (which calls only oracle/).  Bars:
+* (a, k, r, r2) of every interface of every sparsified step: bit-exact;
+* nnz(L) exact, algorithmic flops to 1e-12;
+* PCG on the 4 seeded right-hand sides: iteration counts equal (+-1 allowed),
+  relative residual below the tolerance, and the solution at 64 seeded
+  indices within 1e-8 of the RMS entry of the oracle's solution.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synthetic import workload, rhs
+
+gpu = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CASES = ["lap3d_64_SO_1e-2", "lap3d_64_FO_1e-2", "lap3d_64_SO_1e-1"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_00789_amd import spand
+    return spand.Context(0)
+
+
+@pytest.fixture(scope="module")
+def problem():
+    return workload("lap3d_64")
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a).reshape(-1, order="F").copy()).to("cuda")
+
+
+@gpu
+@pytest.mark.parametrize("case", CASES)
+def test_full_size_against_stored_oracle(ctx, problem, case):
+    from paper_2007_00789_amd import spand
+    path = os.path.join(GOLDEN, case + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{case}: no stored oracle values")
+    with open(path) as f:
+        g = json.load(f)
+    p, w = problem
+    print(f"full size {case}", flush=True)
+    opts = spand.make_opts(depth=g["depth"], skip=g["skip"], eps=g["eps"], scheme=g["scheme"])
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    fac = ctx.factor(plan, _dev(p.vals), opts)
+    for l, st in g["steps"].items():
+        l = int(l)
+        got = fac.ranks(l, plan.step(l)["n_clusters"])
+        pp = np.asarray(st["p"], dtype=np.int64)
+        for key in ("a", "k", "r", "r2"):
+            exp = np.asarray(st[key], dtype=np.int64)
+            bad = np.nonzero(got[key][pp] != exp)[0]
+            assert bad.size == 0, (case, l, key, int(pp[bad[0]]), int(got[key][pp[bad[0]]]),
+                                   int(exp[bad[0]]))
+    info = fac.info()
+    assert info["nnz_L"] == g["nnz_L"]
+    assert info["flops"] == pytest.approx(g["flops"], rel=1e-12)
+
+    nrhs, tol = g["nrhs"], g["tol"]
+    b = rhs(p.n, nrhs, g["rhs_seed"])
+    db = _dev(b)
+    dx = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, nrhs, db, dx, tol, 1000)
+    x = dx.cpu().numpy().reshape(p.n, nrhs, order="F")
+    idx = np.asarray(g["sample_idx"])
+    xs = np.asarray(g["x_sample"])
+    for j in range(nrhs):
+        assert abs(int(it[j]) - g["n_cg"][j]) <= 1, (j, int(it[j]), g["n_cg"][j])
+        assert rr[j] < tol
+        rms = g["x_norm"][j] / np.sqrt(p.n)
+        assert np.abs(x[idx, j] - xs[j]).max() <= 1e-8 * rms, j
+    fac.close()
