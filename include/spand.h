@@ -68,6 +68,8 @@ typedef struct {
   int32_t qr_list_cap;  /* tie candidates exchanged per workgroup: -1 default (32), 0..32 (testing) */
   int32_t qr_xcd_local; /* cooperative QR groups synchronize inside one XCD's L2: 1 (default),
                            0 device-wide exchanges only (testing) */
+  int32_t qr_regs;      /* cooperative QR with W held in registers when a <= 288 and the
+                           coupling fits 32 x 64 columns: 1, or LDS-resident slices: 0 (default) */
 } spand_opts;
 
 void spand_default_opts(spand_opts* opts);

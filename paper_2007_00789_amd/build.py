@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libspand.so")
 ARCH = os.environ.get("SPAND_ARCH", "gfx950")
 
 SOURCES = ["analyze.cpp", "factor.cpp", "solve.cpp", "capi.cpp",
-           "kernels_factor.hip", "kernels_qr_coop.hip", "kernels_solve.hip"]
+           "kernels_factor.hip", "kernels_qr_coop.hip", "kernels_qr_reg.hip",
+           "kernels_solve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -120,6 +120,19 @@ void launch_wy_t(const WyDesc* d, int32_t count, const int32_t* nref_of, hipStre
 // maximum co-resident workgroups of the cooperative QR for a given LDS size
 int coop_max_blocks(size_t lds_bytes);
 // blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block)
+// register-resident cooperative QR (a <= kCpqrRegMaxA, at most kCpqrRegCols
+// columns per workgroup): rows per lane for a given a (0 if a is too large),
+// dynamic LDS bytes, co-resident workgroups, launch
+constexpr int kCpqrRegMaxA = 288;
+constexpr int kCpqrRegCols = 64;
+int cpqr_reg_rows(int a);
+size_t cpqr_reg_lds(int G, int a);
+int cpqr_reg_max_blocks(int rows, size_t lds_bytes);
+hipError_t launch_cpqr_reg(int rows, const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
+                           int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
+                           int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
+                           double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s);
+void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,

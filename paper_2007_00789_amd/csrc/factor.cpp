@@ -449,7 +449,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       coop_used.assign(nc, 0);
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrDesc> cd;
-        std::vector<CoopDesc> qd;
+        std::vector<CoopDesc> qd, qd_reg;
         std::vector<CpqrNbr> cn;
         int ma = 1, mk = 1;
         for (int p : st.order) {
@@ -487,7 +487,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           d.V = R.V[p];
           d.tau = R.tau[p];
           d.T = R.T[p];
-          const int64_t cap = a > 0 ? ((int64_t)(kCoopLdsBytes / 8) - a) / (a + 1) : 0;
+          // register-resident slices when they fit, else LDS-resident slices
+          bool reg = o.qr_regs && cpqr_reg_rows(a) > 0 &&
+                     (kmax + kCpqrRegCols - 1) / kCpqrRegCols <= kCoopMaxGroup;
+          const int64_t cap = !(a > 0) ? 0
+                              : reg    ? kCpqrRegCols
+                                       : ((int64_t)(kCoopLdsBytes / 8) - a) / (a + 1);
           int64_t G = cap > 0 ? (kmax + cap - 1) / cap : 0;
           if (o.qr_group > 0) G = std::max(G, std::min<int64_t>(o.qr_group, kmax));
           if (o.qr_group >= 0 && a > 0 && kmax > 0 && G >= 1 && G <= kCoopMaxGroup) {
@@ -496,8 +501,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             q.G = (int32_t)G;
             q.ncap = (int32_t)((kmax + G - 1) / G);
             q.list_cap = o.qr_list_cap < 0 ? 32 : o.qr_list_cap;
-            qd.push_back(q);
-            coop_used[p] = 1;
+            (reg ? qd_reg : qd).push_back(q);
+            coop_used[p] = reg ? 2 : 1;
             continue;
           }
           if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
@@ -515,24 +520,38 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         // cooperative groups, packed onto XCDs (all workgroups of a group on
         // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
         // groups per launch as can be co-resident
-        if (!qd.empty()) {
+        for (int kind = 0; kind < 2; ++kind) {
+          std::vector<CoopDesc>& list = kind == 0 ? qd_reg : qd;
+          if (list.empty()) continue;
           size_t lds = 0;
-          for (const CoopDesc& q : qd)
-            lds = std::max(lds, ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double));
-          const int cap_blocks = coop_max_blocks(lds);
+          int rows = 0, cap_blocks = 0;
+          if (kind == 0) {
+            int amax = 0;
+            for (const CoopDesc& q : list) {
+              amax = std::max(amax, q.d.a);
+              lds = std::max(lds, cpqr_reg_lds(q.G, q.d.a));
+            }
+            rows = cpqr_reg_rows(amax);
+            cap_blocks = cpqr_reg_max_blocks(rows, lds);
+          } else {
+            for (const CoopDesc& q : list)
+              lds = std::max(lds, ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double));
+            cap_blocks = coop_max_blocks(lds);
+          }
           const int slots = cap_blocks / kCoopXcds;
           if (slots <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
-          std::vector<int> ord(qd.size());
+          std::vector<int> ord(list.size());
           for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-          std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return qd[x].G > qd[y].G; });
-          std::vector<char> done(qd.size(), 0);
+          std::stable_sort(ord.begin(), ord.end(),
+                           [&](int x, int y) { return list[x].G > list[y].G; });
+          std::vector<char> done(list.size(), 0);
           size_t ndone = 0;
-          while (ndone < qd.size()) {
+          while (ndone < list.size()) {
             int fill[kCoopXcds] = {};
             std::vector<int> members, at_xcd, at_slot;
             for (int i : ord) {
               if (done[i]) continue;
-              const int G = qd[i].G;
+              const int G = list[i].G;
               if (G > slots) throw Error(SPAND_E_LIMIT, "cooperative QR group larger than an XCD");
               int best = -1;
               for (int x = 0; x < kCoopXcds; ++x)
@@ -549,14 +568,14 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             const int nblocks = maxfill * kCoopXcds;
             std::vector<int32_t> blk_map((size_t)nblocks, -1);
             int64_t xdoubles = 0;
-            for (int i : members) xdoubles += coop_xch_doubles(qd[i].G, qd[i].d.a);
+            for (int i : members) xdoubles += coop_xch_doubles(list[i].G, list[i].d.a);
             const int nsync = (int)members.size() * kCoopSyncInts;
             int32_t* sync = C.upload.alloc_n<int32_t>((size_t)nsync);
             double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
             std::vector<CoopDesc> batch;
             int64_t xo = 0;
             for (size_t bi = 0; bi < members.size(); ++bi) {
-              CoopDesc q = qd[members[bi]];
+              CoopDesc q = list[members[bi]];
               q.xcd = o.qr_xcd_local ? at_xcd[bi] : -1;
               q.sync = sync + bi * kCoopSyncInts;
               q.xch = xch + xo;
@@ -569,9 +588,15 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             const auto* d_qd = C.upload.upload(batch);
             const auto* d_map = C.upload.upload(blk_map);
             hipError_t he = hipSuccess;
-            SPAND_PROF(C, "k_cpqr_coop",
-                       he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur, d_r,
-                                             d_r2, d_k, eps, eps_stop, d_err, lds, s));
+            if (kind == 0) {
+              SPAND_PROF(C, "k_cpqr_reg",
+                         he = launch_cpqr_reg(rows, d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur,
+                                              d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
+            } else {
+              SPAND_PROF(C, "k_cpqr_coop",
+                         he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur,
+                                               d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
+            }
             SPAND_HIP(he);
           }
         }
@@ -630,7 +655,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         double qr = 0.0;
         for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
         flops += qr;
-        C.prof.add_work(coop_used[p] ? "k_cpqr_coop" : "k_cpqr", qr);
+        C.prof.add_work(coop_used[p] == 2 ? "k_cpqr_reg" : coop_used[p] ? "k_cpqr_coop" : "k_cpqr", qr);
         nnzL += (int64_t)a * r2 - (int64_t)r2 * (r2 - 1) / 2 + r2;
         if (so) nnzL += (int64_t)(a - r) * (k - r);
         if (sf) {

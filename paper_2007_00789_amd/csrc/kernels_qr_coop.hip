@@ -508,11 +508,15 @@ int coop_max_blocks(size_t lds_bytes) {
   return nb * ncu;
 }
 
+void launch_fill_int(int32_t* p, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
 hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
                             double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_int, dim3((nsync + 255) / 256), dim3(256), 0, s, sync, (int64_t)nsync);
+  launch_fill_int(sync, nsync, s);
   void* args[] = {(void*)&d, (void*)&nb, (void*)&blk_map, (void*)&n_cur, (void*)&out_r,
                   (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cpqr_coop), dim3(nblocks),
