@@ -66,8 +66,9 @@ typedef struct {
   int32_t qr_group;     /* QR workgroups per interface: 0 auto, -1 single-workgroup kernel only,
                            g >= 1 force g (testing; capped by the coupling width and 32) */
   int32_t qr_list_cap;  /* tie candidates exchanged per workgroup: -1 default (32), 0..32 (testing) */
-  int32_t qr_xcd_local; /* cooperative QR groups synchronize inside one XCD's L2: 1 (default),
-                           0 device-wide exchanges only (testing) */
+  int32_t qr_xcd_local; /* 1 (default); 0 treats every cooperative QR group as not placed on one
+                           XCD, which makes the factorization fall back to the single-workgroup
+                           QR (testing) */
   int32_t qr_regs;      /* cooperative QR with W held in registers when a <= 288 and the
                            coupling fits 32 x 64 columns: 1, or LDS-resident slices: 0 (default) */
 } spand_opts;

@@ -7,7 +7,7 @@
 //          t_s = G_s^T z_s written to a scratch buffer;
 //   ApGat  (one workgroup per interface): z_w -= sum_s t_s[w] (ascending s),
 //          then z_w <- Z_w^{-1} z_w on sparsified steps;
-//   per colour: ApSp  z_p <- Q_p^T z_p, t_p = E_p^T z_f (second order);
+//   per colour: ApSp  z_p <- Q_p^T z_p; ApEt tiles t_p = E_p^T z_f (second order);
 //               ApGat z_w -= sum_p t_p[w] (ascending p).
 // Backward (y <- L^{-T} y) runs the transposes in reverse.
 #pragma once
@@ -48,8 +48,24 @@ struct ApSp {
   const int32_t* nbr_pos;  // k
   int64_t toff;
   int64_t lde;
-  int32_t a, nref, f0, f1, k, pad;
+  int64_t part0;           // backward: first partial-sum slot of the E tiles (units of one rhs)
+  int32_t a, nref, f0, f1, k, ntiles;
 };
+
+// One tile of at most kEtTile columns of an interface's E (second order:
+// E = rows f0.. of Q^T W, stored transposed, element (c, i) = E[i, c] at
+// Et[c + i*lde]).  Forward: t[c0 + c] = sum_i E[i, c0 + c] z_f[i] for the
+// tile's columns, into the interface's scratch vector (offset off, length k).
+// Backward: part[i] = sum_c E[i, c0 + c] y_W[c0 + c] for every fine row i, into
+// the tile's partial-sum slot (offset off, length nf).
+struct ApEt {
+  const double* Et;
+  const int32_t* pos;      // forward: positions of the nf fine rows; backward: of the k columns
+  int64_t lde;
+  int64_t off;             // units of one right-hand side
+  int32_t nf, k, c0, cn;
+};
+constexpr int kEtTile = 256;
 
 struct ApScale {
   const double* Zinv;
@@ -61,10 +77,17 @@ void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, in
                        double* T, int32_t max_n, hipStream_t s);
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
                       int32_t nrhs, const double* T, int32_t max_n, hipStream_t s);
+// z_p <- Q_p^T z_p (one workgroup per interface)
 void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      double* T, int32_t max_a, hipStream_t s);
-void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       int32_t max_a, hipStream_t s);
+// E tiles, forward (t = E^T z_f) or backward (partial sums of E y_W)
+void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
+                      double* T, int32_t max_nf, hipStream_t s);
+void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
+                      double* P, hipStream_t s);
+// y_f -= sum of the interface's E-tile partial sums (fixed order); y_p <- Q_p y_p
+void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                      const double* P, int32_t max_a, hipStream_t s);
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s);
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,

@@ -259,7 +259,20 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
     SPAND_HIP(hipMalloc(&f->d_vals, std::max<int64_t>(nnz, 1) * sizeof(double)));
     SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
                              ctx->c.stream));
-    spand::run_factor(ctx->c, plan->p, f->d_vals, *opts, f->f);
+    try {
+      spand::run_factor(ctx->c, plan->p, f->d_vals, *opts, f->f);
+    } catch (const spand::CoopPlacement&) {
+      // a cooperative QR group was not on one XCD: redo with single-workgroup QRs
+      SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+      auto g = std::make_unique<spand_factor_s>();
+      g->device = f->device;
+      std::swap(g->d_vals, f->d_vals);
+      f = std::move(g);
+      spand_opts o2 = *opts;
+      o2.qr_group = -1;
+      spand::run_factor(ctx->c, plan->p, f->d_vals, o2, f->f);
+      f->f.opts = *opts;
+    }
     if (f->f.stopped_at < 0) spand::build_apply(ctx->c, f->f);
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();

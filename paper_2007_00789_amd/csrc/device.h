@@ -69,8 +69,8 @@ struct CpqrDesc {
 // One interface of a cooperative QR launch: G workgroups share the columns of
 // W, at most ncap each.  The launcher places all G workgroups of a group on
 // one XCD (block index = xcd + 8 * slot) so that the group synchronizes through
-// that XCD's L2; the kernel verifies the placement and otherwise falls back to
-// device-coherent exchanges.
+// that XCD's L2; the kernel verifies the placement (xcd < 0: treat as not
+// placed) and a misplaced group leaves with bit 2 of the error flag set.
 struct CoopDesc {
   CpqrDesc d;
   int32_t* sync;     // kCoopSyncInts ints, zeroed by the launcher: [0] placement

@@ -628,7 +628,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     SPAND_HIP(hipStreamSynchronize(s));
     check_info(info_i, pd_cluster, l, "interior block");
     check_info(info_f, zd_cluster, l, "interface block");
-    if (herr) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
+    if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
+    if (herr & 2) throw CoopPlacement();
 
     std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
     if (st.sparsified) {

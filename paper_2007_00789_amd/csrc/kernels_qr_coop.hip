@@ -20,10 +20,11 @@
 // data through that XCD's L2: plain stores (the CU's L1 is write-through) and
 // agent-scope loads (which miss the L1), with barrier flags polled the same
 // way.  At entry every workgroup checks its XCD against the planned one with
-// one round of device-coherent atomics; a group that is not on one XCD uses
-// agent-scope stores, which reach the device coherence point, for everything.
-// The launch is cooperative (all workgroups resident) and every spin is
-// bounded: a timeout raises an error flag and all workgroups leave.
+// one round of device-coherent atomics; a group that is not on one XCD leaves
+// before writing anything and raises bit 2 of the error flag, and the host
+// then redoes the factorization with the single-workgroup QR.  The launch is
+// cooperative (all workgroups resident) and every spin is bounded: a timeout
+// raises bit 1 of the error flag and all workgroups leave.
 #include <climits>
 
 #include "device.h"
@@ -105,15 +106,11 @@ __device__ __forceinline__ int xcc_id() {
   return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
 }
 
-// exchange stores: into the XCD's L2 when the group is XCD-local, through to
-// the device coherence point otherwise
-__device__ __forceinline__ void xst(double* p, double v, bool local) {
-  auto* q = reinterpret_cast<unsigned long long*>(p);
-  const auto u = static_cast<unsigned long long>(__double_as_longlong(v));
-  if (local)
-    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  else
-    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// exchange stores: plain stores, which land in the XCD's L2 (the L1 is write-through)
+__device__ __forceinline__ void xst(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 // exchange loads bypass the CU's L1
 __device__ __forceinline__ double xld(double* p) {
@@ -126,19 +123,13 @@ __device__ __forceinline__ double xld(double* p) {
 // reached: the workgroup waits for its own exchange stores, member g raises
 // its flag to `phase`, and wave 0 polls the G flags (one load per lane) until
 // all have reached it.  Returns false after a timeout.
-__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, bool local, int32_t* err,
-                              int* sok) {
+__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, int32_t* err, int* sok) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
   __syncthreads();
   if (G == 1) return true;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
-    if (lane == 0) {
-      if (local)
-        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      else
-        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane == 0) __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     long spins = 0;
     int ok = 1;
     while (true) {
@@ -149,7 +140,7 @@ __device__ bool group_barrier(int32_t* flags, int phase, int G, int g, bool loca
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         ok = 0;
-        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
@@ -170,7 +161,6 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   __shared__ double sM;
   __shared__ int sC, sover, sfirst, shead;
   __shared__ int s_wcnt[kCW + 1];
-  __shared__ int slocal;
   const int code = blk_map[blockIdx.x];
   if (code < 0) return;   // idle slot of the XCD packing
   const CoopDesc cd = descs[code / kCoopMaxGroup];
@@ -184,7 +174,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   // placement check: one round of device-coherent atomics on sync[0] (low
   // half counts arrivals, high half counts members off the planned XCD)
   if (tid == 0) {
-    int ok = 1, loc = 0;
+    int ok = 1, loc = 1;
     if (G > 1) {
       const int mine = 1 + ((cd.xcd >= 0 && xcc_id() == cd.xcd) ? 0 : (1 << 16));
       __hip_atomic_fetch_add(cd.sync, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -195,18 +185,17 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           ok = 0;
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
       }
       loc = ok && (cnt >> 16) == 0;
+      if (ok && !loc) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    slocal = loc;
-    sok = ok;
+    sok = ok && loc;
   }
   __syncthreads();
-  if (!sok) return;
-  const bool local = slocal != 0;
+  if (!sok) return;   // timed out, or not on one XCD: nothing has been written
 
   int k = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
@@ -280,24 +269,24 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         const int at = before + __popcll(mask & ((1ULL << lane) - 1ULL));
         if (at == 0) sfirst = c;
         if (at < cd.list_cap) {
-          xst(Xg + 2 + at, (double)(c0 + c), local);
-          xst(Xg + 2 + kList + at, nrm2[c], local);
+          xst(Xg + 2 + at, (double)(c0 + c));
+          xst(Xg + 2 + kList + at, nrm2[c]);
         }
       }
       for (int w = 0; w < kCW; ++w) total += s_wcnt[w];
       __syncthreads();
     }
     if (tid == 0) {
-      xst(Xg, Mg, local);
-      xst(Xg + 1, (double)total, local);
+      xst(Xg, Mg);
+      xst(Xg + 1, (double)total);
     }
     const int first = sfirst;  // local index of my first candidate, or -1
     if (first >= 0) {
       double* Pg = PVs + (int64_t)g * (a + 1);
-      if (tid == 0) xst(Pg, nrm2[first], local);
-      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a], local);
+      if (tid == 0) xst(Pg, nrm2[first]);
+      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
     }
-    if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+    if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
     // global maximum and pivot (every workgroup computes the same).  One
     // round of loads: thread (q, e) fetches group q's maximum, count and list
     // entry e; the decision is made with workgroup reductions.
@@ -341,9 +330,9 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
       if (tid == 0) {
         int mn = redi[0];
         for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
-        xst(XB + g, (double)mn, local);
+        xst(XB + g, (double)mn);
       }
-      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
       for (int qq = tid; qq < G; qq += kCT) C = min(C, (int)xld(XB + qq));
     }
     C = wave_min_int(C);
@@ -368,10 +357,10 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     if (!spec) {
       PV = PVx;
       if (owner) {
-        if (tid == 0) xst(PV, nrm2[Cl], local);
-        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a], local);
+        if (tid == 0) xst(PV, nrm2[Cl]);
+        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
       }
-      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
     }
     // one round of loads: the pivot's norm, its first entry and the rest of it
     const double pn = xld(PV), alpha = xld(PV + 1);

@@ -86,13 +86,10 @@ __device__ __forceinline__ double uni(double x) {
 __device__ __forceinline__ int xcc_id() {
   return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
 }
-__device__ __forceinline__ void xst(double* p, double v, bool local) {
-  auto* q = reinterpret_cast<unsigned long long*>(p);
-  const auto u = static_cast<unsigned long long>(__double_as_longlong(v));
-  if (local)
-    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  else
-    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void xst(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ double xld(const double* p) {
   const unsigned long long u = __hip_atomic_load(
@@ -101,19 +98,13 @@ __device__ __forceinline__ double xld(const double* p) {
   return __longlong_as_double(static_cast<long long>(u));
 }
 
-__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, bool local, int32_t* err,
-                              int* sok) {
+__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, int32_t* err, int* sok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (G == 1) return true;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
-    if (lane == 0) {
-      if (local)
-        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      else
-        __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane == 0) __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     long spins = 0;
     int ok = 1;
     while (true) {
@@ -124,7 +115,7 @@ __device__ bool group_barrier(int32_t* flags, int phase, int G, int g, bool loca
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) {
         ok = 0;
-        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
@@ -142,7 +133,7 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
   extern __shared__ double sm[];
   __shared__ double red_max[kRW], red_M[kRW];
   __shared__ int red_over[kRW], red_C[kRW], red_C2[kRW], s_wcnt[kRW];
-  __shared__ int sok, slocal, sC, sover;
+  __shared__ int sok, sC, sover;
   __shared__ double sM;
   const int code = blk_map[blockIdx.x];
   if (code < 0) return;   // idle slot of the XCD packing
@@ -155,8 +146,8 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
   const int grp = lane >> 3, r8 = lane & 7;
   int32_t* flags = cd.sync + kCoopFlag0;
 
-  if (tid == 0) {   // placement check (see k_cpqr_coop)
-    int ok = 1, loc = 0;
+  if (tid == 0) {
+    int ok = 1, loc = 1;
     if (G > 1) {
       const int mine = 1 + ((cd.xcd >= 0 && xcc_id() == cd.xcd) ? 0 : (1 << 16));
       __hip_atomic_fetch_add(cd.sync, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -167,18 +158,17 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
         __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           ok = 0;
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
       }
       loc = ok && (cnt >> 16) == 0;
+      if (ok && !loc) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    slocal = loc;
-    sok = ok;
+    sok = ok && loc;
   }
   __syncthreads();
-  if (!sok) return;
-  const bool local = slocal != 0;
+  if (!sok) return;   // timed out, or not on one XCD: nothing has been written
 
   int k = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
@@ -256,24 +246,24 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
     double* Xg = X + (int64_t)g * kXs;
     const int at = before + __popcll(mask & ((1ULL << (lane & ~7)) - 1ULL));
     if (f && r8 == 0 && at < cd.list_cap) {
-      xst(Xg + 2 + at, (double)gc, local);
-      xst(Xg + 2 + kList + at, nrm, local);
+      xst(Xg + 2 + at, (double)gc);
+      xst(Xg + 2 + kList + at, nrm);
     }
     if (f && at == 0) {   // first candidate: publish its column
       double* Pg = PVs + (int64_t)g * (a + 1);
-      if (r8 == 0) xst(Pg, nrm, local);
+      if (r8 == 0) xst(Pg, nrm);
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int i = r8 + 8 * t;
-        if (i >= j && i < a) xst(Pg + 1 + (i - j), y[t], local);
+        if (i >= j && i < a) xst(Pg + 1 + (i - j), y[t]);
       }
     }
     if (tid == 0) {
-      xst(Xg, Mg, local);
-      xst(Xg + 1, (double)total, local);
+      xst(Xg, Mg);
+      xst(Xg + 1, (double)total);
     }
     // ---- 2. group barrier ----
-    if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+    if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
     // ---- 3. one round of loads: all lists and all published columns ----
     constexpr int kSlots = (kCoopMaxGroup * kList + kRT - 1) / kRT;
     double nv[kSlots];
@@ -335,9 +325,9 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
       __syncthreads();
       if (wid == 0) {
         const int mn = wave_min_int(lane < kRW ? red_C[lane] : INT_MAX);
-        if (lane == 0) xst(XB + g, (double)mn, local);
+        if (lane == 0) xst(XB + g, (double)mn);
       }
-      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
       for (int qq = tid; qq < G; qq += kRT) C = min(C, (int)xld(XB + qq));
     }
     C = wave_min_int(C);
@@ -350,14 +340,14 @@ __global__ __launch_bounds__(kRT) void k_cpqr_reg(const CoopDesc* descs, const C
     if (!spec) {
       // the owner publishes the pivot column; everybody loads it into slot og
       if (mine && gc == C) {
-        if (r8 == 0) xst(PVx, nrm, local);
+        if (r8 == 0) xst(PVx, nrm);
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           const int i = r8 + 8 * t;
-          if (i >= j && i < a) xst(PVx + 1 + (i - j), y[t], local);
+          if (i >= j && i < a) xst(PVx + 1 + (i - j), y[t]);
         }
       }
-      if (!group_barrier(flags, ++phase, G, g, local, err, &sok)) return;
+      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
       for (int ii = tid; ii < len; ii += kRT) Pc[(int64_t)og * (a + 1) + ii] = xld(PVx + ii);
       __syncthreads();
     }

@@ -9,6 +9,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kT = 256;
+constexpr int kST = 512;   // threads of the sparsification apply kernels
 
 // DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
 template <int kCtrl>
@@ -134,37 +135,103 @@ __device__ void wg_rowsum_gather(const double* __restrict__ M, int64_t ld, int r
   __syncthreads();
 }
 
-// x <- Q^T x (trans = true) or Q x, Q = I - V T V^T with V (a x nref, ld a,
-// zero above the unit diagonal) and T (nref x nref upper triangular).
-// u, u2: LDS scratch of nref * nrhs.  x: LDS (a x nrhs).  Ends with a barrier.
-__device__ void wg_apply_wy(const double* __restrict__ V, const double* __restrict__ T, int a, int nref,
-                            double* __restrict__ x, int nrhs, double* __restrict__ u,
-                            double* __restrict__ u2, bool trans) {
-  if (nref == 0) return;
-  wg_coldots(V, a, a, nref, x, a, nrhs, u, nref);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nref * nrhs; idx += kT) {
-    const int j = idx % nref, r = idx / nref;
-    double acc = 0.0;
-    if (trans) {  // (T^T u)_j = sum_{i<=j} T_ij u_i
-#pragma unroll 8
-      for (int i = 0; i <= j; ++i) acc = fma(T[i + (int64_t)j * nref], u[i + r * nref], acc);
-    } else {      // (T u)_j = sum_{i>=j} T_ji u_i
-#pragma unroll 8
-      for (int i = j; i < nref; ++i) acc = fma(T[j + (int64_t)i * nref], u[i + r * nref], acc);
+// ---------------------------------------------------------------------------
+// Helpers for NT-thread workgroups (the sparsification apply uses 512).
+// ---------------------------------------------------------------------------
+// out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx]: one wave per kBatch
+// columns, lanes over rows (coalesced), one wave reduction per output.
+template <int NT>
+__device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, int cols,
+                            const double* __restrict__ x, int ldx, int nrhs, double* __restrict__ out,
+                            int64_t ldo) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int c0 = wid * kBatch; c0 < cols; c0 += NW * kBatch) {
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+      double acc[kBatch][4];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
+      for (int i = lane; i < rows; i += kWave) {
+        double m[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+          m[q] = c0 + q < cols ? M[i + (int64_t)(c0 + q) * ld] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double xv = x[i + (r0 + rr) * ldx];
+#pragma unroll
+          for (int q = 0; q < kBatch; ++q) acc[q][rr] = fma(m[q], xv, acc[q][rr]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double v = wave_sum(acc[q][rr]);
+          if (lane == 0 && c0 + q < cols) out[c0 + q + (int64_t)(r0 + rr) * ldo] = v;
+        }
     }
-    u2[idx] = acc;
   }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
-    const int i = idx % a, r = idx / a;
-    double acc = 0.0;
-    const int jm = min(i, nref - 1);
-#pragma unroll 8
-    for (int j = 0; j <= jm; ++j) acc = fma(V[i + (int64_t)j * a], u2[j + r * nref], acc);
-    x[idx] -= acc;
+}
+
+// y[i + r*ldy] += sign * sum_{c<cols} M[i + c*ld] w[c + r*ldw] for i < rows:
+// lanes over rows (coalesced), waves over columns, per-wave partial sums in
+// LDS (part: NW x rows x 2) added in wave order.  Ends with a barrier.
+template <int NT>
+__device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows, int cols,
+                             const double* __restrict__ w, int ldw, int nrhs, double sign,
+                             double* __restrict__ y, int ldy, double* __restrict__ part) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int r0 = 0; r0 < nrhs; r0 += 2) {
+    const bool two = r0 + 1 < nrhs;
+    for (int i = lane; i < rows; i += kWave) {
+      double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 4
+      for (int c = wid; c < cols; c += NW) {
+        const double m = M[i + (int64_t)c * ld];
+        acc0 = fma(m, w[c + r0 * ldw], acc0);
+        if (two) acc1 = fma(m, w[c + (r0 + 1) * ldw], acc1);
+      }
+      part[(wid * rows + i) * 2] = acc0;
+      part[(wid * rows + i) * 2 + 1] = acc1;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * 2; idx += NT) {
+      const int i = idx >> 1, rr = idx & 1;
+      if (r0 + rr >= nrhs) continue;
+      double sacc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) sacc += part[(q * rows + i) * 2 + rr];
+      y[i + (r0 + rr) * ldy] += sign * sacc;
+    }
+    __syncthreads();
   }
+}
+
+// x <- Q^T x (trans) or Q x with Q = I - V T V^T (V a x nref, ld a, zero above
+// its unit diagonal; T nref x nref upper triangular, zero below).  x, u, u2,
+// part in LDS (part: NW x max(a, nref) x 2).  Ends with a barrier.
+template <int NT>
+__device__ void wgt_apply_wy(const double* __restrict__ V, const double* __restrict__ T, int a,
+                             int nref, double* __restrict__ x, int nrhs, double* __restrict__ u,
+                             double* __restrict__ u2, double* __restrict__ part, bool trans) {
+  if (nref == 0) return;
+  wgt_coldots<NT>(V, a, a, nref, x, a, nrhs, u, nref);                 // u = V^T x
   __syncthreads();
+  if (trans) {
+    wgt_coldots<NT>(T, nref, nref, nref, u, nref, nrhs, u2, nref);     // u2 = T^T u
+    __syncthreads();
+  } else {
+    for (int idx = threadIdx.x; idx < nref * nrhs; idx += NT) u2[idx] = 0.0;
+    __syncthreads();
+    wgt_gemv_acc<NT>(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part);   // u2 = T u
+  }
+  wgt_gemv_acc<NT>(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part);   // x -= V u2
 }
 
 // ---------------------------------------------------------------------------
@@ -226,48 +293,121 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
 }
 
 // ---------------------------------------------------------------------------
-// forward sparsification: z_p <- Q^T z_p ; t = E^T z_f
+// forward sparsification: z_p <- Q^T z_p
 // LDS: xs (a x nrhs) | u, u2 (nref x nrhs each)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_ap_sp_fwd(const ApSp* descs, double* z, int64_t ldz,
-                                                  int nrhs, double* T) {
+__global__ __launch_bounds__(kST) void k_ap_sp_fwd(const ApSp* descs, double* z, int64_t ldz,
+                                                   int nrhs) {
   extern __shared__ double sm[];
   const ApSp d = descs[blockIdx.x];
   const int a = d.a;
+  if (d.nref == 0) return;
   double* xs = sm;
   double* u = sm + a * nrhs;
   double* u2 = u + d.nref * nrhs;
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
+  double* part = u2 + d.nref * nrhs;
+  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
     const int i = idx % a, r = idx / a;
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  wg_apply_wy(d.V, d.T, a, d.nref, xs, nrhs, u, u2, true);
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
+  wgt_apply_wy<kST>(d.V, d.T, a, d.nref, xs, nrhs, u, u2, part, true);
+  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
     const int i = idx % a, r = idx / a;
     z[d.pos[i] + r * ldz] = xs[idx];
   }
-  if (!d.Et || d.f1 <= d.f0 || d.k == 0) return;
-  // t_c = sum_i E[i, c] z_f[i]: one thread per column of E, rows of E^T are contiguous
-  const int nf = d.f1 - d.f0;
-  double* t = T + d.toff * nrhs;
-  for (int c = threadIdx.x; c < d.k; c += kT) {
-    for (int r = 0; r < nrhs; ++r) {
-      const double* xf = xs + d.f0 + r * a;
-      double acc = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// E tiles.  Forward: t[c] = sum_i E[i, c] z_f[i], one column per thread (rows
+// of E^T are contiguous, so a wave reads 64 consecutive entries per row).
+// LDS: z_f (nf x nrhs).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kT) void k_ap_et_fwd(const ApEt* descs, const double* z, int64_t ldz,
+                                                  int nrhs, double* T) {
+  extern __shared__ double sm[];
+  const ApEt d = descs[blockIdx.x];
+  const int nf = d.nf;
+  double* zf = sm;
+  for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) {
+    const int i = idx % nf, r = idx / nf;
+    zf[idx] = z[d.pos[i] + r * ldz];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c >= d.cn) return;
+  const double* e = d.Et + d.c0 + c;
+  double* t = T + d.off * nrhs + d.c0 + c;
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-      for (int i = 0; i < nf; ++i) acc = fma(d.Et[c + i * d.lde], xf[i], acc);
-      t[c + (int64_t)r * d.k] = acc;
+    for (int i = 0; i < nf; ++i) {
+      const double ev = e[(int64_t)i * d.lde];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if (r0 + rr < nrhs) acc[rr] = fma(ev, zf[i + (r0 + rr) * nf], acc[rr]);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+      if (r0 + rr < nrhs) t[(int64_t)(r0 + rr) * d.k] = acc[rr];
+  }
+}
+
+// Backward: part[i] = sum_{c in tile} E[i, c] y_W[c] for every fine row i.
+// The tile's neighbour values are staged in LDS (cn x nrhs); each wave takes
+// four rows of E at a time, lanes over the tile's columns.
+__global__ __launch_bounds__(kT) void k_ap_et_bwd(const ApEt* descs, const double* z, int64_t ldz,
+                                                  int nrhs, double* P) {
+  extern __shared__ double sm[];
+  const ApEt d = descs[blockIdx.x];
+  const int nf = d.nf, cn = d.cn;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  double* yw = sm;
+  for (int idx = threadIdx.x; idx < cn * nrhs; idx += kT) {
+    const int c = idx % cn, r = idx / cn;
+    yw[idx] = z[d.pos[d.c0 + c] + r * ldz];
+  }
+  __syncthreads();
+  double* out = P + d.off * nrhs;
+  for (int i0 = wid * 4; i0 < nf; i0 += kNW * 4) {
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+      double acc[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
+      for (int c = lane; c < cn; c += kWave) {
+        double ev[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          ev[q] = i0 + q < nf ? d.Et[d.c0 + c + (int64_t)(i0 + q) * d.lde] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double yv = yw[c + (r0 + rr) * cn];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q][rr] = fma(ev[q], yv, acc[q][rr]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (r0 + rr >= nrhs) break;
+          const double v = wave_sum(acc[q][rr]);
+          if (lane == 0 && i0 + q < nf) out[i0 + q + (int64_t)(r0 + rr) * nf] = v;
+        }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// backward sparsification: y_f -= E y_W ; y_p <- Q y_p
-// LDS: xs (a x nrhs) | u, u2 (nref x nrhs) | acc (nf x nrhs) | part (kChunk x nrhs)
+// backward sparsification: y_f -= E y_W (sum of the tiles' partial sums, in
+// tile order) ; y_p <- Q y_p
+// LDS: xs (a x nrhs) | u, u2 (nref x nrhs)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_ap_sp_bwd(const ApSp* descs, double* z, int64_t ldz,
-                                                  int nrhs) {
+__global__ __launch_bounds__(kST) void k_ap_sp_bwd(const ApSp* descs, double* z, int64_t ldz,
+                                                   int nrhs, const double* P) {
   extern __shared__ double sm[];
   const ApSp d = descs[blockIdx.x];
   const int a = d.a;
@@ -275,46 +415,18 @@ __global__ __launch_bounds__(kT) void k_ap_sp_bwd(const ApSp* descs, double* z, 
   double* xs = sm;
   double* u = sm + a * nrhs;
   double* u2 = u + d.nref * nrhs;
-  double* acc = u2 + d.nref * nrhs;
-  double* part = acc + nf * nrhs;
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
+  double* part = u2 + d.nref * nrhs;
+  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
     const int i = idx % a, r = idx / a;
-    xs[idx] = z[d.pos[i] + r * ldz];
+    double v = z[d.pos[i] + r * ldz];
+    if (i >= d.f0 && i < d.f1)
+      for (int t = 0; t < d.ntiles; ++t)
+        v -= P[(d.part0 + (int64_t)t * nf) * nrhs + (i - d.f0) + (int64_t)r * nf];
+    xs[idx] = v;
   }
   __syncthreads();
-  if (d.Et && nf > 0 && d.k > 0) {
-    // y_f[i] -= sum_c E[i, c] y_W[c]: the neighbours' values are staged in LDS
-    // (chunks of kChunk columns); one wave per row of E, lanes over columns.
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) acc[idx] = 0.0;
-    for (int c0 = 0; c0 < d.k; c0 += kChunk) {
-      const int cn = min(kChunk, d.k - c0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < cn * nrhs; idx += kT) {
-        const int c = idx % cn, r = idx / cn;
-        part[idx] = z[d.nbr_pos[c0 + c] + r * ldz];
-      }
-      __syncthreads();
-      for (int i = wid; i < nf; i += kNW) {
-        const double* er = d.Et + c0 + (int64_t)i * d.lde;
-        for (int r = 0; r < nrhs; ++r) {
-          double sacc = 0.0;
-#pragma unroll 8
-          for (int c = lane; c < cn; c += kWave) sacc = fma(er[c], part[c + r * cn], sacc);
-          sacc = wave_sum(sacc);
-          if (lane == 0) acc[i + r * nf] += sacc;
-        }
-      }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) {
-      const int i = idx % nf, r = idx / nf;
-      xs[d.f0 + i + r * a] -= acc[idx];
-    }
-    __syncthreads();
-  }
-  wg_apply_wy(d.V, d.T, a, d.nref, xs, nrhs, u, u2, false);
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kT) {
+  wgt_apply_wy<kST>(d.V, d.T, a, d.nref, xs, nrhs, u, u2, part, false);
+  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
     const int i = idx % a, r = idx / a;
     z[d.pos[i] + r * ldz] = xs[idx];
   }
@@ -464,18 +576,30 @@ void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z
                      d, src, z, ldz, nrhs, T);
 }
 size_t sp_lds(int32_t max_a, int32_t nrhs) {
-  // xs (a) + u, u2 (nref <= a) + acc (nf <= a) per rhs, + part (kChunk per rhs)
-  return ((size_t)max_a * nrhs * 4 + (size_t)kChunk * nrhs) * sizeof(double);
+  // xs (a) + u, u2 (nref <= a) per rhs, + part (kST/64 x a x 2)
+  return ((size_t)max_a * nrhs * 3 + (size_t)(kST / kWave) * max_a * 2) * sizeof(double);
 }
 void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      double* T, int32_t max_a, hipStream_t s) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_fwd, dim3(count), dim3(kT), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs, T);
-}
-void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       int32_t max_a, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kT), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs);
+  hipLaunchKernelGGL(k_ap_sp_fwd, dim3(count), dim3(kST), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs);
+}
+void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
+                      double* T, int32_t max_nf, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_et_fwd, dim3(count), dim3(kT), (size_t)max_nf * nrhs * sizeof(double), s,
+                     d, z, ldz, nrhs, T);
+}
+void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
+                      double* P, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kT), (size_t)kEtTile * nrhs * sizeof(double), s,
+                     d, z, ldz, nrhs, P);
+}
+void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
+                      const double* P, int32_t max_a, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kST), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs, P);
 }
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s) {

@@ -133,6 +133,11 @@ struct FactorObj {
   ~FactorObj();
 };
 
+// Thrown by run_factor when a cooperative QR group did not run on one XCD
+// (its workgroups left without writing); the factorization is then redone with
+// the single-workgroup QR.
+struct CoopPlacement {};
+
 void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F);
 
 }  // namespace spand

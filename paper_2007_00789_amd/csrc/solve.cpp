@@ -12,6 +12,9 @@ namespace spand {
 struct ApplyColour {
   ApSp* sp = nullptr;
   int32_t n_sp = 0, max_a = 0;
+  ApEt* etf = nullptr;   // E tiles, forward
+  ApEt* etb = nullptr;   // E tiles, backward
+  int32_t n_et = 0, max_nf = 0;
   ApGat* gat = nullptr;
   ApSrc* src = nullptr;
   int32_t n_gat = 0, max_n = 0;
@@ -32,7 +35,8 @@ struct ApplyStep {
 struct ApplyProg {
   std::vector<ApplyStep> steps;  // in forward order (depth ... 0)
   int64_t scratch = 0;           // doubles per right-hand side
-  DevBuf T;
+  int64_t pscratch = 0;          // partial sums of the backward E tiles, per right-hand side
+  DevBuf T, P;
 };
 
 FactorObj::~FactorObj() { delete prog; }
@@ -138,7 +142,8 @@ void build_apply(Ctx& C, FactorObj& F) {
       for (int colour = 0; colour < st.ncolours; ++colour) {
         ApplyColour& ac = as.colours[colour];
         std::vector<ApSp> sps;
-        int64_t csz = 0;
+        std::vector<ApEt> etf, etb;
+        int64_t csz = 0, psz = 0;
         std::vector<int64_t> ptoff(nc, -1);
         for (int p : st.order) {
           if (st.colour[p] != colour || R.n0[p] == 0) continue;
@@ -158,12 +163,39 @@ void build_apply(Ctx& C, FactorObj& F) {
           d.toff = csz;
           ptoff[p] = csz;
           csz += d.k;
+          const int nf = d.f1 - d.f0;
+          d.part0 = psz;
+          d.ntiles = 0;
+          if (d.Et && nf > 0 && d.k > 0) {
+            for (int c0 = 0; c0 < d.k; c0 += kEtTile) {
+              ApEt t{};
+              t.Et = d.Et;
+              t.lde = d.lde;
+              t.nf = nf;
+              t.k = d.k;
+              t.c0 = c0;
+              t.cn = std::min(kEtTile, d.k - c0);
+              t.pos = d.pos + d.f0;
+              t.off = d.toff;
+              etf.push_back(t);
+              t.pos = d.nbr_pos;
+              t.off = psz;
+              etb.push_back(t);
+              psz += nf;
+              ++d.ntiles;
+            }
+            ac.max_nf = std::max(ac.max_nf, nf);
+          }
           sps.push_back(d);
           ac.max_a = std::max(ac.max_a, d.a);
         }
         prog->scratch = std::max(prog->scratch, csz);
+        prog->pscratch = std::max(prog->pscratch, psz);
         ac.sp = F.meta.upload(sps);
         ac.n_sp = (int32_t)sps.size();
+        ac.etf = F.meta.upload(etf);
+        ac.etb = F.meta.upload(etb);
+        ac.n_et = (int32_t)etf.size();
         if (!(so || sf)) continue;
         // targets: interfaces adjacent to an interface of this colour
         std::vector<ApGat> eg;
@@ -213,14 +245,17 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   const int64_t n = F.plan->n;
   ApplyProg& pg = *F.prog;
   double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
+  double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
   // every apply kernel stages its cluster's slice of the vectors in LDS
   constexpr int64_t kLds = 160 * 1024;
   for (const ApplyStep& as : pg.steps) {
     int64_t need = std::max<int64_t>((int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
                                       (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
     for (const ApplyColour& ac : as.colours)
-      need = std::max<int64_t>(need, std::max<int64_t>((int64_t)ac.max_a * 4 * nrhs + 1024 * nrhs,
-                                                       (int64_t)ac.max_n * nrhs));
+      need = std::max<int64_t>(need, std::max<int64_t>({(int64_t)ac.max_a * (3 * nrhs + 16),
+                                                        (int64_t)ac.max_n * nrhs,
+                                                        (int64_t)ac.max_nf * nrhs,
+                                                        (int64_t)kEtTile * nrhs}));
     if (need * (int64_t)sizeof(double) > kLds)
       throw Error(SPAND_E_LIMIT, "cluster too large for the apply with nrhs = " + std::to_string(nrhs));
   }
@@ -229,14 +264,17 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
     SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
     SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
     for (const ApplyColour& ac : as.colours) {
-      SPAND_PROF(C, "k_ap_sp_fwd", launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, T, ac.max_a, s));
+      SPAND_PROF(C, "k_ap_sp_fwd", launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, ac.max_a, s));
+      SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_et, y, n, nrhs, T, ac.max_nf, s));
       SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s));
     }
   }
   for (auto it = pg.steps.rbegin(); it != pg.steps.rend(); ++it) {
     const ApplyStep& as = *it;
-    for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c)
-      SPAND_PROF(C, "k_ap_sp_bwd", launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, c->max_a, s));
+    for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c) {
+      SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_et, y, n, nrhs, Pp, s));
+      SPAND_PROF(C, "k_ap_sp_bwd", launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, Pp, c->max_a, s));
+    }
     SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
     SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
   }

@@ -220,17 +220,18 @@ def test_tiny_and_degenerate_problems(ctx):
 @pytest.mark.parametrize("qr_group,qr_list_cap,xcd_local,regs", [
     (-1, -1, 1, 1), (1, -1, 1, 1), (3, -1, 1, 1), (5, 0, 1, 1), (8, 1, 1, 1), (3, -1, 0, 1),
     (8, 1, 0, 1), (32, -1, 1, 1), (1, -1, 1, 0), (3, -1, 1, 0), (5, 0, 1, 0), (8, 1, 0, 0)],
-    ids=["single-wg", "reg-1", "reg-3", "reg-5-roundB", "reg-8-cap1", "reg-3-devicewide",
-         "reg-8-cap1-devicewide", "reg-32", "lds-1", "lds-3", "lds-5-roundB",
-         "lds-8-cap1-devicewide"])
+    ids=["single-wg", "reg-1", "reg-3", "reg-5-roundB", "reg-8-cap1", "reg-3-misplaced",
+         "reg-8-cap1-misplaced", "reg-32", "lds-1", "lds-3", "lds-5-roundB",
+         "lds-8-cap1-misplaced"])
 @pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[4]],
                          ids=[CASES[1][0], CASES[3][0], CASES[4][0]])
 def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group, qr_list_cap,
                                     xcd_local, regs):
     """Every QR path (single workgroup on a global workspace; cooperative groups
-    of several workgroups, with and without the overflow round, synchronizing
-    inside one XCD or device-wide) gives the oracle's ranks and the same
-    preconditioner."""
+    of several workgroups with W in LDS or in registers, with and without the
+    overflow round; groups reported as not placed on one XCD, which makes the
+    factorization fall back to single-workgroup QRs) gives the oracle's ranks
+    and the same preconditioner."""
     p = make()
     print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local} regs={regs}",
           flush=True)
