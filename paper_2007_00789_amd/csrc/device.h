@@ -87,13 +87,14 @@ inline int64_t coop_xch_doubles(int G, int a) {
 constexpr int kCoopSyncInts = 64;        // 256 bytes per group
 constexpr int kCoopFlag0 = 32;           // flags on their own 128-byte line
 
-// Triangular factor of the compact WY form of one interface's reflectors
-// (n = nref_of[p] reflectors, V a x n, T n x n, both column-major).
+// Triangular factor of the compact WY form of one interface's n reflectors
+// (V a x n, T n x n, both column-major); T holds V^T V in its lower triangle
+// on entry.
 struct WyDesc {
   const double* V;
   const double* tau;
   double* T;
-  int32_t a, p;
+  int32_t a, n;
 };
 constexpr int kWyThreads = 1024;
 constexpr int kWyLdsN = 143;   // 143^2 doubles fit in the 160 KiB of LDS
@@ -116,7 +117,7 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
                  int32_t max_a, int32_t max_k, hipStream_t s);
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
-void launch_wy_t(const WyDesc* d, int32_t count, const int32_t* nref_of, hipStream_t s);
+void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s);
 // maximum co-resident workgroups of the cooperative QR for a given LDS size
 int coop_max_blocks(size_t lds_bytes);
 // blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block)

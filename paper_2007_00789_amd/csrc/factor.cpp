@@ -601,14 +601,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           }
         }
       }
-      // triangular factors of the compact WY forms, all interfaces of the step
-      std::vector<WyDesc> wy;
-      for (int p = nI; p < nc; ++p)
-        if (R.V[p]) wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], sizes[p], p});
-      if (!wy.empty()) {
-        const auto* d_wy = C.upload.upload(wy);
-        SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), d_r2, s));
-      }
     }
     // read back breakdown flags and ranks
     std::vector<int32_t> info_i(pd.size()), info_f(zd.size()), hr(nc), hr2(nc), hk(nc);
@@ -723,6 +715,45 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     lay = std::move(nlay);
     sizes = std::move(nsz);
     pos = std::move(npos);
+  }
+  if (F.stopped_at < 0) {
+    // triangular factors of the compact WY forms of every sparsified interface:
+    // S = V^T V (lower triangle) by one batched GEMM, then the column recurrence
+    C.upload.reset();
+    std::vector<GemmDesc> gd;
+    std::vector<GemmTerm> gt;
+    std::vector<TileRef> tiles;
+    std::vector<WyDesc> wy;
+    for (const StepRec& R : F.steps) {
+      for (size_t p = 0; p < R.V.size(); ++p) {
+        if (!R.V[p] || R.r2[p] <= 0) continue;
+        const int nref = R.r2[p], a = R.n0[p];
+        GemmDesc g{};
+        g.C = R.T[p];
+        g.ldc = nref;
+        g.m = nref;
+        g.n = nref;
+        g.transA = 1;
+        g.transB = 0;
+        g.lower_only = 1;
+        g.alpha = 1.0;
+        g.beta = 0.0;
+        g.term0 = (int64_t)gt.size();
+        gt.push_back(GemmTerm{R.V[p], R.V[p], a, a, a, 0});
+        g.term1 = (int64_t)gt.size();
+        add_gemm_tiles(tiles, (int32_t)gd.size(), nref, nref, true);
+        gd.push_back(g);
+        wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], a, nref});
+      }
+    }
+    if (!wy.empty()) {
+      const auto* d_gd = C.upload.upload(gd);
+      const auto* d_gt = C.upload.upload(gt);
+      const auto* d_tl = C.upload.upload(tiles);
+      const auto* d_wy = C.upload.upload(wy);
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), s));
+      SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), s));
+    }
   }
   SPAND_HIP(hipStreamSynchronize(s));
   F.stats.flops = flops;

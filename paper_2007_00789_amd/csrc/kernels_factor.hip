@@ -602,38 +602,24 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
 // of one interface's n reflectors.  T is upper triangular with
 // T^{-1} = diag(1/tau) + (strict upper part of V^T V), so column j follows from
 // the earlier ones: T_jj = tau_j, T_{0:j,j} = -tau_j T_{0:j,0:j} (V^T V)_{0:j,j}.
-// The work array A (n x n, column-major) holds T on and above the diagonal and
-// (V^T V)_{ij} at (j, i) below it; it lives in LDS when n <= kWyLdsN, else in
-// T itself.  All dot products and row sums use 8-lane groups.
+// On entry T holds V^T V in its lower triangle.  The work array A (n x n,
+// column-major) holds T on and above the diagonal and V^T V below it; it lives
+// in LDS when n <= kWyLdsN, else in T itself.  Row sums use 8-lane groups.
 template <bool kInLds>
-__global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs, const int32_t* nref_of) {
+__global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
   extern __shared__ double lds[];
   const WyDesc d = descs[blockIdx.x];
-  const int n = nref_of[d.p], a = d.a;
+  const int n = d.n;
   if (n <= 0 || (n <= kWyLdsN) != kInLds) return;
   double* A = kInLds ? lds : d.T;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int grp = lane >> 3, r8 = lane & 7;
   constexpr int kGroups = kWyThreads / 8;
-  // (V^T V)_{ij}, i < j: v_i and v_j are zero above their own row and v_j(j) = 1
-  const int64_t npairs = (int64_t)n * (n - 1) / 2;
-  for (int64_t base = (int64_t)wid * 8; base < npairs; base += kGroups) {
-    const int64_t pr = base + grp;
-    int i = 0, j = 1;
-    if (pr < npairs) {
-      j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5);
-      while ((int64_t)j * (j - 1) / 2 > pr) --j;
-      while ((int64_t)(j + 1) * j / 2 <= pr) ++j;
-      i = (int)(pr - (int64_t)j * (j - 1) / 2);
+  if (kInLds)
+    for (int64_t idx = tid; idx < (int64_t)n * n; idx += kWyThreads) {
+      const int i = (int)(idx % n), c = (int)(idx / n);
+      if (i > c) A[idx] = d.T[idx];
     }
-    const double* vi = d.V + (int64_t)i * a;
-    const double* vj = d.V + (int64_t)j * a;
-    double acc = 0.0;
-    if (pr < npairs)
-      for (int q = j + r8; q < a; q += 8) acc = fma(vi[q], vj[q], acc);
-    acc = group8_sum(acc);
-    if (pr < npairs && r8 == 0) A[j + (int64_t)i * n] = acc;
-  }
   for (int j = tid; j < n; j += kWyThreads) A[j + (int64_t)j * n] = d.tau[j];
   __syncthreads();
   for (int j = 1; j < n; ++j) {
@@ -718,11 +704,11 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
                      out_k, eps, eps_stop, max_k);
 }
 
-void launch_wy_t(const WyDesc* d, int32_t count, const int32_t* nref_of, hipStream_t s) {
+void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_wy_t<true>, dim3(count), dim3(kWyThreads),
-                     (size_t)kWyLdsN * kWyLdsN * sizeof(double), s, d, nref_of);
-  hipLaunchKernelGGL(k_wy_t<false>, dim3(count), dim3(kWyThreads), 0, s, d, nref_of);
+                     (size_t)kWyLdsN * kWyLdsN * sizeof(double), s, d);
+  hipLaunchKernelGGL(k_wy_t<false>, dim3(count), dim3(kWyThreads), 0, s, d);
 }
 
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {

@@ -10,6 +10,8 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kT = 256;
 constexpr int kST = 512;   // threads of the sparsification apply kernels
+// right-hand sides per pass of the WY products (bounds their LDS partial sums)
+__host__ __device__ constexpr int sp_rb(int nrhs) { return nrhs > 4 ? 2 : 4; }
 
 // DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
 template <int kCtrl>
@@ -179,34 +181,36 @@ __device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, 
 }
 
 // y[i + r*ldy] += sign * sum_{c<cols} M[i + c*ld] w[c + r*ldw] for i < rows:
-// lanes over rows (coalesced), waves over columns, per-wave partial sums in
-// LDS (part: NW x rows x 2) added in wave order.  Ends with a barrier.
+// lanes over rows (coalesced), waves over columns, rb right-hand sides per
+// pass; per-wave partial sums in LDS (part: NW x rows x rb) added in wave
+// order.  Ends with a barrier.
 template <int NT>
 __device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows, int cols,
                              const double* __restrict__ w, int ldw, int nrhs, double sign,
-                             double* __restrict__ y, int ldy, double* __restrict__ part) {
+                             double* __restrict__ y, int ldy, double* __restrict__ part, int rb) {
   constexpr int NW = NT / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int r0 = 0; r0 < nrhs; r0 += 2) {
-    const bool two = r0 + 1 < nrhs;
+  for (int r0 = 0; r0 < nrhs; r0 += rb) {
+    const int nr = min(rb, nrhs - r0);
     for (int i = lane; i < rows; i += kWave) {
-      double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll 4
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
       for (int c = wid; c < cols; c += NW) {
         const double m = M[i + (int64_t)c * ld];
-        acc0 = fma(m, w[c + r0 * ldw], acc0);
-        if (two) acc1 = fma(m, w[c + (r0 + 1) * ldw], acc1);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          if (rr < nr) acc[rr] = fma(m, w[c + (r0 + rr) * ldw], acc[rr]);
       }
-      part[(wid * rows + i) * 2] = acc0;
-      part[(wid * rows + i) * 2 + 1] = acc1;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        if (rr < nr) part[(wid * rows + i) * rb + rr] = acc[rr];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < rows * 2; idx += NT) {
-      const int i = idx >> 1, rr = idx & 1;
-      if (r0 + rr >= nrhs) continue;
+    for (int idx = threadIdx.x; idx < rows * nr; idx += NT) {
+      const int i = idx / nr, rr = idx - i * nr;
       double sacc = 0.0;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) sacc += part[(q * rows + i) * 2 + rr];
+      for (int q = 0; q < NW; ++q) sacc += part[(q * rows + i) * rb + rr];
       y[i + (r0 + rr) * ldy] += sign * sacc;
     }
     __syncthreads();
@@ -215,7 +219,7 @@ __device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows,
 
 // x <- Q^T x (trans) or Q x with Q = I - V T V^T (V a x nref, ld a, zero above
 // its unit diagonal; T nref x nref upper triangular, zero below).  x, u, u2,
-// part in LDS (part: NW x max(a, nref) x 2).  Ends with a barrier.
+// part in LDS (part: NW x a x sp_rb(nrhs)).  Ends with a barrier.
 template <int NT>
 __device__ void wgt_apply_wy(const double* __restrict__ V, const double* __restrict__ T, int a,
                              int nref, double* __restrict__ x, int nrhs, double* __restrict__ u,
@@ -229,9 +233,9 @@ __device__ void wgt_apply_wy(const double* __restrict__ V, const double* __restr
   } else {
     for (int idx = threadIdx.x; idx < nref * nrhs; idx += NT) u2[idx] = 0.0;
     __syncthreads();
-    wgt_gemv_acc<NT>(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part);   // u2 = T u
+    wgt_gemv_acc<NT>(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part, sp_rb(nrhs));   // u2 = T u
   }
-  wgt_gemv_acc<NT>(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part);   // x -= V u2
+  wgt_gemv_acc<NT>(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part, sp_rb(nrhs));   // x -= V u2
 }
 
 // ---------------------------------------------------------------------------
@@ -576,8 +580,8 @@ void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z
                      d, src, z, ldz, nrhs, T);
 }
 size_t sp_lds(int32_t max_a, int32_t nrhs) {
-  // xs (a) + u, u2 (nref <= a) per rhs, + part (kST/64 x a x 2)
-  return ((size_t)max_a * nrhs * 3 + (size_t)(kST / kWave) * max_a * 2) * sizeof(double);
+  // xs (a) + u, u2 (nref <= a) per rhs, + part (kST/64 x a x sp_rb)
+  return ((size_t)max_a * nrhs * 3 + (size_t)(kST / kWave) * max_a * sp_rb(nrhs)) * sizeof(double);
 }
 void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       int32_t max_a, hipStream_t s) {

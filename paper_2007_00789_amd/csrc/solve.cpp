@@ -252,7 +252,7 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
     int64_t need = std::max<int64_t>((int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
                                       (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
     for (const ApplyColour& ac : as.colours)
-      need = std::max<int64_t>(need, std::max<int64_t>({(int64_t)ac.max_a * (3 * nrhs + 16),
+      need = std::max<int64_t>(need, std::max<int64_t>({(int64_t)ac.max_a * (3 * nrhs + 8 * (nrhs > 4 ? 2 : 4)),
                                                         (int64_t)ac.max_n * nrhs,
                                                         (int64_t)ac.max_nf * nrhs,
                                                         (int64_t)kEtTile * nrhs}));
