@@ -108,65 +108,92 @@ __device__ int block_min_int(int v, int* red) {
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + inverse of the lower factor.  Column-oriented right-looking
-// factorization; the inverse is formed in place column by column from the
-// right (X_jj = 1/L_jj, X_{j+1:,j} = -X_jj X_{j+1:,j+1:} L_{j+1:,j}).
-// S: n x n column-major (LDS or global), tmp: n doubles of LDS.
-// Returns 0 or the 1-based column of the first non-positive pivot.
+// Cholesky of an n x n SPD block (n <= 64, column-major in LDS, lower triangle
+// read).  Right-looking with one barrier per column: every thread reads the
+// pivot v, updates its share of the trailing lower triangle with the unscaled
+// column (S_ic -= S_ij S_cj / v), and scales the previous column, which is no
+// longer read.  Returns 0 or the 1-based column of the first non-positive pivot.
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ int chol_inplace(double* S, int n, int ld, int* flag) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *flag = 0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double v = S[j + (int64_t)j * ld];
-      if (!(v > 0.0)) *flag = j + 1;
-      else S[j + (int64_t)j * ld] = sqrt(v);
+__device__ int chol_inplace(double* S, int n, int ld) {
+  constexpr int TX = 16, TY = NT / TX;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  double vprev = 0.0;
+  for (int j = 0; j <= n; ++j) {
+    if (j > 0) {   // finish column j-1
+      const double d = sqrt(vprev), rd = 1.0 / d;
+      const int jp = j - 1;
+      for (int i = j + threadIdx.x; i < n; i += NT) S[i + (int64_t)jp * ld] *= rd;
+      if (threadIdx.x == 0) S[jp + (int64_t)jp * ld] = d;
+    }
+    if (j == n) break;
+    const double v = S[j + (int64_t)j * ld];
+    if (!(v > 0.0)) return j + 1;   // every thread reads the same value
+    const double rv = 1.0 / v;
+    for (int c = j + 1 + ty; c < n; c += TY) {
+      const double scj = S[c + (int64_t)j * ld] * rv;
+      for (int i = c + tx; i < n; i += TX)
+        S[i + (int64_t)c * ld] = fma(-S[i + (int64_t)j * ld], scj, S[i + (int64_t)c * ld]);
     }
     __syncthreads();
-    if (*flag) return *flag;
-    const double djj = S[j + (int64_t)j * ld];
-    for (int i = j + 1 + tid; i < n; i += NT) S[i + (int64_t)j * ld] /= djj;
+    vprev = v;
+  }
+  __syncthreads();
+  return 0;
+}
+
+// X = L^{-1} for a lower triangular n x n L (n <= 64, in LDS, X not aliasing
+// L; X is zeroed above the diagonal).  16 x 16 blocks: wave I inverts diagonal
+// block I by forward substitution (lane c builds column c), then the blocks
+// below the diagonal follow one block diagonal at a time,
+// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  tmp: 768 doubles of LDS.
+template <int NT>
+__device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, double* tmp) {
+  static_assert(NT >= 256, "one wave per 16-row diagonal block");
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int nbk = (n + 15) / 16;
+  for (int c = wid; c < n; c += NT / kWave)
+    for (int i = lane; i < n; i += kWave) X[i + (int64_t)c * ldx] = 0.0;
+  __syncthreads();
+  if (wid < nbk && lane < 16) {
+    const int b0 = wid * 16, bw = min(16, n - b0), c = lane;
+    if (c < bw) {
+      const int gc = b0 + c;
+      X[gc + (int64_t)gc * ldx] = 1.0 / L[gc + (int64_t)gc * ldl];
+      for (int i = c + 1; i < bw; ++i) {
+        const int gi = b0 + i;
+        double acc = 0.0;
+        for (int k = c; k < i; ++k)
+          acc = fma(L[gi + (int64_t)(b0 + k) * ldl], X[b0 + k + (int64_t)gc * ldx], acc);
+        X[gi + (int64_t)gc * ldx] = -acc / L[gi + (int64_t)gi * ldl];
+      }
+    }
+  }
+  __syncthreads();
+  for (int dd = 1; dd < nbk; ++dd) {
+    const int nblk = nbk - dd;
+    for (int idx = tid; idx < nblk * 256; idx += NT) {   // S_IJ = sum_K L_IK X_KJ
+      const int q = idx >> 8, e = idx & 255, ii = e & 15, jj = e >> 4;
+      const int I = q + dd, i = I * 16 + ii, j = q * 16 + jj;
+      double acc = 0.0;
+      if (i < n && j < n)
+        for (int k = q * 16; k < I * 16; ++k)
+          acc = fma(L[i + (int64_t)k * ldl], X[k + (int64_t)j * ldx], acc);
+      tmp[idx] = acc;
+    }
     __syncthreads();
-    const int m = n - j - 1;
-    for (int idx = tid; idx < m * m; idx += NT) {
-      const int ii = idx % m, cc = idx / m;
-      if (ii >= cc) {
-        const int i = j + 1 + ii, c = j + 1 + cc;
-        S[i + (int64_t)c * ld] -= S[i + (int64_t)j * ld] * S[c + (int64_t)j * ld];
+    for (int idx = tid; idx < nblk * 256; idx += NT) {   // X_IJ = -X_II S_IJ
+      const int q = idx >> 8, e = idx & 255, ii = e & 15, jj = e >> 4;
+      const int I = q + dd, i = I * 16 + ii, j = q * 16 + jj;
+      if (i < n && j < n) {
+        double acc = 0.0;
+        for (int k = I * 16; k <= i; ++k)
+          acc = fma(X[i + (int64_t)k * ldx], tmp[(q << 8) + (k - I * 16) + jj * 16], acc);
+        X[i + (int64_t)j * ldx] = -acc;
       }
     }
     __syncthreads();
   }
-  return 0;
-}
-
-template <int NT>
-__device__ void trinv_inplace(double* S, int n, int ld, double* tmp) {
-  const int tid = threadIdx.x;
-  for (int j = n - 1; j >= 0; --j) {
-    for (int i = j + 1 + tid; i < n; i += NT) tmp[i] = S[i + (int64_t)j * ld];
-    __syncthreads();
-    const double inv = 1.0 / S[j + (int64_t)j * ld];
-    for (int i = j + 1 + tid; i < n; i += NT) {
-      double acc = 0.0;
-      for (int m2 = j + 1; m2 <= i; ++m2) acc = fma(S[i + (int64_t)m2 * ld], tmp[m2], acc);
-      S[i + (int64_t)j * ld] = -inv * acc;
-    }
-    __syncthreads();
-    if (tid == 0) S[j + (int64_t)j * ld] = inv;
-    __syncthreads();
-  }
-}
-
-template <int NT>
-__device__ int chol_inv_inplace(double* S, int n, int ld, double* tmp, int* flag) {
-  const int f = chol_inplace<NT>(S, n, ld, flag);
-  if (f) return f;
-  trinv_inplace<NT>(S, n, ld, tmp);
-  return 0;
 }
 
 constexpr int kPotrfThreads = 256;
@@ -212,7 +239,7 @@ __device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
 // inverses of the diagonal tiles into X's diagonal tiles, then the off-diagonal
 // tiles of X = L^{-1} by block forward substitution
 // X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  LDS: four 64x65 tiles.
-__device__ int chol_inv_blocked(double* A, double* X, int n, double* lds, int* flag) {
+__device__ int chol_inv_blocked(double* A, double* X, int n, double* lds) {
   double* T0 = lds;
   double* T1 = lds + kNb * kTl;
   double* T2 = lds + 2 * kNb * kTl;
@@ -224,15 +251,11 @@ __device__ int chol_inv_blocked(double* A, double* X, int n, double* lds, int* f
     const int k0 = kb * kNb, kw = min(kNb, n - k0);
     // diagonal tile: factor (T1 = L_kk), invert a copy (T0 = L_kk^{-1})
     tile_load(T1, A + k0 + (int64_t)k0 * n, n, kw, kw);
+    for (int idx = threadIdx.x; idx < kNb * kTl; idx += kPotrfThreads) T0[idx] = 0.0;
     __syncthreads();
-    const int f = chol_inplace<kPotrfThreads>(T1, kw, kTl, flag);
+    const int f = chol_inplace<kPotrfThreads>(T1, kw, kTl);
     if (f) return k0 + f;
-    for (int idx = threadIdx.x; idx < kNb * kNb; idx += kPotrfThreads) {
-      const int i = idx % kNb, j = idx / kNb;
-      T0[i + j * kTl] = (i >= j && i < kw) ? T1[i + j * kTl] : 0.0;
-    }
-    __syncthreads();
-    trinv_inplace<kPotrfThreads>(T0, kw, kTl, tmp);
+    trinv<kPotrfThreads>(T1, kTl, T0, kTl, kw, tmp);
     for (int idx = threadIdx.x; idx < kw * kw; idx += kPotrfThreads) {
       const int i = idx % kw, j = idx / kw;
       A[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T1[i + j * kTl] : 0.0;
@@ -318,28 +341,29 @@ __device__ int chol_inv_blocked(double* A, double* X, int n, double* lds, int* f
 
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* descs, int32_t* info) {
   extern __shared__ double sm[];
-  __shared__ int flag;
   const PotrfDesc d = descs[blockIdx.x];
   const int n = d.n;
   if (n == 0) return;
   const int tid = threadIdx.x;
   if (n <= kNb) {
     double* S = sm;
-    double* tmp = sm + n * n;
+    double* X = sm + n * n;
+    double* tmp = X + n * n;
     for (int idx = tid; idx < n * n; idx += kPotrfThreads) {
       const int i = idx % n, j = idx / n;
       S[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : 0.0;
     }
     __syncthreads();
-    const int f = chol_inv_inplace<kPotrfThreads>(S, n, n, tmp, &flag);
+    const int f = chol_inplace<kPotrfThreads>(S, n, n);
     if (f) {
       if (tid == 0) info[blockIdx.x] = f;
       return;
     }
-    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = S[idx];
+    trinv<kPotrfThreads>(S, n, X, n, n, tmp);
+    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = X[idx];
   } else {
     // the panel's diagonal block (ld n) is dead after this call: factor in place
-    const int f = chol_inv_blocked(const_cast<double*>(d.A), d.X, n, sm, &flag);
+    const int f = chol_inv_blocked(const_cast<double*>(d.A), d.X, n, sm);
     if (f && tid == 0) info[blockIdx.x] = f;
   }
 }
@@ -683,8 +707,9 @@ void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double
 void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s) {
   if (count <= 0) return;
-  // n <= 64: the whole block and a column in LDS; larger: four 64x65 tiles
-  size_t lds = max_n <= kNb ? ((size_t)max_n * max_n + max_n) * sizeof(double)
+  // n <= 64: the block, its inverse and the inverse's products in LDS; larger:
+  // four 64x65 tiles
+  size_t lds = max_n <= kNb ? ((size_t)2 * max_n * max_n + 768) * sizeof(double)
                             : (size_t)4 * kNb * kTl * sizeof(double);
   hipLaunchKernelGGL(k_potrf_inv, dim3(count), dim3(kPotrfThreads), lds, s, d, info);
 }
