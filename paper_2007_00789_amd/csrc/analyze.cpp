@@ -128,6 +128,66 @@ inline void sort_unique(std::vector<int64_t>& v) {
   v.erase(std::unique(v.begin(), v.end()), v.end());
 }
 
+// position of `target` in c's sorted adjacency list, or -1
+int64_t adj_pos(const StepPlan& st, int c, int target) {
+  const int32_t* b = st.adj.data() + st.adj_ptr[c];
+  const int32_t* e = st.adj.data() + st.adj_ptr[c + 1];
+  const int32_t* it = std::lower_bound(b, e, target);
+  if (it == e || *it != target) return -1;
+  return st.adj_ptr[c] + (it - b);
+}
+
+// reverse adjacency positions, Schur targets and merge copies of step l
+void build_numeric_lists(Plan& P, int l) {
+  StepPlan& st = P.steps[l];
+  const int nI = st.nI, nc = st.nc;
+  st.adj_rev.assign(st.adj.size(), -1);
+  for (int c = 0; c < nc; ++c)
+    for (int64_t e = st.adj_ptr[c]; e < st.adj_ptr[c + 1]; ++e)
+      st.adj_rev[e] = adj_pos(st, st.adj[e], c);
+  st.schur.clear();
+  st.schur_terms.clear();
+  for (int w1 = nI; w1 < nc; ++w1) {
+    const int64_t b1 = st.adj_ptr[w1], e1 = st.adj_ptr[w1 + 1];
+    int64_t i1end = b1;
+    while (i1end < e1 && st.adj[i1end] < nI) ++i1end;
+    if (i1end == b1) continue;  // no interior neighbour
+    for (int64_t e = i1end; e < e1; ++e) {
+      const int w2 = st.adj[e];
+      if (w2 < w1) continue;
+      const int64_t b2 = st.adj_ptr[w2], e2 = st.adj_ptr[w2 + 1];
+      const int64_t t0 = (int64_t)st.schur_terms.size();
+      int64_t x = b1, y = b2;
+      while (x < i1end && y < e2 && st.adj[y] < nI) {
+        if (st.adj[x] < st.adj[y]) ++x;
+        else if (st.adj[y] < st.adj[x]) ++y;
+        else {
+          st.schur_terms.push_back({st.adj[x], 0, st.adj_rev[x], st.adj_rev[y]});
+          ++x;
+          ++y;
+        }
+      }
+      if ((int64_t)st.schur_terms.size() > t0)
+        st.schur.push_back({w1, w2, e, t0, (int64_t)st.schur_terms.size()});
+    }
+  }
+  st.merge.clear();
+  if (l == 0) return;
+  const StepPlan& nx = P.steps[l - 1];
+  for (int Pc = 0; Pc < nx.nc; ++Pc)
+    for (int64_t e = nx.adj_ptr[Pc]; e < nx.adj_ptr[Pc + 1]; ++e) {
+      const int Q = nx.adj[e];
+      for (int64_t a = nx.child_ptr[Pc]; a < nx.child_ptr[Pc + 1]; ++a) {
+        const int ci = nx.child[a];
+        for (int64_t b = nx.child_ptr[Q]; b < nx.child_ptr[Q + 1]; ++b) {
+          const int cj = nx.child[b];
+          const int64_t ee = adj_pos(st, ci, cj);
+          if (ee >= 0) st.merge.push_back({Pc, ci, cj, 0, e, ee});
+        }
+      }
+    }
+}
+
 }  // namespace
 
 void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const double* coords,
@@ -317,6 +377,7 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
   P.steps[0].parent.assign(P.steps[0].nc, -1);
   for (int l = 0; l <= D; ++l)
     if (P.steps[l].parent.empty()) P.steps[l].parent.assign(P.steps[l].nc, -1);
+  for (int l = 0; l <= D; ++l) build_numeric_lists(P, l);
 }
 
 PanelLayout make_layout(const StepPlan& st, const std::vector<int32_t>& sizes) {

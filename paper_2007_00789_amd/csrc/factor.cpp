@@ -214,7 +214,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.l = l;
     R.sparsified = st.sparsified;
     R.n0 = sizes;
-    R.pos = pos;
+    R.pos = std::move(pos);   // `pos` is refilled with step l-1's lists at the merge
+    const std::vector<std::vector<int32_t>>& cpos = R.pos;
     const int nI = st.nI, nc = st.nc;
     R.r.assign(nc, -1);
     R.r2.assign(nc, -1);
@@ -296,55 +297,42 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         const auto* d_tiles = C.upload.upload(tiles);
         SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
       }
-      // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2}
+      // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
+      // from the plan: targets and their interiors in ascending order)
       gd.clear();
       gt.clear();
       tiles.clear();
-      for (int w1 = nI; w1 < nc; ++w1) {
-        if (sizes[w1] == 0) continue;
-        const int64_t b1 = st.adj_ptr[w1], e1 = st.adj_ptr[w1 + 1];
-        int64_t i1end = b1;
-        while (i1end < e1 && st.adj[i1end] < nI) ++i1end;
-        if (i1end == b1) continue;  // no interior neighbour
-        for (int64_t e = i1end; e < e1; ++e) {
-          const int w2 = st.adj[e];
-          if (w2 < w1 || sizes[w2] == 0) continue;
-          const int64_t b2 = st.adj_ptr[w2];
-          const int64_t t0 = (int64_t)gt.size();
-          int64_t x = b1, y = b2;
-          while (x < i1end && y < st.adj_ptr[w2 + 1] && st.adj[y] < nI) {
-            if (st.adj[x] < st.adj[y]) ++x;
-            else if (st.adj[y] < st.adj[x]) ++y;
-            else {
-              const int sI = st.adj[x];
-              const int ns = sizes[sI];
-              if (ns > 0) {
-                const int64_t c1 = lay.coff[find_adj(st, sI, w1)] - ns;
-                const int64_t c2 = lay.coff[find_adj(st, sI, w2)] - ns;
-                gt.push_back({R.G[sI] + c1 * ns, R.G[sI] + c2 * ns, ns, ns, ns, 0});
-              }
-              ++x;
-              ++y;
-            }
-          }
-          if ((int64_t)gt.size() == t0) continue;
-          GemmDesc g{};
-          g.C = blk(w1, e);
-          g.C2 = w1 == w2 ? nullptr : blk(w2, find_adj(st, w2, w1));
-          g.term0 = t0;
-          g.term1 = (int64_t)gt.size();
-          g.ldc = sizes[w1];
-          g.ldc2 = sizes[w2];
-          g.m = sizes[w1];
-          g.n = sizes[w2];
-          g.transA = 1;
-          g.transB = 0;
-          g.lower_only = w1 == w2;
-          g.alpha = -1.0;
-          g.beta = 1.0;
-          gd.push_back(g);
-          add_gemm_tiles(tiles, (int32_t)gd.size() - 1, g.m, g.n, w1 == w2);
+      gd.reserve(st.schur.size());
+      gt.reserve(st.schur_terms.size());
+      for (const StepPlan::SchurTarget& tg : st.schur) {
+        const int w1 = tg.w1, w2 = tg.w2;
+        if (sizes[w1] == 0 || sizes[w2] == 0) continue;
+        const int64_t t0 = (int64_t)gt.size();
+        for (int64_t q = tg.t0; q < tg.t1; ++q) {
+          const StepPlan::SchurTerm& tm = st.schur_terms[q];
+          const int ns = sizes[tm.s];
+          if (ns == 0) continue;
+          const int64_t c1 = lay.coff[tm.e1] - ns;
+          const int64_t c2 = lay.coff[tm.e2] - ns;
+          gt.push_back({R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0});
         }
+        if ((int64_t)gt.size() == t0) continue;
+        GemmDesc g{};
+        g.C = blk(w1, tg.e);
+        g.C2 = w1 == w2 ? nullptr : blk(w2, st.adj_rev[tg.e]);
+        g.term0 = t0;
+        g.term1 = (int64_t)gt.size();
+        g.ldc = sizes[w1];
+        g.ldc2 = sizes[w2];
+        g.m = sizes[w1];
+        g.n = sizes[w2];
+        g.transA = 1;
+        g.transB = 0;
+        g.lower_only = w1 == w2;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        gd.push_back(g);
+        add_gemm_tiles(tiles, (int32_t)gd.size() - 1, g.m, g.n, w1 == w2);
       }
       if (!tiles.empty()) {
         const auto* d_gd = C.upload.upload(gd);
@@ -419,7 +407,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           t2.push_back({Tpq, R.Zinv[q], ap, aq, aq, 0});
           GemmDesc b{};
           b.C = blk(p, e);
-          b.C2 = blk(q, find_adj(st, q, p));
+          b.C2 = blk(q, st.adj_rev[e]);
           b.term0 = (int64_t)t2.size() - 1;
           b.term1 = (int64_t)t2.size();
           b.ldc = ap;
@@ -466,7 +454,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             if (w == p) { d.diag_col = lay.coff[e]; continue; }
             if (w < nI) continue;
             CpqrNbr nb{};
-            nb.blk_wp = blk(w, find_adj(st, w, p));
+            nb.blk_wp = blk(w, st.adj_rev[e]);
             nb.col = lay.coff[e];
             nb.w = w;
             nb.ldw = sizes[w];
@@ -638,7 +626,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           const int w = st.adj[e];
           if (w == p || w < nI) continue;
           const int wc = st.colour[w] < st.colour[p] ? R.r[w] : sizes[w];
-          np.insert(np.end(), pos[w].begin(), pos[w].begin() + wc);
+          np.insert(np.end(), cpos[w].begin(), cpos[w].begin() + wc);
         }
         if ((int)np.size() != R.k[p])
           throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " +
@@ -678,35 +666,26 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         const int ch = nx.child[e];
         choff[ch] = nsz[c];
         nsz[c] += cur_sizes[ch];
-        npos[c].insert(npos[c].end(), pos[ch].begin(), pos[ch].begin() + cur_sizes[ch]);
+        npos[c].insert(npos[c].end(), cpos[ch].begin(), cpos[ch].begin() + cur_sizes[ch]);
       }
     PanelLayout nlay = make_layout(nx, nsz);
     double* npanel =
         static_cast<double*>(C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
     SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
     std::vector<CopyDesc> cp;
-    for (int P_ = 0; P_ < nx.nc; ++P_)
-      for (int64_t e = nx.adj_ptr[P_]; e < nx.adj_ptr[P_ + 1]; ++e) {
-        const int Q = nx.adj[e];
-        for (int64_t a = nx.child_ptr[P_]; a < nx.child_ptr[P_ + 1]; ++a) {
-          const int ci = nx.child[a];
-          if (cur_sizes[ci] == 0) continue;
-          for (int64_t b = nx.child_ptr[Q]; b < nx.child_ptr[Q + 1]; ++b) {
-            const int cj = nx.child[b];
-            if (cur_sizes[cj] == 0) continue;
-            const int64_t ee = find_adj(st, ci, cj);
-            if (ee < 0) continue;
-            CopyDesc d{};
-            d.src = blk(ci, ee);
-            d.lds = sizes[ci];
-            d.dst = npanel + nlay.off[P_] + (nlay.coff[e] + choff[cj]) * nsz[P_] + choff[ci];
-            d.ldd = nsz[P_];
-            d.m = cur_sizes[ci];
-            d.n = cur_sizes[cj];
-            cp.push_back(d);
-          }
-        }
-      }
+    cp.reserve(st.merge.size());
+    for (const StepPlan::MergeCopy& mc : st.merge) {
+      const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
+      if (cur_sizes[ci] == 0 || cur_sizes[cj] == 0) continue;
+      CopyDesc d{};
+      d.src = blk(ci, mc.ee);
+      d.lds = sizes[ci];
+      d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
+      d.ldd = nsz[P_];
+      d.m = cur_sizes[ci];
+      d.n = cur_sizes[cj];
+      cp.push_back(d);
+    }
     const auto* d_cp = C.upload.upload(cp);
     SPAND_PROF(C, "k_copy", launch_copy(d_cp, (int64_t)cp.size(), s));
     SPAND_HIP(hipStreamSynchronize(s));

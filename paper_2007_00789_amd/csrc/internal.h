@@ -45,6 +45,29 @@ struct StepPlan {
   std::vector<int32_t> parent;         // index in step l-1 (-1 for interiors / l == 0)
   std::vector<int64_t> vert_ptr;       // l == depth: vertices of each cluster, ascending
   std::vector<int32_t> verts;
+  // Structural lists for the numeric factorization (they depend on the
+  // pattern only; sizes and addresses are filled in per factorization).
+  std::vector<int64_t> adj_rev;        // entry e = (c, w): position of c in w's list
+  // Schur update of one block B_{w1 w2} (w1 <= w2 interfaces sharing an
+  // interior): e = position of w2 in w1's list; its terms [t0, t1) in
+  // ascending interior order give s and the positions of w1 and w2 in s's list
+  struct SchurTarget {
+    int32_t w1, w2;
+    int64_t e, t0, t1;
+  };
+  struct SchurTerm {
+    int32_t s, pad;
+    int64_t e1, e2;
+  };
+  std::vector<SchurTarget> schur;
+  std::vector<SchurTerm> schur_terms;
+  // merge of this step into step l-1: child block (ci, cj) (cj at position ee
+  // of ci's list) goes to parent block (P, Q = adj[e]) of step l-1
+  struct MergeCopy {
+    int32_t P, ci, cj, pad;
+    int64_t e, ee;
+  };
+  std::vector<MergeCopy> merge;
 };
 
 struct Plan {
