@@ -79,10 +79,16 @@ struct CoopDesc {
   int32_t G, xcd, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
 };
 constexpr int kCoopMaxGroup = 32;
+constexpr int kCoopList = 32;           // tie candidates exchanged per workgroup
 constexpr int kCoopXcds = 8;             // XCDs of an MI355X; block b runs on XCD b % 8
 constexpr size_t kCoopLdsBytes = 140 * 1024;
 inline int64_t coop_xch_doubles(int G, int a) {
-  return 2 * (int64_t)G * (2 + 2 * 32) + (int64_t)(2 * G + 1) * (a + 1) + G;
+  return 2 * (int64_t)G * (2 + 2 * kCoopList) + (int64_t)(2 * G + 1) * (a + 1) + G;
+}
+// dynamic LDS of the LDS-resident cooperative QR: the slice (a x ncap), its
+// norms and the Householder vector
+inline size_t coop_lds_bytes(int /*G*/, int a, int ncap) {
+  return ((size_t)a * ncap + ncap + a) * sizeof(double);
 }
 constexpr int kCoopSyncInts = 64;        // 256 bytes per group
 constexpr int kCoopFlag0 = 32;           // flags on their own 128-byte line

@@ -522,8 +522,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             rows = cpqr_reg_rows(amax);
             cap_blocks = cpqr_reg_max_blocks(rows, lds);
           } else {
-            for (const CoopDesc& q : list)
-              lds = std::max(lds, ((size_t)q.d.a * q.ncap + q.ncap + q.d.a) * sizeof(double));
+            for (const CoopDesc& q : list) lds = std::max(lds, coop_lds_bytes(q.G, q.d.a, q.ncap));
             cap_blocks = coop_max_blocks(lds);
           }
           const int slots = cap_blocks / kCoopXcds;

@@ -1,20 +1,24 @@
 // Cooperative early-stopping column-pivoted Householder QR (Alg. 1): the
 // coupling W (a x k) of one interface is split by columns over a group of G
 // workgroups, each holding its column slice in LDS for the whole
-// factorization, so every pivot step is on-chip work plus one group barrier
-// (two on rare slow paths):
+// factorization.  A pivot step is a serial chain run by wave 0 of every
+// workgroup, then a parallel update by all waves:
 //
-//  A. every workgroup publishes its largest trailing norm, the complete list
-//     of its columns within the tie band of that maximum and the column of its
-//     first candidate; since the global band lies inside every local band, the
-//     union of the lists holds every global candidate and each workgroup picks
-//     the same pivot (lowest index among columns within the band of the global
+//  A. wave 0 finds its largest trailing norm and the ordered list of its
+//     columns within the tie band of that maximum, publishes both and the
+//     column of its first candidate, and meets the other workgroups at a group
+//     barrier.  Since the global band lies inside every local band, the union
+//     of the lists holds every global candidate, and each workgroup picks the
+//     same pivot (lowest index among the columns within the band of the global
 //     maximum).  If a list overflows, an extra round exchanges exact local
-//     candidates; if the pivot is not the owner's first candidate, the owner
-//     publishes it in an extra round.
-//  C. every workgroup builds the Householder vector and updates its columns,
-//     recomputing their trailing norms exactly.
+//     candidates; if the pivot is not its owner's first candidate, the owner
+//     publishes it in an extra round.  Wave 0 then builds the Householder
+//     vector in LDS.
+//  C. every wave updates its columns and recomputes their trailing norms
+//     exactly (8 lanes per column, one DPP reduction for the dot product and
+//     one for the norm).
 //
+// One workgroup alone (G = 1) skips the exchange and reads the pivot from LDS.
 // Synchronization.  The launcher puts all workgroups of a group on one XCD
 // (workgroup b of a launch runs on XCD b mod 8).  The group then exchanges
 // data through that XCD's L2: plain stores (the CU's L1 is write-through) and
@@ -36,7 +40,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kCT = 1024;               // threads per workgroup
 constexpr int kCW = kCT / kWave;        // waves per workgroup
-constexpr int kList = 32;               // tie candidates published per workgroup
+constexpr int kList = kCoopList;        // tie candidates published per workgroup
 constexpr int kXs = 2 + 2 * kList;      // exchange stride: max, count, idx[], nrm2[]
 constexpr long kSpinLimit = 1L << 24;   // ~ seconds of s_sleep before giving up
 constexpr int kRpl = 16;                // rows per lane kept in registers by the update
@@ -113,41 +117,34 @@ __device__ __forceinline__ void xst(double* p, double v) {
                      __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 // exchange loads bypass the CU's L1
-__device__ __forceinline__ double xld(double* p) {
-  const unsigned long long u = __hip_atomic_load(reinterpret_cast<unsigned long long*>(p),
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ double xld(const double* p) {
+  const unsigned long long u = __hip_atomic_load(
+      reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT);
   return __longlong_as_double(static_cast<long long>(u));
 }
 
 // Group barrier on per-member flags holding the last phase each member
-// reached: the workgroup waits for its own exchange stores, member g raises
-// its flag to `phase`, and wave 0 polls the G flags (one load per lane) until
-// all have reached it.  Returns false after a timeout.
-__device__ bool group_barrier(int32_t* flags, int phase, int G, int g, int32_t* err, int* sok) {
+// reached, run by one wave (the only one that writes exchange data): it waits
+// for its own exchange stores, raises flag g to `phase` and polls the G flags
+// (one load per lane) until all have reached it.  Returns false after a
+// timeout (bit 1 of the error flag set).
+__device__ bool wave_barrier(int32_t* flags, int phase, int G, int g, int32_t* err) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
-  __syncthreads();
-  if (G == 1) return true;
-  if (threadIdx.x < kWave) {
-    const int lane = threadIdx.x;
-    if (lane == 0) __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    long spins = 0;
-    int ok = 1;
-    while (true) {
-      const int f = lane < G
-                        ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : phase;
-      if (__all(f >= phase)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
-        ok = 0;
-        if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
+  const int lane = threadIdx.x & (kWave - 1);
+  if (lane == 0) __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  long spins = 0;
+  while (true) {
+    const int f = lane < G
+                      ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : phase;
+    if (__all(f >= phase)) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
     }
-    if (lane == 0) *sok = ok;
   }
-  __syncthreads();
-  return *sok != 0;
 }
 
 __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const CpqrNbr* nbrs,
@@ -155,12 +152,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
                                                   int32_t* out_r, int32_t* out_r2, int32_t* out_k,
                                                   double eps, double eps_stop, int32_t* err) {
   extern __shared__ double sm[];
-  __shared__ double redd[kCW];
-  __shared__ int redi[kCW];
-  __shared__ int sok;
-  __shared__ double sM;
-  __shared__ int sC, sover, sfirst, shead;
-  __shared__ int s_wcnt[kCW + 1];
+  __shared__ int sok, sC, s_go, s_r;
+  __shared__ double s_beta, s_tau;
   const int code = blk_map[blockIdx.x];
   if (code < 0) return;   // idle slot of the XCD packing
   const CoopDesc cd = descs[code / kCoopMaxGroup];
@@ -234,167 +227,186 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     s = wave_sum(s);
     if (lane == 0) nrm2[c] = s;
   }
+  if (tid == 0) s_r = -1;
   __syncthreads();
 
+  // Per pivot step the serial chain runs in wave 0 alone (local maximum and
+  // ordered candidate list from nrm2, publishing, the group barrier, the
+  // global decision, the pivot column and the reflector into LDS); every wave
+  // then updates its columns.  Two workgroup barriers per step.
   int phase = 0;
   int r = -1, j = 0;
   double R00 = 0.0;
   const int jmax = min(a, k);
   for (; j < jmax; ++j) {
-    // ---- A: local maximum, the ordered list of local tie candidates, and
-    //      the column of the first local candidate (speculative pivot) ----
-    double* X = X2 + (int64_t)(j & 1) * G * kXs;
-    double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
-    double ml = -1.0;
-    for (int c = tid; c < m; c += kCT) ml = fmax(ml, nrm2[c]);
-    ml = wave_max(ml);
-    if (lane == 0) redd[wid] = ml;
-    if (tid == 0) sfirst = -1;
-    __syncthreads();
-    double Mg = redd[0];
-#pragma unroll
-    for (int w = 1; w < kCW; ++w) Mg = fmax(Mg, redd[w]);
-    const double thl = Mg * (1.0 - kPivotTieRtol);
-    double* Xg = X + (int64_t)g * kXs;
-    int total = 0;
-    for (int cb = 0; cb < m; cb += kCT) {      // ordered compaction, kCT columns at a time
-      const int c = cb + tid;
-      const bool f = Mg >= 0.0 && c < m && nrm2[c] >= 0.0 && nrm2[c] >= thl;
-      const unsigned long long mask = __ballot(f);
-      if (lane == 0) s_wcnt[wid] = __popcll(mask);
-      __syncthreads();
-      int before = total;
-      for (int w = 0; w < wid; ++w) before += s_wcnt[w];
-      if (f) {
-        const int at = before + __popcll(mask & ((1ULL << lane) - 1ULL));
-        if (at == 0) sfirst = c;
-        if (at < cd.list_cap) {
-          xst(Xg + 2 + at, (double)(c0 + c));
-          xst(Xg + 2 + kList + at, nrm2[c]);
+    if (wid == 0) {
+      int go = 1;
+      // ---- local maximum and the ordered list of local tie candidates ----
+      double ml = -1.0;
+      for (int c = lane; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
+      const double Mg = wave_max(ml);
+      const double thl = Mg * (1.0 - kPivotTieRtol);
+      double* X = X2 + (int64_t)(j & 1) * G * kXs;
+      double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
+      double* Xg = X + (int64_t)g * kXs;
+      int total = 0, first = -1;
+      for (int cb = 0; cb < m; cb += kWave) {
+        const int c = cb + lane;
+        const bool f = Mg >= 0.0 && c < m && nrm2[c] >= 0.0 && nrm2[c] >= thl;
+        const unsigned long long mask = __ballot(f);
+        if (f && G > 1) {
+          const int at = total + __popcll(mask & ((1ULL << lane) - 1ULL));
+          if (at < cd.list_cap) {
+            xst(Xg + 2 + at, (double)(c0 + c));
+            xst(Xg + 2 + kList + at, nrm2[c]);
+          }
+        }
+        if (first < 0 && mask) first = cb + __ffsll((long long)mask) - 1;
+        total += __popcll(mask);
+      }
+      int C = INT_MAX;
+      const double* PVl = nullptr;   // pivot column in LDS (one workgroup) ...
+      const double* PVg = nullptr;   // ... or in the exchange buffer
+      if (G == 1) {
+        if (Mg < 0.0) go = 0;   // every column used up
+        else {
+          C = c0 + first;
+          PVl = Ys + (int64_t)first * a;
+        }
+      } else {
+        if (lane == 0) {
+          xst(Xg, Mg);
+          xst(Xg + 1, (double)total);
+        }
+        if (first >= 0) {
+          double* Pg = PVs + (int64_t)g * (a + 1);
+          if (lane == 0) xst(Pg, nrm2[first]);
+          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
+        }
+        if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
+        if (go > 0) {
+          // one round of loads: lane q fetches group q's maximum, count and
+          // first list entry; further entries are fetched only from groups
+          // that have more than one and whose maximum reaches the global band
+          double Mq = -2.0, nv0 = -1.0;
+          int cq = 0, ix0 = INT_MAX;
+          if (lane < G) {
+            const double* Xq = X + (int64_t)lane * kXs;
+            Mq = xld(Xq);
+            cq = (int)xld(Xq + 1);
+            ix0 = (int)xld(Xq + 2);
+            nv0 = xld(Xq + 2 + kList);
+          }
+          const double M = wave_max(Mq);
+          const bool over = __ballot(lane < G && cq > cd.list_cap) != 0ULL;
+          if (M < 0.0) go = 0;   // every column used up
+          else {
+            const double thr = M * (1.0 - kPivotTieRtol);
+            if (!over) {
+              if (lane < G && cq > 0 && cd.list_cap > 0 && nv0 >= thr) C = ix0;
+              unsigned long long more = __ballot(lane < G && cq > 1 && Mq >= thr);
+              while (more) {   // rare: several candidates in one group
+                const int q = __ffsll((long long)more) - 1;
+                more &= more - 1ULL;
+                const int cqq = min(__shfl(cq, q, kWave), cd.list_cap);
+                const double* Xq = X + (int64_t)q * kXs;
+                if (lane >= 1 && lane < cqq && xld(Xq + 2 + kList + lane) >= thr)
+                  C = min(C, (int)xld(Xq + 2 + lane));
+              }
+              C = wave_min_int(C);
+            } else {
+              // exact local candidates against the global threshold
+              int cl = INT_MAX;
+              for (int cb = 0; cb < m && cl == INT_MAX; cb += kWave) {
+                const int c = cb + lane;
+                const unsigned long long mk = __ballot(c < m && nrm2[c] >= 0.0 && nrm2[c] >= thr);
+                if (mk) cl = c0 + cb + __ffsll((long long)mk) - 1;
+              }
+              if (lane == 0) xst(XB + g, (double)cl);
+              if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
+              if (go > 0) {
+                for (int qq = lane; qq < G; qq += kWave) C = min(C, (int)xld(XB + qq));
+                C = wave_min_int(C);
+              }
+            }
+            if (go > 0) {
+              const int og = min(C / max(per, 1), G - 1);   // owner workgroup
+              // the owner's published first candidate is the pivot unless the
+              // lists overflowed or it fell outside the global band
+              const int head_og =
+                  __shfl(cq, og, kWave) > 0 && cd.list_cap > 0 ? __shfl(ix0, og, kWave) : -1;
+              if (!over && head_og == C) {
+                PVg = PVs + (int64_t)og * (a + 1);
+              } else {
+                if (C >= c0 && C < c1) {
+                  const int Cl = C - c0;
+                  if (lane == 0) xst(PVx, nrm2[Cl]);
+                  for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
+                }
+                if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
+                PVg = PVx;
+              }
+            }
+          }
         }
       }
-      for (int w = 0; w < kCW; ++w) total += s_wcnt[w];
-      __syncthreads();
-    }
-    if (tid == 0) {
-      xst(Xg, Mg);
-      xst(Xg + 1, (double)total);
-    }
-    const int first = sfirst;  // local index of my first candidate, or -1
-    if (first >= 0) {
-      double* Pg = PVs + (int64_t)g * (a + 1);
-      if (tid == 0) xst(Pg, nrm2[first]);
-      for (int i = j + tid; i < a; i += kCT) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
-    }
-    if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
-    // global maximum and pivot (every workgroup computes the same).  One
-    // round of loads: thread (q, e) fetches group q's maximum, count and list
-    // entry e; the decision is made with workgroup reductions.
-    const int q = tid / kList, e = tid % kList;
-    double Mq = -2.0, nv = -1.0;
-    int cq = 0, ix = INT_MAX;
-    if (q < G) {
-      const double* Xq = X + (int64_t)q * kXs;
-      Mq = xld(const_cast<double*>(Xq));
-      cq = (int)xld(const_cast<double*>(Xq + 1));
-      if (e < cd.list_cap) {
-        ix = (int)xld(const_cast<double*>(Xq + 2 + e));
-        nv = xld(const_cast<double*>(Xq + 2 + kList + e));
+      if (go > 0) {
+        // the pivot column: norm, first entry and the rest, into v
+        double pn, alpha;
+        if (PVl) {
+          pn = nrm2[C - c0];
+          alpha = PVl[j];
+          for (int i = j + 1 + lane; i < a; i += kWave) v[i] = PVl[i];
+        } else {
+          pn = xld(PVg);
+          alpha = xld(PVg + 1);
+          for (int i0 = j + 1; i0 < a; i0 += 4 * kWave) {   // four loads in flight per lane
+            double xr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int i = i0 + lane + t * kWave;
+              xr[t] = i < a ? xld(PVg + 1 + (i - j)) : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int i = i0 + lane + t * kWave;
+              if (i < a) v[i] = xr[t];
+            }
+          }
+        }
+        const double nrm = sqrt(pn);
+        if (j == 0) R00 = nrm;
+        if (nrm == 0.0 || nrm < eps_stop * R00) go = 0;
+        else {
+          if (r < 0 && nrm < eps * R00) r = j;
+          const double beta = alpha >= 0.0 ? -nrm : nrm;
+          const double rden = 1.0 / (alpha - beta);
+          for (int i = j + 1 + lane; i < a; i += kWave) v[i] *= rden;
+          if (lane == 0) {
+            v[j] = 1.0;
+            s_beta = beta;
+            s_tau = (beta - alpha) / beta;
+            sC = C;
+          }
+        }
+      }
+      if (lane == 0) {
+        s_go = go;
+        s_r = r;
       }
     }
-    {
-      double mm = wave_max(Mq);
-      const int ov = wave_max_int(q < G && e == 0 && cq > cd.list_cap ? 1 : 0);
-      if (lane == 0) { redd[wid] = mm; redi[wid] = ov; }
-      __syncthreads();
-      double M = redd[0];
-      int over = redi[0];
-      for (int w = 1; w < kCW; ++w) { M = fmax(M, redd[w]); over = max(over, redi[w]); }
-      if (tid == 0) { sM = M; sover = over; }
-      __syncthreads();
-    }
-    const double M = sM;
-    if (M < 0.0) break;
-    const double thr = M * (1.0 - kPivotTieRtol);
-    int C = INT_MAX;
-    if (!sover) {
-      if (q < G && e < cq && nv >= thr) C = ix;
-    } else {
-      // B: exact local candidates against the global threshold
-      int cl = INT_MAX;
-      for (int c = tid; c < m; c += kCT)
-        if (nrm2[c] >= 0.0 && nrm2[c] >= thr) { cl = c0 + c; break; }
-      cl = wave_min_int(cl);
-      if (lane == 0) redi[wid] = cl;
-      __syncthreads();
-      if (tid == 0) {
-        int mn = redi[0];
-        for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
-        xst(XB + g, (double)mn);
-      }
-      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
-      for (int qq = tid; qq < G; qq += kCT) C = min(C, (int)xld(XB + qq));
-    }
-    C = wave_min_int(C);
-    if (lane == 0) redi[wid] = C;
     __syncthreads();
-    if (tid == 0) {
-      int mn = redi[0];
-      for (int w = 1; w < kCW; ++w) mn = min(mn, redi[w]);
-      sC = mn;
-    }
-    __syncthreads();
-    C = sC;
+    const int go = s_go;
+    if (go < 0) return;   // a group barrier timed out (error flag set)
+    if (go == 0) break;
+    const int C = sC;
+    const double tau = s_tau, beta = s_beta;
     const bool owner = C >= c0 && C < c1;
     const int Cl = C - c0;
-    const int og = min(C / max(per, 1), G - 1);   // owner workgroup
-    // the owner's published first candidate is the pivot unless the lists
-    // overflowed or its first candidate fell outside the global band
-    if (q == og && e == 0) shead = (cq > 0 && cd.list_cap > 0) ? ix : -1;
-    __syncthreads();
-    const bool spec = !sover && shead == C;
-    double* PV = PVs + (int64_t)og * (a + 1);
-    if (!spec) {
-      PV = PVx;
-      if (owner) {
-        if (tid == 0) xst(PV, nrm2[Cl]);
-        for (int i = j + tid; i < a; i += kCT) xst(PV + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
-      }
-      if (!group_barrier(flags, ++phase, G, g, err, &sok)) return;
+    if (g == 0) {
+      for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? 0.0 : v[i];
+      if (tid == 0) d.tau[j] = tau;
     }
-    // one round of loads: the pivot's norm, its first entry and the rest of it
-    const double pn = xld(PV), alpha = xld(PV + 1);
-    double xi[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i = j + 1 + tid + t * kCT;
-      xi[t] = i < a ? xld(PV + 1 + (i - j)) : 0.0;
-    }
-    const double nrm = sqrt(pn);
-    if (j == 0) R00 = nrm;
-    if (nrm == 0.0 || nrm < eps_stop * R00) break;
-    if (r < 0 && nrm < eps * R00) r = j;
-    const double beta = alpha >= 0.0 ? -nrm : nrm;
-    const double denom = alpha - beta;
-    const double tau = (beta - alpha) / beta;
-    for (int i = tid; i <= j; i += kCT) {
-      v[i] = i == j ? 1.0 : 0.0;
-      if (g == 0) d.V[i + (int64_t)j * a] = v[i];
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i = j + 1 + tid + t * kCT;
-      if (i < a) {
-        v[i] = xi[t] / denom;
-        if (g == 0) d.V[i + (int64_t)j * a] = v[i];
-      }
-    }
-    for (int i = j + 1 + tid + 4 * kCT; i < a; i += kCT) {
-      v[i] = xld(PV + 1 + (i - j)) / denom;
-      if (g == 0) d.V[i + (int64_t)j * a] = v[i];
-    }
-    if (g == 0 && tid == 0) d.tau[j] = tau;
-    __syncthreads();
     // fused reflector update + exact trailing norms: 8 lanes per column,
     // 8 columns per wave; one 3-step DPP reduction serves 8 columns at once
     {
@@ -441,6 +453,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     }
     __syncthreads();
   }
+  r = s_r;
   const int nref = j;
   if (r < 0) r = nref;
 
