@@ -52,7 +52,7 @@ struct ApSp {
   int32_t a, nref, f0, f1, k, ntiles;
 };
 
-// One tile of at most kEtTile columns of an interface's E (second order:
+// One tile of at most kEtTileF (forward) or kEtTileB (backward) columns of an interface's E (second order:
 // E = rows f0.. of Q^T W, stored transposed, element (c, i) = E[i, c] at
 // Et[c + i*lde]).  Forward: t[c0 + c] = sum_i E[i, c0 + c] z_f[i] for the
 // tile's columns, into the interface's scratch vector (offset off, length k).
@@ -65,7 +65,8 @@ struct ApEt {
   int64_t off;             // units of one right-hand side
   int32_t nf, k, c0, cn;
 };
-constexpr int kEtTile = 256;
+constexpr int kEtTileF = 64;    // columns per forward E tile
+constexpr int kEtTileB = 256;   // columns per backward E tile
 
 struct ApScale {
   const double* Zinv;

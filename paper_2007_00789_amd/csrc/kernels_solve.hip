@@ -12,6 +12,7 @@ constexpr int kT = 256;
 constexpr int kST = 512;   // threads of the sparsification apply kernels
 // right-hand sides per pass of the WY products (bounds their LDS partial sums)
 __host__ __device__ constexpr int sp_rb(int nrhs) { return nrhs > 4 ? 2 : 4; }
+__host__ __device__ constexpr int ap_rb(int nrhs) { return nrhs > 4 ? 2 : 4; }
 
 // DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
 template <int kCtrl>
@@ -57,45 +58,6 @@ constexpr int kNW = kT / kWave;
 constexpr int kBatch = 8;   // columns per wave iteration (independent loads in flight)
 constexpr int kChunk = 1024;  // staged neighbour values of the backward E product
 
-// out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx] for c < cols, r < nrhs.
-// One wave per batch of kBatch columns, lanes over rows; x lives in LDS, out
-// in LDS or global memory.
-__device__ void wg_coldots(const double* __restrict__ M, int64_t ld, int rows, int cols,
-                           const double* __restrict__ x, int ldx, int nrhs, double* __restrict__ out,
-                           int64_t ldo) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int c0 = wid * kBatch; c0 < cols; c0 += kNW * kBatch) {
-    double acc[kBatch][4];
-    for (int r0 = 0; r0 < nrhs; r0 += 4) {
-#pragma unroll
-      for (int q = 0; q < kBatch; ++q)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
-      for (int i = lane; i < rows; i += kWave) {
-        double m[kBatch];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-          m[q] = c0 + q < cols ? M[i + (int64_t)(c0 + q) * ld] : 0.0;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          if (r0 + rr >= nrhs) break;
-          const double xv = x[i + (r0 + rr) * ldx];
-#pragma unroll
-          for (int q = 0; q < kBatch; ++q) acc[q][rr] = fma(m[q], xv, acc[q][rr]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kBatch; ++q)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          if (r0 + rr >= nrhs) break;
-          const double v = wave_sum(acc[q][rr]);
-          if (lane == 0 && c0 + q < cols) out[c0 + q + (int64_t)(r0 + rr) * ldo] = v;
-        }
-    }
-  }
-}
-
 // acc_out[i + r*rows] = sum_{c<cols} M[i + c*ld] z[pos[c] + r*ldz] for i < rows.
 // The gathered values are staged in LDS (chunks of kChunk columns, all
 // threads loading); then lanes hold rows and waves split the columns, and the
@@ -140,36 +102,53 @@ __device__ void wg_rowsum_gather(const double* __restrict__ M, int64_t ld, int r
 // ---------------------------------------------------------------------------
 // Helpers for NT-thread workgroups (the sparsification apply uses 512).
 // ---------------------------------------------------------------------------
-// out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx]: one wave per kBatch
-// columns, lanes over rows (coalesced), one wave reduction per output.
-template <int NT>
+// The GEMV helpers below keep many loads in flight per lane: a lane loads
+// every 64-row chunk it needs (RC chunks, 64*RC rows per block) for a small
+// batch of columns before the first FMA, so a workgroup's product costs a few
+// memory round trips instead of one per chunk.  Interior kernels (many small
+// workgroups) use a low-register shape, the WY kernels a deep one.
+#define SP_COLDOTS wgt_coldots<NT, 5, 2>
+#define SP_GEMV wgt_gemv_acc<NT, 5, 2>
+#define IN_COLDOTS wgt_coldots<kT, 1, 8>
+#define IN_GEMV wgt_gemv_acc<kT, 1, 8>
+// out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx]: one wave per batch of
+// CB columns, lanes over rows (coalesced, RC chunks of 64 per block), one wave
+// reduction per output.
+template <int NT, int RC, int CB>
 __device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, int cols,
                             const double* __restrict__ x, int ldx, int nrhs, double* __restrict__ out,
                             int64_t ldo) {
-  constexpr int NW = NT / kWave;
+  constexpr int NW = NT / kWave, kRC = RC;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  for (int c0 = wid * kBatch; c0 < cols; c0 += NW * kBatch) {
+  for (int c0 = wid * CB; c0 < cols; c0 += NW * CB) {
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
-      double acc[kBatch][4];
+      double acc[CB][4];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q)
+      for (int q = 0; q < CB; ++q)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
-      for (int i = lane; i < rows; i += kWave) {
-        double m[kBatch];
+      for (int ib = 0; ib < rows; ib += kWave * kRC) {
+        double m[kRC][CB];
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-          m[q] = c0 + q < cols ? M[i + (int64_t)(c0 + q) * ld] : 0.0;
+        for (int t = 0; t < kRC; ++t)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          if (r0 + rr >= nrhs) break;
-          const double xv = x[i + (r0 + rr) * ldx];
+          for (int q = 0; q < CB; ++q) {
+            const int i = ib + lane + kWave * t;
+            m[t][q] = (i < rows && c0 + q < cols) ? M[i + (int64_t)(c0 + q) * ld] : 0.0;
+          }
 #pragma unroll
-          for (int q = 0; q < kBatch; ++q) acc[q][rr] = fma(m[q], xv, acc[q][rr]);
+        for (int t = 0; t < kRC; ++t) {
+          const int i = ib + lane + kWave * t;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const double xv = (i < rows && r0 + rr < nrhs) ? x[i + (r0 + rr) * ldx] : 0.0;
+#pragma unroll
+            for (int q = 0; q < CB; ++q) acc[q][rr] = fma(m[t][q], xv, acc[q][rr]);
+          }
         }
       }
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q)
+      for (int q = 0; q < CB; ++q)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           if (r0 + rr >= nrhs) break;
@@ -181,29 +160,44 @@ __device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, 
 }
 
 // y[i + r*ldy] += sign * sum_{c<cols} M[i + c*ld] w[c + r*ldw] for i < rows:
-// lanes over rows (coalesced), waves over columns, rb right-hand sides per
-// pass; per-wave partial sums in LDS (part: NW x rows x rb) added in wave
-// order.  Ends with a barrier.
-template <int NT>
+// lanes over rows (coalesced, RC chunks of 64 per lane), waves over columns
+// (CU columns in flight), rb right-hand sides per pass; per-wave partial sums
+// in LDS (part: NW x rows x rb) added in wave order.  Ends with a barrier.
+template <int NT, int RC, int CU>
 __device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows, int cols,
                              const double* __restrict__ w, int ldw, int nrhs, double sign,
                              double* __restrict__ y, int ldy, double* __restrict__ part, int rb) {
-  constexpr int NW = NT / kWave;
+  constexpr int NW = NT / kWave, kRC = RC;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   for (int r0 = 0; r0 < nrhs; r0 += rb) {
     const int nr = min(rb, nrhs - r0);
-    for (int i = lane; i < rows; i += kWave) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-      for (int c = wid; c < cols; c += NW) {
-        const double m = M[i + (int64_t)c * ld];
+    for (int ib = 0; ib < rows; ib += kWave * kRC) {
+      double acc[kRC][4];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-          if (rr < nr) acc[rr] = fma(m, w[c + (r0 + rr) * ldw], acc[rr]);
+      for (int t = 0; t < kRC; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[t][rr] = 0.0;
+#pragma unroll CU
+      for (int c = wid; c < cols; c += NW) {
+        double wv[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) wv[rr] = rr < nr ? w[c + (r0 + rr) * ldw] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kRC; ++t) {
+          const int i = ib + lane + kWave * t;
+          const double m = i < rows ? M[i + (int64_t)c * ld] : 0.0;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) acc[t][rr] = fma(m, wv[rr], acc[t][rr]);
+        }
       }
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        if (rr < nr) part[(wid * rows + i) * rb + rr] = acc[rr];
+      for (int t = 0; t < kRC; ++t) {
+        const int i = ib + lane + kWave * t;
+        if (i < rows)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            if (rr < nr) part[(wid * rows + i) * rb + rr] = acc[t][rr];
+      }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < rows * nr; idx += NT) {
@@ -225,17 +219,17 @@ __device__ void wgt_apply_wy(const double* __restrict__ V, const double* __restr
                              int nref, double* __restrict__ x, int nrhs, double* __restrict__ u,
                              double* __restrict__ u2, double* __restrict__ part, bool trans) {
   if (nref == 0) return;
-  wgt_coldots<NT>(V, a, a, nref, x, a, nrhs, u, nref);                 // u = V^T x
+  SP_COLDOTS(V, a, a, nref, x, a, nrhs, u, nref);                 // u = V^T x
   __syncthreads();
   if (trans) {
-    wgt_coldots<NT>(T, nref, nref, nref, u, nref, nrhs, u2, nref);     // u2 = T^T u
+    SP_COLDOTS(T, nref, nref, nref, u, nref, nrhs, u2, nref);     // u2 = T^T u
     __syncthreads();
   } else {
     for (int idx = threadIdx.x; idx < nref * nrhs; idx += NT) u2[idx] = 0.0;
     __syncthreads();
-    wgt_gemv_acc<NT>(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part, sp_rb(nrhs));   // u2 = T u
+    SP_GEMV(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part, sp_rb(nrhs));   // u2 = T u
   }
-  wgt_gemv_acc<NT>(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part, sp_rb(nrhs));   // x -= V u2
+  SP_GEMV(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part, sp_rb(nrhs));   // x -= V u2
 }
 
 // ---------------------------------------------------------------------------
@@ -248,22 +242,21 @@ __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z
   const int n = d.n, k = d.k;
   double* xs = sm;             // n x nrhs
   double* ys = sm + n * nrhs;  // n x nrhs
+  double* part = ys + n * nrhs;   // kNW x n x ap_rb(nrhs)
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     xs[idx] = z[d.pos[i] + r * ldz];
+    ys[idx] = 0.0;
   }
   __syncthreads();
+  // ys = L^{-1} xs (L^{-1} is stored with zeros above its diagonal)
+  IN_GEMV(d.Linv, n, n, n, xs, n, nrhs, 1.0, ys, n, part, ap_rb(nrhs));
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int m = 0; m <= i; ++m) acc = fma(d.Linv[i + (int64_t)m * n], xs[m + r * n], acc);
-    ys[idx] = acc;
-    z[d.pos[i] + r * ldz] = acc;
+    z[d.pos[i] + r * ldz] = ys[idx];
   }
-  __syncthreads();
   if (k == 0) return;
-  wg_coldots(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
+  IN_COLDOTS(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,74 +316,96 @@ __global__ __launch_bounds__(kST) void k_ap_sp_fwd(const ApSp* descs, double* z,
 }
 
 // ---------------------------------------------------------------------------
-// E tiles.  Forward: t[c] = sum_i E[i, c] z_f[i], one column per thread (rows
-// of E^T are contiguous, so a wave reads 64 consecutive entries per row).
-// LDS: z_f (nf x nrhs).
+// E tiles.  Forward: t[c] = sum_i E[i, c] z_f[i] over a tile of kEtTileF
+// columns: lanes over the columns (rows of E^T are contiguous), the waves split
+// the rows, and the per-wave partial sums are added in wave order.
+// LDS: z_f (nf x nrhs) | part (kSNW x 64 x 4).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kT) void k_ap_et_fwd(const ApEt* descs, const double* z, int64_t ldz,
-                                                  int nrhs, double* T) {
+__global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const double* z, int64_t ldz,
+                                                   int nrhs, double* T) {
   extern __shared__ double sm[];
+  constexpr int NW = kST / kWave;
   const ApEt d = descs[blockIdx.x];
-  const int nf = d.nf;
+  const int nf = d.nf, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   double* zf = sm;
-  for (int idx = threadIdx.x; idx < nf * nrhs; idx += kT) {
+  double* part = sm + nf * nrhs;
+  for (int idx = threadIdx.x; idx < nf * nrhs; idx += kST) {
     const int i = idx % nf, r = idx / nf;
     zf[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  const int c = threadIdx.x;
-  if (c >= d.cn) return;
-  const double* e = d.Et + d.c0 + c;
-  double* t = T + d.off * nrhs + d.c0 + c;
+  const int per = (nf + NW - 1) / NW, i0 = min(nf, wid * per), i1 = min(nf, i0 + per);
+  const bool col = lane < d.cn;
+  const double* e = d.Et + d.c0 + (col ? lane : 0);
+  double* t = T + d.off * nrhs + d.c0 + lane;
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (col) {
 #pragma unroll 8
-    for (int i = 0; i < nf; ++i) {
-      const double ev = e[(int64_t)i * d.lde];
+      for (int i = i0; i < i1; ++i) {
+        const double ev = e[(int64_t)i * d.lde];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        if (r0 + rr < nrhs) acc[rr] = fma(ev, zf[i + (r0 + rr) * nf], acc[rr]);
+        for (int rr = 0; rr < 4; ++rr)
+          if (r0 + rr < nrhs) acc[rr] = fma(ev, zf[i + (r0 + rr) * nf], acc[rr]);
+      }
     }
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-      if (r0 + rr < nrhs) t[(int64_t)(r0 + rr) * d.k] = acc[rr];
+    for (int rr = 0; rr < 4; ++rr) part[(wid * kWave + lane) * 4 + rr] = acc[rr];
+    __syncthreads();
+    if (wid == 0 && col)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        if (r0 + rr >= nrhs) break;
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sacc += part[(q * kWave + lane) * 4 + rr];
+        t[(int64_t)(r0 + rr) * d.k] = sacc;
+      }
+    __syncthreads();
   }
 }
 
 // Backward: part[i] = sum_{c in tile} E[i, c] y_W[c] for every fine row i.
 // The tile's neighbour values are staged in LDS (cn x nrhs); each wave takes
-// four rows of E at a time, lanes over the tile's columns.
-__global__ __launch_bounds__(kT) void k_ap_et_bwd(const ApEt* descs, const double* z, int64_t ldz,
-                                                  int nrhs, double* P) {
+// four rows of E at a time with all of the tile's columns in flight (lanes over
+// columns, up to kEtTileB / 64 chunks per lane).
+__global__ __launch_bounds__(kST) void k_ap_et_bwd(const ApEt* descs, const double* z, int64_t ldz,
+                                                   int nrhs, double* P) {
   extern __shared__ double sm[];
+  constexpr int NW = kST / kWave, CH = kEtTileB / kWave;
   const ApEt d = descs[blockIdx.x];
   const int nf = d.nf, cn = d.cn;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   double* yw = sm;
-  for (int idx = threadIdx.x; idx < cn * nrhs; idx += kT) {
+  for (int idx = threadIdx.x; idx < cn * nrhs; idx += kST) {
     const int c = idx % cn, r = idx / cn;
     yw[idx] = z[d.pos[d.c0 + c] + r * ldz];
   }
   __syncthreads();
   double* out = P + d.off * nrhs;
-  for (int i0 = wid * 4; i0 < nf; i0 += kNW * 4) {
+  for (int i0 = wid * 4; i0 < nf; i0 += NW * 4) {
+    double ev[4][CH];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int c = lane + kWave * t;
+        ev[q][t] = (i0 + q < nf && c < cn) ? d.Et[d.c0 + c + (int64_t)(i0 + q) * d.lde] : 0.0;
+      }
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
       double acc[4][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) acc[q][rr] = 0.0;
-      for (int c = lane; c < cn; c += kWave) {
-        double ev[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          ev[q] = i0 + q < nf ? d.Et[d.c0 + c + (int64_t)(i0 + q) * d.lde] : 0.0;
+      for (int t = 0; t < CH; ++t) {
+        const int c = lane + kWave * t;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          if (r0 + rr >= nrhs) break;
-          const double yv = yw[c + (r0 + rr) * cn];
+          const double yv = (c < cn && r0 + rr < nrhs) ? yw[c + (r0 + rr) * cn] : 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[q][rr] = fma(ev[q], yv, acc[q][rr]);
+          for (int q = 0; q < 4; ++q) acc[q][rr] = fma(ev[q][t], yv, acc[q][rr]);
         }
       }
 #pragma unroll
@@ -449,7 +464,7 @@ __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, doubl
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  wg_coldots(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
+  IN_COLDOTS(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -474,7 +489,7 @@ __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z
     us[idx] = z[d.pos[i] + r * ldz] - (k > 0 ? ys[idx] : 0.0);
   }
   __syncthreads();
-  wg_coldots(d.Linv, n, n, n, us, n, nrhs, ys, n);
+  IN_COLDOTS(d.Linv, n, n, n, us, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -570,7 +585,8 @@ inline unsigned grid_for(int64_t n, int bs) {
 void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        double* T, int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_int_fwd, dim3(count), dim3(kT), 2 * (size_t)max_n * nrhs * sizeof(double),
+  hipLaunchKernelGGL(k_ap_int_fwd, dim3(count), dim3(kT),
+                     ((size_t)2 * max_n * nrhs + (size_t)kNW * max_n * ap_rb(nrhs)) * sizeof(double),
                      s, d, z, ldz, nrhs, T);
 }
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
@@ -591,14 +607,14 @@ void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int3
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* T, int32_t max_nf, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_et_fwd, dim3(count), dim3(kT), (size_t)max_nf * nrhs * sizeof(double), s,
-                     d, z, ldz, nrhs, T);
+  hipLaunchKernelGGL(k_ap_et_fwd, dim3(count), dim3(kST),
+                     ((size_t)max_nf * nrhs + (size_t)kST * 4) * sizeof(double), s, d, z, ldz, nrhs, T);
 }
 void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* P, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kT), (size_t)kEtTile * nrhs * sizeof(double), s,
-                     d, z, ldz, nrhs, P);
+  hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kST), (size_t)kEtTileB * nrhs * sizeof(double),
+                     s, d, z, ldz, nrhs, P);
 }
 void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       const double* P, int32_t max_a, hipStream_t s) {

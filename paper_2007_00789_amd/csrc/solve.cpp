@@ -14,7 +14,7 @@ struct ApplyColour {
   int32_t n_sp = 0, max_a = 0;
   ApEt* etf = nullptr;   // E tiles, forward
   ApEt* etb = nullptr;   // E tiles, backward
-  int32_t n_et = 0, max_nf = 0;
+  int32_t n_etf = 0, n_etb = 0, max_nf = 0;
   ApGat* gat = nullptr;
   ApSrc* src = nullptr;
   int32_t n_gat = 0, max_n = 0;
@@ -167,17 +167,21 @@ void build_apply(Ctx& C, FactorObj& F) {
           d.part0 = psz;
           d.ntiles = 0;
           if (d.Et && nf > 0 && d.k > 0) {
-            for (int c0 = 0; c0 < d.k; c0 += kEtTile) {
-              ApEt t{};
-              t.Et = d.Et;
-              t.lde = d.lde;
-              t.nf = nf;
-              t.k = d.k;
+            ApEt t{};
+            t.Et = d.Et;
+            t.lde = d.lde;
+            t.nf = nf;
+            t.k = d.k;
+            for (int c0 = 0; c0 < d.k; c0 += kEtTileF) {
               t.c0 = c0;
-              t.cn = std::min(kEtTile, d.k - c0);
+              t.cn = std::min(kEtTileF, d.k - c0);
               t.pos = d.pos + d.f0;
               t.off = d.toff;
               etf.push_back(t);
+            }
+            for (int c0 = 0; c0 < d.k; c0 += kEtTileB) {
+              t.c0 = c0;
+              t.cn = std::min(kEtTileB, d.k - c0);
               t.pos = d.nbr_pos;
               t.off = psz;
               etb.push_back(t);
@@ -195,7 +199,8 @@ void build_apply(Ctx& C, FactorObj& F) {
         ac.n_sp = (int32_t)sps.size();
         ac.etf = F.meta.upload(etf);
         ac.etb = F.meta.upload(etb);
-        ac.n_et = (int32_t)etf.size();
+        ac.n_etf = (int32_t)etf.size();
+        ac.n_etb = (int32_t)etb.size();
         if (!(so || sf)) continue;
         // targets: interfaces adjacent to an interface of this colour
         std::vector<ApGat> eg;
@@ -249,13 +254,16 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   // every apply kernel stages its cluster's slice of the vectors in LDS
   constexpr int64_t kLds = 160 * 1024;
   for (const ApplyStep& as : pg.steps) {
-    int64_t need = std::max<int64_t>((int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
-                                      (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
+    // interiors: x, y and the GEMV partial sums (forward); y, u, partial sums
+    // and a gather chunk (backward); interfaces: 2 vectors (scaling)
+    int64_t need = std::max<int64_t>({(int64_t)as.max_in * (2 * nrhs + 4 * 4),
+                                      (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
+                                      (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs});
     for (const ApplyColour& ac : as.colours)
       need = std::max<int64_t>(need, std::max<int64_t>({(int64_t)ac.max_a * (3 * nrhs + 8 * (nrhs > 4 ? 2 : 4)),
                                                         (int64_t)ac.max_n * nrhs,
-                                                        (int64_t)ac.max_nf * nrhs,
-                                                        (int64_t)kEtTile * nrhs}));
+                                                        (int64_t)ac.max_nf * nrhs + 2048,
+                                                        (int64_t)kEtTileB * nrhs}));
     if (need * (int64_t)sizeof(double) > kLds)
       throw Error(SPAND_E_LIMIT, "cluster too large for the apply with nrhs = " + std::to_string(nrhs));
   }
@@ -265,14 +273,14 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
     SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
     for (const ApplyColour& ac : as.colours) {
       SPAND_PROF(C, "k_ap_sp_fwd", launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, ac.max_a, s));
-      SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_et, y, n, nrhs, T, ac.max_nf, s));
+      SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_etf, y, n, nrhs, T, ac.max_nf, s));
       SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s));
     }
   }
   for (auto it = pg.steps.rbegin(); it != pg.steps.rend(); ++it) {
     const ApplyStep& as = *it;
     for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c) {
-      SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_et, y, n, nrhs, Pp, s));
+      SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_etb, y, n, nrhs, Pp, s));
       SPAND_PROF(C, "k_ap_sp_bwd", launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, Pp, c->max_a, s));
     }
     SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
