@@ -93,7 +93,26 @@ const char* spand_last_error(spand_ctx_t ctx);
 spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
                            const double* coords, int32_t dim, const spand_opts* opts,
                            spand_plan_t* out);
+/* Batch of independent problems (a block-diagonal system) analysed into one
+ * plan, so that spand_factor, spand_apply and spand_pcg process all of them in
+ * the same kernel launches (multi-problem batching, a project addition).
+ * Problem i is given as for spand_analyze (n[i], rowptr[i], colind[i],
+ * coords[i], dim[i]; host pointers, copied); its rows follow those of problems
+ * 0..i-1 in the batch numbering, and the batch's CSR values are the problems'
+ * values concatenated in that order.  depth[i] (NULL: opts->depth, and <= 0
+ * means round(log2(n[i]/64)) per problem) is each problem's own nested-
+ * dissection depth; levels are aligned at the leaves, which keeps every
+ * problem's own sparsified levels 1 <= l <= depth[i] - skip (Alg. 2, Sec. 4),
+ * so each problem's factor is the one spand_analyze + spand_factor would give
+ * it alone.  spand_pcg runs one CG per problem and column. */
+spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* n,
+                                 const int64_t* const* rowptr, const int32_t* const* colind,
+                                 const double* const* coords, const int32_t* dim,
+                                 const int32_t* depth, const spand_opts* opts, spand_plan_t* out);
 void spand_destroy_plan(spand_plan_t plan);
+/* Problems of a plan (1 unless it came from spand_analyze_batch) and their row
+ * offsets: offsets[count+1] (host, may be NULL to query the count). */
+spand_status spand_plan_segments(spand_plan_t plan, int32_t* count, int64_t* offsets);
 
 /* Plan queries (host arrays supplied by the caller, sized from the counts). */
 spand_status spand_plan_sizes(spand_plan_t plan, int64_t* n, int64_t* nnz, int32_t* depth);
@@ -134,10 +153,12 @@ spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st);
 /* y = M x for nrhs columns; x, y: device pointers, n x nrhs column-major. */
 spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y);
 
-/* PCG (Sec. 4): x0 = 0, stop when ||r_k||_2 < tol ||b||_2 per column; b, x:
- * device pointers (n x nrhs column-major); iters[nrhs], relres[nrhs] (true
- * residual ||b - A x|| / ||b|| at exit): host pointers.  Returns
- * SPAND_E_NO_CONVERGENCE if a column reaches maxit. */
+/* PCG (Sec. 4): x0 = 0, stop when ||r_k||_2 < tol ||b||_2 per column and, for
+ * a batch plan, per problem (each (problem, column) is an independent CG run);
+ * b, x: device pointers (n x nrhs column-major); iters and relres (true
+ * residual ||b - A x|| / ||b|| at exit): host arrays of segments x nrhs,
+ * entry [s * nrhs + c] (segments = 1 for a single problem).  Returns
+ * SPAND_E_NO_CONVERGENCE if a run reaches maxit. */
 spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* b, double* x,
                        double tol, int32_t maxit, int32_t* iters, double* relres);
 

@@ -380,6 +380,157 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
   for (int l = 0; l <= D; ++l) build_numeric_lists(P, l);
 }
 
+void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
+  const int np = (int)parts.size();
+  int D = 0;
+  for (const Plan& q : parts) D = std::max(D, q.depth);
+  M.depth = D;
+  M.skip = skip;
+  M.dim = parts.empty() ? 0 : parts[0].dim;
+  std::vector<int64_t> voff(np + 1, 0), eoff(np + 1, 0);
+  for (int i = 0; i < np; ++i) {
+    voff[i + 1] = voff[i] + parts[i].n;
+    eoff[i + 1] = eoff[i] + parts[i].nnz;
+  }
+  M.n = voff[np];
+  M.nnz = eoff[np];
+  if (M.n >= (int64_t(1) << 31)) throw Error(SPAND_E_LIMIT, "batch larger than 2^31 rows");
+  M.rowptr.assign(1, 0);
+  M.colind.clear();
+  M.lvl.clear();
+  M.path.clear();
+  M.perm.clear();
+  M.seg_off = voff;
+  M.seg_id.assign(M.n, 0);
+  for (int i = 0; i < np; ++i) {
+    const Plan& q = parts[i];
+    const int shift = D - q.depth;
+    for (int64_t v = 0; v < q.n; ++v) {
+      M.rowptr.push_back(eoff[i] + q.rowptr[v + 1]);
+      M.lvl.push_back(q.lvl[v] + shift);
+      M.path.push_back(q.path[v]);
+      M.perm.push_back(q.perm[v] + voff[i]);
+      M.seg_id[voff[i] + v] = i;
+    }
+    for (int64_t e = 0; e < q.nnz; ++e) M.colind.push_back((int32_t)(q.colind[e] + voff[i]));
+  }
+  // cluster maps of every merged step: interiors of all problems first (in
+  // problem order), then their interfaces
+  M.steps.assign(D + 1, StepPlan());
+  std::vector<std::vector<int32_t>> ioff(D + 1, std::vector<int32_t>(np, 0)),
+      foff(D + 1, std::vector<int32_t>(np, 0));
+  auto own = [&](int i, int lm) { return lm - (D - parts[i].depth); };   // problem step
+  for (int lm = 0; lm <= D; ++lm) {
+    StepPlan& S = M.steps[lm];
+    S.l = lm;
+    int nI = 0, nF = 0;
+    for (int i = 0; i < np; ++i) {
+      const int l = own(i, lm);
+      ioff[lm][i] = nI;
+      foff[lm][i] = nF;
+      if (l < 0) continue;
+      nI += parts[i].steps[l].nI;
+      nF += parts[i].steps[l].nc - parts[i].steps[l].nI;
+    }
+    S.nI = nI;
+    S.nc = nI + nF;
+    S.sparsified = lm >= 1 && lm <= D - skip;
+  }
+  auto map = [&](int lm, int i, int c) {
+    const StepPlan& q = parts[i].steps[own(i, lm)];
+    return c < q.nI ? ioff[lm][i] + c : M.steps[lm].nI + foff[lm][i] + (c - q.nI);
+  };
+  for (int lm = 0; lm <= D; ++lm) {
+    StepPlan& S = M.steps[lm];
+    const int nc = S.nc;
+    S.key_lvl.assign(nc, 0);
+    S.key_prefix.assign(nc, 0);
+    S.colour.assign(nc, -1);
+    S.parent.assign(nc, -1);
+    std::vector<std::pair<int, int>> owner(nc);
+    for (int i = 0; i < np; ++i) {
+      const int l = own(i, lm);
+      if (l < 0) continue;
+      const StepPlan& q = parts[i].steps[l];
+      for (int c = 0; c < q.nc; ++c) {
+        const int x = map(lm, i, c);
+        owner[x] = {i, c};
+        S.key_lvl[x] = q.key_lvl[c] + (D - parts[i].depth);
+        S.key_prefix[x] = q.key_prefix[c];
+        S.colour[x] = q.colour[c];
+        if (lm > 0 && !q.parent.empty() && q.parent[c] >= 0 && l > 0)
+          S.parent[x] = map(lm - 1, i, q.parent[c]);
+      }
+    }
+    S.adj_ptr.assign(nc + 1, 0);
+    S.adj.clear();
+    for (int x = 0; x < nc; ++x) {
+      const auto [i, c] = owner[x];
+      const StepPlan& q = parts[i].steps[own(i, lm)];
+      for (int64_t e = q.adj_ptr[c]; e < q.adj_ptr[c + 1]; ++e) S.adj.push_back(map(lm, i, q.adj[e]));
+      S.adj_ptr[x + 1] = (int64_t)S.adj.size();
+    }
+    S.ncolours = 0;
+    for (int x = S.nI; x < nc; ++x) S.ncolours = std::max(S.ncolours, S.colour[x] + 1);
+    S.order.clear();
+    for (int x = S.nI; x < nc; ++x) S.order.push_back(x);
+    std::stable_sort(S.order.begin(), S.order.end(),
+                     [&](int a, int b) { return S.colour[a] < S.colour[b]; });
+    if (lm < D) {   // children in step lm + 1
+      S.child_ptr.assign(nc + 1, 0);
+      S.child.clear();
+      for (int x = 0; x < nc; ++x) {
+        const auto [i, c] = owner[x];
+        const StepPlan& q = parts[i].steps[own(i, lm)];
+        if (!q.child_ptr.empty())
+          for (int64_t e = q.child_ptr[c]; e < q.child_ptr[c + 1]; ++e)
+            S.child.push_back(map(lm + 1, i, q.child[e]));
+        S.child_ptr[x + 1] = (int64_t)S.child.size();
+      }
+    } else {        // leaf step: vertices of every cluster
+      S.vert_ptr.assign(nc + 1, 0);
+      S.verts.clear();
+      for (int x = 0; x < nc; ++x) {
+        const auto [i, c] = owner[x];
+        const StepPlan& q = parts[i].steps[parts[i].depth];
+        for (int64_t e = q.vert_ptr[c]; e < q.vert_ptr[c + 1]; ++e)
+          S.verts.push_back((int32_t)(q.verts[e] + voff[i]));
+        S.vert_ptr[x + 1] = (int64_t)S.verts.size();
+      }
+    }
+  }
+  for (int lm = 0; lm <= D; ++lm) build_numeric_lists(M, lm);
+}
+
+void build_leaf_map(Plan& P) {
+  const int64_t n = P.n;
+  const StepPlan& st0 = P.steps[P.depth];
+  std::vector<int32_t> sizes(st0.nc), cid(n), loc(n);
+  for (int c = 0; c < st0.nc; ++c) {
+    sizes[c] = (int32_t)(st0.vert_ptr[c + 1] - st0.vert_ptr[c]);
+    for (int64_t e = st0.vert_ptr[c]; e < st0.vert_ptr[c + 1]; ++e) {
+      cid[st0.verts[e]] = c;
+      loc[st0.verts[e]] = (int32_t)(e - st0.vert_ptr[c]);
+    }
+  }
+  PanelLayout lay = make_layout(st0, sizes);
+  std::vector<int64_t> dest(P.nnz);
+  for (int64_t v = 0; v < n; ++v) {
+    const int c = cid[v];
+    for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1]; ++e) {
+      const int32_t u = P.colind[e];
+      const int c2 = cid[u];
+      const int32_t* b = st0.adj.data() + st0.adj_ptr[c];
+      const int32_t* en = st0.adj.data() + st0.adj_ptr[c + 1];
+      const int64_t ee = st0.adj_ptr[c] + (std::lower_bound(b, en, c2) - b);
+      dest[e] = lay.off[c] + (lay.coff[ee] + loc[u]) * sizes[c] + loc[v];
+    }
+  }
+  P.leaf_panel_elems = lay.total;
+  P.leaf_dest = std::move(dest);
+  if (P.seg_off.empty()) P.seg_off = {0, n};
+}
+
 PanelLayout make_layout(const StepPlan& st, const std::vector<int32_t>& sizes) {
   PanelLayout L;
   L.n = sizes;

@@ -94,22 +94,28 @@ void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        int32_t max_n, hipStream_t s);
 
-// PCG helpers (all per column j < nrhs; vectors n x nrhs, ld n)
+// PCG helpers.  Vectors are n x nrhs (ld n); the rows are split into nseg
+// segments (independent problems of a batch, seg_off: nseg + 1 offsets on the
+// device, seg_id: the segment of every row, nullptr when nseg == 1), and every
+// scalar is per (segment s, column c), stored at s * nrhs + c.
 void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,
                  int32_t nrhs, const double* x, double* y, hipStream_t s);
-// out[j] = sum_i x[i,j] * y[i,j] (deterministic two-stage reduction)
-void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, double* partial,
-                double* out, hipStream_t s);
-// alpha = rho/pq for active columns; x += alpha p; r -= alpha q
+// out[s, c] = sum_{i in s} x[i,c] * y[i,c] (deterministic two-stage reduction)
+void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, const int64_t* seg_off,
+                int32_t nseg, double* partial, double* out, hipStream_t s);
+// alpha = rho/pq for active (s, c); x += alpha p; r -= alpha q
 void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
-                   const double* pq, const int32_t* active, int64_t n, int32_t nrhs,
-                   hipStream_t s);
-// p = z + (rho_new/rho) p for active columns (p = z when first != 0); rho <- rho_new
+                   const double* pq, const int32_t* active, const int32_t* seg_id, int64_t n,
+                   int32_t nrhs, hipStream_t s);
+// p = z + (rho_new/rho) p for active (s, c) (p = z when first != 0); rho <- rho_new
 void launch_pcg_p(double* p, const double* z, double* rho, const double* rho_new,
-                  const int32_t* active, int64_t n, int32_t nrhs, int32_t first, hipStream_t s);
+                  const int32_t* active, const int32_t* seg_id, int64_t n, int32_t nrhs,
+                  int32_t nseg, int32_t first, hipStream_t s);
 // y = b - y
 void launch_residual(const double* b, double* y, int64_t n, int32_t nrhs, hipStream_t s);
 void launch_copy_vec(const double* src, double* dst, int64_t count, hipStream_t s);
+// blocks per (segment, column) of launch_dot and the size of its partial buffer
+int32_t dot_blocks(int32_t nseg);
 
 constexpr int kDotBlocks = 256;
 

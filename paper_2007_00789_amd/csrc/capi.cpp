@@ -68,6 +68,13 @@ void upload_plan(spand::Plan& P, int device) {
   SPAND_HIP(hipMemcpy(P.d_colind, P.colind.data(), P.nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   SPAND_HIP(hipMemcpy(P.d_leaf_dest, P.leaf_dest.data(), P.nnz * sizeof(int64_t),
                       hipMemcpyHostToDevice));
+  SPAND_HIP(hipMalloc(&P.d_seg_off, P.seg_off.size() * sizeof(int64_t)));
+  SPAND_HIP(hipMemcpy(P.d_seg_off, P.seg_off.data(), P.seg_off.size() * sizeof(int64_t),
+                      hipMemcpyHostToDevice));
+  if (!P.seg_id.empty()) {
+    SPAND_HIP(hipMalloc(&P.d_seg_id, P.n * sizeof(int32_t)));
+    SPAND_HIP(hipMemcpy(P.d_seg_id, P.seg_id.data(), P.n * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
 }
 
 }  // namespace
@@ -159,34 +166,50 @@ spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, co
     spand::Plan& P = plan->p;
     P.n = n;
     spand::analyze_plan(P, rowptr, colind, coords, dim, depth, opts->skip);
-    // leaf-step panel layout and the destination of every CSR value in it
-    const spand::StepPlan& st0 = P.steps[P.depth];
-    std::vector<int32_t> sizes(st0.nc), cid(n), loc(n);
-    for (int c = 0; c < st0.nc; ++c) {
-      sizes[c] = (int32_t)(st0.vert_ptr[c + 1] - st0.vert_ptr[c]);
-      for (int64_t e = st0.vert_ptr[c]; e < st0.vert_ptr[c + 1]; ++e) {
-        cid[st0.verts[e]] = c;
-        loc[st0.verts[e]] = (int32_t)(e - st0.vert_ptr[c]);
-      }
-    }
-    spand::PanelLayout lay = spand::make_layout(st0, sizes);
-    std::vector<int64_t> dest(P.nnz);
-    for (int64_t v = 0; v < n; ++v) {
-      const int c = cid[v];
-      for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1]; ++e) {
-        const int32_t u = P.colind[e];
-        const int c2 = cid[u];
-        const int32_t* b = st0.adj.data() + st0.adj_ptr[c];
-        const int32_t* en = st0.adj.data() + st0.adj_ptr[c + 1];
-        const int64_t ee = st0.adj_ptr[c] + (std::lower_bound(b, en, c2) - b);
-        dest[e] = lay.off[c] + (lay.coff[ee] + loc[u]) * sizes[c] + loc[v];
-      }
-    }
-    P.leaf_panel_elems = lay.total;
-    P.leaf_dest = std::move(dest);
+    spand::build_leaf_map(P);
   });
   if (st == SPAND_OK) *out = plan.release();
   return st;
+}
+
+spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* n,
+                                 const int64_t* const* rowptr, const int32_t* const* colind,
+                                 const double* const* coords, const int32_t* dim,
+                                 const int32_t* depth, const spand_opts* opts, spand_plan_t* out) {
+  if (!out) return SPAND_E_INVALID;
+  *out = nullptr;
+  auto plan = std::make_unique<spand_plan_s>();
+  spand_status st = guarded(ctx, [&] {
+    using spand::Error;
+    check_opts(opts);
+    if (count < 1 || !n || !rowptr || !colind || !coords || !dim)
+      throw Error(SPAND_E_INVALID, "bad batch arguments");
+    std::vector<spand::Plan> parts((size_t)count);   // sized once: plans are not moved
+    for (int i = 0; i < count; ++i) {
+      if (n[i] <= 0 || !rowptr[i] || !colind[i] || !coords[i] || dim[i] < 1 || dim[i] > 3)
+        throw Error(SPAND_E_INVALID, "bad matrix or coordinates of problem " + std::to_string(i));
+      if (rowptr[i][0] != 0 || rowptr[i][n[i]] < 0)
+        throw Error(SPAND_E_INVALID, "bad rowptr of problem " + std::to_string(i));
+      int d = depth ? depth[i] : opts->depth;
+      if (d <= 0) d = std::max(0, (int)std::lround(std::log2((double)n[i] / 64.0)));
+      if (d > 40) throw Error(SPAND_E_INVALID, "depth too large");
+      parts[i].n = n[i];
+      spand::analyze_plan(parts[i], rowptr[i], colind[i], coords[i], dim[i], d, opts->skip);
+    }
+    spand::Plan& P = plan->p;
+    spand::merge_plans(P, parts, opts->skip);
+    spand::build_leaf_map(P);
+  });
+  if (st == SPAND_OK) *out = plan.release();
+  return st;
+}
+
+spand_status spand_plan_segments(spand_plan_t plan, int32_t* count, int64_t* offsets) {
+  if (!plan || !count) return SPAND_E_INVALID;
+  const auto& so = plan->p.seg_off;
+  *count = (int32_t)so.size() - 1;
+  if (offsets) std::copy(so.begin(), so.end(), offsets);
+  return SPAND_OK;
 }
 
 void spand_destroy_plan(spand_plan_t plan) { delete plan; }

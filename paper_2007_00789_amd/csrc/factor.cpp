@@ -146,6 +146,8 @@ Plan::~Plan() {
   if (d_rowptr) (void)hipFree(d_rowptr);
   if (d_colind) (void)hipFree(d_colind);
   if (d_leaf_dest) (void)hipFree(d_leaf_dest);
+  if (d_seg_id) (void)hipFree(d_seg_id);
+  if (d_seg_off) (void)hipFree(d_seg_off);
 }
 
 namespace {

@@ -87,11 +87,25 @@ struct Plan {
   std::vector<int64_t> leaf_dest;      // host copy of the same map
   int64_t leaf_panel_elems = 0;
   std::vector<int64_t> leaf_panel_off; // per leaf-step cluster
+  // independent problems of a batch plan: problem s owns rows seg_off[s] ..
+  // seg_off[s+1]-1 (one segment for a single problem)
+  std::vector<int64_t> seg_off;
+  std::vector<int32_t> seg_id;         // segment of every row (batch plans only)
+  int32_t* d_seg_id = nullptr;
+  int64_t* d_seg_off = nullptr;
   ~Plan();
 };
 
 void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const double* coords,
                   int dim, int depth, int skip);
+// One plan for independent problems (a block-diagonal system): problem i's
+// rows follow those of problems < i, and its own step l becomes step
+// l + (D - D_i) with D the largest depth, so every problem keeps its own
+// levels, and the rule 1 <= l <= D_i - skip for sparsified steps becomes
+// 1 <= l' <= D - skip for all of them.
+void merge_plans(Plan& M, std::vector<Plan>& parts, int skip);
+// destination of every CSR value in the leaf-step row panels
+void build_leaf_map(Plan& P);
 
 // Layout of one step's row panels: cluster c holds rows n[c] x width[c] in
 // column-major order (ld = n[c]) at offset off[c]; the block (c, adj[e]) starts

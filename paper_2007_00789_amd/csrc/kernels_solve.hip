@@ -1,6 +1,8 @@
 // HIP kernels of the preconditioner apply and of PCG (FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "apply.h"
 
 namespace spand {
@@ -513,53 +515,60 @@ __global__ void k_spmv(const int64_t* rowptr, const int32_t* colind, const doubl
   }
 }
 
+// block (b, s, c) sums its chunk of segment s, column c
 __global__ __launch_bounds__(kT) void k_dot_partial(const double* x, const double* y, int64_t n,
-                                                    double* partial) {
+                                                    const int64_t* seg_off, double* partial) {
   __shared__ double red[kT / kWave];
-  const int r = blockIdx.y;
-  const double* xr = x + r * n;
-  const double* yr = y + r * n;
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t b = blockIdx.x * chunk, e = min(n, b + chunk);
+  const int b = blockIdx.x, sg = blockIdx.y, c = blockIdx.z, bps = gridDim.x;
+  const int nrhs = gridDim.z;
+  const double* xr = x + (int64_t)c * n;
+  const double* yr = y + (int64_t)c * n;
+  const int64_t o0 = seg_off[sg], o1 = seg_off[sg + 1];
+  const int64_t chunk = (o1 - o0 + bps - 1) / bps;
+  const int64_t lo = o0 + (int64_t)b * chunk, hi = min(o1, lo + chunk);
   double acc = 0.0;
-  for (int64_t i = b + threadIdx.x; i < e; i += kT) acc = fma(xr[i], yr[i], acc);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kT) acc = fma(xr[i], yr[i], acc);
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x + (int64_t)r * gridDim.x] = acc;
+  if (threadIdx.x == 0) partial[((int64_t)sg * nrhs + c) * bps + b] = acc;
 }
 
-__global__ void k_dot_final(const double* partial, int nparts, double* out) {
-  if (threadIdx.x != 0) return;
-  const int r = blockIdx.x;
+__global__ void k_dot_final(const double* partial, int bps, int count, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
   double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += partial[i + (int64_t)r * nparts];
-  out[r] = s;
+  for (int i = 0; i < bps; ++i) s += partial[(int64_t)e * bps + i];
+  out[e] = s;
 }
 
 __global__ void k_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
-                         const double* pq, const int32_t* active, int64_t n, int nrhs) {
+                         const double* pq, const int32_t* active, const int32_t* seg_id, int64_t n,
+                         int nrhs) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * nrhs;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(idx / n);
-    if (!active[c]) continue;
-    const double alpha = rho[c] / pq[c];
+    const int e = (seg_id ? seg_id[idx - (int64_t)c * n] : 0) * nrhs + c;
+    if (!active[e]) continue;
+    const double alpha = rho[e] / pq[e];
     x[idx] = fma(alpha, p[idx], x[idx]);
     r[idx] = fma(-alpha, q[idx], r[idx]);
   }
 }
 
 __global__ void k_pcg_p(double* p, const double* z, const double* rho, const double* rho_new,
-                        const int32_t* active, int64_t n, int nrhs, int first) {
+                        const int32_t* active, const int32_t* seg_id, int64_t n, int nrhs,
+                        int first) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * nrhs;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(idx / n);
-    if (!active[c]) continue;
-    p[idx] = first ? z[idx] : fma(rho_new[c] / rho[c], p[idx], z[idx]);
+    const int e = (seg_id ? seg_id[idx - (int64_t)c * n] : 0) * nrhs + c;
+    if (!active[e]) continue;
+    p[idx] = first ? z[idx] : fma(rho_new[e] / rho[e], p[idx], z[idx]);
   }
 }
 
-__global__ void k_copy_rho(double* rho, const double* rho_new, const int32_t* active, int nrhs) {
-  const int c = threadIdx.x;
-  if (c < nrhs && active[c]) rho[c] = rho_new[c];
+__global__ void k_copy_rho(double* rho, const double* rho_new, const int32_t* active, int count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count && active[e]) rho[e] = rho_new[e];
 }
 
 __global__ void k_residual(const double* b, double* y, int64_t count) {
@@ -640,22 +649,28 @@ void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* val
   hipLaunchKernelGGL(k_spmv, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colind, vals, n, nrhs,
                      x, y);
 }
-void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, double* partial,
-                double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, nrhs), dim3(kT), 0, s, x, y, n, partial);
-  hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(64), 0, s, partial, kDotBlocks, out);
+int32_t dot_blocks(int32_t nseg) { return std::max(1, kDotBlocks / std::max(nseg, 1)); }
+
+void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, const int64_t* seg_off,
+                int32_t nseg, double* partial, double* out, hipStream_t s) {
+  const int bps = dot_blocks(nseg);
+  hipLaunchKernelGGL(k_dot_partial, dim3(bps, nseg, nrhs), dim3(kT), 0, s, x, y, n, seg_off, partial);
+  const int count = nseg * nrhs;
+  hipLaunchKernelGGL(k_dot_final, dim3((count + 63) / 64), dim3(64), 0, s, partial, bps, count, out);
 }
 void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
-                   const double* pq, const int32_t* active, int64_t n, int32_t nrhs,
-                   hipStream_t s) {
+                   const double* pq, const int32_t* active, const int32_t* seg_id, int64_t n,
+                   int32_t nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_xr, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, s, x, r, p, q, rho, pq,
-                     active, n, nrhs);
+                     active, seg_id, n, nrhs);
 }
 void launch_pcg_p(double* p, const double* z, double* rho, const double* rho_new,
-                  const int32_t* active, int64_t n, int32_t nrhs, int32_t first, hipStream_t s) {
+                  const int32_t* active, const int32_t* seg_id, int64_t n, int32_t nrhs,
+                  int32_t nseg, int32_t first, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, s, p, z, rho, rho_new,
-                     active, n, nrhs, first);
-  hipLaunchKernelGGL(k_copy_rho, dim3(1), dim3(64), 0, s, rho, rho_new, active, nrhs);
+                     active, seg_id, n, nrhs, first);
+  const int count = nseg * nrhs;
+  hipLaunchKernelGGL(k_copy_rho, dim3((count + 63) / 64), dim3(64), 0, s, rho, rho_new, active, count);
 }
 void launch_residual(const double* b, double* y, int64_t n, int32_t nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_residual, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, s, b, y, n * nrhs);

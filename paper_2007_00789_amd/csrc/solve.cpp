@@ -290,75 +290,81 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
 
 void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const double* b, double* x,
              double tol, int32_t maxit, int32_t* iters, double* relres, bool* converged) {
+  // one CG run per (segment, column): the segments are the independent
+  // problems of a batch plan (one segment otherwise)
   hipStream_t s = C.stream;
   const Plan& P = *F.plan;
   const int64_t n = P.n;
   const int64_t nv = n * nrhs;
+  const int32_t nseg = (int32_t)P.seg_off.size() - 1;
+  const int32_t ne = nseg * nrhs;
+  const int32_t* seg_id = nseg > 1 ? P.d_seg_id : nullptr;
   DevArena work;
   double* r = work.alloc_n<double>(nv);
   double* z = work.alloc_n<double>(nv);
   double* p = work.alloc_n<double>(nv);
   double* q = work.alloc_n<double>(nv);
-  double* partial = work.alloc_n<double>((size_t)kDotBlocks * nrhs);
-  double* sc = work.alloc_n<double>(4 * (size_t)nrhs);  // rho | rho_new | pq | rr
+  double* partial = work.alloc_n<double>((size_t)dot_blocks(nseg) * ne);
+  double* sc = work.alloc_n<double>(4 * (size_t)ne);  // rho | rho_new | pq | rr
   double* rho = sc;
-  double* rho_new = sc + nrhs;
-  double* pq = sc + 2 * nrhs;
-  double* rr = sc + 3 * nrhs;
-  int32_t* active = work.alloc_n<int32_t>(nrhs);
-  std::vector<int32_t> h_active(nrhs, 1);
-  std::vector<double> h_bn(nrhs), h_rr(nrhs);
+  double* rho_new = sc + ne;
+  double* pq = sc + 2 * ne;
+  double* rr = sc + 3 * ne;
+  int32_t* active = work.alloc_n<int32_t>(ne);
+  std::vector<int32_t> h_active(ne, 1);
+  std::vector<double> h_bn(ne), h_rr(ne);
 
-  SPAND_PROF(C, "k_dot", launch_dot(b, b, n, nrhs, partial, rr, s));
-  SPAND_HIP(hipMemcpyAsync(h_bn.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPAND_PROF(C, "k_dot", launch_dot(b, b, n, nrhs, P.d_seg_off, nseg, partial, rr, s));
+  SPAND_HIP(hipMemcpyAsync(h_bn.data(), rr, ne * sizeof(double), hipMemcpyDeviceToHost, s));
   SPAND_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < nrhs; ++c) {
-    h_bn[c] = std::sqrt(h_bn[c]);
-    iters[c] = 0;
-    if (h_bn[c] == 0.0) h_active[c] = 0;
+  for (int e = 0; e < ne; ++e) {
+    h_bn[e] = std::sqrt(h_bn[e]);
+    iters[e] = 0;
+    if (h_bn[e] == 0.0) h_active[e] = 0;
   }
   SPAND_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
-  SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SPAND_HIP(hipMemcpyAsync(active, h_active.data(), ne * sizeof(int32_t), hipMemcpyHostToDevice, s));
   SPAND_PROF(C, "k_copy_vec", launch_copy_vec(b, r, nv, s));
   run_apply(C, F, nrhs, r, z);
-  SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, partial, rho_new, s));
-  SPAND_PROF(C, "k_pcg_p", launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 1, s));
+  SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, P.d_seg_off, nseg, partial, rho_new, s));
+  SPAND_PROF(C, "k_pcg_p",
+             launch_pcg_p(p, z, rho, rho_new, active, seg_id, n, nrhs, nseg, 1, s));
   int nact = 0;
-  for (int c = 0; c < nrhs; ++c) nact += h_active[c];
+  for (int e = 0; e < ne; ++e) nact += h_active[e];
   for (int it = 1; it <= maxit && nact > 0; ++it) {
     SPAND_PROF(C, "k_spmv", launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, p, q, s));
-    SPAND_PROF(C, "k_dot", launch_dot(p, q, n, nrhs, partial, pq, s));
-    SPAND_PROF(C, "k_pcg_xr", launch_pcg_xr(x, r, p, q, rho, pq, active, n, nrhs, s));
-    SPAND_PROF(C, "k_dot", launch_dot(r, r, n, nrhs, partial, rr, s));
-    SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    SPAND_PROF(C, "k_dot", launch_dot(p, q, n, nrhs, P.d_seg_off, nseg, partial, pq, s));
+    SPAND_PROF(C, "k_pcg_xr", launch_pcg_xr(x, r, p, q, rho, pq, active, seg_id, n, nrhs, s));
+    SPAND_PROF(C, "k_dot", launch_dot(r, r, n, nrhs, P.d_seg_off, nseg, partial, rr, s));
+    SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, ne * sizeof(double), hipMemcpyDeviceToHost, s));
     SPAND_HIP(hipStreamSynchronize(s));
     bool changed = false;
-    for (int c = 0; c < nrhs; ++c)
-      if (h_active[c] && std::sqrt(h_rr[c]) < tol * h_bn[c]) {
-        h_active[c] = 0;
-        iters[c] = it;
+    for (int e = 0; e < ne; ++e)
+      if (h_active[e] && std::sqrt(h_rr[e]) < tol * h_bn[e]) {
+        h_active[e] = 0;
+        iters[e] = it;
         --nact;
         changed = true;
-      } else if (h_active[c]) {
-        iters[c] = it;
+      } else if (h_active[e]) {
+        iters[e] = it;
       }
     if (nact == 0) break;
     if (changed)
-      SPAND_HIP(hipMemcpyAsync(active, h_active.data(), nrhs * sizeof(int32_t),
+      SPAND_HIP(hipMemcpyAsync(active, h_active.data(), ne * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
     run_apply(C, F, nrhs, r, z);
-    SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, partial, rho_new, s));
-    SPAND_PROF(C, "k_pcg_p", launch_pcg_p(p, z, rho, rho_new, active, n, nrhs, 0, s));
+    SPAND_PROF(C, "k_dot", launch_dot(r, z, n, nrhs, P.d_seg_off, nseg, partial, rho_new, s));
+    SPAND_PROF(C, "k_pcg_p",
+               launch_pcg_p(p, z, rho, rho_new, active, seg_id, n, nrhs, nseg, 0, s));
   }
   // true residual
   SPAND_PROF(C, "k_spmv", launch_spmv(P.d_rowptr, P.d_colind, d_vals, n, nrhs, x, q, s));
   SPAND_PROF(C, "k_residual", launch_residual(b, q, n, nrhs, s));
-  SPAND_PROF(C, "k_dot", launch_dot(q, q, n, nrhs, partial, rr, s));
-  SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPAND_PROF(C, "k_dot", launch_dot(q, q, n, nrhs, P.d_seg_off, nseg, partial, rr, s));
+  SPAND_HIP(hipMemcpyAsync(h_rr.data(), rr, ne * sizeof(double), hipMemcpyDeviceToHost, s));
   SPAND_HIP(hipStreamSynchronize(s));
   *converged = nact == 0;
-  for (int c = 0; c < nrhs; ++c)
-    relres[c] = h_bn[c] > 0 ? std::sqrt(h_rr[c]) / h_bn[c] : 0.0;
+  for (int e = 0; e < ne; ++e) relres[e] = h_bn[e] > 0 ? std::sqrt(h_rr[e]) / h_bn[e] : 0.0;
 }
 
 }  // namespace spand

@@ -64,6 +64,10 @@ SIGNATURES = {
     "spand_analyze": (C.c_int, [_P, C.c_int64, _I64P, _I32P, _DP, C.c_int32, C.POINTER(Opts),
                                 C.POINTER(_P)]),
     "spand_destroy_plan": (None, [_P]),
+    "spand_analyze_batch": (C.c_int, [_P, C.c_int32, _I64P, C.POINTER(_I64P), C.POINTER(_I32P),
+                                      C.POINTER(_DP), _I32P, _I32P, C.POINTER(Opts),
+                                      C.POINTER(_P)]),
+    "spand_plan_segments": (C.c_int, [_P, _I32P, _I64P]),
     "spand_plan_sizes": (C.c_int, [_P, _I64P, _I64P, _I32P]),
     "spand_plan_vertices": (C.c_int, [_P, _I32P, _I64P, _I64P]),
     "spand_plan_step_counts": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I64P, _I64P, _I32P]),
@@ -180,13 +184,17 @@ class Context:
         self._check(self.lib.spand_apply(self.h, fac.h, int(nrhs), _ptr(x), _ptr(y)))
 
     def pcg(self, fac: "Factor", nrhs: int, b, x, tol=1e-10, maxit=1000, check=True):
-        """spand_pcg; returns (iters, relres) numpy arrays."""
-        it = np.zeros(nrhs, dtype=np.int32)
-        rr = np.zeros(nrhs, dtype=np.float64)
+        """spand_pcg; returns (iters, relres) numpy arrays of nrhs entries, or of
+        (problems, nrhs) for a batch plan."""
+        nseg = fac.plan.segments()[0]
+        it = np.zeros(nseg * nrhs, dtype=np.int32)
+        rr = np.zeros(nseg * nrhs, dtype=np.float64)
         st = self.lib.spand_pcg(self.h, fac.h, int(nrhs), _ptr(b), _ptr(x), float(tol), int(maxit),
                                 it.ctypes.data_as(_I32P), rr.ctypes.data_as(_DP))
         if check or st not in (SPAND_OK, -4):
             self._check(st)
+        if nseg > 1:
+            return it.reshape(nseg, nrhs), rr.reshape(nseg, nrhs)
         return it, rr
 
 
@@ -206,6 +214,39 @@ def analyze(n, rowptr, colind, coords, opts: Opts, ctx: Context | None = None) -
     return Plan(lib, h)
 
 
+def analyze_batch(problems, opts: Opts, ctx: Context | None = None, depths=None) -> "Plan":
+    """spand_analyze_batch: problems is a list of (n, rowptr, colind, coords);
+    depths an optional list of per-problem depths (default: opts.depth rule)."""
+    lib = load()
+    keep = []
+    cnt = len(problems)
+    ns = np.ascontiguousarray([int(p[0]) for p in problems], dtype=np.int64)
+    rp_arr = (_I64P * cnt)()
+    ci_arr = (_I32P * cnt)()
+    xy_arr = (_DP * cnt)()
+    dims = np.zeros(cnt, dtype=np.int32)
+    for i, (n, rowptr, colind, coords) in enumerate(problems):
+        rp, rp_p = _np(rowptr, np.int64)
+        ci, ci_p = _np(colind, np.int32)
+        xy, xy_p = _np(coords, np.float64)
+        keep += [rp, ci, xy]
+        rp_arr[i], ci_arr[i], xy_arr[i] = rp_p, ci_p, xy_p
+        dims[i] = 1 if xy.ndim == 1 else xy.shape[1]
+    dp = None
+    if depths is not None:
+        dpa = np.ascontiguousarray(depths, dtype=np.int32)
+        keep.append(dpa)
+        dp = dpa.ctypes.data_as(_I32P)
+    h = C.c_void_p()
+    st = lib.spand_analyze_batch(ctx.h if ctx else None, cnt, ns.ctypes.data_as(_I64P), rp_arr,
+                                 ci_arr, xy_arr, dims.ctypes.data_as(_I32P), dp, C.byref(opts),
+                                 C.byref(h))
+    if st != SPAND_OK:
+        msg = lib.spand_last_error(ctx.h).decode() if ctx else ""
+        raise SpandError(st, msg or "spand_analyze_batch failed")
+    return Plan(lib, h)
+
+
 class Plan:
     def __init__(self, lib, h):
         self.lib, self.h = lib, h
@@ -219,6 +260,14 @@ class Plan:
             self.h = None
 
     __del__ = close
+
+    def segments(self):
+        """(count, offsets[count+1]) of the plan's independent problems."""
+        cnt = C.c_int32()
+        self.lib.spand_plan_segments(self.h, C.byref(cnt), None)
+        off = np.zeros(cnt.value + 1, np.int64)
+        self.lib.spand_plan_segments(self.h, C.byref(cnt), off.ctypes.data_as(_I64P))
+        return cnt.value, off
 
     def vertices(self):
         lvl = np.zeros(self.n, np.int32)
