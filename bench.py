@@ -109,6 +109,79 @@ def measured_traffic(kernel):
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
+def bench_batch(args):
+    """Batch workload: 256 independent problems (128 2D Laplacians, side
+    U{32..256}; 128 anisotropic 3D operators, side U{16..48}, axis weights
+    (1, 1e-2, 1e2)), each with its own depth round(log2(n/64)), eps 1e-2, SO,
+    one N(0,1) right-hand side (seed 3000 + j), PCG to 1e-10.  One step =
+    spand_factor + spand_pcg of the whole batch in the same launches."""
+    import torch
+    from paper_2007_00789_amd import spand
+    from synthetic import batch_problems, rhs
+
+    probs = batch_problems()
+    tol = 1e-10
+    opts = spand.make_opts(depth=0, skip=4, eps=args.eps, scheme=args.scheme)
+    ctx = spand.Context(0)
+    t0 = time.perf_counter()
+    plan = spand.analyze_batch([(p.n, p.rowptr, p.colind, p.coords) for p in probs], opts, ctx)
+    analyze_s = time.perf_counter() - t0
+    vals = torch.from_numpy(np.concatenate([p.vals for p in probs])).to("cuda:0")
+    b = torch.from_numpy(np.concatenate([rhs(p.n, 1, 3000 + j)[:, 0] for j, p in enumerate(probs)])).to("cuda:0")
+    x = torch.zeros_like(b)
+
+    def step():
+        t = time.perf_counter()
+        fac = ctx.factor(plan, vals, opts)
+        tf = time.perf_counter() - t
+        it, rr = ctx.pcg(fac, 1, b, x, tol, 1000)
+        ts = time.perf_counter() - t - tf
+        info = fac.info()
+        fac.close()
+        return tf, ts, it, rr, info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    facs, sols = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        tf, ts, it, rr, info = step()
+        facs.append(tf)
+        sols.append(ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    assert np.all(rr < 10 * tol), rr.max()
+    nnz = sum(p.nnz for p in probs)
+    out = {
+        "metric": "PCG solves/s to 1e-10 rel. residual (batch of independent problems)",
+        "value": len(probs) * args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(probs)} problems: 128 2D 5-point Laplacians side "
+                               f"U{{32..256}}, 128 3D anisotropic (1, 1e-2, 1e2) side U{{16..48}}; "
+                               f"n={plan.n}, eps {args.eps:g}, {args.scheme}, FP64, 1 RHS each, "
+                               f"PCG tol {tol:g}",
+                   "global_batch": len(probs), "parallelism": "single GPU"},
+        "factor_ms": 1e3 * float(np.mean(facs)),
+        "solve_ms": 1e3 * float(np.mean(sols)),
+        "n_cg_max": int(it.max()), "n_cg_mean": float(it.mean()),
+        "relres_max": float(rr.max()),
+        "mu": info["nnz_L"] / nnz,
+        "factor_gflop": info["flops"] / 1e9,
+        "analyze_s": analyze_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +208,9 @@ def main():
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
               "(see DESIGN.md for how it would shard); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch256":
+        return bench_batch(args)
 
     import torch
     from paper_2007_00789_amd import spand

@@ -12,5 +12,6 @@ from .problems import (  # noqa: F401
     high_contrast_2d,
     rhs,
     workload,
+    batch_problems,
     WORKLOADS,
 )

@@ -201,6 +201,19 @@ WORKLOADS = {
 }
 
 
+def batch_problems(count2d: int = 128, count3d: int = 128, seed: int = 3000):
+    """Independent problems of the batch workload: count2d 2D 5-point
+    Laplacians with side ~ U{32..256} and count3d anisotropic 3D 7-point
+    operators with side ~ U{16..48} and axis weights (1, 1e-2, 1e2), sides
+    drawn from numpy.random.default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    s2 = rng.integers(32, 257, size=count2d)
+    s3 = rng.integers(16, 49, size=count3d)
+    probs = [laplacian_2d(int(d)) for d in s2]
+    probs += [laplacian_3d(int(d), weights=(1.0, 1e-2, 1e2)) for d in s3]
+    return probs
+
+
 def workload(name: str):
     """Return (problem, settings dict) of a named workload."""
     w = dict(WORKLOADS[name])
