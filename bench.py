@@ -1,7 +1,7 @@
 """Benchmark of the spaND hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps 1e-2] [--scheme SO]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--workload lap3d_64|lap2d_64|fv3d_128|batch256|serve]
 
 Workload (the metric's configuration that fits one GPU): 3D 7-point Laplacian
 on a 64^3 grid (n = 262,144), nested-dissection depth 12, skip 4, eps 1e-2,
@@ -182,6 +182,92 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Serving workload: a stream of solve requests with Poisson arrivals at
+    50 per second; 3D FV diffusion matrices with side U{32..96} and k = 10^u,
+    u ~ U[-2,2] per cell; 1..16 N(0,1) right-hand sides per request; about 30%
+    of the requests reuse the matrix of an earlier one (synthetic.serve_stream).
+    Requests are submitted at their arrival times to the library's server
+    (spand_server_*: continuous batching of new matrices into one analysis and
+    factorization per slot, resident factors, one PCG per factor and slot).
+    One step = one request; value = right-hand sides solved to 1e-10 per second
+    over the stream's makespan (first arrival to last completion)."""
+    import torch
+    from paper_2007_00789_amd import spand
+    from synthetic import serve_stream, fv_diffusion_3d, laplacian_3d, rhs
+
+    tol = 1e-10
+    stream = serve_stream(count=args.serve_count)
+    mats = {}
+    for r in stream:
+        if r["key"] not in mats:
+            mats[r["key"]] = fv_diffusion_3d(r["side"], r["umax"], r["mseed"])
+    bs = [rhs(mats[r["key"]].n, r["nrhs"], r["rhs_seed"]) for r in stream]
+    opts = spand.make_opts(depth=0, skip=4, eps=args.eps, scheme=args.scheme)
+    # warm-up: load the device code once, outside the stream
+    w = laplacian_3d(16)
+    with spand.Server(opts, tol=tol, slots=1) as srv:
+        srv.result(srv.submit(-1, rhs(w.n, 1, 1), (w.n, w.rowptr, w.colind, w.coords, w.vals)))
+    torch.cuda.synchronize()
+    seen = set()
+    handles, t_sub = [], []
+    with spand.Server(opts, tol=tol, maxit=1000, max_bytes=args.serve_bytes << 30,
+                      slots=args.serve_slots, max_batch=args.serve_batch) as srv:
+        t0 = time.perf_counter()
+        for r, b in zip(stream, bs):
+            delay = t0 + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            key = r["side"] * 1_000_000 + r["mseed"]
+            m = mats[r["key"]]
+            mat = None if key in seen else (m.n, m.rowptr, m.colind, m.coords, m.vals)
+            seen.add(key)
+            t_sub.append(time.perf_counter())
+            handles.append(srv.submit(key, b, mat))
+        res = [srv.result(h, check=False) for h in handles]
+        stats = srv.stats()
+    lat = np.array([q[3] for q in res])
+    done = np.array(t_sub) + lat
+    makespan = float(done.max() - t0)
+    cols = sum(r["nrhs"] for r in stream)
+    iters = np.concatenate([q[1] for q in res])
+    rel = np.concatenate([q[2] for q in res])
+    assert all(q[4] == spand.SPAND_OK for q in res), [q[4] for q in res]
+    assert np.all(rel < 10 * tol), rel.max()
+    n_reuse = len(stream) - len(mats)
+    out = {
+        "metric": "PCG solves/s to 1e-10 rel. residual; p50/p99 request latency (serving stream)",
+        "value": cols / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(stream),
+        "warmup": 1,
+        "ms_per_step": 1e3 * makespan / len(stream),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream of {len(stream)} requests, Poisson arrivals at 50/s; "
+                               f"3D FV diffusion side U{{32..96}}, k = 10^U[-2,2]; 1-16 RHS N(0,1); "
+                               f"{n_reuse} requests reuse a factor; eps {args.eps:g}, {args.scheme}, "
+                               f"FP64, PCG tol {tol:g}; {args.serve_slots} slots, "
+                               f"batch <= {args.serve_batch}, budget {args.serve_bytes} GiB",
+                   "global_batch": len(stream), "parallelism": "single GPU"},
+        "requests_per_s": len(stream) / makespan,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_mean_s": float(lat.mean()),
+        "arrival_span_s": float(stream[-1]["t"]),
+        "makespan_s": makespan,
+        "rhs_total": cols,
+        "n_cg_max": int(iters.max()), "n_cg_mean": float(iters.mean()),
+        "relres_max": float(rel.max()),
+        "server": stats,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +277,10 @@ def main():
     ap.add_argument("--scheme", default="SO")
     ap.add_argument("--workload", default="lap3d_64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=48, help="requests of the serving stream")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=16)
+    ap.add_argument("--serve-bytes", type=int, default=200, help="factor budget, GiB")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -211,6 +301,8 @@ def main():
 
     if args.workload == "batch256":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_2007_00789_amd import spand

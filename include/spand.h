@@ -150,7 +150,8 @@ typedef struct {
 } spand_factor_stats;
 spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st);
 
-/* y = M x for nrhs columns; x, y: device pointers, n x nrhs column-major. */
+/* y = M x for nrhs columns; x, y: device pointers, n x nrhs column-major (any
+ * nrhs: columns are processed in chunks that fit the kernels' LDS). */
 spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y);
 
 /* PCG (Sec. 4): x0 = 0, stop when ||r_k||_2 < tol ||b||_2 per column and, for
@@ -161,6 +162,52 @@ spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const 
  * SPAND_E_NO_CONVERGENCE if a run reaches maxit. */
 spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* b, double* x,
                        double tol, int32_t maxit, int32_t* iters, double* relres);
+
+/* Serving (a project addition around the method): a request loop on one
+ * device.  Requests are solves A x = b with nrhs columns; a request names its
+ * matrix by a caller-chosen key, and the first request with a key brings the
+ * matrix (n, rowptr, colind, coords, dim, vals as for spand_analyze and
+ * spand_factor, but vals is a HOST array; all copied at submit; later requests
+ * with that key pass n = 0 or the same n and NULL matrix pointers).  `slots`
+ * worker threads (1..16), each with its own context and stream, admit waiting
+ * requests continuously: a slot takes up to max_batch of them, analyses and
+ * factors the new matrices among them as one batch (spand_analyze_batch),
+ * keeps those factors resident for later requests with the same keys, and
+ * solves all its requests on one factor with one spand_pcg call (tol, maxit;
+ * x0 = 0).  Factors whose device footprint would exceed max_bytes are not
+ * admitted until least recently used idle factors have been released (their
+ * host copies stay, and a later request re-factors); a single matrix larger
+ * than the budget is admitted when nothing else is resident.  The result of a
+ * request does not depend on the other requests it was batched with: each
+ * problem's factor is the one spand_factor gives it alone, and each column is
+ * its own CG run.  Factorizations of different slots run one at a time on the
+ * device; analysis, transfers and PCG overlap. */
+typedef struct spand_server_s* spand_server_t;
+spand_status spand_server_create(int32_t device, const spand_opts* opts, double tol, int32_t maxit,
+                                 int64_t max_bytes, int32_t slots, int32_t max_batch,
+                                 spand_server_t* out);
+/* Queues a request; b: host, n x nrhs column-major (copied).  *req_id
+ * receives its id.  SPAND_E_INVALID for a new key without its matrix or an n
+ * that differs from the key's. */
+spand_status spand_server_submit(spand_server_t srv, int64_t key, int64_t n, const int64_t* rowptr,
+                                 const int32_t* colind, const double* coords, int32_t dim,
+                                 const double* vals, int32_t nrhs, const double* b,
+                                 int64_t* req_id);
+/* Result of a request: wait = 1 blocks until it is done.  *done = 0: still
+ * queued or running (nothing else written).  *done = 1: x (n x nrhs), iters
+ * and relres (nrhs, as for spand_pcg) and latency (seconds from submit to
+ * completion) are written (any may be NULL), the request is forgotten, and the
+ * status is the request's own (SPAND_E_NO_CONVERGENCE if a column reached
+ * maxit; x is still written then). */
+spand_status spand_server_poll(spand_server_t srv, int64_t req_id, int32_t wait, int32_t* done,
+                               double* x, int32_t* iters, double* relres, double* latency);
+/* counters[6]: resident factor bytes, resident factors, queued requests,
+ * factorization batches run, matrices factored, PCG calls. */
+spand_status spand_server_stats(spand_server_t srv, int64_t* counters);
+/* Last error message of a slot ("" if none). */
+const char* spand_server_error(spand_server_t srv);
+/* Finishes every queued request, then stops the slots and frees the factors. */
+void spand_server_destroy(spand_server_t srv);
 
 /* Per-kernel timing (for measurement).  spand_profile(ctx, 1) clears the
  * counters and starts recording a HIP event pair on the context stream around

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspand.so")
 ARCH = os.environ.get("SPAND_ARCH", "gfx950")
 
-SOURCES = ["analyze.cpp", "factor.cpp", "solve.cpp", "capi.cpp",
+SOURCES = ["analyze.cpp", "factor.cpp", "solve.cpp", "capi.cpp", "server.cpp",
            "kernels_factor.hip", "kernels_qr_coop.hip", "kernels_qr_reg.hip",
            "kernels_solve.hip"]
 
@@ -45,7 +45,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,4 +1,9 @@
 // C ABI of libspand: argument checking, error translation and object lifetime.
+#include <algorithm>
+#include <atomic>
+#include <exception>
+#include <thread>
+#include <vector>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -185,6 +190,7 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
     if (count < 1 || !n || !rowptr || !colind || !coords || !dim)
       throw Error(SPAND_E_INVALID, "bad batch arguments");
     std::vector<spand::Plan> parts((size_t)count);   // sized once: plans are not moved
+    std::vector<int> depths((size_t)count);
     for (int i = 0; i < count; ++i) {
       if (n[i] <= 0 || !rowptr[i] || !colind[i] || !coords[i] || dim[i] < 1 || dim[i] > 3)
         throw Error(SPAND_E_INVALID, "bad matrix or coordinates of problem " + std::to_string(i));
@@ -193,9 +199,29 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
       int d = depth ? depth[i] : opts->depth;
       if (d <= 0) d = std::max(0, (int)std::lround(std::log2((double)n[i] / 64.0)));
       if (d > 40) throw Error(SPAND_E_INVALID, "depth too large");
+      depths[i] = d;
       parts[i].n = n[i];
-      spand::analyze_plan(parts[i], rowptr[i], colind[i], coords[i], dim[i], d, opts->skip);
     }
+    // the problems are analysed independently, on up to 16 host threads
+    std::vector<std::exception_ptr> errs((size_t)count);
+    std::atomic<int> next{0};
+    auto run = [&] {
+      for (int i; (i = next.fetch_add(1)) < count;) {
+        try {
+          spand::analyze_plan(parts[i], rowptr[i], colind[i], coords[i], dim[i], depths[i],
+                              opts->skip);
+        } catch (...) {
+          errs[i] = std::current_exception();
+        }
+      }
+    };
+    const int nth = std::min<int>({count, 16, (int)std::max(1u, std::thread::hardware_concurrency())});
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(run);
+    run();
+    for (auto& t : pool) t.join();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
     spand::Plan& P = plan->p;
     spand::merge_plans(P, parts, opts->skip);
     spand::build_leaf_map(P);

@@ -244,29 +244,45 @@ void build_apply(Ctx& C, FactorObj& F) {
   SPAND_HIP(hipStreamSynchronize(s));
 }
 
-// y = M x for nrhs columns (x and y may alias)
+// LDS doubles the apply kernels stage for nrhs columns, at the largest
+// cluster of each kernel class: interiors (x, y and the GEMV partial sums
+// forward; y, u, partial sums and a gather chunk backward), interfaces (2
+// vectors for the scaling; the WY apply; E tiles)
+static int64_t apply_lds_need(const ApplyProg& pg, int32_t nrhs) {
+  int64_t need = 0;
+  for (const ApplyStep& as : pg.steps) {
+    need = std::max<int64_t>({need, (int64_t)as.max_in * (2 * nrhs + 4 * 4),
+                              (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
+                              (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs});
+    for (const ApplyColour& ac : as.colours)
+      need = std::max<int64_t>({need, (int64_t)ac.max_a * (3 * nrhs + 8 * (nrhs > 4 ? 2 : 4)),
+                                (int64_t)ac.max_n * nrhs, (int64_t)ac.max_nf * nrhs + 2048,
+                                (int64_t)kEtTileB * nrhs});
+  }
+  return need;
+}
+
+static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y);
+
+// y = M x for nrhs columns (x and y may alias).  Columns are independent: they
+// are processed in chunks of as many columns as the kernels' LDS holds.
 void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
+  constexpr int64_t kLds = 160 * 1024;
+  const ApplyProg& pg = *F.prog;
+  int32_t chunk = 0;
+  while (chunk < nrhs && apply_lds_need(pg, chunk + 1) * (int64_t)sizeof(double) <= kLds) ++chunk;
+  if (chunk == 0) throw Error(SPAND_E_LIMIT, "cluster too large for the apply");
+  const int64_t n = F.plan->n;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += chunk)
+    apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n);
+}
+
+static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   hipStream_t s = C.stream;
   const int64_t n = F.plan->n;
   ApplyProg& pg = *F.prog;
   double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
   double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
-  // every apply kernel stages its cluster's slice of the vectors in LDS
-  constexpr int64_t kLds = 160 * 1024;
-  for (const ApplyStep& as : pg.steps) {
-    // interiors: x, y and the GEMV partial sums (forward); y, u, partial sums
-    // and a gather chunk (backward); interfaces: 2 vectors (scaling)
-    int64_t need = std::max<int64_t>({(int64_t)as.max_in * (2 * nrhs + 4 * 4),
-                                      (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
-                                      (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs});
-    for (const ApplyColour& ac : as.colours)
-      need = std::max<int64_t>(need, std::max<int64_t>({(int64_t)ac.max_a * (3 * nrhs + 8 * (nrhs > 4 ? 2 : 4)),
-                                                        (int64_t)ac.max_n * nrhs,
-                                                        (int64_t)ac.max_nf * nrhs + 2048,
-                                                        (int64_t)kEtTileB * nrhs}));
-    if (need * (int64_t)sizeof(double) > kLds)
-      throw Error(SPAND_E_LIMIT, "cluster too large for the apply with nrhs = " + std::to_string(nrhs));
-  }
   if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
     SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));

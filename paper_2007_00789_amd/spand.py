@@ -80,6 +80,14 @@ SIGNATURES = {
     "spand_apply": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "spand_pcg": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_double, C.c_int32, _I32P, _DP]),
     "spand_debug_block": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _I32P, _I32P]),
+    "spand_server_create": (C.c_int, [C.c_int32, C.POINTER(Opts), C.c_double, C.c_int32,
+                                      C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "spand_server_submit": (C.c_int, [_P, C.c_int64, C.c_int64, _I64P, _I32P, _DP, C.c_int32,
+                                      _DP, C.c_int32, _DP, _I64P]),
+    "spand_server_poll": (C.c_int, [_P, C.c_int64, C.c_int32, _I32P, _DP, _I32P, _DP, _DP]),
+    "spand_server_stats": (C.c_int, [_P, _I64P]),
+    "spand_server_error": (C.c_char_p, [_P]),
+    "spand_server_destroy": (None, [_P]),
     "spand_profile": (C.c_int, [_P, C.c_int32]),
     "spand_profile_entries": (C.c_int, [_P, _I32P]),
     "spand_profile_entry": (C.c_int, [_P, C.c_int32, C.c_char_p, C.c_int32, _DP, _I64P, _DP]),
@@ -330,3 +338,82 @@ class Factor:
         out = np.zeros((r.value, c.value), order="F")
         self.lib.spand_debug_block(self.h, ci, cj, out.ctypes.data_as(_DP), C.byref(r), C.byref(c))
         return out
+
+
+class Server:
+    """spand_server_*: a request loop on one device (continuous batching of
+    new matrices, resident factors within a byte budget, one PCG per factor
+    and slot).  submit() returns a request id; result() waits for it."""
+
+    def __init__(self, opts: Opts, device: int = 0, tol=1e-10, maxit=1000,
+                 max_bytes: int = 64 << 30, slots: int = 2, max_batch: int = 32):
+        self.lib = load()
+        self.h = C.c_void_p()
+        st = self.lib.spand_server_create(int(device), C.byref(opts), float(tol), int(maxit),
+                                          int(max_bytes), int(slots), int(max_batch),
+                                          C.byref(self.h))
+        if st != SPAND_OK:
+            raise SpandError(st, "spand_server_create failed")
+        self._n = {}
+
+    def close(self):
+        if self.h:
+            self.lib.spand_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, key: int, b, matrix=None) -> int:
+        """Queue a solve with the matrix of `key`; b is (n,) or (n, nrhs).
+        matrix = (n, rowptr, colind, coords, vals) on the first request with a
+        key (host arrays), None afterwards."""
+        b = np.asarray(b, dtype=np.float64)
+        nrhs = 1 if b.ndim == 1 else b.shape[1]
+        bb, b_p = _np(b.reshape(b.shape[0], nrhs).T, np.float64)   # column-major
+        rid = C.c_int64()
+        if matrix is not None:
+            n, rowptr, colind, coords, vals = matrix
+            rp, rp_p = _np(rowptr, np.int64)
+            ci, ci_p = _np(colind, np.int32)
+            xy, xy_p = _np(coords, np.float64)
+            va, va_p = _np(vals, np.float64)
+            dim = 1 if xy.ndim == 1 else xy.shape[1]
+            st = self.lib.spand_server_submit(self.h, int(key), int(n), rp_p, ci_p, xy_p, dim,
+                                              va_p, nrhs, b_p, C.byref(rid))
+            if st == SPAND_OK:
+                self._n[int(key)] = int(n)
+        else:
+            st = self.lib.spand_server_submit(self.h, int(key), 0, None, None, None, 0, None,
+                                              nrhs, b_p, C.byref(rid))
+        if st != SPAND_OK:
+            raise SpandError(st, "spand_server_submit failed")
+        return rid.value, self._n[int(key)], nrhs
+
+    def result(self, req, wait: bool = True, check=True):
+        """(x (n, nrhs), iters, relres, latency seconds, status), or None if
+        not done and wait is False."""
+        rid, n, nrhs = req
+        done = C.c_int32()
+        x = np.zeros(n * nrhs, dtype=np.float64)
+        it = np.zeros(nrhs, dtype=np.int32)
+        rr = np.zeros(nrhs, dtype=np.float64)
+        lat = C.c_double()
+        st = self.lib.spand_server_poll(self.h, int(rid), int(bool(wait)), C.byref(done),
+                                        x.ctypes.data_as(_DP), it.ctypes.data_as(_I32P),
+                                        rr.ctypes.data_as(_DP), C.byref(lat))
+        if st not in (SPAND_OK, -4) or (check and st != SPAND_OK):
+            raise SpandError(st, self.lib.spand_server_error(self.h).decode())
+        if not done.value:
+            return None
+        return x.reshape(nrhs, n).T, it, rr, lat.value, st
+
+    def stats(self) -> dict:
+        c = np.zeros(6, dtype=np.int64)
+        self.lib.spand_server_stats(self.h, c.ctypes.data_as(_I64P))
+        keys = ["resident_bytes", "resident_factors", "queued", "factor_batches",
+                "factored_matrices", "pcg_calls"]
+        return {k: int(v) for k, v in zip(keys, c)}

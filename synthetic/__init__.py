@@ -13,5 +13,6 @@ from .problems import (  # noqa: F401
     rhs,
     workload,
     batch_problems,
+    serve_stream,
     WORKLOADS,
 )

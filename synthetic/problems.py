@@ -219,3 +219,30 @@ def workload(name: str):
     w = dict(WORKLOADS[name])
     prob = w.pop("make")()
     return prob, w
+
+
+def serve_stream(count: int = 48, rate: float = 50.0, reuse: float = 0.3, side=(32, 96),
+                 umax: float = 2.0, nrhs_max: int = 16, seed: int = 4000):
+    """Requests of the serving workload, in arrival order: Poisson arrivals at
+    `rate` per second; with probability `reuse` a request reuses the matrix of
+    a uniformly drawn earlier request (the first one never does), otherwise it
+    brings a new 3D FV diffusion matrix with side ~ U{side} and coefficient
+    exponents u ~ U[-umax, umax]; nrhs ~ U{1..nrhs_max}.  Each entry is a dict
+    with arrival time t (s), key, side, matrix seed, nrhs and rhs seed; the
+    matrix of a key is fv_diffusion_3d(side, umax, mseed)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out, keys = [], []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        if keys and rng.random() < reuse:
+            key = keys[int(rng.integers(len(keys)))]
+            s, ms = key
+        else:
+            s = int(rng.integers(side[0], side[1] + 1))
+            ms = seed + 1 + i
+            key = (s, ms)
+            keys.append(key)
+        out.append(dict(t=t, key=key, side=s, mseed=ms, umax=umax,
+                        nrhs=int(rng.integers(1, nrhs_max + 1)), rhs_seed=seed + 100000 + i))
+    return out

@@ -124,6 +124,26 @@ def test_apply_matches_oracle(ctx, name, make, depth, skip, eps, scheme):
 
 
 @gpu
+def test_apply_many_columns_in_chunks(ctx):
+    """More right-hand sides than the apply kernels stage in LDS at once: the
+    columns are processed in chunks, each column as in a narrow apply."""
+    p = laplacian_3d(16)
+    nrhs = 100
+    print(f"apply lap3d_16 SO nrhs {nrhs}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, 6, 1)
+    F = ospand.factor(p.scipy(), plan_o, 1e-2, "SO")
+    _, fac = _gpu_factor(ctx, p, 6, 1, 1e-2, "SO")
+    x = rhs(p.n, nrhs, 12)
+    y_ref = ospand.apply(F, x)
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, nrhs, dx, dy)
+    y = dy.cpu().numpy().reshape(p.n, nrhs, order="F")
+    for j in range(nrhs):
+        assert np.linalg.norm(y[:, j] - y_ref[:, j]) <= 1e-11 * np.linalg.norm(y_ref[:, j]), j
+
+
+@gpu
 @pytest.mark.parametrize("scheme", ["FO", "SO"])
 @pytest.mark.parametrize("name,make,depth,skip,eps,tol,nrhs", [
     ("lap2d_64", lambda: laplacian_2d(64), 6, 4, 1e-2, 1e-12, 1),
