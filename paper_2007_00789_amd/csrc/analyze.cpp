@@ -21,8 +21,11 @@
 //  * interfaces are coloured greedily in canonical order and sparsified by
 //    (colour, index) on the levels 1 <= l <= depth - skip (Alg. 2, Sec. 4).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <memory>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -42,83 +45,173 @@ struct Node {
   std::vector<int32_t> sep;
 };
 
-std::vector<Node> build_tree(const Plan& P, const double* coords, int dim) {
-  const int D = P.depth;
-  std::vector<Node> nodes(1);
-  nodes[0].verts.resize(P.n);
-  std::iota(nodes[0].verts.begin(), nodes[0].verts.end(), 0);
-  std::vector<char> onR(P.n, 0);
-  std::vector<int> stack{0};
-  std::vector<double> lo(dim), hi(dim);
+// Runs f(i) for 0 <= i < count on up to nth host threads.
+template <class F>
+void parallel_for(int count, int nth, const F& f) {
+  std::atomic<int> next{0};
+  auto run = [&] {
+    for (int i; (i = next.fetch_add(1)) < count;) f(i);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < std::min(nth, count); ++t) pool.emplace_back(run);
+  run();
+  for (auto& t : pool) t.join();
+}
+
+int host_threads(int64_t work) {
+  return work >= (1 << 17) ? std::min(16, (int)std::max(1u, std::thread::hardware_concurrency())) : 1;
+}
+
+// Marks of the right side of the node being split: a vertex belongs to it if
+// its stamp is the node's own (stamps are unique, so nodes split concurrently
+// on disjoint vertex sets never see each other's marks).
+struct SideMarks {
+  std::unique_ptr<std::atomic<int32_t>[]> owner;
+  std::atomic<int32_t> stamps{0};
+  explicit SideMarks(int64_t n) : owner(new std::atomic<int32_t>[n]) {
+    for (int64_t i = 0; i < n; ++i) owner[i].store(0, std::memory_order_relaxed);
+  }
+};
+
+// Splits node nd into the children ln and rn (their indices are set by the
+// caller), unless it is a leaf.
+bool split_node(Node& nd, Node& ln, Node& rn, const Plan& P, const double* coords, int dim,
+                SideMarks& marks) {
+  if (nd.depth == P.depth || nd.verts.size() <= 1) return false;
+  std::atomic<int32_t>* owner = marks.owner.get();
+  std::atomic<int32_t>& stamps = marks.stamps;
+  double lo[3], hi[3];
+  // the order of a node's vertex list carries no meaning: it is partitioned
+  // in place (the cut and the separator depend on the vertex set only)
+  std::vector<int32_t>& V = nd.verts;
+  for (int a = 0; a < dim; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+  for (int32_t v : V)
+    for (int a = 0; a < dim; ++a) {
+      const double x = coords[(int64_t)v * dim + a];
+      lo[a] = std::min(lo[a], x);
+      hi[a] = std::max(hi[a], x);
+    }
+  int ax = 0;
+  double best = hi[0] - lo[0];
+  for (int a = 1; a < dim; ++a)
+    if (hi[a] - lo[a] > best) { best = hi[a] - lo[a]; ax = a; }
+  if (best == 0.0) return false;
+  auto X = [&](int32_t v) { return coords[(int64_t)v * dim + ax]; };
+  const size_t mid = V.size() / 2;
+  std::nth_element(V.begin(), V.begin() + mid, V.end(), [&](int32_t a, int32_t b) {
+    const double xa = X(a), xb = X(b);
+    return xa < xb || (xa == xb && a < b);
+  });
+  const double t = X(V[mid]);
+  bool le = false;
+  size_t nl = 0;
+  for (int32_t v : V) nl += X(v) < t;
+  if (nl == 0) {
+    le = true;
+    for (int32_t v : V) nl += X(v) <= t;
+  }
+  if (nl == V.size()) return false;
+  std::vector<int32_t> L, R;
+  L.reserve(nl);
+  R.reserve(V.size() - nl);
+  for (int32_t v : V) {
+    const bool left = le ? X(v) <= t : X(v) < t;
+    (left ? L : R).push_back(v);
+  }
+  std::vector<int32_t>().swap(V);
+  const int32_t stamp = stamps.fetch_add(1, std::memory_order_relaxed) + 1;
+  for (int32_t v : R) owner[v].store(stamp, std::memory_order_relaxed);
+  std::vector<int32_t> S, Lrest;
+  for (int32_t v : L) {
+    bool touch = false;
+    for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1] && !touch; ++e)
+      touch = owner[P.colind[e]].load(std::memory_order_relaxed) == stamp;
+    (touch ? S : Lrest).push_back(v);
+  }
+  ln.depth = rn.depth = nd.depth + 1;
+  ln.bits = nd.bits * 2;
+  rn.bits = nd.bits * 2 + 1;
+  ln.verts = std::move(Lrest);
+  rn.verts = std::move(R);
+  nd.leaf = false;
+  nd.ax = ax;
+  nd.t = t;
+  nd.le = le;
+  nd.sep = std::move(S);
+  return true;
+}
+
+// Appends the children of node ni and links them.
+void attach(std::vector<Node>& nodes, int ni, Node& ln, Node& rn) {
+  const int li = (int)nodes.size();
+  nodes.push_back(std::move(ln));
+  nodes.push_back(std::move(rn));
+  nodes[ni].left = li;
+  nodes[ni].right = li + 1;
+}
+
+void grow(std::vector<Node>& nodes, int root, const Plan& P, const double* coords, int dim,
+          SideMarks& marks) {
+  std::vector<int> stack{root};
   while (!stack.empty()) {
     const int ni = stack.back();
     stack.pop_back();
-    if (nodes[ni].depth == D || nodes[ni].verts.size() <= 1) continue;
-    std::vector<int32_t> V = nodes[ni].verts;
-    for (int a = 0; a < dim; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
-    for (int32_t v : V)
-      for (int a = 0; a < dim; ++a) {
-        const double x = coords[(int64_t)v * dim + a];
-        lo[a] = std::min(lo[a], x);
-        hi[a] = std::max(hi[a], x);
-      }
-    int ax = 0;
-    double best = hi[0] - lo[0];
-    for (int a = 1; a < dim; ++a)
-      if (hi[a] - lo[a] > best) { best = hi[a] - lo[a]; ax = a; }
-    if (best == 0.0) continue;
-    auto X = [&](int32_t v) { return coords[(int64_t)v * dim + ax]; };
-    std::vector<int32_t> sorted = V;
-    const size_t mid = V.size() / 2;
-    std::nth_element(sorted.begin(), sorted.begin() + mid, sorted.end(), [&](int32_t a, int32_t b) {
-      const double xa = X(a), xb = X(b);
-      return xa < xb || (xa == xb && a < b);
-    });
-    const double t = X(sorted[mid]);
-    bool le = false;
-    size_t nl = 0;
-    for (int32_t v : V) nl += X(v) < t;
-    if (nl == 0) {
-      le = true;
-      for (int32_t v : V) nl += X(v) <= t;
-    }
-    if (nl == V.size()) continue;
-    std::vector<int32_t> L, R;
-    L.reserve(nl);
-    R.reserve(V.size() - nl);
-    for (int32_t v : V) {
-      const bool left = le ? X(v) <= t : X(v) < t;
-      (left ? L : R).push_back(v);
-    }
-    for (int32_t v : R) onR[v] = 1;
-    std::vector<int32_t> S, Lrest;
-    for (int32_t v : L) {
-      bool touch = false;
-      for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1] && !touch; ++e) touch = onR[P.colind[e]];
-      (touch ? S : Lrest).push_back(v);
-    }
-    for (int32_t v : R) onR[v] = 0;
     Node ln, rn;
-    ln.depth = rn.depth = nodes[ni].depth + 1;
-    ln.bits = nodes[ni].bits * 2;
-    rn.bits = nodes[ni].bits * 2 + 1;
-    ln.verts = std::move(Lrest);
-    rn.verts = std::move(R);
-    const int li = (int)nodes.size();
-    nodes.push_back(std::move(ln));
-    nodes.push_back(std::move(rn));
-    Node& nd = nodes[ni];
-    nd.leaf = false;
-    nd.ax = ax;
-    nd.t = t;
-    nd.le = le;
-    nd.sep = std::move(S);
-    nd.left = li;
-    nd.right = li + 1;
-    nd.verts.clear();
-    nd.verts.shrink_to_fit();
-    stack.push_back(li + 1);
-    stack.push_back(li);
+    if (split_node(nodes[ni], ln, rn, P, coords, dim, marks)) {
+      attach(nodes, ni, ln, rn);
+      stack.push_back(nodes[ni].right);
+      stack.push_back(nodes[ni].left);
+    }
+  }
+}
+
+// The node tree: the top levels on this thread, breadth first, until there
+// are enough independent subtrees; those are grown on up to 16 host threads
+// into lists of their own and spliced in.  Node indices differ from a serial
+// build, which nothing depends on: every node carries its own depth and bits.
+std::vector<Node> build_tree(const Plan& P, const double* coords, int dim) {
+  std::vector<Node> nodes(1);
+  nodes[0].verts.resize(P.n);
+  std::iota(nodes[0].verts.begin(), nodes[0].verts.end(), 0);
+  SideMarks marks(P.n);
+  const int nth = host_threads(P.n);
+  if (nth == 1) {
+    grow(nodes, 0, P, coords, dim, marks);
+    return nodes;
+  }
+  // the top levels: the nodes of one level are split concurrently
+  std::vector<int> frontier{0};
+  while (!frontier.empty() && (int)frontier.size() < 4 * nth) {
+    const int nf = (int)frontier.size();
+    std::vector<Node> kids(2 * (size_t)nf);
+    std::vector<char> split(nf, 0);
+    parallel_for(nf, nth, [&](int i) {
+      split[i] = split_node(nodes[frontier[i]], kids[2 * i], kids[2 * i + 1], P, coords, dim, marks);
+    });
+    std::vector<int> next;
+    for (int i = 0; i < nf; ++i)
+      if (split[i]) {
+        attach(nodes, frontier[i], kids[2 * i], kids[2 * i + 1]);
+        next.push_back(nodes[frontier[i]].left);
+        next.push_back(nodes[frontier[i]].right);
+      }
+    frontier.swap(next);
+  }
+  // the subtrees below, each into a node list of its own
+  const int nf = (int)frontier.size();
+  std::vector<std::vector<Node>> sub(nf);
+  for (int i = 0; i < nf; ++i) sub[i].push_back(std::move(nodes[frontier[i]]));
+  parallel_for(nf, nth, [&](int i) { grow(sub[i], 0, P, coords, dim, marks); });
+  for (int i = 0; i < nf; ++i) {
+    const int base = (int)nodes.size() - 1;
+    auto map = [&](int j) { return j == 0 ? frontier[i] : base + j; };
+    for (Node& nd : sub[i])
+      if (!nd.leaf) {
+        nd.left = map(nd.left);
+        nd.right = map(nd.right);
+      }
+    nodes[frontier[i]] = std::move(sub[i][0]);
+    for (size_t j = 1; j < sub[i].size(); ++j) nodes.push_back(std::move(sub[i][j]));
   }
   return nodes;
 }
@@ -203,18 +296,37 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
 
   // pattern symmetry: sort each row's columns and look every entry up
   {
-    std::vector<int32_t> srt(P.colind);
-    for (int64_t i = 0; i < n; ++i) {
-      if (P.rowptr[i + 1] < P.rowptr[i]) throw Error(SPAND_E_INVALID, "rowptr not monotone");
-      std::sort(srt.begin() + P.rowptr[i], srt.begin() + P.rowptr[i + 1]);
-    }
     for (int64_t i = 0; i < n; ++i)
-      for (int64_t e = P.rowptr[i]; e < P.rowptr[i + 1]; ++e) {
-        const int32_t j = srt[e];
-        if (j < 0 || j >= n) throw Error(SPAND_E_INVALID, "column index out of range");
-        if (!std::binary_search(srt.begin() + P.rowptr[j], srt.begin() + P.rowptr[j + 1], (int32_t)i))
-          throw Error(SPAND_E_NOT_SYMMETRIC, "pattern not symmetric at row " + std::to_string(i) +
-                                                 ", column " + std::to_string(j));
+      if (P.rowptr[i + 1] < P.rowptr[i]) throw Error(SPAND_E_INVALID, "rowptr not monotone");
+    for (int64_t e = 0; e < P.nnz; ++e)
+      if (P.colind[e] < 0 || P.colind[e] >= n) throw Error(SPAND_E_INVALID, "column index out of range");
+    std::vector<int32_t> srt(P.colind);
+    // rows in chunks on host threads; the first asymmetric entry (lowest row)
+    // is reported
+    const int64_t chunk = 1 << 14;
+    const int nchunk = (int)((n + chunk - 1) / chunk);
+    const int nth = host_threads(P.nnz);
+    parallel_for(nchunk, nth, [&](int k) {
+      for (int64_t i = k * chunk; i < std::min(n, (k + 1) * chunk); ++i)
+        std::sort(srt.begin() + P.rowptr[i], srt.begin() + P.rowptr[i + 1]);
+    });
+    std::vector<int64_t> bad(nchunk, -1);
+    parallel_for(nchunk, nth, [&](int k) {
+      for (int64_t i = k * chunk; i < std::min(n, (k + 1) * chunk) && bad[k] < 0; ++i)
+        for (int64_t e = P.rowptr[i]; e < P.rowptr[i + 1]; ++e) {
+          const int32_t j = srt[e];
+          if (!std::binary_search(srt.begin() + P.rowptr[j], srt.begin() + P.rowptr[j + 1], (int32_t)i)) {
+            bad[k] = e;
+            break;
+          }
+        }
+    });
+    for (int k = 0; k < nchunk; ++k)
+      if (bad[k] >= 0) {
+        const int64_t e = bad[k];
+        const int64_t i = std::upper_bound(P.rowptr.begin(), P.rowptr.end(), e) - P.rowptr.begin() - 1;
+        throw Error(SPAND_E_NOT_SYMMETRIC, "pattern not symmetric at row " + std::to_string(i) +
+                                               ", column " + std::to_string(srt[e]));
       }
   }
 
@@ -243,27 +355,45 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
       P.path[v] = base | bits;
     }
   }
-  P.perm.resize(n);
-  std::iota(P.perm.begin(), P.perm.end(), 0);
-  std::sort(P.perm.begin(), P.perm.end(), [&](int64_t a, int64_t b) {
-    const int la = D - P.lvl[a], lb = D - P.lvl[b];
-    if (la != lb) return la < lb;
-    if (P.path[a] != P.path[b]) return P.path[a] < P.path[b];
-    return a < b;
-  });
+  // elimination order by (D - lvl, path, id): (D - lvl) * 2^(D+1) + path packs
+  // the first two into one key (depth <= 40 keeps it below 2^47)
+  {
+    struct KV {
+      uint64_t k;
+      int64_t v;
+      bool operator<(const KV& o) const { return k < o.k || (k == o.k && v < o.v); }
+    };
+    std::vector<KV> kv(n);
+    for (int64_t v = 0; v < n; ++v)
+      kv[v] = {((uint64_t)(D - P.lvl[v]) << (D + 1)) | (uint64_t)P.path[v], v};
+    std::sort(kv.begin(), kv.end());
+    P.perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) P.perm[i] = kv[i].v;
+  }
 
   // clusters, adjacency and colours of every step
   P.steps.assign(D + 1, StepPlan());
-  std::vector<int64_t> prev_pairs;
   const int64_t SH = int64_t(1) << (D + 1);
+  std::vector<int32_t> mark;
   for (int l = D; l >= 0; --l) {
     StepPlan& st = P.steps[l];
     st.l = l;
-    std::vector<int64_t> ikeys, fkeys;  // interior prefixes; interface codes lvl*SH + prefix
-    for (int64_t v = 0; v < n; ++v) {
-      const int64_t pre = P.path[v] >> (D - l);
-      if (P.lvl[v] == l) ikeys.push_back(pre);
-      else if (P.lvl[v] < l) fkeys.push_back(P.lvl[v] * SH + pre);
+    // cluster keys: interior prefixes, interface codes lvl * SH + prefix.  At
+    // the leaf step from the vertices; above it from the interfaces of step
+    // l + 1, which hold exactly the vertices of level < l + 1
+    std::vector<int64_t> ikeys, fkeys;
+    if (l == D) {
+      for (int64_t v = 0; v < n; ++v) {
+        if (P.lvl[v] == l) ikeys.push_back(P.path[v]);
+        else fkeys.push_back(P.lvl[v] * SH + P.path[v]);
+      }
+    } else {
+      const StepPlan& pv = P.steps[l + 1];
+      for (int c = pv.nI; c < pv.nc; ++c) {
+        const int64_t cl = pv.key_lvl[c], cp = pv.key_prefix[c] >> 1;
+        if (cl == l) ikeys.push_back(cp);
+        else fkeys.push_back(cl * SH + cp);
+      }
     }
     sort_unique(ikeys);
     sort_unique(fkeys);
@@ -286,72 +416,100 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
       return st.nI + (int)(it - fkeys.begin());
     };
 
-    std::vector<int64_t> pairs;
+    // adjacency before this step's fill (sorted lists, self included): at the
+    // leaf step the clusters A couples; above it the parents of adjacent
+    // interfaces of step l + 1
+    std::vector<int64_t> ptr(nc + 1, 0);
+    std::vector<int32_t> lst;
+    mark.assign(nc, -1);
     if (l == D) {
       std::vector<int32_t> cid(n);
-      for (int64_t v = 0; v < n; ++v) {
-        const int64_t pre = P.path[v] >> (D - l);
-        cid[v] = P.lvl[v] == l ? find_interior(pre) : find_interface(P.lvl[v] * SH + pre);
-      }
+      for (int64_t v = 0; v < n; ++v)
+        cid[v] = P.lvl[v] == l ? find_interior(P.path[v]) : find_interface(P.lvl[v] * SH + P.path[v]);
       st.vert_ptr.assign(nc + 1, 0);
       for (int64_t v = 0; v < n; ++v) st.vert_ptr[cid[v] + 1]++;
       for (int c = 0; c < nc; ++c) st.vert_ptr[c + 1] += st.vert_ptr[c];
       st.verts.resize(n);
       std::vector<int64_t> fillp(st.vert_ptr.begin(), st.vert_ptr.end() - 1);
       for (int64_t v = 0; v < n; ++v) st.verts[fillp[cid[v]]++] = (int32_t)v;  // ascending ids
-      pairs.reserve(P.nnz + nc);
-      for (int64_t v = 0; v < n; ++v)
-        for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1]; ++e)
-          pairs.push_back((int64_t)cid[v] * nc + cid[P.colind[e]]);
+      for (int c = 0; c < nc; ++c) {
+        const size_t b0 = lst.size();
+        mark[c] = c;
+        lst.push_back(c);
+        for (int64_t i = st.vert_ptr[c]; i < st.vert_ptr[c + 1]; ++i) {
+          const int32_t v = st.verts[i];
+          for (int64_t e = P.rowptr[v]; e < P.rowptr[v + 1]; ++e) {
+            const int32_t q = cid[P.colind[e]];
+            if (mark[q] != c) {
+              mark[q] = c;
+              lst.push_back(q);
+            }
+          }
+        }
+        std::sort(lst.begin() + b0, lst.end());
+        ptr[c + 1] = (int64_t)lst.size();
+      }
     } else {
-      const StepPlan& pv = P.steps[l + 1];
-      StepPlan& pvm = P.steps[l + 1];
-      pvm.parent.assign(pv.nc, -1);
+      StepPlan& pv = P.steps[l + 1];
+      pv.parent.assign(pv.nc, -1);
       st.child_ptr.assign(nc + 1, 0);
       std::vector<std::vector<int32_t>> ch(nc);
       for (int c = pv.nI; c < pv.nc; ++c) {
         const int64_t cl = pv.key_lvl[c], cp = pv.key_prefix[c] >> 1;
         const int par = cl == l ? find_interior(cp) : find_interface(cl * SH + cp);
-        pvm.parent[c] = par;
+        pv.parent[c] = par;
         ch[par].push_back(c);
       }
       for (int c = 0; c < nc; ++c) st.child_ptr[c + 1] = st.child_ptr[c] + ch[c].size();
       st.child.reserve(st.child_ptr[nc]);
       for (int c = 0; c < nc; ++c) st.child.insert(st.child.end(), ch[c].begin(), ch[c].end());
-      const int64_t pnc = pv.nc;
-      pairs.reserve(prev_pairs.size() + nc);
-      for (int64_t code : prev_pairs) {
-        const int32_t a = pvm.parent[code / pnc], b = pvm.parent[code % pnc];
-        if (a >= 0 && b >= 0) pairs.push_back((int64_t)a * nc + b);
+      for (int c = 0; c < nc; ++c) {
+        const size_t b0 = lst.size();
+        mark[c] = c;
+        lst.push_back(c);
+        for (int64_t a = st.child_ptr[c]; a < st.child_ptr[c + 1]; ++a) {
+          const int x = st.child[a];
+          for (int64_t e = pv.adj_ptr[x]; e < pv.adj_ptr[x + 1]; ++e) {
+            const int32_t q = pv.parent[pv.adj[e]];
+            if (q >= 0 && mark[q] != c) {
+              mark[q] = c;
+              lst.push_back(q);
+            }
+          }
+        }
+        std::sort(lst.begin() + b0, lst.end());
+        ptr[c + 1] = (int64_t)lst.size();
       }
     }
-    for (int c = 0; c < nc; ++c) pairs.push_back((int64_t)c * nc + c);
-    sort_unique(pairs);
-    // fill from the interiors of this step
-    {
-      std::vector<int64_t> fill;
-      auto begin_of = [&](int c) {
-        return std::lower_bound(pairs.begin(), pairs.end(), (int64_t)c * nc) - pairs.begin();
-      };
-      for (int s = 0; s < st.nI; ++s) {
-        std::vector<int32_t> nb;
-        for (int64_t e = begin_of(s); e < (int64_t)pairs.size() && pairs[e] / nc == s; ++e)
-          if (pairs[e] % nc != s) nb.push_back((int32_t)(pairs[e] % nc));
-        for (int32_t a : nb)
-          for (int32_t b : nb) fill.push_back((int64_t)a * nc + b);
-      }
-      if (!fill.empty()) {
-        pairs.insert(pairs.end(), fill.begin(), fill.end());
-        sort_unique(pairs);
-      }
-    }
+    // fill from the interiors of this step: two clusters that border a common
+    // interior s become adjacent.  The lists are symmetric, so cluster a gains
+    // the neighbours of every interior s != a in its own list.
     st.adj_ptr.assign(nc + 1, 0);
-    st.adj.resize(pairs.size());
-    for (size_t e = 0; e < pairs.size(); ++e) {
-      st.adj_ptr[pairs[e] / nc + 1]++;
-      st.adj[e] = (int32_t)(pairs[e] % nc);
+    st.adj.clear();
+    st.adj.reserve(lst.size());
+    mark.assign(nc, -1);
+    for (int a = 0; a < nc; ++a) {
+      const size_t b0 = st.adj.size();
+      bool grown = false;
+      for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+        mark[lst[e]] = a;
+        st.adj.push_back(lst[e]);
+      }
+      for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+        const int32_t s = lst[e];
+        if (s >= st.nI || s == a) continue;
+        for (int64_t f = ptr[s]; f < ptr[s + 1]; ++f) {
+          const int32_t b = lst[f];
+          if (b != s && mark[b] != a) {
+            mark[b] = a;
+            st.adj.push_back(b);
+            grown = true;
+          }
+        }
+      }
+      if (grown) std::sort(st.adj.begin() + b0, st.adj.end());
+      st.adj_ptr[a + 1] = (int64_t)st.adj.size();
     }
-    for (int c = 0; c < nc; ++c) st.adj_ptr[c + 1] += st.adj_ptr[c];
     // greedy colouring of the interface graph in canonical order
     st.colour.assign(nc, -1);
     st.ncolours = 0;
@@ -372,12 +530,12 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
     std::stable_sort(st.order.begin(), st.order.end(),
                      [&](int a, int b) { return st.colour[a] < st.colour[b]; });
     st.sparsified = l >= 1 && l <= D - skip;
-    prev_pairs.swap(pairs);
   }
   P.steps[0].parent.assign(P.steps[0].nc, -1);
   for (int l = 0; l <= D; ++l)
     if (P.steps[l].parent.empty()) P.steps[l].parent.assign(P.steps[l].nc, -1);
-  for (int l = 0; l <= D; ++l) build_numeric_lists(P, l);
+  // the lists of step l read step l - 1's structure only
+  parallel_for(D + 1, host_threads(P.nnz), [&](int l) { build_numeric_lists(P, l); });
 }
 
 void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
