@@ -201,8 +201,9 @@ spand_status spand_server_submit(spand_server_t srv, int64_t key, int64_t n, con
  * maxit; x is still written then). */
 spand_status spand_server_poll(spand_server_t srv, int64_t req_id, int32_t wait, int32_t* done,
                                double* x, int32_t* iters, double* relres, double* latency);
-/* counters[6]: resident factor bytes, resident factors, queued requests,
- * factorization batches run, matrices factored, PCG calls. */
+/* counters[9]: resident factor bytes, resident factors, queued requests,
+ * factorization batches run, matrices factored, PCG calls, and microseconds
+ * spent in analysis, factorization and PCG (wall time summed over slots). */
 spand_status spand_server_stats(spand_server_t srv, int64_t* counters);
 /* Last error message of a slot ("" if none). */
 const char* spand_server_error(spand_server_t srv);
@@ -216,6 +217,10 @@ void spand_server_destroy(spand_server_t srv);
  * launches and (where the library knows it) the algorithmic work of those
  * launches (k_cpqr: QR flops).  name receives at most name_len-1 characters. */
 spand_status spand_profile(spand_ctx_t ctx, int32_t enable);
+/* Restricts the timing to the launches of one kernel name (name = NULL or
+ * "": every kernel), so that a timed run carries the event pairs of the
+ * kernel it measures only. */
+spand_status spand_profile_only(spand_ctx_t ctx, const char* name);
 spand_status spand_profile_entries(spand_ctx_t ctx, int32_t* count);
 spand_status spand_profile_entry(spand_ctx_t ctx, int32_t i, char* name, int32_t name_len,
                                  double* ms, int64_t* calls, double* work);

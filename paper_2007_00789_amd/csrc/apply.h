@@ -43,14 +43,29 @@ struct ApSp {
   const double* V;         // a x nref reflectors (ld a, zero above the unit diagonal)
   const double* tau;       // nref
   const double* T;         // nref x nref: Q = I - V T V^T
+  const double* VT;        // a x nref (ld a): V T
   const double* Et;        // E^T: k x (f1-f0), column i = row f0+i of Q^T W (ld lde); nullable
   const int32_t* pos;      // a
   const int32_t* nbr_pos;  // k
   int64_t toff;
   int64_t lde;
   int64_t part0;           // backward: first partial-sum slot of the E tiles (units of one rhs)
+  int64_t uoff;            // offset of u = (VT)^T x or V^T y in the colour's scratch
   int32_t a, nref, f0, f1, k, ntiles;
 };
+
+// The wide WY apply of one colour runs as two launches spread over blocks of
+// every interface: dots (u = M^T x over kApWyCB columns of M per task) and
+// update (x -= N u over kApWyRB rows per task), with (M, N) = (VT, V) forward
+// (x <- Q^T x) and (V, VT) backward (y <- Q y, after the E-tile partial sums
+// are subtracted from the fine rows).
+struct ApWyTask {
+  int32_t sp;   // descriptor of the interface
+  int32_t i0;   // first column (dots) or row (update)
+};
+constexpr int kApWyThreads = 256;
+constexpr int kApWyCB = 8;
+constexpr int kApWyRB = 32;
 
 // One tile of at most kEtTileF (forward) or kEtTileB (backward) columns of an interface's E (second order:
 // E = rows f0.. of Q^T W, stored transposed, element (c, i) = E[i, c] at
@@ -81,6 +96,14 @@ void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z
 // z_p <- Q_p^T z_p (one workgroup per interface)
 void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                       int32_t max_a, hipStream_t s);
+// wide WY apply, dots then update (fwd = 1: Q^T; 0: Q, after the partial
+// sums P); U: the colour's u vectors, usz doubles per right-hand side
+void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
+                       int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,
+                       hipStream_t s);
+void launch_ap_wy_update(const ApWyTask* t, int32_t count, const ApSp* d, double* z, int64_t ldz,
+                         int32_t nrhs, const double* P, const double* U, int64_t usz, int fwd,
+                         hipStream_t s);
 // E tiles, forward (t = E^T z_f) or backward (partial sums of E y_W)
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* T, int32_t max_nf, hipStream_t s);

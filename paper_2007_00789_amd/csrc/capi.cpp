@@ -398,6 +398,12 @@ spand_status spand_profile(spand_ctx_t ctx, int32_t enable) {
   });
 }
 
+spand_status spand_profile_only(spand_ctx_t ctx, const char* name) {
+  if (!ctx) return SPAND_E_INVALID;
+  ctx->c.prof.only = name ? name : "";
+  return SPAND_OK;
+}
+
 spand_status spand_profile_entries(spand_ctx_t ctx, int32_t* count) {
   if (!ctx || !count) return SPAND_E_INVALID;
   *count = (int32_t)ctx->c.prof.entries.size();

@@ -101,7 +101,7 @@ int Prof::find(const char* name) {
 }
 
 int Prof::begin(const char* name, hipStream_t s) {
-  if (!on) return -1;
+  if (!on || (!only.empty() && only != name)) return -1;
   hipEvent_t ev[2];
   for (auto& e : ev) {
     if (!pool.empty()) { e = pool.back(); pool.pop_back(); }
@@ -118,7 +118,7 @@ void Prof::end(int id, hipStream_t s) {
 }
 
 void Prof::add_work(const char* name, double w) {
-  if (on) entries[find(name)].work += w;
+  if (on && (only.empty() || only == name)) entries[find(name)].work += w;
 }
 
 void Prof::resolve() {
@@ -230,6 +230,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.V.assign(nc, nullptr);
     R.tau.assign(nc, nullptr);
     R.T.assign(nc, nullptr);
+    R.VT.assign(nc, nullptr);
     R.kmax.assign(nc, 0);
     R.sp_nbr_pos.assign(nc, {});
     auto blk = [&](int c, int64_t e) { return panel + lay.off[c] + lay.coff[e] * lay.n[c]; };
@@ -733,6 +734,33 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       const auto* d_wy = C.upload.upload(wy);
       SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), s));
       SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), s));
+      // V T of every interface (a x nref): the apply then needs no pass over T
+      // (Q^T x = x - V (VT)^T x, Q y = y - VT V^T y)
+      std::vector<GemmDesc> gv;
+      std::vector<GemmTerm> gvt;
+      std::vector<TileRef> vtiles;
+      for (StepRec& R : F.steps)
+        for (size_t p = 0; p < R.V.size(); ++p) {
+          if (!R.V[p] || R.r2[p] <= 0) continue;
+          const int nref = R.r2[p], a = R.n0[p];
+          R.VT[p] = F.arena.alloc_n<double>((size_t)a * nref);
+          GemmDesc g{};
+          g.C = R.VT[p];
+          g.ldc = a;
+          g.m = a;
+          g.n = nref;
+          g.alpha = 1.0;
+          g.beta = 0.0;
+          g.term0 = (int64_t)gvt.size();
+          gvt.push_back(GemmTerm{R.V[p], R.T[p], a, nref, nref, 0});
+          g.term1 = (int64_t)gvt.size();
+          add_gemm_tiles(vtiles, (int32_t)gv.size(), a, nref, false);
+          gv.push_back(g);
+        }
+      const auto* d_gv = C.upload.upload(gv);
+      const auto* d_gvt = C.upload.upload(gvt);
+      const auto* d_vtl = C.upload.upload(vtiles);
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), s));
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));

@@ -453,6 +453,122 @@ __global__ __launch_bounds__(kST) void k_ap_sp_bwd(const ApSp* descs, double* z,
   }
 }
 
+// ---------------------------------------------------------------------------
+// wide WY apply (one colour): Q^T x = x - V ((VT)^T x) forward, Q y = y - VT
+// (V^T y) backward, each as a dots launch and an update launch spread over
+// column blocks and row blocks of every interface of the colour.
+// ---------------------------------------------------------------------------
+// x_i of interface row i: z at its position, minus (backward) the E tiles'
+// partial sums for the fine rows, added in tile order
+__device__ __forceinline__ double wy_in(const ApSp& d, const double* __restrict__ z, int64_t ldz,
+                                        const double* __restrict__ P, int i, int r, int nrhs) {
+  double v = z[d.pos[i] + (int64_t)r * ldz];
+  if (P && i >= d.f0 && i < d.f1) {
+    const int nf = d.f1 - d.f0;
+    for (int t = 0; t < d.ntiles; ++t)
+      v -= P[(d.part0 + (int64_t)t * nf) * nrhs + (i - d.f0) + (int64_t)r * nf];
+  }
+  return v;
+}
+
+// u[j0 + c] = sum_i M[i, j0 + c] x_i for kApWyCB columns: threads over rows
+// (columns of M are contiguous), wave sums, then the waves in order.
+__global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tasks, const ApSp* descs,
+                                                          const double* __restrict__ z, int64_t ldz,
+                                                          int nrhs, const double* __restrict__ P,
+                                                          double* __restrict__ U, int64_t usz,
+                                                          int fwd) {
+  constexpr int NW = kApWyThreads / kWave;
+  __shared__ double red[NW][kApWyCB * 4];
+  const ApWyTask tk = tasks[blockIdx.x];
+  const ApSp d = descs[tk.sp];
+  const double* __restrict__ M = fwd ? d.VT : d.V;
+  const int a = d.a, j0 = tk.i0, cn = min(kApWyCB, d.nref - j0);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const double* Pp = fwd ? nullptr : P;
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    double acc[kApWyCB][4];
+#pragma unroll
+    for (int c = 0; c < kApWyCB; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[c][rr] = 0.0;
+    for (int i = threadIdx.x; i < a; i += kApWyThreads) {
+      double x[4];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) x[rr] = r0 + rr < nrhs ? wy_in(d, z, ldz, Pp, i, r0 + rr, nrhs) : 0.0;
+#pragma unroll
+      for (int c = 0; c < kApWyCB; ++c) {
+        const double m = c < cn ? M[i + (int64_t)(j0 + c) * a] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[c][rr] = fma(m, x[rr], acc[c][rr]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kApWyCB; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double v = wave_sum(acc[c][rr]);
+        if (lane == 0) red[wid][c * 4 + rr] = v;
+      }
+    __syncthreads();
+    if (threadIdx.x < kApWyCB * 4) {
+      const int c = threadIdx.x / 4, rr = threadIdx.x % 4;
+      if (c < cn && r0 + rr < nrhs) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) v += red[q][c * 4 + rr];
+        U[d.uoff + j0 + c + (int64_t)(r0 + rr) * usz] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// x_i -= sum_j N[i, j] u_j for kApWyRB rows: 32 rows x 8 column groups (a wave
+// reads 2 x 32 consecutive rows of a column), groups summed in order.
+__global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* tasks,
+                                                            const ApSp* descs, double* z,
+                                                            int64_t ldz, int nrhs,
+                                                            const double* __restrict__ P,
+                                                            const double* __restrict__ U,
+                                                            int64_t usz, int fwd) {
+  constexpr int NG = kApWyThreads / kApWyRB;
+  __shared__ double red[NG][kApWyRB * 4];
+  const ApWyTask tk = tasks[blockIdx.x];
+  const ApSp d = descs[tk.sp];
+  const double* __restrict__ N = fwd ? d.V : d.VT;
+  const int a = d.a, nref = d.nref;
+  const int rl = threadIdx.x % kApWyRB, g = threadIdx.x / kApWyRB;
+  const int i = tk.i0 + rl;
+  const double* u = U + d.uoff;
+  const double* Pp = fwd ? nullptr : P;
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < a) {
+#pragma unroll 4
+      for (int j = g; j < nref; j += NG) {
+        const double nv = N[i + (int64_t)j * a];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          if (r0 + rr < nrhs) acc[rr] = fma(nv, u[j + (int64_t)(r0 + rr) * usz], acc[rr]);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) red[g][rl * 4 + rr] = acc[rr];
+    __syncthreads();
+    if (threadIdx.x < kApWyRB * 4) {
+      const int r2 = threadIdx.x / 4, rr = threadIdx.x % 4, i2 = tk.i0 + r2;
+      if (i2 < a && r0 + rr < nrhs) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) v += red[q][r2 * 4 + rr];
+        z[d.pos[i2] + (int64_t)(r0 + rr) * ldz] = wy_in(d, z, ldz, Pp, i2, r0 + rr, nrhs) - v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // backward scaling: y_w <- Zinv^T y_w (column dots of Zinv)
 __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, double* z, int64_t ldz,
                                                      int nrhs) {
@@ -629,6 +745,20 @@ void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int3
                       const double* P, int32_t max_a, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kST), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs, P);
+}
+void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
+                       int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,
+                       hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_wy_dots, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P, U,
+                     usz, fwd);
+}
+void launch_ap_wy_update(const ApWyTask* t, int32_t count, const ApSp* d, double* z, int64_t ldz,
+                         int32_t nrhs, const double* P, const double* U, int64_t usz, int fwd,
+                         hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_wy_update, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P,
+                     U, usz, fwd);
 }
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s) {

@@ -65,6 +65,7 @@ struct DevBuf {
 struct Prof {
   struct Entry { std::string name; double ms = 0.0; int64_t calls = 0; double work = 0.0; };
   bool on = false;
+  std::string only;   // non-empty: time this kernel name only
   std::vector<Entry> entries;
   struct Pending { int entry; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -112,6 +113,7 @@ struct StepRec {
   std::vector<double*> Linv, G;              // interiors
   std::vector<int32_t> kint;                 // interiors: coupling width
   std::vector<double*> Zinv, Y, V, tau, T;   // interfaces of sparsified steps
+  std::vector<double*> VT;                   // interfaces: V T (a x nref), for the apply
   std::vector<std::vector<int32_t>> pos;     // positions of each cluster's variables (step start)
   std::vector<std::vector<int32_t>> sp_nbr_pos;  // interfaces: positions of W's columns
 };

@@ -95,6 +95,7 @@ struct spand_server_s {
   std::vector<std::shared_ptr<Resident>> residents;
   int64_t resident_bytes = 0, reserved_bytes = 0;
   int64_t factor_batches = 0, factored_matrices = 0, pcg_calls = 0;
+  double analyze_s = 0.0, factor_s = 0.0, pcg_s = 0.0;   // summed over slots
   std::vector<std::thread> workers;
   std::vector<spand_ctx_t> ctxs;
   std::vector<hipStream_t> streams;
@@ -207,8 +208,10 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
         nnz += (int64_t)ms[i]->colind.size();
         n += ms[i]->n;
       }
+      const auto ta = Clock::now();
       fst = spand_analyze_batch(ctx, cnt, ns.data(), rp.data(), ci.data(), xy.data(), dims.data(),
                                 nullptr, &opts, &fresh->plan);
+      const auto tb = Clock::now();
       double* d_vals = nullptr;
       if (fst == SPAND_OK && hipMalloc(&d_vals, std::max<int64_t>(nnz, 1) * sizeof(double)) != hipSuccess)
         fst = SPAND_E_OOM;
@@ -216,9 +219,12 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
         if (hipMemcpyAsync(d_vals + o, ms[i]->vals.data(), ms[i]->vals.size() * sizeof(double),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
           fst = SPAND_E_HIP;
+      double tf = 0.0;
       if (fst == SPAND_OK) {
         std::lock_guard<std::mutex> lk(factor_mu);
+        const auto t1 = Clock::now();
         fst = spand_factor(ctx, fresh->plan, d_vals, &opts, &fresh->fac);
+        tf = std::chrono::duration<double>(Clock::now() - t1).count();
       }
       if (d_vals) (void)hipFree(d_vals);   // the factor holds its own copy of the values
       if (fst == SPAND_OK) {
@@ -236,6 +242,8 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
         msg = spand_last_error(ctx);
       }
       std::lock_guard<std::mutex> lk(mu);
+      analyze_s += std::chrono::duration<double>(tb - ta).count();
+      factor_s += tf;
       reserved_bytes -= reserved;
       for (int64_t k : new_keys) in_flight.erase(k);
       if (fst == SPAND_OK) {
@@ -291,6 +299,7 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
         ps = SPAND_E_HIP;
       std::vector<int32_t> it((size_t)nseg * cols, 0);
       std::vector<double> rr((size_t)nseg * cols, 0.0);
+      const auto tp = Clock::now();
       if (ps == SPAND_OK) {
         ps = spand_pcg(ctx, f->fac, cols, db, dx, tol, maxit, it.data(), rr.data());
         if (ps != SPAND_OK && ps != SPAND_E_NO_CONVERGENCE) msg = spand_last_error(ctx);
@@ -304,6 +313,7 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
       if (dx) (void)hipFree(dx);
       std::lock_guard<std::mutex> lk(mu);
       ++pcg_calls;
+      pcg_s += std::chrono::duration<double>(Clock::now() - tp).count();
       for (auto& s : slots) {
         Request& r = *s.r;
         const int64_t o = f->seg_off[s.seg], len = f->seg_off[s.seg + 1] - o;
@@ -454,6 +464,9 @@ spand_status spand_server_stats(spand_server_t s, int64_t* counters) {
   counters[3] = s->factor_batches;
   counters[4] = s->factored_matrices;
   counters[5] = s->pcg_calls;
+  counters[6] = (int64_t)(s->analyze_s * 1e6);
+  counters[7] = (int64_t)(s->factor_s * 1e6);
+  counters[8] = (int64_t)(s->pcg_s * 1e6);
   return SPAND_OK;
 }
 

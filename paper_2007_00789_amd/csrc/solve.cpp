@@ -12,6 +12,10 @@ namespace spand {
 struct ApplyColour {
   ApSp* sp = nullptr;
   int32_t n_sp = 0, max_a = 0;
+  ApWyTask* wyd = nullptr;   // wide WY apply: dots and update tasks
+  ApWyTask* wyu = nullptr;
+  int32_t n_wyd = 0, n_wyu = 0;
+  int64_t usz = 0;           // u doubles per right-hand side
   ApEt* etf = nullptr;   // E tiles, forward
   ApEt* etb = nullptr;   // E tiles, backward
   int32_t n_etf = 0, n_etb = 0, max_nf = 0;
@@ -36,7 +40,8 @@ struct ApplyProg {
   std::vector<ApplyStep> steps;  // in forward order (depth ... 0)
   int64_t scratch = 0;           // doubles per right-hand side
   int64_t pscratch = 0;          // partial sums of the backward E tiles, per right-hand side
-  DevBuf T, P;
+  int64_t uscratch = 0;          // u vectors of the wide WY apply, per right-hand side
+  DevBuf T, P, U;
 };
 
 FactorObj::~FactorObj() { delete prog; }
@@ -143,7 +148,8 @@ void build_apply(Ctx& C, FactorObj& F) {
         ApplyColour& ac = as.colours[colour];
         std::vector<ApSp> sps;
         std::vector<ApEt> etf, etb;
-        int64_t csz = 0, psz = 0;
+        std::vector<ApWyTask> wyd, wyu;
+        int64_t csz = 0, psz = 0, usz = 0;
         std::vector<int64_t> ptoff(nc, -1);
         for (int p : st.order) {
           if (st.colour[p] != colour || R.n0[p] == 0) continue;
@@ -151,6 +157,7 @@ void build_apply(Ctx& C, FactorObj& F) {
           d.V = R.V[p];
           d.tau = R.tau[p];
           d.T = R.T[p];
+          d.VT = R.VT[p];
           d.pos = dpos[p];
           d.nbr_pos = F.meta.upload(R.sp_nbr_pos[p]);
           d.a = R.n0[p];
@@ -190,11 +197,24 @@ void build_apply(Ctx& C, FactorObj& F) {
             }
             ac.max_nf = std::max(ac.max_nf, nf);
           }
+          d.uoff = usz;
+          if (d.nref > 0) {
+            const int32_t idx = (int32_t)sps.size();
+            for (int j0 = 0; j0 < d.nref; j0 += kApWyCB) wyd.push_back({idx, j0});
+            for (int i0 = 0; i0 < d.a; i0 += kApWyRB) wyu.push_back({idx, i0});
+            usz += d.nref;
+          }
           sps.push_back(d);
           ac.max_a = std::max(ac.max_a, d.a);
         }
         prog->scratch = std::max(prog->scratch, csz);
         prog->pscratch = std::max(prog->pscratch, psz);
+        prog->uscratch = std::max(prog->uscratch, usz);
+        ac.usz = usz;
+        ac.wyd = F.meta.upload(wyd);
+        ac.wyu = F.meta.upload(wyu);
+        ac.n_wyd = (int32_t)wyd.size();
+        ac.n_wyu = (int32_t)wyu.size();
         ac.sp = F.meta.upload(sps);
         ac.n_sp = (int32_t)sps.size();
         ac.etf = F.meta.upload(etf);
@@ -255,8 +275,7 @@ static int64_t apply_lds_need(const ApplyProg& pg, int32_t nrhs) {
                               (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
                               (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs});
     for (const ApplyColour& ac : as.colours)
-      need = std::max<int64_t>({need, (int64_t)ac.max_a * (3 * nrhs + 8 * (nrhs > 4 ? 2 : 4)),
-                                (int64_t)ac.max_n * nrhs, (int64_t)ac.max_nf * nrhs + 2048,
+      need = std::max<int64_t>({need, (int64_t)ac.max_n * nrhs, (int64_t)ac.max_nf * nrhs + 2048,
                                 (int64_t)kEtTileB * nrhs});
   }
   return need;
@@ -283,12 +302,16 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
   ApplyProg& pg = *F.prog;
   double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
   double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
+  double* U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * nrhs * sizeof(double)));
   if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
     SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
     SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
     for (const ApplyColour& ac : as.colours) {
-      SPAND_PROF(C, "k_ap_sp_fwd", launch_ap_sp_fwd(ac.sp, ac.n_sp, y, n, nrhs, ac.max_a, s));
+      SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(ac.wyd, ac.n_wyd, ac.sp, y, n, nrhs, nullptr,
+                                                      U, ac.usz, 1, s));
+      SPAND_PROF(C, "k_ap_wy_update", launch_ap_wy_update(ac.wyu, ac.n_wyu, ac.sp, y, n, nrhs,
+                                                          nullptr, U, ac.usz, 1, s));
       SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_etf, y, n, nrhs, T, ac.max_nf, s));
       SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s));
     }
@@ -297,7 +320,10 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
     const ApplyStep& as = *it;
     for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c) {
       SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_etb, y, n, nrhs, Pp, s));
-      SPAND_PROF(C, "k_ap_sp_bwd", launch_ap_sp_bwd(c->sp, c->n_sp, y, n, nrhs, Pp, c->max_a, s));
+      SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(c->wyd, c->n_wyd, c->sp, y, n, nrhs, Pp, U,
+                                                      c->usz, 0, s));
+      SPAND_PROF(C, "k_ap_wy_update", launch_ap_wy_update(c->wyu, c->n_wyu, c->sp, y, n, nrhs, Pp,
+                                                          U, c->usz, 0, s));
     }
     SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
     SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));

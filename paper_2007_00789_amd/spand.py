@@ -89,6 +89,7 @@ SIGNATURES = {
     "spand_server_error": (C.c_char_p, [_P]),
     "spand_server_destroy": (None, [_P]),
     "spand_profile": (C.c_int, [_P, C.c_int32]),
+    "spand_profile_only": (C.c_int, [_P, C.c_char_p]),
     "spand_profile_entries": (C.c_int, [_P, _I32P]),
     "spand_profile_entry": (C.c_int, [_P, C.c_int32, C.c_char_p, C.c_int32, _DP, _I64P, _DP]),
 }
@@ -164,8 +165,10 @@ class Context:
         if st != SPAND_OK:
             raise SpandError(st, self.lib.spand_last_error(self.h).decode())
 
-    def profile(self, enable: bool):
-        """spand_profile: clear and start (or stop) per-kernel event timing."""
+    def profile(self, enable: bool, only: str | None = None):
+        """spand_profile: clear and start (or stop) per-kernel event timing;
+        only: time the launches of this kernel name alone."""
+        self._check(self.lib.spand_profile_only(self.h, only.encode() if only else None))
         self._check(self.lib.spand_profile(self.h, 1 if enable else 0))
 
     def profile_entries(self) -> dict:
@@ -412,8 +415,10 @@ class Server:
         return x.reshape(nrhs, n).T, it, rr, lat.value, st
 
     def stats(self) -> dict:
-        c = np.zeros(6, dtype=np.int64)
+        c = np.zeros(9, dtype=np.int64)
         self.lib.spand_server_stats(self.h, c.ctypes.data_as(_I64P))
         keys = ["resident_bytes", "resident_factors", "queued", "factor_batches",
                 "factored_matrices", "pcg_calls"]
-        return {k: int(v) for k, v in zip(keys, c)}
+        out = {k: int(v) for k, v in zip(keys, c)}
+        out.update(analyze_s=c[6] * 1e-6, factor_s=c[7] * 1e-6, pcg_s=c[8] * 1e-6)
+        return out
