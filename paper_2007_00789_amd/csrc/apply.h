@@ -65,7 +65,7 @@ struct ApWyTask {
 };
 constexpr int kApWyThreads = 256;
 constexpr int kApWyCB = 8;
-constexpr int kApWyRB = 32;
+constexpr int kApWyRB = 16;
 
 // One tile of at most kEtTileF (forward) or kEtTileB (backward) columns of an interface's E (second order:
 // E = rows f0.. of Q^T W, stored transposed, element (c, i) = E[i, c] at
@@ -93,9 +93,6 @@ void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, in
                        double* T, int32_t max_n, hipStream_t s);
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
                       int32_t nrhs, const double* T, int32_t max_n, hipStream_t s);
-// z_p <- Q_p^T z_p (one workgroup per interface)
-void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      int32_t max_a, hipStream_t s);
 // wide WY apply, dots then update (fwd = 1: Q^T; 0: Q, after the partial
 // sums P); U: the colour's u vectors, usz doubles per right-hand side
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
@@ -109,9 +106,6 @@ void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz
                       double* T, int32_t max_nf, hipStream_t s);
 void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* P, hipStream_t s);
-// y_f -= sum of the interface's E-tile partial sums (fixed order); y_p <- Q_p y_p
-void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      const double* P, int32_t max_a, hipStream_t s);
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s);
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,

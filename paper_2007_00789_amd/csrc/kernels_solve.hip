@@ -11,9 +11,8 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kT = 256;
-constexpr int kST = 512;   // threads of the sparsification apply kernels
-// right-hand sides per pass of the WY products (bounds their LDS partial sums)
-__host__ __device__ constexpr int sp_rb(int nrhs) { return nrhs > 4 ? 2 : 4; }
+constexpr int kST = 512;   // threads of the E-tile kernels
+// right-hand sides per pass of the interior GEMVs (bounds their LDS partial sums)
 __host__ __device__ constexpr int ap_rb(int nrhs) { return nrhs > 4 ? 2 : 4; }
 
 // DPP move of a double (two 32-bit halves); lanes whose source is invalid read 0.
@@ -102,17 +101,18 @@ __device__ void wg_rowsum_gather(const double* __restrict__ M, int64_t ld, int r
 }
 
 // ---------------------------------------------------------------------------
-// Helpers for NT-thread workgroups (the sparsification apply uses 512).
+// Helpers for NT-thread workgroups.
 // ---------------------------------------------------------------------------
 // The GEMV helpers below keep many loads in flight per lane: a lane loads
 // every 64-row chunk it needs (RC chunks, 64*RC rows per block) for a small
 // batch of columns before the first FMA, so a workgroup's product costs a few
-// memory round trips instead of one per chunk.  Interior kernels (many small
-// workgroups) use a low-register shape, the WY kernels a deep one.
-#define SP_COLDOTS wgt_coldots<NT, 5, 2>
-#define SP_GEMV wgt_gemv_acc<NT, 5, 2>
-#define IN_COLDOTS wgt_coldots<kT, 1, 8>
-#define IN_GEMV wgt_gemv_acc<kT, 1, 8>
+// memory round trips instead of one per chunk.  The interior and scaling
+// kernels come in two shapes: CB = 8 columns per wave batch (few large
+// workgroups: fewer round trips) and CB = 2 (many small workgroups: 76 VGPRs
+// instead of 248, so four times the waves per SIMD).
+constexpr int kApWide = 8, kApNarrow = 2;
+// launches of at least this many workgroups take the narrow shape
+constexpr int kApNarrowFrom = 512;
 // out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx]: one wave per batch of
 // CB columns, lanes over rows (coalesced, RC chunks of 64 per block), one wave
 // reduction per output.
@@ -213,30 +213,10 @@ __device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows,
   }
 }
 
-// x <- Q^T x (trans) or Q x with Q = I - V T V^T (V a x nref, ld a, zero above
-// its unit diagonal; T nref x nref upper triangular, zero below).  x, u, u2,
-// part in LDS (part: NW x a x sp_rb(nrhs)).  Ends with a barrier.
-template <int NT>
-__device__ void wgt_apply_wy(const double* __restrict__ V, const double* __restrict__ T, int a,
-                             int nref, double* __restrict__ x, int nrhs, double* __restrict__ u,
-                             double* __restrict__ u2, double* __restrict__ part, bool trans) {
-  if (nref == 0) return;
-  SP_COLDOTS(V, a, a, nref, x, a, nrhs, u, nref);                 // u = V^T x
-  __syncthreads();
-  if (trans) {
-    SP_COLDOTS(T, nref, nref, nref, u, nref, nrhs, u2, nref);     // u2 = T^T u
-    __syncthreads();
-  } else {
-    for (int idx = threadIdx.x; idx < nref * nrhs; idx += NT) u2[idx] = 0.0;
-    __syncthreads();
-    SP_GEMV(T, nref, nref, nref, u, nref, nrhs, 1.0, u2, nref, part, sp_rb(nrhs));   // u2 = T u
-  }
-  SP_GEMV(V, a, a, nref, u2, nref, nrhs, -1.0, x, a, part, sp_rb(nrhs));   // x -= V u2
-}
-
 // ---------------------------------------------------------------------------
 // forward interior: z_s <- L^{-1} z_s ; t = G^T z_s
 // ---------------------------------------------------------------------------
+template <int CB>
 __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z, int64_t ldz,
                                                    int nrhs, double* T) {
   extern __shared__ double sm[];
@@ -252,13 +232,13 @@ __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z
   }
   __syncthreads();
   // ys = L^{-1} xs (L^{-1} is stored with zeros above its diagonal)
-  IN_GEMV(d.Linv, n, n, n, xs, n, nrhs, 1.0, ys, n, part, ap_rb(nrhs));
+  wgt_gemv_acc<kT, 1, CB>(d.Linv, n, n, n, xs, n, nrhs, 1.0, ys, n, part, ap_rb(nrhs));
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     z[d.pos[i] + r * ldz] = ys[idx];
   }
   if (k == 0) return;
-  IN_COLDOTS(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
+  wgt_coldots<kT, 1, CB>(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -288,32 +268,6 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
 #pragma unroll 8
     for (int m = 0; m <= i; ++m) acc = fma(d.Zinv[i + (int64_t)m * n], xs[m + r * n], acc);
     z[d.pos[i] + r * ldz] = acc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// forward sparsification: z_p <- Q^T z_p
-// LDS: xs (a x nrhs) | u, u2 (nref x nrhs each)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kST) void k_ap_sp_fwd(const ApSp* descs, double* z, int64_t ldz,
-                                                   int nrhs) {
-  extern __shared__ double sm[];
-  const ApSp d = descs[blockIdx.x];
-  const int a = d.a;
-  if (d.nref == 0) return;
-  double* xs = sm;
-  double* u = sm + a * nrhs;
-  double* u2 = u + d.nref * nrhs;
-  double* part = u2 + d.nref * nrhs;
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
-    const int i = idx % a, r = idx / a;
-    xs[idx] = z[d.pos[i] + r * ldz];
-  }
-  __syncthreads();
-  wgt_apply_wy<kST>(d.V, d.T, a, d.nref, xs, nrhs, u, u2, part, true);
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
-    const int i = idx % a, r = idx / a;
-    z[d.pos[i] + r * ldz] = xs[idx];
   }
 }
 
@@ -423,37 +377,6 @@ __global__ __launch_bounds__(kST) void k_ap_et_bwd(const ApEt* descs, const doub
 }
 
 // ---------------------------------------------------------------------------
-// backward sparsification: y_f -= E y_W (sum of the tiles' partial sums, in
-// tile order) ; y_p <- Q y_p
-// LDS: xs (a x nrhs) | u, u2 (nref x nrhs)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kST) void k_ap_sp_bwd(const ApSp* descs, double* z, int64_t ldz,
-                                                   int nrhs, const double* P) {
-  extern __shared__ double sm[];
-  const ApSp d = descs[blockIdx.x];
-  const int a = d.a;
-  const int nf = d.f1 - d.f0;
-  double* xs = sm;
-  double* u = sm + a * nrhs;
-  double* u2 = u + d.nref * nrhs;
-  double* part = u2 + d.nref * nrhs;
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
-    const int i = idx % a, r = idx / a;
-    double v = z[d.pos[i] + r * ldz];
-    if (i >= d.f0 && i < d.f1)
-      for (int t = 0; t < d.ntiles; ++t)
-        v -= P[(d.part0 + (int64_t)t * nf) * nrhs + (i - d.f0) + (int64_t)r * nf];
-    xs[idx] = v;
-  }
-  __syncthreads();
-  wgt_apply_wy<kST>(d.V, d.T, a, d.nref, xs, nrhs, u, u2, part, false);
-  for (int idx = threadIdx.x; idx < a * nrhs; idx += kST) {
-    const int i = idx % a, r = idx / a;
-    z[d.pos[i] + r * ldz] = xs[idx];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // wide WY apply (one colour): Q^T x = x - V ((VT)^T x) forward, Q y = y - VT
 // (V^T y) backward, each as a dots launch and an update launch spread over
 // column blocks and row blocks of every interface of the colour.
@@ -472,46 +395,54 @@ __device__ __forceinline__ double wy_in(const ApSp& d, const double* __restrict_
 }
 
 // u[j0 + c] = sum_i M[i, j0 + c] x_i for kApWyCB columns: threads over rows
-// (columns of M are contiguous), wave sums, then the waves in order.
+// (columns of M are contiguous), two rows per thread in flight, wave sums,
+// then the waves in order.
 __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tasks, const ApSp* descs,
-                                                          const double* __restrict__ z, int64_t ldz,
-                                                          int nrhs, const double* __restrict__ P,
-                                                          double* __restrict__ U, int64_t usz,
-                                                          int fwd) {
-  constexpr int NW = kApWyThreads / kWave;
-  __shared__ double red[NW][kApWyCB * 4];
+                                                            const double* __restrict__ z, int64_t ldz,
+                                                            int nrhs, const double* __restrict__ P,
+                                                            double* __restrict__ U, int64_t usz,
+                                                            int fwd) {
+  constexpr int NW = kApWyThreads / kWave, CB = kApWyCB;
+  __shared__ double red[NW][CB * 4];
   const ApWyTask tk = tasks[blockIdx.x];
   const ApSp d = descs[tk.sp];
   const double* __restrict__ M = fwd ? d.VT : d.V;
-  const int a = d.a, j0 = tk.i0, cn = min(kApWyCB, d.nref - j0);
+  const int a = d.a, j0 = tk.i0, cn = min(CB, d.nref - j0);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const double* Pp = fwd ? nullptr : P;
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
-    double acc[kApWyCB][4];
+    double acc[CB][4];
 #pragma unroll
-    for (int c = 0; c < kApWyCB; ++c)
+    for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) acc[c][rr] = 0.0;
-    for (int i = threadIdx.x; i < a; i += kApWyThreads) {
-      double x[4];
+    for (int i0 = threadIdx.x; i0 < a; i0 += 2 * kApWyThreads) {
+      double x[2][4], m[2][CB];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) x[rr] = r0 + rr < nrhs ? wy_in(d, z, ldz, Pp, i, r0 + rr, nrhs) : 0.0;
+      for (int t = 0; t < 2; ++t) {
+        const int i = i0 + t * kApWyThreads;
 #pragma unroll
-      for (int c = 0; c < kApWyCB; ++c) {
-        const double m = c < cn ? M[i + (int64_t)(j0 + c) * a] : 0.0;
+        for (int rr = 0; rr < 4; ++rr)
+          x[t][rr] = (i < a && r0 + rr < nrhs) ? wy_in(d, z, ldz, Pp, i, r0 + rr, nrhs) : 0.0;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) acc[c][rr] = fma(m, x[rr], acc[c][rr]);
+        for (int c = 0; c < CB; ++c) m[t][c] = (i < a && c < cn) ? M[i + (int64_t)(j0 + c) * a] : 0.0;
       }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) acc[c][rr] = fma(m[t][c], x[t][rr], acc[c][rr]);
     }
 #pragma unroll
-    for (int c = 0; c < kApWyCB; ++c)
+    for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const double v = wave_sum(acc[c][rr]);
         if (lane == 0) red[wid][c * 4 + rr] = v;
       }
     __syncthreads();
-    if (threadIdx.x < kApWyCB * 4) {
+    if (threadIdx.x < CB * 4) {
       const int c = threadIdx.x / 4, rr = threadIdx.x % 4;
       if (c < cn && r0 + rr < nrhs) {
         double v = 0.0;
@@ -524,41 +455,61 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tas
   }
 }
 
-// x_i -= sum_j N[i, j] u_j for kApWyRB rows: 32 rows x 8 column groups (a wave
-// reads 2 x 32 consecutive rows of a column), groups summed in order.
+// x_i -= sum_j N[i, j] u_j for kApWyRB rows: 16 rows x 16 column groups (a
+// wave reads 4 x 16 consecutive rows of 4 columns), eight columns per thread
+// in flight, u staged in LDS in chunks, the groups summed in order.
+constexpr int kApWyUChunk = 512;
 __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* tasks,
                                                             const ApSp* descs, double* z,
                                                             int64_t ldz, int nrhs,
                                                             const double* __restrict__ P,
                                                             const double* __restrict__ U,
                                                             int64_t usz, int fwd) {
-  constexpr int NG = kApWyThreads / kApWyRB;
-  __shared__ double red[NG][kApWyRB * 4];
+  constexpr int RB = kApWyRB, NG = kApWyThreads / RB, UC = kApWyUChunk;
+  __shared__ double red[NG][RB * 4];
+  __shared__ double us[UC * 4];
   const ApWyTask tk = tasks[blockIdx.x];
   const ApSp d = descs[tk.sp];
   const double* __restrict__ N = fwd ? d.V : d.VT;
   const int a = d.a, nref = d.nref;
-  const int rl = threadIdx.x % kApWyRB, g = threadIdx.x / kApWyRB;
+  const int rl = threadIdx.x % RB, g = threadIdx.x / RB;
   const int i = tk.i0 + rl;
   const double* u = U + d.uoff;
   const double* Pp = fwd ? nullptr : P;
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nr = min(4, nrhs - r0);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < a) {
-#pragma unroll 4
-      for (int j = g; j < nref; j += NG) {
-        const double nv = N[i + (int64_t)j * a];
+    for (int jc = 0; jc < nref; jc += UC) {
+      const int jn = min(UC, nref - jc);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < jn * 4; idx += kApWyThreads) {
+        const int jj = idx / 4, rr = idx % 4;
+        us[idx] = rr < nr ? u[jc + jj + (int64_t)(r0 + rr) * usz] : 0.0;
+      }
+      __syncthreads();
+      if (i < a) {
+        for (int j = g; j < jn; j += NG * 8) {
+          double nv[8];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-          if (r0 + rr < nrhs) acc[rr] = fma(nv, u[j + (int64_t)(r0 + rr) * usz], acc[rr]);
+          for (int t = 0; t < 8; ++t) {
+            const int jj = j + t * NG;
+            nv[t] = jj < jn ? N[i + (int64_t)(jc + jj) * a] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int jj = min(j + t * NG, jn - 1);   // nv[t] is 0 past the end
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) acc[rr] = fma(nv[t], us[jj * 4 + rr], acc[rr]);
+          }
+        }
       }
     }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) red[g][rl * 4 + rr] = acc[rr];
     __syncthreads();
-    if (threadIdx.x < kApWyRB * 4) {
+    if (threadIdx.x < RB * 4) {
       const int r2 = threadIdx.x / 4, rr = threadIdx.x % 4, i2 = tk.i0 + r2;
-      if (i2 < a && r0 + rr < nrhs) {
+      if (i2 < a && rr < nr) {
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NG; ++q) v += red[q][r2 * 4 + rr];
@@ -570,6 +521,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* t
 }
 
 // backward scaling: y_w <- Zinv^T y_w (column dots of Zinv)
+template <int CB>
 __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, double* z, int64_t ldz,
                                                      int nrhs) {
   extern __shared__ double sm[];
@@ -582,7 +534,7 @@ __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, doubl
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  IN_COLDOTS(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
+  wgt_coldots<kT, 1, CB>(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -592,6 +544,7 @@ __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, doubl
 
 // backward interior: y_s <- L^{-T} (y_s - G y_W)
 // LDS: us (n x nrhs) | ys (n x nrhs) | part (kNW x n x nrhs) | stage (kChunk x nrhs)
+template <int CB>
 __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z, int64_t ldz,
                                                    int nrhs) {
   extern __shared__ double sm[];
@@ -607,7 +560,7 @@ __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z
     us[idx] = z[d.pos[i] + r * ldz] - (k > 0 ? ys[idx] : 0.0);
   }
   __syncthreads();
-  IN_COLDOTS(d.Linv, n, n, n, us, n, nrhs, ys, n);
+  wgt_coldots<kT, 1, CB>(d.Linv, n, n, n, us, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -710,24 +663,17 @@ inline unsigned grid_for(int64_t n, int bs) {
 void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        double* T, int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_int_fwd, dim3(count), dim3(kT),
-                     ((size_t)2 * max_n * nrhs + (size_t)kNW * max_n * ap_rb(nrhs)) * sizeof(double),
-                     s, d, z, ldz, nrhs, T);
+  const size_t lds = ((size_t)2 * max_n * nrhs + (size_t)kNW * max_n * ap_rb(nrhs)) * sizeof(double);
+  if (count >= kApNarrowFrom)
+    hipLaunchKernelGGL(k_ap_int_fwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+  else
+    hipLaunchKernelGGL(k_ap_int_fwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
 }
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
                       int32_t nrhs, const double* T, int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ap_gather, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
                      d, src, z, ldz, nrhs, T);
-}
-size_t sp_lds(int32_t max_a, int32_t nrhs) {
-  // xs (a) + u, u2 (nref <= a) per rhs, + part (kST/64 x a x sp_rb)
-  return ((size_t)max_a * nrhs * 3 + (size_t)(kST / kWave) * max_a * sp_rb(nrhs)) * sizeof(double);
-}
-void launch_ap_sp_fwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      int32_t max_a, hipStream_t s) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_fwd, dim3(count), dim3(kST), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs);
 }
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* T, int32_t max_nf, hipStream_t s) {
@@ -740,11 +686,6 @@ void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kST), (size_t)kEtTileB * nrhs * sizeof(double),
                      s, d, z, ldz, nrhs, P);
-}
-void launch_ap_sp_bwd(const ApSp* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                      const double* P, int32_t max_a, hipStream_t s) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_sp_bwd, dim3(count), dim3(kST), sp_lds(max_a, nrhs), s, d, z, ldz, nrhs, P);
 }
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
                        int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,
@@ -763,15 +704,20 @@ void launch_ap_wy_update(const ApWyTask* t, int32_t count, const ApSp* d, double
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                          int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_scale_bwd, dim3(count), dim3(kT), 2 * (size_t)max_n * nrhs * sizeof(double),
-                     s, d, z, ldz, nrhs);
+  const size_t lds = 2 * (size_t)max_n * nrhs * sizeof(double);
+  if (count >= kApNarrowFrom)
+    hipLaunchKernelGGL(k_ap_scale_bwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  else
+    hipLaunchKernelGGL(k_ap_scale_bwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
 }
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        int32_t max_n, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_int_bwd, dim3(count), dim3(kT),
-                     ((size_t)(2 + kNW) * max_n * nrhs + (size_t)kChunk * nrhs) * sizeof(double), s,
-                     d, z, ldz, nrhs);
+  const size_t lds = ((size_t)(2 + kNW) * max_n * nrhs + (size_t)kChunk * nrhs) * sizeof(double);
+  if (count >= kApNarrowFrom)
+    hipLaunchKernelGGL(k_ap_int_bwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  else
+    hipLaunchKernelGGL(k_ap_int_bwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
 }
 
 void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,
