@@ -1,5 +1,7 @@
 """Full-size parity on the benchmark workload (3D 7-point Laplacian 64^3,
-n = 262,144, depth 12, skip 4), in the launch configuration bench.py times.
+n = 262,144, depth 12, skip 4), in the launch configuration bench.py times,
+and on the high-contrast workload (3D FV diffusion 128^3, k = 10^U[-3,3],
+n = 2,097,152, depth 15, skip 4).
 
 Expected values are the FP64 oracle's, stored in tests/golden/ by
 tests/golden/make_golden.py (which calls only oracle/).  Bars:
@@ -20,7 +22,7 @@ from synthetic import workload, rhs
 gpu = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = ["lap3d_64_SO_1e-2", "lap3d_64_FO_1e-2", "lap3d_64_SO_1e-1"]
+CASES = ["lap3d_64_SO_1e-2", "lap3d_64_FO_1e-2", "lap3d_64_SO_1e-1", "fv3d_128_SO_1e-2"]
 
 
 @pytest.fixture(scope="module")
@@ -32,8 +34,15 @@ def ctx():
 
 
 @pytest.fixture(scope="module")
-def problem():
-    return workload("lap3d_64")
+def problems():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache.clear()   # one full-size problem held at a time
+            cache[name] = workload(name)
+        return cache[name]
+    return get
 
 
 def _dev(a):
@@ -42,14 +51,14 @@ def _dev(a):
 
 @gpu
 @pytest.mark.parametrize("case", CASES)
-def test_full_size_against_stored_oracle(ctx, problem, case):
+def test_full_size_against_stored_oracle(ctx, problems, case):
     from paper_2007_00789_amd import spand
     path = os.path.join(GOLDEN, case + ".json")
     if not os.path.exists(path):
         pytest.skip(f"{case}: no stored oracle values")
     with open(path) as f:
         g = json.load(f)
-    p, w = problem
+    p, w = problems(g["workload"])
     print(f"full size {case}", flush=True)
     opts = spand.make_opts(depth=g["depth"], skip=g["skip"], eps=g["eps"], scheme=g["scheme"])
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
