@@ -27,6 +27,35 @@ struct ApInt {
   int32_t n, k;
 };
 
+// Split GEMV over many workgroups, for the large interiors of the top levels
+// (one workgroup per interior leaves most of the chip idle there).  A
+// descriptor is one matrix product with its operand and result addresses:
+//  rows kernel (tasks of kApMvRB rows): out_i = base_i - sum_j M[i, j] x_j
+//    (base from z at bpos; without bpos, out_i = + sum_j M[i, j] x_j)
+//  cols kernel (tasks of 4 x kApMvCB columns): out_c = sum_i M[i, c] x_i;
+//    the task of column 0 also writes x_i to z at wpos when wpos is set.
+// x_j: z[xpos[j] + r ldz] if xpos, else S[xoff nrhs + j + r xld];
+// out: z[opos[i] + r ldz] if opos, else O[ooff nrhs + i + r old]
+// (scratch offsets in units of one right-hand side, as the T scratch).
+// tri = 1: M is lower triangular (zeros above the diagonal are skipped).
+struct ApMv {
+  const double* M;
+  const int32_t* xpos;
+  const int32_t* opos;
+  const int32_t* bpos;
+  const int32_t* wpos;
+  int64_t ld, xoff, xld, ooff, old;
+  int32_t rows, cols, tri, pad;
+};
+struct ApMvTask {
+  int32_t mv;   // descriptor
+  int32_t i0;   // first row (rows kernel) or column (cols kernel)
+};
+constexpr int kApMvRB = 16;
+constexpr int kApMvCB = 8;
+// interiors per step below which the split kernels are used
+constexpr int kApSplitBelow = 512;
+
 struct ApSrc {             // one slice of a scratch vector subtracted from a target
   int64_t toff;            // scratch offset of the producer (units of one rhs)
   int32_t col, ld;         // slice start inside the producer's vector, producer length
@@ -93,6 +122,11 @@ void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, in
                        double* T, int32_t max_n, hipStream_t s);
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
                       int32_t nrhs, const double* T, int32_t max_n, hipStream_t s);
+// split GEMV kernels (S: operand scratch, O: result scratch)
+void launch_ap_mv_rows(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
+                       int32_t nrhs, const double* S, double* O, hipStream_t s);
+void launch_ap_mv_cols(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
+                       int32_t nrhs, const double* S, double* O, hipStream_t s);
 // wide WY apply, dots then update (fwd = 1: Q^T; 0: Q, after the partial
 // sums P); U: the colour's u vectors, usz doubles per right-hand side
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,

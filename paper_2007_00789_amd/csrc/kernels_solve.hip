@@ -520,6 +520,132 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* t
   }
 }
 
+// ---------------------------------------------------------------------------
+// split GEMV (large interiors): rows and column-dot kernels over ApMv tasks
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mv_x(const ApMv& d, const double* __restrict__ z, int64_t ldz,
+                                       const double* __restrict__ S, int nrhs, int j, int r) {
+  return d.xpos ? z[d.xpos[j] + (int64_t)r * ldz] : S[d.xoff * nrhs + j + (int64_t)r * d.xld];
+}
+
+// kApMvRB rows per task: 16 rows x 16 column groups, x staged in LDS in
+// chunks, eight columns per thread in flight, groups summed in order.
+constexpr int kApMvChunk = 512;
+__global__ __launch_bounds__(kApWyThreads) void k_ap_mv_rows(const ApMvTask* tasks, const ApMv* descs,
+                                                            double* z, int64_t ldz, int nrhs,
+                                                            const double* __restrict__ S,
+                                                            double* __restrict__ O) {
+  constexpr int RB = kApMvRB, NG = kApWyThreads / RB, UC = kApMvChunk;
+  __shared__ double red[NG][RB * 4];
+  __shared__ double xs[UC * 4];
+  const ApMvTask tk = tasks[blockIdx.x];
+  const ApMv d = descs[tk.mv];
+  const int rl = threadIdx.x % RB, g = threadIdx.x / RB;
+  const int i = tk.i0 + rl;
+  const int jmax = d.tri ? min(d.cols, tk.i0 + RB) : d.cols;
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nr = min(4, nrhs - r0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int jc = 0; jc < jmax; jc += UC) {
+      const int jn = min(UC, jmax - jc);
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < jn * 4; idx += kApWyThreads) {
+        const int jj = idx / 4, rr = idx % 4;
+        xs[idx] = rr < nr ? mv_x(d, z, ldz, S, nrhs, jc + jj, r0 + rr) : 0.0;
+      }
+      __syncthreads();
+      if (i < d.rows) {
+        for (int j = g; j < jn; j += NG * 8) {
+          double mv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int jj = j + t * NG;
+            mv[t] = jj < jn ? d.M[i + (int64_t)(jc + jj) * d.ld] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int jj = min(j + t * NG, jn - 1);   // mv[t] is 0 past the end
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) acc[rr] = fma(mv[t], xs[jj * 4 + rr], acc[rr]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) red[g][rl * 4 + rr] = acc[rr];
+    __syncthreads();
+    if (threadIdx.x < RB * 4) {
+      const int r2 = threadIdx.x / 4, rr = threadIdx.x % 4, i2 = tk.i0 + r2;
+      if (i2 < d.rows && rr < nr) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) v += red[q][r2 * 4 + rr];
+        if (d.bpos) v = z[d.bpos[i2] + (int64_t)(r0 + rr) * ldz] - v;
+        if (d.opos) z[d.opos[i2] + (int64_t)(r0 + rr) * ldz] = v;
+        else O[d.ooff * nrhs + i2 + (int64_t)(r0 + rr) * d.old] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 4 x kApMvCB columns per task, one wave per kApMvCB columns: lanes over rows
+// (columns of M are contiguous), two rows per lane in flight, one wave sum per
+// output.
+__global__ __launch_bounds__(kApWyThreads) void k_ap_mv_cols(const ApMvTask* tasks, const ApMv* descs,
+                                                            double* z, int64_t ldz, int nrhs,
+                                                            const double* __restrict__ S,
+                                                            double* __restrict__ O) {
+  constexpr int CB = kApMvCB;
+  const ApMvTask tk = tasks[blockIdx.x];
+  const ApMv d = descs[tk.mv];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (d.wpos && tk.i0 == 0)
+    for (int idx = threadIdx.x; idx < d.rows * nrhs; idx += kApWyThreads) {
+      const int i = idx % d.rows, r = idx / d.rows;
+      z[d.wpos[i] + (int64_t)r * ldz] = mv_x(d, z, ldz, S, nrhs, i, r);
+    }
+  const int c0 = tk.i0 + wid * CB, cn = min(CB, d.cols - c0);
+  if (cn <= 0) return;
+  const int i_lo = d.tri ? c0 : 0;
+  for (int r0 = 0; r0 < nrhs; r0 += 4) {
+    double acc[CB][4];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[c][rr] = 0.0;
+    for (int ib = i_lo + lane; ib < d.rows; ib += 2 * kWave) {
+      double x[2][4], m[2][CB];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = ib + t * kWave;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          x[t][rr] = (i < d.rows && r0 + rr < nrhs) ? mv_x(d, z, ldz, S, nrhs, i, r0 + rr) : 0.0;
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+          m[t][c] = (i < d.rows && c < cn) ? d.M[i + (int64_t)(c0 + c) * d.ld] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) acc[c][rr] = fma(m[t][c], x[t][rr], acc[c][rr]);
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double v = wave_sum(acc[c][rr]);
+        if (lane == 0 && c < cn && r0 + rr < nrhs) {
+          if (d.opos) z[d.opos[c0 + c] + (int64_t)(r0 + rr) * ldz] = v;
+          else O[d.ooff * nrhs + c0 + c + (int64_t)(r0 + rr) * d.old] = v;
+        }
+      }
+  }
+}
+
 // backward scaling: y_w <- Zinv^T y_w (column dots of Zinv)
 template <int CB>
 __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, double* z, int64_t ldz,
@@ -686,6 +812,16 @@ void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kST), (size_t)kEtTileB * nrhs * sizeof(double),
                      s, d, z, ldz, nrhs, P);
+}
+void launch_ap_mv_rows(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
+                       int32_t nrhs, const double* S, double* O, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_mv_rows, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
+}
+void launch_ap_mv_cols(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
+                       int32_t nrhs, const double* S, double* O, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_ap_mv_cols, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
 }
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
                        int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,

@@ -28,6 +28,11 @@ struct ApplyStep {
   int l = 0;
   ApInt* in = nullptr;
   int32_t n_in = 0, max_in = 0;
+  // large interiors: split GEMVs (forward rows + cols, backward rows + cols)
+  bool split = false;
+  ApMv* mv = nullptr;
+  ApMvTask *f1 = nullptr, *f2 = nullptr, *b1 = nullptr, *b2 = nullptr;
+  int32_t n_f1 = 0, n_f2 = 0, n_b1 = 0, n_b2 = 0;
   ApGat* gat = nullptr;
   ApSrc* src = nullptr;
   int32_t n_gat = 0, max_gat = 0;
@@ -41,7 +46,8 @@ struct ApplyProg {
   int64_t scratch = 0;           // doubles per right-hand side
   int64_t pscratch = 0;          // partial sums of the backward E tiles, per right-hand side
   int64_t uscratch = 0;          // u vectors of the wide WY apply, per right-hand side
-  DevBuf T, P, U;
+  int64_t yscratch = 0;          // interior vectors of the split GEMVs, per right-hand side
+  DevBuf T, P, U, Y;
 };
 
 FactorObj::~FactorObj() { delete prog; }
@@ -103,6 +109,50 @@ void build_apply(Ctx& C, FactorObj& F) {
     prog->scratch = std::max(prog->scratch, tsz);
     as.in = F.meta.upload(ins);
     as.n_in = (int32_t)ins.size();
+    if (as.n_in > 0 && as.n_in < kApSplitBelow) {
+      // forward: y = L^-1 x (rows) into Y; t = G^T y (cols) into T, y back to z
+      // backward: u = z - G z_W (rows) into Y; z = L^-T u (cols)
+      std::vector<ApMv> mv;
+      std::vector<ApMvTask> f1, f2, b1, b2;
+      int64_t ysz = 0;
+      for (const ApInt& d : ins) {
+        const int32_t base = (int32_t)mv.size();
+        ApMv m{};
+        m.M = d.Linv; m.ld = d.n; m.rows = d.n; m.cols = d.n; m.tri = 1;
+        m.xpos = d.pos; m.ooff = ysz; m.old = d.n;
+        mv.push_back(m);                                            // base + 0: forward rows
+        m = ApMv{};
+        m.M = d.G; m.ld = d.n; m.rows = d.n; m.cols = d.k;
+        m.xoff = ysz; m.xld = d.n; m.ooff = d.toff; m.old = d.k; m.wpos = d.pos;
+        mv.push_back(m);                                            // base + 1: forward cols
+        m = ApMv{};
+        m.M = d.G; m.ld = d.n; m.rows = d.n; m.cols = d.k;
+        m.xpos = d.nbr_pos; m.bpos = d.pos; m.ooff = ysz; m.old = d.n;
+        mv.push_back(m);                                            // base + 2: backward rows
+        m = ApMv{};
+        m.M = d.Linv; m.ld = d.n; m.rows = d.n; m.cols = d.n; m.tri = 1;
+        m.xoff = ysz; m.xld = d.n; m.opos = d.pos;
+        mv.push_back(m);                                            // base + 3: backward cols
+        for (int i0 = 0; i0 < d.n; i0 += kApMvRB) {
+          f1.push_back({base + 0, i0});
+          b1.push_back({base + 2, i0});
+        }
+        for (int c0 = 0; c0 == 0 || c0 < d.k; c0 += 4 * kApMvCB) f2.push_back({base + 1, c0});
+        for (int c0 = 0; c0 < d.n; c0 += 4 * kApMvCB) b2.push_back({base + 3, c0});
+        ysz += d.n;
+      }
+      as.split = true;
+      as.mv = F.meta.upload(mv);
+      as.f1 = F.meta.upload(f1);
+      as.f2 = F.meta.upload(f2);
+      as.b1 = F.meta.upload(b1);
+      as.b2 = F.meta.upload(b2);
+      as.n_f1 = (int32_t)f1.size();
+      as.n_f2 = (int32_t)f2.size();
+      as.n_b1 = (int32_t)b1.size();
+      as.n_b2 = (int32_t)b2.size();
+      prog->yscratch = std::max(prog->yscratch, ysz);
+    }
     // interface gathers (+ scaling)
     std::vector<ApGat> gs;
     std::vector<ApSrc> srcs;
@@ -271,9 +321,10 @@ void build_apply(Ctx& C, FactorObj& F) {
 static int64_t apply_lds_need(const ApplyProg& pg, int32_t nrhs) {
   int64_t need = 0;
   for (const ApplyStep& as : pg.steps) {
-    need = std::max<int64_t>({need, (int64_t)as.max_in * (2 * nrhs + 4 * 4),
-                              (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs,
-                              (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs});
+    if (!as.split)
+      need = std::max<int64_t>({need, (int64_t)as.max_in * (2 * nrhs + 4 * 4),
+                                (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs});
+    need = std::max<int64_t>(need, (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
     for (const ApplyColour& ac : as.colours)
       need = std::max<int64_t>({need, (int64_t)ac.max_n * nrhs, (int64_t)ac.max_nf * nrhs + 2048,
                                 (int64_t)kEtTileB * nrhs});
@@ -303,9 +354,15 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
   double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
   double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
   double* U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * nrhs * sizeof(double)));
+  double* Ys = static_cast<double*>(pg.Y.ensure(std::max<int64_t>(pg.yscratch, 1) * nrhs * sizeof(double)));
   if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
-    SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
+    if (as.split) {
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.f1, as.n_f1, as.mv, y, n, nrhs, nullptr, Ys, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.f2, as.n_f2, as.mv, y, n, nrhs, Ys, T, s));
+    } else {
+      SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
+    }
     SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
     for (const ApplyColour& ac : as.colours) {
       SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(ac.wyd, ac.n_wyd, ac.sp, y, n, nrhs, nullptr,
@@ -326,7 +383,12 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
                                                           U, c->usz, 0, s));
     }
     SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
-    SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
+    if (as.split) {
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.b1, as.n_b1, as.mv, y, n, nrhs, nullptr, Ys, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.b2, as.n_b2, as.mv, y, n, nrhs, Ys, nullptr, s));
+    } else {
+      SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
+    }
   }
 }
 
