@@ -65,7 +65,8 @@ struct ApGat {
   const int32_t* pos;      // target positions (first n)
   const double* Zinv;      // nullable: scale after the subtraction (forward only)
   int64_t src0, src1;      // range in the ApSrc list
-  int32_t n, pad;
+  int64_t yoff;            // split scaling: the difference goes to the scratch at yoff
+  int32_t n, split;        // split = 1: no scaling here (a split GEMV applies Zinv)
 };
 
 struct ApSp {
@@ -120,8 +121,10 @@ struct ApScale {
 
 void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
                        double* T, int32_t max_n, hipStream_t s);
+// Y: scratch of the split scaling (descriptors with split = 1), else unused
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
-                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s);
+                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s,
+                      double* Y = nullptr);
 // split GEMV kernels (S: operand scratch, O: result scratch)
 void launch_ap_mv_rows(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
                        int32_t nrhs, const double* S, double* O, hipStream_t s);

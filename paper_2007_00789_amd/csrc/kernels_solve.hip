@@ -245,7 +245,8 @@ __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z
 // gather: z_w -= sum of slices; optional scaling z_w <- Zinv z_w
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSrc* src, double* z,
-                                                  int64_t ldz, int nrhs, const double* T) {
+                                                  int64_t ldz, int nrhs, const double* T,
+                                                  double* Y) {
   extern __shared__ double sm[];
   const ApGat d = descs[blockIdx.x];
   const int n = d.n;
@@ -257,10 +258,11 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
       const ApSrc sv = src[e];
       acc -= T[sv.toff * nrhs + sv.col + i + (int64_t)r * sv.ld];
     }
-    xs[idx] = acc;
-    if (!d.Zinv) z[d.pos[i] + r * ldz] = acc;
+    if (d.split) Y[d.yoff * nrhs + idx] = acc;
+    else if (!d.Zinv) z[d.pos[i] + r * ldz] = acc;
+    else xs[idx] = acc;
   }
-  if (!d.Zinv) return;
+  if (!d.Zinv || d.split) return;
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -727,12 +729,14 @@ __global__ __launch_bounds__(kT) void k_dot_partial(const double* x, const doubl
   if (threadIdx.x == 0) partial[((int64_t)sg * nrhs + c) * bps + b] = acc;
 }
 
-__global__ void k_dot_final(const double* partial, int bps, int count, double* out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
+// one wave per (segment, column): lanes over the partial sums, one wave sum
+__global__ __launch_bounds__(kWave) void k_dot_final(const double* partial, int bps, int count,
+                                                     double* out) {
+  const int e = blockIdx.x;
   double s = 0.0;
-  for (int i = 0; i < bps; ++i) s += partial[(int64_t)e * bps + i];
-  out[e] = s;
+  for (int i = threadIdx.x; i < bps; i += kWave) s += partial[(int64_t)e * bps + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[e] = s;
 }
 
 __global__ void k_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
@@ -796,10 +800,10 @@ void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, in
     hipLaunchKernelGGL(k_ap_int_fwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
 }
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
-                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s) {
+                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s, double* Y) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_ap_gather, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
-                     d, src, z, ldz, nrhs, T);
+                     d, src, z, ldz, nrhs, T, Y);
 }
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
                       double* T, int32_t max_nf, hipStream_t s) {
@@ -868,7 +872,7 @@ void launch_dot(const double* x, const double* y, int64_t n, int32_t nrhs, const
   const int bps = dot_blocks(nseg);
   hipLaunchKernelGGL(k_dot_partial, dim3(bps, nseg, nrhs), dim3(kT), 0, s, x, y, n, seg_off, partial);
   const int count = nseg * nrhs;
-  hipLaunchKernelGGL(k_dot_final, dim3((count + 63) / 64), dim3(64), 0, s, partial, bps, count, out);
+  hipLaunchKernelGGL(k_dot_final, dim3(count), dim3(kWave), 0, s, partial, bps, count, out);
 }
 void launch_pcg_xr(double* x, double* r, const double* p, const double* q, const double* rho,
                    const double* pq, const int32_t* active, const int32_t* seg_id, int64_t n,

@@ -33,6 +33,12 @@ struct ApplyStep {
   ApMv* mv = nullptr;
   ApMvTask *f1 = nullptr, *f2 = nullptr, *b1 = nullptr, *b2 = nullptr;
   int32_t n_f1 = 0, n_f2 = 0, n_b1 = 0, n_b2 = 0;
+  // interface scaling by split GEMVs: forward z = Zinv (gather result) rows;
+  // backward Zinv^T z column dots into the scratch, then copied back
+  bool ssplit = false;
+  ApMv* smv = nullptr;
+  ApMvTask *sf = nullptr, *sb1 = nullptr, *sb2 = nullptr;
+  int32_t n_sf = 0, n_sb1 = 0, n_sb2 = 0;
   ApGat* gat = nullptr;
   ApSrc* src = nullptr;
   int32_t n_gat = 0, max_gat = 0;
@@ -186,6 +192,46 @@ void build_apply(Ctx& C, FactorObj& F) {
         as.max_sc = std::max(as.max_sc, n);
       }
     }
+    if (!scs.empty() && (int)scs.size() < kApSplitBelow) {
+      std::vector<ApMv> mv;
+      std::vector<ApMvTask> sf, sb1, sb2;
+      int64_t ysz = 0;
+      for (ApGat& g : gs) {
+        if (!g.Zinv) continue;
+        g.split = 1;
+        g.yoff = ysz;
+        ApMv m{};
+        m.M = g.Zinv; m.ld = g.n; m.rows = g.n; m.cols = g.n; m.tri = 1;
+        m.xoff = ysz; m.xld = g.n; m.opos = g.pos;
+        const int32_t id = (int32_t)mv.size();
+        mv.push_back(m);
+        for (int i0 = 0; i0 < g.n; i0 += kApMvRB) sf.push_back({id, i0});
+        ysz += g.n;
+      }
+      int64_t ysz2 = 0;
+      for (const ApScale& c : scs) {
+        ApMv m{};
+        m.M = c.Zinv; m.ld = c.n; m.rows = c.n; m.cols = c.n; m.tri = 1;
+        m.xpos = c.pos; m.ooff = ysz2; m.old = c.n;
+        const int32_t id = (int32_t)mv.size();
+        mv.push_back(m);
+        for (int c0 = 0; c0 < c.n; c0 += 4 * kApMvCB) sb1.push_back({id, c0});
+        m = ApMv{};
+        m.rows = c.n; m.cols = 0; m.xoff = ysz2; m.xld = c.n; m.wpos = c.pos;
+        sb2.push_back({(int32_t)mv.size(), 0});
+        mv.push_back(m);
+        ysz2 += c.n;
+      }
+      as.ssplit = true;
+      as.smv = F.meta.upload(mv);
+      as.sf = F.meta.upload(sf);
+      as.sb1 = F.meta.upload(sb1);
+      as.sb2 = F.meta.upload(sb2);
+      as.n_sf = (int32_t)sf.size();
+      as.n_sb1 = (int32_t)sb1.size();
+      as.n_sb2 = (int32_t)sb2.size();
+      prog->yscratch = std::max({prog->yscratch, ysz, ysz2});
+    }
     as.gat = F.meta.upload(gs);
     as.src = F.meta.upload(srcs);
     as.n_gat = (int32_t)gs.size();
@@ -324,7 +370,7 @@ static int64_t apply_lds_need(const ApplyProg& pg, int32_t nrhs) {
     if (!as.split)
       need = std::max<int64_t>({need, (int64_t)as.max_in * (2 * nrhs + 4 * 4),
                                 (int64_t)as.max_in * 6 * nrhs + 1024 * nrhs});
-    need = std::max<int64_t>(need, (int64_t)std::max(as.max_gat, 2 * as.max_sc) * nrhs);
+    need = std::max<int64_t>(need, (int64_t)(as.ssplit ? 0 : std::max(as.max_gat, 2 * as.max_sc)) * nrhs);
     for (const ApplyColour& ac : as.colours)
       need = std::max<int64_t>({need, (int64_t)ac.max_n * nrhs, (int64_t)ac.max_nf * nrhs + 2048,
                                 (int64_t)kEtTileB * nrhs});
@@ -363,7 +409,10 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
     } else {
       SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
     }
-    SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T, as.max_gat, s));
+    SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T,
+                                                  as.ssplit ? 0 : as.max_gat, s, Ys));
+    if (as.ssplit)
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.sf, as.n_sf, as.smv, y, n, nrhs, Ys, nullptr, s));
     for (const ApplyColour& ac : as.colours) {
       SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(ac.wyd, ac.n_wyd, ac.sp, y, n, nrhs, nullptr,
                                                       U, ac.usz, 1, s));
@@ -382,7 +431,12 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
       SPAND_PROF(C, "k_ap_wy_update", launch_ap_wy_update(c->wyu, c->n_wyu, c->sp, y, n, nrhs, Pp,
                                                           U, c->usz, 0, s));
     }
-    SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
+    if (as.ssplit) {
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb1, as.n_sb1, as.smv, y, n, nrhs, nullptr, Ys, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb2, as.n_sb2, as.smv, y, n, nrhs, Ys, nullptr, s));
+    } else {
+      SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
+    }
     if (as.split) {
       SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.b1, as.n_b1, as.mv, y, n, nrhs, nullptr, Ys, s));
       SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.b2, as.n_b2, as.mv, y, n, nrhs, Ys, nullptr, s));
