@@ -43,7 +43,9 @@ constexpr int kCW = kCT / kWave;        // waves per workgroup
 constexpr int kList = kCoopList;        // tie candidates published per workgroup
 constexpr int kXs = 2 + 2 * kList;      // exchange stride: max, count, idx[], nrm2[]
 constexpr long kSpinLimit = 1L << 24;   // ~ seconds of s_sleep before giving up
-constexpr int kRpl = 16;                // rows per lane kept in registers by the update
+constexpr int kRpl = 16;                // rows per lane kept in registers by the update (8 lanes
+constexpr int kRpl16 = 12;              // per column); with 16 and 32 lanes per column
+constexpr int kRpl32 = 8;
 
 template <int kCtrl>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -71,6 +73,69 @@ __device__ __forceinline__ double group8_sum(double v) {
   v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);  // row_half_mirror
   return v;
+}
+
+// Sum over each group of L lanes (8, 16 or 32), returned to all of them.
+template <int L>
+__device__ __forceinline__ double groupL_sum(double v) {
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  if (L == 8) {
+    v += dpp_move<0x141>(v);  // row_half_mirror
+  } else {
+    v += dpp_move<0x124>(v);  // row_ror:4
+    v += dpp_move<0x128>(v);  // row_ror:8
+    if (L == 32) v += __shfl_xor(v, 16, kWave);
+  }
+  return v;
+}
+
+// Reflector update and exact trailing norms of the columns of one workgroup
+// (Ys, a x m in LDS, ld a): L lanes per column (64 / L columns per wave, the
+// waves over the column batches), kRpl rows per lane held in registers between
+// the dot product and the update, one group reduction for each.  Column Cl
+// (the pivot, when owned) and used-up columns (nrm2 < 0) are skipped.
+template <int L, int kRpl>
+__device__ __forceinline__ void update_columns(double* Ys, double* nrm2, const double* v, int a,
+                                               int m, int j, double tau, int skip) {
+  constexpr int CPW = kWave / L;   // columns per wave
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int grp = lane / L, rl = lane % L;
+  for (int cb = wid * CPW; cb < m; cb += kCW * CPW) {
+    const int c = cb + grp;
+    const bool act = c < m && c != skip && nrm2[c] >= 0.0;
+    double* col = Ys + (int64_t)(act ? c : 0) * a;
+    double yv[kRpl];
+    double dot = 0.0;
+#pragma unroll
+    for (int t = 0; t < kRpl; ++t) {
+      const int i = j + rl + L * t;
+      const bool in = act && i < a;
+      yv[t] = in ? col[i] : 0.0;
+      dot = fma(in ? v[i] : 0.0, yv[t], dot);
+    }
+    for (int i = j + rl + L * kRpl; i < a; i += L)
+      if (act) dot = fma(v[i], col[i], dot);
+    dot = groupL_sum<L>(dot) * tau;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < kRpl; ++t) {
+      const int i = j + rl + L * t;
+      if (act && i < a) {
+        const double y = fma(-dot, v[i], yv[t]);
+        col[i] = y;
+        if (i > j) s = fma(y, y, s);
+      }
+    }
+    for (int i = j + rl + L * kRpl; i < a; i += L)
+      if (act) {
+        const double y = fma(-dot, v[i], col[i]);
+        col[i] = y;
+        s = fma(y, y, s);
+      }
+    s = groupL_sum<L>(s);
+    if (act && rl == 0) nrm2[c] = s;
+  }
 }
 
 // DPP move whose invalid source lanes read -inf (for maxima)
@@ -407,45 +472,13 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
       for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? 0.0 : v[i];
       if (tid == 0) d.tau[j] = tau;
     }
-    // fused reflector update + exact trailing norms: 8 lanes per column,
-    // 8 columns per wave; one 3-step DPP reduction serves 8 columns at once
+    // fused reflector update + exact trailing norms; the lanes per column
+    // grow as the columns per workgroup shrink, so that every wave has work
     {
-      const int grp = lane >> 3, r8 = lane & 7;
-      for (int cb = wid * 8; cb < m; cb += kCW * 8) {
-        const int c = cb + grp;
-        const bool act = c < m && !(owner && c == Cl) && nrm2[c] >= 0.0;
-        double* col = Ys + (int64_t)(act ? c : 0) * a;
-        double yv[kRpl];
-        double dot = 0.0;
-#pragma unroll
-        for (int t = 0; t < kRpl; ++t) {
-          const int i = j + r8 + 8 * t;
-          const bool in = act && i < a;
-          yv[t] = in ? col[i] : 0.0;
-          dot = fma(in ? v[i] : 0.0, yv[t], dot);
-        }
-        for (int i = j + r8 + 8 * kRpl; i < a; i += 8)
-          if (act) dot = fma(v[i], col[i], dot);
-        dot = group8_sum(dot) * tau;
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < kRpl; ++t) {
-          const int i = j + r8 + 8 * t;
-          if (act && i < a) {
-            const double y = fma(-dot, v[i], yv[t]);
-            col[i] = y;
-            if (i > j) s = fma(y, y, s);
-          }
-        }
-        for (int i = j + r8 + 8 * kRpl; i < a; i += 8)
-          if (act) {
-            const double y = fma(-dot, v[i], col[i]);
-            col[i] = y;
-            s = fma(y, y, s);
-          }
-        s = group8_sum(s);
-        if (act && r8 == 0) nrm2[c] = s;
-      }
+      const int skip = owner ? Cl : -1;
+      if (m > kCW * 4) update_columns<8, kRpl>(Ys, nrm2, v, a, m, j, tau, skip);
+      else if (m > kCW * 2) update_columns<16, kRpl16>(Ys, nrm2, v, a, m, j, tau, skip);
+      else update_columns<32, kRpl32>(Ys, nrm2, v, a, m, j, tau, skip);
     }
     if (owner) {
       for (int i = j + tid; i < a; i += kCT) Ys[i + (int64_t)Cl * a] = i == j ? beta : 0.0;
