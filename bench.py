@@ -1,7 +1,7 @@
 """Benchmark of the spaND hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps 1e-2] [--scheme SO]
-                    [--no-cpu-baseline] [--workload lap3d_64|lap2d_64|fv3d_128|batch256|serve]
+                    [--no-cpu-baseline] [--workload lap3d_64|lap2d_64|fv3d_128|batch256|serve|eig2d|table1]
 
 Workload (the metric's configuration that fits one GPU): 3D 7-point Laplacian
 on a 64^3 grid (n = 262,144), nested-dissection depth 12, skip 4, eps 1e-2,
@@ -268,6 +268,128 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_eig2d(args):
+    """Forward-error study on the 2D constant-coefficient Poisson problem
+    (Sec. 4): d = 1000 grid (n = 10^6, depth 14, skip 4), modes
+    p = floor(1.25^k) <= d, errors ||(I - M A) v_p||_2 for FO and SO at
+    eps = 0.1 and 0.01.  A v_p is formed on the host (closed-form input); each
+    factorization applies M to all modes at once on the device."""
+    import torch
+    from paper_2007_00789_amd import spand
+    from synthetic import laplacian_2d, poisson_modes, poisson_eigvec
+
+    d = args.eig_d
+    depth = max(0, int(round(np.log2(d * d / 64.0))))
+    prob = laplacian_2d(d)
+    ps = poisson_modes(d)
+    V = np.stack([poisson_eigvec(d, q)[0] for q in ps], 1)
+    lam = [poisson_eigvec(d, q)[1] for q in ps]
+    AV = prob.scipy() @ V
+    nm = len(ps)
+    ctx = spand.Context(0)
+    dx = torch.from_numpy(np.asfortranarray(AV).reshape(-1, order="F").copy()).to("cuda:0")
+    dy = torch.zeros_like(dx)
+    vals = torch.from_numpy(prob.vals).to("cuda:0")
+    errs, times = {}, {}
+    plan = None
+    for eps in (0.1, 0.01):
+        for scheme in ("FO", "SO"):
+            opts = spand.make_opts(depth=depth, skip=4, eps=eps, scheme=scheme)
+            if plan is None:
+                plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac = ctx.factor(plan, vals, opts)
+            t1 = time.perf_counter()
+            ctx.apply(fac, nm, dx, dy)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            Z = dy.cpu().numpy().reshape(prob.n, nm, order="F")
+            errs[f"{scheme}_{eps:g}"] = np.linalg.norm(V - Z, axis=0).tolist()
+            times[f"{scheme}_{eps:g}"] = {"factor_ms": 1e3 * (t1 - t0), "apply_ms": 1e3 * (t2 - t1),
+                                          "mu": fac.info()["nnz_L"] / prob.nnz}
+            fac.close()
+    better = [so < fo for e in ("0.1", "0.01")
+              for so, fo in zip(errs[f"SO_{e}"], errs[f"FO_{e}"])]
+    mid = [i for i, l in enumerate(lam) if l >= 1e-2]
+    ratio = float(np.exp(np.mean([np.log(errs["SO_0.1"][i] / errs["FO_0.01"][i]) for i in mid])))
+    out = {
+        "metric": "forward error ||(I - M A) v||_2 on unit eigenvectors, 2D Poisson",
+        "value": float(np.mean(better)),
+        "unit": "fraction of (mode, eps) with SO error below FO error",
+        "n_gpus": 1, "steps": 4, "warmup": 0, "higher_is_better": True, "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D 5-point Poisson {d}x{d}, n={prob.n}, depth {depth}, skip 4, "
+                               f"modes p = floor(1.25^k) <= {d} ({nm} modes)"},
+        "modes": ps, "eigenvalues": lam, "errors": errs, "timing": times,
+        "so_eps0.1_over_fo_eps0.01_geomean_lambda_ge_1e-2": ratio,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_table1(args):
+    """Scaling study on 2D Laplacians (the paper's Table 1 setting): d x d
+    grids, d = 400 ... d_max doubling, contrast rho in {1, 100} (the field of
+    synthetic.high_contrast_2d, seed 5000 + d; rho = 1 is the constant
+    coefficient case), b = ones, eps in {0.01, 0.001}, FO and SO, depth
+    round(log2(n/64)), skip 4, PCG to 1e-10.  Reports mu, n_cg, factor and
+    solve seconds per run (device times; the analysis per grid is separate)."""
+    import torch
+    from paper_2007_00789_amd import spand
+    from synthetic import high_contrast_2d
+
+    rows = []
+    ctx = spand.Context(0)
+    d = 400
+    while d <= args.table1_dmax:
+        for rho in (1.0, 100.0):
+            prob = high_contrast_2d(d, rho, seed=5000 + d)
+            depth = max(0, int(round(np.log2(prob.n / 64.0))))
+            t0 = time.perf_counter()
+            plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords,
+                                 spand.make_opts(depth=depth, skip=4), ctx)
+            analyze_s = time.perf_counter() - t0
+            vals = torch.from_numpy(prob.vals).to("cuda:0")
+            b = torch.ones(prob.n, dtype=torch.float64, device="cuda:0")
+            x = torch.zeros_like(b)
+            for eps in (0.01, 0.001):
+                for scheme in ("FO", "SO"):
+                    opts = spand.make_opts(depth=depth, skip=4, eps=eps, scheme=scheme)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    fac = ctx.factor(plan, vals, opts)
+                    t2 = time.perf_counter()
+                    it, rr = ctx.pcg(fac, 1, b, x, 1e-10, 1000)
+                    t3 = time.perf_counter()
+                    row = {"d": d, "n": prob.n, "rho": rho, "eps": eps, "scheme": scheme,
+                           "mu": fac.info()["nnz_L"] / prob.nnz, "n_cg": int(it[0]),
+                           "relres": float(rr[0]), "T_f": t2 - t1, "T_s": t3 - t2,
+                           "analyze_s": analyze_s}
+                    rows.append(row)
+                    print(json.dumps(row), file=sys.stderr, flush=True)
+                    fac.close()
+            plan.close()
+            del vals, b, x
+        d *= 2
+    ratios = {}
+    for r in rows:
+        if r["scheme"] == "SO":
+            fo = next(q for q in rows if q["scheme"] == "FO" and
+                      (q["d"], q["rho"], q["eps"]) == (r["d"], r["rho"], r["eps"]))
+            ratios[f"d{r['d']}_rho{r['rho']:g}_eps{r['eps']:g}"] = r["n_cg"] / fo["n_cg"]
+    out = {
+        "metric": "PCG iterations SO / FO on 2D Laplacians (scaling study)",
+        "value": float(np.mean(list(ratios.values()))),
+        "unit": "mean n_cg ratio SO/FO",
+        "n_gpus": 1, "steps": len(rows), "warmup": 0, "higher_is_better": False,
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D 5-point, d = 400..{args.table1_dmax}, rho in {{1, 100}}, "
+                               "b = ones, eps in {0.01, 0.001}, skip 4, PCG tol 1e-10"},
+        "ratios": ratios, "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +400,8 @@ def main():
     ap.add_argument("--workload", default="lap3d_64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=48, help="requests of the serving stream")
+    ap.add_argument("--eig-d", type=int, default=1000, help="grid side of the eigenvector study")
+    ap.add_argument("--table1-dmax", type=int, default=3200, help="largest grid side of the scaling study")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--serve-bytes", type=int, default=200, help="factor budget, GiB")
@@ -303,6 +427,10 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "eig2d":
+        return bench_eig2d(args)
+    if args.workload == "table1":
+        return bench_table1(args)
 
     import torch
     from paper_2007_00789_amd import spand

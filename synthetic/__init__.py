@@ -14,5 +14,7 @@ from .problems import (  # noqa: F401
     workload,
     batch_problems,
     serve_stream,
+    poisson_modes,
+    poisson_eigvec,
     WORKLOADS,
 )

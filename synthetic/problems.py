@@ -246,3 +246,26 @@ def serve_stream(count: int = 48, rate: float = 50.0, reuse: float = 0.3, side=(
         out.append(dict(t=t, key=key, side=s, mseed=ms, umax=umax,
                         nrhs=int(rng.integers(1, nrhs_max + 1)), rhs_seed=seed + 100000 + i))
     return out
+
+
+def poisson_modes(d: int):
+    """Mode numbers p = floor(1.25^k) <= d, k = 0, 1, ..., without repeats."""
+    out, k = [], 0
+    while True:
+        p = int(np.floor(1.25 ** k))
+        if p > d:
+            return out
+        if not out or p != out[-1]:
+            out.append(p)
+        k += 1
+
+
+def poisson_eigvec(d: int, p: int):
+    """Unit eigenvector of the d x d 5-point Dirichlet Laplacian for the grid
+    function sin(p i pi/(d+1)) sin(p j pi/(d+1)), i, j = 1..d (vertex id
+    x + d y with i = x + 1, j = y + 1), and its eigenvalue
+    8 sin^2(p pi / (2 (d+1)))."""
+    s = np.sin(p * np.arange(1, d + 1) * np.pi / (d + 1))
+    v = np.outer(s, s).reshape(-1)     # row y, column x: index x + d y
+    v /= np.linalg.norm(v)
+    return v, 8.0 * np.sin(p * np.pi / (2.0 * (d + 1))) ** 2
