@@ -11,16 +11,17 @@
 #include "runtime.h"
 
 struct spand_ctx_s { spand::Ctx c; };
+// idle device memory a context keeps for the next factorization or solve
+constexpr size_t kPoolIdleBytes = size_t(16) << 30;
 struct spand_plan_s { spand::Plan p; };
 struct spand_factor_s {
   spand::FactorObj f;
-  double* d_vals = nullptr;  // copy of A's values (SpMV inside PCG)
+  spand::DevBuf vals;        // copy of A's values (SpMV inside PCG)
+  double* d_vals = nullptr;  // = vals.p
   int device = 0;
-  ~spand_factor_s() { if (d_vals) (void)hipFree(d_vals); }
 };
 
 namespace spand {
-void build_apply(Ctx& C, FactorObj& F);
 void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y);
 void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const double* b, double* x,
              double tol, int32_t maxit, int32_t* iters, double* relres, bool* converged);
@@ -127,6 +128,7 @@ spand_status spand_create(spand_ctx_t* out, int device, void* stream) {
     if (device < 0 || device >= ndev) throw spand::Error(SPAND_E_INVALID, "bad device ordinal");
     SPAND_HIP(hipSetDevice(device));
     ctx->c.device = device;
+    ctx->c.pool = std::make_shared<spand::MemPool>(device, kPoolIdleBytes);
     if (stream) {
       ctx->c.stream = static_cast<hipStream_t>(stream);
     } else {
@@ -305,7 +307,8 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
     f->device = ctx->c.device;
     upload_plan(plan->p, ctx->c.device);
     const int64_t nnz = plan->p.nnz;
-    SPAND_HIP(hipMalloc(&f->d_vals, std::max<int64_t>(nnz, 1) * sizeof(double)));
+    f->vals.pool = ctx->c.pool;
+    f->d_vals = static_cast<double*>(f->vals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
     SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
                              ctx->c.stream));
     try {
@@ -315,6 +318,9 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
       SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
       auto g = std::make_unique<spand_factor_s>();
       g->device = f->device;
+      std::swap(g->vals.p, f->vals.p);
+      std::swap(g->vals.bytes, f->vals.bytes);
+      std::swap(g->vals.pool, f->vals.pool);
       std::swap(g->d_vals, f->d_vals);
       f = std::move(g);
       spand_opts o2 = *opts;
@@ -322,7 +328,6 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
       spand::run_factor(ctx->c, plan->p, f->d_vals, o2, f->f);
       f->f.opts = *opts;
     }
-    if (f->f.stopped_at < 0) spand::build_apply(ctx->c, f->f);
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();
     f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();

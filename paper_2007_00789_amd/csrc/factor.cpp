@@ -14,8 +14,14 @@
 // per step (a few KB).
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <exception>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 #include "runtime.h"
 
@@ -38,6 +44,13 @@ void* DevArena::alloc(size_t bytes) {
   }
   size_t sz = std::max<size_t>(bytes, size_t(mirrored_ ? 16 : 64) << 20);
   Chunk c{nullptr, nullptr, sz, SIZE_MAX, 0};
+  if (pool_ && pool_->take(sz, mirrored_, &c.p, &c.h, &c.size)) {
+    chunks_.push_back(c);
+    reserved_ += c.size;
+    cur_ = chunks_.size() - 1;
+    used_ = bytes;
+    return c.p;
+  }
   SPAND_HIP(hipMalloc(&c.p, sz));
   if (mirrored_) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c.h), sz, hipHostMallocDefault);
@@ -64,6 +77,10 @@ void DevArena::flush(hipStream_t s) {
 
 void DevArena::release() {
   for (auto& c : chunks_) {
+    if (pool_) {
+      pool_->give(c.p, c.h, c.size);
+      continue;
+    }
     (void)hipFree(c.p);
     if (c.h) (void)hipHostFree(c.h);
   }
@@ -77,18 +94,66 @@ size_t DevArena::bytes_used() const {
   return s + used_;
 }
 
+bool MemPool::take(size_t bytes, bool mirrored, char** dev, char** host, size_t* size) {
+  std::lock_guard<std::mutex> lk(mu_);
+  int best = -1;
+  for (int i = 0; i < (int)idle_.size(); ++i)
+    if (idle_[i].size >= bytes && (idle_[i].h != nullptr) == mirrored &&
+        (best < 0 || idle_[i].size < idle_[best].size))
+      best = i;
+  if (best < 0) return false;
+  *dev = idle_[best].d;
+  *host = idle_[best].h;
+  *size = idle_[best].size;
+  held_ -= idle_[best].size;
+  idle_.erase(idle_.begin() + best);
+  return true;
+}
+
+void MemPool::give(char* dev, char* host, size_t size) {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (held_ + size <= cap_) {
+      idle_.push_back({dev, host, size});
+      held_ += size;
+      return;
+    }
+  }
+  (void)hipSetDevice(device_);
+  (void)hipFree(dev);
+  if (host) (void)hipHostFree(host);
+}
+
+MemPool::~MemPool() {
+  (void)hipSetDevice(device_);
+  for (auto& c : idle_) {
+    (void)hipFree(c.d);
+    if (c.h) (void)hipHostFree(c.h);
+  }
+}
+
 void* DevBuf::ensure(size_t need) {
   if (need <= bytes && p) return p;
   release();
   size_t sz = std::max<size_t>(need, 1 << 20);
   sz += sz / 4;
+  char *d = nullptr, *h = nullptr;
+  size_t got = 0;
+  if (pool && pool->take(sz, false, &d, &h, &got)) {
+    p = d;
+    bytes = got;
+    return p;
+  }
   SPAND_HIP(hipMalloc(&p, sz));
   bytes = sz;
   return p;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (pool) pool->give(static_cast<char*>(p), nullptr, bytes);
+    else (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
 }
@@ -180,6 +245,67 @@ void check_info(const std::vector<int32_t>& info, const std::vector<int32_t>& cl
 
 }  // namespace
 
+// Builds the apply program of every step whose factorization records are
+// final on a host thread, beside the factorization of the later steps.
+class ApplyBuilder {
+ public:
+  ApplyBuilder(FactorObj& F, int device) : F_(F), device_(device) {
+    begin_apply(F_);
+    th_ = std::thread([this] { run(); });
+  }
+  ApplyBuilder(const ApplyBuilder&) = delete;
+  ApplyBuilder& operator=(const ApplyBuilder&) = delete;
+  // steps D ... l are final
+  void publish(int l) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      ready_ = l;
+    }
+    cv_.notify_one();
+  }
+  // waits for every step (all published), rethrows the builder's error
+  void finish() {
+    publish(0);
+    th_.join();
+    if (err_) std::rethrow_exception(err_);
+  }
+  ~ApplyBuilder() {   // error or early stop: abandon the remaining steps
+    if (th_.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+      }
+      cv_.notify_one();
+      th_.join();
+    }
+  }
+
+ private:
+  void run() {
+    try {
+      SPAND_HIP(hipSetDevice(device_));   // the metadata arena allocates on the factor's device
+      for (int l = F_.plan->depth; l >= 0; --l) {
+        {
+          std::unique_lock<std::mutex> lk(mu_);
+          cv_.wait(lk, [&] { return stop_ || ready_ <= l; });
+          if (stop_) return;
+        }
+        build_apply_step(F_, l);
+      }
+    } catch (...) {
+      err_ = std::current_exception();
+    }
+  }
+  FactorObj& F_;
+  int device_;
+  std::thread th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  int ready_ = INT_MAX;
+  bool stop_ = false;
+  std::exception_ptr err_;
+};
+
 void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = C.stream;
@@ -187,6 +313,13 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   F.plan = &P;
   F.opts = o;
   F.steps.assign(D + 1, StepRec());
+  F.arena_pool = C.pool;
+  F.arena.set_pool(C.pool);
+  F.meta.set_pool(C.pool);
+  // the apply program is built step by step as the steps finish (not when
+  // stopping after a step for a debug dump)
+  std::unique_ptr<ApplyBuilder> apb;
+  if (o.debug_stop_step < 0) apb = std::make_unique<ApplyBuilder>(F, C.device);
   const bool so = o.scheme == SPAND_SECOND_ORDER;
   const bool sf = o.scheme == SPAND_SUPERFINE;
   const double eps = o.eps;
@@ -212,7 +345,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
     StepRec& R = F.steps[l];
-    C.upload.reset();
+    C.upload.next();
     R.l = l;
     R.sparsified = st.sparsified;
     R.n0 = sizes;
@@ -634,6 +767,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " +
                                          std::to_string(l));
         const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
+        if (R.V[p] && r2 > 0) R.VT[p] = F.arena.alloc_n<double>((size_t)a * r2);   // V T, formed at the end
         flops += (double)a * a * k;
         double qr = 0.0;
         for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
@@ -647,6 +781,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         }
       }
     }
+
+    if (apb) apb->publish(l);
 
     if (o.debug_stop_step == l) {
       F.stopped_at = l;
@@ -690,7 +826,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
     const auto* d_cp = C.upload.upload(cp);
     SPAND_PROF(C, "k_copy", launch_copy(d_cp, (int64_t)cp.size(), s));
-    SPAND_HIP(hipStreamSynchronize(s));
+    // no wait: the next step is planned while the merge runs (its uploads go
+    // to the other descriptor arena)
     cur = 1 - cur;
     panel = npanel;
     lay = std::move(nlay);
@@ -700,7 +837,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   if (F.stopped_at < 0) {
     // triangular factors of the compact WY forms of every sparsified interface:
     // S = V^T V (lower triangle) by one batched GEMM, then the column recurrence
-    C.upload.reset();
+    C.upload.next();
     std::vector<GemmDesc> gd;
     std::vector<GemmTerm> gt;
     std::vector<TileRef> tiles;
@@ -739,11 +876,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       std::vector<GemmDesc> gv;
       std::vector<GemmTerm> gvt;
       std::vector<TileRef> vtiles;
-      for (StepRec& R : F.steps)
+      for (const StepRec& R : F.steps)
         for (size_t p = 0; p < R.V.size(); ++p) {
           if (!R.V[p] || R.r2[p] <= 0) continue;
           const int nref = R.r2[p], a = R.n0[p];
-          R.VT[p] = F.arena.alloc_n<double>((size_t)a * nref);
           GemmDesc g{};
           g.C = R.VT[p];
           g.ldc = a;
@@ -764,6 +900,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));
+  if (apb && F.stopped_at < 0) {
+    apb->finish();
+    finish_apply(C, F);
+  }
   F.stats.flops = flops;
   F.stats.nnz_L = nnzL;
   F.stats.factor_bytes = (int64_t)F.arena.bytes_used();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -13,6 +15,30 @@
 
 namespace spand {
 
+// Device chunks (with their pinned host mirrors, for mirrored arenas) kept
+// for reuse by the arenas of later factorizations and solves on one device, so
+// that a factor-solve cycle does not pay hipMalloc / hipFree (which waits for
+// the device) for its large buffers.  Holds at most `cap` idle bytes; beyond
+// that, returned chunks are freed.  Thread-safe (factors may be destroyed on
+// any thread); owned jointly by the context and the arenas drawing from it.
+class MemPool {
+ public:
+  MemPool(int device, size_t cap) : device_(device), cap_(cap) {}
+  MemPool(const MemPool&) = delete;
+  MemPool& operator=(const MemPool&) = delete;
+  ~MemPool();
+  // a chunk of at least `bytes` (the smallest idle one), or false
+  bool take(size_t bytes, bool mirrored, char** dev, char** host, size_t* size);
+  void give(char* dev, char* host, size_t size);
+
+ private:
+  struct Chunk { char* d; char* h; size_t size; };
+  std::mutex mu_;
+  std::vector<Chunk> idle_;
+  int device_;
+  size_t cap_, held_ = 0;
+};
+
 // Chunked bump allocator of device memory.  Chunks are kept until release();
 // reset() makes every chunk reusable (the caller must have synchronized).
 // A mirrored arena keeps a pinned host copy of every chunk: upload() writes
@@ -20,6 +46,8 @@ namespace spand {
 class DevArena {
  public:
   explicit DevArena(bool mirrored = false) : mirrored_(mirrored) {}
+  // chunks come from and go back to `pool` (nullptr: hipMalloc / hipFree)
+  void set_pool(std::shared_ptr<MemPool> pool) { pool_ = std::move(pool); }
   DevArena(const DevArena&) = delete;
   DevArena& operator=(const DevArena&) = delete;
   ~DevArena() { release(); }
@@ -47,14 +75,38 @@ class DevArena {
  private:
   struct Chunk { char* p; char* h; size_t size, lo, hi; };
   bool mirrored_;
+  std::shared_ptr<MemPool> pool_;
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, used_ = 0, reserved_ = 0;
+};
+
+// Two mirrored descriptor arenas used by alternate steps of the factorization:
+// a step's uploads may still be in flight on the stream while the host plans
+// the next step, and are consumed by the time the step after that resets them
+// (every step synchronizes once, to read its ranks).
+class UploadRing {
+ public:
+  template <class T>
+  T* upload(const std::vector<T>& v) { return a_[cur_].upload(v); }
+  template <class T>
+  T* alloc_n(size_t n) { return a_[cur_].alloc_n<T>(n); }
+  void flush(hipStream_t s) { a_[cur_].flush(s); }
+  // switch to the other arena and make all of it reusable
+  void next() {
+    cur_ ^= 1;
+    a_[cur_].reset();
+  }
+
+ private:
+  DevArena a_[2] = {DevArena(true), DevArena(true)};
+  int cur_ = 0;
 };
 
 // A device buffer that only grows (contents are not preserved on growth).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  std::shared_ptr<MemPool> pool;   // nullptr: hipMalloc / hipFree
   void* ensure(size_t need);
   void release();
   ~DevBuf() { release(); }
@@ -95,7 +147,8 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string last_error;
-  DevArena upload{true};   // per-step descriptors
+  std::shared_ptr<MemPool> pool;   // chunks of factor and solve arenas
+  UploadRing upload;       // per-step descriptors (two arenas, alternate steps)
   DevBuf panels[2];        // ping-pong row panels of consecutive steps
   DevBuf temp;             // scaling temporaries
   DevBuf ints;             // per-step integer outputs (n_cur, ranks, info)
@@ -121,6 +174,7 @@ struct StepRec {
 struct FactorObj {
   Plan* plan = nullptr;
   spand_opts opts{};
+  std::shared_ptr<MemPool> arena_pool;       // the context's pool (chunks of the buffers below)
   DevArena arena;                            // numeric factor data
   DevArena meta{true};                       // apply descriptors and position lists
   std::vector<StepRec> steps;                // indexed by l
@@ -130,7 +184,7 @@ struct FactorObj {
   std::vector<double> dbg_panels;
   PanelLayout dbg_layout;
   std::vector<int32_t> dbg_ncur;
-  // apply program (built by build_apply)
+  // apply program (built step by step during run_factor)
   struct ApplyProg* prog = nullptr;
   ~FactorObj();
 };
@@ -140,6 +194,12 @@ struct FactorObj {
 // the single-workgroup QR.
 struct CoopPlacement {};
 
+// Factorization (Alg. 2); builds the apply program too unless stopped early.
 void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F);
+// apply program: a fresh one, the records of step l (steps in order D ... 0),
+// then the upload of its descriptors
+void begin_apply(FactorObj& F);
+void build_apply_step(FactorObj& F, int l);
+void finish_apply(Ctx& C, FactorObj& F);
 
 }  // namespace spand

@@ -70,17 +70,25 @@ int64_t find_adj(const StepPlan& st, int c, int target) {
 
 }  // namespace
 
-void build_apply(Ctx& C, FactorObj& F) {
-  hipStream_t s = C.stream;
+void begin_apply(FactorObj& F) {
+  delete F.prog;
+  F.prog = new ApplyProg();
+  for (DevBuf* b : {&F.prog->T, &F.prog->P, &F.prog->U, &F.prog->Y}) b->pool = F.arena_pool;
+}
+
+// The apply program of step l (host descriptors written to the factor's
+// mirrored metadata arena; flushed by finish_apply).  Steps are added in
+// elimination order D ... 0, each once its factorization records are final,
+// so this can run on a host thread beside the factorization of later steps.
+void build_apply_step(FactorObj& F, int l) {
   const Plan& P = *F.plan;
-  auto* prog = new ApplyProg();
-  F.prog = prog;
+  ApplyProg* prog = F.prog;
   const bool so = F.opts.scheme == SPAND_SECOND_ORDER;
   const bool sf = F.opts.scheme == SPAND_SUPERFINE;
-  for (int l = P.depth; l >= 0; --l) {
+  {
     const StepPlan& st = P.steps[l];
     const StepRec& R = F.steps[l];
-    if (R.n0.empty()) break;  // stopped early
+    if (R.n0.empty()) return;  // stopped early
     ApplyStep as;
     as.l = l;
     const int nI = st.nI, nc = st.nc;
@@ -356,9 +364,13 @@ void build_apply(Ctx& C, FactorObj& F) {
     }
     prog->steps.push_back(std::move(as));
   }
-  F.meta.flush(s);
-  SPAND_HIP(hipStreamSynchronize(s));
 }
+
+void finish_apply(Ctx& C, FactorObj& F) {
+  F.meta.flush(C.stream);
+  SPAND_HIP(hipStreamSynchronize(C.stream));
+}
+
 
 // LDS doubles the apply kernels stage for nrhs columns, at the largest
 // cluster of each kernel class: interiors (x, y and the GEMV partial sums
@@ -458,6 +470,7 @@ void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const dou
   const int32_t ne = nseg * nrhs;
   const int32_t* seg_id = nseg > 1 ? P.d_seg_id : nullptr;
   DevArena work;
+  work.set_pool(C.pool);
   double* r = work.alloc_n<double>(nv);
   double* z = work.alloc_n<double>(nv);
   double* p = work.alloc_n<double>(nv);
