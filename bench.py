@@ -86,10 +86,10 @@ def cpu_baseline(scheme: str, eps: float, gpu_ref: dict) -> dict:
 MEASURED_TRAFFIC = {
     "k_cpqr_coop": {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c7d3b50dbb4c9ed745598afeb45d54694c60b83db02925c53f83feecda1a8ff6",
-            "paper_2007_00789_amd/csrc/factor.cpp": "122dfd893be6a00689206354de2ce8e4eaea3d1647141f7e603b57a204e1c594",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "128cd1366348736164d74c9dcf5cfa50658204477449b734707ae5e5a72da1a3",
+            "paper_2007_00789_amd/csrc/factor.cpp": "6a6ae9e884e9c3bd20bb9f84ee1e88d78e86f6d0895bcc6c5f4206d62698bd2f",
         },
-        "fetch_kib": 7584.5, "write_kib": 38525.3,
+        "fetch_kib": 7599.6, "write_kib": 41257.5,
         "fetch_scale": 1.9998, "write_scale": 1.0,
     },
 }
