@@ -56,7 +56,7 @@ void check_opts(const spand_opts* o) {
   if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
   if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
   if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
-      o->qr_xcd_local > 1 || o->qr_regs < 0 || o->qr_regs > 1)
+      o->qr_xcd_local > 1 || o->qr_regs < 0 || o->qr_regs > 1 || o->qr_lds_cols < 0)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
 }
 
@@ -100,6 +100,7 @@ void spand_default_opts(spand_opts* o) {
   o->qr_list_cap = -1;
   o->qr_xcd_local = 1;
   o->qr_regs = 0;
+  o->qr_lds_cols = 0;
 }
 
 const char* spand_status_string(spand_status s) {

@@ -77,6 +77,9 @@ struct CoopDesc {
                      // check counter, [kCoopFlag0 + g] barrier flag of member g
   double* xch;       // exchange buffer, coop_xch_doubles(G, a)
   int32_t G, xcd, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
+  int32_t ncap_lds;  // columns per workgroup held in LDS; the rest of its
+                     // columns (up to ncap) stay in the panel (global memory)
+  int32_t pad;
 };
 constexpr int kCoopMaxGroup = 32;
 constexpr int kCoopList = 32;           // tie candidates exchanged per workgroup
@@ -87,9 +90,15 @@ inline int64_t coop_xch_doubles(int G, int a) {
 }
 // dynamic LDS of the LDS-resident cooperative QR: the slice (a x ncap), its
 // norms and the Householder vector
-inline size_t coop_lds_bytes(int /*G*/, int a, int ncap) {
-  return ((size_t)a * ncap + ncap + a) * sizeof(double);
+inline size_t coop_lds_bytes(int a, int ncap, int ncap_lds) {
+  // slice | norms | Householder vector | pointers of the columns kept in the panel
+  return ((size_t)a * ncap_lds + ncap + a + (ncap - ncap_lds)) * sizeof(double);
 }
+// columns of an a-row slice that fit the cooperative QR's LDS
+inline int64_t coop_cols(int a) { return ((int64_t)(kCoopLdsBytes / 8) - a) / (a + 1); }
+// a workgroup may hold up to this many times its LDS columns, the rest in the
+// panel, when an interface is too wide for kCoopMaxGroup workgroups' LDS
+constexpr int kCoopOverflow = 4;
 constexpr int kCoopSyncInts = 64;        // 256 bytes per group
 constexpr int kCoopFlag0 = 32;           // flags on their own 128-byte line
 
@@ -125,7 +134,8 @@ void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s);
 void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s);
 // maximum co-resident workgroups of the cooperative QR for a given LDS size
-int coop_max_blocks(size_t lds_bytes);
+// (panel: the instance that supports columns kept in the row panel)
+int coop_max_blocks(size_t lds_bytes, bool panel);
 // blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block)
 // register-resident cooperative QR (a <= kCpqrRegMaxA, at most kCpqrRegCols
 // columns per workgroup): rows per lane for a given a (0 if a is too large),
@@ -143,7 +153,8 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
-                            double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s);
+                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
+                            hipStream_t s);
 
 constexpr int kGemmTile = 64;
 constexpr int kCpqrMaxK = 12288;      // trailing norms of a CPQR live in LDS

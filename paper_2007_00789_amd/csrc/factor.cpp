@@ -614,16 +614,22 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           // register-resident slices when they fit, else LDS-resident slices
           bool reg = o.qr_regs && cpqr_reg_rows(a) > 0 &&
                      (kmax + kCpqrRegCols - 1) / kCpqrRegCols <= kCoopMaxGroup;
-          const int64_t cap = !(a > 0) ? 0
-                              : reg    ? kCpqrRegCols
-                                       : ((int64_t)(kCoopLdsBytes / 8) - a) / (a + 1);
+          const int64_t cap = !(a > 0) ? 0 : reg ? kCpqrRegCols : coop_cols(a);
           int64_t G = cap > 0 ? (kmax + cap - 1) / cap : 0;
           if (o.qr_group > 0) G = std::max(G, std::min<int64_t>(o.qr_group, kmax));
+          // too wide for kCoopMaxGroup workgroups' LDS: kCoopMaxGroup
+          // workgroups, each keeping its columns beyond the LDS in the panel
+          if (!reg && G > kCoopMaxGroup && o.qr_group >= 0 &&
+              (kmax + kCoopMaxGroup - 1) / kCoopMaxGroup <= kCoopOverflow * cap)
+            G = kCoopMaxGroup;
           if (o.qr_group >= 0 && a > 0 && kmax > 0 && G >= 1 && G <= kCoopMaxGroup) {
             CoopDesc q{};
             q.d = d;
             q.G = (int32_t)G;
             q.ncap = (int32_t)((kmax + G - 1) / G);
+            int64_t capl = cap;
+            if (o.qr_lds_cols > 0) capl = std::min<int64_t>(capl, o.qr_lds_cols);
+            q.ncap_lds = reg ? q.ncap : (int32_t)std::min<int64_t>(q.ncap, capl);
             q.list_cap = o.qr_list_cap < 0 ? 32 : o.qr_list_cap;
             (reg ? qd_reg : qd).push_back(q);
             coop_used[p] = reg ? 2 : 1;
@@ -649,6 +655,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           if (list.empty()) continue;
           size_t lds = 0;
           int rows = 0, cap_blocks = 0;
+          bool panel = false;   // some workgroup keeps columns in the row panel
+          for (const CoopDesc& q : list) panel = panel || q.ncap_lds < q.ncap;
           if (kind == 0) {
             int amax = 0;
             for (const CoopDesc& q : list) {
@@ -658,8 +666,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             rows = cpqr_reg_rows(amax);
             cap_blocks = cpqr_reg_max_blocks(rows, lds);
           } else {
-            for (const CoopDesc& q : list) lds = std::max(lds, coop_lds_bytes(q.G, q.d.a, q.ncap));
-            cap_blocks = coop_max_blocks(lds);
+            for (const CoopDesc& q : list)
+              lds = std::max(lds, coop_lds_bytes(q.d.a, q.ncap, q.ncap_lds));
+            cap_blocks = coop_max_blocks(lds, panel);
           }
           const int slots = cap_blocks / kCoopXcds;
           if (slots <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
@@ -718,7 +727,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             } else {
               SPAND_PROF(C, "k_cpqr_coop",
                          he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur,
-                                               d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
+                                               d_r, d_r2, d_k, eps, eps_stop, d_err, lds, panel,
+                                               s));
             }
             SPAND_HIP(he);
           }

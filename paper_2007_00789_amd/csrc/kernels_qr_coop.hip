@@ -90,21 +90,24 @@ __device__ __forceinline__ double groupL_sum(double v) {
   return v;
 }
 
-// Reflector update and exact trailing norms of the columns of one workgroup
-// (Ys, a x m in LDS, ld a): L lanes per column (64 / L columns per wave, the
+// Reflector update and exact trailing norms of m columns of one workgroup
+// (in the LDS slice Ys, ld a, or, kPanel, at the addresses gcol in the row
+// panel): L lanes per column (64 / L columns per wave, the
 // waves over the column batches), kRpl rows per lane held in registers between
 // the dot product and the update, one group reduction for each.  Column Cl
 // (the pivot, when owned) and used-up columns (nrm2 < 0) are skipped.
-template <int L, int kRpl>
-__device__ __forceinline__ void update_columns(double* Ys, double* nrm2, const double* v, int a,
-                                               int m, int j, double tau, int skip) {
+template <int L, int kRpl, bool kPanel>
+__device__ __forceinline__ void update_columns(double* Ys, double* const* gcol, double* nrm2,
+                                               const double* v, int a, int m, int j, double tau,
+                                               int skip) {
   constexpr int CPW = kWave / L;   // columns per wave
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int grp = lane / L, rl = lane % L;
   for (int cb = wid * CPW; cb < m; cb += kCW * CPW) {
     const int c = cb + grp;
     const bool act = c < m && c != skip && nrm2[c] >= 0.0;
-    double* col = Ys + (int64_t)(act ? c : 0) * a;
+    // LDS slice, or (kPanel) the column's place in the panel
+    double* col = kPanel ? (act ? gcol[c] : gcol[0]) : Ys + (int64_t)(act ? c : 0) * a;
     double yv[kRpl];
     double dot = 0.0;
 #pragma unroll
@@ -212,6 +215,10 @@ __device__ bool wave_barrier(int32_t* flags, int phase, int G, int g, int32_t* e
   }
 }
 
+// kPanel: some columns of a workgroup may live in the row panel (an interface
+// wider than its group's LDS); the LDS-only instance keeps its registers for
+// the common case.
+template <bool kPanel>
 __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const CpqrNbr* nbrs,
                                                   const int32_t* blk_map, int32_t* n_cur,
                                                   int32_t* out_r, int32_t* out_r2, int32_t* out_k,
@@ -259,9 +266,17 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
   const int per = (k + G - 1) / G;
   const int c0 = min(k, g * per), c1 = min(k, c0 + per), m = c1 - c0;
-  double* Ys = sm;                                  // a x ncap (ld a)
-  double* nrm2 = sm + (int64_t)a * cd.ncap;         // ncap
+  // the first mL of my columns in LDS, the rest (when the interface is wider
+  // than the group's LDS) in place in the row panel
+  const int mL = kPanel ? min(m, cd.ncap_lds) : m;
+  double* Ys = sm;                                  // a x ncap_lds (ld a)
+  double* nrm2 = sm + (int64_t)a * cd.ncap_lds;     // ncap
   double* v = nrm2 + cd.ncap;                       // a
+  double** gcol = reinterpret_cast<double**>(v + a);   // ncap - ncap_lds panel columns
+  auto colp = [&](int c) -> double* {
+    if constexpr (kPanel) return c < mL ? Ys + (int64_t)c * a : gcol[c - mL];
+    return Ys + (int64_t)c * a;
+  };
   // exchange: lists and first-candidate columns are double buffered by step
   // parity (a workgroup may publish step j+1 while others still read step j)
   double* X2 = cd.xch;                              // 2 x G x kXs
@@ -276,17 +291,21 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
       const CpqrNbr nb = nbrs[e];
       const int wc = n_cur[nb.w];
       const int lo = max(kk, c0), hi = min(kk + wc, c1);
-      if (hi > lo) {
+      const int hiL = min(hi, c0 + mL);
+      if (hiL > lo) {
         const double* src = d.panel + (nb.col + (lo - kk)) * a;
         double* dst = Ys + (int64_t)(lo - c0) * a;
-        for (int idx = tid; idx < (hi - lo) * a; idx += kCT) dst[idx] = src[idx];
+        for (int idx = tid; idx < (hiL - lo) * a; idx += kCT) dst[idx] = src[idx];
       }
+      if (kPanel)
+        for (int c = max(lo, c0 + mL) + tid; c < hi; c += kCT)
+          gcol[c - c0 - mL] = d.panel + (nb.col + (c - kk)) * a;
       kk += wc;
     }
   }
   __syncthreads();
   for (int c = wid; c < m; c += kCW) {
-    const double* col = Ys + (int64_t)c * a;
+    const double* col = colp(c);
     double s = 0.0;
     for (int i = lane; i < a; i += kWave) s = fma(col[i], col[i], s);
     s = wave_sum(s);
@@ -336,7 +355,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         if (Mg < 0.0) go = 0;   // every column used up
         else {
           C = c0 + first;
-          PVl = Ys + (int64_t)first * a;
+          PVl = colp(first);
         }
       } else {
         if (lane == 0) {
@@ -346,7 +365,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         if (first >= 0) {
           double* Pg = PVs + (int64_t)g * (a + 1);
           if (lane == 0) xst(Pg, nrm2[first]);
-          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), Ys[i + (int64_t)first * a]);
+          const double* fc = colp(first);
+          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
         }
         if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
         if (go > 0) {
@@ -406,7 +426,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
                 if (C >= c0 && C < c1) {
                   const int Cl = C - c0;
                   if (lane == 0) xst(PVx, nrm2[Cl]);
-                  for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), Ys[i + (int64_t)Cl * a]);
+                  const double* pc = colp(Cl);
+                  for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), pc[i]);
                 }
                 if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
                 PVg = PVx;
@@ -476,12 +497,15 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     // grow as the columns per workgroup shrink, so that every wave has work
     {
       const int skip = owner ? Cl : -1;
-      if (m > kCW * 4) update_columns<8, kRpl>(Ys, nrm2, v, a, m, j, tau, skip);
-      else if (m > kCW * 2) update_columns<16, kRpl16>(Ys, nrm2, v, a, m, j, tau, skip);
-      else update_columns<32, kRpl32>(Ys, nrm2, v, a, m, j, tau, skip);
+      if (mL > kCW * 4) update_columns<8, kRpl, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+      else if (mL > kCW * 2) update_columns<16, kRpl16, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+      else if (mL > 0) update_columns<32, kRpl32, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+      if constexpr (kPanel)
+        if (m > mL) update_columns<8, 8, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
     }
     if (owner) {
-      for (int i = j + tid; i < a; i += kCT) Ys[i + (int64_t)Cl * a] = i == j ? beta : 0.0;
+      double* pc = colp(Cl);
+      for (int i = j + tid; i < a; i += kCT) pc[i] = i == j ? beta : 0.0;
       if (tid == 0) nrm2[Cl] = -1.0;
     }
     __syncthreads();
@@ -493,7 +517,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   // Q^T W of my columns into the transposed workspace (E^T lives in rows r..)
   for (int idx = tid; idx < m * a; idx += kCT) {
     const int c = idx % m, i = idx / m;
-    d.Y[(c0 + c) + i * K] = Ys[i + (int64_t)c * a];
+    d.Y[(c0 + c) + i * K] = colp(c)[i];
   }
   // coarse rows into p's panel and, transposed, into the neighbours' panels
   {
@@ -505,7 +529,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
       for (int idx = tid; idx < r * (hi - lo); idx += kCT) {
         const int cc = idx % (hi - lo), i = idx / (hi - lo);
         const int cw = lo - kk + cc;  // column inside block (p, w)
-        const double y = Ys[i + (int64_t)(lo - c0 + cc) * a];
+        const double y = colp(lo - c0 + cc)[i];
         d.panel[i + (nb.col + cw) * a] = y;
         nb.blk_wp[cw + (int64_t)i * nb.ldw] = y;
       }
@@ -533,12 +557,13 @@ __global__ void k_fill_int(int32_t* p, int64_t n) {
 
 }  // namespace
 
-int coop_max_blocks(size_t lds_bytes) {
+int coop_max_blocks(size_t lds_bytes, bool panel) {
   int dev = 0, ncu = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_cpqr_coop),
-                                                   kCT, lds_bytes) != hipSuccess)
+  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<true>)
+                        : reinterpret_cast<const void*>(k_cpqr_coop<false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kCT, lds_bytes) != hipSuccess)
     return 0;
   return nb * ncu;
 }
@@ -550,12 +575,14 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s) {
 hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
-                            double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s) {
+                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
+                            hipStream_t s) {
   launch_fill_int(sync, nsync, s);
   void* args[] = {(void*)&d, (void*)&nb, (void*)&blk_map, (void*)&n_cur, (void*)&out_r,
                   (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cpqr_coop), dim3(nblocks),
-                                    dim3(kCT), args, lds_bytes, s);
+  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<true>)
+                        : reinterpret_cast<const void*>(k_cpqr_coop<false>);
+  return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kCT), args, lds_bytes, s);
 }
 
 }  // namespace spand

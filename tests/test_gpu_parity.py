@@ -31,9 +31,10 @@ def ctx():
 
 
 def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1, qr_group=0, qr_list_cap=-1,
-                qr_xcd_local=1, qr_regs=0):
+                qr_xcd_local=1, qr_regs=0, qr_lds_cols=0):
     from paper_2007_00789_amd import spand
     opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop,
+                           qr_lds_cols=qr_lds_cols,
                            qr_group=qr_group, qr_list_cap=qr_list_cap, qr_xcd_local=qr_xcd_local,
                            qr_regs=qr_regs)
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
@@ -264,6 +265,34 @@ def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group,
         for (p_, a, k, r, r2) in recs:
             assert (got["k"][p_], got["r"][p_]) == (k, r), (l, p_)
     x = rhs(p.n, 2, 13)
+    y_ref = ospand.apply(F, x)
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, 2, dx, dy)
+    y = dy.cpu().numpy().reshape(p.n, 2, order="F")
+    assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+
+
+@gpu
+@pytest.mark.parametrize("qr_group,lds_cols", [(1, 4), (3, 2), (5, 1), (0, 3), (2, 16)],
+                         ids=["g1-lds4", "g3-lds2", "g5-lds1", "auto-lds3", "g2-lds16"])
+@pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[4]],
+                         ids=[CASES[1][0], CASES[3][0], CASES[4][0]])
+def test_qr_panel_columns_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group,
+                                            lds_cols):
+    """Cooperative QR workgroups that keep only some of their columns in LDS
+    and the rest in place in the row panel (the path of interfaces wider than
+    a group's LDS) give the oracle's ranks and the same preconditioner."""
+    p = make()
+    print(f"qr panel columns {name} group={qr_group} lds_cols={lds_cols}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, "SO")
+    _, fac = _gpu_factor(ctx, p, depth, skip, eps, "SO", qr_group=qr_group, qr_lds_cols=lds_cols)
+    for l, recs in F.ranks.items():
+        got = fac.ranks(l, plan_o.steps[l].n_clusters)
+        for (p_, a, k, r, r2) in recs:
+            assert (got["k"][p_], got["r"][p_], got["r2"][p_]) == (k, r, r2), (l, p_)
+    x = rhs(p.n, 2, 14)
     y_ref = ospand.apply(F, x)
     dx = _dev(x)
     dy = torch.zeros_like(dx)
