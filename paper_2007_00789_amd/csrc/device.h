@@ -74,7 +74,8 @@ struct CpqrDesc {
 struct CoopDesc {
   CpqrDesc d;
   int32_t* sync;     // kCoopSyncInts ints, zeroed by the launcher: [0] placement
-                     // check counter, [kCoopFlag0 + g] barrier flag of member g
+                     // check counter, barrier flags from [kCoopFlag0] (32-bit) or
+                     // [kCoopFlag64] (64-bit, two parities)
   double* xch;       // exchange buffer, coop_xch_doubles(G, a)
   int32_t G, xcd, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
   int32_t ncap_lds;  // columns per workgroup held in LDS; the rest of its
@@ -99,8 +100,9 @@ inline int64_t coop_cols(int a) { return ((int64_t)(kCoopLdsBytes / 8) - a) / (a
 // a workgroup may hold up to this many times its LDS columns, the rest in the
 // panel, when an interface is too wide for kCoopMaxGroup workgroups' LDS
 constexpr int kCoopOverflow = 4;
-constexpr int kCoopSyncInts = 64;        // 256 bytes per group
-constexpr int kCoopFlag0 = 32;           // flags on their own 128-byte line
+constexpr int kCoopSyncInts = 192;       // 768 bytes per group
+constexpr int kCoopFlag0 = 32;           // 32-bit flags (register-resident QR), own 128-byte line
+constexpr int kCoopFlag64 = 64;          // 2 x kCoopMaxGroup 64-bit flags (LDS-resident QR)
 
 // Triangular factor of the compact WY form of one interface's n reflectors
 // (V a x n, T n x n, both column-major); T holds V^T V in its lower triangle

@@ -7,7 +7,11 @@
 //  A. wave 0 finds its largest trailing norm and the ordered list of its
 //     columns within the tie band of that maximum, publishes both and the
 //     column of its first candidate, and meets the other workgroups at a group
-//     barrier.  Since the global band lies inside every local band, the union
+//     barrier whose flag words also carry each maximum (as float) and first
+//     candidate: when one group's maximum exceeds all others by more than
+//     float rounding, far more than the band, the pivot is that group's first
+//     candidate and no further round is needed.  Otherwise, since the global
+//     band lies inside every local band, the union
 //     of the lists holds every global candidate, and each workgroup picks the
 //     same pivot (lowest index among the columns within the band of the global
 //     maximum).  If a list overflows, an extra round exchanges exact local
@@ -192,27 +196,42 @@ __device__ __forceinline__ double xld(const double* p) {
   return __longlong_as_double(static_cast<long long>(u));
 }
 
-// Group barrier on per-member flags holding the last phase each member
-// reached, run by one wave (the only one that writes exchange data): it waits
-// for its own exchange stores, raises flag g to `phase` and polls the G flags
-// (one load per lane) until all have reached it.  Returns false after a
-// timeout (bit 1 of the error flag set).
-__device__ bool wave_barrier(int32_t* flags, int phase, int G, int g, int32_t* err) {
+// Group barrier on per-member 64-bit flags, run by one wave (the only one that
+// writes exchange data): it waits for its own exchange stores, then writes its
+// flag word (phase in bits 63..48, a 48-bit payload below) and polls the G
+// words of the same phase parity (one load per lane) until all carry the
+// phase.  Flags are double buffered by phase parity: a member can be at most
+// one barrier ahead of a slow reader, so the word a reader sees for phase p is
+// the one written for p.  Lane q returns member q's word.  Returns false after
+// a timeout (bit 1 of the error flag set).
+__device__ bool wave_barrier(unsigned long long* flags, int phase, unsigned long long payload, int G,
+                             int g, int32_t* err, unsigned long long* word) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
   const int lane = threadIdx.x & (kWave - 1);
-  if (lane == 0) __hip_atomic_store(flags + g, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  unsigned long long* f = flags + (phase & 1) * kCoopMaxGroup;
+  const unsigned long long mine =
+      ((unsigned long long)phase << 48) | (payload & 0xFFFFFFFFFFFFull);
+  if (lane == 0) __hip_atomic_store(f + g, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   long spins = 0;
   while (true) {
-    const int f = lane < G
-                      ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                      : phase;
-    if (__all(f >= phase)) return true;
+    const unsigned long long w =
+        lane < G ? __hip_atomic_load(f + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : mine;
+    if (__all((int)(w >> 48) == phase)) {
+      *word = w;
+      return true;
+    }
     __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit) {
       if (lane == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
   }
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
 }
 
 // kPanel: some columns of a workgroup may live in the row panel (an interface
@@ -234,7 +253,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   const int a = d.a;
   const int64_t K = d.kmax;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  int32_t* flags = cd.sync + kCoopFlag0;
+  unsigned long long* flags = reinterpret_cast<unsigned long long*>(cd.sync + kCoopFlag64);
+  unsigned long long bw = 0;   // flag words of the last barrier (lane q: member q)
 
   // placement check: one round of device-coherent atomics on sync[0] (low
   // half counts arrivals, high half counts members off the planned XCD)
@@ -368,8 +388,33 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
           const double* fc = colp(first);
           for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
         }
-        if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
-        if (go > 0) {
+        // the flag word carries the local maximum (as float) and the first
+        // candidate's column, which decide the pivot whenever one group's
+        // maximum exceeds all others by more than float rounding and the band
+        const unsigned long long pay =
+            ((unsigned long long)(first >= 0 ? c0 + first : 0xFFFF) << 32) |
+            __float_as_uint(__double2float_rn(Mg));
+        if (!wave_barrier(flags, ++phase, pay, G, g, err, &bw)) go = -1;
+        bool fast = false;
+        if (go > 0 && cd.list_cap == kCoopList) {
+          const float Mf = lane < G ? __uint_as_float((unsigned)(bw & 0xFFFFFFFFull)) : -INFINITY;
+          const float Mmax = wave_max_f(Mf);
+          const unsigned long long at = __ballot(lane < G && Mf == Mmax);
+          const int og = __ffsll((long long)at) - 1;
+          const float second = wave_max_f(lane == og ? -INFINITY : Mf);
+          if (Mmax < 0.0f) {
+            fast = true;
+            go = 0;   // every column used up
+          } else if (Mmax > 0.0f && Mmax <= 3.0e38f &&
+                     second < Mmax * (1.0f - 1.0f / (1 << 20))) {
+            // the true maxima keep the order with a margin far above the band,
+            // so the pivot is og's lowest-index candidate: its published one
+            fast = true;
+            C = (int)((__shfl(bw, og, kWave) >> 32) & 0xFFFFull);
+            PVg = PVs + (int64_t)og * (a + 1);
+          }
+        }
+        if (go > 0 && !fast) {
           // one round of loads: lane q fetches group q's maximum, count and
           // first list entry; further entries are fetched only from groups
           // that have more than one and whose maximum reaches the global band
@@ -408,7 +453,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
                 if (mk) cl = c0 + cb + __ffsll((long long)mk) - 1;
               }
               if (lane == 0) xst(XB + g, (double)cl);
-              if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
+              if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
               if (go > 0) {
                 for (int qq = lane; qq < G; qq += kWave) C = min(C, (int)xld(XB + qq));
                 C = wave_min_int(C);
@@ -429,7 +474,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
                   const double* pc = colp(Cl);
                   for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), pc[i]);
                 }
-                if (!wave_barrier(flags, ++phase, G, g, err)) go = -1;
+                if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
                 PVg = PVx;
               }
             }
