@@ -21,6 +21,7 @@
 #include <exception>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <thread>
 
 #include "runtime.h"
@@ -305,6 +306,52 @@ class ApplyBuilder {
   bool stop_ = false;
   std::exception_ptr err_;
 };
+
+// Spare compute units in a cooperative QR launch: widen every group by the
+// largest common factor that keeps all groups in one launch (worst-fit on the
+// 8 XCDs, kCoopMaxGroup workgroups each), so that each workgroup holds fewer
+// columns and its update per pivot step is shorter.  The pivot sequence does
+// not depend on the group size.
+void widen_groups(std::vector<CoopDesc>& list) {
+  auto widened = [&](double f) {
+    std::vector<int> G(list.size());
+    for (size_t i = 0; i < list.size(); ++i)
+      G[i] = (int)std::max<int64_t>(
+          list[i].G, std::min<int64_t>({(int64_t)kCoopMaxGroup, (int64_t)list[i].d.kmax,
+                                        (int64_t)std::floor(list[i].G * f)}));
+    return G;
+  };
+  auto packs = [&](const std::vector<int>& G) {
+    std::vector<int> ord(G.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return G[x] > G[y]; });
+    int fill[kCoopXcds] = {};
+    for (int i : ord) {
+      int best = -1;
+      for (int x = 0; x < kCoopXcds; ++x)
+        if (kCoopMaxGroup - fill[x] >= G[i] && (best < 0 || fill[x] < fill[best])) best = x;
+      if (best < 0) return false;
+      fill[best] += G[i];
+    }
+    return true;
+  };
+  if (list.empty() || !packs(widened(1.0))) return;
+  double lo = 1.0, hi = kCoopMaxGroup;
+  for (int it = 0; it < 12; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (packs(widened(mid)) ? lo : hi) = mid;
+  }
+  const std::vector<int> G = widened(lo);
+  for (size_t i = 0; i < list.size(); ++i) {
+    CoopDesc& q = list[i];
+    if (G[i] == q.G) continue;
+    const bool capped = q.ncap_lds < q.ncap;   // LDS columns limited below ncap
+    const int capl = q.ncap_lds;
+    q.G = G[i];
+    q.ncap = (int32_t)((q.d.kmax + q.G - 1) / q.G);
+    q.ncap_lds = capped ? std::min(q.ncap, capl) : q.ncap;
+  }
+}
 
 void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -653,6 +700,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         for (int kind = 0; kind < 2; ++kind) {
           std::vector<CoopDesc>& list = kind == 0 ? qd_reg : qd;
           if (list.empty()) continue;
+          if (kind == 1 && o.qr_group == 0) widen_groups(list);
           size_t lds = 0;
           int rows = 0, cap_blocks = 0;
           bool panel = false;   // some workgroup keeps columns in the row panel
