@@ -685,6 +685,7 @@ void build_leaf_map(Plan& P) {
     }
   }
   P.leaf_panel_elems = lay.total;
+  P.leaf_layout = std::move(lay);
   P.leaf_dest = std::move(dest);
   if (P.seg_off.empty()) P.seg_off = {0, n};
 }

@@ -147,6 +147,9 @@ constexpr int kCpqrRegCols = 64;
 int cpqr_reg_rows(int a);
 size_t cpqr_reg_lds(int G, int a);
 int cpqr_reg_max_blocks(int rows, size_t lds_bytes);
+// The launches below first clear the nsync barrier words at `sync` (each
+// group's CoopDesc::sync points into them); nsync = 0 when the caller has
+// cleared them already.
 hipError_t launch_cpqr_reg(int rows, const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                            int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,

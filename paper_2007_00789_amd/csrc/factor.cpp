@@ -76,6 +76,18 @@ void DevArena::flush(hipStream_t s) {
     }
 }
 
+void DevArena::mark(const char* h, size_t bytes) {
+  if (bytes == 0) return;
+  for (auto& c : chunks_)
+    if (c.h && h >= c.h && h < c.h + c.size) {
+      const size_t off = (size_t)(h - c.h);
+      c.lo = std::min(c.lo, off);
+      c.hi = std::max(c.hi, off + bytes);
+      return;
+    }
+  throw Error(SPAND_E_STATE, "internal: staged descriptors outside the arena");
+}
+
 void DevArena::release() {
   for (auto& c : chunks_) {
     if (pool_) {
@@ -378,16 +390,15 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   std::vector<int32_t> sizes(P.steps[D].nc);
   for (int c = 0; c < P.steps[D].nc; ++c)
     sizes[c] = (int32_t)(P.steps[D].vert_ptr[c + 1] - P.steps[D].vert_ptr[c]);
+  int cur = 0;
+  PanelLayout lay = P.leaf_layout;
+  double* panel = static_cast<double*>(C.panels[cur].ensure(lay.total * sizeof(double)));
+  SPAND_PROF(C, "k_fill", launch_fill(panel, lay.total, 0.0, s));
+  SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
   std::vector<std::vector<int32_t>> pos(P.steps[D].nc);
   for (int c = 0; c < P.steps[D].nc; ++c)
     pos[c].assign(P.steps[D].verts.begin() + P.steps[D].vert_ptr[c],
                   P.steps[D].verts.begin() + P.steps[D].vert_ptr[c + 1]);
-
-  int cur = 0;
-  PanelLayout lay = make_layout(P.steps[D], sizes);
-  double* panel = static_cast<double*>(C.panels[cur].ensure(lay.total * sizeof(double)));
-  SPAND_PROF(C, "k_fill", launch_fill(panel, lay.total, 0.0, s));
-  SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
 
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
@@ -481,30 +492,33 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
       }
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
-      // from the plan: targets and their interiors in ascending order)
-      gd.clear();
-      gt.clear();
+      // from the plan: targets and their interiors in ascending order).  The
+      // descriptors are written in place into the pinned upload buffer.
       tiles.clear();
-      gd.reserve(st.schur.size());
-      gt.reserve(st.schur_terms.size());
+      GemmDesc* d_sgd = nullptr;
+      GemmTerm* d_sgt = nullptr;
+      GemmDesc* hgd = C.upload.stage<GemmDesc>(st.schur.size(), &d_sgd);
+      GemmTerm* hgt = C.upload.stage<GemmTerm>(st.schur_terms.size(), &d_sgt);
+      int64_t ngd = 0, ngt = 0;
       for (const StepPlan::SchurTarget& tg : st.schur) {
         const int w1 = tg.w1, w2 = tg.w2;
         if (sizes[w1] == 0 || sizes[w2] == 0) continue;
-        const int64_t t0 = (int64_t)gt.size();
+        const int64_t t0 = ngt;
         for (int64_t q = tg.t0; q < tg.t1; ++q) {
           const StepPlan::SchurTerm& tm = st.schur_terms[q];
           const int ns = sizes[tm.s];
           if (ns == 0) continue;
           const int64_t c1 = lay.coff[tm.e1] - ns;
           const int64_t c2 = lay.coff[tm.e2] - ns;
-          gt.push_back({R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0});
+          hgt[ngt++] = GemmTerm{R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0};
         }
-        if ((int64_t)gt.size() == t0) continue;
-        GemmDesc g{};
+        if (ngt == t0) continue;
+        GemmDesc& g = hgd[ngd];
+        g = GemmDesc{};
         g.C = blk(w1, tg.e);
         g.C2 = w1 == w2 ? nullptr : blk(w2, st.adj_rev[tg.e]);
         g.term0 = t0;
-        g.term1 = (int64_t)gt.size();
+        g.term1 = ngt;
         g.ldc = sizes[w1];
         g.ldc2 = sizes[w2];
         g.m = sizes[w1];
@@ -514,14 +528,14 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         g.lower_only = w1 == w2;
         g.alpha = -1.0;
         g.beta = 1.0;
-        gd.push_back(g);
-        add_gemm_tiles(tiles, (int32_t)gd.size() - 1, g.m, g.n, w1 == w2);
+        add_gemm_tiles(tiles, (int32_t)ngd, g.m, g.n, w1 == w2);
+        ++ngd;
       }
       if (!tiles.empty()) {
-        const auto* d_gd = C.upload.upload(gd);
-        const auto* d_gt = C.upload.upload(gt);
+        C.upload.commit(hgd, (size_t)ngd);
+        C.upload.commit(hgt, (size_t)ngt);
         const auto* d_tiles = C.upload.upload(tiles);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_tiles, (int64_t)tiles.size(), s));
       }
     }
 
@@ -618,6 +632,22 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
       // the others the single-workgroup QR on a global-memory workspace
       coop_used.assign(nc, 0);
+      // All colours are planned (and their descriptors staged) first, then the
+      // barrier words of every cooperative launch of the step are cleared by
+      // one fill and the launches follow back to back.
+      struct QrLaunch {
+        int kind;   // 0 register-resident, 1 LDS-resident, 2 single-workgroup
+        const CpqrDesc* cd;
+        const CoopDesc* qd;
+        const CpqrNbr* cn;
+        const int32_t* map;
+        int32_t count, ma, mk, rows;
+        size_t lds;
+        bool panel;
+      };
+      std::vector<QrLaunch> qrl;
+      int32_t* sync_all = C.upload.alloc_n<int32_t>((size_t)std::max(nc - nI, 1) * kCoopSyncInts);
+      int64_t sync_used = 0;
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrDesc> cd;
         std::vector<CoopDesc> qd, qd_reg;
@@ -689,11 +719,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           cd.push_back(d);
         }
         const CpqrNbr* d_cn = C.upload.upload(cn);
-        if (!cd.empty()) {
-          const auto* d_cd = C.upload.upload(cd);
-          SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r, d_r2,
-                                              d_k, eps, eps_stop, ma, mk, s));
-        }
+        if (!cd.empty())
+          qrl.push_back({2, C.upload.upload(cd), nullptr, d_cn, nullptr, (int32_t)cd.size(), ma, mk,
+                         0, 0, false});
         // cooperative groups, packed onto XCDs (all workgroups of a group on
         // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
         // groups per launch as can be co-resident
@@ -749,8 +777,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             std::vector<int32_t> blk_map((size_t)nblocks, -1);
             int64_t xdoubles = 0;
             for (int i : members) xdoubles += coop_xch_doubles(list[i].G, list[i].d.a);
-            const int nsync = (int)members.size() * kCoopSyncInts;
-            int32_t* sync = C.upload.alloc_n<int32_t>((size_t)nsync);
+            int32_t* sync = sync_all + sync_used;
+            sync_used += (int64_t)members.size() * kCoopSyncInts;
+            if (sync_used > (int64_t)std::max(nc - nI, 1) * kCoopSyncInts)
+              throw Error(SPAND_E_STATE, "internal: cooperative QR barrier words exhausted");
             double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
             std::vector<CoopDesc> batch;
             int64_t xo = 0;
@@ -765,54 +795,93 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
                     (int32_t)(bi * kCoopMaxGroup + g);
               batch.push_back(q);
             }
-            const auto* d_qd = C.upload.upload(batch);
-            const auto* d_map = C.upload.upload(blk_map);
-            hipError_t he = hipSuccess;
-            if (kind == 0) {
-              SPAND_PROF(C, "k_cpqr_reg",
-                         he = launch_cpqr_reg(rows, d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur,
-                                              d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
-            } else {
-              SPAND_PROF(C, "k_cpqr_coop",
-                         he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, sync, nsync, d_ncur,
-                                               d_r, d_r2, d_k, eps, eps_stop, d_err, lds, panel,
-                                               s));
-            }
-            SPAND_HIP(he);
+            qrl.push_back({kind, nullptr, C.upload.upload(batch), d_cn, C.upload.upload(blk_map),
+                           nblocks, 0, 0, rows, lds, panel});
           }
         }
       }
+      launch_fill_int(sync_all, sync_used, s);
+      for (const QrLaunch& q : qrl) {
+        hipError_t he = hipSuccess;
+        if (q.kind == 2) {
+          SPAND_PROF(C, "k_cpqr", launch_cpqr(q.cd, q.cn, q.count, d_ncur, d_r, d_r2, d_k, eps,
+                                              eps_stop, q.ma, q.mk, s));
+        } else if (q.kind == 0) {
+          SPAND_PROF(C, "k_cpqr_reg",
+                     he = launch_cpqr_reg(q.rows, q.qd, q.cn, q.map, q.count, nullptr, 0, d_ncur,
+                                          d_r, d_r2, d_k, eps, eps_stop, d_err, q.lds, s));
+        } else {
+          SPAND_PROF(C, "k_cpqr_coop",
+                     he = launch_cpqr_coop(q.qd, q.cn, q.map, q.count, nullptr, 0, d_ncur, d_r,
+                                           d_r2, d_k, eps, eps_stop, d_err, q.lds, q.panel, s));
+        }
+        SPAND_HIP(he);
+      }
     }
-    // read back breakdown flags and ranks
-    std::vector<int32_t> info_i(pd.size()), info_f(zd.size()), hr(nc), hr2(nc), hk(nc);
-    if (!pd.empty())
-      SPAND_HIP(hipMemcpyAsync(info_i.data(), d_info_i, sizeof(int32_t) * pd.size(),
-                               hipMemcpyDeviceToHost, s));
-    if (!zd.empty())
-      SPAND_HIP(hipMemcpyAsync(info_f.data(), d_info_f, sizeof(int32_t) * zd.size(),
-                               hipMemcpyDeviceToHost, s));
-    int32_t herr = 0;
-    if (st.sparsified) {
-      SPAND_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      SPAND_HIP(hipMemcpyAsync(hr.data(), d_r, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-      SPAND_HIP(hipMemcpyAsync(hr2.data(), d_r2, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-      SPAND_HIP(hipMemcpyAsync(hk.data(), d_k, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-    }
+    // read back ranks and breakdown flags in one copy: r | r2 | k | info
+    // (interiors) | info (interfaces) | error word
+    std::vector<int32_t> hb(5 * (size_t)nc + 1);
+    SPAND_HIP(hipMemcpyAsync(hb.data(), d_r, sizeof(int32_t) * hb.size(), hipMemcpyDeviceToHost, s));
     SPAND_HIP(hipStreamSynchronize(s));
-    check_info(info_i, pd_cluster, l, "interior block");
-    check_info(info_f, zd_cluster, l, "interface block");
+    check_info(std::vector<int32_t>(hb.begin() + 3 * (size_t)nc, hb.begin() + 3 * (size_t)nc + pd.size()),
+               pd_cluster, l, "interior block");
+    check_info(std::vector<int32_t>(hb.begin() + 4 * (size_t)nc, hb.begin() + 4 * (size_t)nc + zd.size()),
+               zd_cluster, l, "interface block");
+    const int32_t herr = hb[5 * (size_t)nc];
     if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
     if (herr & 2) throw CoopPlacement();
 
     std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
-    if (st.sparsified) {
-      // sizes of the neighbours at the time each interface was sparsified
+    if (st.sparsified)
       for (int p = nI; p < nc; ++p) {
-        R.r[p] = hr[p];
-        R.r2[p] = hr2[p];
-        R.k[p] = hk[p];
-        cur_sizes[p] = hr[p];
+        R.r[p] = hb[p];
+        R.r2[p] = hb[(size_t)nc + p];
+        R.k[p] = hb[2 * (size_t)nc + p];
+        cur_sizes[p] = R.r[p];
       }
+    const bool stop_here = o.debug_stop_step == l;
+
+    // ---------------- (d) merge into step l-1 ----------------
+    // launched as soon as the ranks are known; the host bookkeeping of this
+    // step (positions, statistics, apply records) follows while it runs
+    std::vector<int32_t> nsz;
+    PanelLayout nlay;
+    double* npanel = nullptr;
+    if (!stop_here) {
+      const StepPlan& nx = P.steps[l - 1];
+      nsz.assign(nx.nc, 0);
+      std::vector<int32_t> choff(st.nc, 0);  // row offset of a child inside its parent
+      for (int c = 0; c < nx.nc; ++c)
+        for (int64_t e = nx.child_ptr[c]; e < nx.child_ptr[c + 1]; ++e) {
+          const int ch = nx.child[e];
+          choff[ch] = nsz[c];
+          nsz[c] += cur_sizes[ch];
+        }
+      nlay = make_layout(nx, nsz);
+      npanel = static_cast<double*>(
+          C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
+      SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
+      CopyDesc* d_cp = nullptr;
+      CopyDesc* hcp = C.upload.stage<CopyDesc>(st.merge.size(), &d_cp);
+      int64_t ncp = 0;
+      for (const StepPlan::MergeCopy& mc : st.merge) {
+        const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
+        if (cur_sizes[ci] == 0 || cur_sizes[cj] == 0) continue;
+        CopyDesc& d = hcp[ncp++];
+        d.src = blk(ci, mc.ee);
+        d.lds = sizes[ci];
+        d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
+        d.ldd = nsz[P_];
+        d.m = cur_sizes[ci];
+        d.n = cur_sizes[cj];
+      }
+      C.upload.commit(hcp, (size_t)ncp);
+      SPAND_PROF(C, "k_copy", launch_copy(d_cp, ncp, s));
+    }
+
+    if (st.sparsified) {
+      // positions of the neighbour columns each interface was sparsified
+      // against (neighbours of earlier colours at their reduced sizes)
       for (int p = nI; p < nc; ++p) {
         auto& np = R.sp_nbr_pos[p];
         for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
@@ -842,7 +911,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
 
     if (apb) apb->publish(l);
 
-    if (o.debug_stop_step == l) {
+    if (stop_here) {
       F.stopped_at = l;
       F.dbg_layout = lay;
       F.dbg_ncur = cur_sizes;
@@ -852,38 +921,17 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       break;
     }
 
-    // ---------------- (d) merge into step l-1 ----------------
+    // variables of every cluster of step l-1 (its children's retained ones)
     const StepPlan& nx = P.steps[l - 1];
-    std::vector<int32_t> nsz(nx.nc, 0);
     std::vector<std::vector<int32_t>> npos(nx.nc);
-    std::vector<int32_t> choff(st.nc, 0);  // row offset of a child inside its parent
-    for (int c = 0; c < nx.nc; ++c)
+    for (int c = 0; c < nx.nc; ++c) {
+      auto& v = npos[c];
+      v.reserve(nsz[c]);
       for (int64_t e = nx.child_ptr[c]; e < nx.child_ptr[c + 1]; ++e) {
         const int ch = nx.child[e];
-        choff[ch] = nsz[c];
-        nsz[c] += cur_sizes[ch];
-        npos[c].insert(npos[c].end(), cpos[ch].begin(), cpos[ch].begin() + cur_sizes[ch]);
+        v.insert(v.end(), cpos[ch].begin(), cpos[ch].begin() + cur_sizes[ch]);
       }
-    PanelLayout nlay = make_layout(nx, nsz);
-    double* npanel =
-        static_cast<double*>(C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
-    SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
-    std::vector<CopyDesc> cp;
-    cp.reserve(st.merge.size());
-    for (const StepPlan::MergeCopy& mc : st.merge) {
-      const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
-      if (cur_sizes[ci] == 0 || cur_sizes[cj] == 0) continue;
-      CopyDesc d{};
-      d.src = blk(ci, mc.ee);
-      d.lds = sizes[ci];
-      d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
-      d.ldd = nsz[P_];
-      d.m = cur_sizes[ci];
-      d.n = cur_sizes[cj];
-      cp.push_back(d);
     }
-    const auto* d_cp = C.upload.upload(cp);
-    SPAND_PROF(C, "k_copy", launch_copy(d_cp, (int64_t)cp.size(), s));
     // no wait: the next step is planned while the merge runs (its uploads go
     // to the other descriptor arena)
     cur = 1 - cur;

@@ -70,6 +70,14 @@ struct StepPlan {
   std::vector<MergeCopy> merge;
 };
 
+struct PanelLayout {
+  std::vector<int32_t> n;
+  std::vector<int64_t> off;
+  std::vector<int64_t> width;
+  std::vector<int64_t> coff;   // per adjacency entry
+  int64_t total = 0;
+};
+
 struct Plan {
   int64_t n = 0, nnz = 0;
   int depth = 0, skip = 4, dim = 0;
@@ -87,6 +95,7 @@ struct Plan {
   std::vector<int64_t> leaf_dest;      // host copy of the same map
   int64_t leaf_panel_elems = 0;
   std::vector<int64_t> leaf_panel_off; // per leaf-step cluster
+  PanelLayout leaf_layout;             // panel layout of the leaf step
   // independent problems of a batch plan: problem s owns rows seg_off[s] ..
   // seg_off[s+1]-1 (one segment for a single problem)
   std::vector<int64_t> seg_off;
@@ -110,13 +119,6 @@ void build_leaf_map(Plan& P);
 // Layout of one step's row panels: cluster c holds rows n[c] x width[c] in
 // column-major order (ld = n[c]) at offset off[c]; the block (c, adj[e]) starts
 // at column coff[e].
-struct PanelLayout {
-  std::vector<int32_t> n;
-  std::vector<int64_t> off;
-  std::vector<int64_t> width;
-  std::vector<int64_t> coff;   // per adjacency entry
-  int64_t total = 0;
-};
 PanelLayout make_layout(const StepPlan& st, const std::vector<int32_t>& sizes);
 
 }  // namespace spand

@@ -66,6 +66,18 @@ class DevArena {
     c.hi = std::max(c.hi, off + bytes);
     return d;
   }
+  // room for n elements to be written in place in the pinned host copy:
+  // returns their host address and sets *dev to the device address;
+  // commit(h, count) then includes the first count of them in the next flush
+  template <class T>
+  T* stage(size_t n, T** dev) {
+    T* d = alloc_n<T>(std::max<size_t>(n, 1));
+    const Chunk& c = chunks_[cur_];
+    *dev = d;
+    return reinterpret_cast<T*>(c.h + (reinterpret_cast<char*>(d) - c.p));
+  }
+  template <class T>
+  void commit(const T* h, size_t count) { mark(reinterpret_cast<const char*>(h), count * sizeof(T)); }
   void flush(hipStream_t s);
   void reset() { cur_ = 0; used_ = 0; }
   void release();
@@ -74,6 +86,7 @@ class DevArena {
 
  private:
   struct Chunk { char* p; char* h; size_t size, lo, hi; };
+  void mark(const char* h, size_t bytes);
   bool mirrored_;
   std::shared_ptr<MemPool> pool_;
   std::vector<Chunk> chunks_;
@@ -90,6 +103,10 @@ class UploadRing {
   T* upload(const std::vector<T>& v) { return a_[cur_].upload(v); }
   template <class T>
   T* alloc_n(size_t n) { return a_[cur_].alloc_n<T>(n); }
+  template <class T>
+  T* stage(size_t n, T** dev) { return a_[cur_].stage<T>(n, dev); }
+  template <class T>
+  void commit(const T* h, size_t count) { a_[cur_].commit(h, count); }
   void flush(hipStream_t s) { a_[cur_].flush(s); }
   // switch to the other arena and make all of it reusable
   void next() {
