@@ -13,6 +13,7 @@
 // The ranks of a step decide the next step's sizes; they are read back once
 // per step (a few KB).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -74,6 +75,20 @@ void DevArena::flush(hipStream_t s) {
       c.lo = SIZE_MAX;
       c.hi = 0;
     }
+}
+
+void UploadRing::next(hipStream_t s) {
+  if (!ev_[cur_]) SPAND_HIP(hipEventCreateWithFlags(&ev_[cur_], hipEventDisableTiming));
+  SPAND_HIP(hipEventRecord(ev_[cur_], s));
+  used_[cur_] = true;
+  cur_ ^= 1;
+  if (used_[cur_]) SPAND_HIP(hipEventSynchronize(ev_[cur_]));
+  a_[cur_].reset();
+}
+
+UploadRing::~UploadRing() {
+  for (hipEvent_t e : ev_)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void DevArena::mark(const char* h, size_t bytes) {
@@ -240,6 +255,43 @@ inline int64_t find_adj(const StepPlan& st, int c, int target) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// output tiles of an m x n GEMM (lower_only: those touching the lower triangle)
+int64_t gemm_tile_count(int m, int n, bool lower_only) {
+  const int64_t tm = ceil_div(m, kGemmTile), tn = ceil_div(n, kGemmTile);
+  if (!lower_only) return tm * tn;
+  int64_t c = 0;
+  for (int64_t j = 0; j < tn; ++j) c += std::max<int64_t>(0, tm - j);
+  return c;
+}
+
+int64_t put_gemm_tiles(TileRef* out, int32_t desc, int m, int n, bool lower_only) {
+  const int tm = (int)ceil_div(m, kGemmTile), tn = (int)ceil_div(n, kGemmTile);
+  int64_t c = 0;
+  for (int j = 0; j < tn; ++j)
+    for (int i = 0; i < tm; ++i)
+      if (!lower_only || i >= j) out[c++] = TileRef{desc, i, j, 0};
+  return c;
+}
+
+// f(i) for i in [0, count) on up to nth threads, the calling one included
+template <class Fn>
+void host_parallel(int count, int nth, const Fn& f) {
+  std::atomic<int> next{0};
+  auto run = [&] {
+    for (int i; (i = next.fetch_add(1)) < count;) f(i);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < std::min(nth, count); ++t) pool.emplace_back(run);
+  run();
+  for (auto& t : pool) t.join();
+}
+
+// threads for building a descriptor list of `items` entries on the host
+int desc_threads(size_t items) {
+  if (items < 16384) return 1;
+  return std::min(8, (int)std::max(1u, std::thread::hardware_concurrency()));
+}
+
 void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, bool lower_only) {
   const int tm = (int)ceil_div(m, kGemmTile), tn = (int)ceil_div(n, kGemmTile);
   for (int j = 0; j < tn; ++j)
@@ -390,25 +442,67 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   std::vector<int32_t> sizes(P.steps[D].nc);
   for (int c = 0; c < P.steps[D].nc; ++c)
     sizes[c] = (int32_t)(P.steps[D].vert_ptr[c + 1] - P.steps[D].vert_ptr[c]);
+  // integer outputs of every step in one device buffer, the steps' regions in
+  // the order D ... 0, each n_cur | r | r2 | k | info (interiors) | info
+  // (interfaces) | error word (n_cur lives in the step's upload instead)
+  std::vector<int64_t> ioff(D + 1, 0);
+  int64_t itotal = 0;
+  for (int l = D; l >= 0; --l) {
+    ioff[l] = itotal;
+    itotal += (6 * (int64_t)P.steps[l].nc + 1 + 63) / 64 * 64;
+  }
+  int32_t* dint_all = static_cast<int32_t*>(C.ints.ensure(sizeof(int32_t) * itotal));
+  SPAND_HIP(hipMemsetAsync(dint_all, 0, sizeof(int32_t) * itotal, s));
+  // Steps without sparsification do not wait for the device: their breakdown
+  // flags are read back with those of the next step that does (a failed block
+  // leaves a zero inverse, so the steps in between stay finite).
+  struct Deferred {
+    int l;
+    std::vector<int32_t> clusters;
+  };
+  std::vector<Deferred> deferred;
+  // reads back the integer outputs of the deferred steps and of step l (whose
+  // region ends at element `end` of that step's region) and checks the
+  // breakdown flags; returns step l's region
+  auto read_back = [&](int l, int64_t end, const std::vector<int32_t>& pdc,
+                       const std::vector<int32_t>& zdc) {
+    const int64_t lo = deferred.empty() ? ioff[l] : ioff[deferred.front().l];
+    std::vector<int32_t> hb((size_t)(ioff[l] + end - lo));
+    SPAND_HIP(hipMemcpyAsync(hb.data(), dint_all + lo, sizeof(int32_t) * hb.size(),
+                             hipMemcpyDeviceToHost, s));
+    SPAND_HIP(hipStreamSynchronize(s));
+    auto flags = [&](int ls, int slot, size_t count) {
+      const size_t b = (size_t)(ioff[ls] - lo) + (size_t)slot * P.steps[ls].nc;
+      return std::vector<int32_t>(hb.begin() + b, hb.begin() + b + count);
+    };
+    for (const Deferred& d : deferred)
+      check_info(flags(d.l, 4, d.clusters.size()), d.clusters, d.l, "interior block");
+    deferred.clear();
+    check_info(flags(l, 4, pdc.size()), pdc, l, "interior block");
+    check_info(flags(l, 5, zdc.size()), zdc, l, "interface block");
+    return std::vector<int32_t>(hb.begin() + (ioff[l] - lo), hb.end());
+  };
+
   int cur = 0;
-  PanelLayout lay = P.leaf_layout;
-  double* panel = static_cast<double*>(C.panels[cur].ensure(lay.total * sizeof(double)));
-  SPAND_PROF(C, "k_fill", launch_fill(panel, lay.total, 0.0, s));
+  PanelLayout lay_store;
+  const PanelLayout* layp = &P.leaf_layout;
+  double* panel = static_cast<double*>(C.panels[cur].ensure(layp->total * sizeof(double)));
+  SPAND_PROF(C, "k_fill", launch_fill(panel, layp->total, 0.0, s));
   SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
-  std::vector<std::vector<int32_t>> pos(P.steps[D].nc);
-  for (int c = 0; c < P.steps[D].nc; ++c)
-    pos[c].assign(P.steps[D].verts.begin() + P.steps[D].vert_ptr[c],
-                  P.steps[D].verts.begin() + P.steps[D].vert_ptr[c + 1]);
+  PosLists pos;
+  pos.ptr = P.steps[D].vert_ptr;
+  pos.idx = P.steps[D].verts;
 
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
     StepRec& R = F.steps[l];
-    C.upload.next();
+    const PanelLayout& lay = *layp;
+    C.upload.next(s);
     R.l = l;
     R.sparsified = st.sparsified;
     R.n0 = sizes;
     R.pos = std::move(pos);   // `pos` is refilled with step l-1's lists at the merge
-    const std::vector<std::vector<int32_t>>& cpos = R.pos;
+    const PosLists& cpos = R.pos;
     const int nI = st.nI, nc = st.nc;
     R.r.assign(nc, -1);
     R.r2.assign(nc, -1);
@@ -423,24 +517,19 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.T.assign(nc, nullptr);
     R.VT.assign(nc, nullptr);
     R.kmax.assign(nc, 0);
-    R.sp_nbr_pos.assign(nc, {});
+    R.sp_nbr_pos = PosLists{};
     auto blk = [&](int c, int64_t e) { return panel + lay.off[c] + lay.coff[e] * lay.n[c]; };
 
-    // per-step integer outputs: n_cur | r | r2 | k | info (interiors) | info (interfaces)
-    int32_t* dint = static_cast<int32_t*>(C.ints.ensure(sizeof(int32_t) * (6 * (size_t)nc + 64)));
-    int32_t* d_ncur = dint;
+    // this step's integer outputs (cleared at the start); the current sizes
+    // n_cur start as a copy of the sizes in the step's upload buffer
+    int32_t* dint = dint_all + ioff[l];
     int32_t* d_r = dint + nc;
     int32_t* d_r2 = dint + 2 * nc;
     int32_t* d_k = dint + 3 * nc;
     int32_t* d_info_i = dint + 4 * nc;
     int32_t* d_info_f = dint + 5 * nc;
     int32_t* d_err = dint + 6 * nc;
-    SPAND_HIP(hipMemsetAsync(dint, 0, sizeof(int32_t) * (6 * (size_t)nc + 1), s));
-    {
-      const int32_t* h = C.upload.upload(sizes);
-      C.upload.flush(s);
-      SPAND_HIP(hipMemcpyAsync(d_ncur, h, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, s));
-    }
+    int32_t* d_ncur = C.upload.upload(sizes);
 
     // ---------------- (a) interiors ----------------
     std::vector<PotrfDesc> pd;
@@ -493,59 +582,89 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       }
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
       // from the plan: targets and their interiors in ascending order).  The
-      // descriptors are written in place into the pinned upload buffer.
-      tiles.clear();
-      GemmDesc* d_sgd = nullptr;
-      GemmTerm* d_sgt = nullptr;
-      GemmDesc* hgd = C.upload.stage<GemmDesc>(st.schur.size(), &d_sgd);
-      GemmTerm* hgt = C.upload.stage<GemmTerm>(st.schur_terms.size(), &d_sgt);
-      int64_t ngd = 0, ngt = 0;
-      for (const StepPlan::SchurTarget& tg : st.schur) {
-        const int w1 = tg.w1, w2 = tg.w2;
-        if (sizes[w1] == 0 || sizes[w2] == 0) continue;
-        const int64_t t0 = ngt;
-        for (int64_t q = tg.t0; q < tg.t1; ++q) {
-          const StepPlan::SchurTerm& tm = st.schur_terms[q];
-          const int ns = sizes[tm.s];
-          if (ns == 0) continue;
-          const int64_t c1 = lay.coff[tm.e1] - ns;
-          const int64_t c2 = lay.coff[tm.e2] - ns;
-          hgt[ngt++] = GemmTerm{R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0};
+      // descriptors are written in place into the pinned upload buffer, in
+      // chunks of targets on several threads for large steps: a counting pass
+      // gives every chunk its offsets, a second pass writes.
+      const int64_t nsch = (int64_t)st.schur.size();
+      const int nth = desc_threads((size_t)nsch);
+      const int nchunk = nth > 1 ? 4 * nth : 1;
+      std::vector<int64_t> o_gd(nchunk + 1, 0), o_gt(nchunk + 1, 0), o_tl(nchunk + 1, 0);
+      auto live_terms = [&](const StepPlan::SchurTarget& tg) {
+        int64_t t = 0;
+        for (int64_t q = tg.t0; q < tg.t1; ++q) t += sizes[st.schur_terms[q].s] != 0;
+        return t;
+      };
+      host_parallel(nchunk, nth, [&](int c) {
+        int64_t ngd = 0, ngt = 0, ntl = 0;
+        for (int64_t i = nsch * c / nchunk; i < nsch * (c + 1) / nchunk; ++i) {
+          const StepPlan::SchurTarget& tg = st.schur[i];
+          if (sizes[tg.w1] == 0 || sizes[tg.w2] == 0) continue;
+          const int64_t t = live_terms(tg);
+          if (t == 0) continue;
+          ++ngd;
+          ngt += t;
+          ntl += gemm_tile_count(sizes[tg.w1], sizes[tg.w2], tg.w1 == tg.w2);
         }
-        if (ngt == t0) continue;
-        GemmDesc& g = hgd[ngd];
-        g = GemmDesc{};
-        g.C = blk(w1, tg.e);
-        g.C2 = w1 == w2 ? nullptr : blk(w2, st.adj_rev[tg.e]);
-        g.term0 = t0;
-        g.term1 = ngt;
-        g.ldc = sizes[w1];
-        g.ldc2 = sizes[w2];
-        g.m = sizes[w1];
-        g.n = sizes[w2];
-        g.transA = 1;
-        g.transB = 0;
-        g.lower_only = w1 == w2;
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        add_gemm_tiles(tiles, (int32_t)ngd, g.m, g.n, w1 == w2);
-        ++ngd;
+        o_gd[c + 1] = ngd;
+        o_gt[c + 1] = ngt;
+        o_tl[c + 1] = ntl;
+      });
+      for (int c = 0; c < nchunk; ++c) {
+        o_gd[c + 1] += o_gd[c];
+        o_gt[c + 1] += o_gt[c];
+        o_tl[c + 1] += o_tl[c];
       }
-      if (!tiles.empty()) {
-        C.upload.commit(hgd, (size_t)ngd);
-        C.upload.commit(hgt, (size_t)ngt);
-        const auto* d_tiles = C.upload.upload(tiles);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_tiles, (int64_t)tiles.size(), s));
+      if (o_tl[nchunk] > 0) {
+        GemmDesc* d_sgd = nullptr;
+        GemmTerm* d_sgt = nullptr;
+        TileRef* d_stl = nullptr;
+        GemmDesc* hgd = C.upload.stage<GemmDesc>((size_t)o_gd[nchunk], &d_sgd);
+        GemmTerm* hgt = C.upload.stage<GemmTerm>((size_t)o_gt[nchunk], &d_sgt);
+        TileRef* htl = C.upload.stage<TileRef>((size_t)o_tl[nchunk], &d_stl);
+        host_parallel(nchunk, nth, [&](int c) {
+          int64_t igd = o_gd[c], igt = o_gt[c], itl = o_tl[c];
+          for (int64_t i = nsch * c / nchunk; i < nsch * (c + 1) / nchunk; ++i) {
+            const StepPlan::SchurTarget& tg = st.schur[i];
+            const int w1 = tg.w1, w2 = tg.w2;
+            if (sizes[w1] == 0 || sizes[w2] == 0) continue;
+            const int64_t t0 = igt;
+            for (int64_t q = tg.t0; q < tg.t1; ++q) {
+              const StepPlan::SchurTerm& tm = st.schur_terms[q];
+              const int ns = sizes[tm.s];
+              if (ns == 0) continue;
+              const int64_t c1 = lay.coff[tm.e1] - ns;
+              const int64_t c2 = lay.coff[tm.e2] - ns;
+              hgt[igt++] = GemmTerm{R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0};
+            }
+            if (igt == t0) continue;
+            GemmDesc& g = hgd[igd];
+            g = GemmDesc{};
+            g.C = blk(w1, tg.e);
+            g.C2 = w1 == w2 ? nullptr : blk(w2, st.adj_rev[tg.e]);
+            g.term0 = t0;
+            g.term1 = igt;
+            g.ldc = sizes[w1];
+            g.ldc2 = sizes[w2];
+            g.m = sizes[w1];
+            g.n = sizes[w2];
+            g.transA = 1;
+            g.transB = 0;
+            g.lower_only = w1 == w2;
+            g.alpha = -1.0;
+            g.beta = 1.0;
+            itl += put_gemm_tiles(htl + itl, (int32_t)igd, g.m, g.n, w1 == w2);
+            ++igd;
+          }
+        });
+        C.upload.commit(hgd, (size_t)o_gd[nchunk]);
+        C.upload.commit(hgt, (size_t)o_gt[nchunk]);
+        C.upload.commit(htl, (size_t)o_tl[nchunk]);
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], s));
       }
     }
 
     if (l == 0) {
-      std::vector<int32_t> info(pd.size());
-      if (!pd.empty())
-        SPAND_HIP(hipMemcpyAsync(info.data(), d_info_i, sizeof(int32_t) * pd.size(),
-                                 hipMemcpyDeviceToHost, s));
-      SPAND_HIP(hipStreamSynchronize(s));
-      check_info(info, pd_cluster, l, "interior block");
+      read_back(l, 6 * (int64_t)nc + 1, pd_cluster, {});
       F.stats.root_size = nc > 0 ? sizes[0] : 0;
       break;
     }
@@ -818,28 +937,25 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         SPAND_HIP(he);
       }
     }
-    // read back ranks and breakdown flags in one copy: r | r2 | k | info
-    // (interiors) | info (interfaces) | error word
-    std::vector<int32_t> hb(5 * (size_t)nc + 1);
-    SPAND_HIP(hipMemcpyAsync(hb.data(), d_r, sizeof(int32_t) * hb.size(), hipMemcpyDeviceToHost, s));
-    SPAND_HIP(hipStreamSynchronize(s));
-    check_info(std::vector<int32_t>(hb.begin() + 3 * (size_t)nc, hb.begin() + 3 * (size_t)nc + pd.size()),
-               pd_cluster, l, "interior block");
-    check_info(std::vector<int32_t>(hb.begin() + 4 * (size_t)nc, hb.begin() + 4 * (size_t)nc + zd.size()),
-               zd_cluster, l, "interface block");
-    const int32_t herr = hb[5 * (size_t)nc];
-    if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
-    if (herr & 2) throw CoopPlacement();
-
-    std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
-    if (st.sparsified)
-      for (int p = nI; p < nc; ++p) {
-        R.r[p] = hb[p];
-        R.r2[p] = hb[(size_t)nc + p];
-        R.k[p] = hb[2 * (size_t)nc + p];
-        cur_sizes[p] = R.r[p];
-      }
+    // ranks and breakdown flags: read back at sparsified steps (and when
+    // stopping after this step), deferred otherwise
     const bool stop_here = o.debug_stop_step == l;
+    std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
+    if (st.sparsified || stop_here) {
+      const std::vector<int32_t> hb = read_back(l, 6 * (int64_t)nc + 1, pd_cluster, zd_cluster);
+      const int32_t herr = hb[6 * (size_t)nc];
+      if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
+      if (herr & 2) throw CoopPlacement();
+      if (st.sparsified)
+        for (int p = nI; p < nc; ++p) {
+          R.r[p] = hb[(size_t)nc + p];
+          R.r2[p] = hb[2 * (size_t)nc + p];
+          R.k[p] = hb[3 * (size_t)nc + p];
+          cur_sizes[p] = R.r[p];
+        }
+    } else {
+      deferred.push_back({l, std::move(pd_cluster)});
+    }
 
     // ---------------- (d) merge into step l-1 ----------------
     // launched as soon as the ranks are known; the host bookkeeping of this
@@ -861,36 +977,54 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       npanel = static_cast<double*>(
           C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
       SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
+      const int64_t nm = (int64_t)st.merge.size();
+      const int mth = desc_threads((size_t)nm);
+      const int mchunk = mth > 1 ? 4 * mth : 1;
+      std::vector<int64_t> o_cp(mchunk + 1, 0);
+      auto live = [&](const StepPlan::MergeCopy& mc) {
+        return cur_sizes[mc.ci] != 0 && cur_sizes[mc.cj] != 0;
+      };
+      host_parallel(mchunk, mth, [&](int c) {
+        int64_t k = 0;
+        for (int64_t i = nm * c / mchunk; i < nm * (c + 1) / mchunk; ++i) k += live(st.merge[i]);
+        o_cp[c + 1] = k;
+      });
+      for (int c = 0; c < mchunk; ++c) o_cp[c + 1] += o_cp[c];
       CopyDesc* d_cp = nullptr;
-      CopyDesc* hcp = C.upload.stage<CopyDesc>(st.merge.size(), &d_cp);
-      int64_t ncp = 0;
-      for (const StepPlan::MergeCopy& mc : st.merge) {
-        const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
-        if (cur_sizes[ci] == 0 || cur_sizes[cj] == 0) continue;
-        CopyDesc& d = hcp[ncp++];
-        d.src = blk(ci, mc.ee);
-        d.lds = sizes[ci];
-        d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
-        d.ldd = nsz[P_];
-        d.m = cur_sizes[ci];
-        d.n = cur_sizes[cj];
-      }
-      C.upload.commit(hcp, (size_t)ncp);
-      SPAND_PROF(C, "k_copy", launch_copy(d_cp, ncp, s));
+      CopyDesc* hcp = C.upload.stage<CopyDesc>((size_t)o_cp[mchunk], &d_cp);
+      host_parallel(mchunk, mth, [&](int c) {
+        int64_t k = o_cp[c];
+        for (int64_t i = nm * c / mchunk; i < nm * (c + 1) / mchunk; ++i) {
+          const StepPlan::MergeCopy& mc = st.merge[i];
+          if (!live(mc)) continue;
+          const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
+          CopyDesc& d = hcp[k++];
+          d.src = blk(ci, mc.ee);
+          d.lds = sizes[ci];
+          d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
+          d.ldd = nsz[P_];
+          d.m = cur_sizes[ci];
+          d.n = cur_sizes[cj];
+        }
+      });
+      C.upload.commit(hcp, (size_t)o_cp[mchunk]);
+      SPAND_PROF(C, "k_copy", launch_copy(d_cp, o_cp[mchunk], s));
     }
 
     if (st.sparsified) {
       // positions of the neighbour columns each interface was sparsified
       // against (neighbours of earlier colours at their reduced sizes)
+      PosLists& np = R.sp_nbr_pos;
+      np.ptr.assign((size_t)nc + 1, 0);
       for (int p = nI; p < nc; ++p) {
-        auto& np = R.sp_nbr_pos[p];
         for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
           const int w = st.adj[e];
           if (w == p || w < nI) continue;
           const int wc = st.colour[w] < st.colour[p] ? R.r[w] : sizes[w];
-          np.insert(np.end(), cpos[w].begin(), cpos[w].begin() + wc);
+          np.idx.insert(np.idx.end(), cpos.begin(w), cpos.begin(w) + wc);
         }
-        if ((int)np.size() != R.k[p])
+        np.ptr[p + 1] = (int64_t)np.idx.size();
+        if (np.size(p) != R.k[p])
           throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " +
                                          std::to_string(l));
         const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
@@ -923,27 +1057,29 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
 
     // variables of every cluster of step l-1 (its children's retained ones)
     const StepPlan& nx = P.steps[l - 1];
-    std::vector<std::vector<int32_t>> npos(nx.nc);
+    PosLists npos;
+    npos.ptr.assign((size_t)nx.nc + 1, 0);
+    npos.idx.reserve((size_t)std::accumulate(nsz.begin(), nsz.end(), int64_t(0)));
     for (int c = 0; c < nx.nc; ++c) {
-      auto& v = npos[c];
-      v.reserve(nsz[c]);
       for (int64_t e = nx.child_ptr[c]; e < nx.child_ptr[c + 1]; ++e) {
         const int ch = nx.child[e];
-        v.insert(v.end(), cpos[ch].begin(), cpos[ch].begin() + cur_sizes[ch]);
+        npos.idx.insert(npos.idx.end(), cpos.begin(ch), cpos.begin(ch) + cur_sizes[ch]);
       }
+      npos.ptr[c + 1] = (int64_t)npos.idx.size();
     }
     // no wait: the next step is planned while the merge runs (its uploads go
     // to the other descriptor arena)
     cur = 1 - cur;
     panel = npanel;
-    lay = std::move(nlay);
+    lay_store = std::move(nlay);
+    layp = &lay_store;
     sizes = std::move(nsz);
     pos = std::move(npos);
   }
   if (F.stopped_at < 0) {
     // triangular factors of the compact WY forms of every sparsified interface:
     // S = V^T V (lower triangle) by one batched GEMM, then the column recurrence
-    C.upload.next();
+    C.upload.next(s);
     std::vector<GemmDesc> gd;
     std::vector<GemmTerm> gt;
     std::vector<TileRef> tiles;
@@ -1006,6 +1142,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));
+  if (!deferred.empty()) throw Error(SPAND_E_STATE, "internal: breakdown flags left unchecked");
   if (apb && F.stopped_at < 0) {
     apb->finish();
     finish_apply(C, F);

@@ -356,7 +356,10 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
     __syncthreads();
     const int f = chol_inplace<kPotrfThreads>(S, n, n);
     if (f) {
+      // breakdown: report it and leave a zero inverse, so that the products
+      // formed with it before the flag is read stay finite
       if (tid == 0) info[blockIdx.x] = f;
+      for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
       return;
     }
     trinv<kPotrfThreads>(S, n, X, n, n, tmp);
@@ -364,7 +367,11 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
   } else {
     // the panel's diagonal block (ld n) is dead after this call: factor in place
     const int f = chol_inv_blocked(const_cast<double*>(d.A), d.X, n, sm);
-    if (f && tid == 0) info[blockIdx.x] = f;
+    if (f) {
+      if (tid == 0) info[blockIdx.x] = f;
+      __syncthreads();
+      for (int64_t idx = tid; idx < (int64_t)n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
+    }
   }
 }
 

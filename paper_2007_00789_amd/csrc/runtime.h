@@ -95,10 +95,15 @@ class DevArena {
 
 // Two mirrored descriptor arenas used by alternate steps of the factorization:
 // a step's uploads may still be in flight on the stream while the host plans
-// the next step, and are consumed by the time the step after that resets them
-// (every step synchronizes once, to read its ranks).
+// the next step.  Switching arenas records an event on the stream for the one
+// left; an arena is reset only after the event of its previous use has
+// completed (the host waits there when the device is more than a step behind).
 class UploadRing {
  public:
+  UploadRing() = default;
+  UploadRing(const UploadRing&) = delete;
+  UploadRing& operator=(const UploadRing&) = delete;
+  ~UploadRing();
   template <class T>
   T* upload(const std::vector<T>& v) { return a_[cur_].upload(v); }
   template <class T>
@@ -108,14 +113,14 @@ class UploadRing {
   template <class T>
   void commit(const T* h, size_t count) { a_[cur_].commit(h, count); }
   void flush(hipStream_t s) { a_[cur_].flush(s); }
-  // switch to the other arena and make all of it reusable
-  void next() {
-    cur_ ^= 1;
-    a_[cur_].reset();
-  }
+  // switch to the other arena and make all of it reusable once the copies
+  // and kernels that read it before have completed
+  void next(hipStream_t s);
 
  private:
   DevArena a_[2] = {DevArena(true), DevArena(true)};
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  bool used_[2] = {false, false};
   int cur_ = 0;
 };
 
@@ -172,6 +177,15 @@ struct Ctx {
   Prof prof;
 };
 
+// Variables of every cluster of one step, flat: cluster c holds
+// idx[ptr[c] .. ptr[c+1]).
+struct PosLists {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> idx;
+  const int32_t* begin(int c) const { return idx.data() + ptr[c]; }
+  int32_t size(int c) const { return (int32_t)(ptr[c + 1] - ptr[c]); }
+};
+
 // Host record of one step of a numeric factorization.  The apply replays the
 // operations from these records (device pointers into the factor arena).
 struct StepRec {
@@ -184,8 +198,8 @@ struct StepRec {
   std::vector<int32_t> kint;                 // interiors: coupling width
   std::vector<double*> Zinv, Y, V, tau, T;   // interfaces of sparsified steps
   std::vector<double*> VT;                   // interfaces: V T (a x nref), for the apply
-  std::vector<std::vector<int32_t>> pos;     // positions of each cluster's variables (step start)
-  std::vector<std::vector<int32_t>> sp_nbr_pos;  // interfaces: positions of W's columns
+  PosLists pos;                              // positions of each cluster's variables (step start)
+  PosLists sp_nbr_pos;                       // interfaces: positions of W's columns
 };
 
 struct FactorObj {

@@ -93,7 +93,11 @@ void build_apply_step(FactorObj& F, int l) {
     as.l = l;
     const int nI = st.nI, nc = st.nc;
     std::vector<const int32_t*> dpos(nc, nullptr);
-    for (int c = 0; c < nc; ++c) dpos[c] = F.meta.upload(R.pos[c]);
+    {
+      const int32_t* base = F.meta.upload(R.pos.idx);
+      for (int c = 0; c < nc; ++c)
+        if (R.pos.size(c) > 0) dpos[c] = base + R.pos.ptr[c];
+    }
     // interiors
     std::vector<ApInt> ins;
     std::vector<int64_t> toff(nc, 0);
@@ -105,7 +109,7 @@ void build_apply_step(FactorObj& F, int l) {
       for (int64_t e = st.adj_ptr[sI]; e < st.adj_ptr[sI + 1]; ++e) {
         const int w = st.adj[e];
         if (w == sI) continue;
-        nbr.insert(nbr.end(), R.pos[w].begin(), R.pos[w].end());
+        nbr.insert(nbr.end(), R.pos.begin(w), R.pos.begin(w) + R.pos.size(w));
       }
       ApInt d{};
       d.Linv = R.Linv[sI];
@@ -247,6 +251,7 @@ void build_apply_step(FactorObj& F, int l) {
     as.n_sc = (int32_t)scs.size();
     // sparsification, per colour
     if (st.sparsified) {
+      const int32_t* d_nbr_pos = F.meta.upload(R.sp_nbr_pos.idx);
       as.colours.resize(st.ncolours);
       for (int colour = 0; colour < st.ncolours; ++colour) {
         ApplyColour& ac = as.colours[colour];
@@ -263,7 +268,7 @@ void build_apply_step(FactorObj& F, int l) {
           d.T = R.T[p];
           d.VT = R.VT[p];
           d.pos = dpos[p];
-          d.nbr_pos = F.meta.upload(R.sp_nbr_pos[p]);
+          d.nbr_pos = R.sp_nbr_pos.size(p) > 0 ? d_nbr_pos + R.sp_nbr_pos.ptr[p] : nullptr;
           d.a = R.n0[p];
           d.nref = R.r2[p];
           d.f0 = R.r[p];

@@ -202,6 +202,25 @@ def test_not_spd_reports_step_and_cluster(ctx):
 
 
 @gpu
+def test_not_spd_in_a_step_without_sparsification(ctx):
+    # steps 4 and 3 are not sparsified (skip 2): their breakdown flags are
+    # read with those of step 2, and the failed block must still be named
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(32)
+    vals = p.vals.copy()
+    diag = p.rowptr[0] + np.flatnonzero(p.colind[p.rowptr[0]:p.rowptr[1]] == 0)[0]
+    vals[diag] = -4.0
+    opts = spand.make_opts(depth=4, skip=2, eps=1e-2)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    with pytest.raises(spand.SpandError) as e:
+        ctx.factor(plan, _dev(vals), opts)
+    assert e.value.status == -3 and "step 4" in e.value.message
+    # the context stays usable: the unmodified matrix factors
+    fac = ctx.factor(plan, _dev(p.vals), opts)
+    fac.close()
+
+
+@gpu
 def test_no_convergence_status(ctx):
     p = laplacian_2d(32)
     _, fac = _gpu_factor(ctx, p, 4, 0, 0.3, "FO")
