@@ -84,6 +84,7 @@ void UploadRing::next(hipStream_t s) {
   cur_ ^= 1;
   if (used_[cur_]) SPAND_HIP(hipEventSynchronize(ev_[cur_]));
   a_[cur_].reset();
+  s_[cur_].reset();
 }
 
 UploadRing::~UploadRing() {
@@ -310,6 +311,55 @@ void check_info(const std::vector<int32_t>& info, const std::vector<int32_t>& cl
 
 }  // namespace
 
+// Position lists of step l, once its records are final: the variables of
+// every cluster (the leaf vertices, or the retained variables of the children
+// in step l+1, in child order) and, for a sparsified step, the columns of the
+// coupling each interface was sparsified against (neighbours of earlier
+// colours at their reduced sizes, in adjacency order).
+void build_positions(FactorObj& F, int l) {
+  const Plan& P = *F.plan;
+  const StepPlan& st = P.steps[l];
+  StepRec& R = F.steps[l];
+  if (l == P.depth) {
+    R.pos.ptr = st.vert_ptr;
+    R.pos.idx = st.verts;
+  } else {
+    const StepPlan& ch_st = P.steps[l + 1];
+    const StepRec& Rc = F.steps[l + 1];
+    auto kept = [&](int ch) {
+      return Rc.sparsified && ch >= ch_st.nI ? Rc.r[ch] : Rc.n0[ch];
+    };
+    PosLists& pos = R.pos;
+    pos.ptr.assign((size_t)st.nc + 1, 0);
+    pos.idx.clear();
+    for (int c = 0; c < st.nc; ++c) {
+      for (int64_t e = st.child_ptr[c]; e < st.child_ptr[c + 1]; ++e) {
+        const int ch = st.child[e];
+        pos.idx.insert(pos.idx.end(), Rc.pos.begin(ch), Rc.pos.begin(ch) + kept(ch));
+      }
+      pos.ptr[c + 1] = (int64_t)pos.idx.size();
+      if (pos.size(c) != R.n0[c])
+        throw Error(SPAND_E_STATE, "internal: cluster size mismatch at step " + std::to_string(l));
+    }
+  }
+  R.sp_nbr_pos = PosLists{};
+  if (!st.sparsified) return;
+  const int nI = st.nI, nc = st.nc;
+  PosLists& np = R.sp_nbr_pos;
+  np.ptr.assign((size_t)nc + 1, 0);
+  for (int p = nI; p < nc; ++p) {
+    for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+      const int w = st.adj[e];
+      if (w == p || w < nI) continue;
+      const int wc = st.colour[w] < st.colour[p] ? R.r[w] : R.n0[w];
+      np.idx.insert(np.idx.end(), R.pos.begin(w), R.pos.begin(w) + wc);
+    }
+    np.ptr[p + 1] = (int64_t)np.idx.size();
+    if (np.size(p) != R.k[p])
+      throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " + std::to_string(l));
+  }
+}
+
 // Builds the apply program of every step whose factorization records are
 // final on a host thread, beside the factorization of the later steps.
 class ApplyBuilder {
@@ -355,6 +405,7 @@ class ApplyBuilder {
           cv_.wait(lk, [&] { return stop_ || ready_ <= l; });
           if (stop_) return;
         }
+        build_positions(F_, l);
         build_apply_step(F_, l);
       }
     } catch (...) {
@@ -443,13 +494,19 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   for (int c = 0; c < P.steps[D].nc; ++c)
     sizes[c] = (int32_t)(P.steps[D].vert_ptr[c + 1] - P.steps[D].vert_ptr[c]);
   // integer outputs of every step in one device buffer, the steps' regions in
-  // the order D ... 0, each n_cur | r | r2 | k | info (interiors) | info
-  // (interfaces) | error word (n_cur lives in the step's upload instead)
+  // the order D ... 0: breakdown flags of the interiors (one per interior),
+  // and for a sparsified step those of the interfaces, an error word and the
+  // ranks r, r2 and coupling widths k (one per cluster):
+  // info_i [nI] | info_f [nc - nI] | err | r [nc] | r2 [nc] | k [nc]
+  auto region = [&](int l) {
+    const StepPlan& q = P.steps[l];
+    return q.sparsified ? 4 * (int64_t)q.nc + 1 : std::max<int64_t>(q.nI, 1);
+  };
   std::vector<int64_t> ioff(D + 1, 0);
   int64_t itotal = 0;
   for (int l = D; l >= 0; --l) {
     ioff[l] = itotal;
-    itotal += (6 * (int64_t)P.steps[l].nc + 1 + 63) / 64 * 64;
+    itotal += (region(l) + 15) / 16 * 16;
   }
   int32_t* dint_all = static_cast<int32_t*>(C.ints.ensure(sizeof(int32_t) * itotal));
   SPAND_HIP(hipMemsetAsync(dint_all, 0, sizeof(int32_t) * itotal, s));
@@ -461,25 +518,24 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     std::vector<int32_t> clusters;
   };
   std::vector<Deferred> deferred;
-  // reads back the integer outputs of the deferred steps and of step l (whose
-  // region ends at element `end` of that step's region) and checks the
-  // breakdown flags; returns step l's region
-  auto read_back = [&](int l, int64_t end, const std::vector<int32_t>& pdc,
-                       const std::vector<int32_t>& zdc) {
+  // reads back the integer outputs of the deferred steps and of step l in one
+  // copy (their regions are adjacent) and checks the breakdown flags;
+  // returns step l's region
+  auto read_back = [&](int l, const std::vector<int32_t>& pdc, const std::vector<int32_t>& zdc) {
     const int64_t lo = deferred.empty() ? ioff[l] : ioff[deferred.front().l];
-    std::vector<int32_t> hb((size_t)(ioff[l] + end - lo));
+    std::vector<int32_t> hb((size_t)(ioff[l] + region(l) - lo));
     SPAND_HIP(hipMemcpyAsync(hb.data(), dint_all + lo, sizeof(int32_t) * hb.size(),
                              hipMemcpyDeviceToHost, s));
     SPAND_HIP(hipStreamSynchronize(s));
-    auto flags = [&](int ls, int slot, size_t count) {
-      const size_t b = (size_t)(ioff[ls] - lo) + (size_t)slot * P.steps[ls].nc;
+    auto flags = [&](int ls, int64_t at, size_t count) {
+      const size_t b = (size_t)(ioff[ls] - lo + at);
       return std::vector<int32_t>(hb.begin() + b, hb.begin() + b + count);
     };
     for (const Deferred& d : deferred)
-      check_info(flags(d.l, 4, d.clusters.size()), d.clusters, d.l, "interior block");
+      check_info(flags(d.l, 0, d.clusters.size()), d.clusters, d.l, "interior block");
     deferred.clear();
-    check_info(flags(l, 4, pdc.size()), pdc, l, "interior block");
-    check_info(flags(l, 5, zdc.size()), zdc, l, "interface block");
+    check_info(flags(l, 0, pdc.size()), pdc, l, "interior block");
+    check_info(flags(l, P.steps[l].nI, zdc.size()), zdc, l, "interface block");
     return std::vector<int32_t>(hb.begin() + (ioff[l] - lo), hb.end());
   };
 
@@ -489,9 +545,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   double* panel = static_cast<double*>(C.panels[cur].ensure(layp->total * sizeof(double)));
   SPAND_PROF(C, "k_fill", launch_fill(panel, layp->total, 0.0, s));
   SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
-  PosLists pos;
-  pos.ptr = P.steps[D].vert_ptr;
-  pos.idx = P.steps[D].verts;
 
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
@@ -501,8 +554,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.l = l;
     R.sparsified = st.sparsified;
     R.n0 = sizes;
-    R.pos = std::move(pos);   // `pos` is refilled with step l-1's lists at the merge
-    const PosLists& cpos = R.pos;
     const int nI = st.nI, nc = st.nc;
     R.r.assign(nc, -1);
     R.r2.assign(nc, -1);
@@ -517,18 +568,17 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     R.T.assign(nc, nullptr);
     R.VT.assign(nc, nullptr);
     R.kmax.assign(nc, 0);
-    R.sp_nbr_pos = PosLists{};
     auto blk = [&](int c, int64_t e) { return panel + lay.off[c] + lay.coff[e] * lay.n[c]; };
 
     // this step's integer outputs (cleared at the start); the current sizes
     // n_cur start as a copy of the sizes in the step's upload buffer
     int32_t* dint = dint_all + ioff[l];
-    int32_t* d_r = dint + nc;
-    int32_t* d_r2 = dint + 2 * nc;
-    int32_t* d_k = dint + 3 * nc;
-    int32_t* d_info_i = dint + 4 * nc;
-    int32_t* d_info_f = dint + 5 * nc;
-    int32_t* d_err = dint + 6 * nc;
+    int32_t* d_info_i = dint;
+    int32_t* d_info_f = st.sparsified ? dint + nI : nullptr;
+    int32_t* d_err = st.sparsified ? dint + nc : nullptr;
+    int32_t* d_r = st.sparsified ? dint + nc + 1 : nullptr;
+    int32_t* d_r2 = st.sparsified ? d_r + nc : nullptr;
+    int32_t* d_k = st.sparsified ? d_r + 2 * nc : nullptr;
     int32_t* d_ncur = C.upload.upload(sizes);
 
     // ---------------- (a) interiors ----------------
@@ -664,7 +714,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
 
     if (l == 0) {
-      read_back(l, 6 * (int64_t)nc + 1, pd_cluster, {});
+      read_back(l, pd_cluster, {});
       F.stats.root_size = nc > 0 ? sizes[0] : 0;
       break;
     }
@@ -751,21 +801,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
       // the others the single-workgroup QR on a global-memory workspace
       coop_used.assign(nc, 0);
-      // All colours are planned (and their descriptors staged) first, then the
-      // barrier words of every cooperative launch of the step are cleared by
-      // one fill and the launches follow back to back.
-      struct QrLaunch {
-        int kind;   // 0 register-resident, 1 LDS-resident, 2 single-workgroup
-        const CpqrDesc* cd;
-        const CoopDesc* qd;
-        const CpqrNbr* cn;
-        const int32_t* map;
-        int32_t count, ma, mk, rows;
-        size_t lds;
-        bool panel;
-      };
-      std::vector<QrLaunch> qrl;
-      int32_t* sync_all = C.upload.alloc_n<int32_t>((size_t)std::max(nc - nI, 1) * kCoopSyncInts);
+      // The barrier words of every cooperative group of the step (at most one
+      // group per interface) are cleared by one fill before the first launch;
+      // each colour is launched as soon as it is planned.
+      const int64_t sync_cap = (int64_t)std::max(nc - nI, 1) * kCoopSyncInts;
+      int32_t* sync_all = C.upload.scratch_n<int32_t>((size_t)sync_cap);
+      launch_fill_int(sync_all, sync_cap, s);
       int64_t sync_used = 0;
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrDesc> cd;
@@ -838,9 +879,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           cd.push_back(d);
         }
         const CpqrNbr* d_cn = C.upload.upload(cn);
-        if (!cd.empty())
-          qrl.push_back({2, C.upload.upload(cd), nullptr, d_cn, nullptr, (int32_t)cd.size(), ma, mk,
-                         0, 0, false});
+        if (!cd.empty()) {
+          const auto* d_cd = C.upload.upload(cd);
+          SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r, d_r2,
+                                              d_k, eps, eps_stop, ma, mk, s));
+        }
         // cooperative groups, packed onto XCDs (all workgroups of a group on
         // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
         // groups per launch as can be co-resident
@@ -898,9 +941,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             for (int i : members) xdoubles += coop_xch_doubles(list[i].G, list[i].d.a);
             int32_t* sync = sync_all + sync_used;
             sync_used += (int64_t)members.size() * kCoopSyncInts;
-            if (sync_used > (int64_t)std::max(nc - nI, 1) * kCoopSyncInts)
+            if (sync_used > sync_cap)
               throw Error(SPAND_E_STATE, "internal: cooperative QR barrier words exhausted");
-            double* xch = C.upload.alloc_n<double>((size_t)xdoubles);
+            double* xch = C.upload.scratch_n<double>((size_t)xdoubles);
             std::vector<CoopDesc> batch;
             int64_t xo = 0;
             for (size_t bi = 0; bi < members.size(); ++bi) {
@@ -914,27 +957,21 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
                     (int32_t)(bi * kCoopMaxGroup + g);
               batch.push_back(q);
             }
-            qrl.push_back({kind, nullptr, C.upload.upload(batch), d_cn, C.upload.upload(blk_map),
-                           nblocks, 0, 0, rows, lds, panel});
+            const auto* d_qd = C.upload.upload(batch);
+            const auto* d_map = C.upload.upload(blk_map);
+            hipError_t he = hipSuccess;
+            if (kind == 0) {
+              SPAND_PROF(C, "k_cpqr_reg",
+                         he = launch_cpqr_reg(rows, d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur,
+                                              d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
+            } else {
+              SPAND_PROF(C, "k_cpqr_coop",
+                         he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur, d_r,
+                                               d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
+            }
+            SPAND_HIP(he);
           }
         }
-      }
-      launch_fill_int(sync_all, sync_used, s);
-      for (const QrLaunch& q : qrl) {
-        hipError_t he = hipSuccess;
-        if (q.kind == 2) {
-          SPAND_PROF(C, "k_cpqr", launch_cpqr(q.cd, q.cn, q.count, d_ncur, d_r, d_r2, d_k, eps,
-                                              eps_stop, q.ma, q.mk, s));
-        } else if (q.kind == 0) {
-          SPAND_PROF(C, "k_cpqr_reg",
-                     he = launch_cpqr_reg(q.rows, q.qd, q.cn, q.map, q.count, nullptr, 0, d_ncur,
-                                          d_r, d_r2, d_k, eps, eps_stop, d_err, q.lds, s));
-        } else {
-          SPAND_PROF(C, "k_cpqr_coop",
-                     he = launch_cpqr_coop(q.qd, q.cn, q.map, q.count, nullptr, 0, d_ncur, d_r,
-                                           d_r2, d_k, eps, eps_stop, d_err, q.lds, q.panel, s));
-        }
-        SPAND_HIP(he);
       }
     }
     // ranks and breakdown flags: read back at sparsified steps (and when
@@ -942,17 +979,18 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     const bool stop_here = o.debug_stop_step == l;
     std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
     if (st.sparsified || stop_here) {
-      const std::vector<int32_t> hb = read_back(l, 6 * (int64_t)nc + 1, pd_cluster, zd_cluster);
-      const int32_t herr = hb[6 * (size_t)nc];
-      if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
-      if (herr & 2) throw CoopPlacement();
-      if (st.sparsified)
+      const std::vector<int32_t> hb = read_back(l, pd_cluster, zd_cluster);
+      if (st.sparsified) {
+        const int32_t herr = hb[nc];
+        if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
+        if (herr & 2) throw CoopPlacement();
         for (int p = nI; p < nc; ++p) {
-          R.r[p] = hb[(size_t)nc + p];
-          R.r2[p] = hb[2 * (size_t)nc + p];
-          R.k[p] = hb[3 * (size_t)nc + p];
+          R.r[p] = hb[(size_t)nc + 1 + p];
+          R.r2[p] = hb[2 * (size_t)nc + 1 + p];
+          R.k[p] = hb[3 * (size_t)nc + 1 + p];
           cur_sizes[p] = R.r[p];
         }
+      }
     } else {
       deferred.push_back({l, std::move(pd_cluster)});
     }
@@ -1012,21 +1050,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
 
     if (st.sparsified) {
-      // positions of the neighbour columns each interface was sparsified
-      // against (neighbours of earlier colours at their reduced sizes)
-      PosLists& np = R.sp_nbr_pos;
-      np.ptr.assign((size_t)nc + 1, 0);
+      // statistics, and room for V T (formed at the end); the position lists
+      // of this step are built by the apply builder
       for (int p = nI; p < nc; ++p) {
-        for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
-          const int w = st.adj[e];
-          if (w == p || w < nI) continue;
-          const int wc = st.colour[w] < st.colour[p] ? R.r[w] : sizes[w];
-          np.idx.insert(np.idx.end(), cpos.begin(w), cpos.begin(w) + wc);
-        }
-        np.ptr[p + 1] = (int64_t)np.idx.size();
-        if (np.size(p) != R.k[p])
-          throw Error(SPAND_E_STATE, "internal: coupling width mismatch at step " +
-                                         std::to_string(l));
         const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
         if (R.V[p] && r2 > 0) R.VT[p] = F.arena.alloc_n<double>((size_t)a * r2);   // V T, formed at the end
         flops += (double)a * a * k;
@@ -1055,18 +1081,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       break;
     }
 
-    // variables of every cluster of step l-1 (its children's retained ones)
-    const StepPlan& nx = P.steps[l - 1];
-    PosLists npos;
-    npos.ptr.assign((size_t)nx.nc + 1, 0);
-    npos.idx.reserve((size_t)std::accumulate(nsz.begin(), nsz.end(), int64_t(0)));
-    for (int c = 0; c < nx.nc; ++c) {
-      for (int64_t e = nx.child_ptr[c]; e < nx.child_ptr[c + 1]; ++e) {
-        const int ch = nx.child[e];
-        npos.idx.insert(npos.idx.end(), cpos.begin(ch), cpos.begin(ch) + cur_sizes[ch]);
-      }
-      npos.ptr[c + 1] = (int64_t)npos.idx.size();
-    }
     // no wait: the next step is planned while the merge runs (its uploads go
     // to the other descriptor arena)
     cur = 1 - cur;
@@ -1074,7 +1088,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     lay_store = std::move(nlay);
     layp = &lay_store;
     sizes = std::move(nsz);
-    pos = std::move(npos);
   }
   if (F.stopped_at < 0) {
     // triangular factors of the compact WY forms of every sparsified interface:

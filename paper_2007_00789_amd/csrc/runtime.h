@@ -106,8 +106,10 @@ class UploadRing {
   ~UploadRing();
   template <class T>
   T* upload(const std::vector<T>& v) { return a_[cur_].upload(v); }
+  // device-only scratch of the current step (never in an uploaded range, so
+  // no flush overwrites it)
   template <class T>
-  T* alloc_n(size_t n) { return a_[cur_].alloc_n<T>(n); }
+  T* scratch_n(size_t n) { return s_[cur_].alloc_n<T>(n); }
   template <class T>
   T* stage(size_t n, T** dev) { return a_[cur_].stage<T>(n, dev); }
   template <class T>
@@ -119,6 +121,7 @@ class UploadRing {
 
  private:
   DevArena a_[2] = {DevArena(true), DevArena(true)};
+  DevArena s_[2];
   hipEvent_t ev_[2] = {nullptr, nullptr};
   bool used_[2] = {false, false};
   int cur_ = 0;
