@@ -126,8 +126,15 @@ struct CopyDesc {
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double* panels,
                     hipStream_t s);
+// X = L^{-1} with A = L L^T for count blocks of at most max_n rows (info[i]:
+// 0, or the 1-based column of the first non-positive pivot of block i, whose
+// X is then left zero).  launch_potrf_inv: max_n <= 64 runs one wave per
+// block, larger max_n one workgroup per block; launch_potrf_blocks always
+// runs one workgroup per block.
 void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s);
+void launch_potrf_blocks(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
+                         hipStream_t s);
 void launch_gemm(const GemmDesc* d, const GemmTerm* t, const TileRef* tiles, int64_t ntiles,
                  hipStream_t s);
 void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n_cur,

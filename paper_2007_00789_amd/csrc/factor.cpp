@@ -300,6 +300,46 @@ void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, boo
       if (!lower_only || i >= j) tiles.push_back({desc, i, j, 0});
 }
 
+// Blocks of at most 64 rows first, the larger ones after; the breakdown flags
+// follow the same order.
+void order_potrf(std::vector<PotrfDesc>& pd, std::vector<int32_t>& clusters) {
+  std::vector<size_t> ord(pd.size());
+  std::iota(ord.begin(), ord.end(), size_t(0));
+  std::stable_partition(ord.begin(), ord.end(), [&](size_t i) { return pd[i].n <= 64; });
+  std::vector<PotrfDesc> p2(pd.size());
+  std::vector<int32_t> c2(pd.size());
+  for (size_t i = 0; i < ord.size(); ++i) {
+    p2[i] = pd[ord[i]];
+    c2[i] = clusters[ord[i]];
+  }
+  pd.swap(p2);
+  clusters.swap(c2);
+}
+
+// Many small blocks go to the one-wave-per-block kernel (its throughput is
+// higher; its latency per block is not, so a few small blocks stay with the
+// workgroup-per-block kernel).
+constexpr int32_t kWaveBlocksMin = 2048;
+
+void launch_potrf_split(const std::vector<PotrfDesc>& pd, const PotrfDesc* d_pd, int32_t* info,
+                        hipStream_t s) {
+  int32_t nsmall = 0, max_s = 0, max_b = 0;
+  for (const PotrfDesc& q : pd) {
+    if (q.n <= 64) {
+      ++nsmall;
+      max_s = std::max(max_s, q.n);
+    } else {
+      max_b = std::max(max_b, q.n);
+    }
+  }
+  if (nsmall < kWaveBlocksMin) {
+    launch_potrf_blocks(d_pd, (int32_t)pd.size(), std::max(max_s, max_b), info, s);
+    return;
+  }
+  launch_potrf_inv(d_pd, nsmall, max_s, info, s);
+  launch_potrf_blocks(d_pd + nsmall, (int32_t)pd.size() - nsmall, max_b, info + nsmall, s);
+}
+
 void check_info(const std::vector<int32_t>& info, const std::vector<int32_t>& clusters, int l,
                 const char* what) {
   for (size_t i = 0; i < info.size(); ++i)
@@ -600,8 +640,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
     if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
     if (!pd.empty()) {
+      order_potrf(pd, pd_cluster);
       const auto* d_pd = C.upload.upload(pd);
-      SPAND_PROF(C, "k_potrf_inv", launch_potrf_inv(d_pd, (int32_t)pd.size(), max_n, d_info_i, s));
+      SPAND_PROF(C, "k_potrf_inv", launch_potrf_split(pd, d_pd, d_info_i, s));
       // G_s = L_s^{-1} B_{s,W}
       std::vector<GemmDesc> gd;
       std::vector<GemmTerm> gt;
@@ -736,8 +777,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         nnzL += (int64_t)a * (a + 1) / 2;
       }
       if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
+      order_potrf(zd, zd_cluster);
       const auto* d_zd = C.upload.upload(zd);
-      SPAND_PROF(C, "k_potrf_inv", launch_potrf_inv(d_zd, (int32_t)zd.size(), max_a, d_info_f, s));
+      SPAND_PROF(C, "k_potrf_inv", launch_potrf_split(zd, d_zd, d_info_f, s));
       // two-sided scaling of every interface pair p < q
       std::vector<GemmDesc> g1, g2;
       std::vector<GemmTerm> t1, t2;

@@ -1,8 +1,9 @@
 // HIP kernels of the factorization (FP64, gfx950).
 //
-//  k_potrf_inv : batched uneven Cholesky + triangular inverse, one workgroup
-//                per block; blocks up to 128 rows live in LDS, larger ones are
-//                factored in place in global memory.
+//  k_potrf_inv_small : batched Cholesky + triangular inverse of blocks of at
+//                most 64 rows, one wave per block, the block in registers.
+//  k_potrf_inv : the same for larger blocks, one workgroup per block, by
+//                64x64 tiles through LDS, factored in place in global memory.
 //  k_gemm      : batched multi-term GEMM over 64x64 output tiles; serves the
 //                TRSM of the interiors (as a product with L^{-1}), the Schur
 //                complement scatter (one tile list per target block, terms in
@@ -376,6 +377,88 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
 }
 
 // ---------------------------------------------------------------------------
+// Cholesky + inverse of blocks of at most NM rows (NM = 32 or 64), one wave
+// per block and the block in registers: lane i holds row i of the lower
+// triangle, padded with the identity up to NM rows.  Column broadcasts go
+// through NM doubles of LDS per wave; there are no workgroup barriers (the
+// accesses of one wave to its LDS are in program order).
+//  Cholesky, right-looking: at column j lane j's diagonal gives l_jj, the
+//  lanes below scale their entry j and publish it, and every lane i updates
+//  its entries c in (j, i] by l_ij l_cj.
+//  Inverse in place, by columns from the last: with the lower-right block
+//  already inverted, x_jj = 1 / l_jj and x_ij = -x_jj sum_{m=j+1..i} x_im l_mj.
+// On breakdown the block's inverse is left zero (as in k_potrf_inv).
+// ---------------------------------------------------------------------------
+constexpr int kSmallWaves = 4;   // blocks (waves) per workgroup
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+template <int NM>
+__global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const PotrfDesc* descs,
+                                                                        int32_t count,
+                                                                        int32_t* info) {
+  __shared__ double colbuf[kSmallWaves][NM];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int b = blockIdx.x * kSmallWaves + w;
+  if (b >= count) return;   // the whole wave leaves; no workgroup barriers follow
+  const PotrfDesc d = descs[b];
+  const int n = d.n;
+  if (n == 0) return;
+  double* cb = colbuf[w];
+  double row[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c)
+    row[c] = (lane < n && c < n) ? (c <= lane ? d.A[lane + (int64_t)c * d.lda] : 0.0)
+                                 : (c == lane ? 1.0 : 0.0);
+  int fail = 0;
+#pragma unroll
+  for (int j = 0; j < NM; ++j) {
+    const double v = readlane_d(row[j], j);
+    if (!(v > 0.0)) {   // the same value in every lane
+      fail = j + 1;
+      break;
+    }
+    const double ljj = sqrt(v);
+    const double lij = lane > j ? row[j] / ljj : (lane == j ? ljj : 0.0);
+    if (lane >= j) row[j] = lij;
+    if (lane < NM) cb[lane] = lij;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = j + 1; c < NM; ++c) {
+      const double lcj = cb[c];
+      if (lane >= c) row[c] = fma(-lij, lcj, row[c]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (fail) {
+    if (lane == 0) info[b] = fail;
+    for (int c = 0; c < n; ++c)
+      if (lane < n) d.X[lane + (int64_t)c * n] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int j = NM - 1; j >= 0; --j) {
+    if (lane < NM) cb[lane] = row[j];   // column j of L, before it is overwritten
+    __builtin_amdgcn_wave_barrier();
+    const double xjj = 1.0 / cb[j];
+    double acc = 0.0;
+#pragma unroll
+    for (int m = j + 1; m < NM; ++m)
+      if (lane >= m) acc = fma(row[m], cb[m], acc);
+    if (lane > j) row[j] = -xjj * acc;
+    else if (lane == j) row[j] = xjj;
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int c = 0; c < NM; ++c)
+    if (lane < n && c < n) d.X[lane + (int64_t)c * n] = row[c];
+}
+
+// ---------------------------------------------------------------------------
 // Batched multi-term GEMM, 64x64 tile per workgroup, 4x4 per thread.
 // ---------------------------------------------------------------------------
 constexpr int kGemmThreads = 256;
@@ -713,6 +796,18 @@ void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double
 
 void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s) {
+  if (count <= 0) return;
+  if (max_n <= 64) {   // one wave per block, in registers
+    const dim3 grid((unsigned)((count + kSmallWaves - 1) / kSmallWaves)), block(kSmallWaves * kWave);
+    if (max_n <= 32) hipLaunchKernelGGL(k_potrf_inv_small<32>, grid, block, 0, s, d, count, info);
+    else hipLaunchKernelGGL(k_potrf_inv_small<64>, grid, block, 0, s, d, count, info);
+    return;
+  }
+  launch_potrf_blocks(d, count, max_n, info, s);
+}
+
+void launch_potrf_blocks(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
+                         hipStream_t s) {
   if (count <= 0) return;
   // n <= 64: the block, its inverse and the inverse's products in LDS; larger:
   // four 64x65 tiles

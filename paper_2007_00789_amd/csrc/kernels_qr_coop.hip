@@ -165,16 +165,21 @@ __device__ __forceinline__ double wave_max(double v) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-  return v;
+// DPP move of a 32-bit value whose invalid source lanes read `fill`
+template <int kCtrl>
+__device__ __forceinline__ int dpp_move_i32(int x, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, x, kCtrl, 0xf, 0xf, false);
 }
 
+// minimum over the wave, returned to every lane (same DPP pattern as wave_max)
 __device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-  return v;
+  v = min(v, dpp_move_i32<0xb1>(v, INT_MAX));
+  v = min(v, dpp_move_i32<0x4e>(v, INT_MAX));
+  v = min(v, dpp_move_i32<0x124>(v, INT_MAX));
+  v = min(v, dpp_move_i32<0x128>(v, INT_MAX));
+  v = min(v, dpp_move_i32<0x142>(v, INT_MAX));
+  v = min(v, dpp_move_i32<0x143>(v, INT_MAX));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // XCD this wave runs on (hardware register XCC_ID, bits 3:0)
@@ -228,10 +233,23 @@ __device__ bool wave_barrier(unsigned long long* flags, int phase, unsigned long
   }
 }
 
+// maximum over the wave, returned to every lane (invalid DPP sources read -inf)
 __device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-  return v;
+  constexpr int kNinf = (int)0xff800000;
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0xb1>(__float_as_int(v), kNinf)));
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0x4e>(__float_as_int(v), kNinf)));
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0x124>(__float_as_int(v), kNinf)));
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0x128>(__float_as_int(v), kNinf)));
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0x142>(__float_as_int(v), kNinf)));
+  v = fmaxf(v, __int_as_float(dpp_move_i32<0x143>(__float_as_int(v), kNinf)));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// 64-bit value of a lane given by a wave-uniform index
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // kPanel: some columns of a workgroup may live in the row panel (an interface
@@ -410,7 +428,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
             // the true maxima keep the order with a margin far above the band,
             // so the pivot is og's lowest-index candidate: its published one
             fast = true;
-            C = (int)((__shfl(bw, og, kWave) >> 32) & 0xFFFFull);
+            C = (int)((readlane_u64(bw, og) >> 32) & 0xFFFFull);
             PVg = PVs + (int64_t)og * (a + 1);
           }
         }
