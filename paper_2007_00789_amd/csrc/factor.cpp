@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <exception>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -274,17 +275,83 @@ int64_t put_gemm_tiles(TileRef* out, int32_t desc, int m, int n, bool lower_only
   return c;
 }
 
-// f(i) for i in [0, count) on up to nth threads, the calling one included
+// Worker threads kept for the descriptor loops of the factorization (thread
+// creation per loop cost more than the loops' own work at the leaf steps).
+// One job at a time; a caller that finds the pool busy runs its loop alone.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool pool;
+    return pool;
+  }
+  // f(i) for i in [0, count) on up to nth threads, the calling one included
+  void run(int count, int nth, const std::function<void(int)>& f) {
+    std::unique_lock<std::mutex> job(job_mu_, std::try_to_lock);
+    if (!job.owns_lock() || nth <= 1 || count <= 1) {
+      for (int i = 0; i < count; ++i) f(i);
+      return;
+    }
+    ensure_workers(nth - 1);
+    const int helpers = std::min<int>(nth - 1, (int)workers_.size());
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &f;
+      count_ = count;
+      next_.store(0);
+      want_ = helpers;
+      busy_ = helpers;
+      ++gen_;
+    }
+    cv_.notify_all();
+    drain();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return busy_ == 0; });
+    fn_ = nullptr;
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+
+ private:
+  void drain() {
+    for (int i; (i = next_.fetch_add(1)) < count_;) (*fn_)(i);
+  }
+  void ensure_workers(int n) {
+    while ((int)workers_.size() < n) workers_.emplace_back([this] { loop(); });
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    while (true) {
+      cv_.wait(lk, [&] { return stop_ || (gen_ != seen && want_ > 0); });
+      if (stop_) return;
+      seen = gen_;
+      --want_;
+      lk.unlock();
+      drain();
+      lk.lock();
+      if (--busy_ == 0) done_cv_.notify_one();
+    }
+  }
+  std::mutex job_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> workers_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int count_ = 0, want_ = 0, busy_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 template <class Fn>
 void host_parallel(int count, int nth, const Fn& f) {
-  std::atomic<int> next{0};
-  auto run = [&] {
-    for (int i; (i = next.fetch_add(1)) < count;) f(i);
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < std::min(nth, count); ++t) pool.emplace_back(run);
-  run();
-  for (auto& t : pool) t.join();
+  const std::function<void(int)> fn = std::cref(f);
+  HostPool::get().run(count, nth, fn);
 }
 
 // threads for building a descriptor list of `items` entries on the host
