@@ -292,20 +292,21 @@ class HostPool {
       return;
     }
     ensure_workers(nth - 1);
-    const int helpers = std::min<int>(nth - 1, (int)workers_.size());
     {
       std::lock_guard<std::mutex> lk(mu_);
       fn_ = &f;
       count_ = count;
       next_.store(0);
-      want_ = helpers;
-      busy_ = helpers;
+      want_ = std::min<int>(nth - 1, (int)workers_.size());
       ++gen_;
     }
     cv_.notify_all();
     drain();
+    // every index is taken: workers that have not woken yet stay out of this
+    // job, those inside it are waited for
     std::unique_lock<std::mutex> lk(mu_);
-    done_cv_.wait(lk, [&] { return busy_ == 0; });
+    want_ = 0;
+    done_cv_.wait(lk, [&] { return active_ == 0; });
     fn_ = nullptr;
   }
   ~HostPool() {
@@ -332,17 +333,18 @@ class HostPool {
       if (stop_) return;
       seen = gen_;
       --want_;
+      ++active_;
       lk.unlock();
       drain();
       lk.lock();
-      if (--busy_ == 0) done_cv_.notify_one();
+      if (--active_ == 0) done_cv_.notify_one();
     }
   }
   std::mutex job_mu_, mu_;
   std::condition_variable cv_, done_cv_;
   std::vector<std::thread> workers_;
   const std::function<void(int)>* fn_ = nullptr;
-  int count_ = 0, want_ = 0, busy_ = 0;
+  int count_ = 0, want_ = 0, active_ = 0;
   std::atomic<int> next_{0};
   uint64_t gen_ = 0;
   bool stop_ = false;
