@@ -86,10 +86,10 @@ def cpu_baseline(scheme: str, eps: float, gpu_ref: dict) -> dict:
 MEASURED_TRAFFIC = {
     "k_cpqr_coop": {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "128cd1366348736164d74c9dcf5cfa50658204477449b734707ae5e5a72da1a3",
-            "paper_2007_00789_amd/csrc/factor.cpp": "6a6ae9e884e9c3bd20bb9f84ee1e88d78e86f6d0895bcc6c5f4206d62698bd2f",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
+            "paper_2007_00789_amd/csrc/factor.cpp": "d253650b95b4696d4241be213c3d103c34ef3d918d1cca71531f7ff8584b42e4",
         },
-        "fetch_kib": 7599.6, "write_kib": 41257.5,
+        "fetch_kib": 7576.6, "write_kib": 42008.3,
         "fetch_scale": 1.9998, "write_scale": 1.0,
     },
 }
