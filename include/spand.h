@@ -74,6 +74,10 @@ typedef struct {
   int32_t qr_lds_cols;  /* 0 (default): a cooperative QR workgroup keeps as many of its columns
                            in LDS as fit, the rest (interfaces wider than 32 workgroups' LDS)
                            in the row panel; c > 0: at most c in LDS (testing) */
+  int32_t prescale;     /* 1: factor D^{-1/2} A D^{-1/2}, D = diag(A) (the symmetric diagonal
+                           prescaling of the experiments, Sec. 4), and apply
+                           M = D^{-1/2} M~ D^{-1/2} (M~ the preconditioner of the scaled matrix);
+                           a non-positive diagonal entry gives SPAND_E_NOT_SPD.  0 (default): off */
 } spand_opts;
 
 void spand_default_opts(spand_opts* opts);
@@ -90,7 +94,12 @@ const char* spand_last_error(spand_ctx_t ctx);
  * Fig. 1; the coordinate-bisection partition replaces the algebraic spaND
  * partition, whose definition the paper defers to the base spaND paper).
  * rowptr[n+1], colind[nnz] (0-based, sorted or not), coords[n*dim] row-major:
- * host pointers.  Checks pattern symmetry (SPAND_E_NOT_SYMMETRIC).  Pure host
+ * host pointers.  coords = NULL with dim = 0 selects the coordinate-free
+ * analysis: the bisection then runs on the hop distances of every vertex to
+ * three landmark vertices of the graph of A (farthest-point sampling: the
+ * vertex farthest from vertex 0, the one farthest from it, the one farthest
+ * from both; lowest id on ties), so only the pattern is needed.
+ * Checks pattern symmetry (SPAND_E_NOT_SYMMETRIC).  Pure host
  * work: ctx may be NULL (errors are then only reported by the status); the
  * plan is bound to a device by its first spand_factor. */
 spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
@@ -100,7 +109,8 @@ spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, co
  * plan, so that spand_factor, spand_apply and spand_pcg process all of them in
  * the same kernel launches (multi-problem batching, a project addition).
  * Problem i is given as for spand_analyze (n[i], rowptr[i], colind[i],
- * coords[i], dim[i]; host pointers, copied); its rows follow those of problems
+ * coords[i], dim[i]; host pointers, copied; coords[i] = NULL with dim[i] = 0
+ * for the coordinate-free analysis); its rows follow those of problems
  * 0..i-1 in the batch numbering, and the batch's CSR values are the problems'
  * values concatenated in that order.  depth[i] (NULL: opts->depth, and <= 0
  * means round(log2(n[i]/64)) per problem) is each problem's own nested-

@@ -42,6 +42,14 @@ Reading (the paper is silent on these points):
   order independent; it is not, for adjacent interfaces.)
 * Sparsified steps (scaling + sparsification, Alg. 2): 1 <= l <= depth - skip;
   the paper skips the first four levels (Sec. 4), so skip defaults to 4.
+
+Coordinate-free analysis (the paper's partition works on the matrix alone,
+Sec. 3; reading of this project): when no coordinates are given, each vertex
+gets as coordinates its hop distances in the graph of A to three landmarks
+chosen by farthest-point sampling -- l0 the vertex farthest from vertex 0, l1
+the vertex farthest from l0, l2 the vertex maximising the distance to the
+nearer of l0 and l1 (lowest vertex id on ties, unreachable vertices at
+distance n) -- and the bisection above runs on those.
 """
 from __future__ import annotations
 
@@ -213,10 +221,45 @@ def greedy_colour(adj, interfaces):
     return colour
 
 
-def analyze(rowptr, colind, coords, depth, skip=4):
-    """Geometric ND plus the per-step cluster structure (see module docstring)."""
+def hop_distances(rowptr, colind, src):
+    """Breadth-first hop distances from vertex src (n for unreachable vertices)."""
+    n = rowptr.size - 1
+    dist = np.full(n, n, dtype=np.int64)
+    dist[src] = 0
+    frontier = np.array([src], dtype=np.int64)
+    d = 0
+    while frontier.size:
+        d += 1
+        starts, ends = rowptr[frontier], rowptr[frontier + 1]
+        nbr = np.concatenate([colind[a:b] for a, b in zip(starts, ends)]) if frontier.size else frontier
+        nbr = np.unique(nbr)
+        new = nbr[dist[nbr] == n]
+        dist[new] = d
+        frontier = new
+    return dist
+
+
+def graph_coords(rowptr, colind):
+    """Landmark hop-distance coordinates (n x 3) of the coordinate-free reading."""
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colind = np.asarray(colind, dtype=np.int64)
+    t = hop_distances(rowptr, colind, 0)
+    l0 = int(np.argmax(t))                     # argmax: first (lowest) index of the maximum
+    d0 = hop_distances(rowptr, colind, l0)
+    l1 = int(np.argmax(d0))
+    d1 = hop_distances(rowptr, colind, l1)
+    l2 = int(np.argmax(np.minimum(d0, d1)))
+    d2 = hop_distances(rowptr, colind, l2)
+    return np.stack([d0, d1, d2], axis=1).astype(np.float64)
+
+
+def analyze(rowptr, colind, coords, depth, skip=4):
+    """Geometric ND plus the per-step cluster structure (see module docstring);
+    coords None: the coordinate-free reading (landmark hop distances)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colind = np.asarray(colind, dtype=np.int64)
+    if coords is None:
+        coords = graph_coords(rowptr, colind)
     coords = np.asarray(coords, dtype=np.float64)
     n = coords.shape[0]
     D = int(depth)

@@ -34,6 +34,11 @@ eq. prescale for the scaling, Alg. 1 and Sec. 2 for the sparsification):
 
 The recorded operations give L^{-1} = B_0 B_1 ... B_D (apply B_D first); the
 preconditioner is M = L^{-T} L^{-1} (Alg. 2 caption).
+
+Prescaling (optional; the experiments scale A symmetrically by its diagonal,
+Sec. 4): with d = diag(A)^{-1/2} the factorization runs on D A D, entry
+(i, j) = a_ij (d_i d_j) (exactly symmetric), and the preconditioner of A is
+D M~ D, M~ the one of D A D.
 """
 from __future__ import annotations
 
@@ -65,6 +70,7 @@ class Factor:
     nnz_L: int = 0
     flops: dict = field(default_factory=dict)      # l -> algorithmic flops of the step
     root_size: int = 0
+    dscale: np.ndarray | None = None               # prescaling: diag(A)^{-1/2}
 
 
 def _chol(B, step, c, what):
@@ -110,17 +116,35 @@ def _assemble_leaf_blocks(A, st):
     return B
 
 
-def factor(A, plan, eps, scheme=SECOND_ORDER, stop_after=None):
+def prescale(A):
+    """(D A D, d) with d = diag(A)^{-1/2}; NotSPD(-1, row) on a non-positive diagonal."""
+    A = sp.csr_matrix(A)
+    a = A.diagonal()
+    bad = np.flatnonzero(~(a > 0.0))
+    if bad.size:
+        raise NotSPD(-1, int(bad[0]), "prescale diagonal")
+    d = 1.0 / np.sqrt(a)
+    C = A.tocoo()
+    As = sp.csr_matrix((C.data * (d[C.row] * d[C.col]), (C.row, C.col)), shape=A.shape)
+    return As, d
+
+
+def factor(A, plan, eps, scheme=SECOND_ORDER, stop_after=None, prescaled=False):
     """Approximate factorization of the SPD matrix A (scipy sparse) on `plan`.
 
+    prescaled: factor D A D (module docstring) and apply D M~ D.
     stop_after=l returns (F, B, sizes) right after step l's sparsification:
     the block dict B[(i, j)] of step l's clusters and their current sizes
     (used to compare intermediate blocks)."""
     if scheme not in (FIRST_ORDER, SECOND_ORDER, SUPERFINE):
         raise ValueError(scheme)
     A = sp.csr_matrix(A)
+    dscale = None
+    if prescaled:
+        A, dscale = prescale(A)
     D = plan.depth
     F = Factor(plan.n, scheme, float(eps))
+    F.dscale = dscale
     st = plan.steps[D]
     pos = [np.asarray(v, dtype=np.int64) for v in st.verts]
     B = _assemble_leaf_blocks(A, st)
@@ -289,8 +313,11 @@ def apply_backward(F, z):
 
 
 def apply(F, b):
-    """y = M b with M = L^{-T} L^{-1}."""
-    return apply_backward(F, apply_forward(F, b))
+    """y = M b with M = L^{-T} L^{-1} (prescaled: D L^{-T} L^{-1} D)."""
+    if F.dscale is None:
+        return apply_backward(F, apply_forward(F, b))
+    d = F.dscale if np.ndim(b) == 1 else F.dscale[:, None]
+    return d * apply_backward(F, apply_forward(F, d * np.asarray(b, dtype=np.float64)))
 
 
 def dense_Linv(F):

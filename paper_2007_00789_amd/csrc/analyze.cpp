@@ -690,6 +690,46 @@ void build_leaf_map(Plan& P) {
   if (P.seg_off.empty()) P.seg_off = {0, n};
 }
 
+std::vector<double> graph_coords(int64_t n, const int64_t* rowptr, const int32_t* colind) {
+  std::vector<int32_t> queue;
+  queue.reserve((size_t)n);
+  auto bfs = [&](int64_t src, std::vector<int64_t>& dist) {
+    dist.assign((size_t)n, n);
+    queue.clear();
+    dist[src] = 0;
+    queue.push_back((int32_t)src);
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int32_t v = queue[h];
+      for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+        const int32_t u = colind[e];
+        if (u < 0 || u >= n) throw Error(SPAND_E_INVALID, "column index out of range");
+        if (dist[u] == n) {
+          dist[u] = dist[v] + 1;
+          queue.push_back(u);
+        }
+      }
+    }
+  };
+  auto farthest = [&](const auto& key) {   // largest key, lowest vertex on ties
+    int64_t best = 0;
+    for (int64_t v = 1; v < n; ++v)
+      if (key(v) > key(best)) best = v;
+    return best;
+  };
+  std::vector<int64_t> t, d0, d1, d2;
+  bfs(0, t);
+  bfs(farthest([&](int64_t v) { return t[v]; }), d0);
+  bfs(farthest([&](int64_t v) { return d0[v]; }), d1);
+  bfs(farthest([&](int64_t v) { return std::min(d0[v], d1[v]); }), d2);
+  std::vector<double> xyz((size_t)n * 3);
+  for (int64_t v = 0; v < n; ++v) {
+    xyz[v * 3] = (double)d0[v];
+    xyz[v * 3 + 1] = (double)d1[v];
+    xyz[v * 3 + 2] = (double)d2[v];
+  }
+  return xyz;
+}
+
 PanelLayout make_layout(const StepPlan& st, const std::vector<int32_t>& sizes) {
   PanelLayout L;
   L.n = sizes;

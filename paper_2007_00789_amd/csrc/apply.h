@@ -168,6 +168,13 @@ void launch_pcg_p(double* p, const double* z, double* rho, const double* rho_new
 // y = b - y
 void launch_residual(const double* b, double* y, int64_t n, int32_t nrhs, hipStream_t s);
 void launch_copy_vec(const double* src, double* dst, int64_t count, hipStream_t s);
+// prescale: d = diag(A)^{-1/2} (*bad: lowest row with a non-positive or missing
+// diagonal, INT32_MAX if none) and out = D^{-1/2} A D^{-1/2} in A's CSR order
+void launch_prescale(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,
+                     double* d, double* out, int32_t* bad, hipStream_t s);
+// y = d o x, column by column (x and y may alias)
+void launch_scale_vec(const double* x, const double* d, double* y, int64_t n, int32_t nrhs,
+                      hipStream_t s);
 // blocks per (segment, column) of launch_dot and the size of its partial buffer
 int32_t dot_blocks(int32_t nseg);
 

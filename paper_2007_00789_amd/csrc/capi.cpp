@@ -8,6 +8,7 @@
 #include <cstring>
 #include <memory>
 
+#include "apply.h"
 #include "runtime.h"
 
 struct spand_ctx_s { spand::Ctx c; };
@@ -18,6 +19,7 @@ struct spand_factor_s {
   spand::FactorObj f;
   spand::DevBuf vals;        // copy of A's values (SpMV inside PCG)
   double* d_vals = nullptr;  // = vals.p
+  spand::DevBuf dscale;      // prescale: D^{-1/2} (n)
   int device = 0;
 };
 
@@ -58,6 +60,7 @@ void check_opts(const spand_opts* o) {
   if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
       o->qr_xcd_local > 1 || o->qr_regs < 0 || o->qr_regs > 1 || o->qr_lds_cols < 0)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
+  if (o->prescale < 0 || o->prescale > 1) throw Error(SPAND_E_INVALID, "prescale must be 0 or 1");
 }
 
 // device copies of the pattern and of the leaf assembly map, made on first use
@@ -101,6 +104,7 @@ void spand_default_opts(spand_opts* o) {
   o->qr_xcd_local = 1;
   o->qr_regs = 0;
   o->qr_lds_cols = 0;
+  o->prescale = 0;
 }
 
 const char* spand_status_string(spand_status s) {
@@ -164,7 +168,7 @@ spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, co
   spand_status st = guarded(ctx, [&] {
     using spand::Error;
     check_opts(opts);
-    if (n <= 0 || !rowptr || !colind || !coords || dim < 1 || dim > 3)
+    if (n <= 0 || !rowptr || !colind || (coords ? (dim < 1 || dim > 3) : dim != 0))
       throw Error(SPAND_E_INVALID, "bad matrix or coordinates");
     if (rowptr[0] != 0 || rowptr[n] < 0) throw Error(SPAND_E_INVALID, "bad rowptr");
     if (n >= (int64_t(1) << 31)) throw Error(SPAND_E_LIMIT, "n must be < 2^31");
@@ -173,6 +177,12 @@ spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, co
     if (depth > 40) throw Error(SPAND_E_INVALID, "depth too large");
     spand::Plan& P = plan->p;
     P.n = n;
+    std::vector<double> gc;
+    if (!coords) {   // coordinate-free: landmark distances in the graph of A
+      gc = spand::graph_coords(n, rowptr, colind);
+      coords = gc.data();
+      dim = 3;
+    }
     spand::analyze_plan(P, rowptr, colind, coords, dim, depth, opts->skip);
     spand::build_leaf_map(P);
   });
@@ -195,7 +205,8 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
     std::vector<spand::Plan> parts((size_t)count);   // sized once: plans are not moved
     std::vector<int> depths((size_t)count);
     for (int i = 0; i < count; ++i) {
-      if (n[i] <= 0 || !rowptr[i] || !colind[i] || !coords[i] || dim[i] < 1 || dim[i] > 3)
+      if (n[i] <= 0 || !rowptr[i] || !colind[i] ||
+          (coords[i] ? (dim[i] < 1 || dim[i] > 3) : dim[i] != 0))
         throw Error(SPAND_E_INVALID, "bad matrix or coordinates of problem " + std::to_string(i));
       if (rowptr[i][0] != 0 || rowptr[i][n[i]] < 0)
         throw Error(SPAND_E_INVALID, "bad rowptr of problem " + std::to_string(i));
@@ -211,8 +222,15 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
     auto run = [&] {
       for (int i; (i = next.fetch_add(1)) < count;) {
         try {
-          spand::analyze_plan(parts[i], rowptr[i], colind[i], coords[i], dim[i], depths[i],
-                              opts->skip);
+          std::vector<double> gc;
+          const double* xy = coords[i];
+          int d = dim[i];
+          if (!xy) {
+            gc = spand::graph_coords(n[i], rowptr[i], colind[i]);
+            xy = gc.data();
+            d = 3;
+          }
+          spand::analyze_plan(parts[i], rowptr[i], colind[i], xy, d, depths[i], opts->skip);
         } catch (...) {
           errs[i] = std::current_exception();
         }
@@ -312,8 +330,29 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
     f->d_vals = static_cast<double*>(f->vals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
     SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
                              ctx->c.stream));
+    // prescale: the factorization reads D^{-1/2} A D^{-1/2}; PCG keeps A
+    const double* fvals = f->d_vals;
+    spand::DevBuf svals;
+    double* dsc = nullptr;
+    if (opts->prescale) {
+      const int64_t n = plan->p.n;
+      f->dscale.pool = ctx->c.pool;
+      svals.pool = ctx->c.pool;
+      dsc = static_cast<double*>(f->dscale.ensure(std::max<int64_t>(n, 1) * sizeof(double)));
+      double* sv = static_cast<double*>(svals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
+      int32_t* bad = static_cast<int32_t*>(ctx->c.ints.ensure(sizeof(int32_t)));
+      spand::launch_prescale(plan->p.d_rowptr, plan->p.d_colind, f->d_vals, n, dsc, sv, bad,
+                             ctx->c.stream);
+      int32_t hbad = 0;
+      SPAND_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->c.stream));
+      SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+      if (hbad != INT32_MAX)
+        throw spand::Error(SPAND_E_NOT_SPD, "prescale: diagonal entry of row " + std::to_string(hbad) +
+                                                " is not positive");
+      fvals = sv;
+    }
     try {
-      spand::run_factor(ctx->c, plan->p, f->d_vals, *opts, f->f);
+      spand::run_factor(ctx->c, plan->p, fvals, *opts, f->f);
     } catch (const spand::CoopPlacement&) {
       // a cooperative QR group was not on one XCD: redo with single-workgroup QRs
       SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
@@ -323,12 +362,16 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
       std::swap(g->vals.bytes, f->vals.bytes);
       std::swap(g->vals.pool, f->vals.pool);
       std::swap(g->d_vals, f->d_vals);
+      std::swap(g->dscale.p, f->dscale.p);
+      std::swap(g->dscale.bytes, f->dscale.bytes);
+      std::swap(g->dscale.pool, f->dscale.pool);
       f = std::move(g);
       spand_opts o2 = *opts;
       o2.qr_group = -1;
-      spand::run_factor(ctx->c, plan->p, f->d_vals, o2, f->f);
+      spand::run_factor(ctx->c, plan->p, fvals, o2, f->f);
       f->f.opts = *opts;
     }
+    f->f.dscale = dsc;
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();
     f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();

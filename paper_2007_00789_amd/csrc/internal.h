@@ -115,6 +115,14 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
 void merge_plans(Plan& M, std::vector<Plan>& parts, int skip);
 // destination of every CSR value in the leaf-step row panels
 void build_leaf_map(Plan& P);
+// Coordinates for a matrix given without any (coordinate-free analysis): for
+// every vertex, its hop distances in the graph of A to three landmarks picked
+// by farthest-point sampling: l0 the vertex farthest from vertex 0, l1 the
+// vertex farthest from l0, l2 the vertex whose distance to the nearer of l0
+// and l1 is largest (ties: lowest vertex id; unreachable vertices at distance
+// n).  Integer work, so the coordinate bisection on them is exact.  n x 3,
+// row-major.
+std::vector<double> graph_coords(int64_t n, const int64_t* rowptr, const int32_t* colind);
 
 // Layout of one step's row panels: cluster c holds rows n[c] x width[c] in
 // column-major order (ld = n[c]) at offset off[c]; the block (c, adj[e]) starts

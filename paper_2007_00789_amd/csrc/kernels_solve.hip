@@ -782,6 +782,42 @@ __global__ void k_copy_vec(const double* s, double* d, int64_t count) {
     d[i] = s[i];
 }
 
+// prescale: d_i = 1 / sqrt(a_ii) per row (the lowest row with a_ii <= 0, or
+// no diagonal entry, into *bad), then every value a_ij (d_i d_j), which keeps
+// the scaled values exactly symmetric
+__global__ void k_prescale_diag(const int64_t* rowptr, const int32_t* colind, const double* vals,
+                                int64_t n, double* d, int32_t* bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+      if (colind[e] == i) a += vals[e];
+    if (a > 0.0) d[i] = 1.0 / sqrt(a);
+    else {
+      d[i] = 0.0;
+      atomicMin(bad, (int32_t)i);
+    }
+  }
+}
+
+__global__ void k_prescale_vals(const int64_t* rowptr, const int32_t* colind, const double* vals,
+                                int64_t n, const double* d, double* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double di = d[i];
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) out[e] = vals[e] * (di * d[colind[e]]);
+  }
+}
+
+// y = d o x for nrhs columns of n (x and y may alias)
+__global__ void k_scale_vec(const double* x, const double* d, double* y, int64_t n, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = d[i % n] * x[i];
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v) { *p = v; }
+
 inline unsigned grid_for(int64_t n, int bs) {
   int64_t g = (n + bs - 1) / bs;
   if (g > 16384) g = 16384;
@@ -893,6 +929,19 @@ void launch_residual(const double* b, double* y, int64_t n, int32_t nrhs, hipStr
 }
 void launch_copy_vec(const double* src, double* dst, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_vec, dim3(grid_for(count, 256)), dim3(256), 0, s, src, dst, count);
+}
+void launch_prescale(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,
+                     double* d, double* out, int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, bad, INT32_MAX);
+  hipLaunchKernelGGL(k_prescale_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colind, vals,
+                     n, d, bad);
+  hipLaunchKernelGGL(k_prescale_vals, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colind, vals,
+                     n, d, out);
+}
+void launch_scale_vec(const double* x, const double* d, double* y, int64_t n, int32_t nrhs,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_vec, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, s, x, d, y, n,
+                     n * nrhs);
 }
 
 }  // namespace spand

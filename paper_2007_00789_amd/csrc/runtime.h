@@ -220,6 +220,8 @@ struct FactorObj {
   std::vector<int32_t> dbg_ncur;
   // apply program (built step by step during run_factor)
   struct ApplyProg* prog = nullptr;
+  // prescale: D^{-1/2} (n, device; owned by the caller of run_factor), or nullptr
+  const double* dscale = nullptr;
   ~FactorObj();
 };
 

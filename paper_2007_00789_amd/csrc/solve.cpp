@@ -418,7 +418,8 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
   double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
   double* U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * nrhs * sizeof(double)));
   double* Ys = static_cast<double*>(pg.Y.ensure(std::max<int64_t>(pg.yscratch, 1) * nrhs * sizeof(double)));
-  if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
+  if (F.dscale) SPAND_PROF(C, "k_scale_vec", launch_scale_vec(x, F.dscale, y, n, nrhs, s));
+  else if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
     if (as.split) {
       SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.f1, as.n_f1, as.mv, y, n, nrhs, nullptr, Ys, s));
@@ -461,6 +462,7 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
       SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
     }
   }
+  if (F.dscale) SPAND_PROF(C, "k_scale_vec", launch_scale_vec(y, F.dscale, y, n, nrhs, s));
 }
 
 void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const double* b, double* x,

@@ -34,7 +34,8 @@ class Opts(C.Structure):
     _fields_ = [("depth", C.c_int32), ("skip", C.c_int32), ("eps", C.c_double),
                 ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32),
                 ("qr_group", C.c_int32), ("qr_list_cap", C.c_int32),
-                ("qr_xcd_local", C.c_int32), ("qr_regs", C.c_int32), ("qr_lds_cols", C.c_int32)]
+                ("qr_xcd_local", C.c_int32), ("qr_regs", C.c_int32), ("qr_lds_cols", C.c_int32),
+                ("prescale", C.c_int32)]
 
 
 class FactorStats(C.Structure):
@@ -127,7 +128,7 @@ def _np(a, dtype):
 
 
 def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
-              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_regs=0, qr_lds_cols=0) -> Opts:
+              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_regs=0, qr_lds_cols=0, prescale=0) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
     o.depth = int(depth)
@@ -141,6 +142,7 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     o.qr_xcd_local = int(qr_xcd_local)
     o.qr_regs = int(qr_regs)
     o.qr_lds_cols = int(qr_lds_cols)
+    o.prescale = int(prescale)
     return o
 
 
@@ -215,8 +217,11 @@ def analyze(n, rowptr, colind, coords, opts: Opts, ctx: Context | None = None) -
     lib = load()
     rp, rp_p = _np(rowptr, np.int64)
     ci, ci_p = _np(colind, np.int32)
-    xy, xy_p = _np(coords, np.float64)
-    dim = 1 if xy.ndim == 1 else xy.shape[1]
+    if coords is None:   # coordinate-free analysis
+        xy, xy_p, dim = None, None, 0
+    else:
+        xy, xy_p = _np(coords, np.float64)
+        dim = 1 if xy.ndim == 1 else xy.shape[1]
     h = C.c_void_p()
     st = lib.spand_analyze(ctx.h if ctx else None, int(n), rp_p, ci_p, xy_p, dim, C.byref(opts),
                            C.byref(h))
@@ -240,10 +245,14 @@ def analyze_batch(problems, opts: Opts, ctx: Context | None = None, depths=None)
     for i, (n, rowptr, colind, coords) in enumerate(problems):
         rp, rp_p = _np(rowptr, np.int64)
         ci, ci_p = _np(colind, np.int32)
-        xy, xy_p = _np(coords, np.float64)
+        if coords is None:   # coordinate-free analysis of this problem
+            xy, xy_p = None, None
+            dims[i] = 0
+        else:
+            xy, xy_p = _np(coords, np.float64)
+            dims[i] = 1 if xy.ndim == 1 else xy.shape[1]
         keep += [rp, ci, xy]
         rp_arr[i], ci_arr[i], xy_arr[i] = rp_p, ci_p, xy_p
-        dims[i] = 1 if xy.ndim == 1 else xy.shape[1]
     dp = None
     if depths is not None:
         dpa = np.ascontiguousarray(depths, dtype=np.int32)

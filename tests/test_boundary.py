@@ -40,12 +40,34 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("name,make,depth,skip", CASES, ids=[c[0] for c in CASES])
+def _two_grids():
+    a, b = laplacian_2d(20, 9), laplacian_3d(7)
+    rowptr = np.concatenate([a.rowptr, a.rowptr[-1] + b.rowptr[1:]])
+    colind = np.concatenate([a.colind, b.colind + a.n])
+
+    class P:
+        pass
+    p = P()
+    p.n, p.rowptr, p.colind, p.nnz, p.coords = a.n + b.n, rowptr, colind, colind.size, None
+    return p
+
+
+# coordinate-free analysis (coords withheld): landmark hop distances
+FREE = [
+    ("free_lap2d_ragged", lambda: laplacian_2d(37, 23), 7, 2),
+    ("free_lap3d_16", lambda: laplacian_3d(16), 6, 4),
+    ("free_fv3d_12", lambda: fv_diffusion_3d(12, 3.0, 1002), 5, 1),
+    ("free_disconnected", _two_grids, 5, 1),
+]
+
+
+@pytest.mark.parametrize("name,make,depth,skip", CASES + FREE, ids=[c[0] for c in CASES + FREE])
 def test_analyze_matches_oracle(lib, name, make, depth, skip):
     from paper_2007_00789_amd import spand
     p = make()
-    ref = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
-    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=depth, skip=skip))
+    coords = None if name.startswith("free_") else p.coords
+    ref = nd.analyze(p.rowptr, p.colind, coords, depth, skip)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, coords, spand.make_opts(depth=depth, skip=skip))
     assert plan.depth == depth and plan.n == p.n and plan.nnz == p.nnz
     lvl, path, perm = plan.vertices()
     assert np.array_equal(lvl, ref.lvl)

@@ -318,3 +318,76 @@ def test_qr_panel_columns_agree_with_oracle(ctx, name, make, depth, skip, eps, q
     ctx.apply(fac, 2, dx, dy)
     y = dy.cpu().numpy().reshape(p.n, 2, order="F")
     assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+
+
+# --- symmetric diagonal prescaling and coordinate-free analysis --------------
+
+def _row_scaled_vals(p, seed):
+    """values of S A S (S = diag(10^U[-3, 3])) in A's CSR order: a_ij (s_i s_j)"""
+    s = 10.0 ** np.random.default_rng(seed).uniform(-3, 3, p.n)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    return p.vals * (s[rows] * s[p.colind])
+
+
+def _csr(p, vals):
+    import scipy.sparse as sp_
+    return sp_.csr_matrix((vals, p.colind, p.rowptr), shape=(p.n, p.n))
+
+
+@gpu
+@pytest.mark.parametrize("coords_given", [True, False], ids=["geometric", "coordinate_free"])
+@pytest.mark.parametrize("prescale", [1, 0])
+def test_prescale_and_coordinate_free_match_oracle(ctx, prescale, coords_given):
+    from paper_2007_00789_amd import spand
+    p = fv_diffusion_3d(10, 2.0, 1003)
+    depth, skip, eps, nrhs, tol = 5, 1, 1e-2, 2, 1e-10
+    print(f"prescale {prescale} coords {coords_given}", flush=True)
+    vals = _row_scaled_vals(p, 77) if prescale else p.vals
+    A = _csr(p, vals)
+    coords = p.coords if coords_given else None
+    plan_o = nd.analyze(p.rowptr, p.colind, coords, depth, skip)
+    F = ospand.factor(A, plan_o, eps, "SO", prescaled=bool(prescale))
+    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme="SO", prescale=prescale)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, coords, opts, ctx)
+    fac = ctx.factor(plan, _dev(vals), opts)
+    ref = _oracle_ranks(F)
+    for l in range(depth, 0, -1):
+        st = plan_o.steps[l]
+        if not st.sparsified:
+            continue
+        got = fac.ranks(l, st.n_clusters)
+        for p_, (a, k, r, r2) in ref[l].items():
+            assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), \
+                (l, p_)
+    b = rhs(p.n, nrhs, 2100)
+    X, its, _ = opcg.pcg_multi(lambda v: A @ v, lambda v: ospand.apply(F, v), b, tol)
+    db = _dev(b)
+    dx = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, nrhs, db, dx, tol, 1000)
+    x = dx.cpu().numpy().reshape(p.n, nrhs, order="F")
+    for j in range(nrhs):
+        assert abs(int(it[j]) - its[j]) <= 1
+        assert rr[j] < 10 * tol
+        assert np.linalg.norm(x[:, j] - X[:, j]) <= 1e-10 * np.linalg.norm(X[:, j])
+    # the apply alone: y = D M~ D b
+    dy = torch.zeros_like(db)
+    ctx.apply(fac, nrhs, db, dy)
+    Y = ospand.apply(F, b)
+    y = dy.cpu().numpy().reshape(p.n, nrhs, order="F")
+    assert np.linalg.norm(y - Y) <= 1e-10 * np.linalg.norm(Y)
+    fac.close()
+
+
+@gpu
+def test_prescale_rejects_a_nonpositive_diagonal(ctx):
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(16)
+    vals = p.vals.copy()
+    v = 40
+    diag = p.rowptr[v] + np.flatnonzero(p.colind[p.rowptr[v]:p.rowptr[v + 1]] == v)[0]
+    vals[diag] = 0.0
+    opts = spand.make_opts(depth=3, skip=0, eps=1e-2, prescale=1)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    with pytest.raises(spand.SpandError) as e:
+        ctx.factor(plan, _dev(vals), opts)
+    assert e.value.status == -3 and "row 40" in e.value.message

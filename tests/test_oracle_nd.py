@@ -95,3 +95,50 @@ def test_colouring_is_greedy_smallest_free():
                 c += 1
             assert st.colour[p_] == c
         assert st.order == sorted(range(nI, st.n_clusters), key=lambda x: (st.colour[x], x))
+
+
+# --- coordinate-free reading: landmark hop distances -------------------------
+
+@pytest.mark.parametrize("W,H", [(7, 5), (8, 8), (13, 4), (1, 9)])
+def test_graph_coords_closed_form_2d(W, H):
+    # On a W x H five-point grid (vertex id = y W + x) hop distance is the
+    # Manhattan distance: l0 is the far corner (W-1, H-1), l1 the corner
+    # (0, 0), and l2 the lowest-id vertex on the anti-diagonal x + y =
+    # floor((W + H - 2) / 2), i.e. the one with the smallest y.
+    p = laplacian_2d(W, H)
+    xy = nd.graph_coords(p.rowptr, p.colind)
+    x, y = p.coords[:, 0], p.coords[:, 1]
+    s = (W + H - 2) // 2
+    ys = max(0, s - (W - 1))
+    xs = s - ys
+    assert np.array_equal(xy[:, 0], (W - 1 - x) + (H - 1 - y))
+    assert np.array_equal(xy[:, 1], x + y)
+    assert np.array_equal(xy[:, 2], np.abs(x - xs) + np.abs(y - ys))
+
+
+def test_graph_coords_closed_form_3d():
+    m = 6
+    p = laplacian_3d(m)
+    xyz = nd.graph_coords(p.rowptr, p.colind)
+    x, y, z = p.coords[:, 0], p.coords[:, 1], p.coords[:, 2]
+    s = 3 * (m - 1) // 2               # lowest id on x + y + z = s: z = 0, then y small
+    zs = 0
+    ys = max(0, s - (m - 1))
+    xs = s - ys
+    assert np.array_equal(xyz[:, 0], 3 * (m - 1) - (x + y + z))
+    assert np.array_equal(xyz[:, 1], x + y + z)
+    assert np.array_equal(xyz[:, 2], np.abs(x - xs) + np.abs(y - ys) + np.abs(z - zs))
+
+
+def test_graph_coords_unreachable_and_plan():
+    # two disjoint grids: vertices of the other component sit at distance n
+    a, b = laplacian_2d(6, 4), laplacian_2d(5, 5)
+    n = a.n + b.n
+    rowptr = np.concatenate([a.rowptr, a.rowptr[-1] + b.rowptr[1:]])
+    colind = np.concatenate([a.colind, b.colind + a.n])
+    xy = nd.graph_coords(rowptr, colind)
+    # l0: farthest from vertex 0 is unreachable, lowest id = first vertex of b
+    assert np.all(xy[:a.n, 0] == n) and xy[a.n, 0] == 0
+    plan = nd.analyze(rowptr, colind, None, 3, 1)
+    nd.check_plan(plan, rowptr, colind)
+    assert np.array_equal(plan.perm[np.argsort(plan.perm)], np.arange(n))

@@ -288,3 +288,53 @@ def test_nnz_counts_match_the_stored_factor():
                 cnt += E.shape[0] * (E.shape[1] - f0)
     assert cnt == F.nnz_L
     assert spand.mu(F, A) == F.nnz_L / p.nnz
+
+
+# --- symmetric diagonal prescaling -----------------------------------------
+
+def _row_scaled(p, seed):
+    """S A S with S = diag(10^U[-3, 3]): same spectrum structure, wild diagonal."""
+    import scipy.sparse as sp_
+    s = 10.0 ** np.random.default_rng(seed).uniform(-3, 3, p.n)
+    C = p.scipy().tocoo()
+    return sp_.csr_matrix((C.data * (s[C.row] * s[C.col]), (C.row, C.col)), shape=C.shape)
+
+
+def test_prescale_unit_diagonal_and_errors():
+    p = fv_diffusion_3d(6, 2.0, 11)
+    As, d = spand.prescale(_row_scaled(p, 3))
+    assert np.allclose(As.diagonal(), 1.0, rtol=4e-16 * 4, atol=0)
+    assert abs(As - As.T).max() == 0.0          # a_ij (d_i d_j): exactly symmetric
+    A = p.scipy().tolil()
+    A[5, 5] = 0.0
+    with pytest.raises(spand.NotSPD) as e:
+        spand.prescale(A.tocsr())
+    assert e.value.cluster == 5
+
+
+def test_prescaled_factor_is_exact_at_eps0():
+    # eps = 0 keeps every reflector, so D M~ D = (D^{-1} (D A D)^{-1} D^{-1})... = A^{-1}
+    p = fv_diffusion_3d(6, 2.0, 12)
+    A = _row_scaled(p, 4)
+    plan = nd.analyze(p.rowptr, p.colind, p.coords, 3, 0)
+    F = spand.factor(A, plan, 0.0, "SO", prescaled=True)
+    X = np.random.default_rng(5).standard_normal((p.n, 2))
+    Y = spand.apply(F, A @ X)
+    assert np.linalg.norm(Y - X) <= 1e-9 * np.linalg.norm(X)
+
+
+def test_prescaling_removes_a_diagonal_scaling():
+    # D' of S A S is S^{-1} D, so the prescaled operator D' S A S D' is D A D up
+    # to rounding: the same ranks and iteration counts as for A itself
+    p = fv_diffusion_3d(8, 2.0, 13)
+    plan = nd.analyze(p.rowptr, p.colind, p.coords, 4, 0)
+    A, As = p.scipy(), _row_scaled(p, 6)
+    Fa = spand.factor(A, plan, 1e-2, "SO", prescaled=True)
+    Fs = spand.factor(As, plan, 1e-2, "SO", prescaled=True)
+    Fn = spand.factor(As, plan, 1e-2, "SO")
+    b = np.ones(p.n)
+    _, it_a, _ = pcg.pcg(lambda v: A @ v, lambda v: spand.apply(Fa, v), b, 1e-10)
+    _, it_s, _ = pcg.pcg(lambda v: As @ v, lambda v: spand.apply(Fs, v), b, 1e-10)
+    _, it_n, _ = pcg.pcg(lambda v: As @ v, lambda v: spand.apply(Fn, v), b, 1e-10, maxit=400)
+    assert abs(it_a - it_s) <= 1
+    assert it_n >= it_s
