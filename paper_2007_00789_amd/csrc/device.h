@@ -111,6 +111,7 @@ struct WyDesc {
   const double* V;
   const double* tau;
   double* T;
+  double* X;         // n > kWyLdsN: n x n scratch for the blocked inverse
   int32_t a, n;
 };
 constexpr int kWyThreads = 1024;

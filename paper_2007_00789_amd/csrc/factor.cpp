@@ -1203,7 +1203,14 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   if (F.stopped_at < 0) {
     // triangular factors of the compact WY forms of every sparsified interface:
     // S = V^T V (lower triangle) by one batched GEMM, then the column recurrence
+    // (more than kWyLdsN reflectors: the tiled inverse of T^-1, with an n x n
+    // scratch each)
     C.upload.next(s);
+    int64_t xdoubles = 0;
+    for (const StepRec& R : F.steps)
+      for (size_t p = 0; p < R.V.size(); ++p)
+        if (R.V[p] && R.r2[p] > kWyLdsN) xdoubles += (int64_t)R.r2[p] * R.r2[p];
+    double* xs = xdoubles ? static_cast<double*>(C.temp.ensure(xdoubles * sizeof(double))) : nullptr;
     std::vector<GemmDesc> gd;
     std::vector<GemmTerm> gt;
     std::vector<TileRef> tiles;
@@ -1227,7 +1234,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         g.term1 = (int64_t)gt.size();
         add_gemm_tiles(tiles, (int32_t)gd.size(), nref, nref, true);
         gd.push_back(g);
-        wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], a, nref});
+        double* X = nullptr;
+        if (nref > kWyLdsN) {
+          X = xs;
+          xs += (int64_t)nref * nref;
+        }
+        wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], X, a, nref});
       }
     }
     if (!wy.empty()) {

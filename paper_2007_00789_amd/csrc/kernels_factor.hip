@@ -235,6 +235,54 @@ __device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
 }
 
+// Off-diagonal tiles of X = L^{-1} for a lower triangular L (in A, ld n) whose
+// diagonal tiles of X are already in place, column block by column block:
+// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  The strictly upper part of X is
+// zeroed.  LDS: two 64x65 tiles.
+__device__ void lower_inv_offdiag(const double* A, double* X, int n, double* lds) {
+  double* T1 = lds + kNb * kTl;
+  double* T2 = lds + 2 * kNb * kTl;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int nb = (n + kNb - 1) / kNb;
+  double acc[4][4];
+  // off-diagonal tiles of X = L^{-1}, column block by column block
+  for (int jb = 0; jb < nb; ++jb) {
+    const int j0 = jb * kNb, jw = min(kNb, n - j0);
+    for (int ib = jb + 1; ib < nb; ++ib) {
+      const int i0 = ib * kNb, iw = min(kNb, n - i0);
+      acc_zero(acc);
+      for (int kb = jb; kb < ib; ++kb) {
+        const int k0 = kb * kNb, kw = min(kNb, n - k0);
+        tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);   // L_IK
+        tile_load(T2, X + k0 + (int64_t)j0 * n, n, kw, jw);   // X_KJ
+        __syncthreads();
+        tile_mma(acc, T1, T2, kw, false);
+        __syncthreads();
+      }
+      // T1 <- S = sum, then X_IJ = -X_II S
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) T1[tx + 16 * r + (ty + 16 * c) * kTl] = acc[r][c];
+      tile_load(T2, X + i0 + (int64_t)i0 * n, n, iw, iw);
+      __syncthreads();
+      acc_zero(acc);
+      tile_mma(acc, T2, T1, iw, false);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = tx + 16 * r, j = ty + 16 * c;
+          if (i < iw && j < jw) {
+            X[i0 + i + (int64_t)(j0 + j) * n] = -acc[r][c];
+            X[j0 + j + (int64_t)(i0 + i) * n] = 0.0;   // strictly upper part
+          }
+        }
+      __syncthreads();
+    }
+  }
+}
+
 // Cholesky + inverse of a block larger than one tile: right-looking blocked
 // Cholesky in place in A (the dead diagonal block of the panel, ld n), the
 // inverses of the diagonal tiles into X's diagonal tiles, then the off-diagonal
@@ -301,42 +349,7 @@ __device__ int chol_inv_blocked(double* A, double* X, int n, double* lds) {
       }
     }
   }
-  // off-diagonal tiles of X = L^{-1}, column block by column block
-  for (int jb = 0; jb < nb; ++jb) {
-    const int j0 = jb * kNb, jw = min(kNb, n - j0);
-    for (int ib = jb + 1; ib < nb; ++ib) {
-      const int i0 = ib * kNb, iw = min(kNb, n - i0);
-      acc_zero(acc);
-      for (int kb = jb; kb < ib; ++kb) {
-        const int k0 = kb * kNb, kw = min(kNb, n - k0);
-        tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);   // L_IK
-        tile_load(T2, X + k0 + (int64_t)j0 * n, n, kw, jw);   // X_KJ
-        __syncthreads();
-        tile_mma(acc, T1, T2, kw, false);
-        __syncthreads();
-      }
-      // T1 <- S = sum, then X_IJ = -X_II S
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) T1[tx + 16 * r + (ty + 16 * c) * kTl] = acc[r][c];
-      tile_load(T2, X + i0 + (int64_t)i0 * n, n, iw, iw);
-      __syncthreads();
-      acc_zero(acc);
-      tile_mma(acc, T2, T1, iw, false);
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int i = tx + 16 * r, j = ty + 16 * c;
-          if (i < iw && j < jw) {
-            X[i0 + i + (int64_t)(j0 + j) * n] = -acc[r][c];
-            X[j0 + j + (int64_t)(i0 + i) * n] = 0.0;   // strictly upper part
-          }
-        }
-      __syncthreads();
-    }
-  }
+  lower_inv_offdiag(A, X, n, lds);
   return 0;
 }
 
@@ -725,6 +738,13 @@ __global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
   const WyDesc d = descs[blockIdx.x];
   const int n = d.n;
   if (n <= 0 || (n <= kWyLdsN) != kInLds) return;
+  // n > kWyLdsN: this recurrence only when some tau is 0 (T^-1 does not exist);
+  // otherwise k_wy_t_inv inverts T^-1 by tiles
+  if (!kInLds) {
+    bool zero = false;
+    for (int j = threadIdx.x; j < n; j += kWyThreads) zero = zero || d.tau[j] == 0.0;
+    if (!__syncthreads_or(zero)) return;
+  }
   double* A = kInLds ? lds : d.T;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int grp = lane >> 3, r8 = lane & 7;
@@ -752,6 +772,47 @@ __global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
   for (int64_t idx = tid; idx < (int64_t)n * n; idx += kWyThreads) {
     const int i = (int)(idx % n), c = (int)(idx / n);
     d.T[idx] = i <= c ? A[idx] : 0.0;
+  }
+}
+
+// T of a compact WY form with more than kWyLdsN reflectors, all tau nonzero:
+// T^{-1} = diag(1/tau) + (strict upper part of V^T V) is upper triangular, so
+// T = X^T with X the inverse of the lower triangular L = diag(1/tau) + (strict
+// lower part of V^T V), by 64x64 tiles (trinv on the diagonal tiles, block
+// forward substitution below).  On entry T holds V^T V in its lower triangle;
+// L is formed in place there, X goes to the scratch d.X.  LDS: four 64x65
+// tiles.
+__global__ __launch_bounds__(kPotrfThreads) void k_wy_t_inv(const WyDesc* descs) {
+  extern __shared__ double sm[];
+  const WyDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  if (n <= kWyLdsN) return;
+  bool zero = false;
+  for (int j = threadIdx.x; j < n; j += kPotrfThreads) zero = zero || d.tau[j] == 0.0;
+  if (__syncthreads_or(zero)) return;   // k_wy_t<false> takes it
+  for (int j = threadIdx.x; j < n; j += kPotrfThreads) d.T[j + (int64_t)j * n] = 1.0 / d.tau[j];
+  __syncthreads();
+  double* T0 = sm;
+  double* T1 = sm + kNb * kTl;
+  double* tmp = sm + 3 * kNb * kTl;
+  const int nb = (n + kNb - 1) / kNb;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * kNb, kw = min(kNb, n - k0);
+    tile_load(T1, d.T + k0 + (int64_t)k0 * n, n, kw, kw);
+    for (int idx = threadIdx.x; idx < kNb * kTl; idx += kPotrfThreads) T0[idx] = 0.0;
+    __syncthreads();
+    trinv<kPotrfThreads>(T1, kTl, T0, kTl, kw, tmp);
+    for (int idx = threadIdx.x; idx < kw * kw; idx += kPotrfThreads) {
+      const int i = idx % kw, j = idx / kw;
+      d.X[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T0[i + j * kTl] : 0.0;
+    }
+    __syncthreads();
+  }
+  lower_inv_offdiag(d.T, d.X, n, sm);
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += kPotrfThreads) {
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    d.T[idx] = i <= c ? d.X[c + (int64_t)i * n] : 0.0;
   }
 }
 
@@ -836,6 +897,8 @@ void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_wy_t<true>, dim3(count), dim3(kWyThreads),
                      (size_t)kWyLdsN * kWyLdsN * sizeof(double), s, d);
   hipLaunchKernelGGL(k_wy_t<false>, dim3(count), dim3(kWyThreads), 0, s, d);
+  hipLaunchKernelGGL(k_wy_t_inv, dim3(count), dim3(kPotrfThreads),
+                     (size_t)4 * kNb * kTl * sizeof(double), s, d);
 }
 
 void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
