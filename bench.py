@@ -87,9 +87,9 @@ MEASURED_TRAFFIC = {
     "k_cpqr_coop": {
         "sources": {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
-            "paper_2007_00789_amd/csrc/factor.cpp": "81373d0608fda3f25d3a3d4498eb1153f16aacb3d1a1f9e81eb3ba767aefe8ac",
+            "paper_2007_00789_amd/csrc/factor.cpp": "4b79be5b712e1c81726860743618e8f262039b5f86f487ad06cd80639b9c156b",
         },
-        "fetch_kib": 7576.6, "write_kib": 41962.4,
+        "fetch_kib": 8216.4, "write_kib": 45941.9,
         "fetch_scale": 1.9998, "write_scale": 1.0000,
     },
 }

@@ -35,10 +35,13 @@ Reading (the paper is silent on these points):
   interior eliminated at this or an earlier step (symbolic fill); adjacency is
   lifted to parents at every merge.  Sparsification keeps the structure.
 * Interfaces of a sparsified step are processed by (colour, canonical index),
-  with colours from a greedy colouring of the interface adjacency graph in
-  canonical order (smallest colour not used by an already coloured neighbour).
-  Interfaces of one colour are never adjacent, so their relative order cannot
-  change the result.  (Alg. 2 writes a FORALL over interfaces, which reads as
+  with colours from a DSATUR colouring of the interface adjacency graph:
+  repeatedly the uncoloured interface with the most distinct colours among its
+  coloured neighbours is taken (ties: the one holding more vertices of A, then
+  the lower canonical index) and given the smallest colour none of its
+  coloured neighbours has.  Interfaces of one colour are never adjacent, so
+  their relative order cannot change the result; fewer colours mean fewer
+  sequential sparsification rounds.  (Alg. 2 writes a FORALL over interfaces, which reads as
   order independent; it is not, for adjacent interfaces.)
 * Sparsified steps (scaling + sparsification, Alg. 2): 1 <= l <= depth - skip;
   the paper skips the first four levels (Sec. 4), so skip defaults to 4.
@@ -210,14 +213,30 @@ def _fill_pairs(adj, interiors, nc):
     return np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
 
 
-def greedy_colour(adj, interfaces):
+def dsatur_colour(adj, interfaces, weight):
+    """DSATUR colouring of the interface graph (see the module docstring).
+
+    adj[p]: neighbours of p (interfaces among them); weight[p]: vertex count.
+    Returns {p: colour}."""
+    import heapq
+    itf = set(interfaces)
     colour = {}
-    for p in interfaces:
-        used = {colour[q] for q in adj[p] if q in colour}
+    seen = {p: set() for p in interfaces}
+    heap = [(0, -int(weight[p]), p) for p in interfaces]
+    heapq.heapify(heap)
+    while heap:
+        negsat, negw, p = heapq.heappop(heap)
+        if p in colour or -negsat != len(seen[p]):
+            continue                      # stale entry
         c = 0
-        while c in used:
+        while c in seen[p]:
             c += 1
         colour[p] = c
+        for q in adj[p]:
+            q = int(q)
+            if q in itf and q not in colour and c not in seen[q]:
+                seen[q].add(c)
+                heapq.heappush(heap, (-len(seen[q]), -int(weight[q]), q))
     return colour
 
 
@@ -275,7 +294,8 @@ def analyze(rowptr, colind, coords, depth, skip=4):
         alive = lvl <= l
         int_keys = np.unique(pre[lvl == l])
         itf_sel = lvl < l
-        itf_codes = np.unique(lvl[itf_sel] * (np.int64(1) << np.int64(D + 1)) + pre[itf_sel])
+        itf_codes, itf_nv = np.unique(lvl[itf_sel] * (np.int64(1) << np.int64(D + 1)) + pre[itf_sel],
+                                      return_counts=True)
         keys = [(0, l, int(p)) for p in int_keys]
         keys += [(1, int(c >> (D + 1)), int(c & ((1 << (D + 1)) - 1))) for c in itf_codes]
         nI = len(int_keys)
@@ -314,7 +334,8 @@ def analyze(rowptr, colind, coords, depth, skip=4):
             adj, pairs = _pairs_to_adj(np.concatenate([pairs, fill]), nc)
         interfaces = list(range(nI, nc))
         itf_adj = [adj[p][adj[p] >= nI] for p in range(nc)]
-        col = greedy_colour(itf_adj, interfaces)
+        weight = {nI + i: int(c) for i, c in enumerate(itf_nv)}
+        col = dsatur_colour(itf_adj, interfaces, weight)
         colour = np.full(nc, -1, dtype=np.int64)
         for p, c in col.items():
             colour[p] = c

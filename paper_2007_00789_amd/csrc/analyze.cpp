@@ -18,9 +18,12 @@
 //  * clusters are adjacent if A couples them or if they border a common
 //    interior eliminated at this or an earlier step; adjacency is inherited by
 //    parents;
-//  * interfaces are coloured greedily in canonical order and sparsified by
-//    (colour, index) on the levels 1 <= l <= depth - skip (Alg. 2, Sec. 4).
+//  * interfaces are coloured by DSATUR (saturation, then vertex count, then
+//    index) and sparsified by (colour, index) on the levels
+//    1 <= l <= depth - skip (Alg. 2, Sec. 4).
 #include <algorithm>
+#include <tuple>
+#include <queue>
 #include <atomic>
 #include <cmath>
 #include <memory>
@@ -375,6 +378,7 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
   P.steps.assign(D + 1, StepPlan());
   const int64_t SH = int64_t(1) << (D + 1);
   std::vector<int32_t> mark;
+  std::vector<int64_t> nv, nv_prev;   // vertices of A in each cluster (this step, the finer one)
   for (int l = D; l >= 0; --l) {
     StepPlan& st = P.steps[l];
     st.l = l;
@@ -510,21 +514,49 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
       if (grown) std::sort(st.adj.begin() + b0, st.adj.end());
       st.adj_ptr[a + 1] = (int64_t)st.adj.size();
     }
-    // greedy colouring of the interface graph in canonical order
+    // vertices of A per cluster: at the leaf step counted, above it summed
+    // over the children
+    nv.assign(nc, 0);
+    if (l == D) {
+      for (int c = 0; c < nc; ++c) nv[c] = st.vert_ptr[c + 1] - st.vert_ptr[c];
+    } else {
+      for (int c = 0; c < nc; ++c)
+        for (int64_t a = st.child_ptr[c]; a < st.child_ptr[c + 1]; ++a) nv[c] += nv_prev[st.child[a]];
+    }
+    // DSATUR colouring of the interface graph: the uncoloured interface with
+    // the most distinct colours among its coloured neighbours goes next (ties:
+    // more vertices of A, then the lower index) and takes the smallest colour
+    // none of them has
     st.colour.assign(nc, -1);
     st.ncolours = 0;
-    std::vector<char> used;
-    for (int p = st.nI; p < nc; ++p) {
-      used.assign(st.ncolours + 2, 0);
-      for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
-        const int q = st.adj[e];
-        if (q >= st.nI && q < p) used[st.colour[q]] = 1;
+    {
+      std::vector<std::vector<int32_t>> seen(nc);   // distinct neighbour colours, ascending
+      using Key = std::tuple<int, int64_t, int>;    // (-saturation, -vertices, index)
+      std::priority_queue<Key, std::vector<Key>, std::greater<Key>> pq;
+      for (int p = st.nI; p < nc; ++p) pq.emplace(0, -nv[p], p);
+      while (!pq.empty()) {
+        const auto [ns, nw, p] = pq.top();
+        pq.pop();
+        if (st.colour[p] >= 0 || -ns != (int)seen[p].size()) continue;   // stale entry
+        int c = 0;
+        for (const int32_t x : seen[p]) {
+          if (x == c) ++c;
+          else if (x > c) break;
+        }
+        st.colour[p] = c;
+        st.ncolours = std::max(st.ncolours, c + 1);
+        for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
+          const int q = st.adj[e];
+          if (q < st.nI || q == p || st.colour[q] >= 0) continue;
+          auto& sq = seen[q];
+          const auto it = std::lower_bound(sq.begin(), sq.end(), c);
+          if (it != sq.end() && *it == c) continue;
+          sq.insert(it, c);
+          pq.emplace(-(int)sq.size(), -nv[q], q);
+        }
       }
-      int c = 0;
-      while (used[c]) ++c;
-      st.colour[p] = c;
-      st.ncolours = std::max(st.ncolours, c + 1);
     }
+    nv_prev.swap(nv);
     st.order.clear();
     for (int p = st.nI; p < nc; ++p) st.order.push_back(p);
     std::stable_sort(st.order.begin(), st.order.end(),

@@ -1001,7 +1001,6 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         for (int kind = 0; kind < 2; ++kind) {
           std::vector<CoopDesc>& list = kind == 0 ? qd_reg : qd;
           if (list.empty()) continue;
-          if (kind == 1 && o.qr_group == 0) widen_groups(list);
           size_t lds = 0;
           int rows = 0, cap_blocks = 0;
           bool panel = false;   // some workgroup keeps columns in the row panel
@@ -1045,11 +1044,47 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
               done[i] = 1;
               ++ndone;
             }
+            // compute units this launch leaves idle: widen its groups and
+            // place them again (the pivot sequence does not depend on G)
+            std::vector<CoopDesc> mq;
+            for (int i : members) mq.push_back(list[i]);
+            if (kind == 1 && o.qr_group == 0 && slots >= kCoopMaxGroup) {
+              std::vector<CoopDesc> wq = mq;
+              widen_groups(wq);
+              bool changed = false;
+              for (size_t b = 0; b < wq.size(); ++b) changed = changed || wq[b].G != mq[b].G;
+              if (changed) {
+                std::vector<int> om(wq.size());
+                std::iota(om.begin(), om.end(), 0);
+                std::stable_sort(om.begin(), om.end(), [&](int x, int y) { return wq[x].G > wq[y].G; });
+                int f2[kCoopXcds] = {};
+                std::vector<int> ax(wq.size()), as(wq.size());
+                bool ok = true;
+                for (int b : om) {
+                  int best = -1;
+                  for (int x = 0; x < kCoopXcds; ++x)
+                    if (slots - f2[x] >= wq[b].G && (best < 0 || f2[x] < f2[best])) best = x;
+                  if (best < 0) {
+                    ok = false;
+                    break;
+                  }
+                  ax[b] = best;
+                  as[b] = f2[best];
+                  f2[best] += wq[b].G;
+                }
+                if (ok) {
+                  mq = wq;
+                  at_xcd = ax;
+                  at_slot = as;
+                  std::copy(f2, f2 + kCoopXcds, fill);
+                }
+              }
+            }
             const int maxfill = *std::max_element(fill, fill + kCoopXcds);
             const int nblocks = maxfill * kCoopXcds;
             std::vector<int32_t> blk_map((size_t)nblocks, -1);
             int64_t xdoubles = 0;
-            for (int i : members) xdoubles += coop_xch_doubles(list[i].G, list[i].d.a);
+            for (const CoopDesc& q : mq) xdoubles += coop_xch_doubles(q.G, q.d.a);
             int32_t* sync = sync_all + sync_used;
             sync_used += (int64_t)members.size() * kCoopSyncInts;
             if (sync_used > sync_cap)
@@ -1058,7 +1093,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             std::vector<CoopDesc> batch;
             int64_t xo = 0;
             for (size_t bi = 0; bi < members.size(); ++bi) {
-              CoopDesc q = list[members[bi]];
+              CoopDesc q = mq[bi];
               q.xcd = o.qr_xcd_local ? at_xcd[bi] : -1;
               q.sync = sync + bi * kCoopSyncInts;
               q.xch = xch + xo;

@@ -83,17 +83,49 @@ def test_degenerate_inputs():
     del Problem
 
 
-def test_colouring_is_greedy_smallest_free():
+def _crown(m):
+    """K_{m,m} minus a perfect matching, vertices u_i = 2i, v_i = 2i + 1: greedy
+    colouring in index order needs m colours, the graph is bipartite."""
+    adj = {x: [] for x in range(2 * m)}
+    for i in range(m):
+        for j in range(m):
+            if i != j:
+                adj[2 * i].append(2 * j + 1)
+                adj[2 * j + 1].append(2 * i)
+    return adj
+
+
+def test_dsatur_on_graphs_with_known_chromatic_numbers():
+    # DSATUR is exact on bipartite graphs (the crown defeats plain greedy)
+    adj = _crown(6)
+    col = nd.dsatur_colour(adj, list(adj), {x: 1 for x in adj})
+    assert max(col.values()) + 1 == 2
+    # odd cycle: 3 colours; complete graph K_5: 5
+    cyc = {x: [(x - 1) % 7, (x + 1) % 7] for x in range(7)}
+    assert max(nd.dsatur_colour(cyc, list(cyc), {x: 1 for x in cyc}).values()) + 1 == 3
+    k5 = {x: [y for y in range(5) if y != x] for x in range(5)}
+    assert sorted(nd.dsatur_colour(k5, list(k5), {x: 1 for x in k5}).values()) == [0, 1, 2, 3, 4]
+
+
+def test_dsatur_tie_breaks():
+    # first pick: largest weight, then lowest index; it takes colour 0 and its
+    # neighbours then lead by saturation
+    path = {0: [1], 1: [0, 2], 2: [1, 3], 3: [2]}
+    col = nd.dsatur_colour(path, [0, 1, 2, 3], {0: 1, 1: 1, 2: 5, 3: 1})
+    assert col[2] == 0 and col[1] == 1 and col[3] == 1 and col[0] == 0
+    col = nd.dsatur_colour(path, [0, 1, 2, 3], {0: 1, 1: 1, 2: 1, 3: 1})
+    assert col[0] == 0 and col[1] == 1 and col[2] == 0 and col[3] == 1
+
+
+def test_plan_colouring_is_proper_and_ordered():
     p = laplacian_3d(12)
     plan = nd.analyze(p.rowptr, p.colind, p.coords, 6)
     for st in plan.steps.values():
         nI = st.n_interior
         for p_ in range(nI, st.n_clusters):
-            earlier = {int(st.colour[q]) for q in st.adj[p_] if nI <= q < p_}
-            c = 0
-            while c in earlier:
-                c += 1
-            assert st.colour[p_] == c
+            assert all(st.colour[q] != st.colour[p_] for q in st.adj[p_] if q >= nI and q != p_)
+        used = sorted({int(c) for c in st.colour[nI:]})
+        assert used == list(range(len(used)))
         assert st.order == sorted(range(nI, st.n_clusters), key=lambda x: (st.colour[x], x))
 
 
