@@ -419,8 +419,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 5}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
-              "(see DESIGN.md for how it would shard); use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the factorization and PCG run on a single MI355X "
+              "(independent problems would shard whole, one problem along its nested-"
+              "dissection tree); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch256":

@@ -155,7 +155,9 @@ void spand_destroy_factor(spand_factor_t f);
 spand_status spand_factor_ranks(spand_factor_t f, int32_t l, int32_t* a, int32_t* k, int32_t* r,
                                 int32_t* r2);
 typedef struct {
-  int64_t nnz_L;          /* memory metric numerator (Sec. 4): see DESIGN counting rule */
+  int64_t nnz_L;          /* memory metric numerator (Sec. 4): lower triangles of the L_s and
+                             Z_p inverses, full G, the Householder vectors (a r - r(r-1)/2 plus
+                             r tau), and the stored E part (second order) */
   double  flops;          /* algorithmic flops of the factorization */
   double  factor_seconds; /* wall time of spand_factor */
   int64_t factor_bytes;   /* device bytes held by the factor */
