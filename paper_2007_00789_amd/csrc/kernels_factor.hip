@@ -2,8 +2,10 @@
 //
 //  k_potrf_inv_small : batched Cholesky + triangular inverse of blocks of at
 //                most 64 rows, one wave per block, the block in registers.
-//  k_potrf_inv : the same for larger blocks, one workgroup per block, by
-//                64x64 tiles through LDS, factored in place in global memory.
+//  k_potrf_inv : the same, one workgroup per block, in LDS.
+//  k_potrf_inv_big : blocks larger than 64 rows, 16 waves per block: 64x64
+//                diagonal tiles in LDS, the tile products on the FP64 matrix
+//                cores, factored in place in global memory.
 //  k_gemm      : batched multi-term GEMM over 64x64 output tiles; serves the
 //                TRSM of the interiors (as a product with L^{-1}), the Schur
 //                complement scatter (one tile list per target block, terms in
@@ -283,108 +285,218 @@ __device__ void lower_inv_offdiag(const double* A, double* X, int n, double* lds
   }
 }
 
-// Cholesky + inverse of a block larger than one tile: right-looking blocked
-// Cholesky in place in A (the dead diagonal block of the panel, ld n), the
-// inverses of the diagonal tiles into X's diagonal tiles, then the off-diagonal
-// tiles of X = L^{-1} by block forward substitution
-// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  LDS: four 64x65 tiles.
-__device__ int chol_inv_blocked(double* A, double* X, int n, double* lds) {
-  double* T0 = lds;
-  double* T1 = lds + kNb * kTl;
-  double* T2 = lds + 2 * kNb * kTl;
-  double* tmp = lds + 3 * kNb * kTl;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int nb = (n + kNb - 1) / kNb;
-  double acc[4][4];
-  for (int kb = 0; kb < nb; ++kb) {
-    const int k0 = kb * kNb, kw = min(kNb, n - k0);
-    // diagonal tile: factor (T1 = L_kk), invert a copy (T0 = L_kk^{-1})
-    tile_load(T1, A + k0 + (int64_t)k0 * n, n, kw, kw);
-    for (int idx = threadIdx.x; idx < kNb * kTl; idx += kPotrfThreads) T0[idx] = 0.0;
-    __syncthreads();
-    const int f = chol_inplace<kPotrfThreads>(T1, kw, kTl);
-    if (f) return k0 + f;
-    trinv<kPotrfThreads>(T1, kTl, T0, kTl, kw, tmp);
-    for (int idx = threadIdx.x; idx < kw * kw; idx += kPotrfThreads) {
-      const int i = idx % kw, j = idx / kw;
-      A[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T1[i + j * kTl] : 0.0;
-      X[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T0[i + j * kTl] : 0.0;
-    }
-    __syncthreads();
-    // panel: A_Ik <- A_Ik L_kk^{-T}
-    for (int ib = kb + 1; ib < nb; ++ib) {
-      const int i0 = ib * kNb, iw = min(kNb, n - i0);
-      tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);
-      __syncthreads();
-      acc_zero(acc);
-      tile_mma(acc, T1, T0, kw, true);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int i = tx + 16 * r, j = ty + 16 * c;
-          if (i < iw && j < kw) A[i0 + i + (int64_t)(k0 + j) * n] = acc[r][c];
-        }
-      __syncthreads();
-    }
-    // trailing update of the lower triangle: A_IJ -= A_Ik A_Jk^T
-    for (int jb = kb + 1; jb < nb; ++jb) {
-      const int j0 = jb * kNb, jw = min(kNb, n - j0);
-      tile_load(T2, A + j0 + (int64_t)k0 * n, n, jw, kw);
-      for (int ib = jb; ib < nb; ++ib) {
-        const int i0 = ib * kNb, iw = min(kNb, n - i0);
-        tile_load(T1, A + i0 + (int64_t)k0 * n, n, iw, kw);
-        __syncthreads();
-        acc_zero(acc);
-        tile_mma(acc, T1, T2, kw, true);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int i = tx + 16 * r, j = ty + 16 * c;
-            if (i < iw && j < jw) A[i0 + i + (int64_t)(j0 + j) * n] -= acc[r][c];
-          }
-        __syncthreads();
-      }
-    }
-  }
-  lower_inv_offdiag(A, X, n, lds);
-  return 0;
-}
-
+// Blocks of at most 64 rows, one workgroup per block, in LDS.
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* descs, int32_t* info) {
   extern __shared__ double sm[];
   const PotrfDesc d = descs[blockIdx.x];
   const int n = d.n;
   if (n == 0) return;
   const int tid = threadIdx.x;
-  if (n <= kNb) {
+  double* S = sm;
+  double* X = sm + n * n;
+  double* tmp = X + n * n;
+  for (int idx = tid; idx < n * n; idx += kPotrfThreads) {
+    const int i = idx % n, j = idx / n;
+    S[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : 0.0;
+  }
+  __syncthreads();
+  const int f = chol_inplace<kPotrfThreads>(S, n, n);
+  if (f) {
+    // breakdown: report it and leave a zero inverse, so that the products
+    // formed with it before the flag is read stay finite
+    if (tid == 0) info[blockIdx.x] = f;
+    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
+    return;
+  }
+  trinv<kPotrfThreads>(S, n, X, n, n, tmp);
+  for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = X[idx];
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky + inverse of blocks larger than one tile, 16 waves per block:
+// right-looking blocked Cholesky in place, with the tile products on the FP64
+// matrix cores (16 x 16 x 4 per instruction) and their operands read straight
+// from global memory (the block stays in L2): the 64 x 64 diagonal tiles are
+// factored and inverted in LDS, the panel below each one is
+// multiplied by the tile's inverse (transposed) one 16-row strip per wave, the
+// trailing lower triangle is updated by 16 x 16 subtiles spread over the
+// waves, and the off-diagonal tiles of X = L^{-1} follow by tile anti-diagonals
+// (X_IJ for I - J = d needs only X_KJ with K - J < d), first
+// S_IJ = sum_{K=J}^{I-1} L_IK X_KJ, kept transposed in the dead upper triangle
+// of A, then X_IJ = -X_II S_IJ.
+// ---------------------------------------------------------------------------
+constexpr int kBigThreads = 1024;
+constexpr int kBigWaves = kBigThreads / kWave;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// Operand of one 16 x 16 x 4 step: lane l supplies row l % 16 of the 16 x 4
+// left factor at column l / 16, and column l % 16 of the 4 x 16 right factor at
+// row l / 16.  The 16 x 16 accumulator gives lane l rows l / 16 + 4 v,
+// v = 0..3, of column l % 16 (checked on gfx950).
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// acc += P Q for one 16 x 16 subtile, with P(i, k) = p[i * pi + k * pk]
+// (i < pm) and Q(k, j) = q[k * qk + j * qj] (j < qn), k < kdim; rows and
+// columns outside the bounds read as zero.  Loads of 32 values of k are issued
+// together before their 8 products.
+__device__ __forceinline__ void sub_mma(d4_t& acc, const double* p, int64_t pi, int64_t pk,
+                                        int pm, const double* q, int64_t qk, int64_t qj, int qn,
+                                        int kdim) {
+  const int lane = threadIdx.x & (kWave - 1), r = lane & 15, kq = lane >> 4;
+  const double* pr = p + r * pi;
+  const double* qr = q + r * qj;
+  for (int kc = 0; kc < kdim; kc += 32) {
+    double a[8], b[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = kc + 4 * t + kq;
+      a[t] = (k < kdim && r < pm) ? pr[k * pk] : 0.0;
+      b[t] = (k < kdim && r < qn) ? qr[k * qk] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc = mfma16(a[t], b[t], acc);
+  }
+}
+
+__device__ int chol_inv_mfma(double* A, double* X, int n, double* lds) {
+  double* T1 = lds;                 // diagonal tile, factored in place
+  double* T0 = lds + kNb * kTl;     // its inverse
+  double* tmp = lds + 2 * kNb * kTl;
+  const int tid = threadIdx.x, wid = tid / kWave, lane = tid & (kWave - 1);
+  const int r = lane & 15, rq = lane >> 4;
+  const int nb = (n + kNb - 1) / kNb;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * kNb, kw = min(kNb, n - k0);
+    for (int idx = tid; idx < kNb * kTl; idx += kBigThreads) {
+      const int i = idx % kTl, j = idx / kTl;
+      T1[idx] = (i < kw && j < kw && i >= j) ? A[k0 + i + (int64_t)(k0 + j) * n] : 0.0;
+      T0[idx] = 0.0;
+    }
+    __syncthreads();
+    const int f = chol_inplace<kBigThreads>(T1, kw, kTl);
+    if (f) return k0 + f;
+    trinv<kBigThreads>(T1, kTl, T0, kTl, kw, tmp);
+    for (int idx = tid; idx < kw * kw; idx += kBigThreads) {
+      const int i = idx % kw, j = idx / kw;
+      X[k0 + i + (int64_t)(k0 + j) * n] = T0[i + j * kTl];   // zero above the diagonal
+    }
+    if (kb == nb - 1) break;
+    // panel: A_Ik <- A_Ik X_kk^T, one 16-row strip per wave (kw = 64 here)
+    const int p0 = k0 + kNb, nstrip = (n - p0 + 15) / 16;
+    for (int s = wid; s < nstrip; s += kBigWaves) {
+      const int i0 = p0 + 16 * s, im = min(16, n - i0);
+      const double* ar = A + i0 + r + (int64_t)(k0 + (lane >> 4)) * n;
+      d4_t acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int kc = 0; kc < kNb; kc += 32) {
+        double a[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[t] = r < im ? ar[(int64_t)(kc + 4 * t) * n] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int t = 0; t < 8; ++t)   // Q(k, j) = X_kk(j, k)
+            acc[c] = mfma16(a[t], T0[16 * c + r + (kc + 4 * t + (lane >> 4)) * kTl], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (rq + 4 * v < im) A[i0 + rq + 4 * v + (int64_t)(k0 + 16 * c + r) * n] = acc[c][v];
+    }
+    __syncthreads();
+    // trailing lower triangle, by 16 x 16 subtiles (I >= J strips)
+    const int npair = nstrip * (nstrip + 1) / 2;
+    for (int q = wid; q < npair; q += kBigWaves) {
+      int I = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      while ((I + 1) * (I + 2) / 2 <= q) ++I;
+      while (I * (I + 1) / 2 > q) --I;
+      const int J = q - I * (I + 1) / 2;
+      const int i0 = p0 + 16 * I, j0 = p0 + 16 * J;
+      const int im = min(16, n - i0), jm = min(16, n - j0);
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+      sub_mma(acc, A + i0 + (int64_t)k0 * n, 1, n, im, A + j0 + (int64_t)k0 * n, n, 1, jm, kNb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rq + 4 * v < im && r < jm) A[i0 + rq + 4 * v + (int64_t)(j0 + r) * n] -= acc[v];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // off-diagonal tiles of X, by anti-diagonals d = I - J
+  for (int d = 1; d < nb; ++d) {
+    const int nt = nb - d;   // tiles (J + d, J), J < nt
+    // S_IJ = sum_{K=J}^{I-1} L_IK X_KJ into A(J-rows, I-cols), transposed
+    for (int q = wid; q < nt * 16; q += kBigWaves) {
+      const int jb = q / 16, sub = q % 16, ib = jb + d;
+      const int i0 = ib * kNb + 16 * (sub / 4), j0 = jb * kNb + 16 * (sub % 4);
+      if (i0 >= n) continue;
+      const int im = min(16, n - i0);
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+      sub_mma(acc, A + i0 + (int64_t)(jb * kNb) * n, 1, n, im, X + jb * kNb + (int64_t)j0 * n, 1,
+              n, 16, d * kNb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rq + 4 * v < im) A[j0 + r + (int64_t)(i0 + rq + 4 * v) * n] = acc[v];
+    }
+    __syncthreads();
+    // X_IJ = -X_II S_IJ; the mirrored upper tile of X is zeroed
+    for (int q = wid; q < nt * 16; q += kBigWaves) {
+      const int jb = q / 16, sub = q % 16, ib = jb + d;
+      const int ii = ib * kNb, iw = min(kNb, n - ii);
+      const int i0 = ii + 16 * (sub / 4), j0 = jb * kNb + 16 * (sub % 4);
+      if (i0 >= n) continue;
+      const int im = min(16, n - i0);
+      d4_t acc = {0.0, 0.0, 0.0, 0.0};
+      sub_mma(acc, X + i0 + (int64_t)ii * n, 1, n, im, A + j0 + (int64_t)ii * n, n, 1, 16, iw);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rq + 4 * v < im) {
+          X[i0 + rq + 4 * v + (int64_t)(j0 + r) * n] = -acc[v];
+          X[j0 + r + (int64_t)(i0 + rq + 4 * v) * n] = 0.0;
+        }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_potrf_inv_big(const PotrfDesc* descs,
+                                                               int32_t* info) {
+  extern __shared__ double sm[];
+  const PotrfDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  if (n == 0) return;
+  const int tid = threadIdx.x;
+  if (n <= kNb) {   // a small block of a launch with large ones: in LDS
     double* S = sm;
     double* X = sm + n * n;
     double* tmp = X + n * n;
-    for (int idx = tid; idx < n * n; idx += kPotrfThreads) {
+    for (int idx = tid; idx < n * n; idx += kBigThreads) {
       const int i = idx % n, j = idx / n;
       S[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : 0.0;
     }
     __syncthreads();
-    const int f = chol_inplace<kPotrfThreads>(S, n, n);
+    const int f = chol_inplace<kBigThreads>(S, n, n);
     if (f) {
-      // breakdown: report it and leave a zero inverse, so that the products
-      // formed with it before the flag is read stay finite
       if (tid == 0) info[blockIdx.x] = f;
-      for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
+      for (int idx = tid; idx < n * n; idx += kBigThreads) d.X[idx] = 0.0;
       return;
     }
-    trinv<kPotrfThreads>(S, n, X, n, n, tmp);
-    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = X[idx];
+    trinv<kBigThreads>(S, n, X, n, n, tmp);
+    for (int idx = tid; idx < n * n; idx += kBigThreads) d.X[idx] = X[idx];
   } else {
-    // the panel's diagonal block (ld n) is dead after this call: factor in place
-    const int f = chol_inv_blocked(const_cast<double*>(d.A), d.X, n, sm);
+    // the panel's diagonal block (ld n) is dead after this call: factored in
+    // place, its upper triangle used for the products S_IJ
+    const int f = chol_inv_mfma(const_cast<double*>(d.A), d.X, n, sm);
     if (f) {
       if (tid == 0) info[blockIdx.x] = f;
       __syncthreads();
-      for (int64_t idx = tid; idx < (int64_t)n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
+      for (int64_t idx = tid; idx < (int64_t)n * n; idx += kBigThreads) d.X[idx] = 0.0;
     }
   }
 }
@@ -870,10 +982,13 @@ void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t*
 void launch_potrf_blocks(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                          hipStream_t s) {
   if (count <= 0) return;
-  // n <= 64: the block, its inverse and the inverse's products in LDS; larger:
-  // four 64x65 tiles
-  size_t lds = max_n <= kNb ? ((size_t)2 * max_n * max_n + 768) * sizeof(double)
-                            : (size_t)4 * kNb * kTl * sizeof(double);
+  if (max_n > kNb) {   // two 64x65 tiles and the inverse's products
+    const size_t lds = ((size_t)2 * kNb * kTl + 768) * sizeof(double);
+    hipLaunchKernelGGL(k_potrf_inv_big, dim3(count), dim3(kBigThreads), lds, s, d, info);
+    return;
+  }
+  // the block, its inverse and the inverse's products in LDS
+  const size_t lds = ((size_t)2 * max_n * max_n + 768) * sizeof(double);
   hipLaunchKernelGGL(k_potrf_inv, dim3(count), dim3(kPotrfThreads), lds, s, d, info);
 }
 
