@@ -110,6 +110,18 @@ __device__ int block_min_int(int v, int* red) {
   return s;
 }
 
+// 1/sqrt(v) for a positive normal v: the hardware estimate refined by two
+// Newton steps y <- y (3 - v y^2) / 2, which leaves a few units in the last
+// place.  The pivots need no correctly rounded root, and this is a short
+// dependent chain where sqrt and two divisions are a long one.
+__device__ __forceinline__ double rsqrt_nr(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+  const double h = 0.5 * v;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky of an n x n SPD block (n <= 64, column-major in LDS, lower triangle
 // read).  Right-looking with one barrier per column: every thread reads the
@@ -121,18 +133,17 @@ template <int NT>
 __device__ int chol_inplace(double* S, int n, int ld) {
   constexpr int TX = 16, TY = NT / TX;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  double vprev = 0.0;
+  double vprev = 0.0, rprev = 0.0;
   for (int j = 0; j <= n; ++j) {
-    if (j > 0) {   // finish column j-1
-      const double d = sqrt(vprev), rd = 1.0 / d;
+    if (j > 0) {   // finish column j-1: l_jj = v rsqrt(v), l_ij = s_ij rsqrt(v)
       const int jp = j - 1;
-      for (int i = j + threadIdx.x; i < n; i += NT) S[i + (int64_t)jp * ld] *= rd;
-      if (threadIdx.x == 0) S[jp + (int64_t)jp * ld] = d;
+      for (int i = j + threadIdx.x; i < n; i += NT) S[i + (int64_t)jp * ld] *= rprev;
+      if (threadIdx.x == 0) S[jp + (int64_t)jp * ld] = vprev * rprev;
     }
     if (j == n) break;
     const double v = S[j + (int64_t)j * ld];
     if (!(v > 0.0)) return j + 1;   // every thread reads the same value
-    const double rv = 1.0 / v;
+    const double rs = rsqrt_nr(v), rv = rs * rs;
     for (int c = j + 1 + ty; c < n; c += TY) {
       const double scj = S[c + (int64_t)j * ld] * rv;
       for (int i = c + tx; i < n; i += TX)
@@ -140,6 +151,7 @@ __device__ int chol_inplace(double* S, int n, int ld) {
     }
     __syncthreads();
     vprev = v;
+    rprev = rs;
   }
   __syncthreads();
   return 0;
@@ -149,7 +161,8 @@ __device__ int chol_inplace(double* S, int n, int ld) {
 // L; X is zeroed above the diagonal).  16 x 16 blocks: wave I inverts diagonal
 // block I by forward substitution (lane c builds column c), then the blocks
 // below the diagonal follow one block diagonal at a time,
-// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  tmp: 768 doubles of LDS.
+// X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  tmp: 768 doubles of LDS (first the
+// reciprocals of L's diagonal).
 template <int NT>
 __device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, double* tmp) {
   static_assert(NT >= 256, "one wave per 16-row diagonal block");
@@ -157,18 +170,19 @@ __device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, doubl
   const int nbk = (n + 15) / 16;
   for (int c = wid; c < n; c += NT / kWave)
     for (int i = lane; i < n; i += kWave) X[i + (int64_t)c * ldx] = 0.0;
+  for (int i = tid; i < n; i += NT) tmp[i] = 1.0 / L[i + (int64_t)i * ldl];
   __syncthreads();
   if (wid < nbk && lane < 16) {
     const int b0 = wid * 16, bw = min(16, n - b0), c = lane;
     if (c < bw) {
       const int gc = b0 + c;
-      X[gc + (int64_t)gc * ldx] = 1.0 / L[gc + (int64_t)gc * ldl];
+      X[gc + (int64_t)gc * ldx] = tmp[gc];
       for (int i = c + 1; i < bw; ++i) {
         const int gi = b0 + i;
         double acc = 0.0;
         for (int k = c; k < i; ++k)
           acc = fma(L[gi + (int64_t)(b0 + k) * ldl], X[b0 + k + (int64_t)gc * ldx], acc);
-        X[gi + (int64_t)gc * ldx] = -acc / L[gi + (int64_t)gi * ldl];
+        X[gi + (int64_t)gc * ldx] = -acc * tmp[gi];
       }
     }
   }
@@ -540,6 +554,7 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
     row[c] = (lane < n && c < n) ? (c <= lane ? d.A[lane + (int64_t)c * d.lda] : 0.0)
                                  : (c == lane ? 1.0 : 0.0);
   int fail = 0;
+  double rdl = 1.0;   // lane j: 1 / l_jj (1 in the identity padding)
 #pragma unroll
   for (int j = 0; j < NM; ++j) {
     const double v = readlane_d(row[j], j);
@@ -547,8 +562,9 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
       fail = j + 1;
       break;
     }
-    const double ljj = sqrt(v);
-    const double lij = lane > j ? row[j] / ljj : (lane == j ? ljj : 0.0);
+    const double rs = rsqrt_nr(v);
+    const double lij = lane > j ? row[j] * rs : (lane == j ? v * rs : 0.0);
+    if (lane == j) rdl = rs;   // 1 / l_jj, for the inverse
     if (lane >= j) row[j] = lij;
     if (lane < NM) cb[lane] = lij;
     __builtin_amdgcn_wave_barrier();
@@ -569,7 +585,7 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
   for (int j = NM - 1; j >= 0; --j) {
     if (lane < NM) cb[lane] = row[j];   // column j of L, before it is overwritten
     __builtin_amdgcn_wave_barrier();
-    const double xjj = 1.0 / cb[j];
+    const double xjj = readlane_d(rdl, j);
     double acc = 0.0;
 #pragma unroll
     for (int m = j + 1; m < NM; ++m)
