@@ -81,26 +81,28 @@ def cpu_baseline(scheme: str, eps: float, gpu_ref: dict) -> dict:
 # HBM traffic per launch of a kernel, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) over `bench.py --steps 1 --warmup 0`,
 # each scaled by what the same counter reads for a plain 256 MiB device copy.
-# The figures hold only for the sources they were taken on: if any listed file
-# has changed since, the traffic is reported as null.
+# The figures hold only for the workload and the sources they were taken on:
+# on another workload, or if any listed file has changed since, the traffic is
+# reported as null.
 MEASURED_TRAFFIC = {
     "k_cpqr_coop": {
+        "workload": "lap3d_64",
         "sources": {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
             "paper_2007_00789_amd/csrc/factor.cpp": "4b79be5b712e1c81726860743618e8f262039b5f86f487ad06cd80639b9c156b",
         },
-        "fetch_kib": 8216.4, "write_kib": 45941.9,
+        "fetch_kib": 8216.8, "write_kib": 45928.4,
         "fetch_scale": 1.9998, "write_scale": 1.0000,
     },
 }
 
 
-def measured_traffic(kernel):
-    """Calibrated HBM bytes per launch of `kernel`, or None if not measured on
-    the current sources."""
+def measured_traffic(kernel, workload):
+    """Calibrated HBM bytes per launch of `kernel` on `workload`, or None if not
+    measured there on the current sources."""
     import hashlib
     m = MEASURED_TRAFFIC.get(kernel)
-    if m is None:
+    if m is None or m["workload"] != workload:
         return None
     for rel, digest in m["sources"].items():
         with open(os.path.join(ROOT, rel), "rb") as f:
@@ -505,7 +507,7 @@ def main():
         ach = dwork / (dms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_TFLOPS,
                 "work": "FP64 flops of the pivoted QR, sum over reflectors j of 4(a-j)(k-j)",
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom, args.workload),
                 "avg_launch_ms": dms / dcalls, "launches": dcalls}
     else:
         roof = {"bound": None, "kernel": dom, "achieved": None, "peak": None, "unit": None,

@@ -221,6 +221,39 @@ def test_not_spd_in_a_step_without_sparsification(ctx):
 
 
 @gpu
+def test_not_spd_in_a_block_of_several_tiles(ctx):
+    # A - 0.25 I on the 12^3 Laplacian (smallest eigenvalue 0.174): the leaf
+    # interiors (300-432 rows) and the halves stay positive definite, the
+    # Schur complement on the root separator (144 rows, three 64-row tiles)
+    # does not.  The oracle fails on the same step and kind of block.
+    from paper_2007_00789_amd import spand
+    import scipy.sparse as sp
+    p = laplacian_3d(12)
+    A = (p.scipy() - 0.25 * sp.identity(p.n)).tocsr()
+    A.sort_indices()
+    assert np.array_equal(A.indptr, p.rowptr) and np.array_equal(A.indices, p.colind)
+    with pytest.raises(ospand.NotSPD) as oe:
+        ospand.factor(A, nd.analyze(p.rowptr, p.colind, p.coords, 2, 0), 1e-2, "SO")
+    assert (oe.value.step, oe.value.what) == (1, "interface block")
+    opts = spand.make_opts(depth=2, skip=0, eps=1e-2)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    with pytest.raises(spand.SpandError) as e:
+        ctx.factor(plan, _dev(A.data), opts)
+    assert e.value.status == -3
+    assert f"interface block not SPD at step 1, cluster {oe.value.cluster}" in e.value.message
+    # the unshifted matrix factors, and its large blocks are exact at eps = 0
+    opts0 = spand.make_opts(depth=2, skip=0, eps=0.0)
+    fac = ctx.factor(plan, _dev(p.vals), opts0)
+    b = rhs(p.n, 1, 9)
+    db = _dev(b)
+    dy = torch.zeros_like(db)
+    ctx.apply(fac, 1, db, dy)
+    res = np.linalg.norm(b[:, 0] - p.scipy() @ dy.cpu().numpy()) / np.linalg.norm(b)
+    assert res < 1e-13
+    fac.close()
+
+
+@gpu
 def test_no_convergence_status(ctx):
     p = laplacian_2d(32)
     _, fac = _gpu_factor(ctx, p, 4, 0, 0.3, "FO")
