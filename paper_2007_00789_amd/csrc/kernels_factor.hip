@@ -600,7 +600,9 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
 }
 
 // ---------------------------------------------------------------------------
-// Batched multi-term GEMM, 64x64 tile per workgroup, 4x4 per thread.
+// Batched multi-term GEMM, 64x64 tile per workgroup: k-slabs of A and B staged
+// in LDS, each wave a 32x32 quadrant as 2x2 FP64 matrix-core tiles
+// (16 x 16 x 4 per instruction).
 // ---------------------------------------------------------------------------
 constexpr int kGemmThreads = 256;
 constexpr int kGemmK = 16;
@@ -612,12 +614,13 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmDesc* descs, co
   const TileRef t = tiles[blockIdx.x];
   const GemmDesc d = descs[t.desc];
   const int i0 = t.ti * kGemmTile, j0 = t.tj * kGemmTile;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int wr = 32 * (w & 1), wc = 32 * (w >> 1), r = lane & 15, kq = lane >> 4;
+  d4_t acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int ci = 0; ci < 2; ++ci) acc[ri][ci] = d4_t{0.0, 0.0, 0.0, 0.0};
   for (int64_t term = d.term0; term < d.term1; ++term) {
     const GemmTerm tm = terms[term];
     for (int k0 = 0; k0 < tm.k; k0 += kGemmK) {
@@ -643,32 +646,32 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmDesc* descs, co
       }
       __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < kGemmK; ++kk) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = As[kk][tx + 16 * r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+      for (int s4 = 0; s4 < kGemmK / 4; ++s4) {
+        const int kk = 4 * s4 + kq;
+        const double a0 = As[kk][wr + r], a1 = As[kk][wr + 16 + r];
+        const double b0 = Bs[kk][wc + r], b1 = Bs[kk][wc + 16 + r];
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int gi = i0 + tx + 16 * r, gj = j0 + ty + 16 * c;
-      if (gi < d.m && gj < d.n) {
-        double v = d.alpha * acc[r][c];
-        if (d.beta != 0.0) v = fma(d.beta, d.C[gi + (int64_t)gj * d.ldc], v);
-        d.C[gi + (int64_t)gj * d.ldc] = v;
-        if (d.C2) d.C2[gj + (int64_t)gi * d.ldc2] = v;
+    for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int gi = i0 + wr + 16 * ri + kq + 4 * v4, gj = j0 + wc + 16 * ci + r;
+        if (gi < d.m && gj < d.n) {
+          double v = d.alpha * acc[ri][ci][v4];
+          if (d.beta != 0.0) v = fma(d.beta, d.C[gi + (int64_t)gj * d.ldc], v);
+          d.C[gi + (int64_t)gj * d.ldc] = v;
+          if (d.C2) d.C2[gj + (int64_t)gi * d.ldc2] = v;
+        }
       }
-    }
 }
 
 // ---------------------------------------------------------------------------
