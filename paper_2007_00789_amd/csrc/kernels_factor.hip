@@ -607,7 +607,7 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
 constexpr int kGemmThreads = 256;
 constexpr int kGemmK = 16;
 
-__global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmDesc* descs, const GemmTerm* terms,
+__global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDesc* descs, const GemmTerm* terms,
                                                         const TileRef* tiles) {
   __shared__ double As[kGemmK][kGemmTile + 1];
   __shared__ double Bs[kGemmK][kGemmTile + 1];
