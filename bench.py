@@ -91,7 +91,7 @@ MEASURED_TRAFFIC = {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
             "paper_2007_00789_amd/csrc/factor.cpp": "4b79be5b712e1c81726860743618e8f262039b5f86f487ad06cd80639b9c156b",
         },
-        "fetch_kib": 8216.8, "write_kib": 45928.4,
+        "fetch_kib": 8216.4, "write_kib": 45951.2,
         "fetch_scale": 1.9998, "write_scale": 1.0000,
     },
 }
