@@ -131,7 +131,9 @@ void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double
 // 0, or the 1-based column of the first non-positive pivot of block i, whose
 // X is then left zero).  launch_potrf_inv: max_n <= 64 runs one wave per
 // block, larger max_n one workgroup per block; launch_potrf_blocks always
-// runs one workgroup per block.
+// runs one workgroup per block (256 threads when max_n <= 64, else 16 waves
+// with the tile products on the matrix cores).  Blocks above 64 rows are
+// factored in place: their diagonal block in A (ld n) is overwritten.
 void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s);
 void launch_potrf_blocks(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
