@@ -1,16 +1,21 @@
 """Benchmark of the spaND hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps 1e-2] [--scheme SO]
-                    [--no-cpu-baseline] [--workload lap3d_64|lap2d_64|fv3d_128|batch256|serve|eig2d|table1]
+                    [--no-cpu-baseline]
+                    [--workload fv3d_128|lap3d_64|lap2d_64|c1grid|batch256|serve|eig2d|table1]
 
-Workload (the metric's configuration that fits one GPU): 3D 7-point Laplacian
-on a 64^3 grid (n = 262,144), nested-dissection depth 12, skip 4, eps 1e-2,
-full second-order scheme, FP64, 4 right-hand sides ~ N(0,1) (seed 2001), PCG
-to 1e-10 relative residual.  Synthetic inputs (synthetic.workload).
+Default workload: the largest single matrix of the metric's configurations,
+3D finite-volume diffusion on a 128^3 grid (n = 2,097,152) with per-cell
+coefficient 10^u, u ~ U[-3,3] (seed 1002), harmonic-mean faces, nested-
+dissection depth 15, skip 4, eps 1e-2, full second-order scheme, FP64, one
+right-hand side ~ N(0,1) (seed 2002), PCG to 1e-10 relative residual.
+`--workload lap3d_64` runs the 3D 7-point Laplacian 64^3 (depth 12, 4 RHS);
+`c1grid` runs it over eps in {1e-1, 1e-2, 1e-3} x {first, second order}.
+Synthetic inputs (synthetic.workload).
 
 One step = the numeric hot path on the device: spand_factor (leaf assembly,
 interior elimination, scaling, sparsification, merge, per level) followed by
-spand_pcg on the 4 right-hand sides (apply + SpMV + BLAS-1 per iteration).
+spand_pcg on the right-hand sides (apply + SpMV + BLAS-1 per iteration).
 The symbolic analysis (host C++) depends only on the sparsity pattern and the
 coordinates; it is computed once and reported separately (analyze_s).
 
@@ -42,40 +47,130 @@ WORKLOAD_NAMES = {
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 
-def cpu_baseline(scheme: str, eps: float, gpu_ref: dict) -> dict:
-    """The oracle, single-threaded, end-to-end (factor + PCG, 1 RHS) on a
-    3D 40^3 Laplacian (depth 10): a bounded sample of the same problem family.
-    Scaled to the 64^3, 4-RHS workload by algorithmic work: factor time by the
-    ratio of factor flops, solve time by the ratio of n_cg * (nnz(L) + nnz(A))
-    per right-hand side, times 4 right-hand sides."""
-    from threadpoolctl import threadpool_limits
-    from synthetic import laplacian_3d, rhs
+# oracle sample of each single-matrix workload: the same matrix family at two
+# smaller sizes (seconds each)
+CPU_SAMPLE = {
+    "lap3d_64": ("laplacian_3d", lambda s: __import__("synthetic").laplacian_3d(s), (24, 32)),
+    "fv3d_128": ("fv_diffusion_3d(s, 3, 1002)",
+                 lambda s: __import__("synthetic").fv_diffusion_3d(s, 3.0, 1002), (24, 32)),
+    "lap2d_64": ("laplacian_2d", lambda s: __import__("synthetic").laplacian_2d(s), (32, 48)),
+}
+
+
+def host_cpu() -> dict:
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def time_oracle(prob, depth, skip, scheme, eps, tol, rhs_seed):
+    """(analyze + factor seconds, PCG seconds per iteration, iterations) of the
+    oracle on one problem and one right-hand side."""
+    from synthetic import rhs
     from oracle import nd, spand as ospand, pcg as opcg
-    with threadpool_limits(1):
-        p = laplacian_3d(40)
-        A = p.scipy()
-        plan = nd.analyze(p.rowptr, p.colind, p.coords, 10, 4)
-        t0 = time.perf_counter()
-        F = ospand.factor(A, plan, eps, scheme)
-        tf = time.perf_counter() - t0
-        b = rhs(p.n, 1, 2001)[:, 0]
-        t0 = time.perf_counter()
-        _, it, _ = opcg.pcg(lambda v: A @ v, lambda v: ospand.apply(F, v), b, 1e-10)
-        ts = time.perf_counter() - t0
-    f_s = sum(F.flops.values())
-    w_s = it * (F.nnz_L + p.nnz)
-    w_g = gpu_ref["iters_mean"] * (gpu_ref["nnz_L"] + gpu_ref["nnz_A"])
-    t_scaled = tf * gpu_ref["flops"] / f_s + gpu_ref["nrhs"] * ts * w_g / w_s
-    return {
-        "value": gpu_ref["nrhs"] / t_scaled,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle (Python/NumPy FP64, 1 thread) factor+PCG on lap3d 40^3 depth 10, "
-                   f"{scheme} eps {eps:g}, 1 RHS: factor {tf:.2f} s ({f_s / 1e9:.2f} GF), "
-                   f"PCG {ts:.2f} s ({it} it); scaled to lap3d 64^3 x {gpu_ref['nrhs']} RHS by "
-                   f"factor flops and n_cg*(nnz(L)+nnz(A)); host {platform.processor() or platform.machine()}"),
-    }
+    A = prob.scipy()
+    t0 = time.perf_counter()
+    plan = nd.analyze(prob.rowptr, prob.colind, prob.coords, depth, skip)
+    F = ospand.factor(A, plan, eps, scheme)
+    t1 = time.perf_counter()
+    b = rhs(prob.n, 1, rhs_seed)[:, 0]
+    _, it, _ = opcg.pcg(lambda v: A @ v, lambda v: ospand.apply(F, v), b, tol)
+    t2 = time.perf_counter()
+    return t1 - t0, (t2 - t1) / max(it, 1), it
+
+
+def oracle_sample(workload: str, w: dict, scheme: str, eps: float, threads: int = 1,
+                  sizes=None) -> dict:
+    """The oracle timed on the sample sizes of a workload (analyze + factor,
+    PCG per iteration), on `threads` BLAS threads."""
+    from threadpoolctl import threadpool_limits
+    fam, make, default_sizes = CPU_SAMPLE[workload]
+    sizes = list(sizes or default_sizes)
+    out = {"family": fam, "sizes": sizes, "n": [], "factor_s": [], "pcg_iter_s": [], "n_cg": [],
+           "threads": threads}
+    with threadpool_limits(threads):
+        for s_ in sizes:
+            p = make(s_)
+            tf, ti, it = time_oracle(p, max(0, int(round(np.log2(p.n / 64.0)))), w["skip"],
+                                     scheme, eps, w["tol"], w["rhs_seed"])
+            out["n"].append(p.n)
+            out["factor_s"].append(tf)
+            out["pcg_iter_s"].append(ti)
+            out["n_cg"].append(it)
+    return out
+
+
+def cpu_baseline(workload: str, w: dict, n_full: int, scheme: str, eps: float, n_cg: list) -> dict:
+    """The oracle (Python/NumPy FP64) as the CPU baseline of a workload.
+
+    The full-size oracle run is too long to repeat here (about an hour at
+    128^3), so this host times a bounded sample instead: the same matrix
+    family at two smaller sizes, on one thread (the paper's protocol).  When
+    the full-size oracle run was timed on the machine that wrote the stored
+    expected values (tests/golden/oracle_timing.json, which holds that run and
+    the same sample timed there), the baseline is that measured full-size time
+    scaled by the ratio of this host's sample time to that machine's.  A power
+    law per phase fitted through the two sample sizes is reported beside it,
+    with its prediction for the measured full run, so the error of a pure
+    size extrapolation stays visible (without stored timings the power law is
+    the baseline).  All host threads are timed on the smaller sample size, and
+    their speed-up over one thread is applied to the same estimate."""
+    one = oracle_sample(workload, w, scheme, eps, 1)
+    ns, tf, ti = one["n"], one["factor_s"], one["pcg_iter_s"]
+    nrhs = w["nrhs"]
+
+    def law(t):
+        p = np.log(t[1] / t[0]) / np.log(ns[1] / ns[0])
+        return (lambda n: t[0] * (n / ns[0]) ** p), float(p)
+
+    ff, pf = law(tf)
+    fi, pi = law(ti)
+    iters = float(np.sum(n_cg))
+    t_law = ff(n_full) + fi(n_full) * iters
+    case = f"{workload}_{scheme}_{eps:.0e}".replace("e-0", "e-")
+    stored = None
+    tpath = os.path.join(ROOT, "tests", "golden", "oracle_timing.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            stored = json.load(f).get(case)
+    out = {"unit": "solves/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
+           "sample_s": {k: one[k] for k in ("sizes", "n", "factor_s", "pcg_iter_s", "n_cg")}}
+    law_txt = (f"power law through the sample (factor exponent {pf:.2f}, PCG per-iteration exponent "
+               f"{pi:.2f})")
+    if stored and stored["sample"]["sizes"] == one["sizes"]:
+        sref = stored["sample"]
+        speed = (sum(tf) + sum(ti)) / (sum(sref["factor_s"]) + sum(sref["pcg_iter_s"]))
+        full = stored["full"]
+        # the stored run's PCG time per iteration, at this run's iteration counts
+        t_est = speed * (full["factor_s"] + full["pcg_s"] / max(1, sum(full["n_cg"])) * iters)
+        t_law_stored = ff(n_full) + fi(n_full) * float(sum(full["n_cg"]))
+        out.update(value=nrhs / t_est, predicted_s_per_step=t_est, sample=(
+            f"oracle full run of this workload ({case}: factor {full['factor_s']:.0f} s, PCG "
+            f"{full['pcg_s']:.0f} s for n_cg {full['n_cg']}, 1 thread, on {stored['host']['model']}) "
+            f"scaled by this host's speed on a sample ({one['family']} at sides {one['sizes']}, "
+            f"1 thread: {speed:.2f} x that machine's time) and to {nrhs} RHS at the GPU run's n_cg"))
+        out["power_law_check"] = {"model": law_txt, "predicted_full_s": t_law_stored * speed,
+                                  "measured_full_s_scaled": speed * (full["factor_s"] + full["pcg_s"]),
+                                  "ratio": t_law_stored / (full["factor_s"] + full["pcg_s"])}
+    else:
+        out.update(value=nrhs / t_law, predicted_s_per_step=t_law, sample=(
+            f"oracle on {one['family']} at sides {one['sizes']} (n={ns}), 1 thread; {law_txt} "
+            f"evaluated at n={n_full} with the GPU run's n_cg x {nrhs} RHS"))
+    allc = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                      os.cpu_count() or 1))
+    if allc > 1:
+        many = oracle_sample(workload, w, scheme, eps, allc, sizes=one["sizes"][:1])
+        su = (tf[0] + ti[0]) / (many["factor_s"][0] + many["pcg_iter_s"][0])
+        out["all_cores"] = {"cores": allc, "speedup_over_1": su, "value": out["value"] * su,
+                            "sample_s": {k: many[k] for k in ("sizes", "factor_s", "pcg_iter_s")}}
+    return out
 
 
 # HBM traffic per launch of a kernel, from two rocprofv3 --pmc passes
@@ -180,6 +275,63 @@ def bench_batch(args):
         "mu": info["nnz_L"] / nnz,
         "factor_gflop": info["flops"] / 1e9,
         "analyze_s": analyze_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c1grid(args):
+    """The 3D 7-point Laplacian 64^3 (depth 12, skip 4, 4 RHS ~ N(0,1), seed
+    2001, PCG to 1e-10) over eps in {1e-1, 1e-2, 1e-3} x {first, second order}:
+    per configuration solves/s (factorization included), factor and solve time,
+    n_cg, nnz(L)/nnz(A) and the true residual.  One JSON line; `value` is the
+    second-order eps = 1e-2 configuration's solves/s."""
+    import torch
+    from paper_2007_00789_amd import spand
+    from synthetic import workload, rhs
+
+    prob, w = workload("lap3d_64")
+    nrhs, tol = w["nrhs"], w["tol"]
+    ctx = spand.Context(0)
+    vals = torch.from_numpy(prob.vals).to("cuda:0")
+    b = torch.from_numpy(np.asfortranarray(rhs(prob.n, nrhs, w["rhs_seed"])).reshape(-1, order="F").copy()).to("cuda:0")
+    x = torch.zeros_like(b)
+    plan = None
+    rows = []
+    for eps in (1e-1, 1e-2, 1e-3):
+        for scheme in ("FO", "SO"):
+            opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=eps, scheme=scheme)
+            if plan is None:
+                plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
+            tfs, tss = [], []
+            for i in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                fac = ctx.factor(plan, vals, opts)
+                tf = time.perf_counter() - t
+                it, rr = ctx.pcg(fac, nrhs, b, x, tol, 1000)
+                ts = time.perf_counter() - t - tf
+                info = fac.info()
+                fac.close()
+                if i >= args.warmup:
+                    tfs.append(tf)
+                    tss.append(ts)
+            step = float(np.mean(tfs) + np.mean(tss))
+            rows.append({"eps": eps, "scheme": scheme, "solves_per_s": nrhs / step,
+                         "factor_ms": 1e3 * float(np.mean(tfs)), "solve_ms": 1e3 * float(np.mean(tss)),
+                         "n_cg": [int(v) for v in it], "relres_max": float(rr.max()),
+                         "mu": info["nnz_L"] / prob.nnz,
+                         "factor_tflops": info["flops"] / float(np.mean(tfs)) / 1e12})
+    ref = [r for r in rows if r["eps"] == 1e-2 and r["scheme"] == "SO"][0]
+    out = {
+        "metric": "PCG solves/s to 1e-10 rel. residual; factor TFLOP/s; p50/p99 solve latency",
+        "value": ref["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * nrhs / ref["solves_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lap3d 64^3 7-point Laplacian, n={prob.n}, depth {w['depth']}, "
+                               f"skip {w['skip']}, eps x scheme grid, FP64, {nrhs} RHS N(0,1), "
+                               f"PCG tol {tol:g}", "global_batch": nrhs, "parallelism": "single GPU"},
+        "grid": rows,
     }
     print(json.dumps(out), flush=True)
 
@@ -399,7 +551,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--scheme", default="SO")
-    ap.add_argument("--workload", default="lap3d_64")
+    ap.add_argument("--workload", default="fv3d_128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=48, help="requests of the serving stream")
     ap.add_argument("--eig-d", type=int, default=1000, help="grid side of the eigenvector study")
@@ -428,6 +580,8 @@ def main():
 
     if args.workload == "batch256":
         return bench_batch(args)
+    if args.workload == "c1grid":
+        return bench_c1grid(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.workload == "eig2d":
@@ -507,6 +661,8 @@ def main():
         ach = dwork / (dms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_TFLOPS,
                 "work": "FP64 flops of the pivoted QR, sum over reflectors j of 4(a-j)(k-j)",
+                "limiter": "latency of the dependent pivot steps (one reduction, barrier and "
+                           "rank-1 update per reflector), not the ALU rate",
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom, args.workload),
                 "avg_launch_ms": dms / dcalls, "launches": dcalls}
     else:
@@ -543,10 +699,9 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and args.workload == "lap3d_64":
-        ref = {"flops": flops, "nnz_L": info["nnz_L"], "nnz_A": prob.nnz, "nrhs": nrhs,
-               "iters_mean": float(it_all.mean())}
-        out["cpu_baseline"] = cpu_baseline(args.scheme, args.eps, ref)
+    if not args.no_cpu_baseline and args.workload in CPU_SAMPLE:
+        out["cpu_baseline"] = cpu_baseline(args.workload, w, prob.n, args.scheme, args.eps,
+                                           iters[-1])
     print(json.dumps(out), flush=True)
 
 

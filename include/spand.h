@@ -54,7 +54,17 @@ typedef enum {
  * trailing-1); full second order keeps E in the outer factors and drops only
  * -E^T E (eq. trailing-2); superfine keeps E_2 only (eq. trailing-3). */
 typedef enum { SPAND_FIRST_ORDER = 1, SPAND_SECOND_ORDER = 2, SPAND_SUPERFINE = 3 } spand_scheme;
-typedef enum { SPAND_FP64 = 0 } spand_precision;
+/* Arithmetic of the factorization (a project addition; the paper's runs are
+ * FP64).  SPAND_FP64: everything in FP64.  SPAND_FP32: the row panels, the
+ * Cholesky factors, the Schur and scaling products, the pivoted QR and the
+ * stored factor in FP32, except the steps l < top_fp64_levels (the top
+ * separator levels and the root), which run in FP64.  SPAND_FP32_BF16: as
+ * SPAND_FP32, with the Schur-complement products of the interior elimination
+ * taken from BF16 operands on the matrix cores and accumulated in FP32.  The
+ * apply keeps its vectors in FP64 (FP32 factor entries are widened on load),
+ * and PCG (SpMV, residuals, dot products) is FP64 in every mode, so PCG
+ * refines the solution to the requested tolerance whatever the precision. */
+typedef enum { SPAND_FP64 = 0, SPAND_FP32 = 1, SPAND_FP32_BF16 = 2 } spand_precision;
 
 typedef struct {
   int32_t depth;      /* nested-dissection depth D (levels D..0, Alg. 2); <= 0: round(log2(n/64)) */
@@ -78,6 +88,11 @@ typedef struct {
                            prescaling of the experiments, Sec. 4), and apply
                            M = D^{-1/2} M~ D^{-1/2} (M~ the preconditioner of the scaled matrix);
                            a non-positive diagonal entry gives SPAND_E_NOT_SPD.  0 (default): off */
+  int32_t top_fp64_levels; /* FP32 precisions: steps l < top_fp64_levels run in FP64 (default 3:
+                              the root and the two separator levels below it); ignored in FP64 */
+  int64_t hbm_budget_bytes; /* > 0: spand_factor fails with SPAND_E_OOM (and frees what it
+                               allocated) as soon as the factor plus the working panels of a step
+                               would hold more device memory than this; 0 (default): no limit */
 } spand_opts;
 
 void spand_default_opts(spand_opts* opts);
@@ -148,6 +163,37 @@ spand_status spand_plan_step_arrays(spand_plan_t plan, int32_t l, int64_t* key_l
 spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals, const spand_opts* opts,
                           spand_factor_t* out);
 void spand_destroy_factor(spand_factor_t f);
+
+/* Factorization of several separately analysed problems in the same kernel
+ * launches (multi-problem batching, a project addition; each problem is
+ * Alg. 2 on its own matrix, Sec. 1).  plans[count]: plans from spand_analyze
+ * (one problem each, all with opts->skip); vals[count]: device pointers to
+ * each problem's CSR values.  The plans are merged as spand_analyze_batch
+ * would merge them (levels aligned at the leaves; the merged plan is cached
+ * in the context for the next call with the same plans), the values are
+ * concatenated on the device, and one factorization runs over all of them.
+ * out[count] receives one factor handle per problem: every handle views the
+ * same batch factor (released when its last handle is destroyed).  On a
+ * handle, spand_factor_ranks reports that problem's own steps and clusters
+ * (exactly what spand_factor gives it alone), spand_apply and spand_pcg take
+ * that problem's own n x nrhs vectors (they run the whole batch's program with
+ * the other problems' columns zero; use spand_pcg_batch to solve all problems
+ * in one pass), and spand_factor_info reports the whole batch. */
+spand_status spand_factor_batch(spand_ctx_t ctx, int32_t count, const spand_plan_t* plans,
+                                const double* const* vals, const spand_opts* opts,
+                                spand_factor_t* out);
+/* PCG (Sec. 4) for several problems in one pass: factors[count] are handles
+ * from spand_factor_batch (all from the same call) or plain factors; nrhs[i]
+ * columns of b[i] / x[i] (device, n_i x nrhs[i] column-major) per problem.
+ * Handles of one batch factor are solved together: one segmented PCG over the
+ * batch (each (problem, column) an independent CG run, zero columns where a
+ * problem has fewer right-hand sides than the widest); plain factors are
+ * solved one after the other.  iters and relres (host) hold sum(nrhs)
+ * entries, problem i's columns after those of problems 0..i-1.  Returns
+ * SPAND_E_NO_CONVERGENCE if any run reaches maxit (results still written). */
+spand_status spand_pcg_batch(spand_ctx_t ctx, int32_t count, const spand_factor_t* factors,
+                             const int32_t* nrhs, const double* const* b, double* const* x,
+                             double tol, int32_t maxit, int32_t* iters, double* relres);
 
 /* Per-cluster sparsification record of step l: a (size before), k (coupling
  * width), r (eps rank), r2 (superfine rank, = r otherwise); -1 for interiors

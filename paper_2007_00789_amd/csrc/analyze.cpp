@@ -570,17 +570,17 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
   parallel_for(D + 1, host_threads(P.nnz), [&](int l) { build_numeric_lists(P, l); });
 }
 
-void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
+void merge_plans(Plan& M, const std::vector<const Plan*>& parts, int skip) {
   const int np = (int)parts.size();
   int D = 0;
-  for (const Plan& q : parts) D = std::max(D, q.depth);
+  for (const Plan* q : parts) D = std::max(D, q->depth);
   M.depth = D;
   M.skip = skip;
-  M.dim = parts.empty() ? 0 : parts[0].dim;
+  M.dim = parts.empty() ? 0 : parts[0]->dim;
   std::vector<int64_t> voff(np + 1, 0), eoff(np + 1, 0);
   for (int i = 0; i < np; ++i) {
-    voff[i + 1] = voff[i] + parts[i].n;
-    eoff[i + 1] = eoff[i] + parts[i].nnz;
+    voff[i + 1] = voff[i] + parts[i]->n;
+    eoff[i + 1] = eoff[i] + parts[i]->nnz;
   }
   M.n = voff[np];
   M.nnz = eoff[np];
@@ -593,7 +593,7 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
   M.seg_off = voff;
   M.seg_id.assign(M.n, 0);
   for (int i = 0; i < np; ++i) {
-    const Plan& q = parts[i];
+    const Plan& q = *parts[i];
     const int shift = D - q.depth;
     for (int64_t v = 0; v < q.n; ++v) {
       M.rowptr.push_back(eoff[i] + q.rowptr[v + 1]);
@@ -609,7 +609,7 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
   M.steps.assign(D + 1, StepPlan());
   std::vector<std::vector<int32_t>> ioff(D + 1, std::vector<int32_t>(np, 0)),
       foff(D + 1, std::vector<int32_t>(np, 0));
-  auto own = [&](int i, int lm) { return lm - (D - parts[i].depth); };   // problem step
+  auto own = [&](int i, int lm) { return lm - (D - parts[i]->depth); };   // problem step
   for (int lm = 0; lm <= D; ++lm) {
     StepPlan& S = M.steps[lm];
     S.l = lm;
@@ -619,15 +619,19 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
       ioff[lm][i] = nI;
       foff[lm][i] = nF;
       if (l < 0) continue;
-      nI += parts[i].steps[l].nI;
-      nF += parts[i].steps[l].nc - parts[i].steps[l].nI;
+      nI += parts[i]->steps[l].nI;
+      nF += parts[i]->steps[l].nc - parts[i]->steps[l].nI;
     }
     S.nI = nI;
     S.nc = nI + nF;
     S.sparsified = lm >= 1 && lm <= D - skip;
+    S.seg_ioff = ioff[lm];
+    S.seg_foff = foff[lm];
   }
+  M.seg_depth.resize(np);
+  for (int i = 0; i < np; ++i) M.seg_depth[i] = parts[i]->depth;
   auto map = [&](int lm, int i, int c) {
-    const StepPlan& q = parts[i].steps[own(i, lm)];
+    const StepPlan& q = parts[i]->steps[own(i, lm)];
     return c < q.nI ? ioff[lm][i] + c : M.steps[lm].nI + foff[lm][i] + (c - q.nI);
   };
   for (int lm = 0; lm <= D; ++lm) {
@@ -641,11 +645,11 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
     for (int i = 0; i < np; ++i) {
       const int l = own(i, lm);
       if (l < 0) continue;
-      const StepPlan& q = parts[i].steps[l];
+      const StepPlan& q = parts[i]->steps[l];
       for (int c = 0; c < q.nc; ++c) {
         const int x = map(lm, i, c);
         owner[x] = {i, c};
-        S.key_lvl[x] = q.key_lvl[c] + (D - parts[i].depth);
+        S.key_lvl[x] = q.key_lvl[c] + (D - parts[i]->depth);
         S.key_prefix[x] = q.key_prefix[c];
         S.colour[x] = q.colour[c];
         if (lm > 0 && !q.parent.empty() && q.parent[c] >= 0 && l > 0)
@@ -656,7 +660,7 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
     S.adj.clear();
     for (int x = 0; x < nc; ++x) {
       const auto [i, c] = owner[x];
-      const StepPlan& q = parts[i].steps[own(i, lm)];
+      const StepPlan& q = parts[i]->steps[own(i, lm)];
       for (int64_t e = q.adj_ptr[c]; e < q.adj_ptr[c + 1]; ++e) S.adj.push_back(map(lm, i, q.adj[e]));
       S.adj_ptr[x + 1] = (int64_t)S.adj.size();
     }
@@ -671,7 +675,7 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
       S.child.clear();
       for (int x = 0; x < nc; ++x) {
         const auto [i, c] = owner[x];
-        const StepPlan& q = parts[i].steps[own(i, lm)];
+        const StepPlan& q = parts[i]->steps[own(i, lm)];
         if (!q.child_ptr.empty())
           for (int64_t e = q.child_ptr[c]; e < q.child_ptr[c + 1]; ++e)
             S.child.push_back(map(lm + 1, i, q.child[e]));
@@ -682,7 +686,7 @@ void merge_plans(Plan& M, std::vector<Plan>& parts, int skip) {
       S.verts.clear();
       for (int x = 0; x < nc; ++x) {
         const auto [i, c] = owner[x];
-        const StepPlan& q = parts[i].steps[parts[i].depth];
+        const StepPlan& q = parts[i]->steps[parts[i]->depth];
         for (int64_t e = q.vert_ptr[c]; e < q.vert_ptr[c + 1]; ++e)
           S.verts.push_back((int32_t)(q.verts[e] + voff[i]));
         S.vert_ptr[x + 1] = (int64_t)S.verts.size();

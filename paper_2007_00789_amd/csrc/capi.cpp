@@ -11,16 +11,38 @@
 #include "apply.h"
 #include "runtime.h"
 
-struct spand_ctx_s { spand::Ctx c; };
 // idle device memory a context keeps for the next factorization or solve
 constexpr size_t kPoolIdleBytes = size_t(16) << 30;
-struct spand_plan_s { spand::Plan p; };
-struct spand_factor_s {
+struct spand_plan_s {
+  spand::Plan p;
+  uint64_t id = 0;   // unique per plan object (keys the context's merged-plan cache)
+};
+// A numeric factor: one problem's, or one batch's (the problems of a
+// spand_factor_batch call), with the plan it was computed on.
+struct FactorCore {
   spand::FactorObj f;
   spand::DevBuf vals;        // copy of A's values (SpMV inside PCG)
   double* d_vals = nullptr;  // = vals.p
   spand::DevBuf dscale;      // prescale: D^{-1/2} (n)
   int device = 0;
+  std::shared_ptr<spand::Plan> merged;   // batch factors: the merged plan (f.plan points to it)
+};
+// A factor handle: the whole core (seg < 0), or problem seg of a batch core.
+struct spand_factor_s {
+  std::shared_ptr<FactorCore> core;
+  int seg = -1;
+  // seg >= 0: the problem's own rows, depth and clusters per own step
+  int64_t n = 0, row0 = 0;
+  int depth = 0;
+  std::vector<int32_t> nI, nc;
+  spand::FactorObj& F() { return core->f; }
+};
+struct spand_ctx_s {
+  spand::Ctx c;
+  // merged plan of the last spand_factor_batch call and the plan ids it was built from
+  std::vector<uint64_t> batch_key;
+  std::shared_ptr<spand::Plan> batch_plan;
+  spand::DevBuf vtmp[2];    // handles of a batch factor: problem vectors embedded in batch vectors
 };
 
 namespace spand {
@@ -30,6 +52,8 @@ void run_pcg(Ctx& C, FactorObj& F, const double* d_vals, int32_t nrhs, const dou
 }  // namespace spand
 
 namespace {
+
+std::atomic<uint64_t> g_plan_ids{1};
 
 template <class F>
 spand_status guarded(spand_ctx_t ctx, F&& fn) {
@@ -61,6 +85,8 @@ void check_opts(const spand_opts* o) {
       o->qr_xcd_local > 1 || o->qr_regs < 0 || o->qr_regs > 1 || o->qr_lds_cols < 0)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
   if (o->prescale < 0 || o->prescale > 1) throw Error(SPAND_E_INVALID, "prescale must be 0 or 1");
+  if (o->top_fp64_levels < 0) throw Error(SPAND_E_INVALID, "top_fp64_levels must be >= 0");
+  if (o->hbm_budget_bytes < 0) throw Error(SPAND_E_INVALID, "hbm_budget_bytes must be >= 0");
 }
 
 // device copies of the pattern and of the leaf assembly map, made on first use
@@ -105,6 +131,8 @@ void spand_default_opts(spand_opts* o) {
   o->qr_regs = 0;
   o->qr_lds_cols = 0;
   o->prescale = 0;
+  o->top_fp64_levels = 3;
+  o->hbm_budget_bytes = 0;
 }
 
 const char* spand_status_string(spand_status s) {
@@ -134,6 +162,7 @@ spand_status spand_create(spand_ctx_t* out, int device, void* stream) {
     SPAND_HIP(hipSetDevice(device));
     ctx->c.device = device;
     ctx->c.pool = std::make_shared<spand::MemPool>(device, kPoolIdleBytes);
+    ctx->vtmp[0].pool = ctx->vtmp[1].pool = ctx->c.pool;
     if (stream) {
       ctx->c.stream = static_cast<hipStream_t>(stream);
     } else {
@@ -165,6 +194,7 @@ spand_status spand_analyze(spand_ctx_t ctx, int64_t n, const int64_t* rowptr, co
   if (!out) return SPAND_E_INVALID;
   *out = nullptr;
   auto plan = std::make_unique<spand_plan_s>();
+  plan->id = g_plan_ids.fetch_add(1);
   spand_status st = guarded(ctx, [&] {
     using spand::Error;
     check_opts(opts);
@@ -197,6 +227,7 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
   if (!out) return SPAND_E_INVALID;
   *out = nullptr;
   auto plan = std::make_unique<spand_plan_s>();
+  plan->id = g_plan_ids.fetch_add(1);
   spand_status st = guarded(ctx, [&] {
     using spand::Error;
     check_opts(opts);
@@ -244,7 +275,9 @@ spand_status spand_analyze_batch(spand_ctx_t ctx, int32_t count, const int64_t* 
     for (auto& e : errs)
       if (e) std::rethrow_exception(e);
     spand::Plan& P = plan->p;
-    spand::merge_plans(P, parts, opts->skip);
+    std::vector<const spand::Plan*> pp;
+    for (const spand::Plan& q : parts) pp.push_back(&q);
+    spand::merge_plans(P, pp, opts->skip);
     spand::build_leaf_map(P);
   });
   if (st == SPAND_OK) *out = plan.release();
@@ -312,6 +345,96 @@ spand_status spand_plan_step_arrays(spand_plan_t plan, int32_t l, int64_t* key_l
   return SPAND_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Numeric factorization of plan P with the device values vals (nnz of P, in
+// its CSR order) into a new core.
+std::shared_ptr<FactorCore> factor_core(spand_ctx_t ctx, spand::Plan& P, const double* vals,
+                                        const spand_opts* opts, bool copy_vals) {
+  auto f = std::make_shared<FactorCore>();
+  SPAND_HIP(hipSetDevice(ctx->c.device));
+  f->device = ctx->c.device;
+  upload_plan(P, ctx->c.device);
+  const int64_t nnz = P.nnz;
+  f->vals.pool = ctx->c.pool;
+  f->d_vals = static_cast<double*>(f->vals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
+  if (copy_vals)
+    SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->c.stream));
+  // prescale: the factorization reads D^{-1/2} A D^{-1/2}; PCG keeps A
+  const double* fvals = f->d_vals;
+  spand::DevBuf svals;
+  double* dsc = nullptr;
+  if (opts->prescale) {
+    const int64_t n = P.n;
+    f->dscale.pool = ctx->c.pool;
+    svals.pool = ctx->c.pool;
+    dsc = static_cast<double*>(f->dscale.ensure(std::max<int64_t>(n, 1) * sizeof(double)));
+    double* sv = static_cast<double*>(svals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
+    int32_t* bad = static_cast<int32_t*>(ctx->c.ints.ensure(sizeof(int32_t)));
+    spand::launch_prescale(P.d_rowptr, P.d_colind, f->d_vals, n, dsc, sv, bad, ctx->c.stream);
+    int32_t hbad = 0;
+    SPAND_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->c.stream));
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    if (hbad != INT32_MAX)
+      throw spand::Error(SPAND_E_NOT_SPD, "prescale: diagonal entry of row " + std::to_string(hbad) +
+                                              " is not positive");
+    fvals = sv;
+  }
+  try {
+    spand::run_factor(ctx->c, P, fvals, *opts, f->f);
+  } catch (const spand::CoopPlacement&) {
+    // a cooperative QR group was not on one XCD: redo with single-workgroup QRs
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    auto g = std::make_shared<FactorCore>();
+    g->device = f->device;
+    std::swap(g->vals.p, f->vals.p);
+    std::swap(g->vals.bytes, f->vals.bytes);
+    std::swap(g->vals.pool, f->vals.pool);
+    std::swap(g->d_vals, f->d_vals);
+    std::swap(g->dscale.p, f->dscale.p);
+    std::swap(g->dscale.bytes, f->dscale.bytes);
+    std::swap(g->dscale.pool, f->dscale.pool);
+    f = std::move(g);
+    spand_opts o2 = *opts;
+    o2.qr_group = -1;
+    spand::run_factor(ctx->c, P, fvals, o2, f->f);
+    f->f.opts = *opts;
+  }
+  f->f.dscale = dsc;
+  SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+  ctx->c.prof.resolve();
+  f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();
+  return f;
+}
+
+// Batch vectors for the handle of one problem: its n x nrhs columns embedded
+// at its rows of an N x nrhs zero buffer (and copied back).
+void embed(spand_ctx_t ctx, int slot, const spand_factor_s* h, int32_t nrhs, const double* x,
+           double** X) {
+  const int64_t N = h->core->f.plan->n;
+  *X = static_cast<double*>(ctx->vtmp[slot].ensure(std::max<int64_t>(N * nrhs, 1) * sizeof(double)));
+  SPAND_HIP(hipMemsetAsync(*X, 0, N * nrhs * sizeof(double), ctx->c.stream));
+  if (x)
+    SPAND_HIP(hipMemcpy2DAsync(*X + h->row0, N * sizeof(double), x, h->n * sizeof(double),
+                               h->n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, ctx->c.stream));
+}
+void extract(spand_ctx_t ctx, const spand_factor_s* h, int32_t nrhs, const double* X, double* y) {
+  const int64_t N = h->core->f.plan->n;
+  SPAND_HIP(hipMemcpy2DAsync(y, h->n * sizeof(double), X + h->row0, N * sizeof(double),
+                             h->n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, ctx->c.stream));
+}
+
+void check_ready(const spand_factor_s* f) {
+  if (!f->core->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
+}
+
+}  // namespace
+
+extern "C" {
+
 spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals, const spand_opts* opts,
                           spand_factor_t* out) {
   if (!ctx || !plan || !out) return SPAND_E_INVALID;
@@ -322,97 +445,135 @@ spand_status spand_factor(spand_ctx_t ctx, spand_plan_t plan, const double* vals
     if (!vals) throw spand::Error(SPAND_E_INVALID, "vals is NULL");
     if (opts->skip != plan->p.skip)
       throw spand::Error(SPAND_E_INVALID, "skip differs from the one given to spand_analyze");
-    SPAND_HIP(hipSetDevice(ctx->c.device));
-    f->device = ctx->c.device;
-    upload_plan(plan->p, ctx->c.device);
-    const int64_t nnz = plan->p.nnz;
-    f->vals.pool = ctx->c.pool;
-    f->d_vals = static_cast<double*>(f->vals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
-    SPAND_HIP(hipMemcpyAsync(f->d_vals, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice,
-                             ctx->c.stream));
-    // prescale: the factorization reads D^{-1/2} A D^{-1/2}; PCG keeps A
-    const double* fvals = f->d_vals;
-    spand::DevBuf svals;
-    double* dsc = nullptr;
-    if (opts->prescale) {
-      const int64_t n = plan->p.n;
-      f->dscale.pool = ctx->c.pool;
-      svals.pool = ctx->c.pool;
-      dsc = static_cast<double*>(f->dscale.ensure(std::max<int64_t>(n, 1) * sizeof(double)));
-      double* sv = static_cast<double*>(svals.ensure(std::max<int64_t>(nnz, 1) * sizeof(double)));
-      int32_t* bad = static_cast<int32_t*>(ctx->c.ints.ensure(sizeof(int32_t)));
-      spand::launch_prescale(plan->p.d_rowptr, plan->p.d_colind, f->d_vals, n, dsc, sv, bad,
-                             ctx->c.stream);
-      int32_t hbad = 0;
-      SPAND_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->c.stream));
-      SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
-      if (hbad != INT32_MAX)
-        throw spand::Error(SPAND_E_NOT_SPD, "prescale: diagonal entry of row " + std::to_string(hbad) +
-                                                " is not positive");
-      fvals = sv;
-    }
-    try {
-      spand::run_factor(ctx->c, plan->p, fvals, *opts, f->f);
-    } catch (const spand::CoopPlacement&) {
-      // a cooperative QR group was not on one XCD: redo with single-workgroup QRs
-      SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
-      auto g = std::make_unique<spand_factor_s>();
-      g->device = f->device;
-      std::swap(g->vals.p, f->vals.p);
-      std::swap(g->vals.bytes, f->vals.bytes);
-      std::swap(g->vals.pool, f->vals.pool);
-      std::swap(g->d_vals, f->d_vals);
-      std::swap(g->dscale.p, f->dscale.p);
-      std::swap(g->dscale.bytes, f->dscale.bytes);
-      std::swap(g->dscale.pool, f->dscale.pool);
-      f = std::move(g);
-      spand_opts o2 = *opts;
-      o2.qr_group = -1;
-      spand::run_factor(ctx->c, plan->p, fvals, o2, f->f);
-      f->f.opts = *opts;
-    }
-    f->f.dscale = dsc;
-    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
-    ctx->c.prof.resolve();
-    f->f.stats.factor_bytes = (int64_t)f->f.arena.bytes_used();
+    f->core = factor_core(ctx, plan->p, vals, opts, true);
   });
   if (st == SPAND_OK) *out = f.release();
   return st;
 }
 
+spand_status spand_factor_batch(spand_ctx_t ctx, int32_t count, const spand_plan_t* plans,
+                                const double* const* vals, const spand_opts* opts,
+                                spand_factor_t* out) {
+  if (!ctx || count < 1 || !plans || !vals || !out) return SPAND_E_INVALID;
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  std::vector<std::unique_ptr<spand_factor_s>> hs((size_t)count);
+  spand_status st = guarded(ctx, [&] {
+    using spand::Error;
+    check_opts(opts);
+    std::vector<uint64_t> key((size_t)count);
+    for (int i = 0; i < count; ++i) {
+      if (!plans[i] || !vals[i]) throw Error(SPAND_E_INVALID, "NULL plan or values of problem " + std::to_string(i));
+      const spand::Plan& q = plans[i]->p;
+      if (q.seg_off.size() != 2)
+        throw Error(SPAND_E_INVALID, "problem " + std::to_string(i) + ": plan holds several problems");
+      if (q.skip != opts->skip)
+        throw Error(SPAND_E_INVALID, "problem " + std::to_string(i) + ": skip differs from opts");
+      key[i] = plans[i]->id;
+    }
+    if (!ctx->batch_plan || ctx->batch_key != key) {
+      auto M = std::make_shared<spand::Plan>();
+      std::vector<const spand::Plan*> pp((size_t)count);
+      for (int i = 0; i < count; ++i) pp[i] = &plans[i]->p;
+      spand::merge_plans(*M, pp, opts->skip);
+      spand::build_leaf_map(*M);
+      ctx->batch_plan = std::move(M);
+      ctx->batch_key = std::move(key);
+    }
+    std::shared_ptr<spand::Plan> M = ctx->batch_plan;
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    // the problems' values, concatenated on the device in the merged CSR order
+    spand::DevBuf cat;
+    cat.pool = ctx->c.pool;
+    double* dv = static_cast<double*>(cat.ensure(std::max<int64_t>(M->nnz, 1) * sizeof(double)));
+    int64_t off = 0;
+    for (int i = 0; i < count; ++i) {
+      const int64_t nz = plans[i]->p.nnz;
+      SPAND_HIP(hipMemcpyAsync(dv + off, vals[i], nz * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->c.stream));
+      off += nz;
+    }
+    std::shared_ptr<FactorCore> core = factor_core(ctx, *M, dv, opts, true);
+    core->merged = M;
+    for (int i = 0; i < count; ++i) {
+      const spand::Plan& q = plans[i]->p;
+      auto h = std::make_unique<spand_factor_s>();
+      h->core = core;
+      h->seg = i;
+      h->n = q.n;
+      h->row0 = M->seg_off[i];
+      h->depth = q.depth;
+      for (int l = 0; l <= q.depth; ++l) {
+        h->nI.push_back(q.steps[l].nI);
+        h->nc.push_back(q.steps[l].nc);
+      }
+      hs[i] = std::move(h);
+    }
+  });
+  if (st == SPAND_OK)
+    for (int i = 0; i < count; ++i) out[i] = hs[i].release();
+  return st;
+}
+
 void spand_destroy_factor(spand_factor_t f) {
   if (!f) return;
-  (void)hipSetDevice(f->device);
+  (void)hipSetDevice(f->core ? f->core->device : 0);
   delete f;
 }
 
 spand_status spand_factor_ranks(spand_factor_t f, int32_t l, int32_t* a, int32_t* k, int32_t* r,
                                 int32_t* r2) {
-  if (!f || l < 0 || l >= (int32_t)f->f.steps.size()) return SPAND_E_INVALID;
-  const spand::StepRec& R = f->f.steps[l];
-  const int nc = (int)R.r.size();
-  for (int c = 0; c < nc; ++c) {
-    const bool sp = R.r[c] >= 0;
-    if (a) a[c] = sp ? R.n0[c] : -1;
-    if (k) k[c] = R.k[c];
-    if (r) r[c] = R.r[c];
-    if (r2) r2[c] = R.r2[c];
+  if (!f) return SPAND_E_INVALID;
+  const spand::FactorObj& F = f->core->f;
+  if (f->seg < 0) {
+    if (l < 0 || l >= (int32_t)F.steps.size()) return SPAND_E_INVALID;
+    const spand::StepRec& R = F.steps[l];
+    const int nc = (int)R.r.size();
+    for (int c = 0; c < nc; ++c) {
+      const bool sp = R.r[c] >= 0;
+      if (a) a[c] = sp ? R.n0[c] : -1;
+      if (k) k[c] = R.k[c];
+      if (r) r[c] = R.r[c];
+      if (r2) r2[c] = R.r2[c];
+    }
+    return SPAND_OK;
+  }
+  // one problem of a batch: its own step l is batch step l + D - D_i, its
+  // clusters sit at its offsets among the batch step's interiors and interfaces
+  if (l < 0 || l > f->depth) return SPAND_E_INVALID;
+  const int lm = l + (F.plan->depth - f->depth);
+  const spand::StepRec& R = F.steps[lm];
+  const spand::StepPlan& S = F.plan->steps[lm];
+  const int own_nI = f->nI[l], own_nc = f->nc[l];
+  for (int c = 0; c < own_nc; ++c) {
+    const int x = c < own_nI ? S.seg_ioff[f->seg] + c : S.nI + S.seg_foff[f->seg] + (c - own_nI);
+    const bool sp = R.r[x] >= 0;
+    if (a) a[c] = sp ? R.n0[x] : -1;
+    if (k) k[c] = R.k[x];
+    if (r) r[c] = R.r[x];
+    if (r2) r2[c] = R.r2[x];
   }
   return SPAND_OK;
 }
 
 spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st) {
   if (!f || !st) return SPAND_E_INVALID;
-  *st = f->f.stats;
+  *st = f->core->f.stats;
   return SPAND_OK;
 }
 
 spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y) {
   if (!ctx || !f || nrhs <= 0 || !x || !y) return SPAND_E_INVALID;
   return guarded(ctx, [&] {
-    if (!f->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
+    check_ready(f);
     SPAND_HIP(hipSetDevice(ctx->c.device));
-    spand::run_apply(ctx->c, f->f, nrhs, x, y);
+    if (f->seg < 0) {
+      spand::run_apply(ctx->c, f->F(), nrhs, x, y);
+    } else {
+      double* X = nullptr;
+      embed(ctx, 0, f, nrhs, x, &X);
+      spand::run_apply(ctx->c, f->F(), nrhs, X, X);
+      extract(ctx, f, nrhs, X, y);
+    }
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();
   });
@@ -424,13 +585,107 @@ spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const do
     return SPAND_E_INVALID;
   bool conv = false;
   spand_status st = guarded(ctx, [&] {
-    if (!f->f.prog) throw spand::Error(SPAND_E_STATE, "factor was stopped early (debug)");
+    check_ready(f);
     SPAND_HIP(hipSetDevice(ctx->c.device));
-    spand::run_pcg(ctx->c, f->f, f->d_vals, nrhs, b, x, tol, maxit, iters, relres, &conv);
+    if (f->seg < 0) {
+      spand::run_pcg(ctx->c, f->F(), f->core->d_vals, nrhs, b, x, tol, maxit, iters, relres, &conv);
+    } else {
+      // the batch's segmented PCG with this problem's columns only (the
+      // others' right-hand sides are zero, so their runs stop at once)
+      const int nseg = (int)f->core->f.plan->seg_off.size() - 1;
+      double *B = nullptr, *X = nullptr;
+      embed(ctx, 0, f, nrhs, b, &B);
+      embed(ctx, 1, f, nrhs, nullptr, &X);
+      std::vector<int32_t> it((size_t)nseg * nrhs);
+      std::vector<double> rr((size_t)nseg * nrhs);
+      spand::run_pcg(ctx->c, f->F(), f->core->d_vals, nrhs, B, X, tol, maxit, it.data(), rr.data(),
+                     &conv);
+      extract(ctx, f, nrhs, X, x);
+      for (int c = 0; c < nrhs; ++c) {
+        iters[c] = it[(size_t)f->seg * nrhs + c];
+        relres[c] = rr[(size_t)f->seg * nrhs + c];
+      }
+    }
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();
   });
   if (st == SPAND_OK && !conv) {
+    ctx->c.last_error = "PCG did not converge within maxit";
+    return SPAND_E_NO_CONVERGENCE;
+  }
+  return st;
+}
+
+spand_status spand_pcg_batch(spand_ctx_t ctx, int32_t count, const spand_factor_t* factors,
+                             const int32_t* nrhs, const double* const* b, double* const* x,
+                             double tol, int32_t maxit, int32_t* iters, double* relres) {
+  if (!ctx || count < 1 || !factors || !nrhs || !b || !x || !iters || !relres || maxit < 0 ||
+      !(tol > 0))
+    return SPAND_E_INVALID;
+  bool all_conv = true;
+  spand_status st = guarded(ctx, [&] {
+    using spand::Error;
+    std::vector<int64_t> col0((size_t)count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      if (!factors[i] || nrhs[i] < 1 || !b[i] || !x[i])
+        throw Error(SPAND_E_INVALID, "bad factor or vectors of problem " + std::to_string(i));
+      check_ready(factors[i]);
+      col0[i + 1] = col0[i] + nrhs[i];
+    }
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    std::vector<char> done((size_t)count, 0);
+    for (int i = 0; i < count; ++i) {
+      if (done[i]) continue;
+      spand_factor_s* fi = factors[i];
+      if (fi->seg < 0) {   // a plain factor: its own PCG
+        bool conv = false;
+        spand::run_pcg(ctx->c, fi->F(), fi->core->d_vals, nrhs[i], b[i], x[i], tol, maxit,
+                       iters + col0[i], relres + col0[i], &conv);
+        all_conv = all_conv && conv;
+        done[i] = 1;
+        continue;
+      }
+      // every handle of this batch core: one segmented PCG over the batch
+      std::vector<int> members;
+      int32_t w = 0;
+      for (int j = i; j < count; ++j)
+        if (!done[j] && factors[j]->core == fi->core) {
+          members.push_back(j);
+          w = std::max(w, nrhs[j]);
+          done[j] = 1;
+        }
+      const int64_t N = fi->core->f.plan->n;
+      const int nseg = (int)fi->core->f.plan->seg_off.size() - 1;
+      double* B = static_cast<double*>(ctx->vtmp[0].ensure(std::max<int64_t>(N * w, 1) * sizeof(double)));
+      double* X = static_cast<double*>(ctx->vtmp[1].ensure(std::max<int64_t>(N * w, 1) * sizeof(double)));
+      SPAND_HIP(hipMemsetAsync(B, 0, N * w * sizeof(double), ctx->c.stream));
+      for (int j : members) {
+        const spand_factor_s* h = factors[j];
+        SPAND_HIP(hipMemcpy2DAsync(B + h->row0, N * sizeof(double), b[j], h->n * sizeof(double),
+                                   h->n * sizeof(double), nrhs[j], hipMemcpyDeviceToDevice,
+                                   ctx->c.stream));
+      }
+      std::vector<int32_t> it((size_t)nseg * w);
+      std::vector<double> rr((size_t)nseg * w);
+      bool conv = false;
+      spand::run_pcg(ctx->c, fi->F(), fi->core->d_vals, w, B, X, tol, maxit, it.data(), rr.data(),
+                     &conv);
+      all_conv = all_conv && conv;
+      for (int j : members) {
+        const spand_factor_s* h = factors[j];
+        SPAND_HIP(hipMemcpy2DAsync(x[j], h->n * sizeof(double), X + h->row0, N * sizeof(double),
+                                   h->n * sizeof(double), nrhs[j], hipMemcpyDeviceToDevice,
+                                   ctx->c.stream));
+        for (int c = 0; c < nrhs[j]; ++c) {
+          iters[col0[j] + c] = it[(size_t)h->seg * w + c];
+          relres[col0[j] + c] = rr[(size_t)h->seg * w + c];
+        }
+      }
+    }
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
+  });
+  if (st == SPAND_OK && !all_conv) {
     ctx->c.last_error = "PCG did not converge within maxit";
     return SPAND_E_NO_CONVERGENCE;
   }
@@ -475,8 +730,8 @@ spand_status spand_profile_entry(spand_ctx_t ctx, int32_t i, char* name, int32_t
 
 spand_status spand_debug_block(spand_factor_t f, int32_t ci, int32_t cj, double* out, int32_t* rows,
                                int32_t* cols) {
-  if (!f || f->f.stopped_at < 0 || !rows || !cols) return SPAND_E_STATE;
-  const spand::FactorObj& F = f->f;
+  if (!f || f->seg >= 0 || f->core->f.stopped_at < 0 || !rows || !cols) return SPAND_E_STATE;
+  const spand::FactorObj& F = f->core->f;
   const spand::StepPlan& st = F.plan->steps[F.stopped_at];
   if (ci < 0 || cj < 0 || ci >= st.nc || cj >= st.nc) return SPAND_E_INVALID;
   const int32_t* b = st.adj.data() + st.adj_ptr[ci];

@@ -1217,6 +1217,17 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
 
     if (apb) apb->publish(l);
 
+    if (o.hbm_budget_bytes > 0) {
+      // device memory held now: the factor so far, both row-panel buffers,
+      // the scaling temporaries and the descriptor arenas
+      const int64_t held = (int64_t)(F.arena.bytes_reserved() + F.meta.bytes_reserved() +
+                                     C.panels[0].bytes + C.panels[1].bytes + C.temp.bytes);
+      if (held > o.hbm_budget_bytes)
+        throw Error(SPAND_E_OOM, "factorization needs more than hbm_budget_bytes (" +
+                                     std::to_string(held) + " bytes held after step " +
+                                     std::to_string(l) + ")");
+    }
+
     if (stop_here) {
       F.stopped_at = l;
       F.dbg_layout = lay;

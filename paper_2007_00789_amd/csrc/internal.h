@@ -68,6 +68,10 @@ struct StepPlan {
     int64_t e, ee;
   };
   std::vector<MergeCopy> merge;
+  // batch plans: per problem, the offsets of its interiors among the step's
+  // interiors and of its interfaces among the step's interfaces (problems not
+  // present at this step keep the running offset)
+  std::vector<int32_t> seg_ioff, seg_foff;
 };
 
 struct PanelLayout {
@@ -100,6 +104,7 @@ struct Plan {
   // seg_off[s+1]-1 (one segment for a single problem)
   std::vector<int64_t> seg_off;
   std::vector<int32_t> seg_id;         // segment of every row (batch plans only)
+  std::vector<int32_t> seg_depth;      // batch plans: each problem's own depth
   int32_t* d_seg_id = nullptr;
   int64_t* d_seg_off = nullptr;
   ~Plan();
@@ -112,7 +117,7 @@ void analyze_plan(Plan& P, const int64_t* rowptr, const int32_t* colind, const d
 // l + (D - D_i) with D the largest depth, so every problem keeps its own
 // levels, and the rule 1 <= l <= D_i - skip for sparsified steps becomes
 // 1 <= l' <= D - skip for all of them.
-void merge_plans(Plan& M, std::vector<Plan>& parts, int skip);
+void merge_plans(Plan& M, const std::vector<const Plan*>& parts, int skip);
 // destination of every CSR value in the leaf-step row panels
 void build_leaf_map(Plan& P);
 // Coordinates for a matrix given without any (coordinate-free analysis): for

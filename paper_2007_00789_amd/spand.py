@@ -10,8 +10,10 @@ raises OSError when it is missing, so no caller can fall back silently.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -21,7 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libspand.so")
 SPAND_OK = 0
 FIRST_ORDER, SECOND_ORDER, SUPERFINE = 1, 2, 3
 SCHEMES = {"FO": FIRST_ORDER, "SO": SECOND_ORDER, "SF": SUPERFINE}
-FP64 = 0
+FP64, FP32, FP32_BF16 = 0, 1, 2
+PRECISIONS = {"FP64": FP64, "FP32": FP32, "FP32_BF16": FP32_BF16}
 
 STATUS = {
     0: "SPAND_OK", -1: "SPAND_E_INVALID", -2: "SPAND_E_NOT_SYMMETRIC", -3: "SPAND_E_NOT_SPD",
@@ -35,7 +38,8 @@ class Opts(C.Structure):
                 ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32),
                 ("qr_group", C.c_int32), ("qr_list_cap", C.c_int32),
                 ("qr_xcd_local", C.c_int32), ("qr_regs", C.c_int32), ("qr_lds_cols", C.c_int32),
-                ("prescale", C.c_int32)]
+                ("prescale", C.c_int32), ("top_fp64_levels", C.c_int32),
+                ("hbm_budget_bytes", C.c_int64)]
 
 
 class FactorStats(C.Structure):
@@ -76,6 +80,10 @@ SIGNATURES = {
                                          _I64P, _I32P]),
     "spand_factor": (C.c_int, [_P, _P, _P, C.POINTER(Opts), C.POINTER(_P)]),
     "spand_destroy_factor": (None, [_P]),
+    "spand_factor_batch": (C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(Opts),
+                                     C.POINTER(_P)]),
+    "spand_pcg_batch": (C.c_int, [_P, C.c_int32, C.POINTER(_P), _I32P, C.POINTER(_P), C.POINTER(_P),
+                                  C.c_double, C.c_int32, _I32P, _DP]),
     "spand_factor_ranks": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I32P, _I32P]),
     "spand_factor_info": (C.c_int, [_P, C.POINTER(FactorStats)]),
     "spand_apply": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
@@ -96,6 +104,22 @@ SIGNATURES = {
 }
 
 _lib = None
+
+# Live library objects, released in dependency order (factors, plans, servers,
+# then contexts) before the interpreter tears down the HIP runtime, so that no
+# device memory or stream is released from a finalizer running after it.
+_live = {"factor": weakref.WeakSet(), "plan": weakref.WeakSet(), "server": weakref.WeakSet(),
+         "ctx": weakref.WeakSet()}
+
+
+def release_all():
+    """Destroy every live factor, plan, server and context (also run at exit)."""
+    for kind in ("factor", "plan", "server", "ctx"):
+        for obj in list(_live[kind]):
+            obj.close()
+
+
+atexit.register(release_all)
 
 
 def load(path: str = LIB_PATH):
@@ -128,14 +152,15 @@ def _np(a, dtype):
 
 
 def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
-              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_regs=0, qr_lds_cols=0, prescale=0) -> Opts:
+              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_regs=0, qr_lds_cols=0, prescale=0,
+              top_fp64_levels=None, hbm_budget_bytes=0) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
     o.depth = int(depth)
     o.skip = int(skip)
     o.eps = float(eps)
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    o.precision = int(precision)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.debug_stop_step = int(debug_stop_step)
     o.qr_group = int(qr_group)
     o.qr_list_cap = int(qr_list_cap)
@@ -143,6 +168,9 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     o.qr_regs = int(qr_regs)
     o.qr_lds_cols = int(qr_lds_cols)
     o.prescale = int(prescale)
+    if top_fp64_levels is not None:
+        o.top_fp64_levels = int(top_fp64_levels)
+    o.hbm_budget_bytes = int(hbm_budget_bytes)
     return o
 
 
@@ -156,6 +184,7 @@ class Context:
         if st != SPAND_OK:
             raise SpandError(st, "spand_create failed")
         self.h = h
+        _live["ctx"].add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -192,6 +221,35 @@ class Context:
         h = C.c_void_p()
         self._check(self.lib.spand_factor(self.h, plan.h, _ptr(vals), C.byref(opts), C.byref(h)))
         return Factor(self.lib, h, plan)
+
+    def factor_batch(self, plans, vals, opts: Opts) -> list:
+        """spand_factor_batch: plans from analyze() (one problem each) and one
+        device buffer of CSR values per problem; returns one Factor handle per
+        problem, all viewing the same batch factor."""
+        cnt = len(plans)
+        hp = (_P * cnt)(*[p.h for p in plans])
+        vp = (_P * cnt)(*[_ptr(v) for v in vals])
+        out = (_P * cnt)()
+        self._check(self.lib.spand_factor_batch(self.h, cnt, hp, vp, C.byref(opts), out))
+        return [Factor(self.lib, C.c_void_p(out[i]), plans[i]) for i in range(cnt)]
+
+    def pcg_batch(self, facs, nrhs, bs, xs, tol=1e-10, maxit=1000, check=True):
+        """spand_pcg_batch: per problem i, nrhs[i] columns of bs[i] / xs[i]
+        (device buffers); returns per problem (iters, relres) arrays."""
+        cnt = len(facs)
+        nr = np.ascontiguousarray(nrhs, dtype=np.int32)
+        tot = int(nr.sum())
+        it = np.zeros(tot, dtype=np.int32)
+        rr = np.zeros(tot, dtype=np.float64)
+        fp = (_P * cnt)(*[f.h for f in facs])
+        bp = (_P * cnt)(*[_ptr(b) for b in bs])
+        xp = (_P * cnt)(*[_ptr(x) for x in xs])
+        st = self.lib.spand_pcg_batch(self.h, cnt, fp, nr.ctypes.data_as(_I32P), bp, xp, float(tol),
+                                      int(maxit), it.ctypes.data_as(_I32P), rr.ctypes.data_as(_DP))
+        if check or st not in (SPAND_OK, -4):
+            self._check(st)
+        off = np.concatenate([[0], np.cumsum(nr)])
+        return [(it[off[i]:off[i + 1]], rr[off[i]:off[i + 1]]) for i in range(cnt)]
 
     def apply(self, fac: "Factor", nrhs: int, x, y):
         """spand_apply: y = M x (device buffers, n x nrhs column-major)."""
@@ -271,6 +329,7 @@ def analyze_batch(problems, opts: Opts, ctx: Context | None = None, depths=None)
 class Plan:
     def __init__(self, lib, h):
         self.lib, self.h = lib, h
+        _live["plan"].add(self)
         n, nnz, d = C.c_int64(), C.c_int64(), C.c_int32()
         lib.spand_plan_sizes(h, C.byref(n), C.byref(nnz), C.byref(d))
         self.n, self.nnz, self.depth = n.value, nnz.value, d.value
@@ -323,6 +382,7 @@ class Plan:
 class Factor:
     def __init__(self, lib, h, plan):
         self.lib, self.h, self.plan = lib, h, plan
+        _live["factor"].add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -368,6 +428,7 @@ class Server:
         if st != SPAND_OK:
             raise SpandError(st, "spand_server_create failed")
         self._n = {}
+        _live["server"].add(self)
 
     def close(self):
         if self.h:

@@ -16,5 +16,7 @@ from .problems import (  # noqa: F401
     serve_stream,
     poisson_modes,
     poisson_eigvec,
+    sketch,
+    SKETCH_ROWS,
     WORKLOADS,
 )

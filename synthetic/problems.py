@@ -269,3 +269,27 @@ def poisson_eigvec(d: int, p: int):
     v = np.outer(s, s).reshape(-1)     # row y, column x: index x + d y
     v /= np.linalg.norm(v)
     return v, 8.0 * np.sin(p * np.pi / (2.0 * (d + 1))) ** 2
+
+
+SKETCH_ROWS = 256
+_SKETCH_CHUNK = 1 << 16
+
+
+def sketch(X, seed: int = 77, m: int = SKETCH_ROWS) -> np.ndarray:
+    """Seeded Gaussian projection S^T X of the columns of X (n or n x nrhs),
+    S ~ N(0,1)^(n x m).  S is drawn in row chunks of 65,536 (chunk c from
+    default_rng([seed, c])), so any n is projected in bounded memory and the
+    same S is drawn for the same (n, seed, m).  Returns m x nrhs.  For any
+    vector v, ||S^T v|| / sqrt(m) estimates ||v|| (to about 10 % at m = 256),
+    so ||S^T (x - y)|| / ||S^T y|| estimates the relative error of x against y
+    over all n entries.  A test-side projection: no step of the method."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    n = X.shape[0]
+    out = np.zeros((m, X.shape[1]))
+    for c, lo in enumerate(range(0, n, _SKETCH_CHUNK)):
+        hi = min(n, lo + _SKETCH_CHUNK)
+        S = np.random.default_rng([seed, c]).standard_normal((hi - lo, m))
+        out += S.T @ X[lo:hi]
+    return out

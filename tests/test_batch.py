@@ -156,3 +156,87 @@ def test_batched_factor_and_pcg_match_the_oracle_per_problem():
             assert abs(int(it[i, j]) - its_ref[i][j]) <= 1, (i, j)
             assert rr[i, j] < tol
             assert np.linalg.norm(xi[:, j] - xs_ref[i][:, j]) <= 1e-10 * np.linalg.norm(xs_ref[i][:, j])
+
+
+@gpu
+def test_factor_batch_handles_match_the_oracle_per_problem():
+    """spand_factor_batch over separately analysed plans: every handle reports
+    its own problem's ranks (bit-exact against the oracle for that problem
+    alone); spand_pcg_batch with different column counts per problem matches
+    the oracle's iterations (+-1) and solutions (1e-10); spand_pcg and
+    spand_apply on one handle give that problem's results alone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    spand = _lib()
+    probs = [make() for make, _ in PROBLEMS]
+    depths = [d for _, d in PROBLEMS]
+    ctx = spand.Context(0)
+    print("factor_batch of", len(probs), "problems", flush=True)
+    plans = [spand.analyze(p.n, p.rowptr, p.colind, p.coords,
+                           spand.make_opts(depth=d, skip=SKIP, eps=EPS, scheme="SO"))
+             for p, d in zip(probs, depths)]
+    opts = spand.make_opts(skip=SKIP, eps=EPS, scheme="SO")
+    facs = ctx.factor_batch(plans, [_dev(p.vals) for p in probs], opts)
+    facs2 = ctx.factor_batch(plans, [_dev(p.vals) for p in probs], opts)   # cached merged plan
+    nrhs = [1, 3, 2, 1]
+    tol = 1e-10
+    bs, xs, refs = [], [], []
+    for i, (p, d) in enumerate(zip(probs, depths)):
+        plan_o = nd.analyze(p.rowptr, p.colind, p.coords, d, SKIP)
+        F = ospand.factor(p.scipy(), plan_o, EPS, "SO")
+        for fset in (facs, facs2):
+            for l, recs in F.ranks.items():
+                got = fset[i].ranks(l, plan_o.steps[l].n_clusters)
+                for (c, a, k, r, r2) in recs:
+                    assert (got["a"][c], got["k"][c], got["r"][c], got["r2"][c]) == (a, k, r, r2), (i, l, c)
+        b = rhs(p.n, nrhs[i], 200 + i)
+        A = p.scipy()
+        X, its, _ = opcg.pcg_multi(lambda v: A @ v, lambda v: ospand.apply(F, v), b, tol)
+        refs.append((X, its, ospand.apply(F, b[:, 0])))
+        bs.append(_dev(b))
+        xs.append(torch.zeros(p.n * nrhs[i], dtype=torch.float64, device="cuda"))
+    res = ctx.pcg_batch(facs, nrhs, bs, xs, tol, 1000)
+    for i, p in enumerate(probs):
+        X, its, _ = refs[i]
+        x = xs[i].cpu().numpy().reshape(p.n, nrhs[i], order="F")
+        it, rr = res[i]
+        for j in range(nrhs[i]):
+            assert abs(int(it[j]) - its[j]) <= 1, (i, j)
+            assert rr[j] < tol
+            assert np.linalg.norm(x[:, j] - X[:, j]) <= 1e-10 * np.linalg.norm(X[:, j]), (i, j)
+    # one handle alone: PCG and apply on its own vectors
+    i = 2
+    p = probs[i]
+    X, its, y_ref = refs[i]
+    dx = torch.zeros(p.n * nrhs[i], dtype=torch.float64, device="cuda")
+    it, rr = ctx.pcg(facs2[i], nrhs[i], bs[i], dx, tol, 1000)
+    x = dx.cpu().numpy().reshape(p.n, nrhs[i], order="F")
+    for j in range(nrhs[i]):
+        assert abs(int(it[j]) - its[j]) <= 1
+        assert np.linalg.norm(x[:, j] - X[:, j]) <= 1e-10 * np.linalg.norm(X[:, j])
+    dy = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    ctx.apply(facs2[i], 1, bs[i][:p.n].contiguous(), dy)
+    assert np.linalg.norm(dy.cpu().numpy() - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+    for f in facs + facs2:
+        f.close()
+
+
+@gpu
+def test_hbm_budget_is_enforced():
+    """opts.hbm_budget_bytes: a budget below the factor's footprint fails with
+    SPAND_E_OOM; the context stays usable and an unlimited factorization of
+    the same plan then succeeds."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    spand = _lib()
+    p = laplacian_3d(16)
+    ctx = spand.Context(0)
+    o = spand.make_opts(depth=6, skip=2, eps=1e-2, scheme="SO", hbm_budget_bytes=1 << 16)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, o)
+    with pytest.raises(spand.SpandError) as e:
+        ctx.factor(plan, _dev(p.vals), o)
+    assert e.value.status == -5 and "hbm_budget_bytes" in e.value.message
+    o.hbm_budget_bytes = 0
+    fac = ctx.factor(plan, _dev(p.vals), o)
+    assert fac.info()["factor_bytes"] > (1 << 16)
+    fac.close()

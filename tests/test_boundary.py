@@ -111,3 +111,19 @@ def test_error_paths(lib):
     with pytest.raises(spand.SpandError) as e:
         spand.analyze(p.n, p.rowptr, p.colind, p.coords, spand.make_opts(depth=3, scheme=7))
     assert e.value.status == -1
+
+
+def test_opts_validation_on_the_host(lib):
+    """spand_analyze checks the options without a device: negative
+    top_fp64_levels or hbm_budget_bytes and unknown precisions are rejected."""
+    from paper_2007_00789_amd import spand
+    p = laplacian_2d(16)
+    o = spand.make_opts(depth=2, skip=0)
+    assert o.top_fp64_levels == 3 and o.hbm_budget_bytes == 0
+    spand.analyze(p.n, p.rowptr, p.colind, p.coords, o).close()
+    for field, bad in (("top_fp64_levels", -1), ("hbm_budget_bytes", -5), ("precision", 7)):
+        o2 = spand.make_opts(depth=2, skip=0)
+        setattr(o2, field, bad)
+        with pytest.raises(spand.SpandError) as e:
+            spand.analyze(p.n, p.rowptr, p.colind, p.coords, o2)
+        assert e.value.status == -1, field

@@ -11,7 +11,7 @@ Bars (FP64):
 import numpy as np
 import pytest
 
-from synthetic import laplacian_2d, laplacian_3d, fv_diffusion_3d, rhs
+from synthetic import laplacian_2d, laplacian_3d, fv_diffusion_3d, high_contrast_2d, rhs
 from oracle import nd, spand as ospand, pcg as opcg
 
 gpu = pytest.mark.gpu
@@ -315,7 +315,7 @@ def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group,
     for l, recs in F.ranks.items():
         got = fac.ranks(l, plan_o.steps[l].n_clusters)
         for (p_, a, k, r, r2) in recs:
-            assert (got["k"][p_], got["r"][p_]) == (k, r), (l, p_)
+            assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), (l, p_)
     x = rhs(p.n, 2, 13)
     y_ref = ospand.apply(F, x)
     dx = _dev(x)
@@ -424,3 +424,36 @@ def test_prescale_rejects_a_nonpositive_diagonal(ctx):
     with pytest.raises(spand.SpandError) as e:
         ctx.factor(plan, _dev(vals), opts)
     assert e.value.status == -3 and "row 40" in e.value.message
+
+
+@gpu
+@pytest.mark.parametrize("scheme", ["FO", "SO"])
+def test_high_contrast_field_of_table1(ctx, scheme):
+    """The rho = 100 high-contrast field of the Table 1 study (Sec. 4.1: uniform
+    noise, Gaussian blur sigma = 2, quantised to rho^{+-1}), 192 x 192, depth
+    round(log2(n/64)) = 9, skip 4, b = ones as in the paper, eps 1e-2: every
+    interface goes through the cooperative QR; ranks (a, k, r, r2) bit-exact,
+    n_cg +-1 and the solution within 1e-10 relative of the oracle's."""
+    d, rho = 192, 100.0
+    p = high_contrast_2d(d, rho, seed=5000 + d)
+    depth = int(round(np.log2(p.n / 64.0)))
+    print(f"high contrast rho={rho:g} d={d} {scheme}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, 4)
+    A = p.scipy()
+    F = ospand.factor(A, plan_o, 1e-2, scheme)
+    _, fac = _gpu_factor(ctx, p, depth, 4, 1e-2, scheme)
+    nsp = 0
+    for l, recs in F.ranks.items():
+        got = fac.ranks(l, plan_o.steps[l].n_clusters)
+        for (p_, a, k, r, r2) in recs:
+            assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), (l, p_)
+            nsp += 1
+    assert nsp > 50
+    b = np.ones(p.n)
+    x_ref, it_ref, _ = opcg.pcg(lambda v: A @ v, lambda v: ospand.apply(F, v), b, 1e-10)
+    db = _dev(b)
+    dx = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, 1, db, dx, 1e-10, 1000)
+    x = dx.cpu().numpy()
+    assert abs(int(it[0]) - it_ref) <= 1, (int(it[0]), it_ref)
+    assert np.linalg.norm(x - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
