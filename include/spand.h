@@ -215,6 +215,22 @@ spand_status spand_factor_info(spand_factor_t f, spand_factor_stats* st);
  * nrhs: columns are processed in chunks that fit the kernels' LDS). */
 spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x, double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = M x as
+ * spand_apply, on the same kernels, with every temporary in one fixed device
+ * array of 64 MiB per device (SPAND_NOALLOC_SCRATCH_BYTES) that the library
+ * holds from the first context on that device until the process ends.  Calls
+ * no hipMalloc, hipFree or other allocating routine.  Columns are processed in
+ * chunks that fit the array; SPAND_E_LIMIT if one column needs more scratch
+ * than the array holds; SPAND_E_INVALID for a handle of a batch factor.  x, y:
+ * device, n x nrhs column-major (may alias).  Every call on one device shares
+ * that device's array (its contents are not kept from one call to the next),
+ * so calls that overlap in time on one device, from different streams or
+ * threads, race and give wrong results. */
+#define SPAND_NOALLOC_SCRATCH_BYTES (64LL << 20)
+spand_status spand_apply_noalloc(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x,
+                                 double* y);
+
 /* PCG (Sec. 4): x0 = 0, stop when ||r_k||_2 < tol ||b||_2 per column and, for
  * a batch plan, per problem (each (problem, column) is an independent CG run);
  * b, x: device pointers (n x nrhs column-major); iters and relres (true

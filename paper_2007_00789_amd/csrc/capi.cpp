@@ -163,6 +163,7 @@ spand_status spand_create(spand_ctx_t* out, int device, void* stream) {
     ctx->c.device = device;
     ctx->c.pool = std::make_shared<spand::MemPool>(device, kPoolIdleBytes);
     ctx->vtmp[0].pool = ctx->vtmp[1].pool = ctx->c.pool;
+    ctx->c.noalloc = spand::noalloc_scratch(device);
     if (stream) {
       ctx->c.stream = static_cast<hipStream_t>(stream);
     } else {
@@ -574,6 +575,23 @@ spand_status spand_apply(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const 
       spand::run_apply(ctx->c, f->F(), nrhs, X, X);
       extract(ctx, f, nrhs, X, y);
     }
+    SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.prof.resolve();
+  });
+}
+
+spand_status spand_apply_noalloc(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const double* x,
+                                 double* y) {
+  if (!ctx || !f || nrhs <= 0 || !x || !y) return SPAND_E_INVALID;
+  return guarded(ctx, [&] {
+    check_ready(f);
+    if (f->seg >= 0)
+      throw spand::Error(SPAND_E_INVALID, "allocation-free apply: a handle of a batch factor "
+                                          "needs batch-sized vectors; use spand_apply");
+    if (f->core->device != ctx->c.device)
+      throw spand::Error(SPAND_E_INVALID, "factor lives on another device");
+    SPAND_HIP(hipSetDevice(ctx->c.device));
+    spand::run_apply_noalloc(ctx->c, f->F(), nrhs, x, y);
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     ctx->c.prof.resolve();
   });

@@ -167,8 +167,13 @@ struct Prof {
     (C).prof.end(pid_, (C).stream);                    \
   } while (0)
 
+// Size of the fixed device scratch of the allocation-free apply (one array per
+// device, held until the process ends).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+
 struct Ctx {
   int device = 0;
+  void* noalloc = nullptr; // device address of the fixed apply scratch of this device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string last_error;
@@ -237,5 +242,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
 void begin_apply(FactorObj& F);
 void build_apply_step(FactorObj& F, int l);
 void finish_apply(Ctx& C, FactorObj& F);
+// device address of the fixed scratch array on `device` (current), looked up
+// once per device
+void* noalloc_scratch(int device);
+// y = M x with every temporary in the fixed scratch (no device allocation);
+// SPAND_E_LIMIT when one column needs more than kNoAllocScratchBytes
+void run_apply_noalloc(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y);
 
 }  // namespace spand

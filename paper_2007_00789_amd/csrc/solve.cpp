@@ -2,6 +2,7 @@
 // (Sec. 4: zero initial guess, stop when ||r_k|| < tol ||b|| per column).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "apply.h"
@@ -395,29 +396,94 @@ static int64_t apply_lds_need(const ApplyProg& pg, int32_t nrhs) {
   return need;
 }
 
-static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y);
+// scratch of one chunk of columns: the interiors' slices (T), the backward E
+// partial sums (P), the WY u vectors (U) and the split-GEMV vectors (Y)
+struct ApplyScratch {
+  double *T, *P, *U, *Y;
+};
+static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y,
+                       const ApplyScratch& sc);
+
+// columns per chunk that the apply kernels' LDS holds
+static int32_t apply_lds_chunk(const ApplyProg& pg, int32_t nrhs) {
+  constexpr int64_t kLds = 160 * 1024;
+  int32_t chunk = 0;
+  while (chunk < nrhs && apply_lds_need(pg, chunk + 1) * (int64_t)sizeof(double) <= kLds) ++chunk;
+  if (chunk == 0) throw Error(SPAND_E_LIMIT, "cluster too large for the apply");
+  return chunk;
+}
 
 // y = M x for nrhs columns (x and y may alias).  Columns are independent: they
 // are processed in chunks of as many columns as the kernels' LDS holds.
 void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
-  constexpr int64_t kLds = 160 * 1024;
-  const ApplyProg& pg = *F.prog;
-  int32_t chunk = 0;
-  while (chunk < nrhs && apply_lds_need(pg, chunk + 1) * (int64_t)sizeof(double) <= kLds) ++chunk;
-  if (chunk == 0) throw Error(SPAND_E_LIMIT, "cluster too large for the apply");
+  ApplyProg& pg = *F.prog;
+  const int32_t chunk = apply_lds_chunk(pg, nrhs);
   const int64_t n = F.plan->n;
+  const int32_t w = std::min(chunk, nrhs);
+  ApplyScratch sc;
+  sc.T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * w * sizeof(double)));
+  sc.P = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * w * sizeof(double)));
+  sc.U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * w * sizeof(double)));
+  sc.Y = static_cast<double*>(pg.Y.ensure(std::max<int64_t>(pg.yscratch, 1) * w * sizeof(double)));
   for (int32_t c0 = 0; c0 < nrhs; c0 += chunk)
-    apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n);
+    apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n, sc);
 }
 
-static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
+// ---------------------------------------------------------------------------
+// Allocation-free apply: the same kernels, with every temporary in one fixed
+// device array per device (held until the process ends).  In host code
+// `scratch` names a host-side stand-in, not device memory: its device address
+// comes from hipGetSymbolAddress, taken once per device at context set-up.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+void* noalloc_scratch(int device) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) throw Error(SPAND_E_INVALID, "bad device ordinal");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[device]) {
+    void* p = nullptr;   // the caller has made `device` current
+    SPAND_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[device] = p;
+  }
+  return ptr[device];
+}
+
+void run_apply_noalloc(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
+  ApplyProg& pg = *F.prog;
+  if (!C.noalloc) throw Error(SPAND_E_STATE, "no fixed scratch on this context's device");
+  // doubles per column of each part, rounded up to 256 bytes
+  auto up = [](int64_t v) { return (std::max<int64_t>(v, 1) + 31) / 32 * 32; };
+  const int64_t pt = up(pg.scratch), pp = up(pg.pscratch), pu = up(pg.uscratch), py = up(pg.yscratch);
+  const int64_t per = (pt + pp + pu + py) * (int64_t)sizeof(double);
+  const int64_t fit = (int64_t)kNoAllocScratchBytes / per;
+  if (fit < 1)
+    throw Error(SPAND_E_LIMIT, "allocation-free apply: one column needs " + std::to_string(per) +
+                                   " bytes of scratch, more than the fixed " +
+                                   std::to_string(kNoAllocScratchBytes) + " bytes");
+  const int32_t chunk = (int32_t)std::min<int64_t>(apply_lds_chunk(pg, nrhs), fit);
+  double* base = static_cast<double*>(C.noalloc);
+  ApplyScratch sc;
+  sc.T = base;
+  sc.P = sc.T + pt * chunk;
+  sc.U = sc.P + pp * chunk;
+  sc.Y = sc.U + pu * chunk;
+  const int64_t n = F.plan->n;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += chunk)
+    apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n, sc);
+}
+
+static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y,
+                       const ApplyScratch& sc) {
   hipStream_t s = C.stream;
   const int64_t n = F.plan->n;
   ApplyProg& pg = *F.prog;
-  double* T = static_cast<double*>(pg.T.ensure(std::max<int64_t>(pg.scratch, 1) * nrhs * sizeof(double)));
-  double* Pp = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * nrhs * sizeof(double)));
-  double* U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * nrhs * sizeof(double)));
-  double* Ys = static_cast<double*>(pg.Y.ensure(std::max<int64_t>(pg.yscratch, 1) * nrhs * sizeof(double)));
+  double* T = sc.T;
+  double* Pp = sc.P;
+  double* U = sc.U;
+  double* Ys = sc.Y;
   if (F.dscale) SPAND_PROF(C, "k_scale_vec", launch_scale_vec(x, F.dscale, y, n, nrhs, s));
   else if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {

@@ -87,6 +87,7 @@ SIGNATURES = {
     "spand_factor_ranks": (C.c_int, [_P, C.c_int32, _I32P, _I32P, _I32P, _I32P]),
     "spand_factor_info": (C.c_int, [_P, C.POINTER(FactorStats)]),
     "spand_apply": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "spand_apply_noalloc": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
     "spand_pcg": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.c_double, C.c_int32, _I32P, _DP]),
     "spand_debug_block": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _I32P, _I32P]),
     "spand_server_create": (C.c_int, [C.c_int32, C.POINTER(Opts), C.c_double, C.c_int32,
@@ -254,6 +255,11 @@ class Context:
     def apply(self, fac: "Factor", nrhs: int, x, y):
         """spand_apply: y = M x (device buffers, n x nrhs column-major)."""
         self._check(self.lib.spand_apply(self.h, fac.h, int(nrhs), _ptr(x), _ptr(y)))
+
+    def apply_noalloc(self, fac: "Factor", nrhs: int, x, y):
+        """spand_apply_noalloc: y = M x with the library's fixed device scratch
+        (no device allocation)."""
+        self._check(self.lib.spand_apply_noalloc(self.h, fac.h, int(nrhs), _ptr(x), _ptr(y)))
 
     def pcg(self, fac: "Factor", nrhs: int, b, x, tol=1e-10, maxit=1000, check=True):
         """spand_pcg; returns (iters, relres) numpy arrays of nrhs entries, or of
