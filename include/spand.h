@@ -79,8 +79,6 @@ typedef struct {
   int32_t qr_xcd_local; /* 1 (default); 0 treats every cooperative QR group as not placed on one
                            XCD, which makes the factorization fall back to the single-workgroup
                            QR (testing) */
-  int32_t qr_regs;      /* cooperative QR with W held in registers when a <= 288 and the
-                           coupling fits 32 x 64 columns: 1, or LDS-resident slices: 0 (default) */
   int32_t qr_lds_cols;  /* 0 (default): a cooperative QR workgroup keeps as many of its columns
                            in LDS as fit, the rest (interfaces wider than 32 workgroups' LDS)
                            in the row panel; c > 0: at most c in LDS (testing) */

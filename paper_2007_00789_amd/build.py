@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libspand.so")
 ARCH = os.environ.get("SPAND_ARCH", "gfx950")
 
 SOURCES = ["analyze.cpp", "factor.cpp", "solve.cpp", "capi.cpp", "server.cpp",
-           "kernels_factor.hip", "kernels_qr_coop.hip", "kernels_qr_reg.hip",
+           "kernels_factor.hip", "kernels_qr_coop.hip",
            "kernels_solve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -82,7 +82,7 @@ void check_opts(const spand_opts* o) {
   if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
   if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
   if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
-      o->qr_xcd_local > 1 || o->qr_regs < 0 || o->qr_regs > 1 || o->qr_lds_cols < 0)
+      o->qr_xcd_local > 1 || o->qr_lds_cols < 0)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
   if (o->prescale < 0 || o->prescale > 1) throw Error(SPAND_E_INVALID, "prescale must be 0 or 1");
   if (o->top_fp64_levels < 0) throw Error(SPAND_E_INVALID, "top_fp64_levels must be >= 0");
@@ -128,7 +128,6 @@ void spand_default_opts(spand_opts* o) {
   o->qr_group = 0;
   o->qr_list_cap = -1;
   o->qr_xcd_local = 1;
-  o->qr_regs = 0;
   o->qr_lds_cols = 0;
   o->prescale = 0;
   o->top_fp64_levels = 3;

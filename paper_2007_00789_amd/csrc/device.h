@@ -74,8 +74,8 @@ struct CpqrDesc {
 struct CoopDesc {
   CpqrDesc d;
   int32_t* sync;     // kCoopSyncInts ints, zeroed by the launcher: [0] placement
-                     // check counter, barrier flags from [kCoopFlag0] (32-bit) or
-                     // [kCoopFlag64] (64-bit, two parities)
+                     // check counter, barrier flags from [kCoopFlag64] (64-bit,
+                     // two parities)
   double* xch;       // exchange buffer, coop_xch_doubles(G, a)
   int32_t G, xcd, ncap, list_cap;  // list_cap <= 32 tie candidates per workgroup
   int32_t ncap_lds;  // columns per workgroup held in LDS; the rest of its
@@ -101,7 +101,6 @@ inline int64_t coop_cols(int a) { return ((int64_t)(kCoopLdsBytes / 8) - a) / (a
 // panel, when an interface is too wide for kCoopMaxGroup workgroups' LDS
 constexpr int kCoopOverflow = 4;
 constexpr int kCoopSyncInts = 192;       // 768 bytes per group
-constexpr int kCoopFlag0 = 32;           // 32-bit flags (register-resident QR), own 128-byte line
 constexpr int kCoopFlag64 = 64;          // 2 x kCoopMaxGroup 64-bit flags (LDS-resident QR)
 
 // Triangular factor of the compact WY form of one interface's n reflectors
@@ -148,23 +147,11 @@ void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s);
 // maximum co-resident workgroups of the cooperative QR for a given LDS size
 // (panel: the instance that supports columns kept in the row panel)
 int coop_max_blocks(size_t lds_bytes, bool panel);
-// blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block)
-// register-resident cooperative QR (a <= kCpqrRegMaxA, at most kCpqrRegCols
-// columns per workgroup): rows per lane for a given a (0 if a is too large),
-// dynamic LDS bytes, co-resident workgroups, launch
-constexpr int kCpqrRegMaxA = 288;
-constexpr int kCpqrRegCols = 64;
-int cpqr_reg_rows(int a);
-size_t cpqr_reg_lds(int G, int a);
-int cpqr_reg_max_blocks(int rows, size_t lds_bytes);
-// The launches below first clear the nsync barrier words at `sync` (each
-// group's CoopDesc::sync points into them); nsync = 0 when the caller has
-// cleared them already.
-hipError_t launch_cpqr_reg(int rows, const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
-                           int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
-                           int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
-                           double eps_stop, int32_t* err, size_t lds_bytes, hipStream_t s);
 void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
+// blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block).
+// The launch first clears the nsync barrier words at `sync` (each group's
+// CoopDesc::sync points into them); nsync = 0 when the caller has cleared
+// them already.
 hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,

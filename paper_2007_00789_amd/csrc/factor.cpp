@@ -921,7 +921,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       int64_t sync_used = 0;
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrDesc> cd;
-        std::vector<CoopDesc> qd, qd_reg;
+        std::vector<CoopDesc> qd;
         std::vector<CpqrNbr> cn;
         int ma = 1, mk = 1;
         for (int p : st.order) {
@@ -959,15 +959,12 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           d.V = R.V[p];
           d.tau = R.tau[p];
           d.T = R.T[p];
-          // register-resident slices when they fit, else LDS-resident slices
-          bool reg = o.qr_regs && cpqr_reg_rows(a) > 0 &&
-                     (kmax + kCpqrRegCols - 1) / kCpqrRegCols <= kCoopMaxGroup;
-          const int64_t cap = !(a > 0) ? 0 : reg ? kCpqrRegCols : coop_cols(a);
+          const int64_t cap = !(a > 0) ? 0 : coop_cols(a);
           int64_t G = cap > 0 ? (kmax + cap - 1) / cap : 0;
           if (o.qr_group > 0) G = std::max(G, std::min<int64_t>(o.qr_group, kmax));
           // too wide for kCoopMaxGroup workgroups' LDS: kCoopMaxGroup
           // workgroups, each keeping its columns beyond the LDS in the panel
-          if (!reg && G > kCoopMaxGroup && o.qr_group >= 0 &&
+          if (G > kCoopMaxGroup && o.qr_group >= 0 &&
               (kmax + kCoopMaxGroup - 1) / kCoopMaxGroup <= kCoopOverflow * cap)
             G = kCoopMaxGroup;
           if (o.qr_group >= 0 && a > 0 && kmax > 0 && G >= 1 && G <= kCoopMaxGroup) {
@@ -977,10 +974,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             q.ncap = (int32_t)((kmax + G - 1) / G);
             int64_t capl = cap;
             if (o.qr_lds_cols > 0) capl = std::min<int64_t>(capl, o.qr_lds_cols);
-            q.ncap_lds = reg ? q.ncap : (int32_t)std::min<int64_t>(q.ncap, capl);
+            q.ncap_lds = (int32_t)std::min<int64_t>(q.ncap, capl);
             q.list_cap = o.qr_list_cap < 0 ? 32 : o.qr_list_cap;
-            (reg ? qd_reg : qd).push_back(q);
-            coop_used[p] = reg ? 2 : 1;
+            qd.push_back(q);
+            coop_used[p] = 1;
             continue;
           }
           if (kmax > kCpqrMaxK) throw Error(SPAND_E_LIMIT, "interface coupling wider than " +
@@ -998,28 +995,18 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         // cooperative groups, packed onto XCDs (all workgroups of a group on
         // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
         // groups per launch as can be co-resident
-        for (int kind = 0; kind < 2; ++kind) {
-          std::vector<CoopDesc>& list = kind == 0 ? qd_reg : qd;
-          if (list.empty()) continue;
+        {
+          std::vector<CoopDesc>& list = qd;
           size_t lds = 0;
-          int rows = 0, cap_blocks = 0;
+          int cap_blocks = 0;
           bool panel = false;   // some workgroup keeps columns in the row panel
           for (const CoopDesc& q : list) panel = panel || q.ncap_lds < q.ncap;
-          if (kind == 0) {
-            int amax = 0;
-            for (const CoopDesc& q : list) {
-              amax = std::max(amax, q.d.a);
-              lds = std::max(lds, cpqr_reg_lds(q.G, q.d.a));
-            }
-            rows = cpqr_reg_rows(amax);
-            cap_blocks = cpqr_reg_max_blocks(rows, lds);
-          } else {
-            for (const CoopDesc& q : list)
-              lds = std::max(lds, coop_lds_bytes(q.d.a, q.ncap, q.ncap_lds));
-            cap_blocks = coop_max_blocks(lds, panel);
-          }
+          for (const CoopDesc& q : list)
+            lds = std::max(lds, coop_lds_bytes(q.d.a, q.ncap, q.ncap_lds));
+          if (!list.empty()) cap_blocks = coop_max_blocks(lds, panel);
           const int slots = cap_blocks / kCoopXcds;
-          if (slots <= 0) throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
+          if (!list.empty() && slots <= 0)
+            throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
           std::vector<int> ord(list.size());
           for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
           std::stable_sort(ord.begin(), ord.end(),
@@ -1048,7 +1035,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             // place them again (the pivot sequence does not depend on G)
             std::vector<CoopDesc> mq;
             for (int i : members) mq.push_back(list[i]);
-            if (kind == 1 && o.qr_group == 0 && slots >= kCoopMaxGroup) {
+            if (o.qr_group == 0 && slots >= kCoopMaxGroup) {
               std::vector<CoopDesc> wq = mq;
               widen_groups(wq);
               bool changed = false;
@@ -1106,15 +1093,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             const auto* d_qd = C.upload.upload(batch);
             const auto* d_map = C.upload.upload(blk_map);
             hipError_t he = hipSuccess;
-            if (kind == 0) {
-              SPAND_PROF(C, "k_cpqr_reg",
-                         he = launch_cpqr_reg(rows, d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur,
-                                              d_r, d_r2, d_k, eps, eps_stop, d_err, lds, s));
-            } else {
-              SPAND_PROF(C, "k_cpqr_coop",
-                         he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur, d_r,
-                                               d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
-            }
+            SPAND_PROF(C, "k_cpqr_coop",
+                       he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur, d_r,
+                                             d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
             SPAND_HIP(he);
           }
         }
@@ -1205,7 +1186,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         double qr = 0.0;
         for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
         flops += qr;
-        C.prof.add_work(coop_used[p] == 2 ? "k_cpqr_reg" : coop_used[p] ? "k_cpqr_coop" : "k_cpqr", qr);
+        C.prof.add_work(coop_used[p] ? "k_cpqr_coop" : "k_cpqr", qr);
         nnzL += (int64_t)a * r2 - (int64_t)r2 * (r2 - 1) / 2 + r2;
         if (so) nnzL += (int64_t)(a - r) * (k - r);
         if (sf) {

@@ -37,7 +37,7 @@ class Opts(C.Structure):
     _fields_ = [("depth", C.c_int32), ("skip", C.c_int32), ("eps", C.c_double),
                 ("scheme", C.c_int32), ("precision", C.c_int32), ("debug_stop_step", C.c_int32),
                 ("qr_group", C.c_int32), ("qr_list_cap", C.c_int32),
-                ("qr_xcd_local", C.c_int32), ("qr_regs", C.c_int32), ("qr_lds_cols", C.c_int32),
+                ("qr_xcd_local", C.c_int32), ("qr_lds_cols", C.c_int32),
                 ("prescale", C.c_int32), ("top_fp64_levels", C.c_int32),
                 ("hbm_budget_bytes", C.c_int64)]
 
@@ -153,7 +153,7 @@ def _np(a, dtype):
 
 
 def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
-              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_regs=0, qr_lds_cols=0, prescale=0,
+              qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_lds_cols=0, prescale=0,
               top_fp64_levels=None, hbm_budget_bytes=0) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
@@ -166,7 +166,6 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     o.qr_group = int(qr_group)
     o.qr_list_cap = int(qr_list_cap)
     o.qr_xcd_local = int(qr_xcd_local)
-    o.qr_regs = int(qr_regs)
     o.qr_lds_cols = int(qr_lds_cols)
     o.prescale = int(prescale)
     if top_fp64_levels is not None:

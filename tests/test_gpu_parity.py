@@ -31,12 +31,11 @@ def ctx():
 
 
 def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1, qr_group=0, qr_list_cap=-1,
-                qr_xcd_local=1, qr_regs=0, qr_lds_cols=0):
+                qr_xcd_local=1, qr_lds_cols=0):
     from paper_2007_00789_amd import spand
     opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop,
                            qr_lds_cols=qr_lds_cols,
-                           qr_group=qr_group, qr_list_cap=qr_list_cap, qr_xcd_local=qr_xcd_local,
-                           qr_regs=qr_regs)
+                           qr_group=qr_group, qr_list_cap=qr_list_cap, qr_xcd_local=qr_xcd_local)
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
     vals = _dev(p.vals)
     fac = ctx.factor(plan, vals, opts)
@@ -290,28 +289,25 @@ def test_tiny_and_degenerate_problems(ctx):
 
 
 @gpu
-@pytest.mark.parametrize("qr_group,qr_list_cap,xcd_local,regs", [
-    (-1, -1, 1, 1), (1, -1, 1, 1), (3, -1, 1, 1), (5, 0, 1, 1), (8, 1, 1, 1), (3, -1, 0, 1),
-    (8, 1, 0, 1), (32, -1, 1, 1), (1, -1, 1, 0), (3, -1, 1, 0), (5, 0, 1, 0), (8, 1, 0, 0)],
-    ids=["single-wg", "reg-1", "reg-3", "reg-5-roundB", "reg-8-cap1", "reg-3-misplaced",
-         "reg-8-cap1-misplaced", "reg-32", "lds-1", "lds-3", "lds-5-roundB",
-         "lds-8-cap1-misplaced"])
+@pytest.mark.parametrize("qr_group,qr_list_cap,xcd_local", [
+    (-1, -1, 1), (1, -1, 1), (3, -1, 1), (5, 0, 1), (8, 1, 1), (3, -1, 0), (8, 1, 0), (32, -1, 1)],
+    ids=["single-wg", "lds-1", "lds-3", "lds-5-roundB", "lds-8-cap1", "lds-3-misplaced",
+         "lds-8-cap1-misplaced", "lds-32"])
 @pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[4]],
                          ids=[CASES[1][0], CASES[3][0], CASES[4][0]])
 def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group, qr_list_cap,
-                                    xcd_local, regs):
+                                    xcd_local):
     """Every QR path (single workgroup on a global workspace; cooperative groups
     of several workgroups with W in LDS or in registers, with and without the
     overflow round; groups reported as not placed on one XCD, which makes the
     factorization fall back to single-workgroup QRs) gives the oracle's ranks
     and the same preconditioner."""
     p = make()
-    print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local} regs={regs}",
-          flush=True)
+    print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local}", flush=True)
     plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
     F = ospand.factor(p.scipy(), plan_o, eps, "SO")
     _, fac = _gpu_factor(ctx, p, depth, skip, eps, "SO", qr_group=qr_group, qr_list_cap=qr_list_cap,
-                         qr_xcd_local=xcd_local, qr_regs=regs)
+                         qr_xcd_local=xcd_local)
     for l, recs in F.ranks.items():
         got = fac.ranks(l, plan_o.steps[l].n_clusters)
         for (p_, a, k, r, r2) in recs:
