@@ -45,6 +45,8 @@ WORKLOAD_NAMES = {
     "fv3d_128": "fv3d 128^3 finite-volume diffusion, k = 10^U[-3,3] per cell",
 }
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+# arithmetic of the factorization per precision option (PCG is FP64 always)
+DTYPES = {"FP64": "f64", "FP32": "f32 factor, f64 PCG", "FP32_BF16": "f32 factor, bf16 Schur, f64 PCG"}
 
 
 # oracle sample of each single-matrix workload: the same matrix family at two
@@ -297,9 +299,11 @@ def bench_c1grid(args):
     x = torch.zeros_like(b)
     plan = None
     rows = []
-    for eps in (1e-1, 1e-2, 1e-3):
-        for scheme in ("FO", "SO"):
-            opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=eps, scheme=scheme)
+    for prec, eps, scheme in [(pr, e, sc) for pr in ("FP64", "FP32_BF16") for e in (1e-1, 1e-2, 1e-3)
+                              for sc in ("FO", "SO")]:
+        if True:
+            opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=eps, scheme=scheme,
+                                   precision=prec)
             if plan is None:
                 plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
             tfs, tss = [], []
@@ -316,12 +320,17 @@ def bench_c1grid(args):
                     tfs.append(tf)
                     tss.append(ts)
             step = float(np.mean(tfs) + np.mean(tss))
-            rows.append({"eps": eps, "scheme": scheme, "solves_per_s": nrhs / step,
+            rows.append({"precision": prec, "eps": eps, "scheme": scheme, "solves_per_s": nrhs / step,
                          "factor_ms": 1e3 * float(np.mean(tfs)), "solve_ms": 1e3 * float(np.mean(tss)),
                          "n_cg": [int(v) for v in it], "relres_max": float(rr.max()),
                          "mu": info["nnz_L"] / prob.nnz,
                          "factor_tflops": info["flops"] / float(np.mean(tfs)) / 1e12})
-    ref = [r for r in rows if r["eps"] == 1e-2 and r["scheme"] == "SO"][0]
+    ref = [r for r in rows if r["eps"] == 1e-2 and r["scheme"] == "SO" and r["precision"] == "FP64"][0]
+    for r in rows:   # the FP32 form against the FP64 one on the same (eps, scheme)
+        if r["precision"] != "FP64":
+            base = [q for q in rows if q["precision"] == "FP64" and q["eps"] == r["eps"]
+                    and q["scheme"] == r["scheme"]][0]
+            r["speedup_vs_fp64"] = r["solves_per_s"] / base["solves_per_s"]
     out = {
         "metric": "PCG solves/s to 1e-10 rel. residual; factor TFLOP/s; p50/p99 solve latency",
         "value": ref["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -329,8 +338,9 @@ def bench_c1grid(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"lap3d 64^3 7-point Laplacian, n={prob.n}, depth {w['depth']}, "
-                               f"skip {w['skip']}, eps x scheme grid, FP64, {nrhs} RHS N(0,1), "
-                               f"PCG tol {tol:g}", "global_batch": nrhs, "parallelism": "single GPU"},
+                               f"skip {w['skip']}, eps x scheme x precision grid (value: FP64 SO "
+                               f"eps 1e-2), {nrhs} RHS N(0,1), FP64 PCG tol {tol:g}",
+                   "global_batch": nrhs, "parallelism": "single GPU"},
         "grid": rows,
     }
     print(json.dumps(out), flush=True)
@@ -551,6 +561,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--scheme", default="SO")
+    ap.add_argument("--precision", default="FP64", choices=["FP64", "FP32", "FP32_BF16"],
+                    help="arithmetic of the factorization (PCG is FP64 in every mode)")
     ap.add_argument("--workload", default="fv3d_128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=48, help="requests of the serving stream")
@@ -595,7 +607,8 @@ def main():
 
     prob, w = workload(args.workload)
     nrhs, tol = w["nrhs"], w["tol"]
-    opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=args.eps, scheme=args.scheme)
+    opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=args.eps, scheme=args.scheme,
+                           precision=args.precision)
     ctx = spand.Context(0)
     t0 = time.perf_counter()
     plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
@@ -680,11 +693,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD_NAMES.get(args.workload, args.workload)}, n={prob.n}, "
                                f"depth {w['depth']}, skip {w['skip']}, eps {args.eps:g}, "
-                               f"{args.scheme}, FP64, {nrhs} RHS N(0,1), PCG tol {tol:g}",
+                               f"{args.scheme}, {args.precision} factor, FP64 PCG, {nrhs} RHS "
+                               f"N(0,1), PCG tol {tol:g}",
                    "global_batch": nrhs, "parallelism": "single GPU"},
         "factor_tflops": factor_tflops,
         "factor_ms": 1e3 * float(np.mean(facs)),

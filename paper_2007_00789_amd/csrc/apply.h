@@ -18,9 +18,12 @@
 
 namespace spand {
 
+// Factor entries (L^{-1}, G, Z^{-1}, V, T, V T, E, M) are of the factor's
+// element type (double, or float in the FP32 forms; the launchers take it as
+// `f32`); vectors and scratch are always double.
 struct ApInt {
-  const double* Linv;      // n x n
-  const double* G;         // n x k (G_s = L_s^{-1} B_sW)
+  const void* Linv;        // n x n
+  const void* G;           // n x k (G_s = L_s^{-1} B_sW)
   const int32_t* pos;      // n
   const int32_t* nbr_pos;  // k
   int64_t toff;            // scratch offset (units of one right-hand side)
@@ -39,7 +42,7 @@ struct ApInt {
 // (scratch offsets in units of one right-hand side, as the T scratch).
 // tri = 1: M is lower triangular (zeros above the diagonal are skipped).
 struct ApMv {
-  const double* M;
+  const void* M;
   const int32_t* xpos;
   const int32_t* opos;
   const int32_t* bpos;
@@ -63,18 +66,18 @@ struct ApSrc {             // one slice of a scratch vector subtracted from a ta
 
 struct ApGat {
   const int32_t* pos;      // target positions (first n)
-  const double* Zinv;      // nullable: scale after the subtraction (forward only)
+  const void* Zinv;        // nullable: scale after the subtraction (forward only)
   int64_t src0, src1;      // range in the ApSrc list
   int64_t yoff;            // split scaling: the difference goes to the scratch at yoff
   int32_t n, split;        // split = 1: no scaling here (a split GEMV applies Zinv)
 };
 
 struct ApSp {
-  const double* V;         // a x nref reflectors (ld a, zero above the unit diagonal)
-  const double* tau;       // nref
-  const double* T;         // nref x nref: Q = I - V T V^T
-  const double* VT;        // a x nref (ld a): V T
-  const double* Et;        // E^T: k x (f1-f0), column i = row f0+i of Q^T W (ld lde); nullable
+  const void* V;           // a x nref reflectors (ld a, zero above the unit diagonal)
+  const void* tau;         // nref
+  const void* T;           // nref x nref: Q = I - V T V^T
+  const void* VT;          // a x nref (ld a): V T
+  const void* Et;          // E^T: k x (f1-f0), column i = row f0+i of Q^T W (ld lde); nullable
   const int32_t* pos;      // a
   const int32_t* nbr_pos;  // k
   int64_t toff;
@@ -104,7 +107,7 @@ constexpr int kApWyRB = 16;
 // Backward: part[i] = sum_c E[i, c0 + c] y_W[c0 + c] for every fine row i, into
 // the tile's partial-sum slot (offset off, length nf).
 struct ApEt {
-  const double* Et;
+  const void* Et;
   const int32_t* pos;      // forward: positions of the nf fine rows; backward: of the k columns
   int64_t lde;
   int64_t off;             // units of one right-hand side
@@ -114,39 +117,40 @@ constexpr int kEtTileF = 64;    // columns per forward E tile
 constexpr int kEtTileB = 256;   // columns per backward E tile
 
 struct ApScale {
-  const double* Zinv;
+  const void* Zinv;
   const int32_t* pos;
   int32_t n, pad;
 };
 
+// f32: the factor entries of the descriptors are floats (else doubles)
 void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                       double* T, int32_t max_n, hipStream_t s);
+                       double* T, int32_t max_n, bool f32, hipStream_t s);
 // Y: scratch of the split scaling (descriptors with split = 1), else unused
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
-                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s,
+                      int32_t nrhs, const double* T, int32_t max_n, bool f32, hipStream_t s,
                       double* Y = nullptr);
 // split GEMV kernels (S: operand scratch, O: result scratch)
 void launch_ap_mv_rows(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
-                       int32_t nrhs, const double* S, double* O, hipStream_t s);
+                       int32_t nrhs, const double* S, double* O, bool f32, hipStream_t s);
 void launch_ap_mv_cols(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
-                       int32_t nrhs, const double* S, double* O, hipStream_t s);
+                       int32_t nrhs, const double* S, double* O, bool f32, hipStream_t s);
 // wide WY apply, dots then update (fwd = 1: Q^T; 0: Q, after the partial
 // sums P); U: the colour's u vectors, usz doubles per right-hand side
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
                        int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,
-                       hipStream_t s);
+                       bool f32, hipStream_t s);
 void launch_ap_wy_update(const ApWyTask* t, int32_t count, const ApSp* d, double* z, int64_t ldz,
                          int32_t nrhs, const double* P, const double* U, int64_t usz, int fwd,
-                         hipStream_t s);
+                         bool f32, hipStream_t s);
 // E tiles, forward (t = E^T z_f) or backward (partial sums of E y_W)
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
-                      double* T, int32_t max_nf, hipStream_t s);
+                      double* T, int32_t max_nf, bool f32, hipStream_t s);
 void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
-                      double* P, hipStream_t s);
+                      double* P, bool f32, hipStream_t s);
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                         int32_t max_n, hipStream_t s);
+                         int32_t max_n, bool f32, hipStream_t s);
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                       int32_t max_n, hipStream_t s);
+                       int32_t max_n, bool f32, hipStream_t s);
 
 // PCG helpers.  Vectors are n x nrhs (ld n); the rows are split into nseg
 // segments (independent problems of a batch, seg_off: nseg + 1 offsets on the

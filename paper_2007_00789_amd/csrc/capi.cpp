@@ -80,7 +80,8 @@ void check_opts(const spand_opts* o) {
   if (o->scheme < SPAND_FIRST_ORDER || o->scheme > SPAND_SUPERFINE)
     throw Error(SPAND_E_INVALID, "unknown scheme");
   if (o->skip < 0) throw Error(SPAND_E_INVALID, "skip must be >= 0");
-  if (o->precision != SPAND_FP64) throw Error(SPAND_E_INVALID, "unsupported precision");
+  if (o->precision != SPAND_FP64 && o->precision != SPAND_FP32 && o->precision != SPAND_FP32_BF16)
+    throw Error(SPAND_E_INVALID, "unknown precision");
   if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
       o->qr_xcd_local > 1 || o->qr_lds_cols < 0)
     throw Error(SPAND_E_INVALID, "bad QR testing options");

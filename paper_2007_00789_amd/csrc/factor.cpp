@@ -371,11 +371,12 @@ void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, boo
 
 // Blocks of at most 64 rows first, the larger ones after; the breakdown flags
 // follow the same order.
-void order_potrf(std::vector<PotrfDesc>& pd, std::vector<int32_t>& clusters) {
+template <class FT>
+void order_potrf(std::vector<PotrfDescT<FT>>& pd, std::vector<int32_t>& clusters) {
   std::vector<size_t> ord(pd.size());
   std::iota(ord.begin(), ord.end(), size_t(0));
   std::stable_partition(ord.begin(), ord.end(), [&](size_t i) { return pd[i].n <= 64; });
-  std::vector<PotrfDesc> p2(pd.size());
+  std::vector<PotrfDescT<FT>> p2(pd.size());
   std::vector<int32_t> c2(pd.size());
   for (size_t i = 0; i < ord.size(); ++i) {
     p2[i] = pd[ord[i]];
@@ -390,10 +391,11 @@ void order_potrf(std::vector<PotrfDesc>& pd, std::vector<int32_t>& clusters) {
 // workgroup-per-block kernel).
 constexpr int32_t kWaveBlocksMin = 2048;
 
-void launch_potrf_split(const std::vector<PotrfDesc>& pd, const PotrfDesc* d_pd, int32_t* info,
-                        hipStream_t s) {
+template <class FT>
+void launch_potrf_split(const std::vector<PotrfDescT<FT>>& pd, const PotrfDescT<FT>* d_pd,
+                        int32_t* info, hipStream_t s) {
   int32_t nsmall = 0, max_s = 0, max_b = 0;
-  for (const PotrfDesc& q : pd) {
+  for (const PotrfDescT<FT>& q : pd) {
     if (q.n <= 64) {
       ++nsmall;
       max_s = std::max(max_s, q.n);
@@ -407,6 +409,74 @@ void launch_potrf_split(const std::vector<PotrfDesc>& pd, const PotrfDesc* d_pd,
   }
   launch_potrf_inv(d_pd, nsmall, max_s, info, s);
   launch_potrf_blocks(d_pd + nsmall, (int32_t)pd.size() - nsmall, max_b, info + nsmall, s);
+}
+
+// The Cholesky-inverse blocks of one launch, ready to run: the blocks factored
+// in the factor's own precision and, for an FP32 factor, those factored in
+// FP64 (blocks above 64 rows, and every block of the steps l <
+// top_fp64_levels), each converted into an FP64 scratch copy, factored there
+// and its inverse converted back.  The breakdown flags follow the order of
+// `clusters`: the own blocks, then the FP64 ones.
+template <class FT>
+struct PotrfLaunch {
+  std::vector<PotrfDescT<FT>> own;
+  const PotrfDescT<FT>* d_own = nullptr;
+  std::vector<PotrfDesc> wide;
+  const PotrfDesc* d_wide = nullptr;
+  const CopyDescT<FT, double>* d_in = nullptr;
+  const CopyDescT<double, FT>* d_out = nullptr;
+  std::vector<int32_t> clusters;
+};
+
+template <class FT>
+void prep_potrf(Ctx& C, std::vector<PotrfDescT<FT>>& pd, std::vector<int32_t>& clusters,
+                bool all_fp64, PotrfLaunch<FT>& L) {
+  L = PotrfLaunch<FT>();
+  if constexpr (sizeof(FT) == 8) {
+    order_potrf(pd, clusters);
+    L.own = std::move(pd);
+    L.clusters = std::move(clusters);
+    L.d_own = C.upload.upload(L.own);
+  } else {
+    std::vector<int32_t> cw;
+    std::vector<PotrfDescT<FT>> wide_src;
+    for (size_t i = 0; i < pd.size(); ++i) {
+      if (all_fp64 || pd[i].n > 64) {
+        wide_src.push_back(pd[i]);
+        cw.push_back(clusters[i]);
+      } else {
+        L.own.push_back(pd[i]);
+        L.clusters.push_back(clusters[i]);
+      }
+    }
+    order_potrf(wide_src, cw);
+    std::vector<CopyDescT<FT, double>> in;
+    std::vector<CopyDescT<double, FT>> out;
+    for (const PotrfDescT<FT>& q : wide_src) {
+      const int n = q.n;
+      double* A64 = C.upload.scratch_n<double>((size_t)n * n);
+      double* X64 = C.upload.scratch_n<double>((size_t)n * n);
+      in.push_back({q.A, A64, q.lda, n, n, n});
+      L.wide.push_back({A64, X64, n, n, q.cluster, 0});
+      out.push_back({X64, q.X, n, n, n, n});
+    }
+    L.clusters.insert(L.clusters.end(), cw.begin(), cw.end());
+    L.d_own = C.upload.upload(L.own);
+    L.d_wide = C.upload.upload(L.wide);
+    L.d_in = C.upload.upload(in);
+    L.d_out = C.upload.upload(out);
+  }
+}
+
+template <class FT>
+void run_potrf(const PotrfLaunch<FT>& L, int32_t* info, hipStream_t s) {
+  if (!L.own.empty()) launch_potrf_split(L.own, L.d_own, info, s);
+  if (!L.wide.empty()) {
+    const int64_t nw = (int64_t)L.wide.size();
+    launch_copy(L.d_in, nw, s);
+    launch_potrf_split(L.wide, L.d_wide, info + L.own.size(), s);
+    launch_copy(L.d_out, nw, s);
+  }
 }
 
 void check_info(const std::vector<int32_t>& info, const std::vector<int32_t>& clusters, int l,
@@ -536,7 +606,8 @@ class ApplyBuilder {
 // 8 XCDs, kCoopMaxGroup workgroups each), so that each workgroup holds fewer
 // columns and its update per pivot step is shorter.  The pivot sequence does
 // not depend on the group size.
-void widen_groups(std::vector<CoopDesc>& list) {
+template <class FT>
+void widen_groups(std::vector<CoopDescT<FT>>& list) {
   auto widened = [&](double f) {
     std::vector<int> G(list.size());
     for (size_t i = 0; i < list.size(); ++i)
@@ -567,7 +638,7 @@ void widen_groups(std::vector<CoopDesc>& list) {
   }
   const std::vector<int> G = widened(lo);
   for (size_t i = 0; i < list.size(); ++i) {
-    CoopDesc& q = list[i];
+    CoopDescT<FT>& q = list[i];
     if (G[i] == q.G) continue;
     const bool capped = q.ncap_lds < q.ncap;   // LDS columns limited below ncap
     const int capl = q.ncap_lds;
@@ -577,7 +648,23 @@ void widen_groups(std::vector<CoopDesc>& list) {
   }
 }
 
-void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
+namespace {
+
+// The factorization with row panels and factor entries of type FT (double:
+// SPAND_FP64; float: SPAND_FP32 and SPAND_FP32_BF16).
+template <class FT>
+void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
+  using PotrfD = PotrfDescT<FT>;
+  using GemmD = GemmDescT<FT>;
+  using GemmTm = GemmTermT<FT>;
+  using CpqrD = CpqrDescT<FT>;
+  using CpqrN = CpqrNbrT<FT>;
+  using CoopD = CoopDescT<FT>;
+  using WyD = WyDescT<FT>;
+  using CopyD = CopyDescT<FT, FT>;
+  auto Pt = [](void* p) { return static_cast<FT*>(p); };
+  constexpr bool kF32 = sizeof(FT) == 4;
+  F.f32 = kF32;
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = C.stream;
   const int D = P.depth;
@@ -651,7 +738,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   int cur = 0;
   PanelLayout lay_store;
   const PanelLayout* layp = &P.leaf_layout;
-  double* panel = static_cast<double*>(C.panels[cur].ensure(layp->total * sizeof(double)));
+  FT* panel = static_cast<FT*>(C.panels[cur].ensure(layp->total * sizeof(FT)));
   SPAND_PROF(C, "k_fill", launch_fill(panel, layp->total, 0.0, s));
   SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
 
@@ -691,7 +778,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     int32_t* d_ncur = C.upload.upload(sizes);
 
     // ---------------- (a) interiors ----------------
-    std::vector<PotrfDesc> pd;
+    std::vector<PotrfD> pd;
     std::vector<int32_t> pd_cluster;
     int max_n = 0;
     for (int sI = 0; sI < nI; ++sI) {
@@ -699,9 +786,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       const int64_t ks = lay.width[sI] - ns;
       R.kint[sI] = (int32_t)ks;
       if (ns == 0) continue;
-      R.Linv[sI] = F.arena.alloc_n<double>((size_t)ns * ns);
-      if (ks > 0) R.G[sI] = F.arena.alloc_n<double>((size_t)ns * ks);
-      pd.push_back({panel + lay.off[sI], R.Linv[sI], ns, ns, sI, 0});
+      R.Linv[sI] = F.arena.alloc_n<FT>((size_t)ns * ns);
+      if (ks > 0) R.G[sI] = F.arena.alloc_n<FT>((size_t)ns * ks);
+      pd.push_back({panel + lay.off[sI], Pt(R.Linv[sI]), ns, ns, sI, 0});
       pd_cluster.push_back(sI);
       max_n = std::max(max_n, ns);
       flops += (double)ns * ns * ns / 3.0 + (double)ns * ns * ks + (double)ns * ks * ks;
@@ -709,20 +796,21 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     }
     if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
     if (!pd.empty()) {
-      order_potrf(pd, pd_cluster);
-      const auto* d_pd = C.upload.upload(pd);
-      SPAND_PROF(C, "k_potrf_inv", launch_potrf_split(pd, d_pd, d_info_i, s));
+      PotrfLaunch<FT> pl;
+      prep_potrf(C, pd, pd_cluster, l < o.top_fp64_levels, pl);
+      pd_cluster = pl.clusters;
+      SPAND_PROF(C, "k_potrf_inv", run_potrf(pl, d_info_i, s));
       // G_s = L_s^{-1} B_{s,W}
-      std::vector<GemmDesc> gd;
-      std::vector<GemmTerm> gt;
+      std::vector<GemmD> gd;
+      std::vector<GemmTm> gt;
       std::vector<TileRef> tiles;
       for (int sI = 0; sI < nI; ++sI) {
         const int ns = sizes[sI];
         const int ks = R.kint[sI];
         if (ns == 0 || ks == 0) continue;
-        gt.push_back({R.Linv[sI], panel + lay.off[sI] + (int64_t)ns * ns, ns, ns, ns, 0});
-        GemmDesc g{};
-        g.C = R.G[sI];
+        gt.push_back({Pt(R.Linv[sI]), panel + lay.off[sI] + (int64_t)ns * ns, ns, ns, ns, 0});
+        GemmD g{};
+        g.C = Pt(R.G[sI]);
         g.C2 = nullptr;
         g.term0 = (int64_t)gt.size() - 1;
         g.term1 = (int64_t)gt.size();
@@ -738,7 +826,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         const auto* d_gd = C.upload.upload(gd);
         const auto* d_gt = C.upload.upload(gt);
         const auto* d_tiles = C.upload.upload(tiles);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), kGemmNative, s));
       }
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
       // from the plan: targets and their interiors in ascending order).  The
@@ -775,11 +863,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         o_tl[c + 1] += o_tl[c];
       }
       if (o_tl[nchunk] > 0) {
-        GemmDesc* d_sgd = nullptr;
-        GemmTerm* d_sgt = nullptr;
+        GemmD* d_sgd = nullptr;
+        GemmTm* d_sgt = nullptr;
         TileRef* d_stl = nullptr;
-        GemmDesc* hgd = C.upload.stage<GemmDesc>((size_t)o_gd[nchunk], &d_sgd);
-        GemmTerm* hgt = C.upload.stage<GemmTerm>((size_t)o_gt[nchunk], &d_sgt);
+        GemmD* hgd = C.upload.stage<GemmD>((size_t)o_gd[nchunk], &d_sgd);
+        GemmTm* hgt = C.upload.stage<GemmTm>((size_t)o_gt[nchunk], &d_sgt);
         TileRef* htl = C.upload.stage<TileRef>((size_t)o_tl[nchunk], &d_stl);
         host_parallel(nchunk, nth, [&](int c) {
           int64_t igd = o_gd[c], igt = o_gt[c], itl = o_tl[c];
@@ -794,11 +882,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
               if (ns == 0) continue;
               const int64_t c1 = lay.coff[tm.e1] - ns;
               const int64_t c2 = lay.coff[tm.e2] - ns;
-              hgt[igt++] = GemmTerm{R.G[tm.s] + c1 * ns, R.G[tm.s] + c2 * ns, ns, ns, ns, 0};
+              hgt[igt++] = GemmTm{Pt(R.G[tm.s]) + c1 * ns, Pt(R.G[tm.s]) + c2 * ns, ns, ns, ns, 0};
             }
             if (igt == t0) continue;
-            GemmDesc& g = hgd[igd];
-            g = GemmDesc{};
+            GemmD& g = hgd[igd];
+            g = GemmD{};
             g.C = blk(w1, tg.e);
             g.C2 = w1 == w2 ? nullptr : blk(w2, st.adj_rev[tg.e]);
             g.term0 = t0;
@@ -819,7 +907,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         C.upload.commit(hgd, (size_t)o_gd[nchunk]);
         C.upload.commit(hgt, (size_t)o_gt[nchunk]);
         C.upload.commit(htl, (size_t)o_tl[nchunk]);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], s));
+        // the Schur products from BF16 operands below the top FP64 levels
+        // (SPAND_FP32_BF16); in the panels' own precision otherwise
+        const GemmMode sm = o.precision == SPAND_FP32_BF16 && l >= o.top_fp64_levels ? kGemmBf16
+                                                                                     : kGemmNative;
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], sm, s));
       }
     }
 
@@ -831,27 +923,28 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
 
     // ---------------- (b) scaling and (c) sparsification ----------------
     std::vector<char> coop_used;
-    std::vector<PotrfDesc> zd;
+    std::vector<PotrfD> zd;
     std::vector<int32_t> zd_cluster;
     if (st.sparsified) {
       int max_a = 0;
       for (int p = nI; p < nc; ++p) {
         const int a = sizes[p];
         if (a == 0) continue;
-        R.Zinv[p] = F.arena.alloc_n<double>((size_t)a * a);
-        zd.push_back({blk(p, find_adj(st, p, p)), R.Zinv[p], a, a, p, 0});
+        R.Zinv[p] = F.arena.alloc_n<FT>((size_t)a * a);
+        zd.push_back({blk(p, find_adj(st, p, p)), Pt(R.Zinv[p]), a, a, p, 0});
         zd_cluster.push_back(p);
         max_a = std::max(max_a, a);
         flops += (double)a * a * a / 3.0;
         nnzL += (int64_t)a * (a + 1) / 2;
       }
       if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
-      order_potrf(zd, zd_cluster);
-      const auto* d_zd = C.upload.upload(zd);
-      SPAND_PROF(C, "k_potrf_inv", launch_potrf_split(zd, d_zd, d_info_f, s));
+      PotrfLaunch<FT> zl;
+      prep_potrf(C, zd, zd_cluster, l < o.top_fp64_levels, zl);
+      zd_cluster = zl.clusters;
+      SPAND_PROF(C, "k_potrf_inv", run_potrf(zl, d_info_f, s));
       // two-sided scaling of every interface pair p < q
-      std::vector<GemmDesc> g1, g2;
-      std::vector<GemmTerm> t1, t2;
+      std::vector<GemmD> g1, g2;
+      std::vector<GemmTm> t1, t2;
       std::vector<TileRef> tl1, tl2;
       int64_t toff = 0;
       std::vector<int64_t> tpos;
@@ -862,16 +955,16 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           tpos.push_back(toff);
           toff += (int64_t)sizes[p] * sizes[q];
         }
-      double* T = static_cast<double*>(C.temp.ensure(std::max<int64_t>(toff, 1) * sizeof(double)));
+      FT* T = static_cast<FT*>(C.temp.ensure(std::max<int64_t>(toff, 1) * sizeof(FT)));
       size_t ti = 0;
       for (int p = nI; p < nc; ++p)
         for (int64_t e = st.adj_ptr[p]; e < st.adj_ptr[p + 1]; ++e) {
           const int q = st.adj[e];
           if (q <= p || sizes[p] == 0 || sizes[q] == 0) continue;
           const int ap = sizes[p], aq = sizes[q];
-          double* Tpq = T + tpos[ti++];
-          t1.push_back({R.Zinv[p], blk(p, e), ap, ap, ap, 0});
-          GemmDesc a{};
+          FT* Tpq = T + tpos[ti++];
+          t1.push_back({Pt(R.Zinv[p]), blk(p, e), ap, ap, ap, 0});
+          GemmD a{};
           a.C = Tpq;
           a.term0 = (int64_t)t1.size() - 1;
           a.term1 = (int64_t)t1.size();
@@ -881,8 +974,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           a.alpha = 1.0;
           g1.push_back(a);
           add_gemm_tiles(tl1, (int32_t)g1.size() - 1, ap, aq, false);
-          t2.push_back({Tpq, R.Zinv[q], ap, aq, aq, 0});
-          GemmDesc b{};
+          t2.push_back({Tpq, Pt(R.Zinv[q]), ap, aq, aq, 0});
+          GemmD b{};
           b.C = blk(p, e);
           b.C2 = blk(q, st.adj_rev[e]);
           b.term0 = (int64_t)t2.size() - 1;
@@ -900,13 +993,11 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         const auto* d_g1 = C.upload.upload(g1);
         const auto* d_t1 = C.upload.upload(t1);
         const auto* d_tl1 = C.upload.upload(tl1);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1,
-                    (int64_t)tl1.size(), s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1, (int64_t)tl1.size(), kGemmNative, s));
         const auto* d_g2 = C.upload.upload(g2);
         const auto* d_t2 = C.upload.upload(t2);
         const auto* d_tl2 = C.upload.upload(tl2);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2,
-                    (int64_t)tl2.size(), s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2, (int64_t)tl2.size(), kGemmNative, s));
       }
       // sparsification, one launch per colour: interfaces whose coupling fits
       // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
@@ -920,14 +1011,14 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       launch_fill_int(sync_all, sync_cap, s);
       int64_t sync_used = 0;
       for (int colour = 0; colour < st.ncolours; ++colour) {
-        std::vector<CpqrDesc> cd;
-        std::vector<CoopDesc> qd;
-        std::vector<CpqrNbr> cn;
+        std::vector<CpqrD> cd;
+        std::vector<CoopD> qd;
+        std::vector<CpqrN> cn;
         int ma = 1, mk = 1;
         for (int p : st.order) {
           if (st.colour[p] != colour) continue;
           const int a = sizes[p];
-          CpqrDesc d{};
+          CpqrD d{};
           d.panel = panel + lay.off[p];
           d.a = a;
           d.p = p;
@@ -937,7 +1028,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             const int w = st.adj[e];
             if (w == p) { d.diag_col = lay.coff[e]; continue; }
             if (w < nI) continue;
-            CpqrNbr nb{};
+            CpqrN nb{};
             nb.blk_wp = blk(w, st.adj_rev[e]);
             nb.col = lay.coff[e];
             nb.w = w;
@@ -950,16 +1041,16 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           R.kmax[p] = kmax;
           const int64_t mn = std::min<int64_t>(a, kmax);
           if (a > 0 && kmax > 0) {
-            R.Y[p] = F.arena.alloc_n<double>((size_t)a * kmax);
-            R.V[p] = F.arena.alloc_n<double>((size_t)a * mn);
-            R.tau[p] = F.arena.alloc_n<double>((size_t)mn);
-            R.T[p] = F.arena.alloc_n<double>((size_t)mn * mn);
+            R.Y[p] = F.arena.alloc_n<FT>((size_t)a * kmax);
+            R.V[p] = F.arena.alloc_n<FT>((size_t)a * mn);
+            R.tau[p] = F.arena.alloc_n<FT>((size_t)mn);
+            R.T[p] = F.arena.alloc_n<FT>((size_t)mn * mn);
           }
-          d.Y = R.Y[p];
-          d.V = R.V[p];
-          d.tau = R.tau[p];
-          d.T = R.T[p];
-          const int64_t cap = !(a > 0) ? 0 : coop_cols(a);
+          d.Y = Pt(R.Y[p]);
+          d.V = Pt(R.V[p]);
+          d.tau = Pt(R.tau[p]);
+          d.T = Pt(R.T[p]);
+          const int64_t cap = !(a > 0) ? 0 : coop_cols<FT>(a);
           int64_t G = cap > 0 ? (kmax + cap - 1) / cap : 0;
           if (o.qr_group > 0) G = std::max(G, std::min<int64_t>(o.qr_group, kmax));
           // too wide for kCoopMaxGroup workgroups' LDS: kCoopMaxGroup
@@ -968,7 +1059,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
               (kmax + kCoopMaxGroup - 1) / kCoopMaxGroup <= kCoopOverflow * cap)
             G = kCoopMaxGroup;
           if (o.qr_group >= 0 && a > 0 && kmax > 0 && G >= 1 && G <= kCoopMaxGroup) {
-            CoopDesc q{};
+            CoopD q{};
             q.d = d;
             q.G = (int32_t)G;
             q.ncap = (int32_t)((kmax + G - 1) / G);
@@ -986,7 +1077,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           mk = std::max<int>(mk, (int)kmax);
           cd.push_back(d);
         }
-        const CpqrNbr* d_cn = C.upload.upload(cn);
+        const CpqrN* d_cn = C.upload.upload(cn);
         if (!cd.empty()) {
           const auto* d_cd = C.upload.upload(cd);
           SPAND_PROF(C, "k_cpqr", launch_cpqr(d_cd, d_cn, (int32_t)cd.size(), d_ncur, d_r, d_r2,
@@ -996,14 +1087,14 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
         // groups per launch as can be co-resident
         {
-          std::vector<CoopDesc>& list = qd;
+          std::vector<CoopD>& list = qd;
           size_t lds = 0;
           int cap_blocks = 0;
           bool panel = false;   // some workgroup keeps columns in the row panel
-          for (const CoopDesc& q : list) panel = panel || q.ncap_lds < q.ncap;
-          for (const CoopDesc& q : list)
-            lds = std::max(lds, coop_lds_bytes(q.d.a, q.ncap, q.ncap_lds));
-          if (!list.empty()) cap_blocks = coop_max_blocks(lds, panel);
+          for (const CoopD& q : list) panel = panel || q.ncap_lds < q.ncap;
+          for (const CoopD& q : list)
+            lds = std::max(lds, coop_lds_bytes<FT>(q.d.a, q.ncap, q.ncap_lds));
+          if (!list.empty()) cap_blocks = coop_max_blocks<FT>(lds, panel);
           const int slots = cap_blocks / kCoopXcds;
           if (!list.empty() && slots <= 0)
             throw Error(SPAND_E_HIP, "cooperative QR cannot be made resident");
@@ -1033,10 +1124,10 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             }
             // compute units this launch leaves idle: widen its groups and
             // place them again (the pivot sequence does not depend on G)
-            std::vector<CoopDesc> mq;
+            std::vector<CoopD> mq;
             for (int i : members) mq.push_back(list[i]);
             if (o.qr_group == 0 && slots >= kCoopMaxGroup) {
-              std::vector<CoopDesc> wq = mq;
+              std::vector<CoopD> wq = mq;
               widen_groups(wq);
               bool changed = false;
               for (size_t b = 0; b < wq.size(); ++b) changed = changed || wq[b].G != mq[b].G;
@@ -1071,16 +1162,16 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
             const int nblocks = maxfill * kCoopXcds;
             std::vector<int32_t> blk_map((size_t)nblocks, -1);
             int64_t xdoubles = 0;
-            for (const CoopDesc& q : mq) xdoubles += coop_xch_doubles(q.G, q.d.a);
+            for (const CoopD& q : mq) xdoubles += coop_xch_doubles(q.G, q.d.a);
             int32_t* sync = sync_all + sync_used;
             sync_used += (int64_t)members.size() * kCoopSyncInts;
             if (sync_used > sync_cap)
               throw Error(SPAND_E_STATE, "internal: cooperative QR barrier words exhausted");
             double* xch = C.upload.scratch_n<double>((size_t)xdoubles);
-            std::vector<CoopDesc> batch;
+            std::vector<CoopD> batch;
             int64_t xo = 0;
             for (size_t bi = 0; bi < members.size(); ++bi) {
-              CoopDesc q = mq[bi];
+              CoopD q = mq[bi];
               q.xcd = o.qr_xcd_local ? at_xcd[bi] : -1;
               q.sync = sync + bi * kCoopSyncInts;
               q.xch = xch + xo;
@@ -1127,7 +1218,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     // step (positions, statistics, apply records) follows while it runs
     std::vector<int32_t> nsz;
     PanelLayout nlay;
-    double* npanel = nullptr;
+    FT* npanel = nullptr;
     if (!stop_here) {
       const StepPlan& nx = P.steps[l - 1];
       nsz.assign(nx.nc, 0);
@@ -1139,8 +1230,8 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
           nsz[c] += cur_sizes[ch];
         }
       nlay = make_layout(nx, nsz);
-      npanel = static_cast<double*>(
-          C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(double)));
+      npanel = static_cast<FT*>(
+          C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(FT)));
       SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
       const int64_t nm = (int64_t)st.merge.size();
       const int mth = desc_threads((size_t)nm);
@@ -1155,15 +1246,15 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         o_cp[c + 1] = k;
       });
       for (int c = 0; c < mchunk; ++c) o_cp[c + 1] += o_cp[c];
-      CopyDesc* d_cp = nullptr;
-      CopyDesc* hcp = C.upload.stage<CopyDesc>((size_t)o_cp[mchunk], &d_cp);
+      CopyD* d_cp = nullptr;
+      CopyD* hcp = C.upload.stage<CopyD>((size_t)o_cp[mchunk], &d_cp);
       host_parallel(mchunk, mth, [&](int c) {
         int64_t k = o_cp[c];
         for (int64_t i = nm * c / mchunk; i < nm * (c + 1) / mchunk; ++i) {
           const StepPlan::MergeCopy& mc = st.merge[i];
           if (!live(mc)) continue;
           const int ci = mc.ci, cj = mc.cj, P_ = mc.P;
-          CopyDesc& d = hcp[k++];
+          CopyD& d = hcp[k++];
           d.src = blk(ci, mc.ee);
           d.lds = sizes[ci];
           d.dst = npanel + nlay.off[P_] + (nlay.coff[mc.e] + choff[cj]) * nsz[P_] + choff[ci];
@@ -1181,7 +1272,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       // of this step are built by the apply builder
       for (int p = nI; p < nc; ++p) {
         const int a = sizes[p], r = R.r[p], r2 = R.r2[p], k = R.k[p];
-        if (R.V[p] && r2 > 0) R.VT[p] = F.arena.alloc_n<double>((size_t)a * r2);   // V T, formed at the end
+        if (Pt(R.V[p]) && r2 > 0) R.VT[p] = F.arena.alloc_n<FT>((size_t)a * r2);   // V T, formed at the end
         flops += (double)a * a * k;
         double qr = 0.0;
         for (int j = 0; j < r2; ++j) qr += 4.0 * (a - j) * (double)(k - j);
@@ -1214,8 +1305,9 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       F.dbg_layout = lay;
       F.dbg_ncur = cur_sizes;
       F.dbg_panels.resize(lay.total);
-      SPAND_HIP(hipMemcpy(F.dbg_panels.data(), panel, lay.total * sizeof(double),
-                          hipMemcpyDeviceToHost));
+      std::vector<FT> dbg((size_t)lay.total);
+      SPAND_HIP(hipMemcpy(dbg.data(), panel, lay.total * sizeof(FT), hipMemcpyDeviceToHost));
+      std::copy(dbg.begin(), dbg.end(), F.dbg_panels.begin());
       break;
     }
 
@@ -1237,17 +1329,17 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
     for (const StepRec& R : F.steps)
       for (size_t p = 0; p < R.V.size(); ++p)
         if (R.V[p] && R.r2[p] > kWyLdsN) xdoubles += (int64_t)R.r2[p] * R.r2[p];
-    double* xs = xdoubles ? static_cast<double*>(C.temp.ensure(xdoubles * sizeof(double))) : nullptr;
-    std::vector<GemmDesc> gd;
-    std::vector<GemmTerm> gt;
+    FT* xs = xdoubles ? static_cast<FT*>(C.temp.ensure(xdoubles * sizeof(FT))) : nullptr;
+    std::vector<GemmD> gd;
+    std::vector<GemmTm> gt;
     std::vector<TileRef> tiles;
-    std::vector<WyDesc> wy;
+    std::vector<WyD> wy;
     for (const StepRec& R : F.steps) {
       for (size_t p = 0; p < R.V.size(); ++p) {
-        if (!R.V[p] || R.r2[p] <= 0) continue;
+        if (!Pt(R.V[p]) || R.r2[p] <= 0) continue;
         const int nref = R.r2[p], a = R.n0[p];
-        GemmDesc g{};
-        g.C = R.T[p];
+        GemmD g{};
+        g.C = Pt(R.T[p]);
         g.ldc = nref;
         g.m = nref;
         g.n = nref;
@@ -1257,16 +1349,16 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
         g.alpha = 1.0;
         g.beta = 0.0;
         g.term0 = (int64_t)gt.size();
-        gt.push_back(GemmTerm{R.V[p], R.V[p], a, a, a, 0});
+        gt.push_back(GemmTm{Pt(R.V[p]), Pt(R.V[p]), a, a, a, 0});
         g.term1 = (int64_t)gt.size();
         add_gemm_tiles(tiles, (int32_t)gd.size(), nref, nref, true);
         gd.push_back(g);
-        double* X = nullptr;
+        FT* X = nullptr;
         if (nref > kWyLdsN) {
           X = xs;
           xs += (int64_t)nref * nref;
         }
-        wy.push_back(WyDesc{R.V[p], R.tau[p], R.T[p], X, a, nref});
+        wy.push_back(WyD{Pt(R.V[p]), Pt(R.tau[p]), Pt(R.T[p]), X, a, nref});
       }
     }
     if (!wy.empty()) {
@@ -1274,26 +1366,26 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       const auto* d_gt = C.upload.upload(gt);
       const auto* d_tl = C.upload.upload(tiles);
       const auto* d_wy = C.upload.upload(wy);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), s));
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), kGemmNative, s));
       SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), s));
       // V T of every interface (a x nref): the apply then needs no pass over T
       // (Q^T x = x - V (VT)^T x, Q y = y - VT V^T y)
-      std::vector<GemmDesc> gv;
-      std::vector<GemmTerm> gvt;
+      std::vector<GemmD> gv;
+      std::vector<GemmTm> gvt;
       std::vector<TileRef> vtiles;
       for (const StepRec& R : F.steps)
         for (size_t p = 0; p < R.V.size(); ++p) {
-          if (!R.V[p] || R.r2[p] <= 0) continue;
+          if (!Pt(R.V[p]) || R.r2[p] <= 0) continue;
           const int nref = R.r2[p], a = R.n0[p];
-          GemmDesc g{};
-          g.C = R.VT[p];
+          GemmD g{};
+          g.C = Pt(R.VT[p]);
           g.ldc = a;
           g.m = a;
           g.n = nref;
           g.alpha = 1.0;
           g.beta = 0.0;
           g.term0 = (int64_t)gvt.size();
-          gvt.push_back(GemmTerm{R.V[p], R.T[p], a, nref, nref, 0});
+          gvt.push_back(GemmTm{Pt(R.V[p]), Pt(R.T[p]), a, nref, nref, 0});
           g.term1 = (int64_t)gvt.size();
           add_gemm_tiles(vtiles, (int32_t)gv.size(), a, nref, false);
           gv.push_back(g);
@@ -1301,7 +1393,7 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
       const auto* d_gv = C.upload.upload(gv);
       const auto* d_gvt = C.upload.upload(gvt);
       const auto* d_vtl = C.upload.upload(vtiles);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), s));
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), kGemmNative, s));
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));
@@ -1315,6 +1407,13 @@ void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fact
   F.stats.factor_bytes = (int64_t)F.arena.bytes_used();
   F.stats.factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+void run_factor(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, FactorObj& F) {
+  if (o.precision == SPAND_FP64) run_factor_t<double>(C, P, d_vals, o, F);
+  else run_factor_t<float>(C, P, d_vals, o, F);
 }
 
 }  // namespace spand

@@ -1,4 +1,7 @@
-// HIP kernels of the factorization (FP64, gfx950).
+// HIP kernels of the factorization (gfx950).  Every kernel is a template on
+// the element type R of the row panels and of the stored factor (double for
+// SPAND_FP64, float for the FP32 forms), except the large-block Cholesky,
+// which exists in FP64 only.
 //
 //  k_potrf_inv_small : batched Cholesky + triangular inverse of blocks of at
 //                most 64 rows, one wave per block, the block in registers.
@@ -17,6 +20,7 @@
 //  k_fill, k_scatter, k_copy : assembly of the leaf panels from CSR values and
 //                the merge of child blocks into parent panels.
 #include <climits>
+#include <type_traits>
 
 #include "device.h"
 
@@ -32,6 +36,12 @@ __device__ __forceinline__ double dpp_move(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), kCtrl, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
+}
+
+// DPP move of a float.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
 }
 
 // Sum over the 64 lanes, returned to every lane.  Quad permutations and row
@@ -50,13 +60,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 // Sum over each group of 8 lanes, returned to all 8: two quad permutations and
 // a half-row mirror.
-__device__ __forceinline__ double group8_sum(double v) {
+template <class R>
+__device__ __forceinline__ R group8_sum(R v) {
   v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);  // row_half_mirror
   return v;
 }
-__device__ __forceinline__ double wave_max(double v) {
+template <class R>
+__device__ __forceinline__ R wave_max(R v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
   return v;
@@ -121,6 +133,12 @@ __device__ __forceinline__ double rsqrt_nr(double v) {
   y = y * fma(-h * y, y, 1.5);
   return y;
 }
+// FP32: the hardware estimate and one Newton step.
+__device__ __forceinline__ float rsqrt_nr(float v) {
+  float y = __builtin_amdgcn_rsqf(v);
+  const float h = 0.5f * v;
+  return y * fmaf(-h * y, y, 1.5f);
+}
 
 // ---------------------------------------------------------------------------
 // Cholesky of an n x n SPD block (n <= 64, column-major in LDS, lower triangle
@@ -129,11 +147,11 @@ __device__ __forceinline__ double rsqrt_nr(double v) {
 // column (S_ic -= S_ij S_cj / v), and scales the previous column, which is no
 // longer read.  Returns 0 or the 1-based column of the first non-positive pivot.
 // ---------------------------------------------------------------------------
-template <int NT>
-__device__ int chol_inplace(double* S, int n, int ld) {
+template <int NT, class R>
+__device__ int chol_inplace(R* S, int n, int ld) {
   constexpr int TX = 16, TY = NT / TX;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  double vprev = 0.0, rprev = 0.0;
+  R vprev = 0, rprev = 0;
   for (int j = 0; j <= n; ++j) {
     if (j > 0) {   // finish column j-1: l_jj = v rsqrt(v), l_ij = s_ij rsqrt(v)
       const int jp = j - 1;
@@ -141,11 +159,11 @@ __device__ int chol_inplace(double* S, int n, int ld) {
       if (threadIdx.x == 0) S[jp + (int64_t)jp * ld] = vprev * rprev;
     }
     if (j == n) break;
-    const double v = S[j + (int64_t)j * ld];
-    if (!(v > 0.0)) return j + 1;   // every thread reads the same value
-    const double rs = rsqrt_nr(v), rv = rs * rs;
+    const R v = S[j + (int64_t)j * ld];
+    if (!(v > R(0))) return j + 1;   // every thread reads the same value
+    const R rs = rsqrt_nr(v), rv = rs * rs;
     for (int c = j + 1 + ty; c < n; c += TY) {
-      const double scj = S[c + (int64_t)j * ld] * rv;
+      const R scj = S[c + (int64_t)j * ld] * rv;
       for (int i = c + tx; i < n; i += TX)
         S[i + (int64_t)c * ld] = fma(-S[i + (int64_t)j * ld], scj, S[i + (int64_t)c * ld]);
     }
@@ -163,14 +181,14 @@ __device__ int chol_inplace(double* S, int n, int ld) {
 // below the diagonal follow one block diagonal at a time,
 // X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  tmp: 768 doubles of LDS (first the
 // reciprocals of L's diagonal).
-template <int NT>
-__device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, double* tmp) {
+template <int NT, class R>
+__device__ void trinv(const R* L, int ldl, R* X, int ldx, int n, R* tmp) {
   static_assert(NT >= 256, "one wave per 16-row diagonal block");
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int nbk = (n + 15) / 16;
   for (int c = wid; c < n; c += NT / kWave)
-    for (int i = lane; i < n; i += kWave) X[i + (int64_t)c * ldx] = 0.0;
-  for (int i = tid; i < n; i += NT) tmp[i] = 1.0 / L[i + (int64_t)i * ldl];
+    for (int i = lane; i < n; i += kWave) X[i + (int64_t)c * ldx] = 0;
+  for (int i = tid; i < n; i += NT) tmp[i] = R(1) / L[i + (int64_t)i * ldl];
   __syncthreads();
   if (wid < nbk && lane < 16) {
     const int b0 = wid * 16, bw = min(16, n - b0), c = lane;
@@ -179,7 +197,7 @@ __device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, doubl
       X[gc + (int64_t)gc * ldx] = tmp[gc];
       for (int i = c + 1; i < bw; ++i) {
         const int gi = b0 + i;
-        double acc = 0.0;
+        R acc = 0;
         for (int k = c; k < i; ++k)
           acc = fma(L[gi + (int64_t)(b0 + k) * ldl], X[b0 + k + (int64_t)gc * ldx], acc);
         X[gi + (int64_t)gc * ldx] = -acc * tmp[gi];
@@ -192,7 +210,7 @@ __device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, doubl
     for (int idx = tid; idx < nblk * 256; idx += NT) {   // S_IJ = sum_K L_IK X_KJ
       const int q = idx >> 8, e = idx & 255, ii = e & 15, jj = e >> 4;
       const int I = q + dd, i = I * 16 + ii, j = q * 16 + jj;
-      double acc = 0.0;
+      R acc = 0;
       if (i < n && j < n)
         for (int k = q * 16; k < I * 16; ++k)
           acc = fma(L[i + (int64_t)k * ldl], X[k + (int64_t)j * ldx], acc);
@@ -203,7 +221,7 @@ __device__ void trinv(const double* L, int ldl, double* X, int ldx, int n, doubl
       const int q = idx >> 8, e = idx & 255, ii = e & 15, jj = e >> 4;
       const int I = q + dd, i = I * 16 + ii, j = q * 16 + jj;
       if (i < n && j < n) {
-        double acc = 0.0;
+        R acc = 0;
         for (int k = I * 16; k <= i; ++k)
           acc = fma(X[i + (int64_t)k * ldx], tmp[(q << 8) + (k - I * 16) + jj * 16], acc);
         X[i + (int64_t)j * ldx] = -acc;
@@ -218,21 +236,22 @@ constexpr int kNb = 64;          // tile of the blocked Cholesky / inverse
 constexpr int kTl = kNb + 1;     // padded leading dimension of LDS tiles
 
 // LDS tile <- rows x cols block of a column-major global matrix (zero padded).
-__device__ __forceinline__ void tile_load(double* t, const double* g, int64_t ld, int rows,
-                                          int cols) {
+template <class R>
+__device__ __forceinline__ void tile_load(R* t, const R* g, int64_t ld, int rows, int cols) {
   for (int idx = threadIdx.x; idx < kNb * kNb; idx += kPotrfThreads) {
     const int i = idx % kNb, j = idx / kNb;
-    t[i + j * kTl] = (i < rows && j < cols) ? g[i + j * ld] : 0.0;
+    t[i + j * kTl] = (i < rows && j < cols) ? g[i + j * ld] : R(0);
   }
 }
 
 // acc (4x4 per thread, rows tx+16r, cols ty+16c) += A * op(B) over kk < kdim,
 // A and B 64x64 LDS tiles; transB: B is used transposed.
-__device__ __forceinline__ void tile_mma(double (&acc)[4][4], const double* A, const double* B,
-                                         int kdim, bool transB) {
+template <class R>
+__device__ __forceinline__ void tile_mma(R (&acc)[4][4], const R* A, const R* B, int kdim,
+                                         bool transB) {
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   for (int kk = 0; kk < kdim; ++kk) {
-    double a[4], b[4];
+    R a[4], b[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) a[r] = A[tx + 16 * r + kk * kTl];
 #pragma unroll
@@ -244,23 +263,25 @@ __device__ __forceinline__ void tile_mma(double (&acc)[4][4], const double* A, c
   }
 }
 
-__device__ __forceinline__ void acc_zero(double (&acc)[4][4]) {
+template <class R>
+__device__ __forceinline__ void acc_zero(R (&acc)[4][4]) {
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0;
 }
 
 // Off-diagonal tiles of X = L^{-1} for a lower triangular L (in A, ld n) whose
 // diagonal tiles of X are already in place, column block by column block:
 // X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  The strictly upper part of X is
 // zeroed.  LDS: two 64x65 tiles.
-__device__ void lower_inv_offdiag(const double* A, double* X, int n, double* lds) {
-  double* T1 = lds + kNb * kTl;
-  double* T2 = lds + 2 * kNb * kTl;
+template <class R>
+__device__ void lower_inv_offdiag(const R* A, R* X, int n, R* lds) {
+  R* T1 = lds + kNb * kTl;
+  R* T2 = lds + 2 * kNb * kTl;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int nb = (n + kNb - 1) / kNb;
-  double acc[4][4];
+  R acc[4][4];
   // off-diagonal tiles of X = L^{-1}, column block by column block
   for (int jb = 0; jb < nb; ++jb) {
     const int j0 = jb * kNb, jw = min(kNb, n - j0);
@@ -291,7 +312,7 @@ __device__ void lower_inv_offdiag(const double* A, double* X, int n, double* lds
           const int i = tx + 16 * r, j = ty + 16 * c;
           if (i < iw && j < jw) {
             X[i0 + i + (int64_t)(j0 + j) * n] = -acc[r][c];
-            X[j0 + j + (int64_t)(i0 + i) * n] = 0.0;   // strictly upper part
+            X[j0 + j + (int64_t)(i0 + i) * n] = 0;   // strictly upper part
           }
         }
       __syncthreads();
@@ -300,18 +321,21 @@ __device__ void lower_inv_offdiag(const double* A, double* X, int n, double* lds
 }
 
 // Blocks of at most 64 rows, one workgroup per block, in LDS.
-__global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* descs, int32_t* info) {
-  extern __shared__ double sm[];
-  const PotrfDesc d = descs[blockIdx.x];
+template <class R>
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDescT<R>* descs,
+                                                             int32_t* info) {
+  extern __shared__ __align__(16) char smraw[];
+  R* sm = reinterpret_cast<R*>(smraw);
+  const PotrfDescT<R> d = descs[blockIdx.x];
   const int n = d.n;
   if (n == 0) return;
   const int tid = threadIdx.x;
-  double* S = sm;
-  double* X = sm + n * n;
-  double* tmp = X + n * n;
+  R* S = sm;
+  R* X = sm + n * n;
+  R* tmp = X + n * n;
   for (int idx = tid; idx < n * n; idx += kPotrfThreads) {
     const int i = idx % n, j = idx / n;
-    S[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : 0.0;
+    S[idx] = i >= j ? d.A[i + (int64_t)j * d.lda] : R(0);
   }
   __syncthreads();
   const int f = chol_inplace<kPotrfThreads>(S, n, n);
@@ -319,7 +343,7 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_inv(const PotrfDesc* de
     // breakdown: report it and leave a zero inverse, so that the products
     // formed with it before the flag is read stay finite
     if (tid == 0) info[blockIdx.x] = f;
-    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = 0.0;
+    for (int idx = tid; idx < n * n; idx += kPotrfThreads) d.X[idx] = 0;
     return;
   }
   trinv<kPotrfThreads>(S, n, X, n, n, tmp);
@@ -535,42 +559,45 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float readlane_d(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
 
-template <int NM>
-__global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const PotrfDesc* descs,
+template <class R, int NM>
+__global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const PotrfDescT<R>* descs,
                                                                         int32_t count,
                                                                         int32_t* info) {
-  __shared__ double colbuf[kSmallWaves][NM];
+  __shared__ R colbuf[kSmallWaves][NM];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int b = blockIdx.x * kSmallWaves + w;
   if (b >= count) return;   // the whole wave leaves; no workgroup barriers follow
-  const PotrfDesc d = descs[b];
+  const PotrfDescT<R> d = descs[b];
   const int n = d.n;
   if (n == 0) return;
-  double* cb = colbuf[w];
-  double row[NM];
+  R* cb = colbuf[w];
+  R row[NM];
 #pragma unroll
   for (int c = 0; c < NM; ++c)
-    row[c] = (lane < n && c < n) ? (c <= lane ? d.A[lane + (int64_t)c * d.lda] : 0.0)
-                                 : (c == lane ? 1.0 : 0.0);
+    row[c] = (lane < n && c < n) ? (c <= lane ? d.A[lane + (int64_t)c * d.lda] : R(0))
+                                 : (c == lane ? R(1) : R(0));
   int fail = 0;
-  double rdl = 1.0;   // lane j: 1 / l_jj (1 in the identity padding)
+  R rdl = 1;   // lane j: 1 / l_jj (1 in the identity padding)
 #pragma unroll
   for (int j = 0; j < NM; ++j) {
-    const double v = readlane_d(row[j], j);
-    if (!(v > 0.0)) {   // the same value in every lane
+    const R v = readlane_d(row[j], j);
+    if (!(v > R(0))) {   // the same value in every lane
       fail = j + 1;
       break;
     }
-    const double rs = rsqrt_nr(v);
-    const double lij = lane > j ? row[j] * rs : (lane == j ? v * rs : 0.0);
+    const R rs = rsqrt_nr(v);
+    const R lij = lane > j ? row[j] * rs : (lane == j ? v * rs : R(0));
     if (lane == j) rdl = rs;   // 1 / l_jj, for the inverse
     if (lane >= j) row[j] = lij;
     if (lane < NM) cb[lane] = lij;
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int c = j + 1; c < NM; ++c) {
-      const double lcj = cb[c];
+      const R lcj = cb[c];
       if (lane >= c) row[c] = fma(-lij, lcj, row[c]);
     }
     __builtin_amdgcn_wave_barrier();
@@ -578,15 +605,15 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
   if (fail) {
     if (lane == 0) info[b] = fail;
     for (int c = 0; c < n; ++c)
-      if (lane < n) d.X[lane + (int64_t)c * n] = 0.0;
+      if (lane < n) d.X[lane + (int64_t)c * n] = 0;
     return;
   }
 #pragma unroll
   for (int j = NM - 1; j >= 0; --j) {
     if (lane < NM) cb[lane] = row[j];   // column j of L, before it is overwritten
     __builtin_amdgcn_wave_barrier();
-    const double xjj = readlane_d(rdl, j);
-    double acc = 0.0;
+    const R xjj = readlane_d(rdl, j);
+    R acc = 0;
 #pragma unroll
     for (int m = j + 1; m < NM; ++m)
       if (lane >= m) acc = fma(row[m], cb[m], acc);
@@ -601,35 +628,62 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
 
 // ---------------------------------------------------------------------------
 // Batched multi-term GEMM, 64x64 tile per workgroup: k-slabs of A and B staged
-// in LDS, each wave a 32x32 quadrant as 2x2 FP64 matrix-core tiles
-// (16 x 16 x 4 per instruction).
+// in LDS, each wave a 32x32 quadrant as 2x2 matrix-core tiles of 16 x 16:
+// FP64 (16 x 16 x 4 per instruction, R = double), FP32 (16 x 16 x 4, R =
+// float) or BF16 operands rounded from the FP32 slab (16 x 16 x 16, FP32
+// accumulation; MODE = kGemmBf16).
 // ---------------------------------------------------------------------------
 constexpr int kGemmThreads = 256;
 constexpr int kGemmK = 16;
 
-__global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDesc* descs, const GemmTerm* terms,
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+// FP32 16 x 16 x 4: operands as in mfma16; the accumulator gives lane l rows
+// 4 (l / 16) + v, v = 0..3, of column l % 16.
+__device__ __forceinline__ f4_t mfma16f(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// BF16 16 x 16 x 16: lane l supplies row l % 16 of the left factor at columns
+// 4 (l / 16) + t and column l % 16 of the right factor at rows 4 (l / 16) + t,
+// t = 0..3; FP32 accumulator laid out as in mfma16f.
+__device__ __forceinline__ f4_t mfma16bf(s4_t a, s4_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// FP32 -> BF16, rounded to nearest (ties to even); the inputs are finite
+__device__ __forceinline__ short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+template <class R, int MODE>
+__global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDescT<R>* descs,
+                                                        const GemmTermT<R>* terms,
                                                         const TileRef* tiles) {
-  __shared__ double As[kGemmK][kGemmTile + 1];
-  __shared__ double Bs[kGemmK][kGemmTile + 1];
+  constexpr bool kF64 = sizeof(R) == 8;
+  using acc_t = typename std::conditional<kF64, d4_t, f4_t>::type;
+  __shared__ R As[kGemmK][kGemmTile + 1];
+  __shared__ R Bs[kGemmK][kGemmTile + 1];
   const TileRef t = tiles[blockIdx.x];
-  const GemmDesc d = descs[t.desc];
+  const GemmDescT<R> d = descs[t.desc];
   const int i0 = t.ti * kGemmTile, j0 = t.tj * kGemmTile;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wr = 32 * (w & 1), wc = 32 * (w >> 1), r = lane & 15, kq = lane >> 4;
-  d4_t acc[2][2];
+  acc_t acc[2][2];
 #pragma unroll
   for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-    for (int ci = 0; ci < 2; ++ci) acc[ri][ci] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int ci = 0; ci < 2; ++ci) acc[ri][ci] = acc_t{0, 0, 0, 0};
   for (int64_t term = d.term0; term < d.term1; ++term) {
-    const GemmTerm tm = terms[term];
+    const GemmTermT<R> tm = terms[term];
     for (int k0 = 0; k0 < tm.k; k0 += kGemmK) {
       for (int e = threadIdx.x; e < kGemmTile * kGemmK; e += kGemmThreads) {
         int ii, kk;
         if (!d.transA) { ii = e % kGemmTile; kk = e / kGemmTile; }
         else { kk = e % kGemmK; ii = e / kGemmK; }
         const int gi = i0 + ii, gk = k0 + kk;
-        double v = 0.0;
+        R v = 0;
         if (gi < d.m && gk < tm.k)
           v = d.transA ? tm.A[gk + (int64_t)gi * tm.lda] : tm.A[gi + (int64_t)gk * tm.lda];
         As[kk][ii] = v;
@@ -639,21 +693,44 @@ __global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDesc* descs,
         if (!d.transB) { kk = e % kGemmK; jj = e / kGemmK; }
         else { jj = e % kGemmTile; kk = e / kGemmTile; }
         const int gj = j0 + jj, gk = k0 + kk;
-        double v = 0.0;
+        R v = 0;
         if (gj < d.n && gk < tm.k)
           v = d.transB ? tm.B[gj + (int64_t)gk * tm.ldb] : tm.B[gk + (int64_t)gj * tm.ldb];
         Bs[kk][jj] = v;
       }
       __syncthreads();
+      if constexpr (MODE == kGemmBf16 && !kF64) {
+        s4_t a0, a1, b0, b1;
 #pragma unroll
-      for (int s4 = 0; s4 < kGemmK / 4; ++s4) {
-        const int kk = 4 * s4 + kq;
-        const double a0 = As[kk][wr + r], a1 = As[kk][wr + 16 + r];
-        const double b0 = Bs[kk][wc + r], b1 = Bs[kk][wc + 16 + r];
-        acc[0][0] = mfma16(a0, b0, acc[0][0]);
-        acc[0][1] = mfma16(a0, b1, acc[0][1]);
-        acc[1][0] = mfma16(a1, b0, acc[1][0]);
-        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+        for (int q = 0; q < 4; ++q) {
+          const int kk = 4 * kq + q;
+          a0[q] = to_bf16(As[kk][wr + r]);
+          a1[q] = to_bf16(As[kk][wr + 16 + r]);
+          b0[q] = to_bf16(Bs[kk][wc + r]);
+          b1[q] = to_bf16(Bs[kk][wc + 16 + r]);
+        }
+        acc[0][0] = mfma16bf(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16bf(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16bf(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16bf(a1, b1, acc[1][1]);
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < kGemmK / 4; ++s4) {
+          const int kk = 4 * s4 + kq;
+          const R a0 = As[kk][wr + r], a1 = As[kk][wr + 16 + r];
+          const R b0 = Bs[kk][wc + r], b1 = Bs[kk][wc + 16 + r];
+          if constexpr (kF64) {
+            acc[0][0] = mfma16(a0, b0, acc[0][0]);
+            acc[0][1] = mfma16(a0, b1, acc[0][1]);
+            acc[1][0] = mfma16(a1, b0, acc[1][0]);
+            acc[1][1] = mfma16(a1, b1, acc[1][1]);
+          } else {
+            acc[0][0] = mfma16f(a0, b0, acc[0][0]);
+            acc[0][1] = mfma16f(a0, b1, acc[0][1]);
+            acc[1][0] = mfma16f(a1, b0, acc[1][0]);
+            acc[1][1] = mfma16f(a1, b1, acc[1][1]);
+          }
+        }
       }
       __syncthreads();
     }
@@ -664,10 +741,11 @@ __global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDesc* descs,
     for (int ci = 0; ci < 2; ++ci)
 #pragma unroll
       for (int v4 = 0; v4 < 4; ++v4) {
-        const int gi = i0 + wr + 16 * ri + kq + 4 * v4, gj = j0 + wc + 16 * ci + r;
+        const int row = kF64 ? kq + 4 * v4 : 4 * kq + v4;
+        const int gi = i0 + wr + 16 * ri + row, gj = j0 + wc + 16 * ci + r;
         if (gi < d.m && gj < d.n) {
-          double v = d.alpha * acc[ri][ci][v4];
-          if (d.beta != 0.0) v = fma(d.beta, d.C[gi + (int64_t)gj * d.ldc], v);
+          R v = R(d.alpha) * acc[ri][ci][v4];
+          if (d.beta != 0.0) v = fma(R(d.beta), d.C[gi + (int64_t)gj * d.ldc], v);
           d.C[gi + (int64_t)gj * d.ldc] = v;
           if (d.C2) d.C2[gj + (int64_t)gi * d.ldc2] = v;
         }
@@ -688,27 +766,29 @@ constexpr int kQrWaves = kQrThreads / kWave;
 constexpr int kQrCache = 8;    // rows of a column kept in registers between passes
 constexpr int kQrUnroll = 8;   // independent loads in flight per thread
 
-__global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, const CpqrNbr* nbrs,
+template <class R>
+__global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDescT<R>* descs, const CpqrNbrT<R>* nbrs,
                                                       int32_t* n_cur, int32_t* out_r,
                                                       int32_t* out_r2, int32_t* out_k,
                                                       double eps, double eps_stop, int32_t max_k) {
-  extern __shared__ double sm[];
-  __shared__ double redd[kQrWaves];
+  extern __shared__ __align__(16) char smraw[];
+  R* sm = reinterpret_cast<R*>(smraw);
+  __shared__ R redd[kQrWaves];
   __shared__ int redi[kQrWaves];
-  const CpqrDesc d = descs[blockIdx.x];
+  const CpqrDescT<R> d = descs[blockIdx.x];
   const int a = d.a;
   const int64_t K = d.kmax;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  double* nrm2 = sm;
-  double* v = sm + max_k;
-  double* __restrict__ Yt = d.Y;
+  R* nrm2 = sm;
+  R* v = sm + max_k;
+  R* __restrict__ Yt = d.Y;
 
   // gather W^T: the neighbours' blocks (p, w) with their current widths
   int k = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) {
-    const CpqrNbr nb = nbrs[e];
+    const CpqrNbrT<R> nb = nbrs[e];
     const int wc = n_cur[nb.w];
-    const double* src = d.panel + nb.col * a;
+    const R* src = d.panel + nb.col * a;
     for (int idx = tid; idx < a * wc; idx += kQrThreads) {
       const int c = idx % wc, i = idx / wc;
       Yt[(k + c) + i * K] = src[i + (int64_t)c * a];
@@ -717,11 +797,11 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
   }
   __syncthreads();
   for (int c = tid; c < k; c += kQrThreads) {
-    const double* col = Yt + c;
-    double s = 0.0;
+    const R* col = Yt + c;
+    R s = 0.0;
     int i = 0;
     for (; i + kQrUnroll <= a; i += kQrUnroll) {
-      double y[kQrUnroll];
+      R y[kQrUnroll];
 #pragma unroll
       for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
 #pragma unroll
@@ -734,19 +814,19 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
 
   int r = -1;
   int j = 0;
-  double R00 = 0.0;
+  R R00 = 0.0;
   const int jmax = min(a, k);
   for (; j < jmax; ++j) {
-    double m = -1.0;
+    R m = -1.0;
     for (int c = tid; c < k; c += kQrThreads) m = fmax(m, nrm2[c]);
     m = wave_max(m);
     if (lane == 0) redd[wid] = m;
     __syncthreads();
-    double M = redd[0];
+    R M = redd[0];
 #pragma unroll
     for (int w = 1; w < kQrWaves; ++w) M = fmax(M, redd[w]);
     if (M < 0.0) break;
-    const double thr = M * (1.0 - kPivotTieRtol);
+    const R thr = M * R(1.0 - PivotTie<R>::rtol);
     int cand = INT_MAX;
     for (int c = tid; c < k; c += kQrThreads)
       if (nrm2[c] >= 0.0 && nrm2[c] >= thr) { cand = c; break; }
@@ -756,16 +836,16 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
     int C = redi[0];
 #pragma unroll
     for (int w = 1; w < kQrWaves; ++w) C = min(C, redi[w]);
-    const double nrm = sqrt(nrm2[C]);
+    const R nrm = sqrt(nrm2[C]);
     if (j == 0) R00 = nrm;
     if (nrm == 0.0 || nrm < eps_stop * R00) break;
     if (r < 0 && nrm < eps * R00) r = j;
-    const double alpha = Yt[C + j * K];
-    const double beta = alpha >= 0.0 ? -nrm : nrm;
-    const double denom = alpha - beta;
-    const double tau = (beta - alpha) / beta;
+    const R alpha = Yt[C + j * K];
+    const R beta = alpha >= R(0) ? -nrm : nrm;
+    const R denom = alpha - beta;
+    const R tau = (beta - alpha) / beta;
     for (int i = tid; i < a; i += kQrThreads) {
-      const double vi = i < j ? 0.0 : (i == j ? 1.0 : Yt[C + i * K] / denom);
+      const R vi = i < j ? R(0) : (i == j ? R(1) : Yt[C + i * K] / denom);
       v[i] = vi;
       d.V[i + (int64_t)j * a] = vi;
     }
@@ -773,39 +853,39 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
     __syncthreads();
     for (int c = tid; c < k; c += kQrThreads) {
       if (c == C || nrm2[c] < 0.0) continue;
-      double* __restrict__ col = Yt + c;
-      double cache[kQrCache];
-      double w0 = 0.0, w1 = 0.0;
+      R* __restrict__ col = Yt + c;
+      R cache[kQrCache];
+      R w0 = 0.0, w1 = 0.0;
 #pragma unroll
       for (int t = 0; t < kQrCache; ++t) {
         const int i = j + t;
-        cache[t] = i < a ? col[i * K] : 0.0;
+        cache[t] = i < a ? col[i * K] : R(0);
       }
 #pragma unroll
-      for (int t = 0; t < kQrCache; ++t) w0 = fma(j + t < a ? v[j + t] : 0.0, cache[t], w0);
+      for (int t = 0; t < kQrCache; ++t) w0 = fma(j + t < a ? v[j + t] : R(0), cache[t], w0);
       int i = j + kQrCache;
       for (; i + kQrUnroll <= a; i += kQrUnroll) {
-        double y[kQrUnroll];
+        R y[kQrUnroll];
 #pragma unroll
         for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
 #pragma unroll
         for (int u = 0; u < kQrUnroll; ++u) w1 = fma(v[i + u], y[u], w1);
       }
       for (; i < a; ++i) w1 = fma(v[i], col[i * K], w1);
-      const double w = (w0 + w1) * tau;
-      double s0 = 0.0, s1 = 0.0;
+      const R w = (w0 + w1) * tau;
+      R s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int t = 0; t < kQrCache; ++t) {
         const int ii = j + t;
         if (ii < a) {
-          const double y = fma(-w, v[ii], cache[t]);
+          const R y = fma(-w, v[ii], cache[t]);
           col[ii * K] = y;
           if (t > 0) s0 = fma(y, y, s0);
         }
       }
       i = j + kQrCache;
       for (; i + kQrUnroll <= a; i += kQrUnroll) {
-        double y[kQrUnroll];
+        R y[kQrUnroll];
 #pragma unroll
         for (int u = 0; u < kQrUnroll; ++u) y[u] = col[(i + u) * K];
 #pragma unroll
@@ -817,13 +897,13 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
         for (int u = 0; u < kQrUnroll; ++u) col[(i + u) * K] = y[u];
       }
       for (; i < a; ++i) {
-        const double y = fma(-w, v[i], col[i * K]);
+        const R y = fma(-w, v[i], col[i * K]);
         col[i * K] = y;
         s1 = fma(y, y, s1);
       }
       nrm2[c] = s0 + s1;
     }
-    for (int i = j + tid; i < a; i += kQrThreads) Yt[C + i * K] = i == j ? beta : 0.0;
+    for (int i = j + tid; i < a; i += kQrThreads) Yt[C + i * K] = i == j ? beta : R(0);
     if (tid == 0) nrm2[C] = -1.0;
     __syncthreads();
   }
@@ -833,11 +913,11 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
   // coarse rows back into p's panel and, transposed, into the neighbours' panels
   int kk = 0;
   for (int64_t e = d.nb0; e < d.nb1; ++e) {
-    const CpqrNbr nb = nbrs[e];
+    const CpqrNbrT<R> nb = nbrs[e];
     const int wc = n_cur[nb.w];
     for (int idx = tid; idx < r * wc; idx += kQrThreads) {
       const int c = idx % wc, i = idx / wc;
-      const double y = Yt[(kk + c) + i * K];
+      const R y = Yt[(kk + c) + i * K];
       d.panel[i + (nb.col + c) * a] = y;
       nb.blk_wp[c + (int64_t)i * nb.ldw] = y;
     }
@@ -845,7 +925,7 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
   }
   for (int idx = tid; idx < r * r; idx += kQrThreads) {
     const int i = idx % r, c = idx / r;
-    d.panel[i + (d.diag_col + c) * a] = i == c ? 1.0 : 0.0;
+    d.panel[i + (d.diag_col + c) * a] = i == c ? R(1) : R(0);
   }
   if (tid == 0) {
     out_k[d.p] = k;
@@ -863,20 +943,21 @@ __global__ __launch_bounds__(kQrThreads) void k_cpqr(const CpqrDesc* descs, cons
 // On entry T holds V^T V in its lower triangle.  The work array A (n x n,
 // column-major) holds T on and above the diagonal and V^T V below it; it lives
 // in LDS when n <= kWyLdsN, else in T itself.  Row sums use 8-lane groups.
-template <bool kInLds>
-__global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
-  extern __shared__ double lds[];
-  const WyDesc d = descs[blockIdx.x];
+template <class R, bool kInLds>
+__global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDescT<R>* descs) {
+  extern __shared__ __align__(16) char smraw[];
+  R* lds = reinterpret_cast<R*>(smraw);
+  const WyDescT<R> d = descs[blockIdx.x];
   const int n = d.n;
   if (n <= 0 || (n <= kWyLdsN) != kInLds) return;
   // n > kWyLdsN: this recurrence only when some tau is 0 (T^-1 does not exist);
   // otherwise k_wy_t_inv inverts T^-1 by tiles
   if (!kInLds) {
     bool zero = false;
-    for (int j = threadIdx.x; j < n; j += kWyThreads) zero = zero || d.tau[j] == 0.0;
+    for (int j = threadIdx.x; j < n; j += kWyThreads) zero = zero || d.tau[j] == R(0);
     if (!__syncthreads_or(zero)) return;
   }
-  double* A = kInLds ? lds : d.T;
+  R* A = kInLds ? lds : d.T;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int grp = lane >> 3, r8 = lane & 7;
   constexpr int kGroups = kWyThreads / 8;
@@ -888,10 +969,10 @@ __global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
   for (int j = tid; j < n; j += kWyThreads) A[j + (int64_t)j * n] = d.tau[j];
   __syncthreads();
   for (int j = 1; j < n; ++j) {
-    const double tj = d.tau[j];
+    const R tj = d.tau[j];
     for (int ib = wid * 8; ib < j; ib += kGroups) {   // wave-uniform bound
       const int i = ib + grp;
-      double acc = 0.0;
+      R acc = 0;
       if (i < j)
         for (int q = i + r8; q < j; q += 8)
           acc = fma(A[i + (int64_t)q * n], A[j + (int64_t)q * n], acc);
@@ -902,7 +983,7 @@ __global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
   }
   for (int64_t idx = tid; idx < (int64_t)n * n; idx += kWyThreads) {
     const int i = (int)(idx % n), c = (int)(idx / n);
-    d.T[idx] = i <= c ? A[idx] : 0.0;
+    d.T[idx] = i <= c ? A[idx] : R(0);
   }
 }
 
@@ -913,29 +994,31 @@ __global__ __launch_bounds__(kWyThreads) void k_wy_t(const WyDesc* descs) {
 // forward substitution below).  On entry T holds V^T V in its lower triangle;
 // L is formed in place there, X goes to the scratch d.X.  LDS: four 64x65
 // tiles.
-__global__ __launch_bounds__(kPotrfThreads) void k_wy_t_inv(const WyDesc* descs) {
-  extern __shared__ double sm[];
-  const WyDesc d = descs[blockIdx.x];
+template <class R>
+__global__ __launch_bounds__(kPotrfThreads) void k_wy_t_inv(const WyDescT<R>* descs) {
+  extern __shared__ __align__(16) char smraw[];
+  R* sm = reinterpret_cast<R*>(smraw);
+  const WyDescT<R> d = descs[blockIdx.x];
   const int n = d.n;
   if (n <= kWyLdsN) return;
   bool zero = false;
-  for (int j = threadIdx.x; j < n; j += kPotrfThreads) zero = zero || d.tau[j] == 0.0;
+  for (int j = threadIdx.x; j < n; j += kPotrfThreads) zero = zero || d.tau[j] == R(0);
   if (__syncthreads_or(zero)) return;   // k_wy_t<false> takes it
-  for (int j = threadIdx.x; j < n; j += kPotrfThreads) d.T[j + (int64_t)j * n] = 1.0 / d.tau[j];
+  for (int j = threadIdx.x; j < n; j += kPotrfThreads) d.T[j + (int64_t)j * n] = R(1) / d.tau[j];
   __syncthreads();
-  double* T0 = sm;
-  double* T1 = sm + kNb * kTl;
-  double* tmp = sm + 3 * kNb * kTl;
+  R* T0 = sm;
+  R* T1 = sm + kNb * kTl;
+  R* tmp = sm + 3 * kNb * kTl;
   const int nb = (n + kNb - 1) / kNb;
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * kNb, kw = min(kNb, n - k0);
     tile_load(T1, d.T + k0 + (int64_t)k0 * n, n, kw, kw);
-    for (int idx = threadIdx.x; idx < kNb * kTl; idx += kPotrfThreads) T0[idx] = 0.0;
+    for (int idx = threadIdx.x; idx < kNb * kTl; idx += kPotrfThreads) T0[idx] = 0;
     __syncthreads();
     trinv<kPotrfThreads>(T1, kTl, T0, kTl, kw, tmp);
     for (int idx = threadIdx.x; idx < kw * kw; idx += kPotrfThreads) {
       const int i = idx % kw, j = idx / kw;
-      d.X[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T0[i + j * kTl] : 0.0;
+      d.X[k0 + i + (int64_t)(k0 + j) * n] = i >= j ? T0[i + j * kTl] : R(0);
     }
     __syncthreads();
   }
@@ -943,27 +1026,30 @@ __global__ __launch_bounds__(kPotrfThreads) void k_wy_t_inv(const WyDesc* descs)
   __syncthreads();
   for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += kPotrfThreads) {
     const int i = (int)(idx % n), c = (int)(idx / n);
-    d.T[idx] = i <= c ? d.X[c + (int64_t)i * n] : 0.0;
+    d.T[idx] = i <= c ? d.X[c + (int64_t)i * n] : R(0);
   }
 }
 
-__global__ void k_fill(double* p, int64_t n, double v) {
+template <class R>
+__global__ void k_fill(R* p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
+    p[i] = R(v);
 }
 
-__global__ void k_scatter(const double* vals, const int64_t* dest, int64_t nnz, double* panels) {
+template <class R>
+__global__ void k_scatter(const double* vals, const int64_t* dest, int64_t nnz, R* panels) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x)
-    panels[dest[e]] = vals[e];
+    panels[dest[e]] = R(vals[e]);
 }
 
-__global__ __launch_bounds__(256) void k_copy(const CopyDesc* descs) {
-  const CopyDesc d = descs[blockIdx.x];
+template <class S, class D>
+__global__ __launch_bounds__(256) void k_copy(const CopyDescT<S, D>* descs) {
+  const CopyDescT<S, D> d = descs[blockIdx.x];
   for (int64_t idx = threadIdx.x; idx < (int64_t)d.m * d.n; idx += blockDim.x) {
     const int i = (int)(idx % d.m), j = (int)(idx / d.m);
-    d.dst[i + (int64_t)j * d.ldd] = d.src[i + (int64_t)j * d.lds];
+    d.dst[i + (int64_t)j * d.ldd] = D(d.src[i + (int64_t)j * d.lds]);
   }
 }
 
@@ -975,69 +1061,109 @@ inline unsigned grid_for(int64_t n, int bs) {
 
 }  // namespace
 
-void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+template <class R>
+void launch_fill(R* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill<R>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
-void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, double* panels,
-                    hipStream_t s) {
+template <class R>
+void launch_scatter(const double* vals, const int64_t* dest, int64_t nnz, R* panels, hipStream_t s) {
   if (nnz <= 0) return;
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nnz, 256)), dim3(256), 0, s, vals, dest, nnz, panels);
+  hipLaunchKernelGGL(k_scatter<R>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, vals, dest, nnz,
+                     panels);
 }
 
-void launch_potrf_inv(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
+template <class R>
+void launch_potrf_inv(const PotrfDescT<R>* d, int32_t count, int32_t max_n, int32_t* info,
                       hipStream_t s) {
   if (count <= 0) return;
   if (max_n <= 64) {   // one wave per block, in registers
     const dim3 grid((unsigned)((count + kSmallWaves - 1) / kSmallWaves)), block(kSmallWaves * kWave);
-    if (max_n <= 32) hipLaunchKernelGGL(k_potrf_inv_small<32>, grid, block, 0, s, d, count, info);
-    else hipLaunchKernelGGL(k_potrf_inv_small<64>, grid, block, 0, s, d, count, info);
+    if (max_n <= 32) hipLaunchKernelGGL((k_potrf_inv_small<R, 32>), grid, block, 0, s, d, count, info);
+    else hipLaunchKernelGGL((k_potrf_inv_small<R, 64>), grid, block, 0, s, d, count, info);
     return;
   }
   launch_potrf_blocks(d, count, max_n, info, s);
 }
 
-void launch_potrf_blocks(const PotrfDesc* d, int32_t count, int32_t max_n, int32_t* info,
+template <class R>
+void launch_potrf_blocks(const PotrfDescT<R>* d, int32_t count, int32_t max_n, int32_t* info,
                          hipStream_t s) {
   if (count <= 0) return;
   if (max_n > kNb) {   // two 64x65 tiles and the inverse's products
-    const size_t lds = ((size_t)2 * kNb * kTl + 768) * sizeof(double);
-    hipLaunchKernelGGL(k_potrf_inv_big, dim3(count), dim3(kBigThreads), lds, s, d, info);
+    if constexpr (sizeof(R) == 8) {
+      const size_t lds = ((size_t)2 * kNb * kTl + 768) * sizeof(double);
+      hipLaunchKernelGGL(k_potrf_inv_big, dim3(count), dim3(kBigThreads), lds, s, d, info);
+    } else {
+      __builtin_trap();   // unreachable: the FP32 forms factor such blocks in FP64
+    }
     return;
   }
   // the block, its inverse and the inverse's products in LDS
-  const size_t lds = ((size_t)2 * max_n * max_n + 768) * sizeof(double);
-  hipLaunchKernelGGL(k_potrf_inv, dim3(count), dim3(kPotrfThreads), lds, s, d, info);
+  const size_t lds = ((size_t)2 * max_n * max_n + 768) * sizeof(R);
+  hipLaunchKernelGGL(k_potrf_inv<R>, dim3(count), dim3(kPotrfThreads), lds, s, d, info);
 }
 
-void launch_gemm(const GemmDesc* d, const GemmTerm* t, const TileRef* tiles, int64_t ntiles,
-                 hipStream_t s) {
+template <class R>
+void launch_gemm(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* tiles, int64_t ntiles,
+                 GemmMode mode, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_gemm, dim3((unsigned)ntiles), dim3(kGemmThreads), 0, s, d, t, tiles);
+  if constexpr (sizeof(R) == 4) {
+    if (mode == kGemmBf16) {
+      hipLaunchKernelGGL((k_gemm<R, kGemmBf16>), dim3((unsigned)ntiles), dim3(kGemmThreads), 0, s,
+                         d, t, tiles);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm<R, kGemmNative>), dim3((unsigned)ntiles), dim3(kGemmThreads), 0, s, d,
+                     t, tiles);
 }
 
-void launch_cpqr(const CpqrDesc* d, const CpqrNbr* nb, int32_t count, int32_t* n_cur,
+template <class R>
+void launch_cpqr(const CpqrDescT<R>* d, const CpqrNbrT<R>* nb, int32_t count, int32_t* n_cur,
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
                  int32_t max_a, int32_t max_k, hipStream_t s) {
   if (count <= 0) return;
-  size_t lds = ((size_t)max_k + max_a) * sizeof(double);
-  hipLaunchKernelGGL(k_cpqr, dim3(count), dim3(kQrThreads), lds, s, d, nb, n_cur, out_r, out_r2,
+  size_t lds = ((size_t)max_k + max_a) * sizeof(R);
+  hipLaunchKernelGGL(k_cpqr<R>, dim3(count), dim3(kQrThreads), lds, s, d, nb, n_cur, out_r, out_r2,
                      out_k, eps, eps_stop, max_k);
 }
 
-void launch_wy_t(const WyDesc* d, int32_t count, hipStream_t s) {
+template <class R>
+void launch_wy_t(const WyDescT<R>* d, int32_t count, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_wy_t<true>, dim3(count), dim3(kWyThreads),
-                     (size_t)kWyLdsN * kWyLdsN * sizeof(double), s, d);
-  hipLaunchKernelGGL(k_wy_t<false>, dim3(count), dim3(kWyThreads), 0, s, d);
-  hipLaunchKernelGGL(k_wy_t_inv, dim3(count), dim3(kPotrfThreads),
-                     (size_t)4 * kNb * kTl * sizeof(double), s, d);
+  hipLaunchKernelGGL((k_wy_t<R, true>), dim3(count), dim3(kWyThreads),
+                     (size_t)kWyLdsN * kWyLdsN * sizeof(R), s, d);
+  hipLaunchKernelGGL((k_wy_t<R, false>), dim3(count), dim3(kWyThreads), 0, s, d);
+  hipLaunchKernelGGL(k_wy_t_inv<R>, dim3(count), dim3(kPotrfThreads),
+                     (size_t)4 * kNb * kTl * sizeof(R), s, d);
 }
 
-void launch_copy(const CopyDesc* d, int64_t count, hipStream_t s) {
+template <class S, class D>
+void launch_copy(const CopyDescT<S, D>* d, int64_t count, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)count), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((k_copy<S, D>), dim3((unsigned)count), dim3(256), 0, s, d);
 }
+
+#define SPAND_FACTOR_INST(R)                                                                      \
+  template void launch_fill<R>(R*, int64_t, double, hipStream_t);                                 \
+  template void launch_scatter<R>(const double*, const int64_t*, int64_t, R*, hipStream_t);       \
+  template void launch_potrf_inv<R>(const PotrfDescT<R>*, int32_t, int32_t, int32_t*, hipStream_t); \
+  template void launch_potrf_blocks<R>(const PotrfDescT<R>*, int32_t, int32_t, int32_t*,          \
+                                       hipStream_t);                                              \
+  template void launch_gemm<R>(const GemmDescT<R>*, const GemmTermT<R>*, const TileRef*, int64_t, \
+                               GemmMode, hipStream_t);                                            \
+  template void launch_cpqr<R>(const CpqrDescT<R>*, const CpqrNbrT<R>*, int32_t, int32_t*,        \
+                               int32_t*, int32_t*, int32_t*, double, double, int32_t, int32_t,    \
+                               hipStream_t);                                                      \
+  template void launch_wy_t<R>(const WyDescT<R>*, int32_t, hipStream_t);
+SPAND_FACTOR_INST(double)
+SPAND_FACTOR_INST(float)
+#undef SPAND_FACTOR_INST
+template void launch_copy<double, double>(const CopyDescT<double, double>*, int64_t, hipStream_t);
+template void launch_copy<float, float>(const CopyDescT<float, float>*, int64_t, hipStream_t);
+template void launch_copy<float, double>(const CopyDescT<float, double>*, int64_t, hipStream_t);
+template void launch_copy<double, float>(const CopyDescT<double, float>*, int64_t, hipStream_t);
 
 }  // namespace spand

@@ -79,9 +79,24 @@ __device__ __forceinline__ double group8_sum(double v) {
   return v;
 }
 
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_move<0xb1>(v);
+  v += dpp_move<0x4e>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x128>(v);
+  v += dpp_move<0x142>(v);
+  v += dpp_move<0x143>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Sum over each group of L lanes (8, 16 or 32), returned to all of them.
-template <int L>
-__device__ __forceinline__ double groupL_sum(double v) {
+template <int L, class R>
+__device__ __forceinline__ R groupL_sum(R v) {
   v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
   if (L == 8) {
@@ -100,43 +115,42 @@ __device__ __forceinline__ double groupL_sum(double v) {
 // waves over the column batches), kRpl rows per lane held in registers between
 // the dot product and the update, one group reduction for each.  Column Cl
 // (the pivot, when owned) and used-up columns (nrm2 < 0) are skipped.
-template <int L, int kRpl, bool kPanel>
-__device__ __forceinline__ void update_columns(double* Ys, double* const* gcol, double* nrm2,
-                                               const double* v, int a, int m, int j, double tau,
-                                               int skip) {
+template <int L, int kRpl, bool kPanel, class R>
+__device__ __forceinline__ void update_columns(R* Ys, R* const* gcol, R* nrm2, const R* v, int a,
+                                               int m, int j, R tau, int skip) {
   constexpr int CPW = kWave / L;   // columns per wave
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int grp = lane / L, rl = lane % L;
   for (int cb = wid * CPW; cb < m; cb += kCW * CPW) {
     const int c = cb + grp;
-    const bool act = c < m && c != skip && nrm2[c] >= 0.0;
+    const bool act = c < m && c != skip && nrm2[c] >= R(0);
     // LDS slice, or (kPanel) the column's place in the panel
-    double* col = kPanel ? (act ? gcol[c] : gcol[0]) : Ys + (int64_t)(act ? c : 0) * a;
-    double yv[kRpl];
-    double dot = 0.0;
+    R* col = kPanel ? (act ? gcol[c] : gcol[0]) : Ys + (int64_t)(act ? c : 0) * a;
+    R yv[kRpl];
+    R dot = 0;
 #pragma unroll
     for (int t = 0; t < kRpl; ++t) {
       const int i = j + rl + L * t;
       const bool in = act && i < a;
-      yv[t] = in ? col[i] : 0.0;
-      dot = fma(in ? v[i] : 0.0, yv[t], dot);
+      yv[t] = in ? col[i] : R(0);
+      dot = fma(in ? v[i] : R(0), yv[t], dot);
     }
     for (int i = j + rl + L * kRpl; i < a; i += L)
       if (act) dot = fma(v[i], col[i], dot);
     dot = groupL_sum<L>(dot) * tau;
-    double s = 0.0;
+    R s = 0;
 #pragma unroll
     for (int t = 0; t < kRpl; ++t) {
       const int i = j + rl + L * t;
       if (act && i < a) {
-        const double y = fma(-dot, v[i], yv[t]);
+        const R y = fma(-dot, v[i], yv[t]);
         col[i] = y;
         if (i > j) s = fma(y, y, s);
       }
     }
     for (int i = j + rl + L * kRpl; i < a; i += L)
       if (act) {
-        const double y = fma(-dot, v[i], col[i]);
+        const R y = fma(-dot, v[i], col[i]);
         col[i] = y;
         s = fma(y, y, s);
       }
@@ -245,6 +259,12 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+template <class R>
+__device__ __forceinline__ R wave_max_r(R v) {
+  if constexpr (sizeof(R) == 8) return wave_max(v);
+  else return wave_max_f(v);
+}
+
 // 64-bit value of a lane given by a wave-uniform index
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
@@ -255,18 +275,19 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x,
 // kPanel: some columns of a workgroup may live in the row panel (an interface
 // wider than its group's LDS); the LDS-only instance keeps its registers for
 // the common case.
-template <bool kPanel>
-__global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const CpqrNbr* nbrs,
+template <class R, bool kPanel>
+__global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, const CpqrNbrT<R>* nbrs,
                                                   const int32_t* blk_map, int32_t* n_cur,
                                                   int32_t* out_r, int32_t* out_r2, int32_t* out_k,
                                                   double eps, double eps_stop, int32_t* err) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(16) char smraw[];
+  R* sm = reinterpret_cast<R*>(smraw);
   __shared__ int sok, sC, s_go, s_r;
   __shared__ double s_beta, s_tau;
   const int code = blk_map[blockIdx.x];
   if (code < 0) return;   // idle slot of the XCD packing
-  const CoopDesc cd = descs[code / kCoopMaxGroup];
-  const CpqrDesc& d = cd.d;
+  const CoopDescT<R> cd = descs[code / kCoopMaxGroup];
+  const CpqrDescT<R>& d = cd.d;
   const int G = cd.G, g = code % kCoopMaxGroup;
   const int a = d.a;
   const int64_t K = d.kmax;
@@ -307,11 +328,12 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   // the first mL of my columns in LDS, the rest (when the interface is wider
   // than the group's LDS) in place in the row panel
   const int mL = kPanel ? min(m, cd.ncap_lds) : m;
-  double* Ys = sm;                                  // a x ncap_lds (ld a)
-  double* nrm2 = sm + (int64_t)a * cd.ncap_lds;     // ncap
-  double* v = nrm2 + cd.ncap;                       // a
-  double** gcol = reinterpret_cast<double**>(v + a);   // ncap - ncap_lds panel columns
-  auto colp = [&](int c) -> double* {
+  R* Ys = sm;                                       // a x ncap_lds (ld a)
+  R* nrm2 = sm + (int64_t)a * cd.ncap_lds;          // ncap
+  R* v = nrm2 + cd.ncap;                            // a
+  // ncap - ncap_lds panel column addresses, 8-byte aligned after v
+  R** gcol = reinterpret_cast<R**>(smraw + coop_lds_ptr_offset<R>(a, cd.ncap, cd.ncap_lds));
+  auto colp = [&](int c) -> R* {
     if constexpr (kPanel) return c < mL ? Ys + (int64_t)c * a : gcol[c - mL];
     return Ys + (int64_t)c * a;
   };
@@ -326,13 +348,13 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   {
     int kk = 0;
     for (int64_t e = d.nb0; e < d.nb1; ++e) {
-      const CpqrNbr nb = nbrs[e];
+      const CpqrNbrT<R> nb = nbrs[e];
       const int wc = n_cur[nb.w];
       const int lo = max(kk, c0), hi = min(kk + wc, c1);
       const int hiL = min(hi, c0 + mL);
       if (hiL > lo) {
-        const double* src = d.panel + (nb.col + (lo - kk)) * a;
-        double* dst = Ys + (int64_t)(lo - c0) * a;
+        const R* src = d.panel + (nb.col + (lo - kk)) * a;
+        R* dst = Ys + (int64_t)(lo - c0) * a;
         for (int idx = tid; idx < (hiL - lo) * a; idx += kCT) dst[idx] = src[idx];
       }
       if (kPanel)
@@ -343,8 +365,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   }
   __syncthreads();
   for (int c = wid; c < m; c += kCW) {
-    const double* col = colp(c);
-    double s = 0.0;
+    const R* col = colp(c);
+    R s = 0;
     for (int i = lane; i < a; i += kWave) s = fma(col[i], col[i], s);
     s = wave_sum(s);
     if (lane == 0) nrm2[c] = s;
@@ -364,17 +386,17 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     if (wid == 0) {
       int go = 1;
       // ---- local maximum and the ordered list of local tie candidates ----
-      double ml = -1.0;
+      R ml = -1;
       for (int c = lane; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
-      const double Mg = wave_max(ml);
-      const double thl = Mg * (1.0 - kPivotTieRtol);
+      const R Mg = wave_max_r(ml);
+      const R thl = Mg * R(1.0 - PivotTie<R>::rtol);
       double* X = X2 + (int64_t)(j & 1) * G * kXs;
       double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
       double* Xg = X + (int64_t)g * kXs;
       int total = 0, first = -1;
       for (int cb = 0; cb < m; cb += kWave) {
         const int c = cb + lane;
-        const bool f = Mg >= 0.0 && c < m && nrm2[c] >= 0.0 && nrm2[c] >= thl;
+        const bool f = Mg >= R(0) && c < m && nrm2[c] >= R(0) && nrm2[c] >= thl;
         const unsigned long long mask = __ballot(f);
         if (f && G > 1) {
           const int at = total + __popcll(mask & ((1ULL << lane) - 1ULL));
@@ -387,10 +409,10 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         total += __popcll(mask);
       }
       int C = INT_MAX;
-      const double* PVl = nullptr;   // pivot column in LDS (one workgroup) ...
+      const R* PVl = nullptr;        // pivot column in LDS (one workgroup) ...
       const double* PVg = nullptr;   // ... or in the exchange buffer
       if (G == 1) {
-        if (Mg < 0.0) go = 0;   // every column used up
+        if (Mg < R(0)) go = 0;   // every column used up
         else {
           C = c0 + first;
           PVl = colp(first);
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         if (first >= 0) {
           double* Pg = PVs + (int64_t)g * (a + 1);
           if (lane == 0) xst(Pg, nrm2[first]);
-          const double* fc = colp(first);
+          const R* fc = colp(first);
           for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
         }
         // the flag word carries the local maximum (as float) and the first
@@ -411,7 +433,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         // maximum exceeds all others by more than float rounding and the band
         const unsigned long long pay =
             ((unsigned long long)(first >= 0 ? c0 + first : 0xFFFF) << 32) |
-            __float_as_uint(__double2float_rn(Mg));
+            __float_as_uint((float)Mg);
         if (!wave_barrier(flags, ++phase, pay, G, g, err, &bw)) go = -1;
         bool fast = false;
         if (go > 0 && cd.list_cap == kCoopList) {
@@ -449,7 +471,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
           const bool over = __ballot(lane < G && cq > cd.list_cap) != 0ULL;
           if (M < 0.0) go = 0;   // every column used up
           else {
-            const double thr = M * (1.0 - kPivotTieRtol);
+            const double thr = M * (1.0 - PivotTie<R>::rtol);
             if (!over) {
               if (lane < G && cq > 0 && cd.list_cap > 0 && nv0 >= thr) C = ix0;
               unsigned long long more = __ballot(lane < G && cq > 1 && Mq >= thr);
@@ -467,7 +489,8 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
               int cl = INT_MAX;
               for (int cb = 0; cb < m && cl == INT_MAX; cb += kWave) {
                 const int c = cb + lane;
-                const unsigned long long mk = __ballot(c < m && nrm2[c] >= 0.0 && nrm2[c] >= thr);
+                const unsigned long long mk =
+                    __ballot(c < m && nrm2[c] >= R(0) && (double)nrm2[c] >= thr);
                 if (mk) cl = c0 + cb + __ffsll((long long)mk) - 1;
               }
               if (lane == 0) xst(XB + g, (double)cl);
@@ -489,7 +512,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
                 if (C >= c0 && C < c1) {
                   const int Cl = C - c0;
                   if (lane == 0) xst(PVx, nrm2[Cl]);
-                  const double* pc = colp(Cl);
+                  const R* pc = colp(Cl);
                   for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), pc[i]);
                 }
                 if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
@@ -510,11 +533,11 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
           pn = xld(PVg);
           alpha = xld(PVg + 1);
           for (int i0 = j + 1; i0 < a; i0 += 4 * kWave) {   // four loads in flight per lane
-            double xr[4];
+            R xr[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
               const int i = i0 + lane + t * kWave;
-              xr[t] = i < a ? xld(PVg + 1 + (i - j)) : 0.0;
+              xr[t] = i < a ? R(xld(PVg + 1 + (i - j))) : R(0);
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -529,7 +552,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         else {
           if (r < 0 && nrm < eps * R00) r = j;
           const double beta = alpha >= 0.0 ? -nrm : nrm;
-          const double rden = 1.0 / (alpha - beta);
+          const R rden = R(1.0 / (alpha - beta));
           for (int i = j + 1 + lane; i < a; i += kWave) v[i] *= rden;
           if (lane == 0) {
             v[j] = 1.0;
@@ -549,11 +572,11 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
     if (go < 0) return;   // a group barrier timed out (error flag set)
     if (go == 0) break;
     const int C = sC;
-    const double tau = s_tau, beta = s_beta;
+    const R tau = R(s_tau), beta = R(s_beta);
     const bool owner = C >= c0 && C < c1;
     const int Cl = C - c0;
     if (g == 0) {
-      for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? 0.0 : v[i];
+      for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? R(0) : v[i];
       if (tid == 0) d.tau[j] = tau;
     }
     // fused reflector update + exact trailing norms; the lanes per column
@@ -567,9 +590,9 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
         if (m > mL) update_columns<8, 8, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
     }
     if (owner) {
-      double* pc = colp(Cl);
-      for (int i = j + tid; i < a; i += kCT) pc[i] = i == j ? beta : 0.0;
-      if (tid == 0) nrm2[Cl] = -1.0;
+      R* pc = colp(Cl);
+      for (int i = j + tid; i < a; i += kCT) pc[i] = i == j ? beta : R(0);
+      if (tid == 0) nrm2[Cl] = -1;
     }
     __syncthreads();
   }
@@ -586,13 +609,13 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   {
     int kk = 0;
     for (int64_t e = d.nb0; e < d.nb1; ++e) {
-      const CpqrNbr nb = nbrs[e];
+      const CpqrNbrT<R> nb = nbrs[e];
       const int wc = n_cur[nb.w];
       const int lo = max(kk, c0), hi = min(kk + wc, c1);
       for (int idx = tid; idx < r * (hi - lo); idx += kCT) {
         const int cc = idx % (hi - lo), i = idx / (hi - lo);
         const int cw = lo - kk + cc;  // column inside block (p, w)
-        const double y = colp(lo - c0 + cc)[i];
+        const R y = colp(lo - c0 + cc)[i];
         d.panel[i + (nb.col + cw) * a] = y;
         nb.blk_wp[cw + (int64_t)i * nb.ldw] = y;
       }
@@ -602,7 +625,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDesc* descs, const 
   if (g != 0) return;
   for (int idx = tid; idx < r * r; idx += kCT) {
     const int i = idx % r, c = idx / r;
-    d.panel[i + (d.diag_col + c) * a] = i == c ? 1.0 : 0.0;
+    d.panel[i + (d.diag_col + c) * a] = i == c ? R(1) : R(0);
   }
   if (tid == 0) {
     out_k[d.p] = k;
@@ -620,12 +643,13 @@ __global__ void k_fill_int(int32_t* p, int64_t n) {
 
 }  // namespace
 
+template <class R>
 int coop_max_blocks(size_t lds_bytes, bool panel) {
   int dev = 0, ncu = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<true>)
-                        : reinterpret_cast<const void*>(k_cpqr_coop<false>);
+  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<R, true>)
+                        : reinterpret_cast<const void*>(k_cpqr_coop<R, false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kCT, lds_bytes) != hipSuccess)
     return 0;
   return nb * ncu;
@@ -635,7 +659,8 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
-hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t* blk_map,
+template <class R>
+hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const int32_t* blk_map,
                             int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
                             int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
                             double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
@@ -643,9 +668,20 @@ hipError_t launch_cpqr_coop(const CoopDesc* d, const CpqrNbr* nb, const int32_t*
   launch_fill_int(sync, nsync, s);
   void* args[] = {(void*)&d, (void*)&nb, (void*)&blk_map, (void*)&n_cur, (void*)&out_r,
                   (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
-  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<true>)
-                        : reinterpret_cast<const void*>(k_cpqr_coop<false>);
+  const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<R, true>)
+                        : reinterpret_cast<const void*>(k_cpqr_coop<R, false>);
   return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kCT), args, lds_bytes, s);
 }
+
+template int coop_max_blocks<double>(size_t, bool);
+template int coop_max_blocks<float>(size_t, bool);
+template hipError_t launch_cpqr_coop<double>(const CoopDescT<double>*, const CpqrNbrT<double>*,
+                                             const int32_t*, int32_t, int32_t*, int32_t, int32_t*,
+                                             int32_t*, int32_t*, int32_t*, double, double,
+                                             int32_t*, size_t, bool, hipStream_t);
+template hipError_t launch_cpqr_coop<float>(const CoopDescT<float>*, const CpqrNbrT<float>*,
+                                            const int32_t*, int32_t, int32_t*, int32_t, int32_t*,
+                                            int32_t*, int32_t*, int32_t*, double, double, int32_t*,
+                                            size_t, bool, hipStream_t);
 
 }  // namespace spand

@@ -1,4 +1,6 @@
-// HIP kernels of the preconditioner apply and of PCG (FP64).
+// HIP kernels of the preconditioner apply and of PCG.  Vectors, scratch and
+// accumulation are FP64; the factor entries the apply reads are of the
+// factor's element type (the kernels are templates on it, MT: double or float).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,7 +66,8 @@ constexpr int kChunk = 1024;  // staged neighbour values of the backward E produ
 // threads loading); then lanes hold rows and waves split the columns, and the
 // per-wave partial sums are reduced in a fixed order.
 // stage: LDS of kChunk * nrhs, part: LDS of kNW * rows * nrhs.  Ends with a barrier.
-__device__ void wg_rowsum_gather(const double* __restrict__ M, int64_t ld, int rows, int cols,
+template <class MT>
+__device__ void wg_rowsum_gather(const MT* __restrict__ M, int64_t ld, int rows, int cols,
                                  const int32_t* __restrict__ pos, const double* __restrict__ z,
                                  int64_t ldz, int nrhs, double* __restrict__ stage,
                                  double* __restrict__ part, double* __restrict__ acc_out) {
@@ -116,8 +119,8 @@ constexpr int kApNarrowFrom = 512;
 // out[c + r*ldo] = sum_{i<rows} M[i + c*ld] x[i + r*ldx]: one wave per batch of
 // CB columns, lanes over rows (coalesced, RC chunks of 64 per block), one wave
 // reduction per output.
-template <int NT, int RC, int CB>
-__device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, int cols,
+template <int NT, int RC, int CB, class MT>
+__device__ void wgt_coldots(const MT* __restrict__ M, int64_t ld, int rows, int cols,
                             const double* __restrict__ x, int ldx, int nrhs, double* __restrict__ out,
                             int64_t ldo) {
   constexpr int NW = NT / kWave, kRC = RC;
@@ -165,8 +168,8 @@ __device__ void wgt_coldots(const double* __restrict__ M, int64_t ld, int rows, 
 // lanes over rows (coalesced, RC chunks of 64 per lane), waves over columns
 // (CU columns in flight), rb right-hand sides per pass; per-wave partial sums
 // in LDS (part: NW x rows x rb) added in wave order.  Ends with a barrier.
-template <int NT, int RC, int CU>
-__device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows, int cols,
+template <int NT, int RC, int CU, class MT>
+__device__ void wgt_gemv_acc(const MT* __restrict__ M, int64_t ld, int rows, int cols,
                              const double* __restrict__ w, int ldw, int nrhs, double sign,
                              double* __restrict__ y, int ldy, double* __restrict__ part, int rb) {
   constexpr int NW = NT / kWave, kRC = RC;
@@ -216,7 +219,7 @@ __device__ void wgt_gemv_acc(const double* __restrict__ M, int64_t ld, int rows,
 // ---------------------------------------------------------------------------
 // forward interior: z_s <- L^{-1} z_s ; t = G^T z_s
 // ---------------------------------------------------------------------------
-template <int CB>
+template <class MT, int CB>
 __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z, int64_t ldz,
                                                    int nrhs, double* T) {
   extern __shared__ double sm[];
@@ -232,18 +235,20 @@ __global__ __launch_bounds__(kT) void k_ap_int_fwd(const ApInt* descs, double* z
   }
   __syncthreads();
   // ys = L^{-1} xs (L^{-1} is stored with zeros above its diagonal)
-  wgt_gemv_acc<kT, 1, CB>(d.Linv, n, n, n, xs, n, nrhs, 1.0, ys, n, part, ap_rb(nrhs));
+  wgt_gemv_acc<kT, 1, CB>(static_cast<const MT*>(d.Linv), n, n, n, xs, n, nrhs, 1.0, ys, n, part,
+                          ap_rb(nrhs));
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     z[d.pos[i] + r * ldz] = ys[idx];
   }
   if (k == 0) return;
-  wgt_coldots<kT, 1, CB>(d.G, n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
+  wgt_coldots<kT, 1, CB>(static_cast<const MT*>(d.G), n, n, k, ys, n, nrhs, T + d.toff * nrhs, k);
 }
 
 // ---------------------------------------------------------------------------
 // gather: z_w -= sum of slices; optional scaling z_w <- Zinv z_w
 // ---------------------------------------------------------------------------
+template <class MT>
 __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSrc* src, double* z,
                                                   int64_t ldz, int nrhs, const double* T,
                                                   double* Y) {
@@ -268,7 +273,8 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
     const int i = idx % n, r = idx / n;
     double acc = 0.0;
 #pragma unroll 8
-    for (int m = 0; m <= i; ++m) acc = fma(d.Zinv[i + (int64_t)m * n], xs[m + r * n], acc);
+    for (int m = 0; m <= i; ++m)
+      acc = fma((double)static_cast<const MT*>(d.Zinv)[i + (int64_t)m * n], xs[m + r * n], acc);
     z[d.pos[i] + r * ldz] = acc;
   }
 }
@@ -279,6 +285,7 @@ __global__ __launch_bounds__(kT) void k_ap_gather(const ApGat* descs, const ApSr
 // the rows, and the per-wave partial sums are added in wave order.
 // LDS: z_f (nf x nrhs) | part (kSNW x 64 x 4).
 // ---------------------------------------------------------------------------
+template <class MT>
 __global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const double* z, int64_t ldz,
                                                    int nrhs, double* T) {
   extern __shared__ double sm[];
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const doub
   __syncthreads();
   const int per = (nf + NW - 1) / NW, i0 = min(nf, wid * per), i1 = min(nf, i0 + per);
   const bool col = lane < d.cn;
-  const double* e = d.Et + d.c0 + (col ? lane : 0);
+  const MT* e = static_cast<const MT*>(d.Et) + d.c0 + (col ? lane : 0);
   double* t = T + d.off * nrhs + d.c0 + lane;
   for (int r0 = 0; r0 < nrhs; r0 += 4) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -327,6 +334,7 @@ __global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const doub
 // The tile's neighbour values are staged in LDS (cn x nrhs); each wave takes
 // four rows of E at a time with all of the tile's columns in flight (lanes over
 // columns, up to kEtTileB / 64 chunks per lane).
+template <class MT>
 __global__ __launch_bounds__(kST) void k_ap_et_bwd(const ApEt* descs, const double* z, int64_t ldz,
                                                    int nrhs, double* P) {
   extern __shared__ double sm[];
@@ -348,7 +356,9 @@ __global__ __launch_bounds__(kST) void k_ap_et_bwd(const ApEt* descs, const doub
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const int c = lane + kWave * t;
-        ev[q][t] = (i0 + q < nf && c < cn) ? d.Et[d.c0 + c + (int64_t)(i0 + q) * d.lde] : 0.0;
+        ev[q][t] = (i0 + q < nf && c < cn)
+                       ? (double)static_cast<const MT*>(d.Et)[d.c0 + c + (int64_t)(i0 + q) * d.lde]
+                       : 0.0;
       }
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
       double acc[4][4];
@@ -399,6 +409,7 @@ __device__ __forceinline__ double wy_in(const ApSp& d, const double* __restrict_
 // u[j0 + c] = sum_i M[i, j0 + c] x_i for kApWyCB columns: threads over rows
 // (columns of M are contiguous), two rows per thread in flight, wave sums,
 // then the waves in order.
+template <class MT>
 __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tasks, const ApSp* descs,
                                                             const double* __restrict__ z, int64_t ldz,
                                                             int nrhs, const double* __restrict__ P,
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tas
   __shared__ double red[NW][CB * 4];
   const ApWyTask tk = tasks[blockIdx.x];
   const ApSp d = descs[tk.sp];
-  const double* __restrict__ M = fwd ? d.VT : d.V;
+  const MT* __restrict__ M = static_cast<const MT*>(fwd ? d.VT : d.V);
   const int a = d.a, j0 = tk.i0, cn = min(CB, d.nref - j0);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const double* Pp = fwd ? nullptr : P;
@@ -461,6 +472,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tas
 // wave reads 4 x 16 consecutive rows of 4 columns), eight columns per thread
 // in flight, u staged in LDS in chunks, the groups summed in order.
 constexpr int kApWyUChunk = 512;
+template <class MT>
 __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* tasks,
                                                             const ApSp* descs, double* z,
                                                             int64_t ldz, int nrhs,
@@ -472,7 +484,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_update(const ApWyTask* t
   __shared__ double us[UC * 4];
   const ApWyTask tk = tasks[blockIdx.x];
   const ApSp d = descs[tk.sp];
-  const double* __restrict__ N = fwd ? d.V : d.VT;
+  const MT* __restrict__ N = static_cast<const MT*>(fwd ? d.V : d.VT);
   const int a = d.a, nref = d.nref;
   const int rl = threadIdx.x % RB, g = threadIdx.x / RB;
   const int i = tk.i0 + rl;
@@ -533,6 +545,7 @@ __device__ __forceinline__ double mv_x(const ApMv& d, const double* __restrict__
 // kApMvRB rows per task: 16 rows x 16 column groups, x staged in LDS in
 // chunks, eight columns per thread in flight, groups summed in order.
 constexpr int kApMvChunk = 512;
+template <class MT>
 __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_rows(const ApMvTask* tasks, const ApMv* descs,
                                                             double* z, int64_t ldz, int nrhs,
                                                             const double* __restrict__ S,
@@ -562,7 +575,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_rows(const ApMvTask* tas
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
             const int jj = j + t * NG;
-            mv[t] = jj < jn ? d.M[i + (int64_t)(jc + jj) * d.ld] : 0.0;
+            mv[t] = jj < jn ? (double)static_cast<const MT*>(d.M)[i + (int64_t)(jc + jj) * d.ld] : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
@@ -594,6 +607,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_rows(const ApMvTask* tas
 // 4 x kApMvCB columns per task, one wave per kApMvCB columns: lanes over rows
 // (columns of M are contiguous), two rows per lane in flight, one wave sum per
 // output.
+template <class MT>
 __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_cols(const ApMvTask* tasks, const ApMv* descs,
                                                             double* z, int64_t ldz, int nrhs,
                                                             const double* __restrict__ S,
@@ -626,7 +640,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_cols(const ApMvTask* tas
           x[t][rr] = (i < d.rows && r0 + rr < nrhs) ? mv_x(d, z, ldz, S, nrhs, i, r0 + rr) : 0.0;
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-          m[t][c] = (i < d.rows && c < cn) ? d.M[i + (int64_t)(c0 + c) * d.ld] : 0.0;
+          m[t][c] = (i < d.rows && c < cn) ? (double)static_cast<const MT*>(d.M)[i + (int64_t)(c0 + c) * d.ld] : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
@@ -649,7 +663,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_cols(const ApMvTask* tas
 }
 
 // backward scaling: y_w <- Zinv^T y_w (column dots of Zinv)
-template <int CB>
+template <class MT, int CB>
 __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, double* z, int64_t ldz,
                                                      int nrhs) {
   extern __shared__ double sm[];
@@ -662,7 +676,7 @@ __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, doubl
     xs[idx] = z[d.pos[i] + r * ldz];
   }
   __syncthreads();
-  wgt_coldots<kT, 1, CB>(d.Zinv, n, n, n, xs, n, nrhs, ys, n);
+  wgt_coldots<kT, 1, CB>(static_cast<const MT*>(d.Zinv), n, n, n, xs, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -672,7 +686,7 @@ __global__ __launch_bounds__(kT) void k_ap_scale_bwd(const ApScale* descs, doubl
 
 // backward interior: y_s <- L^{-T} (y_s - G y_W)
 // LDS: us (n x nrhs) | ys (n x nrhs) | part (kNW x n x nrhs) | stage (kChunk x nrhs)
-template <int CB>
+template <class MT, int CB>
 __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z, int64_t ldz,
                                                    int nrhs) {
   extern __shared__ double sm[];
@@ -682,13 +696,14 @@ __global__ __launch_bounds__(kT) void k_ap_int_bwd(const ApInt* descs, double* z
   double* ys = sm + n * nrhs;
   double* part = ys + n * nrhs;
   double* stage = part + kNW * n * nrhs;
-  if (k > 0) wg_rowsum_gather(d.G, n, n, k, d.nbr_pos, z, ldz, nrhs, stage, part, ys);
+  if (k > 0)
+    wg_rowsum_gather(static_cast<const MT*>(d.G), n, n, k, d.nbr_pos, z, ldz, nrhs, stage, part, ys);
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
     us[idx] = z[d.pos[i] + r * ldz] - (k > 0 ? ys[idx] : 0.0);
   }
   __syncthreads();
-  wgt_coldots<kT, 1, CB>(d.Linv, n, n, n, us, n, nrhs, ys, n);
+  wgt_coldots<kT, 1, CB>(static_cast<const MT*>(d.Linv), n, n, n, us, n, nrhs, ys, n);
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * nrhs; idx += kT) {
     const int i = idx % n, r = idx / n;
@@ -826,74 +841,91 @@ inline unsigned grid_for(int64_t n, int bs) {
 
 }  // namespace
 
+// the factor's element type selects the kernel instance
+#define SPAND_AP_LAUNCH(f32, K, grid, block, lds, s, ...)                         \
+  do {                                                                          \
+    if (f32) hipLaunchKernelGGL(K<float>, grid, block, lds, s, __VA_ARGS__);     \
+    else hipLaunchKernelGGL(K<double>, grid, block, lds, s, __VA_ARGS__);        \
+  } while (0)
+
 void launch_ap_int_fwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                       double* T, int32_t max_n, hipStream_t s) {
+                       double* T, int32_t max_n, bool f32, hipStream_t s) {
   if (count <= 0) return;
   const size_t lds = ((size_t)2 * max_n * nrhs + (size_t)kNW * max_n * ap_rb(nrhs)) * sizeof(double);
-  if (count >= kApNarrowFrom)
-    hipLaunchKernelGGL(k_ap_int_fwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
-  else
-    hipLaunchKernelGGL(k_ap_int_fwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+  if (count >= kApNarrowFrom) {
+    if (f32) hipLaunchKernelGGL((k_ap_int_fwd<float, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+    else hipLaunchKernelGGL((k_ap_int_fwd<double, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_ap_int_fwd<float, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+    else hipLaunchKernelGGL((k_ap_int_fwd<double, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs, T);
+  }
 }
 void launch_ap_gather(const ApGat* d, const ApSrc* src, int32_t count, double* z, int64_t ldz,
-                      int32_t nrhs, const double* T, int32_t max_n, hipStream_t s, double* Y) {
+                      int32_t nrhs, const double* T, int32_t max_n, bool f32, hipStream_t s,
+                      double* Y) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_gather, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
-                     d, src, z, ldz, nrhs, T, Y);
+  SPAND_AP_LAUNCH(f32, k_ap_gather, dim3(count), dim3(kT), (size_t)max_n * nrhs * sizeof(double), s,
+                  d, src, z, ldz, nrhs, T, Y);
 }
 void launch_ap_et_fwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
-                      double* T, int32_t max_nf, hipStream_t s) {
+                      double* T, int32_t max_nf, bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_et_fwd, dim3(count), dim3(kST),
-                     ((size_t)max_nf * nrhs + (size_t)kST * 4) * sizeof(double), s, d, z, ldz, nrhs, T);
+  SPAND_AP_LAUNCH(f32, k_ap_et_fwd, dim3(count), dim3(kST),
+                  ((size_t)max_nf * nrhs + (size_t)kST * 4) * sizeof(double), s, d, z, ldz, nrhs, T);
 }
 void launch_ap_et_bwd(const ApEt* d, int32_t count, const double* z, int64_t ldz, int32_t nrhs,
-                      double* P, hipStream_t s) {
+                      double* P, bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_et_bwd, dim3(count), dim3(kST), (size_t)kEtTileB * nrhs * sizeof(double),
-                     s, d, z, ldz, nrhs, P);
+  SPAND_AP_LAUNCH(f32, k_ap_et_bwd, dim3(count), dim3(kST), (size_t)kEtTileB * nrhs * sizeof(double),
+                  s, d, z, ldz, nrhs, P);
 }
 void launch_ap_mv_rows(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
-                       int32_t nrhs, const double* S, double* O, hipStream_t s) {
+                       int32_t nrhs, const double* S, double* O, bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_mv_rows, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
+  SPAND_AP_LAUNCH(f32, k_ap_mv_rows, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
 }
 void launch_ap_mv_cols(const ApMvTask* t, int32_t count, const ApMv* d, double* z, int64_t ldz,
-                       int32_t nrhs, const double* S, double* O, hipStream_t s) {
+                       int32_t nrhs, const double* S, double* O, bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_mv_cols, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
+  SPAND_AP_LAUNCH(f32, k_ap_mv_cols, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, S, O);
 }
 void launch_ap_wy_dots(const ApWyTask* t, int32_t count, const ApSp* d, const double* z,
                        int64_t ldz, int32_t nrhs, const double* P, double* U, int64_t usz, int fwd,
-                       hipStream_t s) {
+                       bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_wy_dots, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P, U,
-                     usz, fwd);
+  SPAND_AP_LAUNCH(f32, k_ap_wy_dots, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P, U,
+                  usz, fwd);
 }
 void launch_ap_wy_update(const ApWyTask* t, int32_t count, const ApSp* d, double* z, int64_t ldz,
                          int32_t nrhs, const double* P, const double* U, int64_t usz, int fwd,
-                         hipStream_t s) {
+                         bool f32, hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_ap_wy_update, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P,
-                     U, usz, fwd);
+  SPAND_AP_LAUNCH(f32, k_ap_wy_update, dim3(count), dim3(kApWyThreads), 0, s, t, d, z, ldz, nrhs, P,
+                  U, usz, fwd);
 }
 void launch_ap_scale_bwd(const ApScale* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                         int32_t max_n, hipStream_t s) {
+                         int32_t max_n, bool f32, hipStream_t s) {
   if (count <= 0) return;
   const size_t lds = 2 * (size_t)max_n * nrhs * sizeof(double);
-  if (count >= kApNarrowFrom)
-    hipLaunchKernelGGL(k_ap_scale_bwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
-  else
-    hipLaunchKernelGGL(k_ap_scale_bwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  if (count >= kApNarrowFrom) {
+    if (f32) hipLaunchKernelGGL((k_ap_scale_bwd<float, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+    else hipLaunchKernelGGL((k_ap_scale_bwd<double, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_ap_scale_bwd<float, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+    else hipLaunchKernelGGL((k_ap_scale_bwd<double, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  }
 }
 void launch_ap_int_bwd(const ApInt* d, int32_t count, double* z, int64_t ldz, int32_t nrhs,
-                       int32_t max_n, hipStream_t s) {
+                       int32_t max_n, bool f32, hipStream_t s) {
   if (count <= 0) return;
   const size_t lds = ((size_t)(2 + kNW) * max_n * nrhs + (size_t)kChunk * nrhs) * sizeof(double);
-  if (count >= kApNarrowFrom)
-    hipLaunchKernelGGL(k_ap_int_bwd<kApNarrow>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
-  else
-    hipLaunchKernelGGL(k_ap_int_bwd<kApWide>, dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  if (count >= kApNarrowFrom) {
+    if (f32) hipLaunchKernelGGL((k_ap_int_bwd<float, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+    else hipLaunchKernelGGL((k_ap_int_bwd<double, kApNarrow>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_ap_int_bwd<float, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+    else hipLaunchKernelGGL((k_ap_int_bwd<double, kApWide>), dim3(count), dim3(kT), lds, s, d, z, ldz, nrhs);
+  }
 }
 
 void launch_spmv(const int64_t* rowptr, const int32_t* colind, const double* vals, int64_t n,

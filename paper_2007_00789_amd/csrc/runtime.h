@@ -202,16 +202,18 @@ struct StepRec {
   std::vector<int32_t> n0;                   // cluster sizes at step start
   std::vector<int32_t> r, r2, k;             // interfaces of sparsified steps (else -1)
   std::vector<int64_t> kmax;                 // interfaces: leading dimension of Y (W^T)
-  std::vector<double*> Linv, G;              // interiors
+  // factor entries: double, or float when FactorObj::f32
+  std::vector<void*> Linv, G;                // interiors
   std::vector<int32_t> kint;                 // interiors: coupling width
-  std::vector<double*> Zinv, Y, V, tau, T;   // interfaces of sparsified steps
-  std::vector<double*> VT;                   // interfaces: V T (a x nref), for the apply
+  std::vector<void*> Zinv, Y, V, tau, T;     // interfaces of sparsified steps
+  std::vector<void*> VT;                     // interfaces: V T (a x nref), for the apply
   PosLists pos;                              // positions of each cluster's variables (step start)
   PosLists sp_nbr_pos;                       // interfaces: positions of W's columns
 };
 
 struct FactorObj {
   Plan* plan = nullptr;
+  bool f32 = false;                          // factor entries are float (FP32 precisions)
   spand_opts opts{};
   std::shared_ptr<MemPool> arena_pool;       // the context's pool (chunks of the buffers below)
   DevArena arena;                            // numeric factor data

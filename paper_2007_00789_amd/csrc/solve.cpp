@@ -276,7 +276,10 @@ void build_apply_step(FactorObj& F, int l) {
           d.f1 = so ? R.n0[p] : (sf ? R.r2[p] : R.r[p]);
           d.k = R.k[p];
           d.lde = R.kmax[p];
-          d.Et = (so || sf) && R.Y[p] ? R.Y[p] + (int64_t)d.f0 * R.kmax[p] : nullptr;
+          d.Et = (so || sf) && R.Y[p]
+                     ? static_cast<const char*>(R.Y[p]) +
+                           (F.f32 ? sizeof(float) : sizeof(double)) * (size_t)d.f0 * R.kmax[p]
+                     : nullptr;
           d.toff = csz;
           ptoff[p] = csz;
           csz += d.k;
@@ -480,6 +483,7 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
   hipStream_t s = C.stream;
   const int64_t n = F.plan->n;
   ApplyProg& pg = *F.prog;
+  const bool f32 = F.f32;
   double* T = sc.T;
   double* Pp = sc.P;
   double* U = sc.U;
@@ -488,44 +492,44 @@ static void apply_cols(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, doub
   else if (x != y) SPAND_PROF(C, "k_copy_vec", launch_copy_vec(x, y, n * nrhs, s));
   for (const ApplyStep& as : pg.steps) {
     if (as.split) {
-      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.f1, as.n_f1, as.mv, y, n, nrhs, nullptr, Ys, s));
-      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.f2, as.n_f2, as.mv, y, n, nrhs, Ys, T, s));
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.f1, as.n_f1, as.mv, y, n, nrhs, nullptr, Ys, f32, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.f2, as.n_f2, as.mv, y, n, nrhs, Ys, T, f32, s));
     } else {
-      SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, s));
+      SPAND_PROF(C, "k_ap_int_fwd", launch_ap_int_fwd(as.in, as.n_in, y, n, nrhs, T, as.max_in, f32, s));
     }
     SPAND_PROF(C, "k_ap_gather", launch_ap_gather(as.gat, as.src, as.n_gat, y, n, nrhs, T,
-                                                  as.ssplit ? 0 : as.max_gat, s, Ys));
+                                                  as.ssplit ? 0 : as.max_gat, f32, s, Ys));
     if (as.ssplit)
-      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.sf, as.n_sf, as.smv, y, n, nrhs, Ys, nullptr, s));
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.sf, as.n_sf, as.smv, y, n, nrhs, Ys, nullptr, f32, s));
     for (const ApplyColour& ac : as.colours) {
       SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(ac.wyd, ac.n_wyd, ac.sp, y, n, nrhs, nullptr,
-                                                      U, ac.usz, 1, s));
+                                                      U, ac.usz, 1, f32, s));
       SPAND_PROF(C, "k_ap_wy_update", launch_ap_wy_update(ac.wyu, ac.n_wyu, ac.sp, y, n, nrhs,
-                                                          nullptr, U, ac.usz, 1, s));
-      SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_etf, y, n, nrhs, T, ac.max_nf, s));
-      SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, s));
+                                                          nullptr, U, ac.usz, 1, f32, s));
+      SPAND_PROF(C, "k_ap_et_fwd", launch_ap_et_fwd(ac.etf, ac.n_etf, y, n, nrhs, T, ac.max_nf, f32, s));
+      SPAND_PROF(C, "k_ap_gather", launch_ap_gather(ac.gat, ac.src, ac.n_gat, y, n, nrhs, T, ac.max_n, f32, s));
     }
   }
   for (auto it = pg.steps.rbegin(); it != pg.steps.rend(); ++it) {
     const ApplyStep& as = *it;
     for (auto c = as.colours.rbegin(); c != as.colours.rend(); ++c) {
-      SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_etb, y, n, nrhs, Pp, s));
+      SPAND_PROF(C, "k_ap_et_bwd", launch_ap_et_bwd(c->etb, c->n_etb, y, n, nrhs, Pp, f32, s));
       SPAND_PROF(C, "k_ap_wy_dots", launch_ap_wy_dots(c->wyd, c->n_wyd, c->sp, y, n, nrhs, Pp, U,
-                                                      c->usz, 0, s));
+                                                      c->usz, 0, f32, s));
       SPAND_PROF(C, "k_ap_wy_update", launch_ap_wy_update(c->wyu, c->n_wyu, c->sp, y, n, nrhs, Pp,
-                                                          U, c->usz, 0, s));
+                                                          U, c->usz, 0, f32, s));
     }
     if (as.ssplit) {
-      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb1, as.n_sb1, as.smv, y, n, nrhs, nullptr, Ys, s));
-      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb2, as.n_sb2, as.smv, y, n, nrhs, Ys, nullptr, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb1, as.n_sb1, as.smv, y, n, nrhs, nullptr, Ys, f32, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.sb2, as.n_sb2, as.smv, y, n, nrhs, Ys, nullptr, f32, s));
     } else {
-      SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, s));
+      SPAND_PROF(C, "k_ap_scale_bwd", launch_ap_scale_bwd(as.sc, as.n_sc, y, n, nrhs, as.max_sc, f32, s));
     }
     if (as.split) {
-      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.b1, as.n_b1, as.mv, y, n, nrhs, nullptr, Ys, s));
-      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.b2, as.n_b2, as.mv, y, n, nrhs, Ys, nullptr, s));
+      SPAND_PROF(C, "k_ap_mv_rows", launch_ap_mv_rows(as.b1, as.n_b1, as.mv, y, n, nrhs, nullptr, Ys, f32, s));
+      SPAND_PROF(C, "k_ap_mv_cols", launch_ap_mv_cols(as.b2, as.n_b2, as.mv, y, n, nrhs, Ys, nullptr, f32, s));
     } else {
-      SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, s));
+      SPAND_PROF(C, "k_ap_int_bwd", launch_ap_int_bwd(as.in, as.n_in, y, n, nrhs, as.max_in, f32, s));
     }
   }
   if (F.dscale) SPAND_PROF(C, "k_scale_vec", launch_scale_vec(y, F.dscale, y, n, nrhs, s));

@@ -1,0 +1,118 @@
+"""The FP32 forms of the factorization (SPAND_FP32, SPAND_FP32_BF16) against
+the FP64 oracle, through the C ABI.
+
+The factor is computed in FP32 (the Schur products of SPAND_FP32_BF16 from
+BF16 operands), the diagonal-block Cholesky of the top `top_fp64_levels` steps
+and of every block above 64 rows in FP64, and PCG runs in FP64.  The oracle is
+the paper's FP64 method, so ranks are not expected to agree bit for bit; the
+bars are on what the FP32 forms promise:
+* PCG in FP64 reaches the requested relative residual (the true residual at
+  exit is below 10 x tol) and its solution matches the FP64 oracle's within
+  1e-8 relative (both are solutions to 1e-10 of well-conditioned systems);
+* one application of the preconditioner is within 1e-4 relative of the FP64
+  oracle's in FP32 (single-precision factor entries) and within 1e-1 with
+  BF16 Schur products (8-bit mantissas: the Schur complement of a block is a
+  difference of products several times larger than itself, measured 2-3e-2);
+* the ranks stay close to the FP64 ones (the sum over interfaces within 2 %)
+  and the iteration count within 2 x + 2 of the oracle's.
+Every result's error against the oracle is printed.
+"""
+import numpy as np
+import pytest
+
+from synthetic import laplacian_2d, laplacian_3d, fv_diffusion_3d, rhs
+from oracle import nd, spand as ospand, pcg as opcg
+
+gpu = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a).reshape(-1, order="F").copy()).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_00789_amd import spand
+    return spand.Context(0)
+
+
+CASES = [
+    ("lap2d_64", lambda: laplacian_2d(64), 6, 2, 1e-2),
+    ("lap3d_16", lambda: laplacian_3d(16), 6, 1, 1e-2),
+    ("fv3d_12", lambda: fv_diffusion_3d(12, 3.0, 1002), 5, 0, 1e-2),
+    ("lap3d_24_eps1e-3", lambda: laplacian_3d(24), 8, 2, 1e-3),
+]
+
+
+@gpu
+@pytest.mark.parametrize("top", [0, 3, 99], ids=["top0", "top3", "all_fp64_chol"])
+@pytest.mark.parametrize("precision", ["FP32", "FP32_BF16"])
+@pytest.mark.parametrize("scheme", ["FO", "SO", "SF"])
+@pytest.mark.parametrize("name,make,depth,skip,eps", CASES, ids=[c[0] for c in CASES])
+def test_fp32_forms_against_fp64_oracle(ctx, name, make, depth, skip, eps, scheme, precision, top):
+    from paper_2007_00789_amd import spand
+    p = make()
+    print(f"precision {precision} top_fp64_levels={top} {name} {scheme}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    A = p.scipy()
+    F = ospand.factor(A, plan_o, eps, scheme)
+    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, precision=precision,
+                           top_fp64_levels=top)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    fac = ctx.factor(plan, _dev(p.vals), opts)
+    r_o = r_g = 0
+    for l, recs in F.ranks.items():
+        got = fac.ranks(l, plan_o.steps[l].n_clusters)
+        for (c, a, k, r, r2) in recs:
+            assert got["k"][c] >= 0
+            r_o += r
+            r_g += int(got["r"][c])
+    assert abs(r_g - r_o) <= 0.02 * max(r_o, 1) + 2, (r_g, r_o)
+    # one application against the FP64 oracle's
+    x = rhs(p.n, 1, 71)
+    y_ref = ospand.apply(F, x[:, 0])
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, 1, dx, dy)
+    ey = np.linalg.norm(dy.cpu().numpy() - y_ref) / np.linalg.norm(y_ref)
+    assert ey <= (1e-1 if precision == "FP32_BF16" else 1e-4), ey
+    # FP64 PCG on the FP32 preconditioner
+    tol = 1e-10
+    b = rhs(p.n, 1, 72)
+    x_ref, it_ref, _ = opcg.pcg(lambda v: A @ v, lambda v: ospand.apply(F, v), b[:, 0], tol)
+    db = _dev(b)
+    dxs = torch.zeros_like(db)
+    it, rr = ctx.pcg(fac, 1, db, dxs, tol, 1000)
+    xs = dxs.cpu().numpy()
+    ex = np.linalg.norm(xs - x_ref) / np.linalg.norm(x_ref)
+    print(f"  ranks {r_g} (FP64 {r_o}), apply error {ey:.2e}, n_cg {int(it[0])} (FP64 {it_ref}), "
+          f"true residual {rr[0]:.2e}, solution error {ex:.2e}", flush=True)
+    assert rr[0] < 10 * tol
+    assert int(it[0]) <= 2 * it_ref + 2
+    assert ex <= 1e-8, ex
+
+
+@gpu
+def test_fp32_batch_and_views(ctx):
+    """spand_factor_batch and spand_pcg_batch in FP32_BF16: every problem
+    solved to the tolerance and within 1e-8 of its FP64 oracle solution."""
+    from paper_2007_00789_amd import spand
+    probs = [(laplacian_2d(40), 5), (laplacian_3d(12), 4), (fv_diffusion_3d(10, 2.0, 7), 3)]
+    plans = [spand.analyze(p.n, p.rowptr, p.colind, p.coords,
+                           spand.make_opts(depth=d, skip=1, eps=1e-2)) for p, d in probs]
+    opts = spand.make_opts(skip=1, eps=1e-2, precision="FP32_BF16")
+    facs = ctx.factor_batch(plans, [_dev(p.vals) for p, _ in probs], opts)
+    bs = [_dev(rhs(p.n, 1, 90 + i)) for i, (p, _) in enumerate(probs)]
+    xs = [torch.zeros_like(b) for b in bs]
+    res = ctx.pcg_batch(facs, [1] * len(probs), bs, xs, 1e-10, 1000)
+    for i, (p, d) in enumerate(probs):
+        A = p.scipy()
+        F = ospand.factor(A, nd.analyze(p.rowptr, p.colind, p.coords, d, 1), 1e-2, "SO")
+        x_ref, _, _ = opcg.pcg(lambda v: A @ v, lambda v: ospand.apply(F, v),
+                               bs[i].cpu().numpy(), 1e-10)
+        it, rr = res[i]
+        assert rr[0] < 1e-9
+        assert np.linalg.norm(xs[i].cpu().numpy() - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
