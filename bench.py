@@ -563,6 +563,8 @@ def main():
     ap.add_argument("--scheme", default="SO")
     ap.add_argument("--precision", default="FP64", choices=["FP64", "FP32", "FP32_BF16"],
                     help="arithmetic of the factorization (PCG is FP64 in every mode)")
+    ap.add_argument("--prescale", type=int, default=0,
+                    help="1: factor D^-1/2 A D^-1/2 (symmetric diagonal prescaling)")
     ap.add_argument("--workload", default="fv3d_128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-count", type=int, default=48, help="requests of the serving stream")
@@ -608,7 +610,7 @@ def main():
     prob, w = workload(args.workload)
     nrhs, tol = w["nrhs"], w["tol"]
     opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=args.eps, scheme=args.scheme,
-                           precision=args.precision)
+                           precision=args.precision, prescale=args.prescale)
     ctx = spand.Context(0)
     t0 = time.perf_counter()
     plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
@@ -697,7 +699,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD_NAMES.get(args.workload, args.workload)}, n={prob.n}, "
                                f"depth {w['depth']}, skip {w['skip']}, eps {args.eps:g}, "
-                               f"{args.scheme}, {args.precision} factor, FP64 PCG, {nrhs} RHS "
+                               f"{args.scheme}, {args.precision} factor"
+                               f"{', D^-1/2 prescaling' if args.prescale else ''}, FP64 PCG, {nrhs} RHS "
                                f"N(0,1), PCG tol {tol:g}",
                    "global_batch": nrhs, "parallelism": "single GPU"},
         "factor_tflops": factor_tflops,

@@ -56,14 +56,17 @@ typedef enum {
 typedef enum { SPAND_FIRST_ORDER = 1, SPAND_SECOND_ORDER = 2, SPAND_SUPERFINE = 3 } spand_scheme;
 /* Arithmetic of the factorization (a project addition; the paper's runs are
  * FP64).  SPAND_FP64: everything in FP64.  SPAND_FP32: the row panels, the
- * Cholesky factors, the Schur and scaling products, the pivoted QR and the
- * stored factor in FP32, except the steps l < top_fp64_levels (the top
- * separator levels and the root), which run in FP64.  SPAND_FP32_BF16: as
- * SPAND_FP32, with the Schur-complement products of the interior elimination
- * taken from BF16 operands on the matrix cores and accumulated in FP32.  The
- * apply keeps its vectors in FP64 (FP32 factor entries are widened on load),
- * and PCG (SpMV, residuals, dot products) is FP64 in every mode, so PCG
- * refines the solution to the requested tolerance whatever the precision. */
+ * Schur and scaling products, the pivoted QR and the stored factor in FP32;
+ * the diagonal-block Cholesky factorizations (and inverses) of the steps
+ * l < top_fp64_levels (the top separator levels and the root) and of every
+ * block above 64 rows are computed in FP64 and stored in FP32.
+ * SPAND_FP32_BF16: as SPAND_FP32, with the Schur-complement products of the
+ * interior elimination of the steps l >= top_fp64_levels on the BF16 matrix
+ * cores (each FP32 operand split into two BF16 terms, three BF16 products per
+ * pair), accumulated in FP32.  The apply keeps its vectors in FP64 (FP32
+ * factor entries are widened on load), and PCG (SpMV, residuals, dot
+ * products) is FP64 in every mode, so PCG refines the solution to the
+ * requested tolerance whatever the precision. */
 typedef enum { SPAND_FP64 = 0, SPAND_FP32 = 1, SPAND_FP32_BF16 = 2 } spand_precision;
 
 typedef struct {
@@ -86,7 +89,8 @@ typedef struct {
                            prescaling of the experiments, Sec. 4), and apply
                            M = D^{-1/2} M~ D^{-1/2} (M~ the preconditioner of the scaled matrix);
                            a non-positive diagonal entry gives SPAND_E_NOT_SPD.  0 (default): off */
-  int32_t top_fp64_levels; /* FP32 precisions: steps l < top_fp64_levels run in FP64 (default 3:
+  int32_t top_fp64_levels; /* FP32 precisions: the diagonal blocks of the steps l < top_fp64_levels
+                              are factored in FP64 and their Schur products are FP32 (default 3:
                               the root and the two separator levels below it); ignored in FP64 */
   int64_t hbm_budget_bytes; /* > 0: spand_factor fails with SPAND_E_OOM (and frees what it
                                allocated) as soon as the factor plus the working panels of a step

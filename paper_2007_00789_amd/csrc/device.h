@@ -63,8 +63,9 @@ struct TileRef {
 };
 
 // Arithmetic of a GEMM launch: the panels' own precision (FP64 on the FP64
-// matrix cores, FP32 on the FP32 matrix cores), or (R = float only) BF16
-// operands rounded from the FP32 ones, accumulated in FP32 on the matrix cores.
+// matrix cores, FP32 on the FP32 matrix cores), or (R = float only) the BF16
+// matrix cores: each FP32 operand split into two BF16 terms, three BF16
+// products per operand pair, accumulated in FP32.
 enum GemmMode { kGemmNative = 0, kGemmBf16 = 1 };
 
 // Early-stopping column-pivoted QR of one interface (Alg. 1).

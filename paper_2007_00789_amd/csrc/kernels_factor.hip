@@ -630,8 +630,10 @@ __global__ __launch_bounds__(kSmallWaves * kWave) void k_potrf_inv_small(const P
 // Batched multi-term GEMM, 64x64 tile per workgroup: k-slabs of A and B staged
 // in LDS, each wave a 32x32 quadrant as 2x2 matrix-core tiles of 16 x 16:
 // FP64 (16 x 16 x 4 per instruction, R = double), FP32 (16 x 16 x 4, R =
-// float) or BF16 operands rounded from the FP32 slab (16 x 16 x 16, FP32
-// accumulation; MODE = kGemmBf16).
+// float) or BF16 (MODE = kGemmBf16: 16 x 16 x 16, FP32 accumulation), each
+// FP32 operand split into two BF16 terms so that the products keep about 16
+// bits (one BF16 product per pair broke the positive definiteness of the
+// Schur complements of the 10^6-contrast diffusion matrices).
 // ---------------------------------------------------------------------------
 constexpr int kGemmThreads = 256;
 constexpr int kGemmK = 16;
@@ -655,6 +657,15 @@ __device__ __forceinline__ short to_bf16(float x) {
   unsigned u = __float_as_uint(x);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(short h) {
+  return __uint_as_float((unsigned)(unsigned short)h << 16);
+}
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi): two BF16 terms carry
+// 16 bits of x's mantissa
+__device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
+  hi = to_bf16(x);
+  lo = to_bf16(x - from_bf16(hi));
 }
 
 template <class R, int MODE>
@@ -700,19 +711,38 @@ __global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDescT<R>* de
       }
       __syncthreads();
       if constexpr (MODE == kGemmBf16 && !kF64) {
-        s4_t a0, a1, b0, b1;
+        // each FP32 operand as a sum of two BF16 terms; the product keeps the
+        // three terms above the 2^-16 level (hi hi, hi lo, lo hi)
+        s4_t a0, a1, b0, b1, a0l, a1l, b0l, b1l;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int kk = 4 * kq + q;
-          a0[q] = to_bf16(As[kk][wr + r]);
-          a1[q] = to_bf16(As[kk][wr + 16 + r]);
-          b0[q] = to_bf16(Bs[kk][wc + r]);
-          b1[q] = to_bf16(Bs[kk][wc + 16 + r]);
+          short h, l;
+          split_bf16(As[kk][wr + r], h, l);
+          a0[q] = h;
+          a0l[q] = l;
+          split_bf16(As[kk][wr + 16 + r], h, l);
+          a1[q] = h;
+          a1l[q] = l;
+          split_bf16(Bs[kk][wc + r], h, l);
+          b0[q] = h;
+          b0l[q] = l;
+          split_bf16(Bs[kk][wc + 16 + r], h, l);
+          b1[q] = h;
+          b1l[q] = l;
         }
         acc[0][0] = mfma16bf(a0, b0, acc[0][0]);
         acc[0][1] = mfma16bf(a0, b1, acc[0][1]);
         acc[1][0] = mfma16bf(a1, b0, acc[1][0]);
         acc[1][1] = mfma16bf(a1, b1, acc[1][1]);
+        acc[0][0] = mfma16bf(a0, b0l, acc[0][0]);
+        acc[0][1] = mfma16bf(a0, b1l, acc[0][1]);
+        acc[1][0] = mfma16bf(a1, b0l, acc[1][0]);
+        acc[1][1] = mfma16bf(a1, b1l, acc[1][1]);
+        acc[0][0] = mfma16bf(a0l, b0, acc[0][0]);
+        acc[0][1] = mfma16bf(a0l, b1, acc[0][1]);
+        acc[1][0] = mfma16bf(a1l, b0, acc[1][0]);
+        acc[1][1] = mfma16bf(a1l, b1, acc[1][1]);
       } else {
 #pragma unroll
         for (int s4 = 0; s4 < kGemmK / 4; ++s4) {

@@ -2,6 +2,7 @@
 // (Sec. 4: zero initial guess, stop when ||r_k|| < tol ||b|| per column).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 
@@ -48,6 +49,25 @@ struct ApplyStep {
   int32_t n_sc = 0, max_sc = 0;
 };
 
+// The launches of one apply (a fixed sequence for a factor, given the vector
+// and scratch addresses and the column count) captured in a HIP graph: PCG
+// applies the preconditioner to the same buffers every iteration, so the
+// sequence is captured at the first application and replayed afterwards as one
+// graph launch instead of a few hundred kernel launches.
+struct ApplyGraph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  const double* x = nullptr;
+  double* y = nullptr;
+  int32_t nrhs = 0;
+  double *T = nullptr, *P = nullptr, *U = nullptr, *Y = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  ~ApplyGraph() { reset(); }
+};
+
 struct ApplyProg {
   std::vector<ApplyStep> steps;  // in forward order (depth ... 0)
   int64_t scratch = 0;           // doubles per right-hand side
@@ -55,9 +75,19 @@ struct ApplyProg {
   int64_t uscratch = 0;          // u vectors of the wide WY apply, per right-hand side
   int64_t yscratch = 0;          // interior vectors of the split GEMVs, per right-hand side
   DevBuf T, P, U, Y;
+  ApplyGraph graph;
 };
 
 FactorObj::~FactorObj() { delete prog; }
+
+// Graph replay of the apply (disabled by SPAND_APPLY_GRAPH=0, e.g. to compare)
+static bool apply_graphs_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("SPAND_APPLY_GRAPH");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 namespace {
 
@@ -428,8 +458,48 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   sc.P = static_cast<double*>(pg.P.ensure(std::max<int64_t>(pg.pscratch, 1) * w * sizeof(double)));
   sc.U = static_cast<double*>(pg.U.ensure(std::max<int64_t>(pg.uscratch, 1) * w * sizeof(double)));
   sc.Y = static_cast<double*>(pg.Y.ensure(std::max<int64_t>(pg.yscratch, 1) * w * sizeof(double)));
-  for (int32_t c0 = 0; c0 < nrhs; c0 += chunk)
-    apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n, sc);
+  auto launches = [&] {
+    for (int32_t c0 = 0; c0 < nrhs; c0 += chunk)
+      apply_cols(C, F, std::min(chunk, nrhs - c0), x + c0 * n, y + c0 * n, sc);
+  };
+  // per-kernel event timing of the apply's kernels needs the individual launches
+  const bool timed = C.prof.on && (C.prof.only.empty() || C.prof.only.rfind("k_ap_", 0) == 0 ||
+                                   C.prof.only == "k_copy_vec" || C.prof.only == "k_scale_vec");
+  if (timed || !apply_graphs_enabled()) {
+    launches();
+    return;
+  }
+  ApplyGraph& g = pg.graph;
+  const bool same = g.exec && g.stream == C.stream && g.x == x && g.y == y && g.nrhs == nrhs &&
+                    g.T == sc.T && g.P == sc.P && g.U == sc.U && g.Y == sc.Y;
+  if (!same) {
+    g.reset();
+    // the descriptors the apply reads were uploaded when the factor was
+    // finished; nothing is pending, so the capture holds kernel nodes only
+    C.upload.flush(C.stream);
+    SPAND_HIP(hipStreamBeginCapture(C.stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+      launches();
+    } catch (...) {
+      (void)hipStreamEndCapture(C.stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    SPAND_HIP(hipStreamEndCapture(C.stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    SPAND_HIP(e);
+    g.stream = C.stream;
+    g.x = x;
+    g.y = y;
+    g.nrhs = nrhs;
+    g.T = sc.T;
+    g.P = sc.P;
+    g.U = sc.U;
+    g.Y = sc.Y;
+  }
+  SPAND_HIP(hipGraphLaunch(g.exec, C.stream));
 }
 
 // ---------------------------------------------------------------------------
