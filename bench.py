@@ -45,6 +45,33 @@ WORKLOAD_NAMES = {
     "fv3d_128": "fv3d 128^3 finite-volume diffusion, k = 10^U[-3,3] per cell",
 }
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+# dense matrix-core peaks of the GEMM's arithmetic per precision option
+# (FP32_BF16: the Schur products on BF16 MFMA; the other GEMMs stay FP32)
+PEAK_GEMM_TFLOPS = {"FP64": 78.6, "FP32": 157.3, "FP32_BF16": 157.3}
+# kernels whose recorded work is flops (the others record bytes moved)
+FLOP_KERNELS = ("k_gemm", "k_potrf_inv", "k_cpqr", "k_cpqr_coop")
+
+
+def kernel_work(breakdown: dict, per: int, precision: str) -> dict:
+    """Per-kernel algorithmic work and rate of one step, for the kernels whose
+    launches record it: flops (GEMM 2mnk per term, Cholesky n^3/3 per block,
+    pivoted QR 4(a-j)(k-j) per reflector) or HBM bytes (copy, fill, scatter)."""
+    out = {}
+    for k, (ms, calls, work) in sorted(breakdown.items(), key=lambda kv: -kv[1][0]):
+        if work <= 0 or ms <= 0:
+            continue
+        e = {"ms": round(ms / per, 3), "calls": int(calls // per)}
+        if k in FLOP_KERNELS:
+            tf = work / (ms * 1e-3) / 1e12
+            peak = PEAK_GEMM_TFLOPS[precision] if k == "k_gemm" else PEAK_FP64_TFLOPS
+            e.update({"gflop": round(work / per / 1e9, 3), "tflops": round(tf, 3),
+                      "frac_peak": round(tf / peak, 4), "peak_tflops": peak})
+        else:
+            gbs = work / (ms * 1e-3) / 1e9
+            e.update({"gbytes": round(work / per / 1e9, 3), "gbs": round(gbs, 1),
+                      "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
+        out[k] = e
+    return out
 # arithmetic of the factorization per precision option (PCG is FP64 always)
 DTYPES = {"FP64": "f64", "FP32": "f32 factor, f64 PCG", "FP32_BF16": "f32 factor, bf16 Schur, f64 PCG"}
 
@@ -563,6 +590,8 @@ def main():
     ap.add_argument("--scheme", default="SO")
     ap.add_argument("--precision", default="FP64", choices=["FP64", "FP32", "FP32_BF16"],
                     help="arithmetic of the factorization (PCG is FP64 in every mode)")
+    ap.add_argument("--apply-graph", type=int, default=0,
+                    help="1: the apply captured in a HIP graph and replayed by PCG")
     ap.add_argument("--prescale", type=int, default=0,
                     help="1: factor D^-1/2 A D^-1/2 (symmetric diagonal prescaling)")
     ap.add_argument("--workload", default="fv3d_128")
@@ -610,7 +639,8 @@ def main():
     prob, w = workload(args.workload)
     nrhs, tol = w["nrhs"], w["tol"]
     opts = spand.make_opts(depth=w["depth"], skip=w["skip"], eps=args.eps, scheme=args.scheme,
-                           precision=args.precision, prescale=args.prescale)
+                           precision=args.precision, prescale=args.prescale,
+                           apply_graph=args.apply_graph)
     ctx = spand.Context(0)
     t0 = time.perf_counter()
     plan = spand.analyze(prob.n, prob.rowptr, prob.colind, prob.coords, opts, ctx)
@@ -714,6 +744,8 @@ def main():
         "factor_gflop": flops / 1e9,
         "analyze_s": analyze_s,
         "kernel_ms_per_step": kernel_ms,
+        "kernel_work": kernel_work(breakdown, per, args.precision),
+        "gemm_tiles": ctx.gemm_tuning(0 if args.precision == "FP64" else 1),
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.workload in CPU_SAMPLE:

@@ -92,6 +92,14 @@ typedef struct {
   int32_t top_fp64_levels; /* FP32 precisions: the diagonal blocks of the steps l < top_fp64_levels
                               are factored in FP64 and their Schur products are FP32 (default 3:
                               the root and the two separator levels below it); ignored in FP64 */
+  int32_t gemm_tile;    /* 0 (default): GEMM tile per launch from the context's autotuning;
+                           64 or 128: that tile for every GEMM launch (testing) */
+  int32_t apply_graph;  /* 1: the factor's apply is captured in a HIP graph at its first use with a
+                           given set of vector addresses and replayed afterwards (PCG applies
+                           to the same buffers every iteration).  The caller must then not
+                           allocate or free device memory from other threads while a PCG or
+                           apply of this factor runs (those calls synchronize the device and
+                           invalidate a capture).  0 (default): plain launches */
   int64_t hbm_budget_bytes; /* > 0: spand_factor fails with SPAND_E_OOM (and frees what it
                                allocated) as soon as the factor plus the working panels of a step
                                would hold more device memory than this; 0 (default): no limit */
@@ -259,8 +267,10 @@ spand_status spand_pcg(spand_ctx_t ctx, spand_factor_t f, int32_t nrhs, const do
  * than the budget is admitted when nothing else is resident.  The result of a
  * request does not depend on the other requests it was batched with: each
  * problem's factor is the one spand_factor gives it alone, and each column is
- * its own CG run.  Factorizations of different slots run one at a time on the
- * device; analysis, transfers and PCG overlap. */
+ * its own CG run.  The slots' analyses, transfers, factorizations and PCG
+ * solves overlap on the device; only the cooperative pivoted-QR launches of
+ * the sparsified steps run one at a time per device (a lock the library holds
+ * across every context of the process). */
 typedef struct spand_server_s* spand_server_t;
 spand_status spand_server_create(int32_t device, const spand_opts* opts, double tol, int32_t maxit,
                                  int64_t max_bytes, int32_t slots, int32_t max_batch,
@@ -289,12 +299,25 @@ const char* spand_server_error(spand_server_t srv);
 /* Finishes every queued request, then stops the slots and frees the factors. */
 void spand_server_destroy(spand_server_t srv);
 
+/* GEMM tile autotuning of a context (for reporting): the batched GEMM runs on
+ * 64 x 64 or 128 x 128 output tiles; at its first factorization in a given
+ * precision (FP64: precision 0; the FP32 forms: 1) a context times both on
+ * synthetic batches of 64-, 128-, 256- and 512-row blocks and keeps the faster
+ * per block-size class.  tiles[4] receives the chosen tile per class and
+ * ms[8] the two trial times per class (NULL allowed); SPAND_E_STATE if the
+ * context has not tuned that precision yet. */
+spand_status spand_gemm_tuning(spand_ctx_t ctx, int32_t precision, int32_t* tiles, float* ms);
+
 /* Per-kernel timing (for measurement).  spand_profile(ctx, 1) clears the
  * counters and starts recording a HIP event pair on the context stream around
  * every kernel launch of the library; spand_profile(ctx, 0) stops.  Entries
  * accumulate, per kernel name, the summed event time in ms, the number of
  * launches and (where the library knows it) the algorithmic work of those
- * launches (k_cpqr: QR flops).  name receives at most name_len-1 characters. */
+ * launches: flops for k_cpqr / k_cpqr_coop (4(a-j)(k-j) per reflector j),
+ * k_gemm (2 m n k per term; m (m + 1) k for a symmetric target of which only
+ * the lower triangle is formed) and k_potrf_inv (n^3 / 3 per block), bytes
+ * moved for k_copy, k_fill and k_scatter.  name receives at most name_len-1
+ * characters. */
 spand_status spand_profile(spand_ctx_t ctx, int32_t enable);
 /* Restricts the timing to the launches of one kernel name (name = NULL or
  * "": every kernel), so that a timed run carries the event pairs of the

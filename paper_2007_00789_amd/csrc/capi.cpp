@@ -88,6 +88,9 @@ void check_opts(const spand_opts* o) {
   if (o->prescale < 0 || o->prescale > 1) throw Error(SPAND_E_INVALID, "prescale must be 0 or 1");
   if (o->top_fp64_levels < 0) throw Error(SPAND_E_INVALID, "top_fp64_levels must be >= 0");
   if (o->hbm_budget_bytes < 0) throw Error(SPAND_E_INVALID, "hbm_budget_bytes must be >= 0");
+  if (o->apply_graph < 0 || o->apply_graph > 1) throw Error(SPAND_E_INVALID, "apply_graph must be 0 or 1");
+  if (o->gemm_tile != 0 && o->gemm_tile != 64 && o->gemm_tile != 128)
+    throw Error(SPAND_E_INVALID, "gemm_tile must be 0, 64 or 128");
 }
 
 // device copies of the pattern and of the leaf assembly map, made on first use
@@ -132,6 +135,8 @@ void spand_default_opts(spand_opts* o) {
   o->qr_lds_cols = 0;
   o->prescale = 0;
   o->top_fp64_levels = 3;
+  o->apply_graph = 0;
+  o->gemm_tile = 0;
   o->hbm_budget_bytes = 0;
 }
 
@@ -708,6 +713,20 @@ spand_status spand_pcg_batch(spand_ctx_t ctx, int32_t count, const spand_factor_
     return SPAND_E_NO_CONVERGENCE;
   }
   return st;
+}
+
+spand_status spand_gemm_tuning(spand_ctx_t ctx, int32_t precision, int32_t* tiles, float* ms) {
+  if (!ctx || precision < 0 || precision > 1) return SPAND_E_INVALID;
+  const spand::GemmTuner& t = ctx->c.tuner;
+  if (!t.tuned[precision]) return SPAND_E_STATE;
+  for (int c = 0; c < spand::GemmTuner::kClasses; ++c) {
+    if (tiles) tiles[c] = t.tile[precision][c];
+    if (ms) {
+      ms[2 * c] = t.ms[precision][c][0];
+      ms[2 * c + 1] = t.ms[precision][c][1];
+    }
+  }
+  return SPAND_OK;
 }
 
 spand_status spand_profile(spand_ctx_t ctx, int32_t enable) {

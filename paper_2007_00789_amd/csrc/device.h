@@ -174,9 +174,11 @@ void launch_potrf_inv(const PotrfDescT<R>* d, int32_t count, int32_t max_n, int3
 template <class R>
 void launch_potrf_blocks(const PotrfDescT<R>* d, int32_t count, int32_t max_n, int32_t* info,
                          hipStream_t s);
+// tile: the output tile of the launch's TileRefs, kGemmTile (64) or kGemmTileL
+// (128: four 64 x 64 wave quadrants, double-buffered k-slabs)
 template <class R>
 void launch_gemm(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* tiles, int64_t ntiles,
-                 GemmMode mode, hipStream_t s);
+                 GemmMode mode, int tile, hipStream_t s);
 template <class R>
 void launch_cpqr(const CpqrDescT<R>* d, const CpqrNbrT<R>* nb, int32_t count, int32_t* n_cur,
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
@@ -202,6 +204,7 @@ hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const 
                             hipStream_t s);
 
 constexpr int kGemmTile = 64;
+constexpr int kGemmTileL = 128;
 constexpr int kCpqrMaxK = 12288;      // trailing norms of a CPQR live in LDS
 
 }  // namespace spand

@@ -257,17 +257,18 @@ inline int64_t find_adj(const StepPlan& st, int c, int target) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// output tiles of an m x n GEMM (lower_only: those touching the lower triangle)
-int64_t gemm_tile_count(int m, int n, bool lower_only) {
-  const int64_t tm = ceil_div(m, kGemmTile), tn = ceil_div(n, kGemmTile);
+// output tiles (tile x tile) of an m x n GEMM (lower_only: those touching the
+// lower triangle)
+int64_t gemm_tile_count(int m, int n, bool lower_only, int tile) {
+  const int64_t tm = ceil_div(m, tile), tn = ceil_div(n, tile);
   if (!lower_only) return tm * tn;
   int64_t c = 0;
   for (int64_t j = 0; j < tn; ++j) c += std::max<int64_t>(0, tm - j);
   return c;
 }
 
-int64_t put_gemm_tiles(TileRef* out, int32_t desc, int m, int n, bool lower_only) {
-  const int tm = (int)ceil_div(m, kGemmTile), tn = (int)ceil_div(n, kGemmTile);
+int64_t put_gemm_tiles(TileRef* out, int32_t desc, int m, int n, bool lower_only, int tile) {
+  const int tm = (int)ceil_div(m, tile), tn = (int)ceil_div(n, tile);
   int64_t c = 0;
   for (int j = 0; j < tn; ++j)
     for (int i = 0; i < tm; ++i)
@@ -362,11 +363,182 @@ int desc_threads(size_t items) {
   return std::min(8, (int)std::max(1u, std::thread::hardware_concurrency()));
 }
 
-void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, bool lower_only) {
-  const int tm = (int)ceil_div(m, kGemmTile), tn = (int)ceil_div(n, kGemmTile);
+void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, bool lower_only,
+                    int tile) {
+  const int tm = (int)ceil_div(m, tile), tn = (int)ceil_div(n, tile);
   for (int j = 0; j < tn; ++j)
     for (int i = 0; i < tm; ++i)
       if (!lower_only || i >= j) tiles.push_back({desc, i, j, 0});
+}
+
+// ---------------------------------------------------------------------------
+// GEMM tile autotuning.  A GEMM launch is classed by the typical output block
+// of its descriptors (the square root of their mean m n: below 96, below 192,
+// below 384, above); for every class the tuner times both tile kernels (64 x 64
+// and 128 x 128) on the device, on a synthetic batch of such blocks with
+// k = 256 (zero operands; the timing does not depend on the values), and keeps
+// the faster.  Done once per context and element type, at its first
+// factorization (a few tens of milliseconds).  SPAND_GEMM_TILE=64 or 128 forces
+// one kernel (measurement).
+// ---------------------------------------------------------------------------
+constexpr int kTuneSizes[GemmTuner::kClasses] = {64, 128, 256, 512};
+
+int gemm_class(double mean_mn) {
+  const double d = std::sqrt(std::max(mean_mn, 0.0));
+  return d < 96 ? 0 : d < 192 ? 1 : d < 384 ? 2 : 3;
+}
+
+int forced_gemm_tile() {
+  static const int t = [] {
+    const char* e = std::getenv("SPAND_GEMM_TILE");
+    const int v = e ? std::atoi(e) : 0;
+    return v == kGemmTile || v == kGemmTileL ? v : 0;
+  }();
+  return t;
+}
+
+template <class FT>
+void tune_gemm(Ctx& C) {
+  const int w = sizeof(FT) == 4;
+  if (C.tuner.tuned[w]) return;
+  hipStream_t s = C.stream;
+  // every trial launch: kTrialTiles 64 x 64 output tiles (eight per compute
+  // unit) of depth kTrialK, so that both kernels run at throughput
+  constexpr int K = 512;
+  constexpr int64_t kTrialTiles = 2048;
+  std::vector<void*> bufs;
+  auto dalloc = [&](size_t bytes) {
+    void* p = nullptr;
+    SPAND_HIP(hipMalloc(&p, bytes));
+    bufs.push_back(p);
+    return p;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    SPAND_HIP(hipEventCreate(&e0));
+    SPAND_HIP(hipEventCreate(&e1));
+    for (int c = 0; c < GemmTuner::kClasses; ++c) {
+      const int n = kTuneSizes[c];
+      const int count = (int)std::max<int64_t>(1, kTrialTiles / (((int64_t)n / kGemmTile) * (n / kGemmTile)));
+      FT* A = static_cast<FT*>(dalloc((size_t)K * n * sizeof(FT)));
+      FT* Cm = static_cast<FT*>(dalloc((size_t)count * n * n * sizeof(FT)));
+      SPAND_HIP(hipMemsetAsync(A, 0, (size_t)K * n * sizeof(FT), s));
+      std::vector<GemmDescT<FT>> gd(count);
+      std::vector<GemmTermT<FT>> gt(1, GemmTermT<FT>{A, A, K, K, K, 0});
+      for (int i = 0; i < count; ++i) {
+        GemmDescT<FT> g{};
+        g.C = Cm + (size_t)i * n * n;
+        g.term0 = 0;
+        g.term1 = 1;
+        g.ldc = n;
+        g.m = n;
+        g.n = n;
+        g.transA = 1;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        gd[i] = g;
+      }
+      auto* d_gd = static_cast<GemmDescT<FT>*>(dalloc(gd.size() * sizeof(gd[0])));
+      auto* d_gt = static_cast<GemmTermT<FT>*>(dalloc(sizeof(gt[0])));
+      SPAND_HIP(hipMemcpyAsync(d_gd, gd.data(), gd.size() * sizeof(gd[0]), hipMemcpyHostToDevice, s));
+      SPAND_HIP(hipMemcpyAsync(d_gt, gt.data(), sizeof(gt[0]), hipMemcpyHostToDevice, s));
+      float best = 0.f;
+      for (int tile : {kGemmTile, kGemmTileL}) {
+        std::vector<TileRef> tl;
+        for (int i = 0; i < count; ++i) add_gemm_tiles(tl, i, n, n, false, tile);
+        auto* d_tl = static_cast<TileRef*>(dalloc(tl.size() * sizeof(TileRef)));
+        SPAND_HIP(hipMemcpyAsync(d_tl, tl.data(), tl.size() * sizeof(TileRef), hipMemcpyHostToDevice, s));
+        launch_gemm(d_gd, d_gt, d_tl, (int64_t)tl.size(), kGemmNative, tile, s);   // warm-up
+        std::vector<float> ms;
+        for (int rep = 0; rep < 3; ++rep) {
+          SPAND_HIP(hipEventRecord(e0, s));
+          launch_gemm(d_gd, d_gt, d_tl, (int64_t)tl.size(), kGemmNative, tile, s);
+          SPAND_HIP(hipEventRecord(e1, s));
+          SPAND_HIP(hipEventSynchronize(e1));
+          float t = 0.f;
+          SPAND_HIP(hipEventElapsedTime(&t, e0, e1));
+          ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        C.tuner.ms[w][c][tile == kGemmTileL] = ms[1];
+        if (tile == kGemmTile || ms[1] < best) {
+          best = ms[1];
+          C.tuner.tile[w][c] = tile;
+        }
+      }
+    }
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    for (void* p : bufs) (void)hipFree(p);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  SPAND_HIP(hipStreamSynchronize(s));
+  for (void* p : bufs) (void)hipFree(p);
+  C.tuner.tuned[w] = true;
+}
+
+// tile of a launch whose descriptors have this mean output size
+template <class FT>
+int pick_tile(const Ctx& C, const spand_opts& o, double mean_mn) {
+  if (o.gemm_tile) return o.gemm_tile;
+  if (const int t = forced_gemm_tile()) return t;
+  return C.tuner.tile[sizeof(FT) == 4][gemm_class(mean_mn)];
+}
+template <class FT>
+double mean_mn(const std::vector<GemmDescT<FT>>& gd) {
+  double sum = 0.0;
+  for (const auto& g : gd) sum += (double)g.m * g.n;
+  return gd.empty() ? 0.0 : sum / (double)gd.size();
+}
+
+// Algorithmic work of a launch, recorded with the per-kernel timing: a GEMM
+// launch counts 2 m n k flops per term (the lower triangle with its diagonal,
+// m (m + 1) k, for a symmetric target), a Cholesky launch n^3 / 3 per block
+// (the explicit inverse is not counted), a copy or fill the bytes it moves.
+template <class FT>
+double gemm_flops(const GemmDescT<FT>* gd, size_t ngd, const GemmTermT<FT>* gt) {
+  double f = 0.0;
+  for (size_t i = 0; i < ngd; ++i) {
+    double k = 0.0;
+    for (int64_t t = gd[i].term0; t < gd[i].term1; ++t) k += gt[t].k;
+    const double mn = gd[i].lower_only ? 0.5 * gd[i].m * (gd[i].m + 1.0) : (double)gd[i].m * gd[i].n;
+    f += 2.0 * mn * k;
+  }
+  return f;
+}
+template <class FT>
+double gemm_flops(const std::vector<GemmDescT<FT>>& gd, const std::vector<GemmTermT<FT>>& gt) {
+  return gemm_flops(gd.data(), gd.size(), gt.data());
+}
+template <class FT>
+double potrf_flops(const std::vector<PotrfDescT<FT>>& pd) {
+  double f = 0.0;
+  for (const auto& p : pd) f += (double)p.n * p.n * p.n / 3.0;
+  return f;
+}
+
+// One cooperative QR launch at a time per device, across every context of the
+// process: a cooperative launch needs all its workgroups resident at once, and
+// two of them in flight could each hold compute units the other one's waiting
+// workgroups need.  Everything else of a factorization (and other contexts'
+// factorizations, applies and PCG) overlaps freely with it.
+std::mutex& coop_mutex(int device) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu[kMaxDevices];
+  return mu[std::clamp(device, 0, kMaxDevices - 1)];
+}
+
+// the tiles of every descriptor of a launch
+template <class FT>
+std::vector<TileRef> tiles_of(const std::vector<GemmDescT<FT>>& gd, int tile) {
+  std::vector<TileRef> tl;
+  for (size_t i = 0; i < gd.size(); ++i)
+    add_gemm_tiles(tl, (int32_t)i, gd[i].m, gd[i].n, gd[i].lower_only != 0, tile);
+  return tl;
 }
 
 // Blocks of at most 64 rows first, the larger ones after; the breakdown flags
@@ -665,6 +837,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
   auto Pt = [](void* p) { return static_cast<FT*>(p); };
   constexpr bool kF32 = sizeof(FT) == 4;
   F.f32 = kF32;
+  tune_gemm<FT>(C);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = C.stream;
   const int D = P.depth;
@@ -741,6 +914,8 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
   FT* panel = static_cast<FT*>(C.panels[cur].ensure(layp->total * sizeof(FT)));
   SPAND_PROF(C, "k_fill", launch_fill(panel, layp->total, 0.0, s));
   SPAND_PROF(C, "k_scatter", launch_scatter(d_vals, P.d_leaf_dest, P.nnz, panel, s));
+  C.prof.add_work("k_fill", (double)layp->total * sizeof(FT));
+  C.prof.add_work("k_scatter", (double)P.nnz * (sizeof(double) + sizeof(int64_t) + sizeof(FT)));
 
   for (int l = D; l >= 0; --l) {
     const StepPlan& st = P.steps[l];
@@ -800,6 +975,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       prep_potrf(C, pd, pd_cluster, l < o.top_fp64_levels, pl);
       pd_cluster = pl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(pl, d_info_i, s));
+      if (C.prof.on) C.prof.add_work("k_potrf_inv", potrf_flops(pd));
       // G_s = L_s^{-1} B_{s,W}
       std::vector<GemmD> gd;
       std::vector<GemmTm> gt;
@@ -820,13 +996,16 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
         g.alpha = 1.0;
         g.beta = 0.0;
         gd.push_back(g);
-        add_gemm_tiles(tiles, (int32_t)gd.size() - 1, ns, ks, false);
       }
+      const int gtile = pick_tile<FT>(C, o, mean_mn(gd));
+      tiles = tiles_of(gd, gtile);
       if (!tiles.empty()) {
         const auto* d_gd = C.upload.upload(gd);
         const auto* d_gt = C.upload.upload(gt);
         const auto* d_tiles = C.upload.upload(tiles);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), kGemmNative, s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), kGemmNative,
+                                            gtile, s));
+        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gd, gt));
       }
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
       // from the plan: targets and their interiors in ascending order).  The
@@ -842,6 +1021,15 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
         for (int64_t q = tg.t0; q < tg.t1; ++q) t += sizes[st.schur_terms[q].s] != 0;
         return t;
       };
+      // tile of the launch from the mean size of its live target blocks
+      double sch_mn = 0.0;
+      int64_t sch_n = 0;
+      for (const StepPlan::SchurTarget& tg : st.schur)
+        if (sizes[tg.w1] != 0 && sizes[tg.w2] != 0) {
+          sch_mn += (double)sizes[tg.w1] * sizes[tg.w2];
+          ++sch_n;
+        }
+      const int stile = pick_tile<FT>(C, o, sch_n ? sch_mn / (double)sch_n : 0.0);
       host_parallel(nchunk, nth, [&](int c) {
         int64_t ngd = 0, ngt = 0, ntl = 0;
         for (int64_t i = nsch * c / nchunk; i < nsch * (c + 1) / nchunk; ++i) {
@@ -851,7 +1039,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           if (t == 0) continue;
           ++ngd;
           ngt += t;
-          ntl += gemm_tile_count(sizes[tg.w1], sizes[tg.w2], tg.w1 == tg.w2);
+          ntl += gemm_tile_count(sizes[tg.w1], sizes[tg.w2], tg.w1 == tg.w2, stile);
         }
         o_gd[c + 1] = ngd;
         o_gt[c + 1] = ngt;
@@ -900,10 +1088,11 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
             g.lower_only = w1 == w2;
             g.alpha = -1.0;
             g.beta = 1.0;
-            itl += put_gemm_tiles(htl + itl, (int32_t)igd, g.m, g.n, w1 == w2);
+            itl += put_gemm_tiles(htl + itl, (int32_t)igd, g.m, g.n, w1 == w2, stile);
             ++igd;
           }
         });
+        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(hgd, (size_t)o_gd[nchunk], hgt));
         C.upload.commit(hgd, (size_t)o_gd[nchunk]);
         C.upload.commit(hgt, (size_t)o_gt[nchunk]);
         C.upload.commit(htl, (size_t)o_tl[nchunk]);
@@ -911,7 +1100,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
         // (SPAND_FP32_BF16); in the panels' own precision otherwise
         const GemmMode sm = o.precision == SPAND_FP32_BF16 && l >= o.top_fp64_levels ? kGemmBf16
                                                                                      : kGemmNative;
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], sm, s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], sm, stile, s));
       }
     }
 
@@ -923,6 +1112,9 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
 
     // ---------------- (b) scaling and (c) sparsification ----------------
     std::vector<char> coop_used;
+    // held from the step's first cooperative QR launch until its ranks are
+    // read back (the device has finished them)
+    std::unique_lock<std::mutex> coop_lk(coop_mutex(C.device), std::defer_lock);
     std::vector<PotrfD> zd;
     std::vector<int32_t> zd_cluster;
     if (st.sparsified) {
@@ -942,6 +1134,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       prep_potrf(C, zd, zd_cluster, l < o.top_fp64_levels, zl);
       zd_cluster = zl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(zl, d_info_f, s));
+      if (C.prof.on) C.prof.add_work("k_potrf_inv", potrf_flops(zd));
       // two-sided scaling of every interface pair p < q
       std::vector<GemmD> g1, g2;
       std::vector<GemmTm> t1, t2;
@@ -973,7 +1166,6 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           a.n = aq;
           a.alpha = 1.0;
           g1.push_back(a);
-          add_gemm_tiles(tl1, (int32_t)g1.size() - 1, ap, aq, false);
           t2.push_back({Tpq, Pt(R.Zinv[q]), ap, aq, aq, 0});
           GemmD b{};
           b.C = blk(p, e);
@@ -987,22 +1179,28 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           b.transB = 1;
           b.alpha = 1.0;
           g2.push_back(b);
-          add_gemm_tiles(tl2, (int32_t)g2.size() - 1, ap, aq, false);
         }
+      const int ctile = pick_tile<FT>(C, o, mean_mn(g1));
+      tl1 = tiles_of(g1, ctile);
+      tl2 = tiles_of(g2, ctile);
       if (!tl1.empty()) {
         const auto* d_g1 = C.upload.upload(g1);
         const auto* d_t1 = C.upload.upload(t1);
         const auto* d_tl1 = C.upload.upload(tl1);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1, (int64_t)tl1.size(), kGemmNative, s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1, (int64_t)tl1.size(), kGemmNative,
+                                            ctile, s));
         const auto* d_g2 = C.upload.upload(g2);
         const auto* d_t2 = C.upload.upload(t2);
         const auto* d_tl2 = C.upload.upload(tl2);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2, (int64_t)tl2.size(), kGemmNative, s));
+        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2, (int64_t)tl2.size(), kGemmNative,
+                                            ctile, s));
+        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(g1, t1) + gemm_flops(g2, t2));
       }
       // sparsification, one launch per colour: interfaces whose coupling fits
       // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
       // the others the single-workgroup QR on a global-memory workspace
       coop_used.assign(nc, 0);
+      coop_lk.lock();
       // The barrier words of every cooperative group of the step (at most one
       // group per interface) are cleared by one fill before the first launch;
       // each colour is launched as soon as it is planned.
@@ -1198,6 +1396,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
     std::vector<int32_t> cur_sizes = sizes;  // sizes after this step's sparsification
     if (st.sparsified || stop_here) {
       const std::vector<int32_t> hb = read_back(l, pd_cluster, zd_cluster);
+      if (coop_lk.owns_lock()) coop_lk.unlock();
       if (st.sparsified) {
         const int32_t herr = hb[nc];
         if (herr & 1) throw Error(SPAND_E_STATE, "cooperative QR timed out at step " + std::to_string(l));
@@ -1233,6 +1432,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       npanel = static_cast<FT*>(
           C.panels[1 - cur].ensure(std::max<int64_t>(nlay.total, 1) * sizeof(FT)));
       SPAND_PROF(C, "k_fill", launch_fill(npanel, nlay.total, 0.0, s));
+      C.prof.add_work("k_fill", (double)nlay.total * sizeof(FT));
       const int64_t nm = (int64_t)st.merge.size();
       const int mth = desc_threads((size_t)nm);
       const int mchunk = mth > 1 ? 4 * mth : 1;
@@ -1263,6 +1463,11 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           d.n = cur_sizes[cj];
         }
       });
+      if (C.prof.on) {
+        double bytes = 0.0;
+        for (int64_t i = 0; i < o_cp[mchunk]; ++i) bytes += 2.0 * hcp[i].m * hcp[i].n * sizeof(FT);
+        C.prof.add_work("k_copy", bytes);
+      }
       C.upload.commit(hcp, (size_t)o_cp[mchunk]);
       SPAND_PROF(C, "k_copy", launch_copy(d_cp, o_cp[mchunk], s));
     }
@@ -1351,7 +1556,6 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
         g.term0 = (int64_t)gt.size();
         gt.push_back(GemmTm{Pt(R.V[p]), Pt(R.V[p]), a, a, a, 0});
         g.term1 = (int64_t)gt.size();
-        add_gemm_tiles(tiles, (int32_t)gd.size(), nref, nref, true);
         gd.push_back(g);
         FT* X = nullptr;
         if (nref > kWyLdsN) {
@@ -1364,9 +1568,13 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
     if (!wy.empty()) {
       const auto* d_gd = C.upload.upload(gd);
       const auto* d_gt = C.upload.upload(gt);
+      const int wtile = pick_tile<FT>(C, o, mean_mn(gd));
+      tiles = tiles_of(gd, wtile);
       const auto* d_tl = C.upload.upload(tiles);
       const auto* d_wy = C.upload.upload(wy);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), kGemmNative, s));
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), kGemmNative,
+                                          wtile, s));
+      if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gd, gt));
       SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), s));
       // V T of every interface (a x nref): the apply then needs no pass over T
       // (Q^T x = x - V (VT)^T x, Q y = y - VT V^T y)
@@ -1387,13 +1595,16 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           g.term0 = (int64_t)gvt.size();
           gvt.push_back(GemmTm{Pt(R.V[p]), Pt(R.T[p]), a, nref, nref, 0});
           g.term1 = (int64_t)gvt.size();
-          add_gemm_tiles(vtiles, (int32_t)gv.size(), a, nref, false);
           gv.push_back(g);
         }
       const auto* d_gv = C.upload.upload(gv);
       const auto* d_gvt = C.upload.upload(gvt);
+      const int vtile = pick_tile<FT>(C, o, mean_mn(gv));
+      vtiles = tiles_of(gv, vtile);
       const auto* d_vtl = C.upload.upload(vtiles);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), kGemmNative, s));
+      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), kGemmNative,
+                                          vtile, s));
+      if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gv, gvt));
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));

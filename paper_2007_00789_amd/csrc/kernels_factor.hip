@@ -783,6 +783,157 @@ __global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDescT<R>* de
 }
 
 // ---------------------------------------------------------------------------
+// The same batched multi-term GEMM over 128 x 128 output tiles, for launches
+// of large blocks: each of the four waves owns a 64 x 64 quadrant as 4 x 4
+// matrix-core tiles of 16 x 16 (16 instructions per 4-deep k step against 4
+// for the 64-tile kernel, for the same two LDS operand loads per subtile row
+// or column), and the k-slabs are double buffered: the next slab's global
+// loads are issued into registers before the current slab's products, and
+// stored into the other LDS buffer after them, so one barrier per slab
+// separates the two and the global latency hides behind the matrix cores.
+// ---------------------------------------------------------------------------
+constexpr int kG2 = 128;                         // output tile
+constexpr int kG2Per = kG2 * kGemmK / kGemmThreads;   // slab elements per thread and operand
+
+template <class R, int MODE>
+__global__ __launch_bounds__(kGemmThreads, 2) void k_gemm128(const GemmDescT<R>* descs,
+                                                           const GemmTermT<R>* terms,
+                                                           const TileRef* tiles) {
+  constexpr bool kF64 = sizeof(R) == 8;
+  using acc_t = typename std::conditional<kF64, d4_t, f4_t>::type;
+  __shared__ R As[2][kGemmK][kG2 + 1];
+  __shared__ R Bs[2][kGemmK][kG2 + 1];
+  const TileRef t = tiles[blockIdx.x];
+  const GemmDescT<R> d = descs[t.desc];
+  const int i0 = t.ti * kG2, j0 = t.tj * kG2;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int wr = 64 * (w & 1), wc = 64 * (w >> 1), r = lane & 15, kq = lane >> 4;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < 4; ++ci) acc[ri][ci] = acc_t{0, 0, 0, 0};
+  // slab (term, k0) -> registers
+  R ra[kG2Per], rb[kG2Per];
+  auto fetch = [&](int64_t term, int k0) {
+    const GemmTermT<R> tm = terms[term];
+#pragma unroll
+    for (int q = 0; q < kG2Per; ++q) {
+      const int e = threadIdx.x + q * kGemmThreads;
+      int ii, kk;
+      if (!d.transA) { ii = e % kG2; kk = e / kG2; }
+      else { kk = e % kGemmK; ii = e / kGemmK; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      ra[q] = (gi < d.m && gk < tm.k)
+                  ? (d.transA ? tm.A[gk + (int64_t)gi * tm.lda] : tm.A[gi + (int64_t)gk * tm.lda])
+                  : R(0);
+      int jj, kb;
+      if (!d.transB) { kb = e % kGemmK; jj = e / kGemmK; }
+      else { jj = e % kG2; kb = e / kG2; }
+      const int gj = j0 + jj, gk2 = k0 + kb;
+      rb[q] = (gj < d.n && gk2 < tm.k)
+                  ? (d.transB ? tm.B[gj + (int64_t)gk2 * tm.ldb] : tm.B[gk2 + (int64_t)gj * tm.ldb])
+                  : R(0);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kG2Per; ++q) {
+      const int e = threadIdx.x + q * kGemmThreads;
+      if (!d.transA) As[buf][e / kG2][e % kG2] = ra[q];
+      else As[buf][e % kGemmK][e / kGemmK] = ra[q];
+      if (!d.transB) Bs[buf][e % kGemmK][e / kGemmK] = rb[q];
+      else Bs[buf][e / kG2][e % kG2] = rb[q];
+    }
+  };
+  int64_t term = d.term0;
+  int k0 = 0;
+  if (term >= d.term1) return;
+  while (term < d.term1 && terms[term].k == 0) ++term;
+  int cur = 0;
+  if (term < d.term1) {
+    fetch(term, 0);
+    stash(0);
+  }
+  __syncthreads();
+  while (term < d.term1) {
+    // the slab after (term, k0)
+    int64_t nterm = term;
+    int nk0 = k0 + kGemmK;
+    if (nk0 >= terms[term].k) {
+      nk0 = 0;
+      ++nterm;
+      while (nterm < d.term1 && terms[nterm].k == 0) ++nterm;
+    }
+    const bool more = nterm < d.term1;
+    if (more) fetch(nterm, nk0);
+    if constexpr (MODE == kGemmBf16 && !kF64) {
+      s4_t ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 4 * kq + q;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          short h, l;
+          split_bf16(As[cur][kk][wr + 16 * x + r], h, l);
+          ah[x][q] = h;
+          al[x][q] = l;
+          split_bf16(Bs[cur][kk][wc + 16 * x + r], h, l);
+          bh[x][q] = h;
+          bl[x][q] = l;
+        }
+      }
+#pragma unroll
+      for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci) {
+          acc[ri][ci] = mfma16bf(ah[ri], bh[ci], acc[ri][ci]);
+          acc[ri][ci] = mfma16bf(ah[ri], bl[ci], acc[ri][ci]);
+          acc[ri][ci] = mfma16bf(al[ri], bh[ci], acc[ri][ci]);
+        }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < kGemmK / 4; ++s4) {
+        const int kk = 4 * s4 + kq;
+        R a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          a[x] = As[cur][kk][wr + 16 * x + r];
+          b[x] = Bs[cur][kk][wc + 16 * x + r];
+        }
+#pragma unroll
+        for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+          for (int ci = 0; ci < 4; ++ci) {
+            if constexpr (kF64) acc[ri][ci] = mfma16(a[ri], b[ci], acc[ri][ci]);
+            else acc[ri][ci] = mfma16f(a[ri], b[ci], acc[ri][ci]);
+          }
+      }
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+    term = nterm;
+    k0 = nk0;
+  }
+#pragma unroll
+  for (int ri = 0; ri < 4; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int row = kF64 ? kq + 4 * v4 : 4 * kq + v4;
+        const int gi = i0 + wr + 16 * ri + row, gj = j0 + wc + 16 * ci + r;
+        if (gi < d.m && gj < d.n) {
+          R v = R(d.alpha) * acc[ri][ci][v4];
+          if (d.beta != 0.0) v = fma(R(d.beta), d.C[gi + (int64_t)gj * d.ldc], v);
+          d.C[gi + (int64_t)gj * d.ldc] = v;
+          if (d.C2) d.C2[gj + (int64_t)gi * d.ldc2] = v;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Early-stopping column-pivoted Householder QR, one interface per workgroup.
 // The coupling W (a x k) is copied transposed into the workspace Yt
 // (element (i, c) at Yt[c + i*kmax]), so one thread owns one column: the
@@ -1137,17 +1288,18 @@ void launch_potrf_blocks(const PotrfDescT<R>* d, int32_t count, int32_t max_n, i
 
 template <class R>
 void launch_gemm(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* tiles, int64_t ntiles,
-                 GemmMode mode, hipStream_t s) {
+                 GemmMode mode, int tile, hipStream_t s) {
   if (ntiles <= 0) return;
+  const dim3 grid((unsigned)ntiles), block(kGemmThreads);
   if constexpr (sizeof(R) == 4) {
     if (mode == kGemmBf16) {
-      hipLaunchKernelGGL((k_gemm<R, kGemmBf16>), dim3((unsigned)ntiles), dim3(kGemmThreads), 0, s,
-                         d, t, tiles);
+      if (tile == kG2) hipLaunchKernelGGL((k_gemm128<R, kGemmBf16>), grid, block, 0, s, d, t, tiles);
+      else hipLaunchKernelGGL((k_gemm<R, kGemmBf16>), grid, block, 0, s, d, t, tiles);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gemm<R, kGemmNative>), dim3((unsigned)ntiles), dim3(kGemmThreads), 0, s, d,
-                     t, tiles);
+  if (tile == kG2) hipLaunchKernelGGL((k_gemm128<R, kGemmNative>), grid, block, 0, s, d, t, tiles);
+  else hipLaunchKernelGGL((k_gemm<R, kGemmNative>), grid, block, 0, s, d, t, tiles);
 }
 
 template <class R>
@@ -1183,7 +1335,7 @@ void launch_copy(const CopyDescT<S, D>* d, int64_t count, hipStream_t s) {
   template void launch_potrf_blocks<R>(const PotrfDescT<R>*, int32_t, int32_t, int32_t*,          \
                                        hipStream_t);                                              \
   template void launch_gemm<R>(const GemmDescT<R>*, const GemmTermT<R>*, const TileRef*, int64_t, \
-                               GemmMode, hipStream_t);                                            \
+                               GemmMode, int, hipStream_t);                                       \
   template void launch_cpqr<R>(const CpqrDescT<R>*, const CpqrNbrT<R>*, int32_t, int32_t*,        \
                                int32_t*, int32_t*, int32_t*, double, double, int32_t, int32_t,    \
                                hipStream_t);                                                      \

@@ -167,6 +167,15 @@ struct Prof {
     (C).prof.end(pid_, (C).stream);                    \
   } while (0)
 
+// Tile choice of the batched GEMM per size class of the launch's output blocks
+// and per element type (index 0: double, 1: float), measured on the device.
+struct GemmTuner {
+  static constexpr int kClasses = 4;
+  bool tuned[2] = {false, false};
+  int tile[2][kClasses] = {{64, 64, 64, 64}, {64, 64, 64, 64}};
+  float ms[2][kClasses][2] = {};   // trial times, 64- and 128-tile kernels
+};
+
 // Size of the fixed device scratch of the allocation-free apply (one array per
 // device, held until the process ends).
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
@@ -182,6 +191,7 @@ struct Ctx {
   DevBuf panels[2];        // ping-pong row panels of consecutive steps
   DevBuf temp;             // scaling temporaries
   DevBuf ints;             // per-step integer outputs (n_cur, ranks, info)
+  GemmTuner tuner;         // GEMM tile per size class (measured at the first factorization)
   Prof prof;
 };
 

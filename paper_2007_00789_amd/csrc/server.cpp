@@ -10,10 +10,12 @@
 // next to the resident ones within the byte budget, after the least recently
 // used idle factors have been released.
 //
-// Overlap: analysis, uploads and PCG of different slots run concurrently.
-// Factorizations run one at a time on the device, because the cooperative QR
-// kernel waits on workgroups of its own launch: two such launches in flight
-// could hold the compute units each other's groups need.
+// Overlap: the slots' analyses, uploads, factorizations and PCG solves run
+// concurrently on their own streams; only the cooperative QR launches of the
+// sparsified steps go one at a time per device (the library holds a device-wide
+// lock from a step's first cooperative launch until its ranks are read back),
+// because such a launch waits on workgroups of its own: two in flight could
+// hold the compute units each other's groups need.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -83,7 +85,7 @@ struct spand_server_s {
   int32_t maxit = 1000;
   int64_t max_bytes = 0;
   int32_t max_batch = 32;
-  std::mutex mu, factor_mu;
+  std::mutex mu;
   std::condition_variable cv, cv_done;
   bool stop = false;
   int64_t next_id = 1;
@@ -221,7 +223,6 @@ void spand_server_s::worker(spand_ctx_t ctx, hipStream_t stream) {
           fst = SPAND_E_HIP;
       double tf = 0.0;
       if (fst == SPAND_OK) {
-        std::lock_guard<std::mutex> lk(factor_mu);
         const auto t1 = Clock::now();
         fst = spand_factor(ctx, fresh->plan, d_vals, &opts, &fresh->fac);
         tf = std::chrono::duration<double>(Clock::now() - t1).count();

@@ -80,14 +80,7 @@ struct ApplyProg {
 
 FactorObj::~FactorObj() { delete prog; }
 
-// Graph replay of the apply (disabled by SPAND_APPLY_GRAPH=0, e.g. to compare)
-static bool apply_graphs_enabled() {
-  static const bool on = [] {
-    const char* e = std::getenv("SPAND_APPLY_GRAPH");
-    return !(e && e[0] == '0');
-  }();
-  return on;
-}
+
 
 namespace {
 
@@ -465,7 +458,7 @@ void run_apply(Ctx& C, FactorObj& F, int32_t nrhs, const double* x, double* y) {
   // per-kernel event timing of the apply's kernels needs the individual launches
   const bool timed = C.prof.on && (C.prof.only.empty() || C.prof.only.rfind("k_ap_", 0) == 0 ||
                                    C.prof.only == "k_copy_vec" || C.prof.only == "k_scale_vec");
-  if (timed || !apply_graphs_enabled()) {
+  if (timed || !F.opts.apply_graph) {
     launches();
     return;
   }

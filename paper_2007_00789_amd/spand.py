@@ -39,6 +39,7 @@ class Opts(C.Structure):
                 ("qr_group", C.c_int32), ("qr_list_cap", C.c_int32),
                 ("qr_xcd_local", C.c_int32), ("qr_lds_cols", C.c_int32),
                 ("prescale", C.c_int32), ("top_fp64_levels", C.c_int32),
+                ("gemm_tile", C.c_int32), ("apply_graph", C.c_int32),
                 ("hbm_budget_bytes", C.c_int64)]
 
 
@@ -98,6 +99,7 @@ SIGNATURES = {
     "spand_server_stats": (C.c_int, [_P, _I64P]),
     "spand_server_error": (C.c_char_p, [_P]),
     "spand_server_destroy": (None, [_P]),
+    "spand_gemm_tuning": (C.c_int, [_P, C.c_int32, _I32P, C.POINTER(C.c_float)]),
     "spand_profile": (C.c_int, [_P, C.c_int32]),
     "spand_profile_only": (C.c_int, [_P, C.c_char_p]),
     "spand_profile_entries": (C.c_int, [_P, _I32P]),
@@ -154,7 +156,7 @@ def _np(a, dtype):
 
 def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
               qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_lds_cols=0, prescale=0,
-              top_fp64_levels=None, hbm_budget_bytes=0) -> Opts:
+              top_fp64_levels=None, hbm_budget_bytes=0, apply_graph=0, gemm_tile=0) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
     o.depth = int(depth)
@@ -171,6 +173,8 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     if top_fp64_levels is not None:
         o.top_fp64_levels = int(top_fp64_levels)
     o.hbm_budget_bytes = int(hbm_budget_bytes)
+    o.apply_graph = int(apply_graph)
+    o.gemm_tile = int(gemm_tile)
     return o
 
 
@@ -202,6 +206,18 @@ class Context:
         only: time the launches of this kernel name alone."""
         self._check(self.lib.spand_profile_only(self.h, only.encode() if only else None))
         self._check(self.lib.spand_profile(self.h, 1 if enable else 0))
+
+    def gemm_tuning(self, precision: int = 0):
+        """spand_gemm_tuning: {block size class: (tile, ms 64-tile, ms 128-tile)}
+        or None before the first factorization in that precision."""
+        tiles = np.zeros(4, np.int32)
+        ms = np.zeros(8, np.float32)
+        st = self.lib.spand_gemm_tuning(self.h, int(precision), tiles.ctypes.data_as(_I32P),
+                                        ms.ctypes.data_as(C.POINTER(C.c_float)))
+        if st != SPAND_OK:
+            return None
+        return {sz: (int(tiles[i]), float(ms[2 * i]), float(ms[2 * i + 1]))
+                for i, sz in enumerate((64, 128, 256, 512))}
 
     def profile_entries(self) -> dict:
         """{kernel: (total_ms, launches, work)} accumulated since profile(True)."""

@@ -453,3 +453,63 @@ def test_high_contrast_field_of_table1(ctx, scheme):
     x = dx.cpu().numpy()
     assert abs(int(it[0]) - it_ref) <= 1, (int(it[0]), it_ref)
     assert np.linalg.norm(x - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+
+
+@gpu
+def test_apply_graph_replays_match_plain_launches(ctx):
+    """opts.apply_graph = 1: the apply captured in a HIP graph at its first use
+    and replayed afterwards gives, on every replay, exactly what the plain
+    launches give (same kernels, same order), with eager work and
+    synchronizations between the replays; PCG likewise."""
+    from paper_2007_00789_amd import spand
+    p = laplacian_3d(16)
+    print("apply graph replays", flush=True)
+    res = {}
+    for g in (0, 1):
+        opts = spand.make_opts(depth=6, skip=1, eps=1e-2, scheme="SO", apply_graph=g)
+        plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+        res[g] = (plan, ctx.factor(plan, _dev(p.vals), opts))
+    x = _dev(rhs(p.n, 3, 41))
+    yg = torch.zeros_like(x)
+    yp = torch.zeros_like(x)
+    for rep in range(4):
+        ctx.apply(res[1][1], 3, x, yg)          # capture at rep 0, replays after
+        torch.cuda.synchronize()
+        ctx.apply(res[0][1], 3, x, yp)          # plain launches in between
+        x.mul_(1.0 + 0.25 * rep)                # eager work on the captured input buffer
+        torch.cuda.synchronize()
+        assert torch.equal(yg, yp), rep
+    b = _dev(rhs(p.n, 2, 42))
+    xs = {g: torch.zeros_like(b) for g in (0, 1)}
+    its = {g: ctx.pcg(res[g][1], 2, b, xs[g], 1e-10, 1000) for g in (0, 1)}
+    assert np.array_equal(its[0][0], its[1][0])
+    assert torch.equal(xs[0], xs[1])
+
+
+@gpu
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[5]],
+                         ids=[CASES[1][0], CASES[3][0], CASES[5][0]])
+def test_gemm_tiles_agree_with_oracle(ctx, name, make, depth, skip, eps, tile):
+    """Both GEMM kernels (64 x 64 tiles; 128 x 128 tiles with double-buffered
+    k-slabs) for every GEMM launch: ranks (a, k, r, r2) bit-exact and the
+    apply within 1e-11 of the oracle's."""
+    from paper_2007_00789_amd import spand
+    p = make()
+    print(f"gemm tile {tile} {name}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, "SO")
+    opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme="SO", gemm_tile=tile)
+    plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+    fac = ctx.factor(plan, _dev(p.vals), opts)
+    for l, recs in F.ranks.items():
+        got = fac.ranks(l, plan_o.steps[l].n_clusters)
+        for (p_, a, k, r, r2) in recs:
+            assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), (l, p_)
+    x = rhs(p.n, 2, 17)
+    y_ref = ospand.apply(F, x)
+    dx = _dev(x)
+    dy = torch.zeros_like(dx)
+    ctx.apply(fac, 2, dx, dy)
+    y = dy.cpu().numpy().reshape(p.n, 2, order="F")
+    assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)

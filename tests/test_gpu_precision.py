@@ -48,11 +48,13 @@ CASES = [
 
 
 @gpu
-@pytest.mark.parametrize("top", [0, 3, 99], ids=["top0", "top3", "all_fp64_chol"])
+@pytest.mark.parametrize("top,tile", [(0, 0), (3, 0), (99, 0), (3, 128)],
+                         ids=["top0", "top3", "all_fp64_chol", "top3_tile128"])
 @pytest.mark.parametrize("precision", ["FP32", "FP32_BF16"])
 @pytest.mark.parametrize("scheme", ["FO", "SO", "SF"])
 @pytest.mark.parametrize("name,make,depth,skip,eps", CASES, ids=[c[0] for c in CASES])
-def test_fp32_forms_against_fp64_oracle(ctx, name, make, depth, skip, eps, scheme, precision, top):
+def test_fp32_forms_against_fp64_oracle(ctx, name, make, depth, skip, eps, scheme, precision, top,
+                                        tile):
     from paper_2007_00789_amd import spand
     p = make()
     print(f"precision {precision} top_fp64_levels={top} {name} {scheme}", flush=True)
@@ -60,7 +62,7 @@ def test_fp32_forms_against_fp64_oracle(ctx, name, make, depth, skip, eps, schem
     A = p.scipy()
     F = ospand.factor(A, plan_o, eps, scheme)
     opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, precision=precision,
-                           top_fp64_levels=top)
+                           top_fp64_levels=top, gemm_tile=tile)
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
     fac = ctx.factor(plan, _dev(p.vals), opts)
     r_o = r_g = 0
