@@ -50,6 +50,8 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 PEAK_GEMM_TFLOPS = {"FP64": 78.6, "FP32": 157.3, "FP32_BF16": 157.3}
 # kernels whose recorded work is flops (the others record bytes moved)
 FLOP_KERNELS = ("k_gemm", "k_potrf_inv", "k_cpqr", "k_cpqr_coop")
+# arithmetic of the factorization per precision option (PCG is FP64 always)
+DTYPES = {"FP64": "f64", "FP32": "f32 factor, f64 PCG", "FP32_BF16": "f32 factor, bf16 Schur, f64 PCG"}
 
 
 def kernel_work(breakdown: dict, per: int, precision: str) -> dict:
@@ -72,8 +74,6 @@ def kernel_work(breakdown: dict, per: int, precision: str) -> dict:
                       "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
         out[k] = e
     return out
-# arithmetic of the factorization per precision option (PCG is FP64 always)
-DTYPES = {"FP64": "f64", "FP32": "f32 factor, f64 PCG", "FP32_BF16": "f32 factor, bf16 Schur, f64 PCG"}
 
 
 # oracle sample of each single-matrix workload: the same matrix family at two

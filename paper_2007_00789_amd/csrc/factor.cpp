@@ -972,10 +972,11 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
     if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
     if (!pd.empty()) {
       PotrfLaunch<FT> pl;
+      const double pd_flops = C.prof.on ? potrf_flops(pd) : 0.0;
       prep_potrf(C, pd, pd_cluster, l < o.top_fp64_levels, pl);
       pd_cluster = pl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(pl, d_info_i, s));
-      if (C.prof.on) C.prof.add_work("k_potrf_inv", potrf_flops(pd));
+      C.prof.add_work("k_potrf_inv", pd_flops);
       // G_s = L_s^{-1} B_{s,W}
       std::vector<GemmD> gd;
       std::vector<GemmTm> gt;
@@ -1131,10 +1132,11 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       }
       if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
       PotrfLaunch<FT> zl;
+      const double zd_flops = C.prof.on ? potrf_flops(zd) : 0.0;
       prep_potrf(C, zd, zd_cluster, l < o.top_fp64_levels, zl);
       zd_cluster = zl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(zl, d_info_f, s));
-      if (C.prof.on) C.prof.add_work("k_potrf_inv", potrf_flops(zd));
+      C.prof.add_work("k_potrf_inv", zd_flops);
       // two-sided scaling of every interface pair p < q
       std::vector<GemmD> g1, g2;
       std::vector<GemmTm> t1, t2;

@@ -47,9 +47,11 @@ constexpr int kCW = kCT / kWave;        // waves per workgroup
 constexpr int kList = kCoopList;        // tie candidates published per workgroup
 constexpr int kXs = 2 + 2 * kList;      // exchange stride: max, count, idx[], nrm2[]
 constexpr long kSpinLimit = 1L << 24;   // ~ seconds of s_sleep before giving up
-constexpr int kRpl = 16;                // rows per lane kept in registers by the update (8 lanes
-constexpr int kRpl16 = 12;              // per column); with 16 and 32 lanes per column
-constexpr int kRpl32 = 8;
+constexpr int kRpl = 4;                 // rows per lane kept in registers by the update (8 lanes
+constexpr int kRpl16 = 8;               // per column); with 16 and 32 lanes per column
+constexpr int kRpl32 = 4;
+constexpr int kUnrollLds = 4;           // loads in flight per lane in the update's other rows
+constexpr int kUnrollPanel = 8;         // (LDS slice; panel columns in global memory)
 
 template <int kCtrl>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -119,6 +121,7 @@ template <int L, int kRpl, bool kPanel, class R>
 __device__ __forceinline__ void update_columns(R* Ys, R* const* gcol, R* nrm2, const R* v, int a,
                                                int m, int j, R tau, int skip) {
   constexpr int CPW = kWave / L;   // columns per wave
+  constexpr int kU = kPanel ? kUnrollPanel : kUnrollLds;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int grp = lane / L, rl = lane % L;
   for (int cb = wid * CPW; cb < m; cb += kCW * CPW) {
@@ -135,8 +138,24 @@ __device__ __forceinline__ void update_columns(R* Ys, R* const* gcol, R* nrm2, c
       yv[t] = in ? col[i] : R(0);
       dot = fma(in ? v[i] : R(0), yv[t], dot);
     }
-    for (int i = j + rl + L * kRpl; i < a; i += L)
-      if (act) dot = fma(v[i], col[i], dot);
+    // rows beyond the register block: kU rows' loads in flight per lane
+    // (more for panel columns, which live in global memory), accumulated in
+    // the same order
+    const int i4 = j + rl + L * kRpl;
+    if (act) {
+      int i = i4;
+      for (; i + (kU - 1) * L < a; i += kU * L) {
+        R vr[kU], wr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          vr[u] = v[i + u * L];
+          wr[u] = col[i + u * L];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) dot = fma(vr[u], wr[u], dot);
+      }
+      for (; i < a; i += L) dot = fma(v[i], col[i], dot);
+    }
     dot = groupL_sum<L>(dot) * tau;
     R s = 0;
 #pragma unroll
@@ -148,12 +167,28 @@ __device__ __forceinline__ void update_columns(R* Ys, R* const* gcol, R* nrm2, c
         if (i > j) s = fma(y, y, s);
       }
     }
-    for (int i = j + rl + L * kRpl; i < a; i += L)
-      if (act) {
+    if (act) {
+      int i = i4;
+      for (; i + (kU - 1) * L < a; i += kU * L) {
+        R vr[kU], wr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          vr[u] = v[i + u * L];
+          wr[u] = col[i + u * L];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const R y = fma(-dot, vr[u], wr[u]);
+          col[i + u * L] = y;
+          s = fma(y, y, s);
+        }
+      }
+      for (; i < a; i += L) {
         const R y = fma(-dot, v[i], col[i]);
         col[i] = y;
         s = fma(y, y, s);
       }
+    }
     s = groupL_sum<L>(s);
     if (act && rl == 0) nrm2[c] = s;
   }

@@ -298,10 +298,10 @@ def test_tiny_and_degenerate_problems(ctx):
 def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group, qr_list_cap,
                                     xcd_local):
     """Every QR path (single workgroup on a global workspace; cooperative groups
-    of several workgroups with W in LDS or in registers, with and without the
-    overflow round; groups reported as not placed on one XCD, which makes the
-    factorization fall back to single-workgroup QRs) gives the oracle's ranks
-    and the same preconditioner."""
+    of several workgroups with W in LDS, with and without the overflow round;
+    groups reported as not placed on one XCD, which makes the factorization
+    fall back to single-workgroup QRs) gives the oracle's ranks and the same
+    preconditioner."""
     p = make()
     print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local}", flush=True)
     plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
