@@ -209,8 +209,10 @@ def cpu_baseline(workload: str, w: dict, n_full: int, scheme: str, eps: float, n
 # on another workload, or if any listed file has changed since, the traffic is
 # reported as null.
 MEASURED_TRAFFIC = {
-    "k_cpqr_coop": {
-        "workload": "lap3d_64",
+    # (kernel, workload): HBM counters per launch (KiB, raw) from two rocprofv3
+    # --pmc runs of this script, the copy-probe scales, and the sources they
+    # were taken on (profiles/ holds the commands and the full tables)
+    ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
             "paper_2007_00789_amd/csrc/factor.cpp": "4b79be5b712e1c81726860743618e8f262039b5f86f487ad06cd80639b9c156b",
@@ -225,8 +227,8 @@ def measured_traffic(kernel, workload):
     """Calibrated HBM bytes per launch of `kernel` on `workload`, or None if not
     measured there on the current sources."""
     import hashlib
-    m = MEASURED_TRAFFIC.get(kernel)
-    if m is None or m["workload"] != workload:
+    m = MEASURED_TRAFFIC.get((kernel, workload))
+    if m is None:
         return None
     for rel, digest in m["sources"].items():
         with open(os.path.join(ROOT, rel), "rb") as f:
@@ -375,7 +377,9 @@ def bench_c1grid(args):
 
 def bench_serve(args):
     """Serving workload: a stream of solve requests with Poisson arrivals at
-    50 per second; 3D FV diffusion matrices with side U{32..96} and k = 10^u,
+    --serve-rate per second (default 50, far above what one GPU serves, so
+    the server runs saturated and requests_per_s is its saturation rate; a
+    rate below it gives the latency of an unsaturated server); 3D FV diffusion matrices with side U{32..96} and k = 10^u,
     u ~ U[-2,2] per cell; 1..16 N(0,1) right-hand sides per request; about 30%
     of the requests reuse the matrix of an earlier one (synthetic.serve_stream).
     Requests are submitted at their arrival times to the library's server
@@ -388,7 +392,7 @@ def bench_serve(args):
     from synthetic import serve_stream, fv_diffusion_3d, laplacian_3d, rhs
 
     tol = 1e-10
-    stream = serve_stream(count=args.serve_count)
+    stream = serve_stream(count=args.serve_count, rate=args.serve_rate)
     mats = {}
     for r in stream:
         if r["key"] not in mats:
@@ -439,7 +443,8 @@ def bench_serve(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"serving stream of {len(stream)} requests, Poisson arrivals at 50/s; "
+        "config": {"workload": f"serving stream of {len(stream)} requests, Poisson arrivals at "
+                               f"{args.serve_rate:g}/s; "
                                f"3D FV diffusion side U{{32..96}}, k = 10^U[-2,2]; 1-16 RHS N(0,1); "
                                f"{n_reuse} requests reuse a factor; eps {args.eps:g}, {args.scheme}, "
                                f"FP64, PCG tol {tol:g}; {args.serve_slots} slots, "
@@ -600,6 +605,7 @@ def main():
     ap.add_argument("--eig-d", type=int, default=1000, help="grid side of the eigenvector study")
     ap.add_argument("--table1-dmax", type=int, default=3200, help="largest grid side of the scaling study")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="request arrivals per second")
     ap.add_argument("--serve-batch", type=int, default=16)
     ap.add_argument("--serve-bytes", type=int, default=200, help="factor budget, GiB")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

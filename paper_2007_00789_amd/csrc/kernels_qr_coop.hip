@@ -52,6 +52,8 @@ constexpr int kRpl16 = 8;               // per column); with 16 and 32 lanes per
 constexpr int kRpl32 = 4;
 constexpr int kUnrollLds = 4;           // loads in flight per lane in the update's other rows
 constexpr int kUnrollPanel = 8;         // (LDS slice; panel columns in global memory)
+constexpr int kPv = 4;                  // pivot-column entries per lane loaded at once
+constexpr int kScan = 2;                // column norms per lane held by the pivot scan
 
 template <int kCtrl>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -258,8 +260,21 @@ __device__ __forceinline__ double xld(const double* p) {
 // one barrier ahead of a slow reader, so the word a reader sees for phase p is
 // the one written for p.  Lane q returns member q's word.  Returns false after
 // a timeout (bit 1 of the error flag set).
+//
+// Ordering.  Every member of a group runs on one XCD (checked at kernel
+// entry), so the XCD's L2 is the point where all of them see the same memory:
+// a store leaves the CU through its write-through L1 and completes in that L2,
+// and the exchange loads (agent scope) skip the L1 and read that L2.  The
+// writer waits for its data stores to complete (s_waitcnt) before it issues
+// the flag store, so a reader that sees the flag sees the data; a reader's
+// data loads are issued after its poll has returned the flag.  The two
+// workgroup-scope fences only keep the compiler from moving memory accesses
+// across the flag store and the poll (they add no cache maintenance); an
+// agent-scope release or acquire would instead write back or invalidate the
+// whole L2 on every barrier, which the XCD-local placement makes unnecessary.
 __device__ bool wave_barrier(unsigned long long* flags, int phase, unsigned long long payload, int G,
                              int g, int32_t* err, unsigned long long* word) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long* f = flags + (phase & 1) * kCoopMaxGroup;
@@ -271,6 +286,7 @@ __device__ bool wave_barrier(unsigned long long* flags, int phase, unsigned long
     const unsigned long long w =
         lane < G ? __hip_atomic_load(f + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : mine;
     if (__all((int)(w >> 48) == phase)) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       *word = w;
       return true;
     }
@@ -421,28 +437,41 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
     if (wid == 0) {
       int go = 1;
       // ---- local maximum and the ordered list of local tie candidates ----
+      // (the norms of the first kScan * 64 columns read once, into registers)
+      R nv[kScan];
       R ml = -1;
-      for (int c = lane; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
+#pragma unroll
+      for (int t = 0; t < kScan; ++t) {
+        const int c = lane + t * kWave;
+        nv[t] = c < m ? nrm2[c] : R(-1);
+        ml = fmax(ml, nv[t]);
+      }
+      for (int c = lane + kScan * kWave; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
       const R Mg = wave_max_r(ml);
       const R thl = Mg * R(1.0 - PivotTie<R>::rtol);
       double* X = X2 + (int64_t)(j & 1) * G * kXs;
       double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
       double* Xg = X + (int64_t)g * kXs;
       int total = 0, first = -1;
-      for (int cb = 0; cb < m; cb += kWave) {
+      auto chunk = [&](const int cb, const R x) {
         const int c = cb + lane;
-        const bool f = Mg >= R(0) && c < m && nrm2[c] >= R(0) && nrm2[c] >= thl;
+        const bool f = Mg >= R(0) && c < m && x >= R(0) && x >= thl;
         const unsigned long long mask = __ballot(f);
         if (f && G > 1) {
           const int at = total + __popcll(mask & ((1ULL << lane) - 1ULL));
           if (at < cd.list_cap) {
             xst(Xg + 2 + at, (double)(c0 + c));
-            xst(Xg + 2 + kList + at, nrm2[c]);
+            xst(Xg + 2 + kList + at, x);
           }
         }
         if (first < 0 && mask) first = cb + __ffsll((long long)mask) - 1;
         total += __popcll(mask);
-      }
+      };
+#pragma unroll
+      for (int t = 0; t < kScan; ++t)
+        if (t * kWave < m) chunk(t * kWave, nv[t]);
+      for (int cb = kScan * kWave; cb < m; cb += kWave)
+        chunk(cb, cb + lane < m ? nrm2[cb + lane] : R(-1));
       int C = INT_MAX;
       const R* PVl = nullptr;        // pivot column in LDS (one workgroup) ...
       const double* PVg = nullptr;   // ... or in the exchange buffer
@@ -461,7 +490,19 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
           double* Pg = PVs + (int64_t)g * (a + 1);
           if (lane == 0) xst(Pg, nrm2[first]);
           const R* fc = colp(first);
-          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
+          for (int i0 = j; i0 < a; i0 += 8 * kWave) {
+            R xw[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int i = i0 + lane + t * kWave;
+              xw[t] = i < a ? fc[i] : R(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int i = i0 + lane + t * kWave;
+              if (i < a) xst(Pg + 1 + (i - j), xw[t]);
+            }
+          }
         }
         // the flag word carries the local maximum (as float) and the first
         // candidate's column, which decide the pivot whenever one group's
@@ -558,28 +599,30 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
         }
       }
       if (go > 0) {
-        // the pivot column: norm, first entry and the rest, into v
+        // the pivot column: its norm, first entry and the next kPv * 64
+        // entries are loaded together, then written to v once, scaled; the
+        // entries beyond (interfaces of more than ~500 rows) go through v twice
         double pn, alpha;
+        R xr[kPv];
+        const int iend = min(a, j + 1 + kPv * kWave);
         if (PVl) {
           pn = nrm2[C - c0];
           alpha = PVl[j];
-          for (int i = j + 1 + lane; i < a; i += kWave) v[i] = PVl[i];
+#pragma unroll
+          for (int t = 0; t < kPv; ++t) {
+            const int i = j + 1 + lane + t * kWave;
+            xr[t] = i < iend ? PVl[i] : R(0);
+          }
+          for (int i = iend + lane; i < a; i += kWave) v[i] = PVl[i];
         } else {
           pn = xld(PVg);
           alpha = xld(PVg + 1);
-          for (int i0 = j + 1; i0 < a; i0 += 4 * kWave) {   // four loads in flight per lane
-            R xr[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int i = i0 + lane + t * kWave;
-              xr[t] = i < a ? R(xld(PVg + 1 + (i - j))) : R(0);
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int i = i0 + lane + t * kWave;
-              if (i < a) v[i] = xr[t];
-            }
+          for (int t = 0; t < kPv; ++t) {
+            const int i = j + 1 + lane + t * kWave;
+            xr[t] = i < iend ? R(xld(PVg + 1 + (i - j))) : R(0);
           }
+          for (int i = iend + lane; i < a; i += kWave) v[i] = R(xld(PVg + 1 + (i - j)));
         }
         const double nrm = sqrt(pn);
         if (j == 0) R00 = nrm;
@@ -588,7 +631,12 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
           if (r < 0 && nrm < eps * R00) r = j;
           const double beta = alpha >= 0.0 ? -nrm : nrm;
           const R rden = R(1.0 / (alpha - beta));
-          for (int i = j + 1 + lane; i < a; i += kWave) v[i] *= rden;
+#pragma unroll
+          for (int t = 0; t < kPv; ++t) {
+            const int i = j + 1 + lane + t * kWave;
+            if (i < iend) v[i] = xr[t] * rden;
+          }
+          for (int i = iend + lane; i < a; i += kWave) v[i] *= rden;
           if (lane == 0) {
             v[j] = 1.0;
             s_beta = beta;
