@@ -49,7 +49,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # (FP32_BF16: the Schur products on BF16 MFMA; the other GEMMs stay FP32)
 PEAK_GEMM_TFLOPS = {"FP64": 78.6, "FP32": 157.3, "FP32_BF16": 157.3}
 # kernels whose recorded work is flops (the others record bytes moved)
-FLOP_KERNELS = ("k_gemm", "k_potrf_inv", "k_cpqr", "k_cpqr_coop")
+FLOP_KERNELS = ("k_gemm", "k_gemm_small", "k_potrf_inv", "k_cpqr", "k_cpqr_coop")
 # arithmetic of the factorization per precision option (PCG is FP64 always)
 DTYPES = {"FP64": "f64", "FP32": "f32 factor, f64 PCG", "FP32_BF16": "f32 factor, bf16 Schur, f64 PCG"}
 
@@ -65,7 +65,7 @@ def kernel_work(breakdown: dict, per: int, precision: str) -> dict:
         e = {"ms": round(ms / per, 3), "calls": int(calls // per)}
         if k in FLOP_KERNELS:
             tf = work / (ms * 1e-3) / 1e12
-            peak = PEAK_GEMM_TFLOPS[precision] if k == "k_gemm" else PEAK_FP64_TFLOPS
+            peak = PEAK_GEMM_TFLOPS[precision] if k.startswith("k_gemm") else PEAK_FP64_TFLOPS
             e.update({"gflop": round(work / per / 1e9, 3), "tflops": round(tf, 3),
                       "frac_peak": round(tf / peak, 4), "peak_tflops": peak})
         else:

@@ -92,8 +92,10 @@ typedef struct {
   int32_t top_fp64_levels; /* FP32 precisions: the diagonal blocks of the steps l < top_fp64_levels
                               are factored in FP64 and their Schur products are FP32 (default 3:
                               the root and the two separator levels below it); ignored in FP64 */
-  int32_t gemm_tile;    /* 0 (default): GEMM tile per launch from the context's autotuning;
-                           64 or 128: that tile for every GEMM launch (testing) */
+  int32_t gemm_tile;    /* 0 (default): GEMM blocks of at most 32 x 32 on a one-wave-per-block
+                           kernel, the others on the tile chosen per launch by the context's
+                           autotuning; 64 or 128: that tile kernel for every block of every
+                           GEMM launch (testing) */
   int32_t apply_graph;  /* 1: the factor's apply is captured in a HIP graph at its first use with a
                            given set of vector addresses and replayed afterwards (PCG applies
                            to the same buffers every iteration).  The caller must then not

@@ -179,6 +179,12 @@ void launch_potrf_blocks(const PotrfDescT<R>* d, int32_t count, int32_t max_n, i
 template <class R>
 void launch_gemm(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* tiles, int64_t ntiles,
                  GemmMode mode, int tile, hipStream_t s);
+// blocks of at most kGemmSmallN x kGemmSmallN (FP64 or FP32 arithmetic): one
+// wave per block; refs[i].desc names the descriptor of the i-th block
+constexpr int kGemmSmallN = 32;
+template <class R>
+void launch_gemm_small(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* refs,
+                       int64_t count, hipStream_t s);
 template <class R>
 void launch_cpqr(const CpqrDescT<R>* d, const CpqrNbrT<R>* nb, int32_t count, int32_t* n_cur,
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,

@@ -541,6 +541,65 @@ std::vector<TileRef> tiles_of(const std::vector<GemmDescT<FT>>& gd, int tile) {
   return tl;
 }
 
+// Blocks of at most kGemmSmallN x kGemmSmallN go to the one-wave-per-block
+// kernel (the leaf steps' Schur targets, which the tile kernels would pad to
+// 64 x 64), unless a tile is forced (opts.gemm_tile, SPAND_GEMM_TILE) or the
+// products run on the BF16 matrix cores.
+bool gemm_small_ok(const spand_opts& o, GemmMode mode) {
+  return mode == kGemmNative && o.gemm_tile == 0 && forced_gemm_tile() == 0;
+}
+bool gemm_is_small(int m, int n, bool small_ok) {
+  return small_ok && m <= kGemmSmallN && n <= kGemmSmallN;
+}
+template <class FT>
+double mean_mn_large(const std::vector<GemmDescT<FT>>& gd, bool small_ok) {
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (const auto& g : gd)
+    if (!gemm_is_small(g.m, g.n, small_ok)) {
+      sum += (double)g.m * g.n;
+      ++cnt;
+    }
+  return cnt ? sum / (double)cnt : 0.0;
+}
+
+// One GEMM launch of the factorization (native arithmetic): small blocks on
+// the one-wave kernel, the others on the tile kernel chosen for their mean
+// size; the algorithmic flops go to the profile of each.
+template <class FT>
+void run_gemm(Ctx& C, const spand_opts& o, const std::vector<GemmDescT<FT>>& gd,
+              const std::vector<GemmTermT<FT>>& gt, hipStream_t s) {
+  if (gd.empty()) return;
+  const bool small_ok = gemm_small_ok(o, kGemmNative);
+  const int tile = pick_tile<FT>(C, o, mean_mn_large(gd, small_ok));
+  std::vector<TileRef> tiles, small;
+  double f_small = 0.0, f_tiles = 0.0;
+  for (size_t i = 0; i < gd.size(); ++i) {
+    const GemmDescT<FT>& g = gd[i];
+    const double f = C.prof.on ? gemm_flops(&g, 1, gt.data()) : 0.0;
+    if (gemm_is_small(g.m, g.n, small_ok)) {
+      small.push_back(TileRef{(int32_t)i, 0, 0, 0});
+      f_small += f;
+    } else {
+      add_gemm_tiles(tiles, (int32_t)i, g.m, g.n, g.lower_only != 0, tile);
+      f_tiles += f;
+    }
+  }
+  if (tiles.empty() && small.empty()) return;
+  const auto* d_gd = C.upload.upload(gd);
+  const auto* d_gt = C.upload.upload(gt);
+  if (!small.empty()) {
+    const auto* d_sm = C.upload.upload(small);
+    SPAND_PROF(C, "k_gemm_small", launch_gemm_small(d_gd, d_gt, d_sm, (int64_t)small.size(), s));
+    C.prof.add_work("k_gemm_small", f_small);
+  }
+  if (!tiles.empty()) {
+    const auto* d_tl = C.upload.upload(tiles);
+    SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), kGemmNative, tile, s));
+    C.prof.add_work("k_gemm", f_tiles);
+  }
+}
+
 // Blocks of at most 64 rows first, the larger ones after; the breakdown flags
 // follow the same order.
 template <class FT>
@@ -980,7 +1039,6 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       // G_s = L_s^{-1} B_{s,W}
       std::vector<GemmD> gd;
       std::vector<GemmTm> gt;
-      std::vector<TileRef> tiles;
       for (int sI = 0; sI < nI; ++sI) {
         const int ns = sizes[sI];
         const int ks = R.kint[sI];
@@ -998,16 +1056,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
         g.beta = 0.0;
         gd.push_back(g);
       }
-      const int gtile = pick_tile<FT>(C, o, mean_mn(gd));
-      tiles = tiles_of(gd, gtile);
-      if (!tiles.empty()) {
-        const auto* d_gd = C.upload.upload(gd);
-        const auto* d_gt = C.upload.upload(gt);
-        const auto* d_tiles = C.upload.upload(tiles);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tiles, (int64_t)tiles.size(), kGemmNative,
-                                            gtile, s));
-        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gd, gt));
-      }
+      run_gemm(C, o, gd, gt, s);
       // Schur complement: B_{w1 w2} -= sum_s G_{s,w1}^T G_{s,w2} (structure
       // from the plan: targets and their interiors in ascending order).  The
       // descriptors are written in place into the pinned upload buffer, in
@@ -1016,23 +1065,31 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       const int64_t nsch = (int64_t)st.schur.size();
       const int nth = desc_threads((size_t)nsch);
       const int nchunk = nth > 1 ? 4 * nth : 1;
-      std::vector<int64_t> o_gd(nchunk + 1, 0), o_gt(nchunk + 1, 0), o_tl(nchunk + 1, 0);
+      std::vector<int64_t> o_gd(nchunk + 1, 0), o_gt(nchunk + 1, 0), o_tl(nchunk + 1, 0),
+          o_sm(nchunk + 1, 0);
+      // the Schur products from BF16 operands below the top FP64 levels
+      // (SPAND_FP32_BF16); in the panels' own precision otherwise
+      const GemmMode sm = o.precision == SPAND_FP32_BF16 && l >= o.top_fp64_levels ? kGemmBf16
+                                                                                   : kGemmNative;
+      const bool small_ok = gemm_small_ok(o, sm);
       auto live_terms = [&](const StepPlan::SchurTarget& tg) {
         int64_t t = 0;
         for (int64_t q = tg.t0; q < tg.t1; ++q) t += sizes[st.schur_terms[q].s] != 0;
         return t;
       };
       // tile of the launch from the mean size of its live target blocks
+      // (those that the tile kernel takes)
       double sch_mn = 0.0;
       int64_t sch_n = 0;
       for (const StepPlan::SchurTarget& tg : st.schur)
-        if (sizes[tg.w1] != 0 && sizes[tg.w2] != 0) {
+        if (sizes[tg.w1] != 0 && sizes[tg.w2] != 0 &&
+            !gemm_is_small(sizes[tg.w1], sizes[tg.w2], small_ok)) {
           sch_mn += (double)sizes[tg.w1] * sizes[tg.w2];
           ++sch_n;
         }
       const int stile = pick_tile<FT>(C, o, sch_n ? sch_mn / (double)sch_n : 0.0);
       host_parallel(nchunk, nth, [&](int c) {
-        int64_t ngd = 0, ngt = 0, ntl = 0;
+        int64_t ngd = 0, ngt = 0, ntl = 0, nsm = 0;
         for (int64_t i = nsch * c / nchunk; i < nsch * (c + 1) / nchunk; ++i) {
           const StepPlan::SchurTarget& tg = st.schur[i];
           if (sizes[tg.w1] == 0 || sizes[tg.w2] == 0) continue;
@@ -1040,26 +1097,31 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           if (t == 0) continue;
           ++ngd;
           ngt += t;
-          ntl += gemm_tile_count(sizes[tg.w1], sizes[tg.w2], tg.w1 == tg.w2, stile);
+          if (gemm_is_small(sizes[tg.w1], sizes[tg.w2], small_ok)) ++nsm;
+          else ntl += gemm_tile_count(sizes[tg.w1], sizes[tg.w2], tg.w1 == tg.w2, stile);
         }
         o_gd[c + 1] = ngd;
         o_gt[c + 1] = ngt;
         o_tl[c + 1] = ntl;
+        o_sm[c + 1] = nsm;
       });
       for (int c = 0; c < nchunk; ++c) {
         o_gd[c + 1] += o_gd[c];
         o_gt[c + 1] += o_gt[c];
         o_tl[c + 1] += o_tl[c];
+        o_sm[c + 1] += o_sm[c];
       }
-      if (o_tl[nchunk] > 0) {
+      if (o_tl[nchunk] + o_sm[nchunk] > 0) {
         GemmD* d_sgd = nullptr;
         GemmTm* d_sgt = nullptr;
         TileRef* d_stl = nullptr;
+        TileRef* d_ssm = nullptr;
         GemmD* hgd = C.upload.stage<GemmD>((size_t)o_gd[nchunk], &d_sgd);
         GemmTm* hgt = C.upload.stage<GemmTm>((size_t)o_gt[nchunk], &d_sgt);
-        TileRef* htl = C.upload.stage<TileRef>((size_t)o_tl[nchunk], &d_stl);
+        TileRef* htl = C.upload.stage<TileRef>((size_t)std::max<int64_t>(o_tl[nchunk], 1), &d_stl);
+        TileRef* hsm = C.upload.stage<TileRef>((size_t)std::max<int64_t>(o_sm[nchunk], 1), &d_ssm);
         host_parallel(nchunk, nth, [&](int c) {
-          int64_t igd = o_gd[c], igt = o_gt[c], itl = o_tl[c];
+          int64_t igd = o_gd[c], igt = o_gt[c], itl = o_tl[c], ism = o_sm[c];
           for (int64_t i = nsch * c / nchunk; i < nsch * (c + 1) / nchunk; ++i) {
             const StepPlan::SchurTarget& tg = st.schur[i];
             const int w1 = tg.w1, w2 = tg.w2;
@@ -1089,19 +1151,28 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
             g.lower_only = w1 == w2;
             g.alpha = -1.0;
             g.beta = 1.0;
-            itl += put_gemm_tiles(htl + itl, (int32_t)igd, g.m, g.n, w1 == w2, stile);
+            if (gemm_is_small(g.m, g.n, small_ok)) hsm[ism++] = TileRef{(int32_t)igd, 0, 0, 0};
+            else itl += put_gemm_tiles(htl + itl, (int32_t)igd, g.m, g.n, w1 == w2, stile);
             ++igd;
           }
         });
-        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(hgd, (size_t)o_gd[nchunk], hgt));
+        double f_small = 0.0, f_all = 0.0;
+        if (C.prof.on) {
+          f_all = gemm_flops(hgd, (size_t)o_gd[nchunk], hgt);
+          for (int64_t i = 0; i < o_sm[nchunk]; ++i) f_small += gemm_flops(hgd + hsm[i].desc, 1, hgt);
+        }
         C.upload.commit(hgd, (size_t)o_gd[nchunk]);
         C.upload.commit(hgt, (size_t)o_gt[nchunk]);
-        C.upload.commit(htl, (size_t)o_tl[nchunk]);
-        // the Schur products from BF16 operands below the top FP64 levels
-        // (SPAND_FP32_BF16); in the panels' own precision otherwise
-        const GemmMode sm = o.precision == SPAND_FP32_BF16 && l >= o.top_fp64_levels ? kGemmBf16
-                                                                                     : kGemmNative;
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], sm, stile, s));
+        C.upload.commit(htl, (size_t)std::max<int64_t>(o_tl[nchunk], 1));
+        C.upload.commit(hsm, (size_t)std::max<int64_t>(o_sm[nchunk], 1));
+        if (o_sm[nchunk] > 0) {
+          SPAND_PROF(C, "k_gemm_small", launch_gemm_small(d_sgd, d_sgt, d_ssm, o_sm[nchunk], s));
+          C.prof.add_work("k_gemm_small", f_small);
+        }
+        if (o_tl[nchunk] > 0) {
+          SPAND_PROF(C, "k_gemm", launch_gemm(d_sgd, d_sgt, d_stl, o_tl[nchunk], sm, stile, s));
+          C.prof.add_work("k_gemm", f_all - f_small);
+        }
       }
     }
 
@@ -1140,7 +1211,6 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       // two-sided scaling of every interface pair p < q
       std::vector<GemmD> g1, g2;
       std::vector<GemmTm> t1, t2;
-      std::vector<TileRef> tl1, tl2;
       int64_t toff = 0;
       std::vector<int64_t> tpos;
       for (int p = nI; p < nc; ++p)
@@ -1182,22 +1252,8 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           b.alpha = 1.0;
           g2.push_back(b);
         }
-      const int ctile = pick_tile<FT>(C, o, mean_mn(g1));
-      tl1 = tiles_of(g1, ctile);
-      tl2 = tiles_of(g2, ctile);
-      if (!tl1.empty()) {
-        const auto* d_g1 = C.upload.upload(g1);
-        const auto* d_t1 = C.upload.upload(t1);
-        const auto* d_tl1 = C.upload.upload(tl1);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g1, d_t1, d_tl1, (int64_t)tl1.size(), kGemmNative,
-                                            ctile, s));
-        const auto* d_g2 = C.upload.upload(g2);
-        const auto* d_t2 = C.upload.upload(t2);
-        const auto* d_tl2 = C.upload.upload(tl2);
-        SPAND_PROF(C, "k_gemm", launch_gemm(d_g2, d_t2, d_tl2, (int64_t)tl2.size(), kGemmNative,
-                                            ctile, s));
-        if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(g1, t1) + gemm_flops(g2, t2));
-      }
+      run_gemm(C, o, g1, t1, s);
+      run_gemm(C, o, g2, t2, s);
       // sparsification, one launch per colour: interfaces whose coupling fits
       // in the LDS of at most kCoopMaxGroup workgroups run the cooperative QR,
       // the others the single-workgroup QR on a global-memory workspace
@@ -1539,7 +1595,6 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
     FT* xs = xdoubles ? static_cast<FT*>(C.temp.ensure(xdoubles * sizeof(FT))) : nullptr;
     std::vector<GemmD> gd;
     std::vector<GemmTm> gt;
-    std::vector<TileRef> tiles;
     std::vector<WyD> wy;
     for (const StepRec& R : F.steps) {
       for (size_t p = 0; p < R.V.size(); ++p) {
@@ -1568,21 +1623,13 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       }
     }
     if (!wy.empty()) {
-      const auto* d_gd = C.upload.upload(gd);
-      const auto* d_gt = C.upload.upload(gt);
-      const int wtile = pick_tile<FT>(C, o, mean_mn(gd));
-      tiles = tiles_of(gd, wtile);
-      const auto* d_tl = C.upload.upload(tiles);
+      run_gemm(C, o, gd, gt, s);
       const auto* d_wy = C.upload.upload(wy);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gd, d_gt, d_tl, (int64_t)tiles.size(), kGemmNative,
-                                          wtile, s));
-      if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gd, gt));
       SPAND_PROF(C, "k_wy_t", launch_wy_t(d_wy, (int32_t)wy.size(), s));
       // V T of every interface (a x nref): the apply then needs no pass over T
       // (Q^T x = x - V (VT)^T x, Q y = y - VT V^T y)
       std::vector<GemmD> gv;
       std::vector<GemmTm> gvt;
-      std::vector<TileRef> vtiles;
       for (const StepRec& R : F.steps)
         for (size_t p = 0; p < R.V.size(); ++p) {
           if (!Pt(R.V[p]) || R.r2[p] <= 0) continue;
@@ -1599,14 +1646,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           g.term1 = (int64_t)gvt.size();
           gv.push_back(g);
         }
-      const auto* d_gv = C.upload.upload(gv);
-      const auto* d_gvt = C.upload.upload(gvt);
-      const int vtile = pick_tile<FT>(C, o, mean_mn(gv));
-      vtiles = tiles_of(gv, vtile);
-      const auto* d_vtl = C.upload.upload(vtiles);
-      SPAND_PROF(C, "k_gemm", launch_gemm(d_gv, d_gvt, d_vtl, (int64_t)vtiles.size(), kGemmNative,
-                                          vtile, s));
-      if (C.prof.on) C.prof.add_work("k_gemm", gemm_flops(gv, gvt));
+      run_gemm(C, o, gv, gvt, s);
     }
   }
   SPAND_HIP(hipStreamSynchronize(s));

@@ -783,6 +783,81 @@ __global__ __launch_bounds__(kGemmThreads, 8) void k_gemm(const GemmDescT<R>* de
 }
 
 // ---------------------------------------------------------------------------
+// The same batched multi-term GEMM for blocks of at most 32 x 32 (the leaf
+// steps' Schur targets are 5-30 rows): one wave per block, no LDS and no
+// workgroup barriers.  The wave holds the block as 2 x 2 matrix-core tiles of
+// 16 x 16 and reads its operands straight from global memory: in a 16-deep k
+// step lane (r, q) = (l % 16, l / 16) loads rows k0 + 4q .. k0 + 4q + 3 of
+// output row r's and column r's operand columns, and the t-th of the four
+// products takes k = k0 + 4q + t (every k of the step once; the order of
+// summation differs from the tile kernels'). refs[b].desc is the descriptor of
+// wave b of the launch.
+// ---------------------------------------------------------------------------
+constexpr int kGemmSmallWaves = 4;
+
+template <class R>
+__global__ __launch_bounds__(kGemmSmallWaves * kWave) void k_gemm_small(const GemmDescT<R>* descs,
+                                                                      const GemmTermT<R>* terms,
+                                                                      const TileRef* refs,
+                                                                      int64_t count) {
+  constexpr bool kF64 = sizeof(R) == 8;
+  using acc_t = typename std::conditional<kF64, d4_t, f4_t>::type;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t b = (int64_t)blockIdx.x * kGemmSmallWaves + threadIdx.x / kWave;
+  if (b >= count) return;   // the whole wave leaves; no workgroup barriers
+  const GemmDescT<R> d = descs[refs[b].desc];
+  const int r = lane & 15, q = lane >> 4;
+  acc_t acc[2][2];
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci) acc[ri][ci] = acc_t{0, 0, 0, 0};
+  for (int64_t term = d.term0; term < d.term1; ++term) {
+    const GemmTermT<R> tm = terms[term];
+    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+      R a[2][4], bv[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 16 * h + r;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + 4 * q + t;
+          const bool in_a = i < d.m && k < tm.k, in_b = i < d.n && k < tm.k;
+          a[h][t] = in_a ? (d.transA ? tm.A[k + (int64_t)i * tm.lda] : tm.A[i + (int64_t)k * tm.lda])
+                         : R(0);
+          bv[h][t] = in_b ? (d.transB ? tm.B[i + (int64_t)k * tm.ldb] : tm.B[k + (int64_t)i * tm.ldb])
+                          : R(0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+          for (int ci = 0; ci < 2; ++ci) {
+            if constexpr (kF64) acc[ri][ci] = mfma16(a[ri][t], bv[ci][t], acc[ri][ci]);
+            else acc[ri][ci] = mfma16f(a[ri][t], bv[ci][t], acc[ri][ci]);
+          }
+    }
+  }
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci)
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int row = kF64 ? q + 4 * v4 : 4 * q + v4;
+        const int gi = 16 * ri + row, gj = 16 * ci + r;
+        if (gi < d.m && gj < d.n) {
+          R v = R(d.alpha) * acc[ri][ci][v4];
+          if (d.beta != 0.0) v = fma(R(d.beta), d.C[gi + (int64_t)gj * d.ldc], v);
+          d.C[gi + (int64_t)gj * d.ldc] = v;
+          if (d.C2) d.C2[gj + (int64_t)gi * d.ldc2] = v;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // The same batched multi-term GEMM over 128 x 128 output tiles, for launches
 // of large blocks: each of the four waves owns a 64 x 64 quadrant as 4 x 4
 // matrix-core tiles of 16 x 16 (16 instructions per 4-deep k step against 4
@@ -1303,6 +1378,14 @@ void launch_gemm(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* ti
 }
 
 template <class R>
+void launch_gemm_small(const GemmDescT<R>* d, const GemmTermT<R>* t, const TileRef* refs,
+                       int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const dim3 grid((unsigned)((count + kGemmSmallWaves - 1) / kGemmSmallWaves));
+  hipLaunchKernelGGL(k_gemm_small<R>, grid, dim3(kGemmSmallWaves * kWave), 0, s, d, t, refs, count);
+}
+
+template <class R>
 void launch_cpqr(const CpqrDescT<R>* d, const CpqrNbrT<R>* nb, int32_t count, int32_t* n_cur,
                  int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps, double eps_stop,
                  int32_t max_a, int32_t max_k, hipStream_t s) {
@@ -1336,6 +1419,8 @@ void launch_copy(const CopyDescT<S, D>* d, int64_t count, hipStream_t s) {
                                        hipStream_t);                                              \
   template void launch_gemm<R>(const GemmDescT<R>*, const GemmTermT<R>*, const TileRef*, int64_t, \
                                GemmMode, int, hipStream_t);                                       \
+  template void launch_gemm_small<R>(const GemmDescT<R>*, const GemmTermT<R>*, const TileRef*,    \
+                                     int64_t, hipStream_t);                                       \
   template void launch_cpqr<R>(const CpqrDescT<R>*, const CpqrNbrT<R>*, int32_t, int32_t*,        \
                                int32_t*, int32_t*, int32_t*, double, double, int32_t, int32_t,    \
                                hipStream_t);                                                      \

@@ -513,3 +513,41 @@ def test_gemm_tiles_agree_with_oracle(ctx, name, make, depth, skip, eps, tile):
     ctx.apply(fac, 2, dx, dy)
     y = dy.cpu().numpy().reshape(p.n, 2, order="F")
     assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+
+
+@gpu
+@pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[3], CASES[4], CASES[5]],
+                         ids=[CASES[3][0], CASES[4][0], CASES[5][0]])
+def test_small_block_gemm_agrees_with_oracle(ctx, name, make, depth, skip, eps):
+    """With the tile left to the library, GEMM blocks of at most 32 x 32 run on
+    the one-wave-per-block kernel (the profile shows its launches): ranks
+    (a, k, r, r2) bit-exact and the apply within 1e-11 of the oracle's, in FP64
+    and (against the FP64 oracle, at the FP32 bar) in FP32."""
+    from paper_2007_00789_amd import spand
+    p = make()
+    print(f"small-block gemm {name}", flush=True)
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, "SO")
+    x = rhs(p.n, 2, 19)
+    y_ref = ospand.apply(F, x)
+    for precision, bar in (("FP64", 1e-11), ("FP32", 1e-4)):
+        opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme="SO", precision=precision)
+        plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
+        ctx.profile(True)
+        fac = ctx.factor(plan, _dev(p.vals), opts)
+        torch.cuda.synchronize()
+        prof = ctx.profile_entries()
+        ctx.profile(False)
+        assert prof.get("k_gemm_small", (0, 0, 0))[1] > 0, sorted(prof)
+        if precision == "FP64":
+            for l, recs in F.ranks.items():
+                got = fac.ranks(l, plan_o.steps[l].n_clusters)
+                for (p_, a, k, r, r2) in recs:
+                    assert (got["a"][p_], got["k"][p_], got["r"][p_], got["r2"][p_]) == (a, k, r, r2), (l, p_)
+        dx = _dev(x)
+        dy = torch.zeros_like(dx)
+        ctx.apply(fac, 2, dx, dy)
+        y = dy.cpu().numpy().reshape(p.n, 2, order="F")
+        err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+        print(f"  {precision}: apply error {err:.2e}, small-kernel launches {prof['k_gemm_small'][1]}", flush=True)
+        assert err <= bar, (precision, err)
