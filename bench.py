@@ -209,16 +209,25 @@ def cpu_baseline(workload: str, w: dict, n_full: int, scheme: str, eps: float, n
 # on another workload, or if any listed file has changed since, the traffic is
 # reported as null.
 MEASURED_TRAFFIC = {
-    # (kernel, workload): HBM counters per launch (KiB, raw) from two rocprofv3
-    # --pmc runs of this script, the copy-probe scales, and the sources they
-    # were taken on (profiles/ holds the commands and the full tables)
+    # (kernel, workload): HBM counters per launch (KiB, raw, averaged over the
+    # kernel's launches of one factorization) from two rocprofv3 --pmc runs of
+    # this script, the copy-probe scales, and the sources they were taken on
+    # (profiles/ holds the commands and the full tables)
+    ("k_cpqr_coop", "fv3d_128"): {
+        "sources": {
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "618a65bac0805f7baded4da4b86a73c07f9c8fee6d4714a646c02af05f799c48",
+            "paper_2007_00789_amd/csrc/factor.cpp": "8df36f1e97ccf8c5705ce38f3b65b3aa26ec726deb6cda668e23986335f20094",
+        },
+        "fetch_kib": 16092.7, "write_kib": 83385.1,
+        "fetch_scale": 1.99981, "write_scale": 1.0,
+    },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "c8dd2d5633019530cf2c7198c884f4b637247ccccbe987818cbe3ddbac52486e",
-            "paper_2007_00789_amd/csrc/factor.cpp": "4b79be5b712e1c81726860743618e8f262039b5f86f487ad06cd80639b9c156b",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "618a65bac0805f7baded4da4b86a73c07f9c8fee6d4714a646c02af05f799c48",
+            "paper_2007_00789_amd/csrc/factor.cpp": "8df36f1e97ccf8c5705ce38f3b65b3aa26ec726deb6cda668e23986335f20094",
         },
-        "fetch_kib": 8216.4, "write_kib": 45951.2,
-        "fetch_scale": 1.9998, "write_scale": 1.0000,
+        "fetch_kib": 8213.5, "write_kib": 41768.3,
+        "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
 

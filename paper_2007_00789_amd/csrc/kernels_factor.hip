@@ -807,6 +807,7 @@ __global__ __launch_bounds__(kGemmSmallWaves * kWave) void k_gemm_small(const Ge
   if (b >= count) return;   // the whole wave leaves; no workgroup barriers
   const GemmDescT<R> d = descs[refs[b].desc];
   const int r = lane & 15, q = lane >> 4;
+  const bool one = d.m <= 16 && d.n <= 16;
   acc_t acc[2][2];
 #pragma unroll
   for (int ri = 0; ri < 2; ++ri)
@@ -829,15 +830,23 @@ __global__ __launch_bounds__(kGemmSmallWaves * kWave) void k_gemm_small(const Ge
                           : R(0);
         }
       }
+      if (one) {   // a block of at most 16 x 16: one matrix-core tile
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) {
+          if constexpr (kF64) acc[0][0] = mfma16(a[0][t], bv[0][t], acc[0][0]);
+          else acc[0][0] = mfma16f(a[0][t], bv[0][t], acc[0][0]);
+        }
+      } else {
 #pragma unroll
-        for (int ri = 0; ri < 2; ++ri)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int ci = 0; ci < 2; ++ci) {
-            if constexpr (kF64) acc[ri][ci] = mfma16(a[ri][t], bv[ci][t], acc[ri][ci]);
-            else acc[ri][ci] = mfma16f(a[ri][t], bv[ci][t], acc[ri][ci]);
-          }
+          for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+            for (int ci = 0; ci < 2; ++ci) {
+              if constexpr (kF64) acc[ri][ci] = mfma16(a[ri][t], bv[ci][t], acc[ri][ci]);
+              else acc[ri][ci] = mfma16f(a[ri][t], bv[ci][t], acc[ri][ci]);
+            }
+      }
     }
   }
 #pragma unroll
@@ -1303,9 +1312,19 @@ __global__ void k_scatter(const double* vals, const int64_t* dest, int64_t nnz, 
 template <class S, class D>
 __global__ __launch_bounds__(256) void k_copy(const CopyDescT<S, D>* descs) {
   const CopyDescT<S, D> d = descs[blockIdx.x];
-  for (int64_t idx = threadIdx.x; idx < (int64_t)d.m * d.n; idx += blockDim.x) {
-    const int i = (int)(idx % d.m), j = (int)(idx / d.m);
-    d.dst[i + (int64_t)j * d.ldd] = D(d.src[i + (int64_t)j * d.lds]);
+  const int m = d.m;
+  if ((int64_t)d.m * d.n <= INT_MAX) {
+    // 32-bit index arithmetic (a 64-bit division per element cost more than
+    // the copy itself)
+    const int mn = d.m * d.n;
+    for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) {
+      const int j = idx / m, i = idx - j * m;
+      d.dst[i + (int64_t)j * d.ldd] = D(d.src[i + (int64_t)j * d.lds]);
+    }
+  } else {
+    for (int j = 0; j < d.n; ++j)
+      for (int i = threadIdx.x; i < m; i += blockDim.x)
+        d.dst[i + (int64_t)j * d.ldd] = D(d.src[i + (int64_t)j * d.lds]);
   }
 }
 
