@@ -314,8 +314,10 @@ __global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const doub
           if (r0 + rr < nrhs) acc[rr] = fma(ev, zf[i + (r0 + rr) * nf], acc[rr]);
       }
     }
+    // partial sums by column of the right-hand side: consecutive lanes write
+    // consecutive doubles (no LDS bank conflicts)
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) part[(wid * kWave + lane) * 4 + rr] = acc[rr];
+    for (int rr = 0; rr < 4; ++rr) part[rr * kST + wid * kWave + lane] = acc[rr];
     __syncthreads();
     if (wid == 0 && col)
 #pragma unroll
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kST) void k_ap_et_fwd(const ApEt* descs, const doub
         if (r0 + rr >= nrhs) break;
         double sacc = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) sacc += part[(q * kWave + lane) * 4 + rr];
+        for (int q = 0; q < NW; ++q) sacc += part[rr * kST + q * kWave + lane];
         t[(int64_t)(r0 + rr) * d.k] = sacc;
       }
     __syncthreads();
@@ -451,6 +453,7 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_wy_dots(const ApWyTask* tas
     for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
+        if (r0 + rr >= nrhs) break;   // no reduction for the padding columns
         const double v = wave_sum(acc[c][rr]);
         if (lane == 0) red[wid][c * 4 + rr] = v;
       }
@@ -653,8 +656,9 @@ __global__ __launch_bounds__(kApWyThreads) void k_ap_mv_cols(const ApMvTask* tas
     for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
+        if (r0 + rr >= nrhs) break;   // no reduction for the padding columns
         const double v = wave_sum(acc[c][rr]);
-        if (lane == 0 && c < cn && r0 + rr < nrhs) {
+        if (lane == 0 && c < cn) {
           if (d.opos) z[d.opos[c0 + c] + (int64_t)(r0 + rr) * ldz] = v;
           else O[d.ooff * nrhs + c0 + c + (int64_t)(r0 + rr) * d.old] = v;
         }
