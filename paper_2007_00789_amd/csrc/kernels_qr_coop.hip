@@ -490,19 +490,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
           double* Pg = PVs + (int64_t)g * (a + 1);
           if (lane == 0) xst(Pg, nrm2[first]);
           const R* fc = colp(first);
-          for (int i0 = j; i0 < a; i0 += 8 * kWave) {
-            R xw[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int i = i0 + lane + t * kWave;
-              xw[t] = i < a ? fc[i] : R(0);
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int i = i0 + lane + t * kWave;
-              if (i < a) xst(Pg + 1 + (i - j), xw[t]);
-            }
-          }
+          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
         }
         // the flag word carries the local maximum (as float) and the first
         // candidate's column, which decide the pivot whenever one group's
