@@ -566,10 +566,13 @@ def bench_table1(args):
                     t2 = time.perf_counter()
                     it, rr = ctx.pcg(fac, 1, b, x, 1e-10, 1000)
                     t3 = time.perf_counter()
+                    # PCG stops on the recursive residual (the paper's rule);
+                    # relres is the true residual at exit, which can stay
+                    # above the tolerance when kappa(A) is large
                     row = {"d": d, "n": prob.n, "rho": rho, "eps": eps, "scheme": scheme,
                            "mu": fac.info()["nnz_L"] / prob.nnz, "n_cg": int(it[0]),
-                           "relres": float(rr[0]), "T_f": t2 - t1, "T_s": t3 - t2,
-                           "analyze_s": analyze_s}
+                           "relres": float(rr[0]), "true_residual_below_tol": bool(rr[0] < 1e-10),
+                           "T_f": t2 - t1, "T_s": t3 - t2, "analyze_s": analyze_s}
                     rows.append(row)
                     print(json.dumps(row), file=sys.stderr, flush=True)
                     fac.close()
@@ -591,6 +594,9 @@ def bench_table1(args):
         "config": {"workload": f"2D 5-point, d = 400..{args.table1_dmax}, rho in {{1, 100}}, "
                                "b = ones, eps in {0.01, 0.001}, skip 4, PCG tol 1e-10"},
         "ratios": ratios, "rows": rows,
+        "rows_true_residual_above_tol": [
+            f"d{r['d']}_rho{r['rho']:g}_eps{r['eps']:g}_{r['scheme']}: {r['relres']:.2e}"
+            for r in rows if not r["true_residual_below_tol"]],
     }
     print(json.dumps(out), flush=True)
 
