@@ -215,18 +215,18 @@ MEASURED_TRAFFIC = {
     # (profiles/ holds the commands and the full tables)
     ("k_cpqr_coop", "fv3d_128"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "618a65bac0805f7baded4da4b86a73c07f9c8fee6d4714a646c02af05f799c48",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "befa37cd7a03b545a22d7a955283990611bfebcbd285299ec4f0556131834bc9",
             "paper_2007_00789_amd/csrc/factor.cpp": "8df36f1e97ccf8c5705ce38f3b65b3aa26ec726deb6cda668e23986335f20094",
         },
-        "fetch_kib": 16092.7, "write_kib": 83385.1,
+        "fetch_kib": 16132.4, "write_kib": 83815.0,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "618a65bac0805f7baded4da4b86a73c07f9c8fee6d4714a646c02af05f799c48",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "befa37cd7a03b545a22d7a955283990611bfebcbd285299ec4f0556131834bc9",
             "paper_2007_00789_amd/csrc/factor.cpp": "8df36f1e97ccf8c5705ce38f3b65b3aa26ec726deb6cda668e23986335f20094",
         },
-        "fetch_kib": 8213.5, "write_kib": 41768.3,
+        "fetch_kib": 8207.8, "write_kib": 41733.2,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
