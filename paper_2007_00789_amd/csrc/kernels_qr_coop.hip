@@ -98,7 +98,7 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Sum over each group of L lanes (8, 16 or 32), returned to all of them.
+// Sum over each group of L lanes (8, 16, 32 or 64), returned to all of them.
 template <int L, class R>
 __device__ __forceinline__ R groupL_sum(R v) {
   v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
@@ -108,7 +108,8 @@ __device__ __forceinline__ R groupL_sum(R v) {
   } else {
     v += dpp_move<0x124>(v);  // row_ror:4
     v += dpp_move<0x128>(v);  // row_ror:8
-    if (L == 32) v += __shfl_xor(v, 16, kWave);
+    if (L >= 32) v += __shfl_xor(v, 16, kWave);
+    if (L == 64) v += __shfl_xor(v, 32, kWave);
   }
   return v;
 }
@@ -658,7 +659,7 @@ __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, co
       else if (mL > kCW * 2) update_columns<16, kRpl16, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
       else if (mL > 0) update_columns<32, kRpl32, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
       if constexpr (kPanel)
-        if (m > mL) update_columns<8, 8, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
+        if (m > mL) update_columns<64, 4, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
     }
     if (owner) {
       R* pc = colp(Cl);
