@@ -102,6 +102,10 @@ typedef struct {
                            allocate or free device memory from other threads while a PCG or
                            apply of this factor runs (those calls synchronize the device and
                            invalidate a capture).  0 (default): plain launches */
+  int32_t qr_single_launch; /* 1 (default): the cooperative QR groups of one colour that need
+                               several rounds of co-resident workgroups run in one launch, each
+                               workgroup starting its group of the next round as soon as its
+                               previous group is done; 0: one launch per round (testing) */
   int64_t hbm_budget_bytes; /* > 0: spand_factor fails with SPAND_E_OOM (and frees what it
                                allocated) as soon as the factor plus the working panels of a step
                                would hold more device memory than this; 0 (default): no limit */

@@ -83,7 +83,8 @@ void check_opts(const spand_opts* o) {
   if (o->precision != SPAND_FP64 && o->precision != SPAND_FP32 && o->precision != SPAND_FP32_BF16)
     throw Error(SPAND_E_INVALID, "unknown precision");
   if (o->qr_group < -1 || o->qr_list_cap < -1 || o->qr_list_cap > 32 || o->qr_xcd_local < 0 ||
-      o->qr_xcd_local > 1 || o->qr_lds_cols < 0)
+      o->qr_xcd_local > 1 || o->qr_lds_cols < 0 || o->qr_single_launch < 0 ||
+      o->qr_single_launch > 1)
     throw Error(SPAND_E_INVALID, "bad QR testing options");
   if (o->prescale < 0 || o->prescale > 1) throw Error(SPAND_E_INVALID, "prescale must be 0 or 1");
   if (o->top_fp64_levels < 0) throw Error(SPAND_E_INVALID, "top_fp64_levels must be >= 0");
@@ -137,6 +138,7 @@ void spand_default_opts(spand_opts* o) {
   o->top_fp64_levels = 3;
   o->apply_graph = 0;
   o->gemm_tile = 0;
+  o->qr_single_launch = 1;
   o->hbm_budget_bytes = 0;
 }
 

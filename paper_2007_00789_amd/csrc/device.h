@@ -198,16 +198,21 @@ void launch_wy_t(const WyDescT<R>* d, int32_t count, hipStream_t s);
 template <class R>
 int coop_max_blocks(size_t lds_bytes, bool panel);
 void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
-// blk_map[b] = group * kCoopMaxGroup + member for block b, or -1 (idle block).
-// The launch first clears the nsync barrier words at `sync` (each group's
-// CoopDesc::sync points into them); nsync = 0 when the caller has cleared
-// them already.
+// Group memberships are codes group * kCoopMaxGroup + member, or -1 (idle).
+// blk_ptr == nullptr: block b holds the one membership blk_map[b].  Otherwise
+// block b runs the memberships blk_map[blk_ptr[b] .. blk_ptr[b + 1]) one after
+// the other.  The caller numbers the groups in rounds (the groups of a round
+// fit the co-resident blocks together) and lists every block's memberships in
+// round order, so that a group waits only for groups of earlier rounds, which
+// all complete.  The launch first clears the nsync barrier words at `sync`
+// (each group's CoopDesc::sync points into them); nsync = 0 when the caller
+// has cleared them already.
 template <class R>
 hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const int32_t* blk_map,
-                            int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
-                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
-                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
-                            hipStream_t s);
+                            const int32_t* blk_ptr, int32_t nblocks, int32_t* sync, int32_t nsync,
+                            int32_t* n_cur, int32_t* out_r, int32_t* out_r2, int32_t* out_k,
+                            double eps, double eps_stop, int32_t* err, size_t lds_bytes,
+                            bool panel, hipStream_t s);
 
 constexpr int kGemmTile = 64;
 constexpr int kGemmTileL = 128;

@@ -1340,8 +1340,11 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
                                               d_k, eps, eps_stop, ma, mk, s));
         }
         // cooperative groups, packed onto XCDs (all workgroups of a group on
-        // one XCD; block b of a launch runs on XCD b % kCoopXcds), as many
-        // groups per launch as can be co-resident
+        // one XCD; block b of a launch runs on XCD b % kCoopXcds) in rounds of
+        // as many groups as can be co-resident.  The rounds of a colour run
+        // as one launch (each workgroup takes its next group as soon as its
+        // previous one is done, no launch boundary between rounds), or
+        // (opts.qr_single_launch = 0) as one launch each.
         {
           std::vector<CoopD>& list = qd;
           size_t lds = 0;
@@ -1360,6 +1363,12 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
                            [&](int x, int y) { return list[x].G > list[y].G; });
           std::vector<char> done(list.size(), 0);
           size_t ndone = 0;
+          struct Round {
+            std::vector<CoopD> q;
+            std::vector<int> xcd, slot;
+            int maxfill;
+          };
+          std::vector<Round> rounds;
           while (ndone < list.size()) {
             int fill[kCoopXcds] = {};
             std::vector<int> members, at_xcd, at_slot;
@@ -1414,37 +1423,72 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
                 }
               }
             }
-            const int maxfill = *std::max_element(fill, fill + kCoopXcds);
+            rounds.push_back({std::move(mq), std::move(at_xcd), std::move(at_slot),
+                              *std::max_element(fill, fill + kCoopXcds)});
+          }
+          // rounds [r0, r1) in one launch: block b's memberships in round
+          // order, so that a group waits only for groups of earlier rounds
+          auto launch_rounds = [&](size_t r0, size_t r1) {
+            int maxfill = 0;
+            int64_t xdoubles = 0, ngroups = 0;
+            for (size_t r = r0; r < r1; ++r) {
+              maxfill = std::max(maxfill, rounds[r].maxfill);
+              for (const CoopD& q : rounds[r].q) xdoubles += coop_xch_doubles(q.G, q.d.a);
+              ngroups += (int64_t)rounds[r].q.size();
+            }
             const int nblocks = maxfill * kCoopXcds;
-            std::vector<int32_t> blk_map((size_t)nblocks, -1);
-            int64_t xdoubles = 0;
-            for (const CoopD& q : mq) xdoubles += coop_xch_doubles(q.G, q.d.a);
             int32_t* sync = sync_all + sync_used;
-            sync_used += (int64_t)members.size() * kCoopSyncInts;
+            sync_used += ngroups * kCoopSyncInts;
             if (sync_used > sync_cap)
               throw Error(SPAND_E_STATE, "internal: cooperative QR barrier words exhausted");
             double* xch = C.upload.scratch_n<double>((size_t)xdoubles);
             std::vector<CoopD> batch;
+            batch.reserve((size_t)ngroups);
+            std::vector<std::vector<int32_t>> member_of((size_t)nblocks);
             int64_t xo = 0;
-            for (size_t bi = 0; bi < members.size(); ++bi) {
-              CoopD q = mq[bi];
-              q.xcd = o.qr_xcd_local ? at_xcd[bi] : -1;
-              q.sync = sync + bi * kCoopSyncInts;
-              q.xch = xch + xo;
-              xo += coop_xch_doubles(q.G, q.d.a);
-              for (int g = 0; g < q.G; ++g)
-                blk_map[at_xcd[bi] + (size_t)kCoopXcds * (at_slot[bi] + g)] =
-                    (int32_t)(bi * kCoopMaxGroup + g);
-              batch.push_back(q);
+            for (size_t r = r0; r < r1; ++r) {
+              const Round& rd = rounds[r];
+              for (size_t bi = 0; bi < rd.q.size(); ++bi) {
+                CoopD q = rd.q[bi];
+                const int64_t gi = (int64_t)batch.size();
+                q.xcd = o.qr_xcd_local ? rd.xcd[bi] : -1;
+                q.sync = sync + gi * kCoopSyncInts;
+                q.xch = xch + xo;
+                xo += coop_xch_doubles(q.G, q.d.a);
+                for (int g = 0; g < q.G; ++g)
+                  member_of[rd.xcd[bi] + (size_t)kCoopXcds * (rd.slot[bi] + g)].push_back(
+                      (int32_t)(gi * kCoopMaxGroup + g));
+                batch.push_back(q);
+              }
+            }
+            const int32_t* d_map = nullptr;
+            const int32_t* d_ptr = nullptr;
+            if (r1 - r0 == 1) {
+              std::vector<int32_t> blk_map((size_t)nblocks, -1);
+              for (int b = 0; b < nblocks; ++b)
+                if (!member_of[b].empty()) blk_map[b] = member_of[b][0];
+              d_map = C.upload.upload(blk_map);
+            } else {
+              // [block pointers (nblocks + 1) | memberships]
+              std::vector<int32_t> lists((size_t)nblocks + 1);
+              for (int b = 0; b < nblocks; ++b) {
+                lists[b] = (int32_t)(lists.size() - (size_t)nblocks - 1);
+                lists.insert(lists.end(), member_of[b].begin(), member_of[b].end());
+              }
+              lists[nblocks] = (int32_t)(lists.size() - (size_t)nblocks - 1);
+              d_ptr = C.upload.upload(lists);
+              d_map = d_ptr + nblocks + 1;
             }
             const auto* d_qd = C.upload.upload(batch);
-            const auto* d_map = C.upload.upload(blk_map);
             hipError_t he = hipSuccess;
             SPAND_PROF(C, "k_cpqr_coop",
-                       he = launch_cpqr_coop(d_qd, d_cn, d_map, nblocks, nullptr, 0, d_ncur, d_r,
-                                             d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
+                       he = launch_cpqr_coop(d_qd, d_cn, d_map, d_ptr, nblocks, nullptr, 0, d_ncur,
+                                             d_r, d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
             SPAND_HIP(he);
-          }
+          };
+          if (o.qr_single_launch && !rounds.empty()) launch_rounds(0, rounds.size());
+          else
+            for (size_t r = 0; r < rounds.size(); ++r) launch_rounds(r, r + 1);
         }
       }
     }

@@ -23,6 +23,11 @@
 //     one for the norm).
 //
 // One workgroup alone (G = 1) skips the exchange and reads the pivot from LDS.
+// A workgroup may belong to several groups in turn: the groups of one colour
+// that do not fit the co-resident workgroups together are packed in rounds,
+// and one launch runs all rounds, each workgroup starting its group of the
+// next round as soon as it is done with the previous one (its LDS slice,
+// norms and barrier state are set up afresh for every group).
 // Synchronization.  The launcher puts all workgroups of a group on one XCD
 // (workgroup b of a launch runs on XCD b mod 8).  The group then exchanges
 // data through that XCD's L2: plain stores (the CU's L1 is write-through) and
@@ -48,7 +53,7 @@ constexpr int kList = kCoopList;        // tie candidates published per workgrou
 constexpr int kXs = 2 + 2 * kList;      // exchange stride: max, count, idx[], nrm2[]
 constexpr long kSpinLimit = 1L << 24;   // ~ seconds of s_sleep before giving up
 constexpr int kRpl = 4;                 // rows per lane kept in registers by the update (8 lanes
-constexpr int kRpl16 = 8;               // per column); with 16 and 32 lanes per column
+constexpr int kRpl16 = 4;               // per column); with 16 and 32 lanes per column
 constexpr int kRpl32 = 4;
 constexpr int kUnrollLds = 4;           // loads in flight per lane in the update's other rows
 constexpr int kUnrollPanel = 8;         // (LDS slice; panel columns in global memory)
@@ -98,6 +103,17 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// threadIdx.x through an opaque move: in the membership loop of the
+// cooperative QR the compiler would otherwise compute every value derived
+// from it once, before the loop, and keep it live across the whole body
+// (register spills in the pivot steps); this way they are recomputed where
+// they are used
+__device__ __forceinline__ int tid_x() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
 // Sum over each group of L lanes (8, 16, 32 or 64), returned to all of them.
 template <int L, class R>
 __device__ __forceinline__ R groupL_sum(R v) {
@@ -125,7 +141,7 @@ __device__ __forceinline__ void update_columns(R* Ys, R* const* gcol, R* nrm2, c
                                                int m, int j, R tau, int skip) {
   constexpr int CPW = kWave / L;   // columns per wave
   constexpr int kU = kPanel ? kUnrollPanel : kUnrollLds;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int tx = tid_x(), lane = tx & (kWave - 1), wid = tx / kWave;
   const int grp = lane / L, rl = lane % L;
   for (int cb = wid * CPW; cb < m; cb += kCW * CPW) {
     const int c = cb + grp;
@@ -277,7 +293,7 @@ __device__ bool wave_barrier(unsigned long long* flags, int phase, unsigned long
                              int g, int32_t* err, unsigned long long* word) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = tid_x() & (kWave - 1);
   unsigned long long* f = flags + (phase & 1) * kCoopMaxGroup;
   const unsigned long long mine =
       ((unsigned long long)phase << 48) | (payload & 0xFFFFFFFFFFFFull);
@@ -329,381 +345,396 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x,
 // the common case.
 template <class R, bool kPanel>
 __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, const CpqrNbrT<R>* nbrs,
-                                                  const int32_t* blk_map, int32_t* n_cur,
-                                                  int32_t* out_r, int32_t* out_r2, int32_t* out_k,
-                                                  double eps, double eps_stop, int32_t* err) {
+                                                  const int32_t* blk_map, const int32_t* blk_ptr,
+                                                  int32_t* n_cur, int32_t* out_r, int32_t* out_r2,
+                                                  int32_t* out_k, double eps, double eps_stop,
+                                                  int32_t* err) {
   extern __shared__ __align__(16) char smraw[];
   R* sm = reinterpret_cast<R*>(smraw);
   __shared__ int sok, sC, s_go, s_r;
   __shared__ double s_beta, s_tau;
-  const int code = blk_map[blockIdx.x];
-  if (code < 0) return;   // idle slot of the XCD packing
-  const CoopDescT<R> cd = descs[code / kCoopMaxGroup];
-  const CpqrDescT<R>& d = cd.d;
-  const int G = cd.G, g = code % kCoopMaxGroup;
-  const int a = d.a;
-  const int64_t K = d.kmax;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  unsigned long long* flags = reinterpret_cast<unsigned long long*>(cd.sync + kCoopFlag64);
-  unsigned long long bw = 0;   // flag words of the last barrier (lane q: member q)
+  // the group memberships of this workgroup, run in order: blk_map[blockIdx.x]
+  // alone, or (blk_ptr) blk_map[blk_ptr[b] .. blk_ptr[b + 1])
+  const int t0 = blk_ptr ? blk_ptr[blockIdx.x] : (int)blockIdx.x;
+  const int t1 = blk_ptr ? blk_ptr[blockIdx.x + 1] : (int)blockIdx.x + 1;
+  for (int t = t0; t < t1; ++t) {
+    const int code = blk_map[t];
+    if (code < 0) continue;   // idle slot of the XCD packing
+    __syncthreads();          // the previous membership's epilogue is done with the LDS
+    const CoopDescT<R> cd = descs[code / kCoopMaxGroup];
+    const CpqrDescT<R>& d = cd.d;
+    const int G = cd.G, g = code % kCoopMaxGroup;
+    const int a = d.a;
+    const int64_t K = d.kmax;
+    const int tid = tid_x(), lane = tid & (kWave - 1), wid = tid / kWave;
+    unsigned long long* flags = reinterpret_cast<unsigned long long*>(cd.sync + kCoopFlag64);
+    unsigned long long bw = 0;   // flag words of the last barrier (lane q: member q)
 
-  // placement check: one round of device-coherent atomics on sync[0] (low
-  // half counts arrivals, high half counts members off the planned XCD)
-  if (tid == 0) {
-    int ok = 1, loc = 1;
-    if (G > 1) {
-      const int mine = 1 + ((cd.xcd >= 0 && xcc_id() == cd.xcd) ? 0 : (1 << 16));
-      __hip_atomic_fetch_add(cd.sync, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      long spins = 0;
-      int cnt;
-      while (((cnt = __hip_atomic_load(cd.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
-              0xffff) < G) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          ok = 0;
-          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+    // placement check: one round of device-coherent atomics on sync[0] (low
+    // half counts arrivals, high half counts members off the planned XCD)
+    if (tid == 0) {
+      int ok = 1, loc = 1;
+      if (G > 1) {
+        const int mine = 1 + ((cd.xcd >= 0 && xcc_id() == cd.xcd) ? 0 : (1 << 16));
+        __hip_atomic_fetch_add(cd.sync, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        int cnt;
+        while (((cnt = __hip_atomic_load(cd.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                0xffff) < G) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            ok = 0;
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
         }
+        loc = ok && (cnt >> 16) == 0;
+        if (ok && !loc) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      loc = ok && (cnt >> 16) == 0;
-      if (ok && !loc) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    sok = ok && loc;
-  }
-  __syncthreads();
-  if (!sok) return;   // timed out, or not on one XCD: nothing has been written
-
-  int k = 0;
-  for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
-  const int per = (k + G - 1) / G;
-  const int c0 = min(k, g * per), c1 = min(k, c0 + per), m = c1 - c0;
-  // the first mL of my columns in LDS, the rest (when the interface is wider
-  // than the group's LDS) in place in the row panel
-  const int mL = kPanel ? min(m, cd.ncap_lds) : m;
-  R* Ys = sm;                                       // a x ncap_lds (ld a)
-  R* nrm2 = sm + (int64_t)a * cd.ncap_lds;          // ncap
-  R* v = nrm2 + cd.ncap;                            // a
-  // ncap - ncap_lds panel column addresses, 8-byte aligned after v
-  R** gcol = reinterpret_cast<R**>(smraw + coop_lds_ptr_offset<R>(a, cd.ncap, cd.ncap_lds));
-  auto colp = [&](int c) -> R* {
-    if constexpr (kPanel) return c < mL ? Ys + (int64_t)c * a : gcol[c - mL];
-    return Ys + (int64_t)c * a;
-  };
-  // exchange: lists and first-candidate columns are double buffered by step
-  // parity (a workgroup may publish step j+1 while others still read step j)
-  double* X2 = cd.xch;                              // 2 x G x kXs
-  double* PV2 = X2 + 2 * (int64_t)G * kXs;          // 2 x G x (a + 1)
-  double* PVx = PV2 + 2 * (int64_t)G * (a + 1);     // a + 1: pivot of the slow path
-  double* XB = PVx + a + 1;                         // G
-
-  // my columns [c0, c1) of W
-  {
-    int kk = 0;
-    for (int64_t e = d.nb0; e < d.nb1; ++e) {
-      const CpqrNbrT<R> nb = nbrs[e];
-      const int wc = n_cur[nb.w];
-      const int lo = max(kk, c0), hi = min(kk + wc, c1);
-      const int hiL = min(hi, c0 + mL);
-      if (hiL > lo) {
-        const R* src = d.panel + (nb.col + (lo - kk)) * a;
-        R* dst = Ys + (int64_t)(lo - c0) * a;
-        for (int idx = tid; idx < (hiL - lo) * a; idx += kCT) dst[idx] = src[idx];
-      }
-      if (kPanel)
-        for (int c = max(lo, c0 + mL) + tid; c < hi; c += kCT)
-          gcol[c - c0 - mL] = d.panel + (nb.col + (c - kk)) * a;
-      kk += wc;
-    }
-  }
-  __syncthreads();
-  for (int c = wid; c < m; c += kCW) {
-    const R* col = colp(c);
-    R s = 0;
-    for (int i = lane; i < a; i += kWave) s = fma(col[i], col[i], s);
-    s = wave_sum(s);
-    if (lane == 0) nrm2[c] = s;
-  }
-  if (tid == 0) s_r = -1;
-  __syncthreads();
-
-  // Per pivot step the serial chain runs in wave 0 alone (local maximum and
-  // ordered candidate list from nrm2, publishing, the group barrier, the
-  // global decision, the pivot column and the reflector into LDS); every wave
-  // then updates its columns.  Two workgroup barriers per step.
-  int phase = 0;
-  int r = -1, j = 0;
-  double R00 = 0.0;
-  const int jmax = min(a, k);
-  for (; j < jmax; ++j) {
-    if (wid == 0) {
-      int go = 1;
-      // ---- local maximum and the ordered list of local tie candidates ----
-      // (the norms of the first kScan * 64 columns read once, into registers)
-      R nv[kScan];
-      R ml = -1;
-#pragma unroll
-      for (int t = 0; t < kScan; ++t) {
-        const int c = lane + t * kWave;
-        nv[t] = c < m ? nrm2[c] : R(-1);
-        ml = fmax(ml, nv[t]);
-      }
-      for (int c = lane + kScan * kWave; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
-      const R Mg = wave_max_r(ml);
-      const R thl = Mg * R(1.0 - PivotTie<R>::rtol);
-      double* X = X2 + (int64_t)(j & 1) * G * kXs;
-      double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
-      double* Xg = X + (int64_t)g * kXs;
-      int total = 0, first = -1;
-      auto chunk = [&](const int cb, const R x) {
-        const int c = cb + lane;
-        const bool f = Mg >= R(0) && c < m && x >= R(0) && x >= thl;
-        const unsigned long long mask = __ballot(f);
-        if (f && G > 1) {
-          const int at = total + __popcll(mask & ((1ULL << lane) - 1ULL));
-          if (at < cd.list_cap) {
-            xst(Xg + 2 + at, (double)(c0 + c));
-            xst(Xg + 2 + kList + at, x);
-          }
-        }
-        if (first < 0 && mask) first = cb + __ffsll((long long)mask) - 1;
-        total += __popcll(mask);
-      };
-#pragma unroll
-      for (int t = 0; t < kScan; ++t)
-        if (t * kWave < m) chunk(t * kWave, nv[t]);
-      for (int cb = kScan * kWave; cb < m; cb += kWave)
-        chunk(cb, cb + lane < m ? nrm2[cb + lane] : R(-1));
-      int C = INT_MAX;
-      const R* PVl = nullptr;        // pivot column in LDS (one workgroup) ...
-      const double* PVg = nullptr;   // ... or in the exchange buffer
-      if (G == 1) {
-        if (Mg < R(0)) go = 0;   // every column used up
-        else {
-          C = c0 + first;
-          PVl = colp(first);
-        }
-      } else {
-        if (lane == 0) {
-          xst(Xg, Mg);
-          xst(Xg + 1, (double)total);
-        }
-        if (first >= 0) {
-          double* Pg = PVs + (int64_t)g * (a + 1);
-          if (lane == 0) xst(Pg, nrm2[first]);
-          const R* fc = colp(first);
-          for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
-        }
-        // the flag word carries the local maximum (as float) and the first
-        // candidate's column, which decide the pivot whenever one group's
-        // maximum exceeds all others by more than float rounding and the band
-        const unsigned long long pay =
-            ((unsigned long long)(first >= 0 ? c0 + first : 0xFFFF) << 32) |
-            __float_as_uint((float)Mg);
-        if (!wave_barrier(flags, ++phase, pay, G, g, err, &bw)) go = -1;
-        bool fast = false;
-        if (go > 0 && cd.list_cap == kCoopList) {
-          const float Mf = lane < G ? __uint_as_float((unsigned)(bw & 0xFFFFFFFFull)) : -INFINITY;
-          const float Mmax = wave_max_f(Mf);
-          const unsigned long long at = __ballot(lane < G && Mf == Mmax);
-          const int og = __ffsll((long long)at) - 1;
-          const float second = wave_max_f(lane == og ? -INFINITY : Mf);
-          if (Mmax < 0.0f) {
-            fast = true;
-            go = 0;   // every column used up
-          } else if (Mmax > 0.0f && Mmax <= 3.0e38f &&
-                     second < Mmax * (1.0f - 1.0f / (1 << 20))) {
-            // the true maxima keep the order with a margin far above the band,
-            // so the pivot is og's lowest-index candidate: its published one
-            fast = true;
-            C = (int)((readlane_u64(bw, og) >> 32) & 0xFFFFull);
-            PVg = PVs + (int64_t)og * (a + 1);
-          }
-        }
-        if (go > 0 && !fast) {
-          // one round of loads: lane q fetches group q's maximum, count and
-          // first list entry; further entries are fetched only from groups
-          // that have more than one and whose maximum reaches the global band
-          double Mq = -2.0, nv0 = -1.0;
-          int cq = 0, ix0 = INT_MAX;
-          if (lane < G) {
-            const double* Xq = X + (int64_t)lane * kXs;
-            Mq = xld(Xq);
-            cq = (int)xld(Xq + 1);
-            ix0 = (int)xld(Xq + 2);
-            nv0 = xld(Xq + 2 + kList);
-          }
-          const double M = wave_max(Mq);
-          const bool over = __ballot(lane < G && cq > cd.list_cap) != 0ULL;
-          if (M < 0.0) go = 0;   // every column used up
-          else {
-            const double thr = M * (1.0 - PivotTie<R>::rtol);
-            if (!over) {
-              if (lane < G && cq > 0 && cd.list_cap > 0 && nv0 >= thr) C = ix0;
-              unsigned long long more = __ballot(lane < G && cq > 1 && Mq >= thr);
-              while (more) {   // rare: several candidates in one group
-                const int q = __ffsll((long long)more) - 1;
-                more &= more - 1ULL;
-                const int cqq = min(__shfl(cq, q, kWave), cd.list_cap);
-                const double* Xq = X + (int64_t)q * kXs;
-                if (lane >= 1 && lane < cqq && xld(Xq + 2 + kList + lane) >= thr)
-                  C = min(C, (int)xld(Xq + 2 + lane));
-              }
-              C = wave_min_int(C);
-            } else {
-              // exact local candidates against the global threshold
-              int cl = INT_MAX;
-              for (int cb = 0; cb < m && cl == INT_MAX; cb += kWave) {
-                const int c = cb + lane;
-                const unsigned long long mk =
-                    __ballot(c < m && nrm2[c] >= R(0) && (double)nrm2[c] >= thr);
-                if (mk) cl = c0 + cb + __ffsll((long long)mk) - 1;
-              }
-              if (lane == 0) xst(XB + g, (double)cl);
-              if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
-              if (go > 0) {
-                for (int qq = lane; qq < G; qq += kWave) C = min(C, (int)xld(XB + qq));
-                C = wave_min_int(C);
-              }
-            }
-            if (go > 0) {
-              const int og = min(C / max(per, 1), G - 1);   // owner workgroup
-              // the owner's published first candidate is the pivot unless the
-              // lists overflowed or it fell outside the global band
-              const int head_og =
-                  __shfl(cq, og, kWave) > 0 && cd.list_cap > 0 ? __shfl(ix0, og, kWave) : -1;
-              if (!over && head_og == C) {
-                PVg = PVs + (int64_t)og * (a + 1);
-              } else {
-                if (C >= c0 && C < c1) {
-                  const int Cl = C - c0;
-                  if (lane == 0) xst(PVx, nrm2[Cl]);
-                  const R* pc = colp(Cl);
-                  for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), pc[i]);
-                }
-                if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
-                PVg = PVx;
-              }
-            }
-          }
-        }
-      }
-      if (go > 0) {
-        // the pivot column: its norm, first entry and the next kPv * 64
-        // entries are loaded together, then written to v once, scaled; the
-        // entries beyond (interfaces of more than ~500 rows) go through v twice
-        double pn, alpha;
-        R xr[kPv];
-        const int iend = min(a, j + 1 + kPv * kWave);
-        if (PVl) {
-          pn = nrm2[C - c0];
-          alpha = PVl[j];
-#pragma unroll
-          for (int t = 0; t < kPv; ++t) {
-            const int i = j + 1 + lane + t * kWave;
-            xr[t] = i < iend ? PVl[i] : R(0);
-          }
-          for (int i = iend + lane; i < a; i += kWave) v[i] = PVl[i];
-        } else {
-          pn = xld(PVg);
-          alpha = xld(PVg + 1);
-#pragma unroll
-          for (int t = 0; t < kPv; ++t) {
-            const int i = j + 1 + lane + t * kWave;
-            xr[t] = i < iend ? R(xld(PVg + 1 + (i - j))) : R(0);
-          }
-          for (int i = iend + lane; i < a; i += kWave) v[i] = R(xld(PVg + 1 + (i - j)));
-        }
-        const double nrm = sqrt(pn);
-        if (j == 0) R00 = nrm;
-        if (nrm == 0.0 || nrm < eps_stop * R00) go = 0;
-        else {
-          if (r < 0 && nrm < eps * R00) r = j;
-          const double beta = alpha >= 0.0 ? -nrm : nrm;
-          const R rden = R(1.0 / (alpha - beta));
-#pragma unroll
-          for (int t = 0; t < kPv; ++t) {
-            const int i = j + 1 + lane + t * kWave;
-            if (i < iend) v[i] = xr[t] * rden;
-          }
-          for (int i = iend + lane; i < a; i += kWave) v[i] *= rden;
-          if (lane == 0) {
-            v[j] = 1.0;
-            s_beta = beta;
-            s_tau = (beta - alpha) / beta;
-            sC = C;
-          }
-        }
-      }
-      if (lane == 0) {
-        s_go = go;
-        s_r = r;
-      }
+      sok = !ok ? -1 : loc;
     }
     __syncthreads();
-    const int go = s_go;
-    if (go < 0) return;   // a group barrier timed out (error flag set)
-    if (go == 0) break;
-    const int C = sC;
-    const R tau = R(s_tau), beta = R(s_beta);
-    const bool owner = C >= c0 && C < c1;
-    const int Cl = C - c0;
-    if (g == 0) {
-      for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? R(0) : v[i];
-      if (tid == 0) d.tau[j] = tau;
-    }
-    // fused reflector update + exact trailing norms; the lanes per column
-    // grow as the columns per workgroup shrink, so that every wave has work
+    // not on one XCD: the group leaves before writing anything (its members go
+    // on with their next groups, which check their own placement); timed out:
+    // the workgroup leaves
+    if (sok < 0) return;
+    if (sok == 0) continue;
+
+    int k = 0;
+    for (int64_t e = d.nb0; e < d.nb1; ++e) k += n_cur[nbrs[e].w];
+    const int per = (k + G - 1) / G;
+    const int c0 = min(k, g * per), c1 = min(k, c0 + per), m = c1 - c0;
+    // the first mL of my columns in LDS, the rest (when the interface is wider
+    // than the group's LDS) in place in the row panel
+    const int mL = kPanel ? min(m, cd.ncap_lds) : m;
+    R* Ys = sm;                                       // a x ncap_lds (ld a)
+    R* nrm2 = sm + (int64_t)a * cd.ncap_lds;          // ncap
+    R* v = nrm2 + cd.ncap;                            // a
+    // ncap - ncap_lds panel column addresses, 8-byte aligned after v
+    R** gcol = reinterpret_cast<R**>(smraw + coop_lds_ptr_offset<R>(a, cd.ncap, cd.ncap_lds));
+    auto colp = [&](int c) -> R* {
+      if constexpr (kPanel) return c < mL ? Ys + (int64_t)c * a : gcol[c - mL];
+      return Ys + (int64_t)c * a;
+    };
+    // exchange: lists and first-candidate columns are double buffered by step
+    // parity (a workgroup may publish step j+1 while others still read step j)
+    double* X2 = cd.xch;                              // 2 x G x kXs
+    double* PV2 = X2 + 2 * (int64_t)G * kXs;          // 2 x G x (a + 1)
+    double* PVx = PV2 + 2 * (int64_t)G * (a + 1);     // a + 1: pivot of the slow path
+    double* XB = PVx + a + 1;                         // G
+
+    // my columns [c0, c1) of W
     {
-      const int skip = owner ? Cl : -1;
-      if (mL > kCW * 4) update_columns<8, kRpl, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
-      else if (mL > kCW * 2) update_columns<16, kRpl16, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
-      else if (mL > 0) update_columns<32, kRpl32, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
-      if constexpr (kPanel)
-        if (m > mL) update_columns<64, 4, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
-    }
-    if (owner) {
-      R* pc = colp(Cl);
-      for (int i = j + tid; i < a; i += kCT) pc[i] = i == j ? beta : R(0);
-      if (tid == 0) nrm2[Cl] = -1;
+      int kk = 0;
+      for (int64_t e = d.nb0; e < d.nb1; ++e) {
+        const CpqrNbrT<R> nb = nbrs[e];
+        const int wc = n_cur[nb.w];
+        const int lo = max(kk, c0), hi = min(kk + wc, c1);
+        const int hiL = min(hi, c0 + mL);
+        if (hiL > lo) {
+          const R* src = d.panel + (nb.col + (lo - kk)) * a;
+          R* dst = Ys + (int64_t)(lo - c0) * a;
+          for (int idx = tid; idx < (hiL - lo) * a; idx += kCT) dst[idx] = src[idx];
+        }
+        if (kPanel)
+          for (int c = max(lo, c0 + mL) + tid; c < hi; c += kCT)
+            gcol[c - c0 - mL] = d.panel + (nb.col + (c - kk)) * a;
+        kk += wc;
+      }
     }
     __syncthreads();
-  }
-  r = s_r;
-  const int nref = j;
-  if (r < 0) r = nref;
-
-  // Q^T W of my columns into the transposed workspace (E^T lives in rows r..)
-  for (int idx = tid; idx < m * a; idx += kCT) {
-    const int c = idx % m, i = idx / m;
-    d.Y[(c0 + c) + i * K] = colp(c)[i];
-  }
-  // coarse rows into p's panel and, transposed, into the neighbours' panels
-  {
-    int kk = 0;
-    for (int64_t e = d.nb0; e < d.nb1; ++e) {
-      const CpqrNbrT<R> nb = nbrs[e];
-      const int wc = n_cur[nb.w];
-      const int lo = max(kk, c0), hi = min(kk + wc, c1);
-      for (int idx = tid; idx < r * (hi - lo); idx += kCT) {
-        const int cc = idx % (hi - lo), i = idx / (hi - lo);
-        const int cw = lo - kk + cc;  // column inside block (p, w)
-        const R y = colp(lo - c0 + cc)[i];
-        d.panel[i + (nb.col + cw) * a] = y;
-        nb.blk_wp[cw + (int64_t)i * nb.ldw] = y;
-      }
-      kk += wc;
+    for (int c = wid; c < m; c += kCW) {
+      const R* col = colp(c);
+      R s = 0;
+      for (int i = lane; i < a; i += kWave) s = fma(col[i], col[i], s);
+      s = wave_sum(s);
+      if (lane == 0) nrm2[c] = s;
     }
-  }
-  if (g != 0) return;
-  for (int idx = tid; idx < r * r; idx += kCT) {
-    const int i = idx % r, c = idx / r;
-    d.panel[i + (d.diag_col + c) * a] = i == c ? R(1) : R(0);
-  }
-  if (tid == 0) {
-    out_k[d.p] = k;
-    out_r[d.p] = r;
-    out_r2[d.p] = nref;
-    n_cur[d.p] = r;
+    if (tid == 0) s_r = -1;
+    __syncthreads();
+
+    // Per pivot step the serial chain runs in wave 0 alone (local maximum and
+    // ordered candidate list from nrm2, publishing, the group barrier, the
+    // global decision, the pivot column and the reflector into LDS); every wave
+    // then updates its columns.  Two workgroup barriers per step.
+    int phase = 0;
+    int r = -1, j = 0;
+    double R00 = 0.0;
+    const int jmax = min(a, k);
+    for (; j < jmax; ++j) {
+      if (wid == 0) {
+        int go = 1;
+        // ---- local maximum and the ordered list of local tie candidates ----
+        // (the norms of the first kScan * 64 columns read once, into registers)
+        R nv[kScan];
+        R ml = -1;
+  #pragma unroll
+        for (int t = 0; t < kScan; ++t) {
+          const int c = lane + t * kWave;
+          nv[t] = c < m ? nrm2[c] : R(-1);
+          ml = fmax(ml, nv[t]);
+        }
+        for (int c = lane + kScan * kWave; c < m; c += kWave) ml = fmax(ml, nrm2[c]);
+        const R Mg = wave_max_r(ml);
+        const R thl = Mg * R(1.0 - PivotTie<R>::rtol);
+        double* X = X2 + (int64_t)(j & 1) * G * kXs;
+        double* PVs = PV2 + (int64_t)(j & 1) * G * (a + 1);
+        double* Xg = X + (int64_t)g * kXs;
+        int total = 0, first = -1;
+        auto chunk = [&](const int cb, const R x) {
+          const int c = cb + lane;
+          const bool f = Mg >= R(0) && c < m && x >= R(0) && x >= thl;
+          const unsigned long long mask = __ballot(f);
+          if (f && G > 1) {
+            const int at = total + __popcll(mask & ((1ULL << lane) - 1ULL));
+            if (at < cd.list_cap) {
+              xst(Xg + 2 + at, (double)(c0 + c));
+              xst(Xg + 2 + kList + at, x);
+            }
+          }
+          if (first < 0 && mask) first = cb + __ffsll((long long)mask) - 1;
+          total += __popcll(mask);
+        };
+  #pragma unroll
+        for (int t = 0; t < kScan; ++t)
+          if (t * kWave < m) chunk(t * kWave, nv[t]);
+        for (int cb = kScan * kWave; cb < m; cb += kWave)
+          chunk(cb, cb + lane < m ? nrm2[cb + lane] : R(-1));
+        int C = INT_MAX;
+        const R* PVl = nullptr;        // pivot column in LDS (one workgroup) ...
+        const double* PVg = nullptr;   // ... or in the exchange buffer
+        if (G == 1) {
+          if (Mg < R(0)) go = 0;   // every column used up
+          else {
+            C = c0 + first;
+            PVl = colp(first);
+          }
+        } else {
+          if (lane == 0) {
+            xst(Xg, Mg);
+            xst(Xg + 1, (double)total);
+          }
+          if (first >= 0) {
+            double* Pg = PVs + (int64_t)g * (a + 1);
+            if (lane == 0) xst(Pg, nrm2[first]);
+            const R* fc = colp(first);
+            for (int i = j + lane; i < a; i += kWave) xst(Pg + 1 + (i - j), fc[i]);
+          }
+          // the flag word carries the local maximum (as float) and the first
+          // candidate's column, which decide the pivot whenever one group's
+          // maximum exceeds all others by more than float rounding and the band
+          const unsigned long long pay =
+              ((unsigned long long)(first >= 0 ? c0 + first : 0xFFFF) << 32) |
+              __float_as_uint((float)Mg);
+          if (!wave_barrier(flags, ++phase, pay, G, g, err, &bw)) go = -1;
+          bool fast = false;
+          if (go > 0 && cd.list_cap == kCoopList) {
+            const float Mf = lane < G ? __uint_as_float((unsigned)(bw & 0xFFFFFFFFull)) : -INFINITY;
+            const float Mmax = wave_max_f(Mf);
+            const unsigned long long at = __ballot(lane < G && Mf == Mmax);
+            const int og = __ffsll((long long)at) - 1;
+            // no other group's maximum within float rounding of og's
+            const bool close = __ballot(lane < G && lane != og &&
+                                        !(Mf < Mmax * (1.0f - 1.0f / (1 << 20)))) != 0ULL;
+            if (Mmax < 0.0f) {
+              fast = true;
+              go = 0;   // every column used up
+            } else if (Mmax > 0.0f && Mmax <= 3.0e38f && !close) {
+              // the true maxima keep the order with a margin far above the band,
+              // so the pivot is og's lowest-index candidate: its published one
+              fast = true;
+              C = (int)((readlane_u64(bw, og) >> 32) & 0xFFFFull);
+              PVg = PVs + (int64_t)og * (a + 1);
+            }
+          }
+          if (go > 0 && !fast) {
+            // one round of loads: lane q fetches group q's maximum, count and
+            // first list entry; further entries are fetched only from groups
+            // that have more than one and whose maximum reaches the global band
+            double Mq = -2.0, nv0 = -1.0;
+            int cq = 0, ix0 = INT_MAX;
+            if (lane < G) {
+              const double* Xq = X + (int64_t)lane * kXs;
+              Mq = xld(Xq);
+              cq = (int)xld(Xq + 1);
+              ix0 = (int)xld(Xq + 2);
+              nv0 = xld(Xq + 2 + kList);
+            }
+            const double M = wave_max(Mq);
+            const bool over = __ballot(lane < G && cq > cd.list_cap) != 0ULL;
+            if (M < 0.0) go = 0;   // every column used up
+            else {
+              const double thr = M * (1.0 - PivotTie<R>::rtol);
+              if (!over) {
+                if (lane < G && cq > 0 && cd.list_cap > 0 && nv0 >= thr) C = ix0;
+                unsigned long long more = __ballot(lane < G && cq > 1 && Mq >= thr);
+                while (more) {   // rare: several candidates in one group
+                  const int q = __ffsll((long long)more) - 1;
+                  more &= more - 1ULL;
+                  const int cqq = min(__shfl(cq, q, kWave), cd.list_cap);
+                  const double* Xq = X + (int64_t)q * kXs;
+                  if (lane >= 1 && lane < cqq && xld(Xq + 2 + kList + lane) >= thr)
+                    C = min(C, (int)xld(Xq + 2 + lane));
+                }
+                C = wave_min_int(C);
+              } else {
+                // exact local candidates against the global threshold
+                int cl = INT_MAX;
+                for (int cb = 0; cb < m && cl == INT_MAX; cb += kWave) {
+                  const int c = cb + lane;
+                  const unsigned long long mk =
+                      __ballot(c < m && nrm2[c] >= R(0) && (double)nrm2[c] >= thr);
+                  if (mk) cl = c0 + cb + __ffsll((long long)mk) - 1;
+                }
+                if (lane == 0) xst(XB + g, (double)cl);
+                if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
+                if (go > 0) {
+                  for (int qq = lane; qq < G; qq += kWave) C = min(C, (int)xld(XB + qq));
+                  C = wave_min_int(C);
+                }
+              }
+              if (go > 0) {
+                const int og = min(C / max(per, 1), G - 1);   // owner workgroup
+                // the owner's published first candidate is the pivot unless the
+                // lists overflowed or it fell outside the global band
+                const int head_og =
+                    __shfl(cq, og, kWave) > 0 && cd.list_cap > 0 ? __shfl(ix0, og, kWave) : -1;
+                if (!over && head_og == C) {
+                  PVg = PVs + (int64_t)og * (a + 1);
+                } else {
+                  if (C >= c0 && C < c1) {
+                    const int Cl = C - c0;
+                    if (lane == 0) xst(PVx, nrm2[Cl]);
+                    const R* pc = colp(Cl);
+                    for (int i = j + lane; i < a; i += kWave) xst(PVx + 1 + (i - j), pc[i]);
+                  }
+                  if (!wave_barrier(flags, ++phase, 0, G, g, err, &bw)) go = -1;
+                  PVg = PVx;
+                }
+              }
+            }
+          }
+        }
+        if (go > 0) {
+          // the pivot column: its norm, first entry and the next kPv * 64
+          // entries are loaded together, then written to v once, scaled; the
+          // entries beyond (interfaces of more than ~500 rows) go through v twice
+          double pn, alpha;
+          R xr[kPv];
+          const int iend = min(a, j + 1 + kPv * kWave);
+          if (PVl) {
+            pn = nrm2[C - c0];
+            alpha = PVl[j];
+  #pragma unroll
+            for (int t = 0; t < kPv; ++t) {
+              const int i = j + 1 + lane + t * kWave;
+              xr[t] = i < iend ? PVl[i] : R(0);
+            }
+            for (int i = iend + lane; i < a; i += kWave) v[i] = PVl[i];
+          } else {
+            pn = xld(PVg);
+            alpha = xld(PVg + 1);
+  #pragma unroll
+            for (int t = 0; t < kPv; ++t) {
+              const int i = j + 1 + lane + t * kWave;
+              xr[t] = i < iend ? R(xld(PVg + 1 + (i - j))) : R(0);
+            }
+            for (int i = iend + lane; i < a; i += kWave) v[i] = R(xld(PVg + 1 + (i - j)));
+          }
+          const double nrm = sqrt(pn);
+          if (j == 0) R00 = nrm;
+          if (nrm == 0.0 || nrm < eps_stop * R00) go = 0;
+          else {
+            if (r < 0 && nrm < eps * R00) r = j;
+            const double beta = alpha >= 0.0 ? -nrm : nrm;
+            const R rden = R(1.0 / (alpha - beta));
+  #pragma unroll
+            for (int t = 0; t < kPv; ++t) {
+              const int i = j + 1 + lane + t * kWave;
+              if (i < iend) v[i] = xr[t] * rden;
+            }
+            for (int i = iend + lane; i < a; i += kWave) v[i] *= rden;
+            if (lane == 0) {
+              v[j] = 1.0;
+              s_beta = beta;
+              s_tau = (beta - alpha) / beta;
+              sC = C;
+            }
+          }
+        }
+        if (lane == 0) {
+          s_go = go;
+          s_r = r;
+        }
+      }
+      __syncthreads();
+      const int go = s_go;
+      if (go < 0) return;   // a group barrier timed out (error flag set)
+      if (go == 0) break;
+      const int C = sC;
+      const R tau = R(s_tau), beta = R(s_beta);
+      const bool owner = C >= c0 && C < c1;
+      const int Cl = C - c0;
+      if (g == 0) {
+        for (int i = tid; i < a; i += kCT) d.V[i + (int64_t)j * a] = i < j ? R(0) : v[i];
+        if (tid == 0) d.tau[j] = tau;
+      }
+      // fused reflector update + exact trailing norms; the lanes per column
+      // grow as the columns per workgroup shrink, so that every wave has work
+      {
+        const int skip = owner ? Cl : -1;
+        if (mL > kCW * 4) update_columns<8, kRpl, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+        else if (mL > kCW * 2)
+          update_columns<16, kRpl16, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+        else if (mL > 0) update_columns<32, kRpl32, false>(Ys, gcol, nrm2, v, a, mL, j, tau, skip);
+        if constexpr (kPanel)
+          if (m > mL)
+            update_columns<64, 4, true>(Ys, gcol, nrm2 + mL, v, a, m - mL, j, tau, skip - mL);
+      }
+      if (owner) {
+        R* pc = colp(Cl);
+        for (int i = j + tid; i < a; i += kCT) pc[i] = i == j ? beta : R(0);
+        if (tid == 0) nrm2[Cl] = -1;
+      }
+      __syncthreads();
+    }
+    r = s_r;
+    const int nref = j;
+    if (r < 0) r = nref;
+
+    // Q^T W of my columns into the transposed workspace (E^T lives in rows r..)
+    for (int idx = tid; idx < m * a; idx += kCT) {
+      const int c = idx % m, i = idx / m;
+      d.Y[(c0 + c) + i * K] = colp(c)[i];
+    }
+    // coarse rows into p's panel and, transposed, into the neighbours' panels
+    {
+      int kk = 0;
+      for (int64_t e = d.nb0; e < d.nb1; ++e) {
+        const CpqrNbrT<R> nb = nbrs[e];
+        const int wc = n_cur[nb.w];
+        const int lo = max(kk, c0), hi = min(kk + wc, c1);
+        for (int idx = tid; idx < r * (hi - lo); idx += kCT) {
+          const int cc = idx % (hi - lo), i = idx / (hi - lo);
+          const int cw = lo - kk + cc;  // column inside block (p, w)
+          const R y = colp(lo - c0 + cc)[i];
+          d.panel[i + (nb.col + cw) * a] = y;
+          nb.blk_wp[cw + (int64_t)i * nb.ldw] = y;
+        }
+        kk += wc;
+      }
+    }
+    if (g != 0) continue;
+    for (int idx = tid; idx < r * r; idx += kCT) {
+      const int i = idx % r, c = idx / r;
+      d.panel[i + (d.diag_col + c) * a] = i == c ? R(1) : R(0);
+    }
+    if (tid == 0) {
+      out_k[d.p] = k;
+      out_r[d.p] = r;
+      out_r2[d.p] = nref;
+      n_cur[d.p] = r;
+    }
   }
 }
 
@@ -733,13 +764,14 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s) {
 
 template <class R>
 hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const int32_t* blk_map,
-                            int32_t nblocks, int32_t* sync, int32_t nsync, int32_t* n_cur,
-                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
-                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
-                            hipStream_t s) {
+                            const int32_t* blk_ptr, int32_t nblocks, int32_t* sync, int32_t nsync,
+                            int32_t* n_cur, int32_t* out_r, int32_t* out_r2, int32_t* out_k,
+                            double eps, double eps_stop, int32_t* err, size_t lds_bytes,
+                            bool panel, hipStream_t s) {
   launch_fill_int(sync, nsync, s);
-  void* args[] = {(void*)&d, (void*)&nb, (void*)&blk_map, (void*)&n_cur, (void*)&out_r,
-                  (void*)&out_r2, (void*)&out_k, (void*)&eps, (void*)&eps_stop, (void*)&err};
+  void* args[] = {(void*)&d,     (void*)&nb,    (void*)&blk_map, (void*)&blk_ptr,
+                  (void*)&n_cur, (void*)&out_r, (void*)&out_r2,  (void*)&out_k,
+                  (void*)&eps,   (void*)&eps_stop, (void*)&err};
   const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<R, true>)
                         : reinterpret_cast<const void*>(k_cpqr_coop<R, false>);
   return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kCT), args, lds_bytes, s);
@@ -748,12 +780,12 @@ hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const 
 template int coop_max_blocks<double>(size_t, bool);
 template int coop_max_blocks<float>(size_t, bool);
 template hipError_t launch_cpqr_coop<double>(const CoopDescT<double>*, const CpqrNbrT<double>*,
-                                             const int32_t*, int32_t, int32_t*, int32_t, int32_t*,
-                                             int32_t*, int32_t*, int32_t*, double, double,
-                                             int32_t*, size_t, bool, hipStream_t);
+                                             const int32_t*, const int32_t*, int32_t, int32_t*,
+                                             int32_t, int32_t*, int32_t*, int32_t*, int32_t*,
+                                             double, double, int32_t*, size_t, bool, hipStream_t);
 template hipError_t launch_cpqr_coop<float>(const CoopDescT<float>*, const CpqrNbrT<float>*,
-                                            const int32_t*, int32_t, int32_t*, int32_t, int32_t*,
-                                            int32_t*, int32_t*, int32_t*, double, double, int32_t*,
-                                            size_t, bool, hipStream_t);
+                                            const int32_t*, const int32_t*, int32_t, int32_t*,
+                                            int32_t, int32_t*, int32_t*, int32_t*, int32_t*,
+                                            double, double, int32_t*, size_t, bool, hipStream_t);
 
 }  // namespace spand

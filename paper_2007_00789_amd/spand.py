@@ -40,7 +40,7 @@ class Opts(C.Structure):
                 ("qr_xcd_local", C.c_int32), ("qr_lds_cols", C.c_int32),
                 ("prescale", C.c_int32), ("top_fp64_levels", C.c_int32),
                 ("gemm_tile", C.c_int32), ("apply_graph", C.c_int32),
-                ("hbm_budget_bytes", C.c_int64)]
+                ("qr_single_launch", C.c_int32), ("hbm_budget_bytes", C.c_int64)]
 
 
 class FactorStats(C.Structure):
@@ -156,7 +156,8 @@ def _np(a, dtype):
 
 def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop_step=-1,
               qr_group=0, qr_list_cap=-1, qr_xcd_local=1, qr_lds_cols=0, prescale=0,
-              top_fp64_levels=None, hbm_budget_bytes=0, apply_graph=0, gemm_tile=0) -> Opts:
+              top_fp64_levels=None, hbm_budget_bytes=0, apply_graph=0, gemm_tile=0,
+              qr_single_launch=1) -> Opts:
     o = Opts()
     load().spand_default_opts(C.byref(o))
     o.depth = int(depth)
@@ -175,6 +176,7 @@ def make_opts(depth=0, skip=4, eps=1e-2, scheme="SO", precision=FP64, debug_stop
     o.hbm_budget_bytes = int(hbm_budget_bytes)
     o.apply_graph = int(apply_graph)
     o.gemm_tile = int(gemm_tile)
+    o.qr_single_launch = int(qr_single_launch)
     return o
 
 

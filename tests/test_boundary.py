@@ -115,13 +115,16 @@ def test_error_paths(lib):
 
 def test_opts_validation_on_the_host(lib):
     """spand_analyze checks the options without a device: negative
-    top_fp64_levels or hbm_budget_bytes and unknown precisions are rejected."""
+    top_fp64_levels or hbm_budget_bytes, unknown precisions and a
+    qr_single_launch other than 0 or 1 are rejected; the defaults written by
+    spand_default_opts land in the binding's fields (same layout)."""
     from paper_2007_00789_amd import spand
     p = laplacian_2d(16)
     o = spand.make_opts(depth=2, skip=0)
-    assert o.top_fp64_levels == 3 and o.hbm_budget_bytes == 0
+    assert o.top_fp64_levels == 3 and o.hbm_budget_bytes == 0 and o.qr_single_launch == 1
     spand.analyze(p.n, p.rowptr, p.colind, p.coords, o).close()
-    for field, bad in (("top_fp64_levels", -1), ("hbm_budget_bytes", -5), ("precision", 7)):
+    for field, bad in (("top_fp64_levels", -1), ("hbm_budget_bytes", -5), ("precision", 7),
+                       ("qr_single_launch", 2)):
         o2 = spand.make_opts(depth=2, skip=0)
         setattr(o2, field, bad)
         with pytest.raises(spand.SpandError) as e:

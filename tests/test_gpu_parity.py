@@ -31,10 +31,10 @@ def ctx():
 
 
 def _gpu_factor(ctx, p, depth, skip, eps, scheme, stop=-1, qr_group=0, qr_list_cap=-1,
-                qr_xcd_local=1, qr_lds_cols=0):
+                qr_xcd_local=1, qr_lds_cols=0, qr_single_launch=1):
     from paper_2007_00789_amd import spand
     opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme=scheme, debug_stop_step=stop,
-                           qr_lds_cols=qr_lds_cols,
+                           qr_lds_cols=qr_lds_cols, qr_single_launch=qr_single_launch,
                            qr_group=qr_group, qr_list_cap=qr_list_cap, qr_xcd_local=qr_xcd_local)
     plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, ctx)
     vals = _dev(p.vals)
@@ -289,25 +289,31 @@ def test_tiny_and_degenerate_problems(ctx):
 
 
 @gpu
-@pytest.mark.parametrize("qr_group,qr_list_cap,xcd_local", [
-    (-1, -1, 1), (1, -1, 1), (3, -1, 1), (5, 0, 1), (8, 1, 1), (3, -1, 0), (8, 1, 0), (32, -1, 1)],
+@pytest.mark.parametrize("qr_group,qr_list_cap,xcd_local,one_launch", [
+    (-1, -1, 1, 1), (1, -1, 1, 1), (3, -1, 1, 1), (5, 0, 1, 1), (8, 1, 1, 1), (3, -1, 0, 1),
+    (8, 1, 0, 1), (32, -1, 1, 1), (32, -1, 1, 0), (5, 0, 1, 0)],
     ids=["single-wg", "lds-1", "lds-3", "lds-5-roundB", "lds-8-cap1", "lds-3-misplaced",
-         "lds-8-cap1-misplaced", "lds-32"])
+         "lds-8-cap1-misplaced", "lds-32", "lds-32-launch-per-round",
+         "lds-5-roundB-launch-per-round"])
 @pytest.mark.parametrize("name,make,depth,skip,eps", [CASES[1], CASES[3], CASES[4]],
                          ids=[CASES[1][0], CASES[3][0], CASES[4][0]])
 def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group, qr_list_cap,
-                                    xcd_local):
+                                    xcd_local, one_launch):
     """Every QR path (single workgroup on a global workspace; cooperative groups
     of several workgroups with W in LDS, with and without the overflow round;
     groups reported as not placed on one XCD, which makes the factorization
-    fall back to single-workgroup QRs) gives the oracle's ranks and the same
-    preconditioner."""
+    fall back to single-workgroup QRs; the rounds of co-resident groups of a
+    colour in one launch, where each workgroup runs its groups one after the
+    other, or one launch per round; groups of 32 workgroups give colours of
+    several rounds on these problems) gives the oracle's (a, k, r, r2) and the
+    same preconditioner."""
     p = make()
-    print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local}", flush=True)
+    print(f"qr paths {name} group={qr_group} cap={qr_list_cap} local={xcd_local} "
+          f"one_launch={one_launch}", flush=True)
     plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
     F = ospand.factor(p.scipy(), plan_o, eps, "SO")
     _, fac = _gpu_factor(ctx, p, depth, skip, eps, "SO", qr_group=qr_group, qr_list_cap=qr_list_cap,
-                         qr_xcd_local=xcd_local)
+                         qr_xcd_local=xcd_local, qr_single_launch=one_launch)
     for l, recs in F.ranks.items():
         got = fac.ranks(l, plan_o.steps[l].n_clusters)
         for (p_, a, k, r, r2) in recs:
@@ -319,6 +325,29 @@ def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group,
     ctx.apply(fac, 2, dx, dy)
     y = dy.cpu().numpy().reshape(p.n, 2, order="F")
     assert np.linalg.norm(y - y_ref) <= 1e-11 * np.linalg.norm(y_ref)
+
+
+@gpu
+def test_qr_rounds_in_one_launch_match_launch_per_round(ctx):
+    """Groups of 32 workgroups on lap3d 16^3 need several rounds of co-resident
+    groups per colour: in one launch (each workgroup runs its groups one after
+    the other) the cooperative QR takes fewer launches than with one launch per
+    round, and the factor is the same bit for bit (the apply of both)."""
+    p = laplacian_3d(16)
+    out = {}
+    for one in (0, 1):
+        print(f"qr rounds lap3d_16 group=32 one_launch={one}", flush=True)
+        ctx.profile(True, only="k_cpqr_coop")
+        _, fac = _gpu_factor(ctx, p, 6, 1, 1e-2, "SO", qr_group=32, qr_single_launch=one)
+        launches = ctx.profile_entries()["k_cpqr_coop"][1]
+        ctx.profile(False)
+        dx = _dev(rhs(p.n, 2, 15))
+        dy = torch.zeros_like(dx)
+        ctx.apply(fac, 2, dx, dy)
+        out[one] = (launches, dy.cpu().numpy())
+    print(f"  k_cpqr_coop launches: per round {out[0][0]}, one launch per colour {out[1][0]}")
+    assert out[1][0] < out[0][0]
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 @gpu
