@@ -223,10 +223,10 @@ MEASURED_TRAFFIC = {
     },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "befa37cd7a03b545a22d7a955283990611bfebcbd285299ec4f0556131834bc9",
-            "paper_2007_00789_amd/csrc/factor.cpp": "8df36f1e97ccf8c5705ce38f3b65b3aa26ec726deb6cda668e23986335f20094",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "454201c32044fd28729c8ec3131536c21a88928e27f6f217c7b5cd65e312ed0d",
+            "paper_2007_00789_amd/csrc/factor.cpp": "7291757ec3f931ab4093154bc3355055d15fe0dfe1d70fca0f1de3b6f2835025",
         },
-        "fetch_kib": 8207.8, "write_kib": 41733.2,
+        "fetch_kib": 11358.4, "write_kib": 58155.5,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
