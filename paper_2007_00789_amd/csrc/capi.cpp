@@ -5,6 +5,7 @@
 #include <thread>
 #include <vector>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 
@@ -395,6 +396,8 @@ std::shared_ptr<FactorCore> factor_core(spand_ctx_t ctx, spand::Plan& P, const d
     spand::run_factor(ctx->c, P, fvals, *opts, f->f);
   } catch (const spand::CoopPlacement&) {
     // a cooperative QR group was not on one XCD: redo with single-workgroup QRs
+    std::fprintf(stderr, "spand: cooperative QR workgroups ran off their planned XCD; "
+                         "factorization redone with single-workgroup QRs\n");
     SPAND_HIP(hipStreamSynchronize(ctx->c.stream));
     auto g = std::make_shared<FactorCore>();
     g->device = f->device;

@@ -360,7 +360,7 @@ void host_parallel(int count, int nth, const Fn& f) {
 // threads for building a descriptor list of `items` entries on the host
 int desc_threads(size_t items) {
   if (items < 16384) return 1;
-  return std::min(8, (int)std::max(1u, std::thread::hardware_concurrency()));
+  return std::min(16, (int)std::max(1u, std::thread::hardware_concurrency()));
 }
 
 void add_gemm_tiles(std::vector<TileRef>& tiles, int32_t desc, int m, int n, bool lower_only,
@@ -574,9 +574,10 @@ void run_gemm(Ctx& C, const spand_opts& o, const std::vector<GemmDescT<FT>>& gd,
   const int tile = pick_tile<FT>(C, o, mean_mn_large(gd, small_ok));
   std::vector<TileRef> tiles, small;
   double f_small = 0.0, f_tiles = 0.0;
+  const bool count = C.prof.wants("k_gemm_small") || C.prof.wants("k_gemm");
   for (size_t i = 0; i < gd.size(); ++i) {
     const GemmDescT<FT>& g = gd[i];
-    const double f = C.prof.on ? gemm_flops(&g, 1, gt.data()) : 0.0;
+    const double f = count ? gemm_flops(&g, 1, gt.data()) : 0.0;
     if (gemm_is_small(g.m, g.n, small_ok)) {
       small.push_back(TileRef{(int32_t)i, 0, 0, 0});
       f_small += f;
@@ -1031,7 +1032,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
     if (max_n > 3500) throw Error(SPAND_E_LIMIT, "interior block larger than 3500");
     if (!pd.empty()) {
       PotrfLaunch<FT> pl;
-      const double pd_flops = C.prof.on ? potrf_flops(pd) : 0.0;
+      const double pd_flops = C.prof.wants("k_potrf_inv") ? potrf_flops(pd) : 0.0;
       prep_potrf(C, pd, pd_cluster, l < o.top_fp64_levels, pl);
       pd_cluster = pl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(pl, d_info_i, s));
@@ -1157,7 +1158,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           }
         });
         double f_small = 0.0, f_all = 0.0;
-        if (C.prof.on) {
+        if (C.prof.wants("k_gemm_small") || C.prof.wants("k_gemm")) {
           f_all = gemm_flops(hgd, (size_t)o_gd[nchunk], hgt);
           for (int64_t i = 0; i < o_sm[nchunk]; ++i) f_small += gemm_flops(hgd + hsm[i].desc, 1, hgt);
         }
@@ -1203,7 +1204,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       }
       if (max_a > 3500) throw Error(SPAND_E_LIMIT, "interface block larger than 3500");
       PotrfLaunch<FT> zl;
-      const double zd_flops = C.prof.on ? potrf_flops(zd) : 0.0;
+      const double zd_flops = C.prof.wants("k_potrf_inv") ? potrf_flops(zd) : 0.0;
       prep_potrf(C, zd, zd_cluster, l < o.top_fp64_levels, zl);
       zd_cluster = zl.clusters;
       SPAND_PROF(C, "k_potrf_inv", run_potrf(zl, d_info_f, s));
@@ -1565,7 +1566,7 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
           d.n = cur_sizes[cj];
         }
       });
-      if (C.prof.on) {
+      if (C.prof.wants("k_copy")) {
         double bytes = 0.0;
         for (int64_t i = 0; i < o_cp[mchunk]; ++i) bytes += 2.0 * hcp[i].m * hcp[i].n * sizeof(FT);
         C.prof.add_work("k_copy", bytes);

@@ -151,6 +151,8 @@ struct Prof {
   int begin(const char* name, hipStream_t s);
   void end(int id, hipStream_t s);
   void add_work(const char* name, double w);
+  // the work of `name` is recorded (callers skip computing it otherwise)
+  bool wants(const char* name) const { return on && (only.empty() || only == name); }
   void resolve();   // caller has synchronized the stream
   void reset();
   ~Prof();
