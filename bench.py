@@ -216,17 +216,17 @@ MEASURED_TRAFFIC = {
     ("k_cpqr_coop", "fv3d_128"): {
         "sources": {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "454201c32044fd28729c8ec3131536c21a88928e27f6f217c7b5cd65e312ed0d",
-            "paper_2007_00789_amd/csrc/factor.cpp": "7291757ec3f931ab4093154bc3355055d15fe0dfe1d70fca0f1de3b6f2835025",
+            "paper_2007_00789_amd/csrc/factor.cpp": "ad98b12219072fe0ea5b8b786e8e0a26d6bc968da9ab6261b680efbafe08b4ac",
         },
-        "fetch_kib": 78859.2, "write_kib": 445330.2,
+        "fetch_kib": 78833.2, "write_kib": 445136.1,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
             "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "454201c32044fd28729c8ec3131536c21a88928e27f6f217c7b5cd65e312ed0d",
-            "paper_2007_00789_amd/csrc/factor.cpp": "7291757ec3f931ab4093154bc3355055d15fe0dfe1d70fca0f1de3b6f2835025",
+            "paper_2007_00789_amd/csrc/factor.cpp": "ad98b12219072fe0ea5b8b786e8e0a26d6bc968da9ab6261b680efbafe08b4ac",
         },
-        "fetch_kib": 11358.4, "write_kib": 58155.5,
+        "fetch_kib": 11359.8, "write_kib": 58117.6,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
