@@ -88,10 +88,11 @@ struct CpqrDescT {
 };
 
 // One interface of a cooperative QR launch: G workgroups share the columns of
-// W, at most ncap each.  The launcher places all G workgroups of a group on
-// one XCD (block index = xcd + 8 * slot) so that the group synchronizes through
-// that XCD's L2; the kernel verifies the placement (xcd < 0: treat as not
-// placed) and a misplaced group leaves with bit 2 of the error flag set.
+// W, at most ncap each.  The launcher plans all G workgroups of a group on one
+// XCD (planned block index = xcd + 8 * slot) so that the group synchronizes
+// through that XCD's L2; each workgroup takes the next planned index of the
+// XCD it runs on, and the kernel verifies the placement (xcd < 0: treat as
+// not placed; a misplaced group leaves with bit 2 of the error flag set).
 template <class R>
 struct CoopDescT {
   CpqrDescT<R> d;
@@ -198,10 +199,14 @@ void launch_wy_t(const WyDescT<R>* d, int32_t count, hipStream_t s);
 template <class R>
 int coop_max_blocks(size_t lds_bytes, bool panel);
 void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
-// Group memberships are codes group * kCoopMaxGroup + member, or -1 (idle).
-// blk_ptr == nullptr: block b holds the one membership blk_map[b].  Otherwise
-// block b runs the memberships blk_map[blk_ptr[b] .. blk_ptr[b + 1]) one after
-// the other.  The caller numbers the groups in rounds (the groups of a round
+// Group memberships are codes group * kCoopMaxGroup + member, or -1 (idle),
+// for the nblocks planned blocks b = xcd + 8 * slot.  The grid has ngrid
+// workgroups (a multiple of 8 that fills every compute unit, so that every
+// XCD holds ngrid / 8 of them); at entry a workgroup takes the next slot of its
+// XCD from the 8 counters at xcd_slot (cleared by the launch) and runs the
+// planned block of that index, if any.  blk_ptr == nullptr: block b holds the
+// one membership blk_map[b].  Otherwise block b runs the memberships
+// blk_map[blk_ptr[b] .. blk_ptr[b + 1]) one after the other.  The caller numbers the groups in rounds (the groups of a round
 // fit the co-resident blocks together) and lists every block's memberships in
 // round order, so that a group waits only for groups of earlier rounds, which
 // all complete.  The launch first clears the nsync barrier words at `sync`
@@ -209,10 +214,11 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
 // has cleared them already.
 template <class R>
 hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const int32_t* blk_map,
-                            const int32_t* blk_ptr, int32_t nblocks, int32_t* sync, int32_t nsync,
-                            int32_t* n_cur, int32_t* out_r, int32_t* out_r2, int32_t* out_k,
-                            double eps, double eps_stop, int32_t* err, size_t lds_bytes,
-                            bool panel, hipStream_t s);
+                            const int32_t* blk_ptr, int32_t nblocks, int32_t ngrid,
+                            int32_t* xcd_slot, int32_t* sync, int32_t nsync, int32_t* n_cur,
+                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
+                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
+                            hipStream_t s);
 
 constexpr int kGemmTile = 64;
 constexpr int kGemmTileL = 128;

@@ -1481,10 +1481,12 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
               d_map = d_ptr + nblocks + 1;
             }
             const auto* d_qd = C.upload.upload(batch);
+            int32_t* d_xs = C.upload.scratch_n<int32_t>(kCoopXcds);
             hipError_t he = hipSuccess;
             SPAND_PROF(C, "k_cpqr_coop",
-                       he = launch_cpqr_coop(d_qd, d_cn, d_map, d_ptr, nblocks, nullptr, 0, d_ncur,
-                                             d_r, d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
+                       he = launch_cpqr_coop(d_qd, d_cn, d_map, d_ptr, nblocks,
+                                             slots * kCoopXcds, d_xs, nullptr, 0, d_ncur, d_r,
+                                             d_r2, d_k, eps, eps_stop, d_err, lds, panel, s));
             SPAND_HIP(he);
           };
           if (o.qr_single_launch && !rounds.empty()) launch_rounds(0, rounds.size());

@@ -28,9 +28,11 @@
 // and one launch runs all rounds, each workgroup starting its group of the
 // next round as soon as it is done with the previous one (its LDS slice,
 // norms and barrier state are set up afresh for every group).
-// Synchronization.  The launcher puts all workgroups of a group on one XCD
-// (workgroup b of a launch runs on XCD b mod 8).  The group then exchanges
-// data through that XCD's L2: plain stores (the CU's L1 is write-through) and
+// Synchronization.  The launcher plans all workgroups of a group on one XCD
+// (planned block b on XCD b mod 8), and a workgroup takes the next planned
+// block of the XCD it actually runs on (the grid fills every compute unit, so
+// every XCD holds the same number of workgroups in whatever order the hardware
+// places them).  The group then exchanges data through that XCD's L2: plain stores (the CU's L1 is write-through) and
 // agent-scope loads (which miss the L1), with barrier flags polled the same
 // way.  At entry every workgroup checks its XCD against the planned one with
 // one round of device-coherent atomics; a group that is not on one XCD leaves
@@ -346,17 +348,32 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x,
 template <class R, bool kPanel>
 __global__ __launch_bounds__(kCT) void k_cpqr_coop(const CoopDescT<R>* descs, const CpqrNbrT<R>* nbrs,
                                                   const int32_t* blk_map, const int32_t* blk_ptr,
+                                                  int32_t nplan, int32_t* xcd_slot,
                                                   int32_t* n_cur, int32_t* out_r, int32_t* out_r2,
                                                   int32_t* out_k, double eps, double eps_stop,
                                                   int32_t* err) {
   extern __shared__ __align__(16) char smraw[];
   R* sm = reinterpret_cast<R*>(smraw);
-  __shared__ int sok, sC, s_go, s_r;
+  __shared__ int sok, sC, s_go, s_r, s_vb;
   __shared__ double s_beta, s_tau;
-  // the group memberships of this workgroup, run in order: blk_map[blockIdx.x]
-  // alone, or (blk_ptr) blk_map[blk_ptr[b] .. blk_ptr[b + 1])
-  const int t0 = blk_ptr ? blk_ptr[blockIdx.x] : (int)blockIdx.x;
-  const int t1 = blk_ptr ? blk_ptr[blockIdx.x + 1] : (int)blockIdx.x + 1;
+  // The planned block b = xcd + 8 * slot: this workgroup takes the next slot
+  // of the XCD it runs on.  The grid fills every compute unit, so each XCD
+  // holds the same number of workgroups whatever order the hardware places
+  // them in, and every planned block index below nplan is taken once.
+  if (threadIdx.x == 0) {
+    const int x = xcc_id();
+    s_vb = x < kCoopXcds
+               ? x + kCoopXcds * __hip_atomic_fetch_add(xcd_slot + x, 1, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+               : INT_MAX;
+  }
+  __syncthreads();
+  const int vb = s_vb;
+  // the group memberships of this workgroup, run in order: blk_map[vb]
+  // alone, or (blk_ptr) blk_map[blk_ptr[vb] .. blk_ptr[vb + 1]); none beyond
+  // the planned blocks
+  const int t0 = vb >= nplan ? 0 : blk_ptr ? blk_ptr[vb] : vb;
+  const int t1 = vb >= nplan ? 0 : blk_ptr ? blk_ptr[vb + 1] : vb + 1;
   for (int t = t0; t < t1; ++t) {
     const int code = blk_map[t];
     if (code < 0) continue;   // idle slot of the XCD packing
@@ -764,28 +781,34 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s) {
 
 template <class R>
 hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const int32_t* blk_map,
-                            const int32_t* blk_ptr, int32_t nblocks, int32_t* sync, int32_t nsync,
-                            int32_t* n_cur, int32_t* out_r, int32_t* out_r2, int32_t* out_k,
-                            double eps, double eps_stop, int32_t* err, size_t lds_bytes,
-                            bool panel, hipStream_t s) {
+                            const int32_t* blk_ptr, int32_t nblocks, int32_t ngrid,
+                            int32_t* xcd_slot, int32_t* sync, int32_t nsync, int32_t* n_cur,
+                            int32_t* out_r, int32_t* out_r2, int32_t* out_k, double eps,
+                            double eps_stop, int32_t* err, size_t lds_bytes, bool panel,
+                            hipStream_t s) {
+  if (ngrid < nblocks || ngrid % kCoopXcds != 0) return hipErrorInvalidValue;
   launch_fill_int(sync, nsync, s);
-  void* args[] = {(void*)&d,     (void*)&nb,    (void*)&blk_map, (void*)&blk_ptr,
-                  (void*)&n_cur, (void*)&out_r, (void*)&out_r2,  (void*)&out_k,
-                  (void*)&eps,   (void*)&eps_stop, (void*)&err};
+  launch_fill_int(xcd_slot, kCoopXcds, s);
+  void* args[] = {(void*)&d,        (void*)&nb,    (void*)&blk_map, (void*)&blk_ptr,
+                  (void*)&nblocks,  (void*)&xcd_slot, (void*)&n_cur, (void*)&out_r,
+                  (void*)&out_r2,   (void*)&out_k, (void*)&eps,     (void*)&eps_stop,
+                  (void*)&err};
   const void* fn = panel ? reinterpret_cast<const void*>(k_cpqr_coop<R, true>)
                         : reinterpret_cast<const void*>(k_cpqr_coop<R, false>);
-  return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kCT), args, lds_bytes, s);
+  return hipLaunchCooperativeKernel(fn, dim3(ngrid), dim3(kCT), args, lds_bytes, s);
 }
 
 template int coop_max_blocks<double>(size_t, bool);
 template int coop_max_blocks<float>(size_t, bool);
 template hipError_t launch_cpqr_coop<double>(const CoopDescT<double>*, const CpqrNbrT<double>*,
-                                             const int32_t*, const int32_t*, int32_t, int32_t*,
-                                             int32_t, int32_t*, int32_t*, int32_t*, int32_t*,
-                                             double, double, int32_t*, size_t, bool, hipStream_t);
+                                             const int32_t*, const int32_t*, int32_t, int32_t,
+                                             int32_t*, int32_t*, int32_t, int32_t*, int32_t*,
+                                             int32_t*, int32_t*, double, double, int32_t*, size_t,
+                                             bool, hipStream_t);
 template hipError_t launch_cpqr_coop<float>(const CoopDescT<float>*, const CpqrNbrT<float>*,
-                                            const int32_t*, const int32_t*, int32_t, int32_t*,
-                                            int32_t, int32_t*, int32_t*, int32_t*, int32_t*,
-                                            double, double, int32_t*, size_t, bool, hipStream_t);
+                                            const int32_t*, const int32_t*, int32_t, int32_t,
+                                            int32_t*, int32_t*, int32_t, int32_t*, int32_t*,
+                                            int32_t*, int32_t*, double, double, int32_t*, size_t,
+                                            bool, hipStream_t);
 
 }  // namespace spand
