@@ -215,18 +215,18 @@ MEASURED_TRAFFIC = {
     # (profiles/ holds the commands and the full tables)
     ("k_cpqr_coop", "fv3d_128"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "454201c32044fd28729c8ec3131536c21a88928e27f6f217c7b5cd65e312ed0d",
-            "paper_2007_00789_amd/csrc/factor.cpp": "ad98b12219072fe0ea5b8b786e8e0a26d6bc968da9ab6261b680efbafe08b4ac",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "10b599b61cd71e6ece74882b0bb5d930f15249bc9e785d230e8ab1755422e0a8",
+            "paper_2007_00789_amd/csrc/factor.cpp": "e873efbdc3d3f2f12f1bfab2ee02240fc82f593daf201c79c4f792b548a5fa43",
         },
-        "fetch_kib": 78833.2, "write_kib": 445136.1,
+        "fetch_kib": 78878.7, "write_kib": 447986.3,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "454201c32044fd28729c8ec3131536c21a88928e27f6f217c7b5cd65e312ed0d",
-            "paper_2007_00789_amd/csrc/factor.cpp": "ad98b12219072fe0ea5b8b786e8e0a26d6bc968da9ab6261b680efbafe08b4ac",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "10b599b61cd71e6ece74882b0bb5d930f15249bc9e785d230e8ab1755422e0a8",
+            "paper_2007_00789_amd/csrc/factor.cpp": "e873efbdc3d3f2f12f1bfab2ee02240fc82f593daf201c79c4f792b548a5fa43",
         },
-        "fetch_kib": 11359.8, "write_kib": 58117.6,
+        "fetch_kib": 11358.5, "write_kib": 58184.4,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
