@@ -203,8 +203,8 @@ void launch_fill_int(int32_t* p, int64_t n, hipStream_t s);
 // for the nblocks planned blocks b = xcd + 8 * slot.  The grid has ngrid
 // workgroups (a multiple of 8 that fills every compute unit, so that every
 // XCD holds ngrid / 8 of them); at entry a workgroup takes the next slot of its
-// XCD from the 8 counters at xcd_slot (cleared by the launch) and runs the
-// planned block of that index, if any.  blk_ptr == nullptr: block b holds the
+// XCD from the 8 counters at xcd_slot (zero on entry: the caller clears them)
+// and runs the planned block of that index, if any.  blk_ptr == nullptr: block b holds the
 // one membership blk_map[b].  Otherwise block b runs the memberships
 // blk_map[blk_ptr[b] .. blk_ptr[b + 1]) one after the other.  The caller numbers the groups in rounds (the groups of a round
 // fit the co-resident blocks together) and lists every block's memberships in

@@ -1263,10 +1263,13 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
       // The barrier words of every cooperative group of the step (at most one
       // group per interface) are cleared by one fill before the first launch;
       // each colour is launched as soon as it is planned.
+      // after them, the 8 XCD slot counters of every launch (at most one
+      // launch per interface), cleared by the same fill
       const int64_t sync_cap = (int64_t)std::max(nc - nI, 1) * kCoopSyncInts;
-      int32_t* sync_all = C.upload.scratch_n<int32_t>((size_t)sync_cap);
-      launch_fill_int(sync_all, sync_cap, s);
-      int64_t sync_used = 0;
+      const int64_t xcd_cap = (int64_t)std::max(nc - nI, 1) * kCoopXcds;
+      int32_t* sync_all = C.upload.scratch_n<int32_t>((size_t)(sync_cap + xcd_cap));
+      launch_fill_int(sync_all, sync_cap + xcd_cap, s);
+      int64_t sync_used = 0, xcd_used = 0;
       for (int colour = 0; colour < st.ncolours; ++colour) {
         std::vector<CpqrD> cd;
         std::vector<CoopD> qd;
@@ -1481,7 +1484,10 @@ void run_factor_t(Ctx& C, Plan& P, const double* d_vals, const spand_opts& o, Fa
               d_map = d_ptr + nblocks + 1;
             }
             const auto* d_qd = C.upload.upload(batch);
-            int32_t* d_xs = C.upload.scratch_n<int32_t>(kCoopXcds);
+            int32_t* d_xs = sync_all + sync_cap + xcd_used;
+            xcd_used += kCoopXcds;
+            if (xcd_used > xcd_cap)
+              throw Error(SPAND_E_STATE, "internal: cooperative QR slot counters exhausted");
             hipError_t he = hipSuccess;
             SPAND_PROF(C, "k_cpqr_coop",
                        he = launch_cpqr_coop(d_qd, d_cn, d_map, d_ptr, nblocks,

@@ -788,7 +788,6 @@ hipError_t launch_cpqr_coop(const CoopDescT<R>* d, const CpqrNbrT<R>* nb, const 
                             hipStream_t s) {
   if (ngrid < nblocks || ngrid % kCoopXcds != 0) return hipErrorInvalidValue;
   launch_fill_int(sync, nsync, s);
-  launch_fill_int(xcd_slot, kCoopXcds, s);
   void* args[] = {(void*)&d,        (void*)&nb,    (void*)&blk_map, (void*)&blk_ptr,
                   (void*)&nblocks,  (void*)&xcd_slot, (void*)&n_cur, (void*)&out_r,
                   (void*)&out_r2,   (void*)&out_k, (void*)&eps,     (void*)&eps_stop,
