@@ -215,18 +215,18 @@ MEASURED_TRAFFIC = {
     # (profiles/ holds the commands and the full tables)
     ("k_cpqr_coop", "fv3d_128"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "10b599b61cd71e6ece74882b0bb5d930f15249bc9e785d230e8ab1755422e0a8",
-            "paper_2007_00789_amd/csrc/factor.cpp": "e873efbdc3d3f2f12f1bfab2ee02240fc82f593daf201c79c4f792b548a5fa43",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "1626c2057b1427c5c83788d9e9ce5e1c611f16cbe039f461e1bb73ec8c13e94f",
+            "paper_2007_00789_amd/csrc/factor.cpp": "ea2695ebe9dcaf5a55635a9c43c029f245a005e6fbfd85229774c41c5cf2245c",
         },
-        "fetch_kib": 78878.7, "write_kib": 447986.3,
+        "fetch_kib": 78894.6, "write_kib": 447917.1,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
     ("k_cpqr_coop", "lap3d_64"): {
         "sources": {
-            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "10b599b61cd71e6ece74882b0bb5d930f15249bc9e785d230e8ab1755422e0a8",
-            "paper_2007_00789_amd/csrc/factor.cpp": "e873efbdc3d3f2f12f1bfab2ee02240fc82f593daf201c79c4f792b548a5fa43",
+            "paper_2007_00789_amd/csrc/kernels_qr_coop.hip": "1626c2057b1427c5c83788d9e9ce5e1c611f16cbe039f461e1bb73ec8c13e94f",
+            "paper_2007_00789_amd/csrc/factor.cpp": "ea2695ebe9dcaf5a55635a9c43c029f245a005e6fbfd85229774c41c5cf2245c",
         },
-        "fetch_kib": 11358.5, "write_kib": 58184.4,
+        "fetch_kib": 11358.6, "write_kib": 58176.9,
         "fetch_scale": 1.99981, "write_scale": 1.0,
     },
 }
