@@ -328,6 +328,53 @@ def test_qr_paths_agree_with_oracle(ctx, name, make, depth, skip, eps, qr_group,
 
 
 @gpu
+def test_concurrent_contexts_keep_the_cooperative_qr(capfd):
+    """Two contexts, each on its own stream, factoring at the same time from two
+    threads (as the server's slots do): every cooperative QR group runs on its
+    planned XCD (no fallback to the single-workgroup QR is reported) and both
+    factors have the oracle's ranks."""
+    import threading
+    from paper_2007_00789_amd import spand
+    p = laplacian_3d(16)
+    depth, skip, eps = 6, 1, 1e-2
+    plan_o = nd.analyze(p.rowptr, p.colind, p.coords, depth, skip)
+    F = ospand.factor(p.scipy(), plan_o, eps, "SO")
+    ctxs = [spand.Context(0) for _ in range(2)]
+    results, errors = [[] for _ in ctxs], []
+
+    def work(i):
+        try:
+            c = ctxs[i]
+            opts = spand.make_opts(depth=depth, skip=skip, eps=eps, scheme="SO")
+            plan = spand.analyze(p.n, p.rowptr, p.colind, p.coords, opts, c)
+            vals = _dev(p.vals)
+            for _ in range(4):
+                fac = c.factor(plan, vals, opts)
+                results[i].append({l: fac.ranks(l, plan_o.steps[l].n_clusters) for l in F.ranks})
+        except Exception as e:   # reported after the join
+            errors.append(e)
+
+    print("concurrent factorizations on two contexts", flush=True)
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for c in ctxs:
+        c.close()
+    assert not errors, errors
+    err = capfd.readouterr().err
+    assert "ran off" not in err, err
+    for res in results:
+        assert len(res) == 4
+        for ranks in res:
+            for l, recs in F.ranks.items():
+                for (q, a, k, r, r2) in recs:
+                    got = ranks[l]
+                    assert (got["a"][q], got["k"][q], got["r"][q], got["r2"][q]) == (a, k, r, r2)
+
+
+@gpu
 def test_qr_rounds_in_one_launch_match_launch_per_round(ctx):
     """Groups of 32 workgroups on lap3d 16^3 need several rounds of co-resident
     groups per colour: in one launch (each workgroup runs its groups one after
